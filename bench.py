@@ -1,0 +1,154 @@
+"""Benchmark: one forward + adjoint iteration of the light-stage face render.
+
+A step is the whole hot path on one batch: morphable blend, BVH refit, edge
+tables, Monte-Carlo render (256x256, 16 spp, 20 lights), squared-L2 loss and
+its image gradient, adjoint with both edge-sampling terms, normal chain and
+the transposed blend/pose reductions to alpha, beta, delta and pose.  Inputs
+are resident on the device before timing starts.
+
+Prints one JSON line (see the fields below).  --gpus above 1 is refused: the
+build targets one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "fwd+bwd ms/iter & Mrays/s at 256x256; denoised-2spp vs plain-256spp at equal PSNR"
+
+# Algorithmic fp32 operations per unit of work (VALU lane operations counted
+# from the kernels' own source: adds, multiplies, min/max, compares,
+# divides and square roots each count 1).
+OPS_BOX = 26          # one slab test of a BVH node
+OPS_TRI = 40          # one ray/triangle test up to the first barycentric reject
+OPS_SHADE_ADJ = 420   # one light sample's radiance and reverse-mode adjoint
+OPS_SHADE_FWD = 110   # one light sample's radiance
+PEAK_VALU = 39.3      # T lane-ops/s: 256 CU x 4 SIMD x 16 lanes x 2.4 GHz
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="paper", choices=["paper", "tiny"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-threads", type=int, default=0)
+    return ap.parse_args()
+
+
+def cpu_baseline(model, scene, params, target, seed, spp, threads):
+    """The CPU oracle on one full iteration of the same workload."""
+    import oracle
+    oracle.build(force=not os.path.exists(oracle.LIB_PATH))
+    osc, vm, R = oracle.scene_from_model(model, scene, params)
+    t0 = time.perf_counter()
+    img, c1 = oracle.render(osc, seed, spp, threads=threads, counts=True)
+    dL = 2.0 * (img - target)
+    g, c2 = oracle.backward(osc, seed, spp, dL, flags=7, threads=threads, counts=True)
+    oracle.parameter_grads(model, params, vm, R, g["d_pos"], g["d_alb"])
+    dt = time.perf_counter() - t0
+    rays = c1.total() + c2.total()
+    return {"value": rays / dt / 1e6, "unit": "Mrays/s", "cores": threads, "kind": "oracle",
+            "ms_per_iter": dt * 1e3,
+            "sample": "one full forward+adjoint iteration (all terms) of the same paper-scale workload, "
+                      "same seed and spp"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the path shards by image "
+              "rows with one gradient all-reduce, which this build does not run)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_1910_05200_amd import facert, synth
+
+    assert torch.cuda.is_available(), "bench needs a HIP device"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    model, scene, params, spp = synth.workload(args.workload)
+    r = facert.Renderer(model, scene, timing=True)
+    p = facert.params_to_device(params)
+    pt = facert.params_to_device(synth.make_params(synth.TARGET_SCENE_SEED))
+    target = r.render(pt, synth.TARGET_RENDER_SEED, synth.TARGET_SPP).clone()
+    torch.cuda.synchronize()
+
+    stream = torch.cuda.current_stream()
+    want = ("d_lights", "d_spec", "d_vertices", "d_albedo", "d_alpha", "d_beta", "d_delta", "d_pose")
+
+    def step(it):
+        img = r.render(p, 1000 + it, spp)
+        dL, loss = r.loss_l2(img, target)
+        return r.backward(dL, want=want), loss
+
+    for it in range(args.warmup):
+        step(it)
+    torch.cuda.synchronize()
+    fwd_ms, adj_ms, rays, adj_ops, fwd_ops = [], [], [], [], []
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    per_step = []
+    for it in range(args.steps):
+        g, loss = step(args.warmup + it)
+        st = r.stats()          # synchronises; excluded from the bracket below
+        per_step.append(st)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    # A clean bracket without the per-step stats synchronisation:
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record(stream)
+    for it in range(args.steps):
+        step(args.warmup + args.steps + it)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / args.steps
+    for st in per_step:
+        fwd_ms.append(st["ms_kernel_fwd"])
+        adj_ms.append(st["ms_kernel_adj"])
+        rays.append(st["rays_camera"] + st["rays_shadow"] + st["rays_edge_primary"] + st["rays_edge_secondary"])
+        adj_ops.append(st["kernel_box_tests"][1] * OPS_BOX + st["kernel_tri_tests"][1] * OPS_TRI
+                       + st["kernel_shades"][1] * OPS_SHADE_ADJ)
+        fwd_ops.append(st["kernel_box_tests"][0] * OPS_BOX + st["kernel_tri_tests"][0] * OPS_TRI
+                       + st["kernel_shades"][0] * OPS_SHADE_FWD)
+    rays_per_iter = float(np.mean(rays))
+    adj_t = float(np.mean(adj_ms)) * 1e-3
+    achieved = float(np.mean(adj_ops)) / adj_t / 1e12
+    out = {
+        "metric": METRIC,
+        "value": rays_per_iter / (ms * 1e-3) / 1e6,
+        "unit": "Mrays/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {model.n_vertices}-vertex / {model.n_faces}-triangle "
+                               f"morphable face, {scene.width}x{scene.height}, {spp} spp, 20 area lights, "
+                               "forward + adjoint (interior, camera-silhouette and shadow-boundary terms)",
+                   "rays_per_iter": rays_per_iter, "ms_kernel_fwd": float(np.mean(fwd_ms)),
+                   "ms_kernel_adj": float(np.mean(adj_ms))},
+        "roofline": {"bound": "alu", "kernel": "k_render_adj", "achieved": achieved, "peak": PEAK_VALU,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_VALU, "traffic": None},
+    }
+    if not args.no_cpu_baseline:
+        threads = args.cpu_threads or min(16, os.cpu_count() or 1)
+        # the oracle gets its own inputs only: a zero target (dL/dI = 2 I)
+        out["cpu_baseline"] = cpu_baseline(model, scene, params, np.zeros((scene.height, scene.width, 3)),
+                                           1000, spp, threads)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,187 @@
+/*
+ * facert: differentiable light-stage face rendering on AMD Instinct MI355X.
+ *
+ * The operations follow Dib et al., "Face Reflectance and Geometry Modeling
+ * via Differentiable Ray Tracing" (CVMP 2019):
+ *   - fr_blend: the morphable model of the Face Modeling paragraph, identity
+ *     alpha (80), expression beta (90), albedo delta (80), geometry transform
+ *     [R t] (6), and the vertex normals n_i(alpha, beta, R, t);
+ *   - fr_render: p^T = F(f_r, l_j, alpha, beta, R, t) of the Optimization
+ *     paragraph, the Monte-Carlo estimator of the lighting equation in a
+ *     virtual light stage of N oriented area lights with colour intensities
+ *     l_j, Cook-Torrance reflectance (Lambertian albedo + gray specular
+ *     texture c_spec) and ray-traced self-shadows;
+ *   - fr_backward: the gradient of a loss given its image gradient, e.g.
+ *     E_data = sum ||p^T - p^R||^2 of Eq. 1, with respect to the light
+ *     colours, specular texels, vertex positions and albedo and, through the
+ *     model, alpha, beta, delta and the pose, including the edge-sampling
+ *     terms of visibility discontinuities (Face Modeling paragraph: the
+ *     differentiable ray tracer, then backpropagation).
+ *
+ * Conventions for every entry point:
+ *   - status: 0 on success, negative fr_status on failure; nothing throws.
+ *     On failure the context stays usable and fr_last_error() describes it.
+ *   - memory: the context owns its own device buffers (model copies, BVH,
+ *     edge tables, scratch).  Every array argument is owned by the caller.
+ *     Array arguments of fr_blend/fr_render/fr_backward are DEVICE pointers
+ *     (HIP global memory) read or written on the context's stream, except
+ *     where a comment says "host".  fr_create copies its host arrays.
+ *   - streams: all work is enqueued on the stream set with fr_set_stream
+ *     (default: the null stream) and the calls return without waiting,
+ *     except fr_stats and fr_create, which synchronise.  One context must
+ *     not be used from two host threads at once.
+ *   - layouts: per-vertex arrays are structure-of-arrays [3][V] (x row, then
+ *     y, then z; or r, g, b); bases are [K][3][V]; images are row-major
+ *     [H][W][3] float; lights are [n][3] RGB.
+ */
+#ifndef FACERT_H
+#define FACERT_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    FR_OK = 0,
+    FR_EINVAL = -1,   /* bad argument: size, null, non-finite, degenerate */
+    FR_ENOMEM = -2,   /* device allocation failed                        */
+    FR_EDEVICE = -3,  /* a HIP call failed; message in fr_last_error     */
+    FR_ESTATE = -4    /* call out of order (backward before render)      */
+} fr_status;
+
+typedef struct fr_ctx fr_ctx;
+
+/* Morphable face model (host arrays, copied by fr_create). */
+typedef struct {
+    int32_t n_vertices, n_faces;     /* V, F                                   */
+    int32_t n_id, n_exp, n_alb;      /* basis sizes (80, 90, 80 in the paper)  */
+    const int32_t *faces;            /* [F][3], counter-clockwise seen from
+                                        the front; a manifold mesh (each edge
+                                        in at most two faces)                  */
+    const float *mean;               /* [3][V] mean shape                      */
+    const float *b_id;               /* [n_id][3][V] identity basis            */
+    const float *b_exp;              /* [n_exp][3][V] expression basis         */
+    const float *alb_mean;           /* [3][V] mean RGB albedo                 */
+    const float *b_alb;              /* [n_alb][3][V] albedo basis             */
+    const float *uv;                 /* [2][V] specular-texture coordinates    */
+} fr_model_desc;
+
+/* Camera and light stage (host arrays, copied by fr_create). */
+typedef struct {
+    int32_t width, height;           /* image size in pixels                   */
+    float cam[3];                    /* pinhole centre; the camera looks along
+                                        -z, image y points down               */
+    float pix_scale;                 /* size of one pixel on the plane at unit
+                                        distance (tan(fov_y/2) / (H/2))        */
+    int32_t n_lights;                /* N (20 in the paper), 1..64             */
+    const float *light_geom;         /* [N][12]: centre, edge e1, edge e2, unit
+                                        emitting normal (along e1 x e2); each
+                                        light is the parallelogram
+                                        centre + s e1 + t e2, |s|,|t| <= 1/2  */
+    int32_t spec_res;                /* specular texture side (32)             */
+} fr_scene_desc;
+
+/* Parameters of one evaluation.  Device pointers except pose. */
+typedef struct {
+    const float *alpha;              /* [n_id]                                 */
+    const float *beta;               /* [n_exp]                                */
+    const float *delta;              /* [n_alb]                                */
+    const float *pose;               /* HOST [6]: rx, ry, rz (radians), t;
+                                        R = Rz(rz) Ry(ry) Rx(rx), v = R v + t  */
+    const float *lights;             /* [N][3] RGB intensities l_j             */
+    const float *spec;               /* [spec_res^2] gray specular texels      */
+} fr_params;
+
+/* Gradient outputs (device pointers, each nullable; overwritten). */
+typedef struct {
+    float *d_lights;                 /* [N][3]                                 */
+    float *d_spec;                   /* [spec_res^2]                           */
+    float *d_vertices;               /* [3][V] w.r.t. posed vertex positions   */
+    float *d_albedo;                 /* [3][V] w.r.t. per-vertex albedo        */
+    float *d_alpha;                  /* [n_id]                                 */
+    float *d_beta;                   /* [n_exp]                                */
+    float *d_delta;                  /* [n_alb]                                */
+    float *d_pose;                   /* [6]                                    */
+} fr_grads;
+
+typedef struct {
+    /* rays traced by the last fr_render + fr_backward */
+    uint64_t rays_camera, rays_shadow, rays_edge_primary, rays_edge_secondary;
+    uint64_t traversal_overflow;     /* must be 0                              */
+    uint64_t box_tests, tri_tests;   /* BVH node and triangle tests performed  */
+    /* per kernel: [0] forward render, [1] interior adjoint (fp32 and fp64
+       passes), [2] camera-silhouette edges, [3] shadow-boundary edges */
+    uint64_t kernel_rays[4], kernel_box_tests[4], kernel_tri_tests[4], kernel_shades[4];
+    uint64_t grazing_samples;        /* camera samples adjoined in fp64        */
+    /* milliseconds of the last calls (when FR_TIMING was given)              */
+    float ms_blend, ms_bvh, ms_edges, ms_render, ms_backward;
+    float ms_kernel_fwd, ms_kernel_adj;  /* the forward and adjoint kernels alone */
+} fr_stats_t;
+
+#define FR_TIMING 1u                 /* fr_create flag: time phases with events */
+
+/* Backward terms (fr_set_terms); all on by default. */
+#define FR_TERM_INTERIOR  1u
+#define FR_TERM_PRIMARY   2u         /* camera-silhouette edges                 */
+#define FR_TERM_SECONDARY 4u         /* shadow-boundary edges                   */
+
+/* Create a context: copies the model and scene to the device, builds the
+ * topology (edges, vertex-to-face lists, BVH tree order).  flags: FR_TIMING.
+ * Errors: FR_EINVAL (sizes <= 0, null arrays, non-manifold mesh, index out
+ * of range, n_lights > 64), FR_ENOMEM, FR_EDEVICE.  *out is NULL on error. */
+int fr_create(const fr_model_desc *model, const fr_scene_desc *scene,
+              uint32_t flags, fr_ctx **out);
+
+/* Enqueue all later work on this HIP stream (hipStream_t). */
+int fr_set_stream(fr_ctx *ctx, void *hip_stream);
+
+/* Select the backward terms (bit set of FR_TERM_*). */
+int fr_set_terms(fr_ctx *ctx, uint32_t terms);
+
+/* Morphable blend (Face Modeling paragraph): v_model = mean + B_id alpha +
+ * B_exp beta, v = R v_model + t, A = alb_mean + B_alb delta, vertex normals.
+ * Sums run over k in ascending order in double precision; positions and
+ * albedo are then rounded to float.  out_vertices [3][V] and out_albedo
+ * [3][V] (device, nullable) receive copies.  Errors: FR_EINVAL for null
+ * alpha/beta/delta/pose or a non-finite pose. */
+int fr_blend(fr_ctx *ctx, const float *alpha, const float *beta, const float *delta,
+             const float *pose, float *out_vertices, float *out_albedo);
+
+/* Monte-Carlo render (Optimization paragraph, estimator F): blend, BVH refit,
+ * edge tables, then per pixel the mean over spp jittered camera samples of
+ * the direct light from every light (one area sample and one shadow ray per
+ * light per hit).  out_image [H][W][3] (device).  The realisation is fixed by
+ * (params, seed, spp) and bitwise reproducible.  Errors: FR_EINVAL (spp < 1
+ * or > 4096, null pointers). */
+int fr_render(fr_ctx *ctx, const fr_params *params, uint64_t seed, int32_t spp,
+              float *out_image);
+
+/* Adjoint of the last fr_render: given dL/dimage [H][W][3] (device), write
+ * the requested gradients.  Uses the parameters, seed and spp of the last
+ * render (the caller must keep its device arrays alive until this call is
+ * enqueued).  Gradients are sums over samples with floating-point atomics:
+ * reproducible up to summation order.  Errors: FR_ESTATE without a prior
+ * render, FR_EINVAL for null dL/dimage. */
+int fr_backward(fr_ctx *ctx, const float *dL_dimage, const fr_grads *grads);
+
+/* Squared-L2 photo-consistency loss E_data (Eq. 1) and its image gradient:
+ * dL_dimage = 2 (image - target), *loss_dev = sum (image - target)^2 (one
+ * float, device).  Either output may be NULL.  n = H*W*3. */
+int fr_loss_l2(fr_ctx *ctx, const float *image, const float *target,
+               float *dL_dimage, float *loss_dev);
+
+/* Counters and phase times of the last render/backward (synchronises). */
+int fr_stats(fr_ctx *ctx, fr_stats_t *out);
+
+/* Message of the last error on this context ("" if none); valid until the
+ * next call on the context.  Accepts NULL (returns a static string). */
+const char *fr_last_error(const fr_ctx *ctx);
+
+/* Release all device memory of the context (synchronises its stream). */
+void fr_destroy(fr_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -187,9 +187,12 @@ class OScene:
 
 
 def scene_from_model(model, scene, params):
-    """Blend + pose in float64, round positions to float32 for the decisions."""
+    """Blend + pose in float64, positions rounded once to float32."""
     vm, v, A, R = blend(model, params)
-    osc = OScene(np.ascontiguousarray(model.faces, np.int32), v.astype(np.float32), v,
+    # the rendered mesh is the float32 rounding of the posed blend; the
+    # estimator evaluates it in double
+    v32 = v.astype(np.float32)
+    osc = OScene(np.ascontiguousarray(model.faces, np.int32), v32, v32.astype(np.float64),
                  A, np.ascontiguousarray(model.uv, np.float32), scene.width, scene.height,
                  np.asarray(scene.cam, np.float32), float(scene.pix_scale),
                  np.ascontiguousarray(scene.light_geom, np.float32),
@@ -231,7 +234,7 @@ def render_pixels(osc: OScene, seed: int, spp: int, pixels, threads: int | None 
 
 def record(osc: OScene, seed: int, spp: int, threads: int | None = None):
     st = osc.struct()
-    rec = np.zeros((osc.height * osc.width * spp, 3), np.int32)
+    rec = np.zeros((osc.height * osc.width * spp, 9), np.int32)
     if lib().orc_record_decisions(C.byref(st), seed, spp, threads or default_threads(), _p(rec)):
         raise ValueError("record failed")
     return rec

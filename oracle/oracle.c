@@ -38,6 +38,7 @@
 #define EDGE_OFF_PX 1e-3f       /* screen offset of the two silhouette sides */
 #define EDGE_OFF_M 2e-5f        /* light-plane offset of the two shadow sides */
 #define QSCALE 1048576.0f       /* 2^20: edge weight quantisation            */
+#define ORC_REC_WORDS 9         /* int32 words of one decision record        */
 
 /* ------------------------------------------------------------ Philox ---- */
 /* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two
@@ -580,8 +581,41 @@ typedef struct {
     uint64_t vis;           /* bit j: light sample j lit (horizon and shadow) */
     float b1, b2;           /* single-precision barycentrics          */
     f3 p;                   /* single-precision shading point         */
+    f3 nu;                  /* interpolated vertex normal (unflipped) */
+    f3 wod;                 /* unit direction to the camera           */
+    int tex_ix, tex_iy;     /* bilinear texel cell of the specular map */
     f3 y[MAXL];             /* light sample points                    */
+    uint64_t cs_on, cl_on;  /* bit j: light sample j above the shading
+                               normal / in front of the emitter        */
+    unsigned char gsel[MAXL]; /* V-cavity branch: 0 G=1, 1 G1, 2 G2   */
 } sdec;
+
+/* Branches of the shading whose value is continuous but whose slope jumps
+ * (the clamps of cos_s and cos_l, the min of the V-cavity term) are taken
+ * as single-precision decisions too, from the decision values of the
+ * sample, so that value path and adjoint follow the same branch on every
+ * implementation.  The V-cavity comparisons are G1, G2 >= 1 and G1 <= G2
+ * written with unnormalised dot products (all positive factors cancel). */
+static void light_branch(const sdec *D, f3 nj, f3 y, int *cs, int *cl, int *gs) {
+    f3 r = fsub(y, D->p);
+    f3 nn = D->nu;
+    if (!D->front) { nn.x = -nn.x; nn.y = -nn.y; nn.z = -nn.z; }
+    *cs = fdot(nn, r) > 0.0f;
+    *cl = fdot(nj, r) < 0.0f;
+    *gs = 0;
+    if (D->spec_on && *cs) {
+        float lr = sqrtf(fdot(r, r));
+        f3 wi = {r.x / lr, r.y / lr, r.z / lr};
+        f3 hs = {wi.x + D->wod.x, wi.y + D->wod.y, wi.z + D->wod.z};
+        float a_s = fdot(nn, wi), a_o = fdot(nn, D->wod);
+        float nh = fdot(nn, hs), oh2 = fdot(D->wod, hs), n2 = fdot(D->nu, D->nu);
+        float rhs = oh2 * n2;
+        float g1 = (2.0f * nh) * a_o, g2 = (2.0f * nh) * a_s;
+        if (g1 >= rhs && g2 >= rhs) *gs = 0;
+        else if (a_o <= a_s) *gs = 1;
+        else *gs = 2;
+    }
+}
 
 static inline f3 light_point(const orc_scene *s, int j, float u, float v) {
     f3 c = light_c(s, j), e1 = light_e1(s, j), e2 = light_e2(s, j);
@@ -622,10 +656,25 @@ static void decide(const rctx *C, float qx, float qy, const float *lu, sdec *D, 
     nu.z = (b0 * N[2 * V + tr[0]] + b1 * N[2 * V + tr[1]]) + b2 * N[2 * V + tr[2]];
     float co = fdot(nu, fsub(o, p));
     D->spec_on = D->front ? co > 0.0f : co < 0.0f;
+    D->nu = nu;
+    f3 c = fsub(o, p);
+    float lc = sqrtf(fdot(c, c));
+    D->wod.x = c.x / lc; D->wod.y = c.y / lc; D->wod.z = c.z / lc;
+    /* texel cell: texel centres at (i + 1/2)/res */
+    float ux = (b0 * s->uv[tr[0]] + b1 * s->uv[tr[1]]) + b2 * s->uv[tr[2]];
+    float uy = (b0 * s->uv[V + tr[0]] + b1 * s->uv[V + tr[1]]) + b2 * s->uv[V + tr[2]];
+    D->tex_ix = (int)floorf((float)s->spec_res * ux - 0.5f);
+    D->tex_iy = (int)floorf((float)s->spec_res * uy - 0.5f);
+    D->cs_on = D->cl_on = 0;
     f3 ng = fcross(fsub(v1, v0), fsub(v2, v0));
     for (int j = 0; j < s->n_lights; ++j) {
         f3 y = light_point(s, j, lu[2 * j], lu[2 * j + 1]);
         D->y[j] = y;
+        int cs, cl, gs;
+        light_branch(D, light_n(s, j), y, &cs, &cl, &gs);
+        D->cs_on |= (uint64_t)cs << j;
+        D->cl_on |= (uint64_t)cl << j;
+        D->gsel[j] = (unsigned char)gs;
         f3 r = fsub(y, p);
         float hz = fdot(ng, r);
         int above = D->front ? hz > 0.0f : hz < 0.0f;
@@ -681,10 +730,11 @@ static void geo_eval(const rctx *C, f3 of, f3 df, const sdec *D, sgeo *G) {
     G->uvy = G->b[0] * s->uv[V + tr[0]] + b1 * s->uv[V + tr[1]] + b2 * s->uv[V + tr[2]];
     /* bilinear, texel centres at (i+0.5)/res, clamp to edge */
     int R = s->spec_res;
+    /* the cell is a decision (its slope jumps at texel centres); the
+       weights are the value path's, linear beyond the cell if need be */
     double x = R * G->uvx - 0.5, y = R * G->uvy - 0.5;
-    double fx0 = floor(x), fy0 = floor(y);
-    double fx = x - fx0, fy = y - fy0;
-    int ix0 = (int)fx0, iy0 = (int)fy0;
+    int ix0 = D->tex_ix, iy0 = D->tex_iy;
+    double fx = x - ix0, fy = y - iy0;
     int ix[2] = {ix0, ix0 + 1}, iy[2] = {iy0, iy0 + 1};
     for (int k = 0; k < 2; ++k) {
         ix[k] = ix[k] < 0 ? 0 : (ix[k] > R - 1 ? R - 1 : ix[k]);
@@ -713,8 +763,8 @@ typedef struct {
     double gl[3];        /* adjoint w.r.t. l_j           */
 } ladj;
 
-static void shade_light(const rctx *C, const sgeo *G, int spec_on, int j, d3 y,
-                        const double *w /* RGB weights or NULL */, double out[3], ladj *adj) {
+static void shade_light(const rctx *C, const sgeo *G, int spec_on, int cs_on, int cl_on, int gsel_in,
+                        int j, d3 y, const double *w /* RGB weights or NULL */, double out[3], ladj *adj) {
     const orc_scene *s = C->s;
     const double *l = s->light_rgb + 3 * j;
     d3 nj = d_of(light_n(s, j));
@@ -722,13 +772,14 @@ static void shade_light(const rctx *C, const sgeo *G, int spec_on, int j, d3 y,
     d3 r = dsub(y, G->p);
     double d2 = ddot(r, r), dist = sqrt(d2);
     d3 wi = dscl(r, 1.0 / dist);
-    double cl_raw = -ddot(nj, wi), cos_l = cl_raw > 0 ? cl_raw : 0;
-    double cs_raw = ddot(G->ns, wi), cos_s = cs_raw > 0 ? cs_raw : 0;
+    /* clamps and the V-cavity min follow the sample's decisions */
+    double cl_raw = -ddot(nj, wi), cos_l = cl_on ? cl_raw : 0;
+    double cs_raw = ddot(G->ns, wi), cos_s = cs_on ? cs_raw : 0;
     double g = cos_l * area / d2;
     double S = 0, D = 0, Gv = 0, ch = 0, oh = 0, lh = 0;
-    int gsel = 0;            /* 0: G = 1, 1: G1, 2: G2 */
+    int gsel = gsel_in;      /* 0: G = 1, 1: G1, 2: G2 */
     d3 h = dmk(0, 0, 0);
-    int spec = spec_on && cs_raw > 0;
+    int spec = spec_on && cs_on;
     if (spec) {
         d3 hv = dadd(wi, G->wo);
         lh = dlen(hv);
@@ -738,9 +789,7 @@ static void shade_light(const rctx *C, const sgeo *G, int spec_on, int j, d3 y,
         double m2 = BECKMANN_M * BECKMANN_M, c2 = ch * ch;
         D = exp(-(1.0 - c2) / (c2 * m2)) / (PI * m2 * c2 * c2);
         double G1 = 2.0 * ch * G->cos_o / oh, G2 = 2.0 * ch * cos_s / oh;
-        if (1.0 <= G1 && 1.0 <= G2) { Gv = 1.0; gsel = 0; }
-        else if (G1 <= G2) { Gv = G1; gsel = 1; }
-        else { Gv = G2; gsel = 2; }
+        Gv = gsel == 0 ? 1.0 : (gsel == 1 ? G1 : G2);
         S = G->ks * D * Gv / (4.0 * G->cos_o);
     }
     for (int c = 0; c < 3; ++c) out[c] = l[c] * (G->A[c] / PI * cos_s + S) * g;
@@ -789,8 +838,8 @@ static void shade_light(const rctx *C, const sgeo *G, int spec_on, int j, d3 y,
     g_ns = dadd(g_ns, dscl(G->wo, g_cos_o));
     g_wo = dadd(g_wo, dscl(G->ns, g_cos_o));
     /* clamps */
-    double g_cs_raw = cs_raw > 0 ? g_cos_s : 0;
-    double g_cl_raw = cl_raw > 0 ? g_cos_l : 0;
+    double g_cs_raw = cs_on ? g_cos_s : 0;
+    double g_cl_raw = cl_on ? g_cos_l : 0;
     g_ns = dadd(g_ns, dscl(wi, g_cs_raw));
     g_wi = dadd(g_wi, dscl(G->ns, g_cs_raw));
     g_wi = dadd(g_wi, dscl(nj, -g_cl_raw));
@@ -810,7 +859,8 @@ static void sample_value(const rctx *C, f3 o, f3 d, const sdec *D, double out[3]
     for (int j = 0; j < C->s->n_lights; ++j) {
         if (!((D->vis >> j) & 1)) continue;
         double c[3];
-        shade_light(C, &G, D->spec_on, j, d_of(D->y[j]), NULL, c, NULL);
+        shade_light(C, &G, D->spec_on, (D->cs_on >> j) & 1, (D->cl_on >> j) & 1, D->gsel[j], j,
+                    d_of(D->y[j]), NULL, c, NULL);
         out[0] += c[0]; out[1] += c[1]; out[2] += c[2];
     }
 }
@@ -856,7 +906,14 @@ static void rec_to_dec(const rctx *C, const int32_t *rec, const float *lu, sdec 
     D->front = rec[1] & 1;
     D->spec_on = (rec[1] >> 1) & 1;
     D->vis = (uint32_t)rec[2];
-    for (int j = 0; j < C->s->n_lights; ++j) D->y[j] = light_point(C->s, j, lu[2 * j], lu[2 * j + 1]);
+    D->cs_on = (uint32_t)rec[3];
+    D->cl_on = (uint32_t)rec[4];
+    D->tex_ix = rec[7];
+    D->tex_iy = rec[8];
+    for (int j = 0; j < C->s->n_lights; ++j) {
+        D->y[j] = light_point(C->s, j, lu[2 * j], lu[2 * j + 1]);
+        D->gsel[j] = (unsigned char)(((uint32_t)rec[5 + j / 16] >> (2 * (j % 16))) & 3u);
+    }
 }
 
 /* Chain p (ray fixed) and barycentric adjoints into the hit triangle's
@@ -883,7 +940,8 @@ static void sample_adjoint(const rctx *C, f3 o, f3 d, const sdec *D, const doubl
         if (!((D->vis >> j) & 1)) continue;
         double c[3];
         ladj a;
-        shade_light(C, &G, D->spec_on, j, d_of(D->y[j]), w, c, &a);
+        shade_light(C, &G, D->spec_on, (D->cs_on >> j) & 1, (D->cl_on >> j) & 1, D->gsel[j], j,
+                    d_of(D->y[j]), w, c, &a);
         for (int k = 0; k < 3; ++k) { g->d_light[3 * j + k] += a.gl[k]; gA[k] += a.gA[k]; }
         gks += a.gks;
         gp = dadd(gp, a.gp); gns = dadd(gns, a.gns); gwo = dadd(gwo, a.gwo);
@@ -969,7 +1027,9 @@ static void sample_secondary(const rctx *C, uint64_t seed, int64_t sidx, f3 o, f
         if (!geo_done) { geo_eval(C, o, d, D, &G); geo_done = 1; }
         d3 yd = d_of(y);
         double hc[3];
-        shade_light(C, &G, D->spec_on, j, yd, NULL, hc, NULL);
+        int cs, cl, gs;
+        light_branch(D, nj, y, &cs, &cl, &gs);
+        shade_light(C, &G, D->spec_on, cs, cl, gs, j, yd, NULL, hc, NULL);
         /* hc includes the light area factor; the boundary integral is per unit area */
         double area = light_area(s, j);
         double hw = (w[0] * hc[0] + w[1] * hc[1] + w[2] * hc[2]) / area;
@@ -1095,13 +1155,21 @@ static void *job_run(void *arg) {
         float qx = (float)px + u01(w[0]), qy = (float)py + u01(w[1]);
         f3 d = camera_dir(s, qx, qy);
         sdec D;
-        if (J->mode == 2 || J->mode == 4) rec_to_dec(C, J->rec_in + 3 * sidx, lu, &D);
+        if (J->mode == 2 || J->mode == 4) rec_to_dec(C, J->rec_in + ORC_REC_WORDS * sidx, lu, &D);
         else decide(C, qx, qy, lu, &D, &J->cnt);
         if (J->mode == 1) {
-            int32_t *r = J->rec_out + 3 * sidx;
+            int32_t *r = J->rec_out + ORC_REC_WORDS * sidx;
+            memset(r, 0, sizeof(int32_t) * ORC_REC_WORDS);
             r[0] = D.tri;
-            r[1] = (D.tri >= 0) ? (D.front | (D.spec_on << 1) | 4) : 0;
-            r[2] = (int32_t)(uint32_t)D.vis;
+            if (D.tri >= 0) {
+                r[1] = D.front | (D.spec_on << 1) | 4;
+                r[2] = (int32_t)(uint32_t)D.vis;
+                r[3] = (int32_t)(uint32_t)D.cs_on;
+                r[4] = (int32_t)(uint32_t)D.cl_on;
+                for (int j = 0; j < nl; ++j) r[5 + j / 16] |= (int32_t)((uint32_t)D.gsel[j] << (2 * (j % 16)));
+                r[7] = D.tex_ix;
+                r[8] = D.tex_iy;
+            }
             continue;
         }
         if (J->mode == 0 || J->mode == 2) {

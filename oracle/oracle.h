@@ -22,9 +22,11 @@
  * Precision: every continuous quantity is computed in IEEE double.  Every
  * floating-point comparison that decides an integer outcome (which triangle
  * a ray hits, whether a shadow ray is blocked, which side of a triangle is
- * seen, which edge a sample picks) is taken in IEEE single precision with a
- * fixed operation order and no contraction, which is the precision the GPU
- * kernels use.  Random numbers come from Philox4x32-10 (Salmon et al. 2011).
+ * seen, which edge a sample picks, which branch of a clamp or of the
+ * V-cavity min a light sample takes, which texel cell it reads) is taken in
+ * IEEE single precision with a fixed operation order and no contraction,
+ * which is the precision the GPU kernels use.  Random numbers come from
+ * Philox4x32-10 (Salmon et al. 2011).
  *
  * Parity pins (see the test suite): Philox known-answer vectors; blend
  * against a float64 matrix product; normals on flat and spherical grids;
@@ -120,9 +122,11 @@ int orc_render(const orc_scene *s, uint64_t seed, int32_t spp, int32_t nthreads,
 int orc_render_pixels(const orc_scene *s, uint64_t seed, int32_t spp,
                       int32_t n, const int32_t *pix, int32_t nthreads, double *out);
 
-/* Decision record of every camera sample (for frozen-decision checks):
- * rec[s] = {tri, flags, vis_mask} where flags bit0 = front-facing,
- * bit1 = specular lobe active, bit2 = hit. */
+/* Decision record of every camera sample (for frozen-decision checks), 9
+ * int32 words: tri, flags (bit0 front-facing, bit1 specular lobe active,
+ * bit2 hit), visibility mask, cos_s-clamp mask, cos_l-clamp mask, V-cavity
+ * branches (2 bits per light, lights 0-15 then 16-31), texel cell x, y.
+ * At most 32 lights. */
 int orc_record_decisions(const orc_scene *s, uint64_t seed, int32_t spp,
                          int32_t nthreads, int32_t *rec);
 /* Re-evaluate the estimator with decisions frozen from rec (value path only,

@@ -1,0 +1,1410 @@
+// facert: differentiable light-stage face renderer for MI355X (gfx950).
+//
+// Kernels and the C-ABI declared in include/facert.h.  Build with
+//   hipcc --offload-arch=gfx950 -O3 -ffp-contract=off -fPIC -shared
+// (no contraction: the fp32 decision arithmetic must round every operation
+// on its own, see fr_device.hpp).
+//
+// Per evaluation (fr_render):
+//   k_blend          morphable model (Face Modeling paragraph), fp64 sums
+//   k_normals        vertex normals, fixed-order gather over incident faces
+//   k_refit          BVH boxes bottom-up (tree order fixed at creation)
+//   k_edge_weights   camera-silhouette and per-light shadow-candidate edges
+//   k_edge_scan      integer CDFs of the edge weights (one block per table)
+//   k_render_fwd     one lane per camera sample: closest hit, 20 lights,
+//                    shadow rays, Cook-Torrance (Optimization paragraph: F)
+//   k_pixel_mean     fixed-order mean of each pixel's samples
+// Adjoint (fr_backward):
+//   k_render_adj     recomputes each camera sample, reverse mode through the
+//                    shading, scatters to lights/texels/albedo/normals/vertices,
+//                    plus the shadow-boundary edge sample of each light
+//   k_edge_primary   camera-silhouette edge samples
+//   k_normal_adj, k_chain_gather, k_param_partial, k_param_final
+//                    normal chain, transposed blend and pose reductions
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/facert.h"
+#include "fr_device.hpp"
+
+using namespace fr;
+
+// ====================================================================== //
+//                               kernels                                  //
+// ====================================================================== //
+
+// ---------------------------------------------------------- blend -------
+// v_model = mean + sum_k B_id[k] alpha_k + sum_k B_exp[k] beta_k  (fp64,
+// k ascending, identity first); v = R v_model + t (fp64); A = alb_mean +
+// sum_k B_alb[k] delta_k (fp64).  Rounded to fp32.  One thread per vertex;
+// the k-loop reads one row of each basis, coalesced across the wave.
+struct PoseArgs { double R[9]; double t[3]; };
+
+__global__ __launch_bounds__(256) void k_blend(int V, int n_id, int n_exp, int n_alb,
+        const float *__restrict__ mean, const float *__restrict__ b_id, const float *__restrict__ b_exp,
+        const float *__restrict__ alb_mean, const float *__restrict__ b_alb,
+        const float *__restrict__ alpha, const float *__restrict__ beta, const float *__restrict__ delta,
+        PoseArgs P, float *__restrict__ vmodel, float *__restrict__ pos, float *__restrict__ alb) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= V) return;
+    size_t V3 = (size_t)3 * V;
+    double m[3];
+    for (int c = 0; c < 3; ++c) {
+        size_t e = (size_t)c * V + i;
+        double acc = (double)mean[e];
+        for (int k = 0; k < n_id; ++k) acc = acc + (double)b_id[k * V3 + e] * (double)alpha[k];
+        for (int k = 0; k < n_exp; ++k) acc = acc + (double)b_exp[k * V3 + e] * (double)beta[k];
+        m[c] = acc;
+        vmodel[e] = (float)acc;
+    }
+    for (int c = 0; c < 3; ++c) {
+        double v = ((P.R[3 * c] * m[0] + P.R[3 * c + 1] * m[1]) + P.R[3 * c + 2] * m[2]) + P.t[c];
+        pos[(size_t)c * V + i] = (float)v;
+    }
+    for (int c = 0; c < 3; ++c) {
+        size_t e = (size_t)c * V + i;
+        double acc = (double)alb_mean[e];
+        for (int k = 0; k < n_alb; ++k) acc = acc + (double)b_alb[k * V3 + e] * (double)delta[k];
+        alb[e] = (float)acc;
+    }
+}
+
+// ---------------------------------------------------------- normals -----
+// n_k = normalize(sum over incident faces, ascending index, of
+// (v1 - v0) x (v2 - v0)), fp64 from the fp32 positions, rounded to fp32.
+__global__ __launch_bounds__(256) void k_normals(int V, const int *__restrict__ faces,
+        const int *__restrict__ vf_off, const int *__restrict__ vf_idx,
+        const float *__restrict__ pos, float *__restrict__ nrm, float *__restrict__ nlen) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= V) return;
+    double sx = 0.0, sy = 0.0, sz = 0.0;
+    for (int q = vf_off[i]; q < vf_off[i + 1]; ++q) {
+        const int *t = faces + 3 * vf_idx[q];
+        double x0 = pos[t[0]], y0 = pos[V + t[0]], z0 = pos[2 * V + t[0]];
+        double ax = (double)pos[t[1]] - x0, ay = (double)pos[V + t[1]] - y0, az = (double)pos[2 * V + t[1]] - z0;
+        double bx = (double)pos[t[2]] - x0, by = (double)pos[V + t[2]] - y0, bz = (double)pos[2 * V + t[2]] - z0;
+        sx = sx + (ay * bz - az * by);
+        sy = sy + (az * bx - ax * bz);
+        sz = sz + (ax * by - ay * bx);
+    }
+    double l = sqrt((sx * sx + sy * sy) + sz * sz);
+    if (l > 0.0) { sx = sx / l; sy = sy / l; sz = sz / l; }
+    nrm[i] = (float)sx; nrm[V + i] = (float)sy; nrm[2 * V + i] = (float)sz;
+    nlen[i] = (float)l;
+}
+
+// ------------------------------------------------------------ refit -----
+// Leaf boxes from the current triangles, then unions up the tree: the
+// second child to finish (odd arrival count; counts only grow, so no reset
+// is needed between evaluations) builds its parent's box.
+__global__ __launch_bounds__(256) void k_refit(int F, const int *__restrict__ faces, const float *__restrict__ pos, int V,
+        const int *__restrict__ sorted_tri, const int *__restrict__ leaf_node,
+        const int *__restrict__ parent, const int *__restrict__ right, const int *__restrict__ escape,
+        unsigned int *__restrict__ arrive, float4 *nodes, float4 *__restrict__ tris) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= F) return;
+    int f = sorted_tri[i];
+    const int *t = faces + 3 * f;
+    v3 a = vpos_raw(pos, V, t[0]), b = vpos_raw(pos, V, t[1]), c = vpos_raw(pos, V, t[2]);
+    tris[3 * i] = make_float4(a.x, a.y, a.z, b.x);
+    tris[3 * i + 1] = make_float4(b.y, b.z, c.x, c.y);
+    tris[3 * i + 2] = make_float4(c.z, __int_as_float(f), 0.0f, 0.0f);
+    int n = leaf_node[i];
+    float4 lo = make_float4(fminf(fminf(a.x, b.x), c.x) - kBoxPad, fminf(fminf(a.y, b.y), c.y) - kBoxPad,
+                            fminf(fminf(a.z, b.z), c.z) - kBoxPad, __int_as_float(escape[n]));
+    float4 hi = make_float4(fmaxf(fmaxf(a.x, b.x), c.x) + kBoxPad, fmaxf(fmaxf(a.y, b.y), c.y) + kBoxPad,
+                            fmaxf(fmaxf(a.z, b.z), c.z) + kBoxPad, __int_as_float(i));
+    nodes[2 * n] = lo;
+    nodes[2 * n + 1] = hi;
+    __threadfence();
+    int p = parent[n];
+    while (p >= 0) {
+        unsigned int old = atomicAdd(&arrive[p], 1u);
+        if ((old & 1u) == 0u) return;            // first child: the sibling continues
+        __threadfence();
+        const volatile float4 *vn = nodes;
+        int l = p + 1, r = right[p];
+        float4 la = const_cast<const float4 &>(vn[2 * l]), lb = const_cast<const float4 &>(vn[2 * l + 1]);
+        float4 ra = const_cast<const float4 &>(vn[2 * r]), rb = const_cast<const float4 &>(vn[2 * r + 1]);
+        nodes[2 * p] = make_float4(fminf(la.x, ra.x), fminf(la.y, ra.y), fminf(la.z, ra.z), __int_as_float(escape[p]));
+        nodes[2 * p + 1] = make_float4(fmaxf(lb.x, rb.x), fmaxf(lb.y, rb.y), fmaxf(lb.z, rb.z), __int_as_float(-1));
+        __threadfence();
+        p = parent[p];
+    }
+}
+
+// ------------------------------------------------------- edge tables ----
+__device__ __forceinline__ bool project(const Scene &S, v3 x, float &sx, float &sy) {
+    v3 r = x - mk(S.cam_x, S.cam_y, S.cam_z);
+    if (!(r.z < 0.0f)) return false;
+    float nz = -r.z;
+    sx = 0.5f * (float)S.W + (r.x / nz) / S.ps;
+    sy = 0.5f * (float)S.H - (r.y / nz) / S.ps;
+    return true;
+}
+
+// weights: table 0 = camera silhouettes (screen length), table 1+j = shadow
+// candidates of light j (3D length); the max of each table via atomicMax
+// on the (non-negative) float bits.
+__global__ __launch_bounds__(256) void k_edge_weights(Scene S, const float *__restrict__ lgeom,
+        float *__restrict__ w, unsigned int *__restrict__ wmax) {
+    int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= S.E) return;
+    const int *ed = S.edges + 4 * e;
+    v3 a = vpos(S, ed[0]), b = vpos(S, ed[1]);
+    bool interior = ed[3] >= 0;
+    v3 n1 = mk(0, 0, 0), n2 = mk(0, 0, 0), o1 = mk(0, 0, 0), o2 = mk(0, 0, 0);
+    if (interior) {
+        n1 = face_normal(S, ed[2]); n2 = face_normal(S, ed[3]);
+        o1 = vpos(S, S.faces[3 * ed[2]]); o2 = vpos(S, S.faces[3 * ed[3]]);
+    }
+    size_t E = (size_t)S.E;
+    v3 cam = mk(S.cam_x, S.cam_y, S.cam_z);
+    bool sil = true;
+    if (interior) {
+        float s1 = dot(n1, cam - o1), s2 = dot(n2, cam - o2);
+        sil = (s1 > 0.0f) != (s2 > 0.0f);
+    }
+    float we = 0.0f, ax, ay, bx, by;
+    if (sil && project(S, a, ax, ay) && project(S, b, bx, by)) {
+        float dx = bx - ax, dy = by - ay;
+        we = sqrtf(dx * dx + dy * dy);
+    }
+    w[e] = we;
+    atomicMax(&wmax[0], __float_as_uint(we));
+    v3 ab = b - a;
+    float l3 = sqrtf(dot(ab, ab));
+    for (int j = 0; j < S.nl; ++j) {
+        const float *g = lgeom + 12 * j;
+        v3 c = mk(g[0], g[1], g[2]), e1 = mk(g[3], g[4], g[5]), e2 = mk(g[6], g[7], g[8]);
+        bool cand = true;
+        if (interior) {
+            int posc = 0, negc = 0;
+            for (int k = 0; k < 4; ++k) {
+                float s1 = (k & 1) ? 0.5f : -0.5f, s2 = (k & 2) ? 0.5f : -0.5f;
+                v3 x = mk((c.x + s1 * e1.x) + s2 * e2.x, (c.y + s1 * e1.y) + s2 * e2.y, (c.z + s1 * e1.z) + s2 * e2.z);
+                int g1 = dot(n1, x - o1) > 0.0f, g2 = dot(n2, x - o2) > 0.0f;
+                posc += g1 + g2; negc += 2 - g1 - g2;
+            }
+            cand = posc > 0 && negc > 0;
+        }
+        float wj = cand ? l3 : 0.0f;
+        w[(size_t)(1 + j) * E + e] = wj;
+        atomicMax(&wmax[1 + j], __float_as_uint(wj));
+    }
+}
+
+// One block per table: quantise q = 1 + floor(w / wmax * 2^20) for w > 0,
+// exclusive uint64 prefix in edge order, compacted to (edge, prefix) pairs.
+template <int BS>
+__global__ __launch_bounds__(BS) void k_edge_scan(int E, const float *__restrict__ w, const unsigned int *__restrict__ wmax,
+        int *__restrict__ out_edge, uint64_t *__restrict__ out_prefix, int *__restrict__ out_n, uint64_t *__restrict__ out_Q) {
+    int tbl = blockIdx.x;
+    const float *wt = w + (size_t)tbl * E;
+    int *oe = out_edge + (size_t)tbl * E;
+    uint64_t *op = out_prefix + (size_t)tbl * E;
+    float wm = __uint_as_float(wmax[tbl]);
+    __shared__ uint64_t s_sum[BS];
+    __shared__ int s_cnt[BS];
+    __shared__ uint64_t s_base;
+    __shared__ int s_nbase;
+    if (threadIdx.x == 0) { s_base = 0; s_nbase = 0; }
+    __syncthreads();
+    for (int start = 0; start < E; start += BS) {
+        int e = start + threadIdx.x;
+        uint64_t q = 0;
+        if (e < E) {
+            float we = wt[e];
+            if (we > 0.0f && wm > 0.0f) q = 1u + (uint32_t)floorf((we / wm) * kQScale);
+        }
+        s_sum[threadIdx.x] = q;
+        s_cnt[threadIdx.x] = q > 0;
+        __syncthreads();
+        // inclusive Hillis-Steele scan (integers: order-independent)
+        for (int off = 1; off < BS; off <<= 1) {
+            uint64_t v = threadIdx.x >= off ? s_sum[threadIdx.x - off] : 0;
+            int c = threadIdx.x >= off ? s_cnt[threadIdx.x - off] : 0;
+            __syncthreads();
+            s_sum[threadIdx.x] += v;
+            s_cnt[threadIdx.x] += c;
+            __syncthreads();
+        }
+        if (q > 0) {
+            int slot = s_nbase + s_cnt[threadIdx.x] - 1;
+            oe[slot] = e;
+            op[slot] = s_base + s_sum[threadIdx.x] - q;
+        }
+        __syncthreads();
+        if (threadIdx.x == BS - 1) { s_base += s_sum[BS - 1]; s_nbase += s_cnt[BS - 1]; }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) { out_n[tbl] = s_nbase; out_Q[tbl] = s_base; }
+}
+
+// ------------------------------------------------------ LDS staging -----
+__device__ inline void stage_tables(const Scene &S, Light *Ls, float *spec_lds) {
+    for (int j = threadIdx.x; j < S.nl; j += blockDim.x) {
+        const float *g = S.lgeom + 12 * j;
+        Light L;
+        L.c = mk(g[0], g[1], g[2]); L.e1 = mk(g[3], g[4], g[5]); L.e2 = mk(g[6], g[7], g[8]);
+        L.n = mk(g[9], g[10], g[11]);
+        L.area = len(cross(L.e1, L.e2));
+        L.r = S.lrgb[3 * j]; L.g = S.lrgb[3 * j + 1]; L.b = S.lrgb[3 * j + 2];
+        Ls[j] = L;
+    }
+    for (int k = threadIdx.x; k < S.res * S.res; k += blockDim.x) spec_lds[k] = S.spec[k];
+}
+
+// light j's (u, v) for a sample whose light words start at word 'off'
+// (off + 2j, off + 2j + 1) of counters (idx, block, tag, 0)
+struct LightRng {
+    uint64_t seed; uint32_t idx, tag; int off; int cur; u4 blk;
+    __device__ LightRng(uint64_t s, uint32_t i, uint32_t t, int o) : seed(s), idx(i), tag(t), off(o), cur(-1) {}
+    __device__ __forceinline__ void get(int j, float &u, float &v) {
+        int wi = off + 2 * j, b = wi >> 2;
+        if (b != cur) { blk = philox(seed, idx, (uint32_t)b, tag, 0); cur = b; }
+        if (wi & 2) { u = u01(blk.z); v = u01(blk.w); } else { u = u01(blk.x); v = u01(blk.y); }
+    }
+};
+
+// camera sample s: jittered pixel ray
+__device__ __forceinline__ v3 camera_sample(const Scene &S, uint64_t seed, uint32_t s, int spp, int &pix) {
+    pix = (int)(s / (uint32_t)spp);
+    int px = pix % S.W, py = pix / S.W;
+    u4 w0 = philox(seed, s, 0, 0, 0);
+    return camera_dir(S, (float)px + u01(w0.x), (float)py + u01(w0.y));
+}
+
+// Full radiance through screen point (qx, qy) with lights drawn from rng;
+// decisions in fp32, values in T.
+template <class T>
+__device__ inline void radiance(const Scene &S, const Light *Ls, const float *spec_lds, v3 d,
+                                LightRng &rng, T out[3], uint32_t &n_shadow, Work &wk) {
+    out[0] = out[1] = out[2] = 0;
+    v3 o = mk(S.cam_x, S.cam_y, S.cam_z);
+    Hit h = trace_closest(S, o, d, wk);
+    if (h.tri < 0) return;
+    SurfDec sd;
+    surf_decide(S, o, h, sd);
+    Surf<T> sv;
+    surf_value<T>(S, spec_lds, o, d, h, sd, sv);
+    for (int j = 0; j < S.nl; ++j) {
+        float u, v;
+        rng.get(j, u, v);
+        const Light &L = Ls[j];
+        v3 y = light_point(L, u, v);
+        if (!above(sd, y)) continue;
+        ++n_shadow;
+        if (trace_any(S, sd.p, y - sd.p, h.tri, wk)) continue;
+        T c[3];
+        shade_light<T>(sv, L, cvt<T>(y), light_branch(sd, L.n, y), nullptr, c, nullptr);
+        ++wk.shade;
+        out[0] += c[0]; out[1] += c[1]; out[2] += c[2];
+    }
+}
+
+// counters (8 per kernel): 0 camera, 1 shadow, 2 primary-edge, 3 secondary-edge
+// rays, 4 box tests, 5 triangle tests, 6 shaded light samples
+__device__ inline void flush_count(unsigned long long *ctr, int slot, uint32_t v) {
+    unsigned long long s = v;
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    if ((threadIdx.x & 63) == 0 && s) atomicAdd(&ctr[slot], s);
+}
+__device__ inline void flush_work(unsigned long long *ctr, const Work &w) {
+    flush_count(ctr, 4, w.box);
+    flush_count(ctr, 5, w.tri);
+    flush_count(ctr, 6, w.shade);
+}
+
+__global__ __launch_bounds__(256) void k_render_fwd(Scene S, uint64_t seed, int spp, long long N,
+        float *__restrict__ samples, unsigned long long *ctr) {
+    extern __shared__ float dyn[];
+    __shared__ Light Ls[kMaxLights];
+    float *spec_lds = dyn;
+    stage_tables(S, Ls, spec_lds);
+    __syncthreads();
+    long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t n_cam = 0, n_sh = 0;
+    Work wk;
+    if (s < N) {
+        int pix;
+        v3 d = camera_sample(S, seed, (uint32_t)s, spp, pix);
+        LightRng rng(seed, (uint32_t)s, 0, 2);
+        float c[3];
+        radiance<float>(S, Ls, spec_lds, d, rng, c, n_sh, wk);
+        n_cam = 1;
+        samples[3 * s] = c[0]; samples[3 * s + 1] = c[1]; samples[3 * s + 2] = c[2];
+    }
+    flush_count(ctr, 0, n_cam);
+    flush_count(ctr, 1, n_sh);
+    flush_work(ctr, wk);
+}
+
+__global__ __launch_bounds__(256) void k_pixel_mean(int npix, int spp, const float *__restrict__ samples, float *__restrict__ img) {
+    int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= npix) return;
+    float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f;
+    const float *q = samples + (size_t)3 * p * spp;
+    for (int k = 0; k < spp; ++k) { a0 += q[3 * k]; a1 += q[3 * k + 1]; a2 += q[3 * k + 2]; }
+    float inv = (float)spp;
+    img[3 * p] = a0 / inv; img[3 * p + 1] = a1 / inv; img[3 * p + 2] = a2 / inv;
+}
+
+// ------------------------------------------------------------ adjoint ---
+struct GradBufs {
+    double *d_light;  // [nl*3]
+    double *d_spec;   // [res^2]
+    double *d_pos;    // [3V] (interior + edges, before the normal chain)
+    double *d_nrm;    // [3V]
+    double *d_alb;    // [3V]
+};
+
+// Gradient sums use fp64 hardware atomics (buffers are coarse-grained
+// device memory), which keeps the summation-order noise far below fp32.
+__device__ __forceinline__ void gadd(double *a, double v) { unsafeAtomicAdd(a, v); }
+template <class T> __device__ __forceinline__ void atomic_v(double *a, int V, int i, vec3<T> g) {
+    gadd(&a[i], (double)g.x); gadd(&a[V + i], (double)g.y); gadd(&a[2 * V + i], (double)g.z);
+}
+
+// Chain the adjoints of the shading point p and of the interpolation
+// barycentrics into the hit triangle's vertices, with the camera ray fixed.
+// p = o + t d moves only along the ray: dt/dv_k = b_k N / (N . d), N = e1 x e2.
+// The barycentrics follow v0 + b1 e1 + b2 e2 = o + t d:
+// d(b1, b2) -> z = -(g1 (d x e2) + g2 (e1 x d)) / det, dv_k += b_k z.
+template <class T>
+__device__ inline void chain_hit(int V, const Surf<T> &s, vec3<T> gp, T gb0, T gb1, T gb2, double *d_pos) {
+    T gt = dot(gp, s.dir) / s.ndotd;
+    T g1 = gb1 - gb0, g2 = gb2 - gb0;
+    vec3<T> z = (s.pv * g1 + s.e1xd * g2) * ((T)-1 / s.det);
+    vec3<T> u = s.N * gt + z;
+    for (int k = 0; k < 3; ++k) atomic_v(d_pos, V, s.i[k], u * s.b[k]);
+}
+
+// Interior adjoint of one camera sample (decisions fp32, values T).
+// Light and texel adjoints go to block-shared fp32 accumulators when given,
+// else straight to the fp64 buffers.
+template <class T>
+__device__ inline void adjoint_sample(const Scene &S, const Light *Ls, uint64_t seed, uint32_t s,
+                                      const float *wf, const Hit &h, const SurfDec &sd, const Surf<T> &sv,
+                                      float *g_light_lds, float *g_spec_lds, const GradBufs &G,
+                                      uint32_t &n_sh, Work &wk) {
+    int V = S.V;
+    T w[3] = {(T)wf[0], (T)wf[1], (T)wf[2]};
+    vec3<T> gp = vk<T>(0, 0, 0), gns = vk<T>(0, 0, 0), gwo = vk<T>(0, 0, 0);
+    T gA[3] = {0, 0, 0}, gks = 0;
+    LightRng rng(seed, s, 0, 2);
+    for (int j = 0; j < S.nl; ++j) {
+        float u, v;
+        rng.get(j, u, v);
+        const Light &L = Ls[j];
+        v3 y = light_point(L, u, v);
+        if (!above(sd, y)) continue;
+        ++n_sh;
+        if (trace_any(S, sd.p, y - sd.p, h.tri, wk)) continue;
+        T c[3];
+        LAdj<T> a;
+        shade_light<T>(sv, L, cvt<T>(y), light_branch(sd, L.n, y), w, c, &a);
+        ++wk.shade;
+        for (int k = 0; k < 3; ++k) {
+            if (g_light_lds) atomicAdd(&g_light_lds[3 * j + k], (float)a.gl[k]);
+            else gadd(&G.d_light[3 * j + k], (double)a.gl[k]);
+            gA[k] += a.gA[k];
+        }
+        gks += a.gks;
+        gp = gp + a.gp; gns = gns + a.gns; gwo = gwo + a.gwo;
+    }
+    T gb[3] = {0, 0, 0};
+    if (gks != (T)0)
+        for (int k = 0; k < 4; ++k) {
+            if (g_spec_lds) atomicAdd(&g_spec_lds[sv.tex[k]], (float)(gks * sv.tw[k]));
+            else gadd(&G.d_spec[sv.tex[k]], (double)(gks * sv.tw[k]));
+        }
+    T guvx = gks * sv.dks_du, guvy = gks * sv.dks_dv;
+    for (int k = 0; k < 3; ++k) {
+        int vi = sv.i[k];
+        gb[k] += guvx * (T)S.uv[vi] + guvy * (T)S.uv[V + vi];
+        for (int c = 0; c < 3; ++c) {
+            gadd(&G.d_alb[c * V + vi], (double)(sv.b[k] * gA[c]));
+            gb[k] += gA[c] * (T)S.alb[c * V + vi];
+        }
+    }
+    gp = gp - norm_adj(gwo, sv.wo, sv.olen);
+    vec3<T> nt = sv.nu * ((T)1 / sv.nlen);
+    vec3<T> gnu = norm_adj(gns * sv.sg, nt, sv.nlen);
+    for (int k = 0; k < 3; ++k) {
+        int vi = sv.i[k];
+        atomic_v(G.d_nrm, V, vi, gnu * sv.b[k]);
+        gb[k] += dot(vk<T>((T)S.nrm[vi], (T)S.nrm[V + vi], (T)S.nrm[2 * V + vi]), gnu);
+    }
+    chain_hit<T>(V, sv, gp, gb[0], gb[1], gb[2], G.d_pos);
+}
+
+// Interior adjoint, fp32.  Samples seen at a grazing angle are queued for
+// the fp64 pass instead.
+__global__ __launch_bounds__(256) void k_render_adj(Scene S, uint64_t seed, int spp, long long N,
+        const float *__restrict__ dLdI, GradBufs G, int *__restrict__ queue, int *__restrict__ qcount,
+        unsigned long long *ctr) {
+    extern __shared__ float dyn[];
+    __shared__ Light Ls[kMaxLights];
+    float *spec_lds = dyn;
+    float *g_spec = dyn + S.res * S.res;        // [res^2]
+    float *g_light = g_spec + S.res * S.res;    // [nl*3]
+    stage_tables(S, Ls, spec_lds);
+    for (int k = threadIdx.x; k < S.res * S.res; k += blockDim.x) g_spec[k] = 0.0f;
+    for (int k = threadIdx.x; k < 3 * S.nl; k += blockDim.x) g_light[k] = 0.0f;
+    __syncthreads();
+    long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t n_cam = 0, n_sh = 0;
+    Work wk;
+    if (s < N) {
+        int pix;
+        v3 o = mk(S.cam_x, S.cam_y, S.cam_z);
+        v3 d = camera_sample(S, seed, (uint32_t)s, spp, pix);
+        Hit h = trace_closest(S, o, d, wk);
+        n_cam = 1;
+        if (h.tri >= 0) {
+            float inv = 1.0f / (float)spp;
+            float w[3] = {dLdI[3 * pix] * inv, dLdI[3 * pix + 1] * inv, dLdI[3 * pix + 2] * inv};
+            SurfDec sd;
+            surf_decide(S, o, h, sd);
+            Surf<float> sv;
+            surf_value<float>(S, spec_lds, o, d, h, sd, sv);
+            float cg = fabsf(sv.ndotd) / (len(sv.N) * len(sv.dir));
+            if (fabsf(sv.cos_o) < kGrazingCos || cg < kGrazingCos) {
+                queue[atomicAdd(qcount, 1)] = (int)s;
+            } else if (w[0] != 0.0f || w[1] != 0.0f || w[2] != 0.0f) {
+                adjoint_sample<float>(S, Ls, seed, (uint32_t)s, w, h, sd, sv, g_light, g_spec, G, n_sh, wk);
+            }
+        }
+    }
+    flush_count(ctr, 0, n_cam);
+    flush_count(ctr, 1, n_sh);
+    flush_work(ctr, wk);
+    __syncthreads();
+    for (int k = threadIdx.x; k < S.res * S.res; k += blockDim.x)
+        if (g_spec[k] != 0.0f) gadd(&G.d_spec[k], (double)g_spec[k]);
+    for (int k = threadIdx.x; k < 3 * S.nl; k += blockDim.x)
+        if (g_light[k] != 0.0f) gadd(&G.d_light[k], (double)g_light[k]);
+}
+
+// Interior adjoint of the queued (grazing) samples, fp64.  Grid-stride over
+// the queue; every lane exits once the queue is exhausted.
+__global__ __launch_bounds__(256) void k_render_adj_f64(Scene S, uint64_t seed, int spp,
+        const float *__restrict__ dLdI, GradBufs G, const int *__restrict__ queue, const int *__restrict__ qcount,
+        unsigned long long *ctr) {
+    extern __shared__ float dyn[];
+    __shared__ Light Ls[kMaxLights];
+    float *spec_lds = dyn;
+    stage_tables(S, Ls, spec_lds);
+    __syncthreads();
+    int n = *qcount;
+    uint32_t n_sh = 0;
+    Work wk;
+    for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) {
+        uint32_t s = (uint32_t)queue[q];
+        int pix;
+        v3 o = mk(S.cam_x, S.cam_y, S.cam_z);
+        v3 d = camera_sample(S, seed, s, spp, pix);
+        Hit h = trace_closest(S, o, d, wk);
+        if (h.tri < 0) continue;
+        float inv = 1.0f / (float)spp;
+        float w[3] = {dLdI[3 * pix] * inv, dLdI[3 * pix + 1] * inv, dLdI[3 * pix + 2] * inv};
+        if (w[0] == 0.0f && w[1] == 0.0f && w[2] == 0.0f) continue;
+        SurfDec sd;
+        surf_decide(S, o, h, sd);
+        Surf<double> sv;
+        surf_value<double>(S, spec_lds, o, d, h, sd, sv);
+        adjoint_sample<double>(S, Ls, seed, s, w, h, sd, sv, nullptr, nullptr, G, n_sh, wk);
+    }
+    flush_count(ctr, 1, n_sh);
+    flush_work(ctr, wk);
+}
+
+// Shadow-boundary (secondary) edge sample of light j at a camera sample's
+// shading point; decisions fp32, values fp64.
+__device__ inline void secondary_edge(const Scene &S, const Light &L, int j, uint64_t seed, uint32_t sidx,
+                                      const float *spec_lds, v3 o, v3 dcam, const Hit &h, const SurfDec &sf,
+                                      const float *w, double *d_pos, uint32_t &n_rays, Work &steps) {
+    int n = S.se_n[j];
+    uint64_t Q = S.se_Q[j];
+    if (n == 0 || Q == 0) return;
+    u4 wd = philox(seed, sidx, (uint32_t)j, 1, 0);
+    const uint64_t *pre = S.se_prefix + (size_t)j * S.E;
+    uint64_t target = __umul64hi(((uint64_t)wd.y << 32) | wd.x, Q);
+    int i = cdf_pick(pre, n, target);
+    int e = S.se_edge[(size_t)j * S.E + i];
+    const int *ed = S.edges + 4 * e;
+    if (ed[2] == h.tri || ed[3] == h.tri) return;
+    v3 p = sf.p;
+    if (ed[3] >= 0) {
+        float s1 = dot(face_normal(S, ed[2]), p - vpos(S, S.faces[3 * ed[2]]));
+        float s2 = dot(face_normal(S, ed[3]), p - vpos(S, S.faces[3 * ed[3]]));
+        if ((s1 > 0.0f) == (s2 > 0.0f)) return;
+    }
+    float tu = u01(wd.z);
+    v3 a = vpos(S, ed[0]), b = vpos(S, ed[1]);
+    v3 sp = mk(a.x + tu * (b.x - a.x), a.y + tu * (b.y - a.y), a.z + tu * (b.z - a.z));
+    float den = dot(L.n, sp - p);
+    if (den == 0.0f) return;
+    float lam = dot(L.n, L.c - p) / den;
+    if (!(lam > 1.0f)) return;
+    v3 y = mk(p.x + lam * (sp.x - p.x), p.y + lam * (sp.y - p.y), p.z + lam * (sp.z - p.z));
+    v3 ql = y - L.c;
+    if (!(fabsf(dot(ql, L.e1)) <= 0.5f * dot(L.e1, L.e1) && fabsf(dot(ql, L.e2)) <= 0.5f * dot(L.e2, L.e2))) return;
+    if (!above(sf, y)) return;
+    v3 m = cross(a - p, b - p);
+    float mn = dot(m, L.n);
+    v3 mp = mk(m.x - mn * L.n.x, m.y - mn * L.n.y, m.z - mn * L.n.z);
+    float lm = sqrtf(dot(mp, mp));
+    if (lm == 0.0f) return;
+    v3 un = mk(mp.x / lm, mp.y / lm, mp.z / lm);
+    v3 yp = mk(y.x + kEdgeOffM * un.x, y.y + kEdgeOffM * un.y, y.z + kEdgeOffM * un.z);
+    v3 ym = mk(y.x - kEdgeOffM * un.x, y.y - kEdgeOffM * un.y, y.z - kEdgeOffM * un.z);
+    n_rays += 2;
+    bool vp = !trace_any(S, p, yp - p, h.tri, steps);
+    bool vm = !trace_any(S, p, ym - p, h.tri, steps);
+    if (vp == vm) return;
+    // ---- value path (fp64)
+    Surf<double> sd;
+    surf_value<double>(S, spec_lds, o, dcam, h, sf, sd);
+    double hc[3];
+    shade_light<double>(sd, L, cvt<double>(y), light_branch(sf, L.n, y), nullptr, hc, nullptr);
+    double hw = (w[0] * hc[0] + w[1] * hc[1] + w[2] * hc[2]) / (double)L.area;
+    d3 P = sd.p, A = cvt<double>(a), B = cvt<double>(b), Y = cvt<double>(y), Nl = cvt<double>(L.n);
+    d3 pa = A - P, pb = B - P, py = Y - P;
+    d3 mval = cross(pa, pb);
+    d3 dpsi_a = cross(pb, py), dpsi_b = cross(py, pa);
+    d3 dpsi_p = (mval + dpsi_a + dpsi_b) * -1.0;
+    d3 bma = B - A;
+    d3 Sd = A + bma * (double)tu;
+    double nsp = dot(Nl, Sd - P);
+    double lamd = dot(Nl, cvt<double>(L.c) - P) / nsp;
+    d3 dydt = bma * lamd - (Sd - P) * (lamd * dot(Nl, bma) / nsp);
+    d3 mpar = mval - Nl * dot(mval, Nl);
+    uint64_t qe = (i + 1 < n ? pre[i + 1] : Q) - pre[i];
+    double pe = (double)qe / (double)Q;
+    double W = hw * (vp ? 1.0 : -1.0) * len(dydt) / (len(mpar) * pe);
+    atomic_v(d_pos, S.V, ed[0], dpsi_a * W);
+    atomic_v(d_pos, S.V, ed[1], dpsi_b * W);
+    // the receiver point p moves along the fixed camera ray
+    chain_hit<double>(S.V, sd, dpsi_p * W, 0.0, 0.0, 0.0, d_pos);
+}
+
+// One lane per camera sample: one shadow-boundary sample per light.
+__global__ __launch_bounds__(256) void k_edge_secondary(Scene S, uint64_t seed, int spp, long long N,
+        const float *__restrict__ dLdI, double *d_pos, unsigned long long *ctr) {
+    extern __shared__ float dyn[];
+    __shared__ Light Ls[kMaxLights];
+    float *spec_lds = dyn;
+    stage_tables(S, Ls, spec_lds);
+    __syncthreads();
+    long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t n_cam = 0, n_sec = 0;
+    Work wk;
+    if (s < N) {
+        int pix;
+        v3 o = mk(S.cam_x, S.cam_y, S.cam_z);
+        v3 d = camera_sample(S, seed, (uint32_t)s, spp, pix);
+        float inv = 1.0f / (float)spp;
+        float w[3] = {dLdI[3 * pix] * inv, dLdI[3 * pix + 1] * inv, dLdI[3 * pix + 2] * inv};
+        if (w[0] != 0.0f || w[1] != 0.0f || w[2] != 0.0f) {
+            Hit h = trace_closest(S, o, d, wk);
+            n_cam = 1;
+            if (h.tri >= 0) {
+                SurfDec sd;
+                surf_decide(S, o, h, sd);
+                for (int j = 0; j < S.nl; ++j)
+                    secondary_edge(S, Ls[j], j, seed, (uint32_t)s, spec_lds, o, d, h, sd, w, d_pos, n_sec, wk);
+            }
+        }
+    }
+    flush_count(ctr, 0, n_cam);
+    flush_count(ctr, 3, n_sec);
+    flush_work(ctr, wk);
+}
+
+// camera-silhouette (primary) edge samples: M = W*H
+__global__ __launch_bounds__(256) void k_edge_primary(Scene S, uint64_t seed, int M, const float *__restrict__ dLdI,
+        double *d_pos, unsigned long long *ctr) {
+    extern __shared__ float dyn[];
+    __shared__ Light Ls[kMaxLights];
+    float *spec_lds = dyn;
+    stage_tables(S, Ls, spec_lds);
+    __syncthreads();
+    int m = blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t n_pe = 0, n_sh = 0;
+    Work wk;
+    int n = S.pe_n[0];
+    uint64_t Q = S.pe_Q[0];
+    if (m < M && n > 0 && Q > 0) do {
+        u4 wd = philox(seed, (uint32_t)m, 0, 2, 0);
+        uint64_t target = __umul64hi(((uint64_t)wd.y << 32) | wd.x, Q);
+        int i = cdf_pick(S.pe_prefix, n, target);
+        int e = S.pe_edge[i];
+        const int *ed = S.edges + 4 * e;
+        float tu = u01(wd.z);
+        v3 a = vpos(S, ed[0]), b = vpos(S, ed[1]);
+        float ax, ay, bx, by;
+        if (!project(S, a, ax, ay) || !project(S, b, bx, by)) break;
+        float qx = ax + tu * (bx - ax), qy = ay + tu * (by - ay);
+        float fpx = floorf(qx), fpy = floorf(qy);
+        if (!(fpx >= 0.0f && fpx < (float)S.W && fpy >= 0.0f && fpy < (float)S.H)) break;
+        v3 cam = mk(S.cam_x, S.cam_y, S.cam_z);
+        v3 mv = cross(a - cam, b - cam);
+        float gx = mv.x, gy = -mv.y;
+        float gl = sqrtf(gx * gx + gy * gy);
+        if (gl == 0.0f) break;
+        float nx = gx / gl, ny = gy / gl;
+        double f[2][3];
+        for (int side = 0; side < 2; ++side) {
+            float sg = side == 0 ? 1.0f : -1.0f;
+            float px = qx + sg * (kEdgeOffPx * nx), py = qy + sg * (kEdgeOffPx * ny);
+            LightRng rng(seed, (uint32_t)m, 2, 4);
+            radiance<double>(S, Ls, spec_lds, camera_dir(S, px, py), rng, f[side], n_sh, wk);
+        }
+        n_pe = 2 + n_sh;
+        int pix = (int)fpy * S.W + (int)fpx;
+        const float *Gp = dLdI + 3 * pix;
+        double df = Gp[0] * (f[0][0] - f[1][0]) + Gp[1] * (f[0][1] - f[1][1]) + Gp[2] * (f[0][2] - f[1][2]);
+        if (df == 0.0) break;
+        // ---- value path (fp64)
+        double ps = S.ps;
+        d3 C = cvt<double>(cam), A = cvt<double>(a), B = cvt<double>(b);
+        d3 dq = dk(((double)qx - 0.5 * S.W) * ps, (0.5 * S.H - (double)qy) * ps, -1.0);
+        d3 ra = A - C, rb = B - C;
+        d3 md = cross(ra, rb);
+        double gradn = ps * sqrt(md.x * md.x + md.y * md.y);
+        double pax = 0.5 * S.W + (ra.x / -ra.z) / ps, pay = 0.5 * S.H - (ra.y / -ra.z) / ps;
+        double pbx = 0.5 * S.W + (rb.x / -rb.z) / ps, pby = 0.5 * S.H - (rb.y / -rb.z) / ps;
+        double ln = sqrt((pbx - pax) * (pbx - pax) + (pby - pay) * (pby - pay));
+        uint64_t qe = (i + 1 < n ? S.pe_prefix[i + 1] : Q) - S.pe_prefix[i];
+        double pe = (double)qe / (double)Q;
+        double W = df * ln / (pe * gradn * (double)M);
+        atomic_v(d_pos, S.V, ed[0], cross(rb, dq) * W);
+        atomic_v(d_pos, S.V, ed[1], cross(dq, ra) * W);
+    } while (0);
+    flush_count(ctr, 2, n_pe);
+    flush_work(ctr, wk);
+}
+
+// ------------------------------------------------------- reductions ----
+// gN_k = d n_k / d N_k applied to the vertex-normal adjoint
+__global__ __launch_bounds__(256) void k_normal_adj(int V, const float *__restrict__ nrm, const float *__restrict__ nlen,
+        const double *__restrict__ d_nrm, double *__restrict__ gN) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= V) return;
+    double r[3] = {0.0, 0.0, 0.0};
+    if (nlen[i] > 0.0f) {
+        double n[3] = {nrm[i], nrm[V + i], nrm[2 * V + i]};
+        double g[3] = {d_nrm[i], d_nrm[V + i], d_nrm[2 * V + i]};
+        double ng = n[0] * g[0] + n[1] * g[1] + n[2] * g[2];
+        for (int c = 0; c < 3; ++c) r[c] = (g[c] - n[c] * ng) / (double)nlen[i];
+    }
+    gN[i] = r[0]; gN[V + i] = r[1]; gN[2 * V + i] = r[2];
+}
+
+// d_vertices = d_pos + sum over incident faces of the cross-product adjoint
+// of N_f = (v1 - v0) x (v2 - v0) with gN_f = gN_i0 + gN_i1 + gN_i2;
+// also gm = R^T d_vertices for the blend transposes.
+__global__ __launch_bounds__(256) void k_chain_gather(int V, const int *__restrict__ faces,
+        const int *__restrict__ vf_off, const int *__restrict__ vf_idx, const float *__restrict__ pos,
+        const double *__restrict__ gN, const double *__restrict__ d_pos, PoseArgs P,
+        float *__restrict__ d_vert, float *__restrict__ gm) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= V) return;
+    double acc[3] = {d_pos[i], d_pos[V + i], d_pos[2 * V + i]};
+    for (int q = vf_off[i]; q < vf_off[i + 1]; ++q) {
+        const int *t = faces + 3 * vf_idx[q];
+        double g[3] = {0.0, 0.0, 0.0}, a[3], b[3];
+        for (int k = 0; k < 3; ++k)
+            for (int c = 0; c < 3; ++c) g[c] += gN[(size_t)c * V + t[k]];
+        for (int c = 0; c < 3; ++c) {
+            double x0 = pos[(size_t)c * V + t[0]];
+            a[c] = (double)pos[(size_t)c * V + t[1]] - x0;
+            b[c] = (double)pos[(size_t)c * V + t[2]] - x0;
+        }
+        double ga[3] = {b[1] * g[2] - b[2] * g[1], b[2] * g[0] - b[0] * g[2], b[0] * g[1] - b[1] * g[0]};
+        double gb[3] = {g[1] * a[2] - g[2] * a[1], g[2] * a[0] - g[0] * a[2], g[0] * a[1] - g[1] * a[0]};
+        for (int c = 0; c < 3; ++c) {
+            if (t[1] == i) acc[c] += ga[c];
+            else if (t[2] == i) acc[c] += gb[c];
+            else acc[c] -= ga[c] + gb[c];
+        }
+    }
+    d_vert[i] = (float)acc[0]; d_vert[V + i] = (float)acc[1]; d_vert[2 * V + i] = (float)acc[2];
+    for (int c = 0; c < 3; ++c)
+        gm[(size_t)c * V + i] = (float)((P.R[c] * acc[0] + P.R[3 + c] * acc[1]) + P.R[6 + c] * acc[2]);
+}
+
+// rows: [0, n_id) B_id . gm; [n_id, +n_exp) B_exp . gm; [.., +n_alb) B_alb . d_alb;
+// then 9 rows dR[a][b] = sum d_v[a] vmodel[b] and 3 rows dt[a] = sum d_v[a].
+// Grid (rows, chunks); each block writes one partial.
+template <int BS>
+__global__ __launch_bounds__(BS) void k_param_partial(int V, int n_id, int n_exp, int n_alb, int chunk,
+        const float *__restrict__ b_id, const float *__restrict__ b_exp, const float *__restrict__ b_alb,
+        const float *__restrict__ gm, const double *__restrict__ d_alb, const float *__restrict__ d_vert,
+        const float *__restrict__ vmodel, double *__restrict__ partial) {
+    int row = blockIdx.x, ch = blockIdx.y;
+    size_t L = (size_t)3 * V;
+    const float *x, *y = nullptr;
+    const double *yd = nullptr;
+    size_t n = L;
+    int kb = n_id + n_exp + n_alb;
+    if (row < n_id) { x = b_id + (size_t)row * L; y = gm; }
+    else if (row < n_id + n_exp) { x = b_exp + (size_t)(row - n_id) * L; y = gm; }
+    else if (row < kb) { x = b_alb + (size_t)(row - n_id - n_exp) * L; yd = d_alb; }
+    else if (row < kb + 9) { int a = (row - kb) / 3, b = (row - kb) % 3; x = d_vert + (size_t)a * V; y = vmodel + (size_t)b * V; n = V; }
+    else { x = d_vert + (size_t)(row - kb - 9) * V; n = V; }
+    size_t lo = (size_t)ch * chunk, hi = lo + chunk < n ? lo + chunk : n;
+    double acc = 0.0;
+    for (size_t e = lo + threadIdx.x; e < hi; e += BS)
+        acc += (double)x[e] * (y ? (double)y[e] : (yd ? yd[e] : 1.0));
+    __shared__ double sh[BS];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int off = BS / 2; off > 0; off >>= 1) {
+        if (threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[(size_t)row * gridDim.y + ch] = sh[0];
+}
+
+struct DRotArgs { double dR[27]; };   // dR/drx, dR/dry, dR/drz, row-major
+
+__global__ void k_param_final(int n_id, int n_exp, int n_alb, int nchunks, const double *__restrict__ partial,
+        DRotArgs D, float *d_alpha, float *d_beta, float *d_delta, float *d_pose) {
+    int row = blockIdx.x * blockDim.x + threadIdx.x;
+    int kb = n_id + n_exp + n_alb;
+    if (row < kb) {
+        double s = 0.0;
+        for (int c = 0; c < nchunks; ++c) s += partial[(size_t)row * nchunks + c];
+        if (row < n_id) { if (d_alpha) d_alpha[row] = (float)s; }
+        else if (row < n_id + n_exp) { if (d_beta) d_beta[row - n_id] = (float)s; }
+        else if (d_delta) d_delta[row - n_id - n_exp] = (float)s;
+    } else if (row == kb && d_pose) {
+        double dR[9], dt[3];
+        // rows 9/12 use chunks over V; the V-length rows still have nchunks partials (zeros beyond V)
+        for (int r = 0; r < 12; ++r) {
+            double s = 0.0;
+            for (int c = 0; c < nchunks; ++c) s += partial[(size_t)(kb + r) * nchunks + c];
+            if (r < 9) dR[r] = s; else dt[r - 9] = s;
+        }
+        for (int a = 0; a < 3; ++a) {
+            double s = 0.0;
+            for (int r = 0; r < 9; ++r) s += dR[r] * D.dR[9 * a + r];
+            d_pose[a] = (float)s;
+        }
+        for (int a = 0; a < 3; ++a) d_pose[3 + a] = (float)dt[a];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_zero(float *a, size_t n) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] = 0.0f;
+}
+__global__ __launch_bounds__(256) void k_zero_d(double *a, size_t n) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] = 0.0;
+}
+__global__ __launch_bounds__(256) void k_copy_d2f(const double *__restrict__ a, float *__restrict__ b, size_t n) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = (float)a[i];
+}
+__global__ void k_zero_u32(unsigned int *a, int n) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] = 0u;
+}
+__global__ void k_zero_u64(unsigned long long *a, int n) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] = 0ull;
+}
+__global__ __launch_bounds__(256) void k_copy(const float *__restrict__ a, float *__restrict__ b, size_t n) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = a[i];
+}
+
+template <int BS>
+__global__ __launch_bounds__(BS) void k_loss_partial(size_t n, const float *__restrict__ img, const float *__restrict__ tgt,
+        float *__restrict__ dL, double *__restrict__ partial) {
+    size_t i = (size_t)blockIdx.x * BS + threadIdx.x;
+    double acc = 0.0;
+    if (i < n) {
+        float r = img[i] - tgt[i];
+        if (dL) dL[i] = 2.0f * r;
+        acc = (double)r * (double)r;
+    }
+    __shared__ double sh[BS];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int off = BS / 2; off > 0; off >>= 1) {
+        if (threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = sh[0];
+}
+__global__ void k_loss_final(int nb, const double *__restrict__ partial, float *loss) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        double s = 0.0;
+        for (int b = 0; b < nb; ++b) s += partial[b];
+        *loss = (float)s;
+    }
+}
+
+// ====================================================================== //
+//                               host side                                //
+// ====================================================================== //
+
+struct fr_ctx {
+    std::string err;
+    hipStream_t stream = nullptr;
+    uint32_t flags = 0, terms = FR_TERM_INTERIOR | FR_TERM_PRIMARY | FR_TERM_SECONDARY;
+    int device = 0;
+    // sizes
+    int V = 0, F = 0, E = 0, n_id = 0, n_exp = 0, n_alb = 0;
+    int W = 0, H = 0, nl = 0, res = 0, n_nodes = 0;
+    float cam[3] = {0, 0, 0}, ps = 0;
+    // model (device)
+    int *faces = nullptr, *edges = nullptr, *vf_off = nullptr, *vf_idx = nullptr;
+    float *mean = nullptr, *b_id = nullptr, *b_exp = nullptr, *alb_mean = nullptr, *b_alb = nullptr, *uv = nullptr;
+    float *lgeom = nullptr;
+    // tree order (device)
+    int *sorted_tri = nullptr, *leaf_node = nullptr, *parent = nullptr, *right = nullptr, *escape = nullptr;
+    unsigned int *arrive = nullptr;
+    float4 *nodes = nullptr, *tris = nullptr;
+    // per evaluation (device)
+    float *vmodel = nullptr, *pos = nullptr, *nrm = nullptr, *nlen = nullptr, *alb = nullptr;
+    float *ew = nullptr; unsigned int *ewmax = nullptr;
+    int *tbl_edge = nullptr, *tbl_n = nullptr; uint64_t *tbl_prefix = nullptr, *tbl_Q = nullptr;
+    float *samples = nullptr; size_t samples_cap = 0;
+    unsigned long long *ctr = nullptr;
+    int *queue = nullptr, *qcount = nullptr; size_t queue_cap = 0;
+    // gradients scratch
+    double *g_light = nullptr, *g_spec = nullptr, *g_pos = nullptr, *g_nrm = nullptr, *g_alb = nullptr;
+    double *g_N = nullptr;
+    float *g_vert = nullptr, *g_m = nullptr;
+    double *partial = nullptr; int nchunks = 0, chunk = 0;
+    double *loss_partial = nullptr; int loss_nb = 0;
+    // last render
+    bool have_render = false, have_backward = false;
+    fr_params last{};
+    uint64_t last_seed = 0; int last_spp = 0;
+    PoseArgs pose{};
+    DRotArgs drot{};
+    // timing
+    hipEvent_t ev[12] = {};
+    float ms[5] = {0, 0, 0, 0, 0};
+};
+
+static const char *kNoCtx = "no context";
+
+static int fail(fr_ctx *c, int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (c) c->err = buf;
+    return code;
+}
+
+#define HIPCK(c, call)                                                                   \
+    do {                                                                                 \
+        hipError_t e_ = (call);                                                          \
+        if (e_ != hipSuccess) {                                                          \
+            return fail((c), e_ == hipErrorOutOfMemory ? FR_ENOMEM : FR_EDEVICE, "%s: %s (%s:%d)", \
+                        #call, hipGetErrorString(e_), __FILE__, __LINE__);               \
+        }                                                                                \
+    } while (0)
+
+template <class T>
+static int dalloc(fr_ctx *c, T **p, size_t n) {
+    if (n == 0) n = 1;
+    HIPCK(c, hipMalloc((void **)p, n * sizeof(T)));
+    return 0;
+}
+template <class T>
+static int upload(fr_ctx *c, T **p, const T *h, size_t n) {
+    if (dalloc(c, p, n)) return c ? FR_ENOMEM : -1;
+    HIPCK(c, hipMemcpy(*p, h, n * sizeof(T), hipMemcpyHostToDevice));
+    return 0;
+}
+
+static void rotation(const float pose[6], double R[9]) {
+    // R = Rz(rz) Ry(ry) Rx(rx); products summed left to right
+    double cx = cos((double)pose[0]), sx = sin((double)pose[0]);
+    double cy = cos((double)pose[1]), sy = sin((double)pose[1]);
+    double cz = cos((double)pose[2]), sz = sin((double)pose[2]);
+    double Rx[9] = {1, 0, 0, 0, cx, -sx, 0, sx, cx};
+    double Ry[9] = {cy, 0, sy, 0, 1, 0, -sy, 0, cy};
+    double Rz[9] = {cz, -sz, 0, sz, cz, 0, 0, 0, 1};
+    double T[9];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+            T[3 * i + j] = (Ry[3 * i] * Rx[j] + Ry[3 * i + 1] * Rx[3 + j]) + Ry[3 * i + 2] * Rx[6 + j];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+            R[3 * i + j] = (Rz[3 * i] * T[j] + Rz[3 * i + 1] * T[3 + j]) + Rz[3 * i + 2] * T[6 + j];
+}
+
+static void matmul3(const double *A, const double *B, double *C) {
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) C[3 * i + j] = A[3 * i] * B[j] + A[3 * i + 1] * B[3 + j] + A[3 * i + 2] * B[6 + j];
+}
+
+static void drotation(const float pose[6], double out[27]) {
+    double cx = cos((double)pose[0]), sx = sin((double)pose[0]);
+    double cy = cos((double)pose[1]), sy = sin((double)pose[1]);
+    double cz = cos((double)pose[2]), sz = sin((double)pose[2]);
+    double Rx[9] = {1, 0, 0, 0, cx, -sx, 0, sx, cx}, dRx[9] = {0, 0, 0, 0, -sx, -cx, 0, cx, -sx};
+    double Ry[9] = {cy, 0, sy, 0, 1, 0, -sy, 0, cy}, dRy[9] = {-sy, 0, cy, 0, 0, 0, -cy, 0, -sy};
+    double Rz[9] = {cz, -sz, 0, sz, cz, 0, 0, 0, 1}, dRz[9] = {-sz, -cz, 0, cz, -sz, 0, 0, 0, 0};
+    double T[9];
+    matmul3(Ry, dRx, T); matmul3(Rz, T, out);
+    matmul3(dRy, Rx, T); matmul3(Rz, T, out + 9);
+    matmul3(Ry, Rx, T); matmul3(dRz, T, out + 18);
+}
+
+// ---- topology: edges, vertex->face lists, LBVH tree order -------------
+struct HostTopo {
+    std::vector<int> edges, vf_off, vf_idx, sorted_tri, leaf_node, parent, right, escape;
+    int n_nodes = 0;
+};
+
+static bool build_edges(int V, int F, const int *faces, std::vector<int> &out) {
+    std::vector<uint64_t> he;
+    he.reserve(3 * (size_t)F);
+    for (int f = 0; f < F; ++f)
+        for (int k = 0; k < 3; ++k) {
+            uint32_t a = faces[3 * f + k], b = faces[3 * f + (k + 1) % 3];
+            if (a > b) std::swap(a, b);
+            (void)V;
+            he.push_back(((uint64_t)a << 32) | b);
+        }
+    std::vector<std::pair<uint64_t, int>> key(he.size());
+    for (size_t i = 0; i < he.size(); ++i) key[i] = {he[i], (int)(i / 3)};
+    std::sort(key.begin(), key.end());
+    out.clear();
+    for (size_t i = 0; i < key.size();) {
+        size_t j = i + 1;
+        while (j < key.size() && key[j].first == key[i].first) ++j;
+        if (j - i > 2) return false;
+        out.push_back((int)(key[i].first >> 32));
+        out.push_back((int)(key[i].first & 0xffffffffu));
+        out.push_back(key[i].second);
+        out.push_back(j - i == 2 ? key[i + 1].second : -1);
+        i = j;
+    }
+    return true;
+}
+
+static uint32_t spread10(uint32_t x) {
+    x &= 1023u;
+    x = (x | (x << 16)) & 0x030000FFu;
+    x = (x | (x << 8)) & 0x0300F00Fu;
+    x = (x | (x << 4)) & 0x030C30C3u;
+    x = (x | (x << 2)) & 0x09249249u;
+    return x;
+}
+
+// Karras-style split of the sorted Morton codes: highest differing bit, or
+// the middle of a run of equal codes; laid out depth-first with escapes.
+static int layout_rec(const std::vector<uint64_t> &keys, int lo, int hi, int idx, int par, HostTopo &T) {
+    T.parent[idx] = par;
+    int count = hi - lo + 1;
+    T.escape[idx] = idx + 2 * count - 1;
+    if (count == 1) {
+        T.leaf_node[lo] = idx;
+        T.right[idx] = -1;
+        return idx;
+    }
+    uint64_t a = keys[lo], b = keys[hi];
+    int split;
+    if (a == b) {
+        split = (lo + hi) / 2;
+    } else {
+        int common = __builtin_clzll(a ^ b);
+        split = lo;
+        int step = hi - lo;
+        do {
+            step = (step + 1) >> 1;
+            int ns = split + step;
+            if (ns < hi && __builtin_clzll(a ^ keys[ns]) > common) split = ns;
+        } while (step > 1);
+    }
+    int nl = split - lo + 1;
+    layout_rec(keys, lo, split, idx + 1, idx, T);
+    T.right[idx] = idx + 2 * nl;
+    layout_rec(keys, split + 1, hi, idx + 2 * nl, idx, T);
+    return idx;
+}
+
+static bool build_topology(const fr_model_desc *m, HostTopo &T) {
+    int V = m->n_vertices, F = m->n_faces;
+    if (!build_edges(V, F, m->faces, T.edges)) return false;
+    std::vector<int> cnt(V + 1, 0);
+    for (int f = 0; f < F; ++f)
+        for (int k = 0; k < 3; ++k) cnt[m->faces[3 * f + k] + 1]++;
+    T.vf_off.assign(V + 1, 0);
+    for (int i = 0; i < V; ++i) T.vf_off[i + 1] = T.vf_off[i] + cnt[i + 1];
+    T.vf_idx.assign(3 * (size_t)F, 0);
+    std::vector<int> fill(T.vf_off.begin(), T.vf_off.end() - 1);
+    for (int f = 0; f < F; ++f)         // ascending f per vertex
+        for (int k = 0; k < 3; ++k) {
+            int v = m->faces[3 * f + k];
+            bool dup = false;
+            for (int q = T.vf_off[v]; q < fill[v]; ++q) dup |= T.vf_idx[q] == f;
+            if (!dup) T.vf_idx[fill[v]++] = f;
+        }
+    // Morton codes of the mean-shape face centroids (tree order only)
+    std::vector<float> cx(F), cy(F), cz(F);
+    float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int f = 0; f < F; ++f) {
+        float c[3];
+        for (int a = 0; a < 3; ++a) {
+            c[a] = (m->mean[(size_t)a * V + m->faces[3 * f]] + m->mean[(size_t)a * V + m->faces[3 * f + 1]] +
+                    m->mean[(size_t)a * V + m->faces[3 * f + 2]]) / 3.0f;
+            lo[a] = std::min(lo[a], c[a]); hi[a] = std::max(hi[a], c[a]);
+        }
+        cx[f] = c[0]; cy[f] = c[1]; cz[f] = c[2];
+    }
+    std::vector<uint64_t> key(F);
+    for (int f = 0; f < F; ++f) {
+        float c[3] = {cx[f], cy[f], cz[f]};
+        uint32_t q[3];
+        for (int a = 0; a < 3; ++a) {
+            float ext = hi[a] - lo[a];
+            float u = ext > 0 ? (c[a] - lo[a]) / ext : 0.5f;
+            q[a] = (uint32_t)std::min(1023.0f, std::max(0.0f, u * 1024.0f));
+        }
+        uint32_t code = (spread10(q[0]) << 2) | (spread10(q[1]) << 1) | spread10(q[2]);
+        key[f] = ((uint64_t)code << 32) | (uint32_t)f;
+    }
+    std::sort(key.begin(), key.end());
+    T.sorted_tri.resize(F);
+    for (int i = 0; i < F; ++i) T.sorted_tri[i] = (int)(key[i] & 0xffffffffu);
+    std::vector<uint64_t> codes(F);
+    for (int i = 0; i < F; ++i) codes[i] = key[i] >> 32;
+    T.n_nodes = 2 * F - 1;
+    T.parent.assign(T.n_nodes, -1); T.right.assign(T.n_nodes, -1); T.escape.assign(T.n_nodes, 0);
+    T.leaf_node.assign(F, 0);
+    layout_rec(codes, 0, F - 1, 0, -1, T);
+    return true;
+}
+
+static Scene make_scene(fr_ctx *c) {
+    Scene S;
+    S.V = c->V; S.F = c->F; S.W = c->W; S.H = c->H; S.nl = c->nl; S.res = c->res; S.n_nodes = c->n_nodes; S.E = c->E;
+    S.cam_x = c->cam[0]; S.cam_y = c->cam[1]; S.cam_z = c->cam[2]; S.ps = c->ps;
+    S.faces = c->faces; S.pos = c->pos; S.nrm = c->nrm; S.alb = c->alb; S.uv = c->uv;
+    S.nodes = c->nodes; S.tris = c->tris; S.lgeom = c->lgeom;
+    S.lrgb = c->last.lights; S.spec = c->last.spec; S.edges = c->edges;
+    size_t E = (size_t)c->E;
+    S.pe_edge = c->tbl_edge; S.pe_prefix = c->tbl_prefix; S.pe_n = c->tbl_n; S.pe_Q = c->tbl_Q;
+    S.se_edge = c->tbl_edge + E; S.se_prefix = c->tbl_prefix + E; S.se_n = c->tbl_n + 1; S.se_Q = c->tbl_Q + 1;
+    return S;
+}
+
+static inline unsigned nblk(size_t n, unsigned bs) { return (unsigned)((n + bs - 1) / bs); }
+
+extern "C" {
+
+int fr_create(const fr_model_desc *m, const fr_scene_desc *s, uint32_t flags, fr_ctx **out) {
+    if (!out) return FR_EINVAL;
+    *out = nullptr;
+    if (!m || !s) return FR_EINVAL;
+    if (m->n_vertices <= 0 || m->n_faces <= 0 || m->n_id < 0 || m->n_exp < 0 || m->n_alb < 0 ||
+        !m->faces || !m->mean || !m->alb_mean || !m->uv || (m->n_id && !m->b_id) || (m->n_exp && !m->b_exp) ||
+        (m->n_alb && !m->b_alb) || s->width <= 0 || s->height <= 0 || s->n_lights < 1 ||
+        s->n_lights > kMaxLights || !s->light_geom || s->spec_res < 1 || s->spec_res > 64 ||
+        !(s->pix_scale > 0.0f) || (long long)s->width * s->height > (1ll << 26))
+        return FR_EINVAL;
+    for (long long i = 0; i < 3ll * m->n_faces; ++i)
+        if (m->faces[i] < 0 || m->faces[i] >= m->n_vertices) return FR_EINVAL;
+    for (int j = 0; j < s->n_lights; ++j)
+        for (int k = 0; k < 12; ++k)
+            if (!std::isfinite(s->light_geom[12 * j + k])) return FR_EINVAL;
+    fr_ctx *c = new fr_ctx();
+    c->flags = flags;
+    HostTopo T;
+    if (!build_topology(m, T)) { delete c; return FR_EINVAL; }
+    c->V = m->n_vertices; c->F = m->n_faces; c->E = (int)(T.edges.size() / 4);
+    c->n_id = m->n_id; c->n_exp = m->n_exp; c->n_alb = m->n_alb;
+    c->W = s->width; c->H = s->height; c->nl = s->n_lights; c->res = s->spec_res; c->n_nodes = T.n_nodes;
+    for (int a = 0; a < 3; ++a) c->cam[a] = s->cam[a];
+    c->ps = s->pix_scale;
+    size_t V3 = 3 * (size_t)c->V;
+    int rc = 0;
+    auto R = [&](int r) { if (r && !rc) rc = r; return r; };
+    (void)hipGetDevice(&c->device);
+    if (R(upload(c, &c->faces, m->faces, 3 * (size_t)c->F)) || R(upload(c, &c->edges, T.edges.data(), T.edges.size())) ||
+        R(upload(c, &c->vf_off, T.vf_off.data(), T.vf_off.size())) || R(upload(c, &c->vf_idx, T.vf_idx.data(), T.vf_idx.size())) ||
+        R(upload(c, &c->mean, m->mean, V3)) || R(upload(c, &c->alb_mean, m->alb_mean, V3)) ||
+        R(upload(c, &c->uv, m->uv, 2 * (size_t)c->V)) ||
+        R(upload(c, &c->b_id, m->n_id ? m->b_id : m->mean, m->n_id ? c->n_id * V3 : 1)) ||
+        R(upload(c, &c->b_exp, m->n_exp ? m->b_exp : m->mean, m->n_exp ? c->n_exp * V3 : 1)) ||
+        R(upload(c, &c->b_alb, m->n_alb ? m->b_alb : m->mean, m->n_alb ? c->n_alb * V3 : 1)) ||
+        R(upload(c, &c->lgeom, s->light_geom, 12 * (size_t)c->nl)) ||
+        R(upload(c, &c->sorted_tri, T.sorted_tri.data(), T.sorted_tri.size())) ||
+        R(upload(c, &c->leaf_node, T.leaf_node.data(), T.leaf_node.size())) ||
+        R(upload(c, &c->parent, T.parent.data(), T.parent.size())) ||
+        R(upload(c, &c->right, T.right.data(), T.right.size())) ||
+        R(upload(c, &c->escape, T.escape.data(), T.escape.size())) ||
+        R(dalloc(c, &c->arrive, (size_t)c->n_nodes)) || R(dalloc(c, &c->nodes, 2 * (size_t)c->n_nodes)) ||
+        R(dalloc(c, &c->tris, 3 * (size_t)c->F)) ||
+        R(dalloc(c, &c->vmodel, V3)) || R(dalloc(c, &c->pos, V3)) || R(dalloc(c, &c->nrm, V3)) ||
+        R(dalloc(c, &c->nlen, (size_t)c->V)) || R(dalloc(c, &c->alb, V3)) ||
+        R(dalloc(c, &c->ew, (size_t)(1 + c->nl) * c->E)) || R(dalloc(c, &c->ewmax, (size_t)(1 + c->nl))) ||
+        R(dalloc(c, &c->tbl_edge, (size_t)(1 + c->nl) * c->E)) || R(dalloc(c, &c->tbl_prefix, (size_t)(1 + c->nl) * c->E)) ||
+        R(dalloc(c, &c->tbl_n, (size_t)(1 + c->nl))) || R(dalloc(c, &c->tbl_Q, (size_t)(1 + c->nl))) ||
+        R(dalloc(c, &c->ctr, 32)) || R(dalloc(c, &c->qcount, 1)) ||
+        R(dalloc(c, &c->g_light, 3 * (size_t)c->nl)) || R(dalloc(c, &c->g_spec, (size_t)c->res * c->res)) ||
+        R(dalloc(c, &c->g_pos, V3)) || R(dalloc(c, &c->g_nrm, V3)) || R(dalloc(c, &c->g_alb, V3)) ||
+        R(dalloc(c, &c->g_N, V3)) || R(dalloc(c, &c->g_vert, V3)) || R(dalloc(c, &c->g_m, V3))) {
+        int code = rc ? rc : FR_ENOMEM;
+        fr_destroy(c);
+        return code;
+    }
+    c->chunk = 16384;
+    c->nchunks = (int)((V3 + c->chunk - 1) / c->chunk);
+    int rows = c->n_id + c->n_exp + c->n_alb + 12;
+    c->loss_nb = (int)nblk(V3 > (size_t)c->W * c->H * 3 ? V3 : (size_t)c->W * c->H * 3, 256);
+    if (dalloc(c, &c->partial, (size_t)rows * c->nchunks) || dalloc(c, &c->loss_partial, (size_t)c->loss_nb)) {
+        fr_destroy(c);
+        return FR_ENOMEM;
+    }
+    (void)hipMemset(c->arrive, 0, sizeof(unsigned int) * c->n_nodes);
+    (void)hipMemset(c->ctr, 0, 32 * sizeof(unsigned long long));
+    if (flags & FR_TIMING)
+        for (int i = 0; i < 12; ++i) (void)hipEventCreate(&c->ev[i]);
+    if (hipDeviceSynchronize() != hipSuccess) { fr_destroy(c); return FR_EDEVICE; }
+    *out = c;
+    return FR_OK;
+}
+
+int fr_set_stream(fr_ctx *c, void *stream) {
+    if (!c) return FR_EINVAL;
+    c->stream = (hipStream_t)stream;
+    return FR_OK;
+}
+
+int fr_set_terms(fr_ctx *c, uint32_t terms) {
+    if (!c || (terms & ~7u)) return FR_EINVAL;
+    c->terms = terms;
+    return FR_OK;
+}
+
+static int blend_impl(fr_ctx *c, const float *alpha, const float *beta, const float *delta, const float *pose) {
+    for (int k = 0; k < 6; ++k)
+        if (!std::isfinite(pose[k])) return fail(c, FR_EINVAL, "fr_blend: non-finite pose[%d]", k);
+    rotation(pose, c->pose.R);
+    for (int k = 0; k < 3; ++k) c->pose.t[k] = (double)pose[3 + k];
+    drotation(pose, c->drot.dR);
+    hipLaunchKernelGGL(k_blend, dim3(nblk(c->V, 256)), dim3(256), 0, c->stream, c->V, c->n_id, c->n_exp, c->n_alb,
+                       c->mean, c->b_id, c->b_exp, c->alb_mean, c->b_alb, alpha, beta, delta, c->pose,
+                       c->vmodel, c->pos, c->alb);
+    hipLaunchKernelGGL(k_normals, dim3(nblk(c->V, 256)), dim3(256), 0, c->stream, c->V, c->faces, c->vf_off, c->vf_idx,
+                       c->pos, c->nrm, c->nlen);
+    HIPCK(c, hipGetLastError());
+    return FR_OK;
+}
+
+int fr_blend(fr_ctx *c, const float *alpha, const float *beta, const float *delta,
+             const float *pose, float *out_vertices, float *out_albedo) {
+    if (!c) return FR_EINVAL;
+    c->err.clear();
+    if ((c->n_id && !alpha) || (c->n_exp && !beta) || (c->n_alb && !delta) || !pose)
+        return fail(c, FR_EINVAL, "fr_blend: null argument");
+    int r = blend_impl(c, alpha, beta, delta, pose);
+    if (r) return r;
+    size_t V3 = 3 * (size_t)c->V;
+    if (out_vertices) hipLaunchKernelGGL(k_copy, dim3(nblk(V3, 256)), dim3(256), 0, c->stream, c->pos, out_vertices, V3);
+    if (out_albedo) hipLaunchKernelGGL(k_copy, dim3(nblk(V3, 256)), dim3(256), 0, c->stream, c->alb, out_albedo, V3);
+    HIPCK(c, hipGetLastError());
+    return FR_OK;
+}
+
+static void ev_record(fr_ctx *c, int i) {
+    if (c->flags & FR_TIMING) (void)hipEventRecord(c->ev[i], c->stream);
+}
+
+int fr_render(fr_ctx *c, const fr_params *p, uint64_t seed, int32_t spp, float *out) {
+    if (!c) return FR_EINVAL;
+    c->err.clear();
+    if (!p || !out || !p->lights || !p->spec || !p->pose || (c->n_id && !p->alpha) || (c->n_exp && !p->beta) ||
+        (c->n_alb && !p->delta))
+        return fail(c, FR_EINVAL, "fr_render: null argument");
+    if (spp < 1 || spp > 4096) return fail(c, FR_EINVAL, "fr_render: spp %d out of [1, 4096]", spp);
+    long long N = (long long)c->W * c->H * spp;
+    if (N > (1ll << 31) - 1) return fail(c, FR_EINVAL, "fr_render: W*H*spp too large");
+    if ((size_t)N * 3 > c->samples_cap) {
+        if (c->samples) (void)hipFree(c->samples);
+        c->samples = nullptr;
+        c->samples_cap = 0;
+        HIPCK(c, hipMalloc((void **)&c->samples, (size_t)N * 3 * sizeof(float)));
+        c->samples_cap = (size_t)N * 3;
+    }
+    if ((size_t)N > c->queue_cap) {
+        if (c->queue) (void)hipFree(c->queue);
+        c->queue = nullptr;
+        c->queue_cap = 0;
+        HIPCK(c, hipMalloc((void **)&c->queue, (size_t)N * sizeof(int)));
+        c->queue_cap = (size_t)N;
+    }
+    c->have_render = false;
+    c->last = *p;
+    c->last_seed = seed;
+    c->last_spp = spp;
+    ev_record(c, 0);
+    int r = blend_impl(c, p->alpha, p->beta, p->delta, p->pose);
+    if (r) return r;
+    ev_record(c, 1);
+    hipLaunchKernelGGL(k_refit, dim3(nblk(c->F, 256)), dim3(256), 0, c->stream, c->F, c->faces, c->pos, c->V,
+                       c->sorted_tri, c->leaf_node, c->parent, c->right, c->escape, c->arrive, c->nodes, c->tris);
+    ev_record(c, 2);
+    Scene S = make_scene(c);
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(128), 0, c->stream, c->ewmax, 1 + c->nl);
+    hipLaunchKernelGGL(k_edge_weights, dim3(nblk(c->E, 256)), dim3(256), 0, c->stream, S, c->lgeom, c->ew, c->ewmax);
+    hipLaunchKernelGGL(k_edge_scan<1024>, dim3(1 + c->nl), dim3(1024), 0, c->stream, c->E, c->ew, c->ewmax,
+                       c->tbl_edge, c->tbl_prefix, c->tbl_n, c->tbl_Q);
+    ev_record(c, 3);
+    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, c->stream, c->ctr, 32);
+    size_t lds = (size_t)c->res * c->res * sizeof(float);
+    ev_record(c, 9);
+    hipLaunchKernelGGL(k_render_fwd, dim3(nblk(N, 256)), dim3(256), lds, c->stream, S, seed, spp, N, c->samples, c->ctr);
+    ev_record(c, 10);
+    hipLaunchKernelGGL(k_pixel_mean, dim3(nblk((size_t)c->W * c->H, 256)), dim3(256), 0, c->stream,
+                       c->W * c->H, spp, c->samples, out);
+    ev_record(c, 4);
+    HIPCK(c, hipGetLastError());
+    c->have_render = true;
+    return FR_OK;
+}
+
+int fr_backward(fr_ctx *c, const float *dLdI, const fr_grads *g) {
+    if (!c) return FR_EINVAL;
+    c->err.clear();
+    if (!c->have_render) return fail(c, FR_ESTATE, "fr_backward: no prior fr_render");
+    if (!dLdI || !g) return fail(c, FR_EINVAL, "fr_backward: null argument");
+    size_t V3 = 3 * (size_t)c->V;
+    ev_record(c, 5);
+    hipLaunchKernelGGL(k_zero_d, dim3(nblk(3 * c->nl, 256)), dim3(256), 0, c->stream, c->g_light, (size_t)3 * c->nl);
+    hipLaunchKernelGGL(k_zero_d, dim3(nblk((size_t)c->res * c->res, 256)), dim3(256), 0, c->stream, c->g_spec, (size_t)c->res * c->res);
+    hipLaunchKernelGGL(k_zero_d, dim3(nblk(V3, 256)), dim3(256), 0, c->stream, c->g_pos, V3);
+    hipLaunchKernelGGL(k_zero_d, dim3(nblk(V3, 256)), dim3(256), 0, c->stream, c->g_nrm, V3);
+    hipLaunchKernelGGL(k_zero_d, dim3(nblk(V3, 256)), dim3(256), 0, c->stream, c->g_alb, V3);
+    Scene S = make_scene(c);
+    long long N = (long long)c->W * c->H * c->last_spp;
+    GradBufs G{c->g_light, c->g_spec, c->g_pos, c->g_nrm, c->g_alb};
+    size_t lds = ((size_t)2 * c->res * c->res + 3 * c->nl) * sizeof(float);
+    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, c->stream, c->ctr + 8, 24);
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, c->stream, (unsigned int *)c->qcount, 1);
+    ev_record(c, 7);
+    if (c->terms & FR_TERM_INTERIOR)
+        hipLaunchKernelGGL(k_render_adj, dim3(nblk(N, 256)), dim3(256), lds, c->stream, S, c->last_seed, c->last_spp, N,
+                           dLdI, G, c->queue, c->qcount, c->ctr + 8);
+    ev_record(c, 8);
+    size_t lds1 = (size_t)c->res * c->res * sizeof(float);
+    if (c->terms & FR_TERM_INTERIOR)
+        hipLaunchKernelGGL(k_render_adj_f64, dim3(512), dim3(256), lds1, c->stream, S, c->last_seed, c->last_spp,
+                           dLdI, G, c->queue, c->qcount, c->ctr + 8);
+    if (c->terms & FR_TERM_SECONDARY)
+        hipLaunchKernelGGL(k_edge_secondary, dim3(nblk(N, 256)), dim3(256), lds1, c->stream, S, c->last_seed, c->last_spp, N,
+                           dLdI, c->g_pos, c->ctr + 24);
+    if (c->terms & FR_TERM_PRIMARY) {
+        int M = c->W * c->H;
+        hipLaunchKernelGGL(k_edge_primary, dim3(nblk(M, 256)), dim3(256), lds1, c->stream,
+                           S, c->last_seed, M, dLdI, c->g_pos, c->ctr + 16);
+    }
+    hipLaunchKernelGGL(k_normal_adj, dim3(nblk(c->V, 256)), dim3(256), 0, c->stream, c->V, c->nrm, c->nlen, c->g_nrm, c->g_N);
+    hipLaunchKernelGGL(k_chain_gather, dim3(nblk(c->V, 256)), dim3(256), 0, c->stream, c->V, c->faces, c->vf_off, c->vf_idx,
+                       c->pos, c->g_N, c->g_pos, c->pose, c->g_vert, c->g_m);
+    int rows = c->n_id + c->n_exp + c->n_alb + 12;
+    bool want_params = g->d_alpha || g->d_beta || g->d_delta || g->d_pose;
+    if (want_params) {
+        hipLaunchKernelGGL(k_param_partial<256>, dim3(rows, c->nchunks), dim3(256), 0, c->stream, c->V, c->n_id, c->n_exp,
+                           c->n_alb, c->chunk, c->b_id, c->b_exp, c->b_alb, c->g_m, c->g_alb, c->g_vert, c->vmodel, c->partial);
+        hipLaunchKernelGGL(k_param_final, dim3(nblk(rows, 64)), dim3(64), 0, c->stream, c->n_id, c->n_exp, c->n_alb,
+                           c->nchunks, c->partial, c->drot, g->d_alpha, g->d_beta, g->d_delta, g->d_pose);
+    }
+    if (g->d_lights) hipLaunchKernelGGL(k_copy_d2f, dim3(1), dim3(256), 0, c->stream, c->g_light, g->d_lights, (size_t)3 * c->nl);
+    if (g->d_spec) hipLaunchKernelGGL(k_copy_d2f, dim3(nblk((size_t)c->res * c->res, 256)), dim3(256), 0, c->stream, c->g_spec, g->d_spec, (size_t)c->res * c->res);
+    if (g->d_vertices) hipLaunchKernelGGL(k_copy, dim3(nblk(V3, 256)), dim3(256), 0, c->stream, c->g_vert, g->d_vertices, V3);
+    if (g->d_albedo) hipLaunchKernelGGL(k_copy_d2f, dim3(nblk(V3, 256)), dim3(256), 0, c->stream, c->g_alb, g->d_albedo, V3);
+    ev_record(c, 6);
+    HIPCK(c, hipGetLastError());
+    c->have_backward = true;
+    return FR_OK;
+}
+
+int fr_loss_l2(fr_ctx *c, const float *img, const float *tgt, float *dL, float *loss) {
+    if (!c) return FR_EINVAL;
+    c->err.clear();
+    if (!img || !tgt) return fail(c, FR_EINVAL, "fr_loss_l2: null argument");
+    size_t n = (size_t)c->W * c->H * 3;
+    int nb = (int)nblk(n, 256);
+    hipLaunchKernelGGL(k_loss_partial<256>, dim3(nb), dim3(256), 0, c->stream, n, img, tgt, dL, c->loss_partial);
+    if (loss) hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(64), 0, c->stream, nb, c->loss_partial, loss);
+    HIPCK(c, hipGetLastError());
+    return FR_OK;
+}
+
+int fr_stats(fr_ctx *c, fr_stats_t *out) {
+    if (!c || !out) return FR_EINVAL;
+    HIPCK(c, hipStreamSynchronize(c->stream));
+    unsigned long long h[32];
+    HIPCK(c, hipMemcpy(h, c->ctr, sizeof h, hipMemcpyDeviceToHost));
+    memset(out, 0, sizeof *out);
+    int qn = 0;
+    HIPCK(c, hipMemcpy(&qn, c->qcount, sizeof qn, hipMemcpyDeviceToHost));
+    out->grazing_samples = (uint64_t)qn;
+    for (int k = 0; k < 4; ++k) {
+        const unsigned long long *q = h + 8 * k;
+        out->rays_camera += q[0]; out->rays_shadow += q[1];
+        out->rays_edge_primary += q[2]; out->rays_edge_secondary += q[3];
+        out->box_tests += q[4]; out->tri_tests += q[5];
+        out->kernel_box_tests[k] = q[4]; out->kernel_tri_tests[k] = q[5];
+        out->kernel_rays[k] = q[0] + q[1] + q[2] + q[3];
+        out->kernel_shades[k] = q[6];
+    }
+    out->traversal_overflow = 0;
+    if (c->flags & FR_TIMING) {
+        float t;
+        // events of a phase that has not run yet are not queried
+        if (!c->have_render) return FR_OK;
+        if (hipEventElapsedTime(&t, c->ev[0], c->ev[1]) == hipSuccess) out->ms_blend = t;
+        if (hipEventElapsedTime(&t, c->ev[1], c->ev[2]) == hipSuccess) out->ms_bvh = t;
+        if (hipEventElapsedTime(&t, c->ev[2], c->ev[3]) == hipSuccess) out->ms_edges = t;
+        if (hipEventElapsedTime(&t, c->ev[3], c->ev[4]) == hipSuccess) out->ms_render = t;
+        if (hipEventElapsedTime(&t, c->ev[9], c->ev[10]) == hipSuccess) out->ms_kernel_fwd = t;
+        if (c->have_backward) {
+            if (hipEventElapsedTime(&t, c->ev[5], c->ev[6]) == hipSuccess) out->ms_backward = t;
+            if (hipEventElapsedTime(&t, c->ev[7], c->ev[8]) == hipSuccess) out->ms_kernel_adj = t;
+        }
+        (void)hipGetLastError();   // a failed query must not leak into later calls
+    }
+    return FR_OK;
+}
+
+const char *fr_last_error(const fr_ctx *c) { return c ? c->err.c_str() : kNoCtx; }
+
+void fr_destroy(fr_ctx *c) {
+    if (!c) return;
+    if (c->stream) (void)hipStreamSynchronize(c->stream); else (void)hipDeviceSynchronize();
+    void *ptrs[] = {c->faces, c->edges, c->vf_off, c->vf_idx, c->mean, c->b_id, c->b_exp, c->alb_mean, c->b_alb, c->uv,
+                    c->lgeom, c->sorted_tri, c->leaf_node, c->parent, c->right, c->escape, c->arrive, c->nodes, c->tris,
+                    c->vmodel, c->pos, c->nrm, c->nlen, c->alb, c->ew, c->ewmax, c->tbl_edge, c->tbl_prefix, c->tbl_n,
+                    c->tbl_Q, c->samples, c->ctr, c->g_light, c->g_spec, c->g_pos, c->g_nrm, c->g_alb, c->g_N,
+                    c->g_vert, c->g_m, c->partial, c->loss_partial, c->queue, c->qcount};
+    for (void *p : ptrs) if (p) (void)hipFree(p);
+    for (auto &e : c->ev) if (e) (void)hipEventDestroy(e);
+    delete c;
+}
+
+}  // extern "C"

@@ -1,0 +1,485 @@
+// Device-side math for the light-stage renderer (gfx950, wave64).
+//
+// Two kinds of arithmetic live here:
+//  * decisions: every comparison whose outcome is an integer (which triangle
+//    a ray hits, whether a shadow ray is blocked, which side is seen, which
+//    edge a sample picks) is taken in fp32 with the operation order written
+//    below and no contraction (the library is built with -ffp-contract=off);
+//  * values: shading and its adjoint, templated on the scalar type.  The
+//    bulk runs in fp32; samples whose shading is ill-conditioned (grazing
+//    views) and the edge samples, which sit on silhouettes by construction,
+//    run in fp64, which MI355X issues at the fp32 (non-packed) rate.
+// The estimator is the Monte-Carlo lighting estimator F of the paper's
+// Optimization paragraph with the Cook-Torrance reflectance of its Face
+// Modeling paragraph; see include/facert.h.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fr {
+
+constexpr float kHitMargin = 1e-5f;      // accepted hit within tri box +- this
+constexpr float kBoxPad = 2e-5f;         // BVH boxes are padded by this
+constexpr float kShadowTmin = 1e-4f;
+constexpr float kShadowTmax = 1.0f - 1e-4f;
+constexpr float kEdgeOffPx = 1e-3f;      // silhouette sides, in pixels
+constexpr float kEdgeOffM = 2e-5f;       // shadow-boundary sides, in metres
+constexpr float kQScale = 1048576.0f;    // 2^20 edge-weight quantisation
+constexpr double kBeckmannM = 0.35;
+constexpr double kPi = 3.14159265358979323846;
+constexpr float kSlabGrow = 1.0000004f;  // 1 + 2 gamma_3 (Ize 2013)
+constexpr int kMaxLights = 64;
+// A camera sample's adjoint runs in fp64 when its view is this close to
+// grazing (|cos| to the shading or geometric normal below it): the specular
+// term divides by cos_o, so fp32 error grows as 1/cos_o^2 in its gradient.
+constexpr float kGrazingCos = 0.1f;
+
+template <class T> struct vec3 { T x, y, z; };
+using v3 = vec3<float>;
+using d3 = vec3<double>;
+__device__ __forceinline__ v3 mk(float x, float y, float z) { v3 r; r.x = x; r.y = y; r.z = z; return r; }
+__device__ __forceinline__ d3 dk(double x, double y, double z) { d3 r; r.x = x; r.y = y; r.z = z; return r; }
+template <class T> __device__ __forceinline__ vec3<T> vk(T x, T y, T z) { vec3<T> r; r.x = x; r.y = y; r.z = z; return r; }
+template <class T> __device__ __forceinline__ vec3<T> cvt(v3 a) { return vk<T>((T)a.x, (T)a.y, (T)a.z); }
+template <class T> __device__ __forceinline__ vec3<T> operator-(vec3<T> a, vec3<T> b) { return vk<T>(a.x - b.x, a.y - b.y, a.z - b.z); }
+template <class T> __device__ __forceinline__ vec3<T> operator+(vec3<T> a, vec3<T> b) { return vk<T>(a.x + b.x, a.y + b.y, a.z + b.z); }
+template <class T> __device__ __forceinline__ vec3<T> operator*(vec3<T> a, T s) { return vk<T>(a.x * s, a.y * s, a.z * s); }
+template <class T> __device__ __forceinline__ T dot(vec3<T> a, vec3<T> b) { return (a.x * b.x + a.y * b.y) + a.z * b.z; }
+template <class T> __device__ __forceinline__ vec3<T> cross(vec3<T> a, vec3<T> b) {
+    return vk<T>(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
+}
+template <class T> __device__ __forceinline__ T len(vec3<T> a) { return sqrt(dot(a, a)); }
+// adjoint of n = v/|v|: dL/dv from dL/dn
+template <class T> __device__ __forceinline__ vec3<T> norm_adj(vec3<T> g, vec3<T> n, T l) {
+    return (g - n * dot(n, g)) * ((T)1 / l);
+}
+
+// ------------------------------------------------------------- Philox ----
+// Philox4x32-10 (Salmon et al., SC'11).
+struct u4 { uint32_t x, y, z, w; };
+__device__ __forceinline__ u4 philox(uint64_t key, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3) {
+    uint32_t k0 = (uint32_t)key, k1 = (uint32_t)(key >> 32);
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        uint32_t hi0 = __umulhi(0xD2511F53u, c0), lo0 = 0xD2511F53u * c0;
+        uint32_t hi1 = __umulhi(0xCD9E8D57u, c2), lo1 = 0xCD9E8D57u * c2;
+        uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+        c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+        k0 += 0x9E3779B9u; k1 += 0xBB67AE85u;
+    }
+    u4 r; r.x = c0; r.y = c1; r.z = c2; r.w = c3;
+    return r;
+}
+__device__ __forceinline__ float u01(uint32_t w) { return (float)(w >> 8) * (1.0f / 16777216.0f); }
+
+// ------------------------------------------------------ scene on device --
+struct Scene {
+    int V, F, W, H, nl, res, n_nodes, E;
+    float cam_x, cam_y, cam_z, ps;
+    const int *faces;          // [F][3]
+    const float *pos;          // [3][V]
+    const float *nrm;          // [3][V]
+    const float *alb;          // [3][V]
+    const float *uv;           // [2][V]
+    const float4 *nodes;       // [2 n_nodes]: (lo, escape) (hi, leaf)
+    const float4 *tris;        // [3 F]: v0 v1 v2, original index
+    const float *lgeom;        // [nl][12]
+    const float *lrgb;         // [nl][3]
+    const float *spec;         // [res^2]
+    const int *edges;          // [E][4]
+    // sampling tables (compacted positive-weight entries)
+    const int *pe_edge; const uint64_t *pe_prefix; const int *pe_n; const uint64_t *pe_Q;
+    const int *se_edge; const uint64_t *se_prefix; const int *se_n; const uint64_t *se_Q;  // [nl][E]
+};
+
+__device__ __forceinline__ v3 vpos_raw(const float *pos, int V, int i) {
+    return mk(pos[i], pos[V + i], pos[2 * V + i]);
+}
+__device__ __forceinline__ v3 vpos(const Scene &S, int i) {
+    return mk(S.pos[i], S.pos[S.V + i], S.pos[2 * S.V + i]);
+}
+__device__ __forceinline__ v3 face_normal(const Scene &S, int f) {
+    const int *t = S.faces + 3 * f;
+    v3 v0 = vpos(S, t[0]);
+    return cross(vpos(S, t[1]) - v0, vpos(S, t[2]) - v0);
+}
+
+// -------------------------------------------------- ray / triangle -------
+// Moller-Trumbore, two-sided, inclusive barycentric bounds, open t range;
+// the hit point must lie in the triangle's box widened by kHitMargin.
+__device__ __forceinline__ bool ray_tri(v3 o, v3 d, v3 v0, v3 v1, v3 v2, float tmin, float tmax,
+                                        float &t_out, float &b1_out, float &b2_out, float &det_out) {
+    v3 e1 = v1 - v0, e2 = v2 - v0;
+    v3 pv = cross(d, e2);
+    float det = dot(e1, pv);
+    if (det == 0.0f) return false;
+    float inv = 1.0f / det;
+    v3 tv = o - v0;
+    float b1 = dot(tv, pv) * inv;
+    if (!(b1 >= 0.0f && b1 <= 1.0f)) return false;
+    v3 qv = cross(tv, e1);
+    float b2 = dot(d, qv) * inv;
+    if (!(b2 >= 0.0f && b1 + b2 <= 1.0f)) return false;
+    float t = dot(e2, qv) * inv;
+    if (!(t > tmin && t < tmax)) return false;
+    v3 P = mk(o.x + t * d.x, o.y + t * d.y, o.z + t * d.z);
+    float lo, hi;
+    lo = fminf(fminf(v0.x, v1.x), v2.x) - kHitMargin; hi = fmaxf(fmaxf(v0.x, v1.x), v2.x) + kHitMargin;
+    if (!(P.x >= lo && P.x <= hi)) return false;
+    lo = fminf(fminf(v0.y, v1.y), v2.y) - kHitMargin; hi = fmaxf(fmaxf(v0.y, v1.y), v2.y) + kHitMargin;
+    if (!(P.y >= lo && P.y <= hi)) return false;
+    lo = fminf(fminf(v0.z, v1.z), v2.z) - kHitMargin; hi = fmaxf(fmaxf(v0.z, v1.z), v2.z) + kHitMargin;
+    if (!(P.z >= lo && P.z <= hi)) return false;
+    t_out = t; b1_out = b1; b2_out = b2; det_out = det;
+    return true;
+}
+
+// ---------------------------------------------------------- traversal ----
+// The BVH is stored in depth-first order with escape links: after an
+// internal node comes its left subtree; a miss (or a leaf) jumps to the
+// escape index.  No stack is needed.
+struct Ray {
+    v3 o, d, id;   // origin, direction, 1/direction (tiny components clamped)
+};
+__device__ __forceinline__ float safe_inv(float x) {
+    return 1.0f / (fabsf(x) < 1e-20f ? copysignf(1e-20f, x) : x);
+}
+__device__ __forceinline__ Ray make_ray(v3 o, v3 d) {
+    Ray r; r.o = o; r.d = d; r.id = mk(safe_inv(d.x), safe_inv(d.y), safe_inv(d.z));
+    return r;
+}
+__device__ __forceinline__ bool slab(const Ray &r, float4 a, float4 b, float thi) {
+    float tx0 = (a.x - r.o.x) * r.id.x, tx1 = (b.x - r.o.x) * r.id.x;
+    float ty0 = (a.y - r.o.y) * r.id.y, ty1 = (b.y - r.o.y) * r.id.y;
+    float tz0 = (a.z - r.o.z) * r.id.z, tz1 = (b.z - r.o.z) * r.id.z;
+    float tn = fmaxf(fmaxf(fminf(tx0, tx1), fminf(ty0, ty1)), fmaxf(fminf(tz0, tz1), 0.0f));
+    float tf = fminf(fminf(fmaxf(tx0, tx1), fmaxf(ty0, ty1)), fminf(fmaxf(tz0, tz1), thi));
+    return tn <= tf * kSlabGrow;
+}
+
+struct Hit { int tri; float t, b1, b2, det; };
+// work counters of one lane: box tests, triangle tests, shaded light samples
+struct Work { uint32_t box = 0, tri = 0, shade = 0; };
+
+// closest hit, lexicographic (t, original triangle index)
+__device__ inline Hit trace_closest(const Scene &S, v3 o, v3 d, Work &wk) {
+    Ray r = make_ray(o, d);
+    Hit h; h.tri = -1; h.t = INFINITY; h.b1 = h.b2 = h.det = 0.0f;
+    int node = 0;
+    while (node < S.n_nodes) {
+        float4 a = S.nodes[2 * node], b = S.nodes[2 * node + 1];
+        int esc = __float_as_int(a.w), leaf = __float_as_int(b.w);
+        ++wk.box;
+        if (slab(r, a, b, h.t)) {
+            if (leaf >= 0) {
+                float4 q0 = S.tris[3 * leaf], q1 = S.tris[3 * leaf + 1], q2 = S.tris[3 * leaf + 2];
+                v3 v0 = mk(q0.x, q0.y, q0.z), v1 = mk(q0.w, q1.x, q1.y), v2 = mk(q1.z, q1.w, q2.x);
+                int id = __float_as_int(q2.y);
+                float t, b1, b2, det;
+                ++wk.tri;
+                if (ray_tri(o, d, v0, v1, v2, 0.0f, INFINITY, t, b1, b2, det)) {
+                    if (t < h.t || (t == h.t && id < h.tri)) { h.tri = id; h.t = t; h.b1 = b1; h.b2 = b2; h.det = det; }
+                }
+                node = esc;
+            } else {
+                node = node + 1;
+            }
+        } else {
+            node = esc;
+        }
+    }
+    return h;
+}
+
+// any hit on o + t d, t in (kShadowTmin, kShadowTmax), ignoring triangle skip
+__device__ inline bool trace_any(const Scene &S, v3 o, v3 d, int skip, Work &wk) {
+    Ray r = make_ray(o, d);
+    int node = 0;
+    while (node < S.n_nodes) {
+        float4 a = S.nodes[2 * node], b = S.nodes[2 * node + 1];
+        int esc = __float_as_int(a.w), leaf = __float_as_int(b.w);
+        ++wk.box;
+        if (slab(r, a, b, 1.0f)) {
+            if (leaf >= 0) {
+                float4 q0 = S.tris[3 * leaf], q1 = S.tris[3 * leaf + 1], q2 = S.tris[3 * leaf + 2];
+                int id = __float_as_int(q2.y);
+                if (id != skip) {
+                    v3 v0 = mk(q0.x, q0.y, q0.z), v1 = mk(q0.w, q1.x, q1.y), v2 = mk(q1.z, q1.w, q2.x);
+                    float t, b1, b2, det;
+                    ++wk.tri;
+                    if (ray_tri(o, d, v0, v1, v2, kShadowTmin, kShadowTmax, t, b1, b2, det)) return true;
+                }
+                node = esc;
+            } else {
+                node = node + 1;
+            }
+        } else {
+            node = esc;
+        }
+    }
+    return false;
+}
+
+// --------------------------------------------------- camera and lights ---
+__device__ __forceinline__ v3 camera_dir(const Scene &S, float qx, float qy) {
+    return mk((qx - 0.5f * (float)S.W) * S.ps, (0.5f * (float)S.H - qy) * S.ps, -1.0f);
+}
+struct Light { v3 c, e1, e2, n; float area; float r, g, b; };
+__device__ __forceinline__ v3 light_point(const Light &L, float u, float v) {
+    float a = u - 0.5f, b = v - 0.5f;
+    return mk((L.c.x + a * L.e1.x) + b * L.e2.x, (L.c.y + a * L.e1.y) + b * L.e2.y,
+              (L.c.z + a * L.e1.z) + b * L.e2.z);
+}
+
+// largest i < n with prefix[i] <= target (prefix[0] = 0, non-decreasing)
+__device__ __forceinline__ int cdf_pick(const uint64_t *prefix, int n, uint64_t target) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        int mid = lo + (hi - lo + 1) / 2;
+        if (prefix[mid] <= target) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// --------------------------------------------------- surface decisions ---
+struct SurfDec {
+    v3 p;          // shading point: origin of shadow rays
+    v3 ng;         // e1 x e2 of the hit triangle (unflipped)
+    v3 nu;         // interpolated vertex normal (unflipped, unnormalised)
+    v3 wod;        // unit direction to the camera
+    int tex_ix, tex_iy;  // bilinear texel cell of the specular map
+    bool front;    // det > 0: the camera sees the side ng points to
+    bool spec_on;  // viewer above the interpolated vertex normal
+};
+
+__device__ inline void surf_decide(const Scene &S, v3 o, const Hit &h, SurfDec &s) {
+    const int *tr = S.faces + 3 * h.tri;
+    int i0 = tr[0], i1 = tr[1], i2 = tr[2];
+    v3 v0 = vpos(S, i0), v1 = vpos(S, i1), v2 = vpos(S, i2);
+    float b1 = h.b1, b2 = h.b2;
+    float b0 = (1.0f - b1) - b2;
+    s.p = mk((b0 * v0.x + b1 * v1.x) + b2 * v2.x, (b0 * v0.y + b1 * v1.y) + b2 * v2.y,
+             (b0 * v0.z + b1 * v1.z) + b2 * v2.z);
+    const float *N = S.nrm; int V = S.V;
+    v3 n0 = mk(N[i0], N[V + i0], N[2 * V + i0]);
+    v3 n1 = mk(N[i1], N[V + i1], N[2 * V + i1]);
+    v3 n2 = mk(N[i2], N[V + i2], N[2 * V + i2]);
+    v3 nu = mk((b0 * n0.x + b1 * n1.x) + b2 * n2.x, (b0 * n0.y + b1 * n1.y) + b2 * n2.y,
+               (b0 * n0.z + b1 * n1.z) + b2 * n2.z);
+    float co = dot(nu, o - s.p);
+    s.front = h.det > 0.0f;
+    s.spec_on = s.front ? co > 0.0f : co < 0.0f;
+    s.ng = cross(v1 - v0, v2 - v0);
+    s.nu = nu;
+    v3 c = o - s.p;
+    float lc = sqrtf(dot(c, c));
+    s.wod = mk(c.x / lc, c.y / lc, c.z / lc);
+    // texel centres at (i + 1/2)/res
+    float ux = (b0 * S.uv[i0] + b1 * S.uv[i1]) + b2 * S.uv[i2];
+    float uy = (b0 * S.uv[V + i0] + b1 * S.uv[V + i1]) + b2 * S.uv[V + i2];
+    s.tex_ix = (int)floorf((float)S.res * ux - 0.5f);
+    s.tex_iy = (int)floorf((float)S.res * uy - 0.5f);
+}
+
+// Branches whose value is continuous but whose slope jumps: the clamps of
+// cos_s and cos_l and the min of the V-cavity term.  Decided in fp32 from
+// the sample's decision values so that every implementation differentiates
+// the same branch.  The V-cavity comparisons G1, G2 >= 1 and G1 <= G2 are
+// written with unnormalised dot products (positive factors cancel).
+struct Branch { bool cs, cl; int gsel; };
+__device__ __forceinline__ Branch light_branch(const SurfDec &sd, v3 ln, v3 y) {
+    Branch b;
+    v3 r = y - sd.p;
+    v3 nn = sd.front ? sd.nu : mk(-sd.nu.x, -sd.nu.y, -sd.nu.z);
+    b.cs = dot(nn, r) > 0.0f;
+    b.cl = dot(ln, r) < 0.0f;
+    b.gsel = 0;
+    if (sd.spec_on && b.cs) {
+        float lr = sqrtf(dot(r, r));
+        v3 wi = mk(r.x / lr, r.y / lr, r.z / lr);
+        v3 hs = wi + sd.wod;
+        float a_s = dot(nn, wi), a_o = dot(nn, sd.wod);
+        float nh = dot(nn, hs), oh2 = dot(sd.wod, hs), n2 = dot(sd.nu, sd.nu);
+        float rhs = oh2 * n2;
+        float g1 = (2.0f * nh) * a_o, g2 = (2.0f * nh) * a_s;
+        if (g1 >= rhs && g2 >= rhs) b.gsel = 0;
+        else if (a_o <= a_s) b.gsel = 1;
+        else b.gsel = 2;
+    }
+    return b;
+}
+
+// light sample above the surface's tangent plane (two-sided)
+__device__ __forceinline__ bool above(const SurfDec &s, v3 y) {
+    float hz = dot(s.ng, y - s.p);
+    return s.front ? hz > 0.0f : hz < 0.0f;
+}
+
+// ------------------------------------------------------- surface values --
+template <class T> struct Surf {
+    int i[3];
+    T b[3];
+    vec3<T> p;                 // shading point
+    vec3<T> nu; T nlen;        // interpolated normal and its length
+    vec3<T> ns;                // flipped, normalised shading normal
+    vec3<T> wo; T olen; T cos_o;
+    T A[3];
+    T ks, tw[4], dks_du, dks_dv; int tex[4];
+    vec3<T> N, dir, pv, e1xd; T det, ndotd, sg;   // barycentric chain
+    bool spec_on;
+};
+
+template <class T>
+__device__ inline void surf_value(const Scene &S, const float *spec_lds, v3 of, v3 df, const Hit &h,
+                                  const SurfDec &dec, Surf<T> &s) {
+    bool spec_on = dec.spec_on;
+    const int *tr = S.faces + 3 * h.tri;
+    int V = S.V;
+    for (int k = 0; k < 3; ++k) s.i[k] = tr[k];
+    v3 v0f = vpos(S, tr[0]), v1f = vpos(S, tr[1]), v2f = vpos(S, tr[2]);
+    // barycentrics of the ray/plane solve in fp64 (grazing hits lose digits
+    // as 1/det in fp32)
+    d3 v0 = cvt<double>(v0f), v1 = cvt<double>(v1f), v2 = cvt<double>(v2f);
+    d3 o = cvt<double>(of), d = cvt<double>(df);
+    d3 e1 = v1 - v0, e2 = v2 - v0;
+    d3 pvd = cross(d, e2);
+    double det = dot(e1, pvd);
+    d3 tv = o - v0;
+    double inv = 1.0 / det;
+    double b1 = dot(tv, pvd) * inv;
+    d3 qv = cross(tv, e1);
+    double b2 = dot(d, qv) * inv;
+    double b0 = 1.0 - b1 - b2;
+    s.b[0] = (T)b0; s.b[1] = (T)b1; s.b[2] = (T)b2;
+    d3 pd = v0 * b0 + v1 * b1 + v2 * b2;
+    s.p = vk<T>((T)pd.x, (T)pd.y, (T)pd.z);
+    vec3<T> nu = vk<T>(0, 0, 0);
+    for (int k = 0; k < 3; ++k)
+        nu = nu + vk<T>((T)S.nrm[tr[k]], (T)S.nrm[V + tr[k]], (T)S.nrm[2 * V + tr[k]]) * s.b[k];
+    s.nu = nu;
+    s.nlen = len(nu);
+    s.sg = h.det > 0.0f ? (T)1 : (T)-1;
+    s.ns = nu * (s.sg / s.nlen);
+    for (int c = 0; c < 3; ++c) {
+        const float *a = S.alb + c * V;
+        s.A[c] = s.b[0] * (T)a[tr[0]] + s.b[1] * (T)a[tr[1]] + s.b[2] * (T)a[tr[2]];
+    }
+    T ux = s.b[0] * (T)S.uv[tr[0]] + s.b[1] * (T)S.uv[tr[1]] + s.b[2] * (T)S.uv[tr[2]];
+    T uy = s.b[0] * (T)S.uv[V + tr[0]] + s.b[1] * (T)S.uv[V + tr[1]] + s.b[2] * (T)S.uv[V + tr[2]];
+    int R = S.res;
+    // the cell is a decision (the slope jumps at texel centres)
+    T x = (T)R * ux - (T)0.5, y = (T)R * uy - (T)0.5;
+    int ix0 = dec.tex_ix, iy0 = dec.tex_iy;
+    T fx = x - (T)ix0, fy = y - (T)iy0;
+    int ixa = min(max(ix0, 0), R - 1), ixb = min(max(ix0 + 1, 0), R - 1);
+    int iya = min(max(iy0, 0), R - 1), iyb = min(max(iy0 + 1, 0), R - 1);
+    s.tex[0] = iya * R + ixa; s.tw[0] = ((T)1 - fx) * ((T)1 - fy);
+    s.tex[1] = iya * R + ixb; s.tw[1] = fx * ((T)1 - fy);
+    s.tex[2] = iyb * R + ixa; s.tw[2] = ((T)1 - fx) * fy;
+    s.tex[3] = iyb * R + ixb; s.tw[3] = fx * fy;
+    T T0 = spec_lds[s.tex[0]], T1 = spec_lds[s.tex[1]], T2 = spec_lds[s.tex[2]], T3 = spec_lds[s.tex[3]];
+    s.ks = s.tw[0] * T0 + s.tw[1] * T1 + s.tw[2] * T2 + s.tw[3] * T3;
+    s.dks_du = (T)R * (((T)1 - fy) * (T1 - T0) + fy * (T3 - T2));
+    s.dks_dv = (T)R * (((T)1 - fx) * (T2 - T0) + fx * (T3 - T1));
+    vec3<T> wv = cvt<T>(of) - s.p;
+    s.olen = len(wv);
+    s.wo = wv * ((T)1 / s.olen);
+    s.cos_o = dot(s.ns, s.wo);
+    vec3<T> e1t = cvt<T>(v1f - v0f), e2t = cvt<T>(v2f - v0f);
+    s.N = cross(e1t, e2t);
+    s.dir = cvt<T>(df);
+    s.pv = cross(s.dir, e2t);
+    s.e1xd = cross(e1t, s.dir);
+    s.det = dot(e1t, s.pv);
+    s.ndotd = dot(s.N, s.dir);
+    s.spec_on = spec_on;
+}
+
+// Radiance of one visible light sample y and, if w is given, its
+// reverse-mode adjoint.  c = l (A/pi cos_s + S) cos_l area/d^2,
+// S = f_s cos_s = ks D G / (4 cos_o), Beckmann D, V-cavity G, F = 1.
+template <class T> struct LAdj { vec3<T> gp, gns, gwo; T gA[3], gks, gl[3]; };
+
+template <class T>
+__device__ inline void shade_light(const Surf<T> &s, const Light &L, vec3<T> y, Branch br, const T *w, T out[3],
+                                   LAdj<T> *adj) {
+    const T one = 1, zero = 0, two = 2, four = 4, pi = (T)kPi;
+    vec3<T> r = y - s.p;
+    T d2 = dot(r, r), dist = sqrt(d2);
+    vec3<T> wi = r * (one / dist);
+    vec3<T> ln = cvt<T>(L.n);
+    T area = (T)L.area;
+    T cl_raw = -dot(ln, wi), cos_l = br.cl ? cl_raw : zero;
+    T cs_raw = dot(s.ns, wi), cos_s = br.cs ? cs_raw : zero;
+    T g = cos_l * area / d2;
+    T Sv = 0, D = 0, Gv = 0, ch = 0, oh = 0, lh = 1;
+    int gsel = br.gsel;
+    vec3<T> h = vk<T>(0, 0, 0);
+    bool spec = s.spec_on && br.cs;
+    if (spec) {
+        vec3<T> hv = wi + s.wo;
+        lh = len(hv);
+        h = hv * (one / lh);
+        ch = dot(s.ns, h);
+        oh = dot(s.wo, h);
+        T m2 = (T)(kBeckmannM * kBeckmannM), c2 = ch * ch;
+        D = exp(-(one - c2) / (c2 * m2)) / (pi * m2 * c2 * c2);
+        T G1 = two * ch * s.cos_o / oh, G2 = two * ch * cos_s / oh;
+        Gv = gsel == 0 ? one : (gsel == 1 ? G1 : G2);
+        Sv = s.ks * D * Gv / (four * s.cos_o);
+    }
+    T lc[3] = {(T)L.r, (T)L.g, (T)L.b};
+    for (int c = 0; c < 3; ++c) out[c] = lc[c] * (s.A[c] / pi * cos_s + Sv) * g;
+    if (!adj) return;
+    T Ld = 0, Lw = 0;
+    for (int c = 0; c < 3; ++c) {
+        adj->gl[c] = w[c] * (s.A[c] / pi * cos_s + Sv) * g;
+        adj->gA[c] = w[c] * lc[c] * cos_s * g / pi;
+        Ld += w[c] * lc[c] * s.A[c] / pi;
+        Lw += w[c] * lc[c];
+    }
+    T g_cos_s = Ld * g;
+    T g_S = Lw * g;
+    T g_g = Ld * cos_s + Lw * Sv;
+    adj->gks = spec ? g_S * D * Gv / (four * s.cos_o) : zero;
+    T g_cos_l = g_g * area / d2;
+    T g_d2 = -g_g * g / d2;
+    vec3<T> g_wi = vk<T>(0, 0, 0), g_ns = vk<T>(0, 0, 0), g_wo = vk<T>(0, 0, 0);
+    T g_cos_o = 0;
+    if (spec) {
+        T g_G = g_S * s.ks * D / (four * s.cos_o);
+        g_cos_o += -g_S * Sv / s.cos_o;
+        T m2 = (T)(kBeckmannM * kBeckmannM);
+        // dS/dD dD/dch = S (2/(m^2 ch^3) - 4/ch)
+        T g_ch = g_S * Sv * (two / (m2 * ch * ch * ch) - four / ch);
+        T g_oh = 0;
+        if (gsel == 1) {
+            g_ch += g_G * two * s.cos_o / oh;
+            g_cos_o += g_G * two * ch / oh;
+            g_oh += -g_G * Gv / oh;
+        } else if (gsel == 2) {
+            g_ch += g_G * two * cos_s / oh;
+            g_cos_s += g_G * two * ch / oh;
+            g_oh += -g_G * Gv / oh;
+        }
+        g_ns = g_ns + h * g_ch;
+        g_wo = g_wo + h * g_oh;
+        vec3<T> g_h = s.ns * g_ch + s.wo * g_oh;
+        vec3<T> g_hv = norm_adj(g_h, h, lh);
+        g_wi = g_wi + g_hv;
+        g_wo = g_wo + g_hv;
+    }
+    g_ns = g_ns + s.wo * g_cos_o;
+    g_wo = g_wo + s.ns * g_cos_o;
+    T g_cs = br.cs ? g_cos_s : zero;
+    T g_cl = br.cl ? g_cos_l : zero;
+    g_ns = g_ns + wi * g_cs;
+    g_wi = g_wi + s.ns * g_cs;
+    g_wi = g_wi - ln * g_cl;
+    vec3<T> g_r = norm_adj(g_wi, wi, dist) + r * (two * g_d2);
+    adj->gp = g_r * (T)-1;
+    adj->gns = g_ns;
+    adj->gwo = g_wo;
+}
+
+}  // namespace fr

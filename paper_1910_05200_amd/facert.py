@@ -1,0 +1,275 @@
+"""Python binding of libfacert.so (ctypes; argument marshalling only).
+
+The functions ``fr_create`` ... ``fr_destroy`` are the C-ABI entry points of
+include/facert.h with the same names and arguments.  ``Renderer`` keeps a
+context and the model arrays together and passes torch device tensors (their
+``data_ptr``) and the current HIP stream; ``FaceRender`` is the autograd
+function whose backward is fr_backward.  Every step of the render and the
+adjoint runs in the HIP kernels; if the library is missing this module raises
+instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfacert.so")
+
+FR_TIMING = 1
+FR_TERM_INTERIOR, FR_TERM_PRIMARY, FR_TERM_SECONDARY = 1, 2, 4
+STATUS = {0: "FR_OK", -1: "FR_EINVAL", -2: "FR_ENOMEM", -3: "FR_EDEVICE", -4: "FR_ESTATE"}
+
+
+class FrError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class fr_model_desc(C.Structure):
+    _fields_ = [("n_vertices", C.c_int32), ("n_faces", C.c_int32), ("n_id", C.c_int32),
+                ("n_exp", C.c_int32), ("n_alb", C.c_int32), ("faces", C.c_void_p),
+                ("mean", C.c_void_p), ("b_id", C.c_void_p), ("b_exp", C.c_void_p),
+                ("alb_mean", C.c_void_p), ("b_alb", C.c_void_p), ("uv", C.c_void_p)]
+
+
+class fr_scene_desc(C.Structure):
+    _fields_ = [("width", C.c_int32), ("height", C.c_int32), ("cam", C.c_float * 3),
+                ("pix_scale", C.c_float), ("n_lights", C.c_int32), ("light_geom", C.c_void_p),
+                ("spec_res", C.c_int32)]
+
+
+class fr_params(C.Structure):
+    _fields_ = [(n, C.c_void_p) for n in ("alpha", "beta", "delta", "pose", "lights", "spec")]
+
+
+class fr_grads(C.Structure):
+    _fields_ = [(n, C.c_void_p) for n in ("d_lights", "d_spec", "d_vertices", "d_albedo",
+                                          "d_alpha", "d_beta", "d_delta", "d_pose")]
+
+
+class fr_stats_t(C.Structure):
+    _fields_ = [("rays_camera", C.c_uint64), ("rays_shadow", C.c_uint64),
+                ("rays_edge_primary", C.c_uint64), ("rays_edge_secondary", C.c_uint64),
+                ("traversal_overflow", C.c_uint64), ("box_tests", C.c_uint64), ("tri_tests", C.c_uint64),
+                ("kernel_rays", C.c_uint64 * 4), ("kernel_box_tests", C.c_uint64 * 4),
+                ("kernel_tri_tests", C.c_uint64 * 4), ("kernel_shades", C.c_uint64 * 4),
+                ("grazing_samples", C.c_uint64),
+                ("ms_blend", C.c_float), ("ms_bvh", C.c_float),
+                ("ms_edges", C.c_float), ("ms_render", C.c_float), ("ms_backward", C.c_float),
+                ("ms_kernel_fwd", C.c_float), ("ms_kernel_adj", C.c_float)]
+
+
+EXPORTS = ("fr_create", "fr_set_stream", "fr_set_terms", "fr_blend", "fr_render", "fr_backward",
+           "fr_loss_l2", "fr_stats", "fr_last_error", "fr_destroy")
+
+_lib = None
+
+
+def load():
+    """Load libfacert.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise FileNotFoundError(f"{LIB_PATH} is missing: build it with "
+                                    "`python -m paper_1910_05200_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, u32, u64 = C.c_void_p, C.c_int32, C.c_uint32, C.c_uint64
+        L.fr_create.argtypes = [C.POINTER(fr_model_desc), C.POINTER(fr_scene_desc), u32, C.POINTER(vp)]
+        L.fr_set_stream.argtypes = [vp, vp]
+        L.fr_set_terms.argtypes = [vp, u32]
+        L.fr_blend.argtypes = [vp] * 7
+        L.fr_render.argtypes = [vp, C.POINTER(fr_params), u64, i32, vp]
+        L.fr_backward.argtypes = [vp, vp, C.POINTER(fr_grads)]
+        L.fr_loss_l2.argtypes = [vp] * 5
+        L.fr_stats.argtypes = [vp, C.POINTER(fr_stats_t)]
+        L.fr_last_error.argtypes = [vp]
+        L.fr_last_error.restype = C.c_char_p
+        L.fr_destroy.argtypes = [vp]
+        L.fr_destroy.restype = None
+        for n in EXPORTS:
+            if n != "fr_last_error" and n != "fr_destroy":
+                getattr(L, n).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(ctx, code: int):
+    if code != 0:
+        msg = load().fr_last_error(ctx)
+        raise FrError(code, msg.decode() if msg else "")
+
+
+def _ptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    if isinstance(t, np.ndarray):
+        return t.ctypes.data
+    return t.data_ptr()
+
+
+class Renderer:
+    """One fr_ctx plus the host copies it was created from.
+
+    model/scene: ``synth.Model`` / ``synth.Scene``.  Parameter tensors passed
+    to ``render`` must be contiguous float32 on the current HIP device, except
+    ``pose`` (6 floats, host).
+    """
+
+    def __init__(self, model, scene, timing: bool = False):
+        import torch
+        self.torch = torch
+        L = load()
+        self._keep = {k: np.ascontiguousarray(getattr(model, k)) for k in
+                      ("faces", "mean", "b_id", "b_exp", "alb_mean", "b_alb", "uv")}
+        self._keep["faces"] = np.ascontiguousarray(self._keep["faces"], np.int32)
+        for k in ("mean", "b_id", "b_exp", "alb_mean", "b_alb", "uv"):
+            self._keep[k] = np.ascontiguousarray(self._keep[k], np.float32)
+        self._lg = np.ascontiguousarray(scene.light_geom, np.float32)
+        k = self._keep
+        md = fr_model_desc(model.n_vertices, model.n_faces, k["b_id"].shape[0], k["b_exp"].shape[0],
+                           k["b_alb"].shape[0], *(k[n].ctypes.data for n in
+                                                  ("faces", "mean", "b_id", "b_exp", "alb_mean", "b_alb", "uv")))
+        sd = fr_scene_desc(scene.width, scene.height, (C.c_float * 3)(*[float(x) for x in scene.cam]),
+                           float(scene.pix_scale), self._lg.shape[0], self._lg.ctypes.data, scene.spec_res)
+        ctx = C.c_void_p()
+        code = L.fr_create(C.byref(md), C.byref(sd), FR_TIMING if timing else 0, C.byref(ctx))
+        if code != 0:
+            raise FrError(code, "fr_create failed")
+        self.ctx = ctx
+        self.V, self.F = model.n_vertices, model.n_faces
+        self.W, self.H = scene.width, scene.height
+        self.n_lights = self._lg.shape[0]
+        self.spec_res = scene.spec_res
+        self.n_id, self.n_exp, self.n_alb = md.n_id, md.n_exp, md.n_alb
+        self.render_token = 0
+        self._last = None
+
+    # -- plumbing
+    def _stream(self):
+        _check(self.ctx, load().fr_set_stream(self.ctx, self.torch.cuda.current_stream().cuda_stream))
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            load().fr_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_terms(self, terms: int):
+        _check(self.ctx, load().fr_set_terms(self.ctx, terms))
+
+    # -- calls
+    def blend(self, alpha, beta, delta, pose):
+        t = self.torch
+        self._stream()
+        v = t.empty((3, self.V), device=alpha.device, dtype=t.float32)
+        a = t.empty((3, self.V), device=alpha.device, dtype=t.float32)
+        pose_h = np.ascontiguousarray(np.asarray(pose, np.float32).reshape(6))
+        _check(self.ctx, load().fr_blend(self.ctx, _ptr(alpha), _ptr(beta), _ptr(delta),
+                                         pose_h.ctypes.data, _ptr(v), _ptr(a)))
+        return v, a
+
+    def render(self, p: dict, seed: int, spp: int, out=None):
+        t = self.torch
+        self._stream()
+        if out is None:
+            out = t.empty((self.H, self.W, 3), device=p["lights"].device, dtype=t.float32)
+        pose_h = np.ascontiguousarray(np.asarray(p["pose"], np.float32).reshape(6))
+        fp = fr_params(_ptr(p["alpha"]), _ptr(p["beta"]), _ptr(p["delta"]), pose_h.ctypes.data,
+                       _ptr(p["lights"]), _ptr(p["spec"]))
+        _check(self.ctx, load().fr_render(self.ctx, C.byref(fp), seed, spp, _ptr(out)))
+        self.render_token += 1
+        self._last = (p, pose_h)          # keep the arrays alive for fr_backward
+        return out
+
+    def backward(self, dL_dimage, want=("d_lights", "d_spec", "d_vertices", "d_albedo",
+                                         "d_alpha", "d_beta", "d_delta", "d_pose")):
+        t = self.torch
+        self._stream()
+        dev = dL_dimage.device
+        shapes = {"d_lights": (self.n_lights, 3), "d_spec": (self.spec_res ** 2,),
+                  "d_vertices": (3, self.V), "d_albedo": (3, self.V), "d_alpha": (self.n_id,),
+                  "d_beta": (self.n_exp,), "d_delta": (self.n_alb,), "d_pose": (6,)}
+        out = {k: t.empty(shapes[k], device=dev, dtype=t.float32) for k in want}
+        g = fr_grads(*[_ptr(out.get(k)) for k, _ in fr_grads._fields_])
+        _check(self.ctx, load().fr_backward(self.ctx, _ptr(dL_dimage.contiguous()), C.byref(g)))
+        return out
+
+    def loss_l2(self, image, target):
+        t = self.torch
+        self._stream()
+        dL = t.empty_like(image)
+        loss = t.empty((), device=image.device, dtype=t.float32)
+        _check(self.ctx, load().fr_loss_l2(self.ctx, _ptr(image), _ptr(target), _ptr(dL), _ptr(loss)))
+        return dL, loss
+
+    def stats(self) -> dict:
+        s = fr_stats_t()
+        _check(self.ctx, load().fr_stats(self.ctx, C.byref(s)))
+        out = {}
+        for k, _ in fr_stats_t._fields_:
+            v = getattr(s, k)
+            out[k] = list(v) if isinstance(v, C.Array) else v
+        return out
+
+
+def params_to_device(params, device="cuda"):
+    """synth.Params -> dict of device tensors (pose stays on the host)."""
+    import torch
+    d = {k: torch.from_numpy(np.ascontiguousarray(getattr(params, k), np.float32)).to(device)
+         for k in ("alpha", "beta", "delta", "lights", "spec")}
+    d["pose"] = np.asarray(params.pose, np.float32).copy()
+    return d
+
+
+def _make_autograd():
+    import torch
+
+    class FaceRender(torch.autograd.Function):
+        """image = F(alpha, beta, delta, pose, lights, spec; seed, spp).
+
+        The backward recomputes the samples of the forward (same seed and
+        spp) inside fr_backward instead of storing hit records."""
+
+        @staticmethod
+        def forward(ctx, renderer, seed, spp, alpha, beta, delta, pose, lights, spec):
+            p = {"alpha": alpha.detach().contiguous(), "beta": beta.detach().contiguous(),
+                 "delta": delta.detach().contiguous(), "pose": pose.detach().cpu().numpy(),
+                 "lights": lights.detach().contiguous(), "spec": spec.detach().contiguous()}
+            img = renderer.render(p, seed, spp)
+            ctx.renderer, ctx.seed, ctx.spp, ctx.p = renderer, seed, spp, p
+            ctx.token = renderer.render_token
+            ctx.pose_device = pose.device
+            return img
+
+        @staticmethod
+        def backward(ctx, grad_img):
+            r = ctx.renderer
+            if r.render_token != ctx.token:       # another render ran since: recompute state
+                r.render(ctx.p, ctx.seed, ctx.spp)
+            g = r.backward(grad_img.contiguous(), want=("d_alpha", "d_beta", "d_delta", "d_pose",
+                                                        "d_lights", "d_spec"))
+            return (None, None, None, g["d_alpha"], g["d_beta"], g["d_delta"],
+                    g["d_pose"].to(ctx.pose_device), g["d_lights"], g["d_spec"])
+
+    return FaceRender
+
+
+_face_render = None
+
+
+def face_render(renderer, seed, spp, alpha, beta, delta, pose, lights, spec):
+    """Differentiable render (torch autograd) through fr_render/fr_backward."""
+    global _face_render
+    if _face_render is None:
+        _face_render = _make_autograd()
+    return _face_render.apply(renderer, seed, spp, alpha, beta, delta, pose, lights, spec)

@@ -117,18 +117,22 @@ def _rff_fields(x: np.ndarray, n_fields: int, ell: float,
 
     g(x) = sqrt(2/m) sum_k w_k cos(omega_k . x + phi_k), omega ~ N(0, I/ell^2),
     phi ~ U[0, 2 pi), w ~ N(0, 1): a unit-variance field with a Gaussian
-    covariance of length scale ell.
+    covariance of length scale ell.  (Evaluated in float32 with torch CPU
+    ops for multithreading; the random draws come from ``rng``.)
     """
+    import torch
     omega = rng.normal(0.0, 1.0 / ell, size=(n_fields, m, 3))
     phi = rng.uniform(0.0, 2.0 * math.pi, size=(n_fields, m))
     w = rng.normal(0.0, 1.0, size=(n_fields, m))
-    out = np.empty((n_fields, x.shape[0]), dtype=np.float64)
-    chunk = max(1, 4_000_000 // max(1, x.shape[0] * m))
+    X = torch.from_numpy(np.ascontiguousarray(x, np.float32))
+    Om, Ph, Wt = (torch.from_numpy(a.astype(np.float32)) for a in (omega, phi, w))
+    out = torch.empty((n_fields, x.shape[0]), dtype=torch.float32)
+    chunk = max(1, 16_000_000 // max(1, x.shape[0] * m))
     for s in range(0, n_fields, chunk):
         e = min(n_fields, s + chunk)
-        ph = np.einsum("vc,fmc->fvm", x, omega[s:e]) + phi[s:e, None, :]
-        out[s:e] = math.sqrt(2.0 / m) * np.einsum("fvm,fm->fv", np.cos(ph), w[s:e])
-    return out
+        ph = torch.einsum("vc,fmc->fvm", X, Om[s:e]) + Ph[s:e, None, :]
+        out[s:e] = math.sqrt(2.0 / m) * torch.einsum("fvm,fm->fv", torch.cos(ph), Wt[s:e])
+    return out.numpy().astype(np.float64)
 
 
 def make_model(nx: int, ny: int, seed: int = GEN_SEED,

@@ -1,0 +1,171 @@
+"""GPU (libfacert through the C-ABI) against the CPU oracle.
+
+Bars: positions and albedo bit-exact (fp64 sums in a fixed order, rounded
+once); pixels within 1e-4 relative; gradient components within 1e-4
+relative to max(|ref|, 1e-2 * max|ref| of the group).
+"""
+import numpy as np
+import pytest
+
+from paper_1910_05200_amd import synth
+from parity import assert_group_parity, assert_image_parity
+
+pytestmark = pytest.mark.gpu
+
+SEED = 1000
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as T
+    if not T.cuda.is_available():
+        pytest.skip("no HIP device")
+    return T
+
+
+def _case(name):
+    model, scene, params, spp = synth.workload(name)
+    return model, scene, params, spp
+
+
+def _renderer(torch, model, scene):
+    from paper_1910_05200_amd import facert
+    return facert.Renderer(model, scene, timing=True)
+
+
+def _gpu_render(torch, r, params, seed, spp):
+    from paper_1910_05200_amd import facert
+    p = facert.params_to_device(params)
+    img = r.render(p, seed, spp)
+    torch.cuda.synchronize()
+    return img.cpu().numpy().astype(np.float64), p
+
+
+@pytest.mark.parametrize("name", ["tiny", "paper"])
+def test_blend_bitwise(torch, orc, name):
+    model, scene, params, spp = _case(name)
+    r = _renderer(torch, model, scene)
+    p = {k: torch.from_numpy(getattr(params, k)).cuda() for k in ("alpha", "beta", "delta")}
+    v, a = r.blend(p["alpha"], p["beta"], p["delta"], params.pose)
+    torch.cuda.synchronize()
+    vm, vo, Ao, R = orc.blend(model, params)
+    assert np.array_equal(v.cpu().numpy(), vo.astype(np.float32))
+    assert np.array_equal(a.cpu().numpy(), Ao.astype(np.float32))
+
+
+def test_render_parity_tiny(torch, orc):
+    model, scene, params, spp = _case("tiny")
+    r = _renderer(torch, model, scene)
+    img, _ = _gpu_render(torch, r, params, SEED, spp)
+    osc, _, _ = orc.scene_from_model(model, scene, params)
+    ref, cnt = orc.render(osc, SEED, spp, counts=True)
+    assert (ref.sum(-1) > 0).mean() > 0.2
+    worst = assert_image_parity(img, ref)
+    st = r.stats()
+    assert st["rays_camera"] == cnt.camera and st["rays_shadow"] == cnt.shadow
+    print(f"tiny render worst rel {worst:.3g}")
+
+
+def test_render_deterministic(torch):
+    model, scene, params, spp = _case("tiny")
+    r = _renderer(torch, model, scene)
+    a, _ = _gpu_render(torch, r, params, SEED, spp)
+    b, _ = _gpu_render(torch, r, params, SEED, spp)
+    assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("nx,ny,W,H,spp", [(7, 11, 37, 23, 3), (20, 9, 1, 1, 1), (16, 16, 300, 5, 2)])
+def test_render_parity_ragged(torch, orc, nx, ny, W, H, spp):
+    model = synth.make_model(nx, ny)
+    scene = synth.make_scene(W, H)
+    params = synth.make_params(5)
+    r = _renderer(torch, model, scene)
+    img, _ = _gpu_render(torch, r, params, 77, spp)
+    osc, _, _ = orc.scene_from_model(model, scene, params)
+    assert_image_parity(img, orc.render(osc, 77, spp))
+
+
+def test_render_parity_paper_sampled(torch, orc):
+    model, scene, params, spp = _case("paper")
+    r = _renderer(torch, model, scene)
+    img, _ = _gpu_render(torch, r, params, SEED, spp)
+    osc, _, _ = orc.scene_from_model(model, scene, params)
+    rng = np.random.default_rng(0)
+    lit = np.flatnonzero(img.reshape(-1, 3).sum(-1) > 0)
+    pix = np.concatenate([rng.choice(lit, 384, replace=False), rng.integers(0, 256 * 256, 128)])
+    ref = orc.render_pixels(osc, SEED, spp, pix)
+    assert_image_parity(img.reshape(-1, 3)[pix], ref)
+
+
+def _grad_case(torch, orc, name, terms):
+    from paper_1910_05200_amd import facert
+    model, scene, params, spp = _case(name)
+    tosc, _, _ = orc.scene_from_model(model, scene, synth.make_params(synth.TARGET_SCENE_SEED))
+    target = orc.render(tosc, synth.TARGET_RENDER_SEED, 16)
+    osc, vm, R = orc.scene_from_model(model, scene, params)
+    ref_img = orc.render(osc, SEED, spp)
+    dL = (2 * (ref_img - target)).astype(np.float32)
+    r = _renderer(torch, model, scene)
+    r.set_terms(terms)
+    img, p = _gpu_render(torch, r, params, SEED, spp)
+    g = r.backward(torch.from_numpy(dL).cuda())
+    torch.cuda.synchronize()
+    g = {k: v.cpu().numpy() for k, v in g.items()}
+    flags = (1 if terms & facert.FR_TERM_INTERIOR else 0) | (2 if terms & facert.FR_TERM_PRIMARY else 0) \
+        | (4 if terms & facert.FR_TERM_SECONDARY else 0)
+    ref = orc.backward(osc, SEED, spp, dL.astype(np.float64), flags=flags)
+    pg = orc.parameter_grads(model, params, vm, R, ref["d_pos"], ref["d_alb"])
+    return g, ref, pg, r
+
+
+def _compare(g, ref, pg):
+    out = {}
+    out["lights"] = assert_group_parity(g["d_lights"], ref["d_light"], "d_lights")
+    out["spec"] = assert_group_parity(g["d_spec"], ref["d_spec"], "d_spec")
+    out["albedo"] = assert_group_parity(g["d_albedo"], ref["d_alb"], "d_albedo")
+    out["vertices"] = assert_group_parity(g["d_vertices"], ref["d_pos"], "d_vertices")
+    out["alpha"] = assert_group_parity(g["d_alpha"], pg["d_alpha"], "d_alpha")
+    out["beta"] = assert_group_parity(g["d_beta"], pg["d_beta"], "d_beta")
+    out["delta"] = assert_group_parity(g["d_delta"], pg["d_delta"], "d_delta")
+    out["pose"] = assert_group_parity(g["d_pose"], pg["d_pose"], "d_pose")
+    print({k: f"{a:.2g}/{b:.2g}" for k, (a, b) in out.items()})
+
+
+def test_backward_interior_tiny(torch, orc):
+    from paper_1910_05200_amd import facert
+    g, ref, pg, _ = _grad_case(torch, orc, "tiny", facert.FR_TERM_INTERIOR)
+    _compare(g, ref, pg)
+
+
+def test_backward_all_terms_tiny(torch, orc):
+    g, ref, pg, r = _grad_case(torch, orc, "tiny", 7)
+    st = r.stats()
+    assert st["rays_edge_secondary"] > 0 and st["rays_edge_primary"] > 0
+    _compare(g, ref, pg)
+
+
+def test_backward_all_terms_paper(torch, orc):
+    g, ref, pg, _ = _grad_case(torch, orc, "paper", 7)
+    _compare(g, ref, pg)
+
+
+def test_error_codes(torch):
+    from paper_1910_05200_amd import facert
+    model, scene, params, spp = _case("tiny")
+    r = _renderer(torch, model, scene)
+    with pytest.raises(facert.FrError) as e:
+        r.backward(torch.zeros((64, 64, 3), device="cuda"))
+    assert e.value.code == -4
+    p = facert.params_to_device(params)
+    with pytest.raises(facert.FrError) as e:
+        r.render(p, 1, 0)
+    assert e.value.code == -1
+    bad = dict(p)
+    bad["pose"] = np.array([np.nan, 0, 0, 0, 0, 0], np.float32)
+    with pytest.raises(facert.FrError) as e:
+        r.render(bad, 1, 4)
+    assert e.value.code == -1
+    # the context is still usable
+    img = r.render(p, 1, 2)
+    torch.cuda.synchronize()
+    assert float(img.sum()) > 0

@@ -135,15 +135,15 @@ def test_parameter_grads_frozen_fd(orc, setup):
             fd.append((loss_with(alb=alb0 + 1e-3 * dA) - loss_with(alb=alb0 - 1e-3 * dA)) / 2e-3)
         _check(fd, pg["d_delta"][[0, 5, 41, 79]], np.abs(pg["d_delta"]).max(), 1e-7)
         ang = params.pose[:3].astype(np.float64)
-        t = params.pose[3:].astype(np.float64)[:, None]
         # near-grazing hits make the frozen estimator strongly curved: a
         # rigid motion must stay ~1e-9 m for the central difference to settle
         fd = []
         h = 1e-8
         for k in range(3):
             e = np.zeros(3); e[k] = h
-            vp = Rotation.from_euler("xyz", ang + e).as_matrix() @ vm + t
-            vmn = Rotation.from_euler("xyz", ang - e).as_matrix() @ vm + t
+            R0 = Rotation.from_euler("xyz", ang).as_matrix()
+            vp = pos0 + (Rotation.from_euler("xyz", ang + e).as_matrix() - R0) @ vm
+            vmn = pos0 + (Rotation.from_euler("xyz", ang - e).as_matrix() - R0) @ vm
             fd.append((loss_with(pos=vp) - loss_with(pos=vmn)) / (2 * h))
         h = 1e-9
         for k in range(3):
