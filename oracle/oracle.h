@@ -30,8 +30,11 @@
  *
  * Parity pins (see the test suite): Philox known-answer vectors; blend
  * against a float64 matrix product; normals on flat and spherical grids;
- * intersection against brute force; Lambert's polygon irradiance formula;
- * a furnace box; central finite differences for gradients.
+ * intersection against exact rational arithmetic and brute force; Lambert's
+ * polygon irradiance formula with and without a triangle shadow; a furnace
+ * box; the textbook Beckmann lobe; central finite differences for the
+ * interior gradient; for the edge terms, finite differences of exact
+ * (quadrature, clipped-polygon Lambert) image and shadow integrals.
  */
 #ifndef FACERT_ORACLE_H
 #define FACERT_ORACLE_H
