@@ -43,6 +43,8 @@ def parse():
     ap.add_argument("--workload", default="paper", choices=["paper", "tiny"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run one plain 256 MiB device copy first (scale for HBM byte counters)")
     return ap.parse_args()
 
 
@@ -76,6 +78,12 @@ def main():
     assert torch.cuda.is_available(), "bench needs a HIP device"
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.calibrate_copy:
+        src = torch.ones(64 << 20, device=dev, dtype=torch.float32)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     model, scene, params, spp = synth.workload(args.workload)
     r = facert.Renderer(model, scene, timing=True)
     p = facert.params_to_device(params)
@@ -138,7 +146,11 @@ def main():
                                f"morphable face, {scene.width}x{scene.height}, {spp} spp, 20 area lights, "
                                "forward + adjoint (interior, camera-silhouette and shadow-boundary terms)",
                    "rays_per_iter": rays_per_iter, "ms_kernel_fwd": float(np.mean(fwd_ms)),
-                   "ms_kernel_adj": float(np.mean(adj_ms))},
+                   "ms_kernel_adj": float(np.mean(adj_ms)),
+                   "box_tests_per_ray": [round(b / max(1, n), 2) for b, n in
+                                         zip(per_step[-1]["kernel_box_tests"], per_step[-1]["kernel_rays"])],
+                   "tri_tests_per_ray": [round(b / max(1, n), 2) for b, n in
+                                         zip(per_step[-1]["kernel_tri_tests"], per_step[-1]["kernel_rays"])]},
         "roofline": {"bound": "alu", "kernel": "k_render_adj", "achieved": achieved, "peak": PEAK_VALU,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_VALU, "traffic": None},
     }

@@ -286,8 +286,9 @@ __device__ __forceinline__ v3 camera_sample(const Scene &S, uint64_t seed, uint3
 // decisions in fp32, values in T.
 template <class T>
 __device__ inline void radiance(const Scene &S, const Light *Ls, const float *spec_lds, v3 d,
-                                LightRng &rng, T out[3], uint32_t &n_shadow, Work &wk) {
+                                LightRng &rng, T out[3], uint32_t &n_shadow, Work &wk, uint32_t *vis = nullptr) {
     out[0] = out[1] = out[2] = 0;
+    if (vis) *vis = 0u;
     v3 o = mk(S.cam_x, S.cam_y, S.cam_z);
     Hit h = trace_closest(S, o, d, wk);
     if (h.tri < 0) return;
@@ -303,6 +304,7 @@ __device__ inline void radiance(const Scene &S, const Light *Ls, const float *sp
         if (!above(sd, y)) continue;
         ++n_shadow;
         if (trace_any(S, sd.p, y - sd.p, h.tri, wk)) continue;
+        if (vis) *vis |= 1u << j;
         T c[3];
         shade_light<T>(sv, L, cvt<T>(y), light_branch(sd, L.n, y), nullptr, c, nullptr);
         ++wk.shade;
@@ -323,8 +325,10 @@ __device__ inline void flush_work(unsigned long long *ctr, const Work &w) {
     flush_count(ctr, 6, w.shade);
 }
 
+// One lane per camera sample.  With at most 32 lights each sample's light
+// visibility (horizon and shadow ray) is kept as a bit mask for the adjoint.
 __global__ __launch_bounds__(256) void k_render_fwd(Scene S, uint64_t seed, int spp, long long N,
-        float *__restrict__ samples, unsigned long long *ctr) {
+        float *__restrict__ samples, uint32_t *__restrict__ vis_out, unsigned long long *ctr) {
     extern __shared__ float dyn[];
     __shared__ Light Ls[kMaxLights];
     float *spec_lds = dyn;
@@ -338,9 +342,11 @@ __global__ __launch_bounds__(256) void k_render_fwd(Scene S, uint64_t seed, int 
         v3 d = camera_sample(S, seed, (uint32_t)s, spp, pix);
         LightRng rng(seed, (uint32_t)s, 0, 2);
         float c[3];
-        radiance<float>(S, Ls, spec_lds, d, rng, c, n_sh, wk);
+        uint32_t vis;
+        radiance<float>(S, Ls, spec_lds, d, rng, c, n_sh, wk, &vis);
         n_cam = 1;
         samples[3 * s] = c[0]; samples[3 * s + 1] = c[1]; samples[3 * s + 2] = c[2];
+        if (vis_out) vis_out[s] = vis;
     }
     flush_count(ctr, 0, n_cam);
     flush_count(ctr, 1, n_sh);
@@ -394,7 +400,7 @@ template <class T>
 __device__ inline void adjoint_sample(const Scene &S, const Light *Ls, uint64_t seed, uint32_t s,
                                       const float *wf, const Hit &h, const SurfDec &sd, const Surf<T> &sv,
                                       float *g_light_lds, float *g_spec_lds, const GradBufs &G,
-                                      uint32_t &n_sh, Work &wk) {
+                                      const uint32_t *vis, uint32_t &n_sh, Work &wk) {
     int V = S.V;
     T w[3] = {(T)wf[0], (T)wf[1], (T)wf[2]};
     vec3<T> gp = vk<T>(0, 0, 0), gns = vk<T>(0, 0, 0), gwo = vk<T>(0, 0, 0);
@@ -405,9 +411,13 @@ __device__ inline void adjoint_sample(const Scene &S, const Light *Ls, uint64_t 
         rng.get(j, u, v);
         const Light &L = Ls[j];
         v3 y = light_point(L, u, v);
-        if (!above(sd, y)) continue;
-        ++n_sh;
-        if (trace_any(S, sd.p, y - sd.p, h.tri, wk)) continue;
+        if (vis) {
+            if (!((*vis >> j) & 1u)) continue;     // the forward pass's decision
+        } else {
+            if (!above(sd, y)) continue;
+            ++n_sh;
+            if (trace_any(S, sd.p, y - sd.p, h.tri, wk)) continue;
+        }
         T c[3];
         LAdj<T> a;
         shade_light<T>(sv, L, cvt<T>(y), light_branch(sd, L.n, y), w, c, &a);
@@ -446,11 +456,12 @@ __device__ inline void adjoint_sample(const Scene &S, const Light *Ls, uint64_t 
     chain_hit<T>(V, sv, gp, gb[0], gb[1], gb[2], G.d_pos);
 }
 
-// Interior adjoint, fp32.  Samples seen at a grazing angle are queued for
-// the fp64 pass instead.
+// Interior adjoint, fp32: one lane per camera sample.  The camera hit is
+// recomputed (no hit records are stored); light visibility comes from the
+// forward pass's bit masks when it kept them, else the shadow rays are
+// traced again.
 __global__ __launch_bounds__(256) void k_render_adj(Scene S, uint64_t seed, int spp, long long N,
-        const float *__restrict__ dLdI, GradBufs G, int *__restrict__ queue, int *__restrict__ qcount,
-        unsigned long long *ctr) {
+        const float *__restrict__ dLdI, GradBufs G, const uint32_t *__restrict__ vis_in, unsigned long long *ctr) {
     extern __shared__ float dyn[];
     __shared__ Light Ls[kMaxLights];
     float *spec_lds = dyn;
@@ -476,11 +487,10 @@ __global__ __launch_bounds__(256) void k_render_adj(Scene S, uint64_t seed, int 
             surf_decide(S, o, h, sd);
             Surf<float> sv;
             surf_value<float>(S, spec_lds, o, d, h, sd, sv);
-            float cg = fabsf(sv.ndotd) / (len(sv.N) * len(sv.dir));
-            if (fabsf(sv.cos_o) < kGrazingCos || cg < kGrazingCos) {
-                queue[atomicAdd(qcount, 1)] = (int)s;
-            } else if (w[0] != 0.0f || w[1] != 0.0f || w[2] != 0.0f) {
-                adjoint_sample<float>(S, Ls, seed, (uint32_t)s, w, h, sd, sv, g_light, g_spec, G, n_sh, wk);
+            if (w[0] != 0.0f || w[1] != 0.0f || w[2] != 0.0f) {
+                uint32_t vis = vis_in ? vis_in[s] : 0u;
+                adjoint_sample<float>(S, Ls, seed, (uint32_t)s, w, h, sd, sv, g_light, g_spec, G,
+                                      vis_in ? &vis : nullptr, n_sh, wk);
             }
         }
     }
@@ -494,41 +504,14 @@ __global__ __launch_bounds__(256) void k_render_adj(Scene S, uint64_t seed, int 
         if (g_light[k] != 0.0f) gadd(&G.d_light[k], (double)g_light[k]);
 }
 
-// Interior adjoint of the queued (grazing) samples, fp64.  Grid-stride over
-// the queue; every lane exits once the queue is exhausted.
-__global__ __launch_bounds__(256) void k_render_adj_f64(Scene S, uint64_t seed, int spp,
-        const float *__restrict__ dLdI, GradBufs G, const int *__restrict__ queue, const int *__restrict__ qcount,
-        unsigned long long *ctr) {
-    extern __shared__ float dyn[];
-    __shared__ Light Ls[kMaxLights];
-    float *spec_lds = dyn;
-    stage_tables(S, Ls, spec_lds);
-    __syncthreads();
-    int n = *qcount;
-    uint32_t n_sh = 0;
-    Work wk;
-    for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) {
-        uint32_t s = (uint32_t)queue[q];
-        int pix;
-        v3 o = mk(S.cam_x, S.cam_y, S.cam_z);
-        v3 d = camera_sample(S, seed, s, spp, pix);
-        Hit h = trace_closest(S, o, d, wk);
-        if (h.tri < 0) continue;
-        float inv = 1.0f / (float)spp;
-        float w[3] = {dLdI[3 * pix] * inv, dLdI[3 * pix + 1] * inv, dLdI[3 * pix + 2] * inv};
-        if (w[0] == 0.0f && w[1] == 0.0f && w[2] == 0.0f) continue;
-        SurfDec sd;
-        surf_decide(S, o, h, sd);
-        Surf<double> sv;
-        surf_value<double>(S, spec_lds, o, d, h, sd, sv);
-        adjoint_sample<double>(S, Ls, seed, s, w, h, sd, sv, nullptr, nullptr, G, n_sh, wk);
-    }
-    flush_count(ctr, 1, n_sh);
-    flush_work(ctr, wk);
-}
+#ifndef FR_EDGE_REAL
+#define FR_EDGE_REAL double
+#endif
+using ER = FR_EDGE_REAL;   // value type of the edge samples
+using e3 = vec3<ER>;
 
 // Shadow-boundary (secondary) edge sample of light j at a camera sample's
-// shading point; decisions fp32, values fp64.
+// shading point; decisions fp32, values in ER.
 __device__ inline void secondary_edge(const Scene &S, const Light &L, int j, uint64_t seed, uint32_t sidx,
                                       const float *spec_lds, v3 o, v3 dcam, const Hit &h, const SurfDec &sf,
                                       const float *w, double *d_pos, uint32_t &n_rays, Work &steps) {
@@ -571,30 +554,30 @@ __device__ inline void secondary_edge(const Scene &S, const Light &L, int j, uin
     bool vp = !trace_any(S, p, yp - p, h.tri, steps);
     bool vm = !trace_any(S, p, ym - p, h.tri, steps);
     if (vp == vm) return;
-    // ---- value path (fp64)
-    Surf<double> sd;
-    surf_value<double>(S, spec_lds, o, dcam, h, sf, sd);
-    double hc[3];
-    shade_light<double>(sd, L, cvt<double>(y), light_branch(sf, L.n, y), nullptr, hc, nullptr);
-    double hw = (w[0] * hc[0] + w[1] * hc[1] + w[2] * hc[2]) / (double)L.area;
-    d3 P = sd.p, A = cvt<double>(a), B = cvt<double>(b), Y = cvt<double>(y), Nl = cvt<double>(L.n);
-    d3 pa = A - P, pb = B - P, py = Y - P;
-    d3 mval = cross(pa, pb);
-    d3 dpsi_a = cross(pb, py), dpsi_b = cross(py, pa);
-    d3 dpsi_p = (mval + dpsi_a + dpsi_b) * -1.0;
-    d3 bma = B - A;
-    d3 Sd = A + bma * (double)tu;
-    double nsp = dot(Nl, Sd - P);
-    double lamd = dot(Nl, cvt<double>(L.c) - P) / nsp;
-    d3 dydt = bma * lamd - (Sd - P) * (lamd * dot(Nl, bma) / nsp);
-    d3 mpar = mval - Nl * dot(mval, Nl);
+    // ---- value path
+    Surf<ER> sd;
+    surf_value<ER>(S, spec_lds, o, dcam, h, sf, sd);
+    ER hc[3];
+    shade_light<ER>(sd, L, cvt<ER>(y), light_branch(sf, L.n, y), nullptr, hc, nullptr);
+    ER hw = ((ER)w[0] * hc[0] + (ER)w[1] * hc[1] + (ER)w[2] * hc[2]) / (ER)L.area;
+    e3 P = sd.p, A = cvt<ER>(a), B = cvt<ER>(b), Y = cvt<ER>(y), Nl = cvt<ER>(L.n);
+    e3 pa = A - P, pb = B - P, py = Y - P;
+    e3 mval = cross(pa, pb);
+    e3 dpsi_a = cross(pb, py), dpsi_b = cross(py, pa);
+    e3 dpsi_p = (mval + dpsi_a + dpsi_b) * (ER)-1;
+    e3 bma = B - A;
+    e3 Sd = A + bma * (ER)tu;
+    ER nsp = dot(Nl, Sd - P);
+    ER lamd = dot(Nl, cvt<ER>(L.c) - P) / nsp;
+    e3 dydt = bma * lamd - (Sd - P) * (lamd * dot(Nl, bma) / nsp);
+    e3 mpar = mval - Nl * dot(mval, Nl);
     uint64_t qe = (i + 1 < n ? pre[i + 1] : Q) - pre[i];
-    double pe = (double)qe / (double)Q;
-    double W = hw * (vp ? 1.0 : -1.0) * len(dydt) / (len(mpar) * pe);
+    ER pe = (ER)((double)qe / (double)Q);
+    ER W = hw * (vp ? (ER)1 : (ER)-1) * len(dydt) / (len(mpar) * pe);
     atomic_v(d_pos, S.V, ed[0], dpsi_a * W);
     atomic_v(d_pos, S.V, ed[1], dpsi_b * W);
     // the receiver point p moves along the fixed camera ray
-    chain_hit<double>(S.V, sd, dpsi_p * W, 0.0, 0.0, 0.0, d_pos);
+    chain_hit<ER>(S.V, sd, dpsi_p * W, (ER)0, (ER)0, (ER)0, d_pos);
 }
 
 // One lane per camera sample: one shadow-boundary sample per light.
@@ -630,68 +613,152 @@ __global__ __launch_bounds__(256) void k_edge_secondary(Scene S, uint64_t seed, 
     flush_work(ctr, wk);
 }
 
-// camera-silhouette (primary) edge samples: M = W*H
-__global__ __launch_bounds__(256) void k_edge_primary(Scene S, uint64_t seed, int M, const float *__restrict__ dLdI,
-        double *d_pos, unsigned long long *ctr) {
+// ---------------------------------------------- camera silhouettes -----
+// M = W*H edge samples, in three passes so that the 40 shadow rays of a
+// sample run on 40 lanes:
+//   k_edge_primary_setup  one lane per sample: pick the edge, the point q
+//                         on its projection, the two sides q +- offset; trace
+//                         both camera rays and keep the hits;
+//   k_edge_primary_shade  one lane per (sample, side, light): shadow ray and
+//                         fp64 radiance of that light, summed per side;
+//   k_edge_primary_scatter one lane per sample: (f+ - f-) times the boundary
+//                         Jacobian into the edge's two endpoints.
+struct PeSample { int e, i, pix; float qx, qy; };
+
+__global__ __launch_bounds__(256) void k_edge_primary_setup(Scene S, uint64_t seed, int M,
+        PeSample *__restrict__ ps_out, Hit *__restrict__ hits, unsigned long long *ctr) {
+    int m = blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t n_cam = 0;
+    Work wk;
+    int n = S.pe_n[0];
+    uint64_t Q = S.pe_Q[0];
+    if (m < M) {
+        PeSample ps; ps.e = -1; ps.i = 0; ps.pix = -1; ps.qx = ps.qy = 0.0f;
+        Hit h0; h0.tri = -1; h0.t = 0.0f; h0.b1 = h0.b2 = h0.det = 0.0f;
+        Hit hs[2] = {h0, h0};
+        do {
+            if (n <= 0 || Q == 0) break;
+            u4 wd = philox(seed, (uint32_t)m, 0, 2, 0);
+            uint64_t target = __umul64hi(((uint64_t)wd.y << 32) | wd.x, Q);
+            int i = cdf_pick(S.pe_prefix, n, target);
+            int e = S.pe_edge[i];
+            const int *ed = S.edges + 4 * e;
+            float tu = u01(wd.z);
+            v3 a = vpos(S, ed[0]), b = vpos(S, ed[1]);
+            float ax, ay, bx, by;
+            if (!project(S, a, ax, ay) || !project(S, b, bx, by)) break;
+            float qx = ax + tu * (bx - ax), qy = ay + tu * (by - ay);
+            float fpx = floorf(qx), fpy = floorf(qy);
+            if (!(fpx >= 0.0f && fpx < (float)S.W && fpy >= 0.0f && fpy < (float)S.H)) break;
+            v3 cam = mk(S.cam_x, S.cam_y, S.cam_z);
+            v3 mv = cross(a - cam, b - cam);
+            float gx = mv.x, gy = -mv.y;
+            float gl = sqrtf(gx * gx + gy * gy);
+            if (gl == 0.0f) break;
+            float nx = gx / gl, ny = gy / gl;
+            for (int side = 0; side < 2; ++side) {
+                float sg = side == 0 ? 1.0f : -1.0f;
+                float px = qx + sg * (kEdgeOffPx * nx), py = qy + sg * (kEdgeOffPx * ny);
+                hs[side] = trace_closest(S, cam, camera_dir(S, px, py), wk);
+                ++n_cam;
+            }
+            ps.e = e; ps.i = i; ps.pix = (int)fpy * S.W + (int)fpx; ps.qx = qx; ps.qy = qy;
+        } while (0);
+        ps_out[m] = ps;
+        hits[2 * m] = hs[0];
+        hits[2 * m + 1] = hs[1];
+    }
+    flush_count(ctr, 0, n_cam);
+    flush_work(ctr, wk);
+}
+
+// screen point of side 'side' of a primary sample (same fp32 ops as setup)
+__device__ __forceinline__ void pe_side_point(const Scene &S, const PeSample &ps, int side, float &px, float &py) {
+    const int *ed = S.edges + 4 * ps.e;
+    v3 cam = mk(S.cam_x, S.cam_y, S.cam_z);
+    v3 mv = cross(vpos(S, ed[0]) - cam, vpos(S, ed[1]) - cam);
+    float gx = mv.x, gy = -mv.y;
+    float gl = sqrtf(gx * gx + gy * gy);
+    float nx = gx / gl, ny = gy / gl;
+    float sg = side == 0 ? 1.0f : -1.0f;
+    px = ps.qx + sg * (kEdgeOffPx * nx);
+    py = ps.qy + sg * (kEdgeOffPx * ny);
+}
+
+__global__ __launch_bounds__(256) void k_edge_primary_shade(Scene S, uint64_t seed, int M,
+        const PeSample *__restrict__ ps_in, const Hit *__restrict__ hits, double *__restrict__ fbuf,
+        unsigned long long *ctr) {
     extern __shared__ float dyn[];
     __shared__ Light Ls[kMaxLights];
     float *spec_lds = dyn;
     stage_tables(S, Ls, spec_lds);
     __syncthreads();
-    int m = blockIdx.x * blockDim.x + threadIdx.x;
-    uint32_t n_pe = 0, n_sh = 0;
+    long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t n_sh = 0;
     Work wk;
-    int n = S.pe_n[0];
-    uint64_t Q = S.pe_Q[0];
-    if (m < M && n > 0 && Q > 0) do {
-        u4 wd = philox(seed, (uint32_t)m, 0, 2, 0);
-        uint64_t target = __umul64hi(((uint64_t)wd.y << 32) | wd.x, Q);
-        int i = cdf_pick(S.pe_prefix, n, target);
-        int e = S.pe_edge[i];
-        const int *ed = S.edges + 4 * e;
-        float tu = u01(wd.z);
-        v3 a = vpos(S, ed[0]), b = vpos(S, ed[1]);
-        float ax, ay, bx, by;
-        if (!project(S, a, ax, ay) || !project(S, b, bx, by)) break;
-        float qx = ax + tu * (bx - ax), qy = ay + tu * (by - ay);
-        float fpx = floorf(qx), fpy = floorf(qy);
-        if (!(fpx >= 0.0f && fpx < (float)S.W && fpy >= 0.0f && fpy < (float)S.H)) break;
-        v3 cam = mk(S.cam_x, S.cam_y, S.cam_z);
-        v3 mv = cross(a - cam, b - cam);
-        float gx = mv.x, gy = -mv.y;
-        float gl = sqrtf(gx * gx + gy * gy);
-        if (gl == 0.0f) break;
-        float nx = gx / gl, ny = gy / gl;
-        double f[2][3];
-        for (int side = 0; side < 2; ++side) {
-            float sg = side == 0 ? 1.0f : -1.0f;
-            float px = qx + sg * (kEdgeOffPx * nx), py = qy + sg * (kEdgeOffPx * ny);
+    if (g < (long long)M * 2 * S.nl) {
+        int j = (int)(g % S.nl);
+        int ms = (int)(g / S.nl);           // 2 m + side
+        int m = ms >> 1, side = ms & 1;
+        PeSample ps = ps_in[m];
+        Hit h = hits[ms];
+        if (ps.e >= 0 && h.tri >= 0) {
+            float px, py;
+            pe_side_point(S, ps, side, px, py);
+            v3 o = mk(S.cam_x, S.cam_y, S.cam_z), d = camera_dir(S, px, py);
+            SurfDec sd;
+            surf_decide(S, o, h, sd);
             LightRng rng(seed, (uint32_t)m, 2, 4);
-            radiance<double>(S, Ls, spec_lds, camera_dir(S, px, py), rng, f[side], n_sh, wk);
+            float u, v;
+            rng.get(j, u, v);
+            const Light &L = Ls[j];
+            v3 y = light_point(L, u, v);
+            if (above(sd, y)) {
+                ++n_sh;
+                if (!trace_any(S, sd.p, y - sd.p, h.tri, wk)) {
+                    Surf<ER> sv;
+                    surf_value<ER>(S, spec_lds, o, d, h, sd, sv);
+                    ER c[3];
+                    shade_light<ER>(sv, L, cvt<ER>(y), light_branch(sd, L.n, y), nullptr, c, nullptr);
+                    ++wk.shade;
+                    for (int k = 0; k < 3; ++k) gadd(&fbuf[3 * ms + k], (double)c[k]);
+                }
+            }
         }
-        n_pe = 2 + n_sh;
-        int pix = (int)fpy * S.W + (int)fpx;
-        const float *Gp = dLdI + 3 * pix;
-        double df = Gp[0] * (f[0][0] - f[1][0]) + Gp[1] * (f[0][1] - f[1][1]) + Gp[2] * (f[0][2] - f[1][2]);
-        if (df == 0.0) break;
-        // ---- value path (fp64)
-        double ps = S.ps;
-        d3 C = cvt<double>(cam), A = cvt<double>(a), B = cvt<double>(b);
-        d3 dq = dk(((double)qx - 0.5 * S.W) * ps, (0.5 * S.H - (double)qy) * ps, -1.0);
-        d3 ra = A - C, rb = B - C;
-        d3 md = cross(ra, rb);
-        double gradn = ps * sqrt(md.x * md.x + md.y * md.y);
-        double pax = 0.5 * S.W + (ra.x / -ra.z) / ps, pay = 0.5 * S.H - (ra.y / -ra.z) / ps;
-        double pbx = 0.5 * S.W + (rb.x / -rb.z) / ps, pby = 0.5 * S.H - (rb.y / -rb.z) / ps;
-        double ln = sqrt((pbx - pax) * (pbx - pax) + (pby - pay) * (pby - pay));
-        uint64_t qe = (i + 1 < n ? S.pe_prefix[i + 1] : Q) - S.pe_prefix[i];
-        double pe = (double)qe / (double)Q;
-        double W = df * ln / (pe * gradn * (double)M);
+    }
+    flush_count(ctr, 2, n_sh);
+    flush_work(ctr, wk);
+}
+
+__global__ __launch_bounds__(256) void k_edge_primary_scatter(Scene S, int M, const float *__restrict__ dLdI,
+        const PeSample *__restrict__ ps_in, const double *__restrict__ fbuf, double *d_pos) {
+    int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m < M) do {
+        PeSample ps = ps_in[m];
+        if (ps.e < 0) break;
+        const float *Gp = dLdI + 3 * ps.pix;
+        const double *f = fbuf + 6 * m;
+        ER df = (ER)Gp[0] * (ER)(f[0] - f[3]) + (ER)Gp[1] * (ER)(f[1] - f[4]) + (ER)Gp[2] * (ER)(f[2] - f[5]);
+        if (df == (ER)0) break;
+        const int *ed = S.edges + 4 * ps.e;
+        ER pxs = S.ps;
+        e3 C = vk<ER>(S.cam_x, S.cam_y, S.cam_z), A = cvt<ER>(vpos(S, ed[0])), B = cvt<ER>(vpos(S, ed[1]));
+        e3 dq = vk<ER>(((ER)ps.qx - (ER)0.5 * (ER)S.W) * pxs, ((ER)0.5 * (ER)S.H - (ER)ps.qy) * pxs, (ER)-1);
+        e3 ra = A - C, rb = B - C;
+        e3 md = cross(ra, rb);
+        ER gradn = pxs * sqrt(md.x * md.x + md.y * md.y);
+        ER hW = (ER)0.5 * (ER)S.W, hH = (ER)0.5 * (ER)S.H;
+        ER pax = hW + (ra.x / -ra.z) / pxs, pay = hH - (ra.y / -ra.z) / pxs;
+        ER pbx = hW + (rb.x / -rb.z) / pxs, pby = hH - (rb.y / -rb.z) / pxs;
+        ER ln = sqrt((pbx - pax) * (pbx - pax) + (pby - pay) * (pby - pay));
+        int n = S.pe_n[0];
+        uint64_t Q = S.pe_Q[0];
+        uint64_t qe = (ps.i + 1 < n ? S.pe_prefix[ps.i + 1] : Q) - S.pe_prefix[ps.i];
+        ER pe = (ER)((double)qe / (double)Q);
+        ER W = df * ln / (pe * gradn * (ER)M);
         atomic_v(d_pos, S.V, ed[0], cross(rb, dq) * W);
         atomic_v(d_pos, S.V, ed[1], cross(dq, ra) * W);
     } while (0);
-    flush_count(ctr, 2, n_pe);
-    flush_work(ctr, wk);
 }
 
 // ------------------------------------------------------- reductions ----
@@ -849,12 +916,18 @@ __global__ __launch_bounds__(BS) void k_loss_partial(size_t n, const float *__re
     }
     if (threadIdx.x == 0) partial[blockIdx.x] = sh[0];
 }
-__global__ void k_loss_final(int nb, const double *__restrict__ partial, float *loss) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        double s = 0.0;
-        for (int b = 0; b < nb; ++b) s += partial[b];
-        *loss = (float)s;
+template <int BS>
+__global__ __launch_bounds__(BS) void k_loss_final(int nb, const double *__restrict__ partial, float *loss) {
+    __shared__ double sh[BS];
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < nb; b += BS) acc += partial[b];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int off = BS / 2; off > 0; off >>= 1) {
+        if (threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+        __syncthreads();
     }
+    if (threadIdx.x == 0) *loss = (float)sh[0];
 }
 
 // ====================================================================== //
@@ -883,8 +956,9 @@ struct fr_ctx {
     float *ew = nullptr; unsigned int *ewmax = nullptr;
     int *tbl_edge = nullptr, *tbl_n = nullptr; uint64_t *tbl_prefix = nullptr, *tbl_Q = nullptr;
     float *samples = nullptr; size_t samples_cap = 0;
+    uint32_t *vis = nullptr; size_t vis_cap = 0; bool vis_valid = false;
+    PeSample *pe_samples = nullptr; Hit *pe_hits = nullptr; double *pe_f = nullptr;
     unsigned long long *ctr = nullptr;
-    int *queue = nullptr, *qcount = nullptr; size_t queue_cap = 0;
     // gradients scratch
     double *g_light = nullptr, *g_spec = nullptr, *g_pos = nullptr, *g_nrm = nullptr, *g_alb = nullptr;
     double *g_N = nullptr;
@@ -903,6 +977,8 @@ struct fr_ctx {
 };
 
 static const char *kNoCtx = "no context";
+// light-visibility masks are kept for the adjoint up to this size
+static constexpr size_t kVisBudgetBytes = (size_t)1 << 30;
 
 static int fail(fr_ctx *c, int code, const char *fmt, ...) {
     char buf[512];
@@ -1163,7 +1239,9 @@ int fr_create(const fr_model_desc *m, const fr_scene_desc *s, uint32_t flags, fr
         R(dalloc(c, &c->ew, (size_t)(1 + c->nl) * c->E)) || R(dalloc(c, &c->ewmax, (size_t)(1 + c->nl))) ||
         R(dalloc(c, &c->tbl_edge, (size_t)(1 + c->nl) * c->E)) || R(dalloc(c, &c->tbl_prefix, (size_t)(1 + c->nl) * c->E)) ||
         R(dalloc(c, &c->tbl_n, (size_t)(1 + c->nl))) || R(dalloc(c, &c->tbl_Q, (size_t)(1 + c->nl))) ||
-        R(dalloc(c, &c->ctr, 32)) || R(dalloc(c, &c->qcount, 1)) ||
+        R(dalloc(c, &c->ctr, 32)) ||
+        R(dalloc(c, &c->pe_samples, (size_t)c->W * c->H)) || R(dalloc(c, &c->pe_hits, 2 * (size_t)c->W * c->H)) ||
+        R(dalloc(c, &c->pe_f, 6 * (size_t)c->W * c->H)) ||
         R(dalloc(c, &c->g_light, 3 * (size_t)c->nl)) || R(dalloc(c, &c->g_spec, (size_t)c->res * c->res)) ||
         R(dalloc(c, &c->g_pos, V3)) || R(dalloc(c, &c->g_nrm, V3)) || R(dalloc(c, &c->g_alb, V3)) ||
         R(dalloc(c, &c->g_N, V3)) || R(dalloc(c, &c->g_vert, V3)) || R(dalloc(c, &c->g_m, V3))) {
@@ -1250,13 +1328,17 @@ int fr_render(fr_ctx *c, const fr_params *p, uint64_t seed, int32_t spp, float *
         HIPCK(c, hipMalloc((void **)&c->samples, (size_t)N * 3 * sizeof(float)));
         c->samples_cap = (size_t)N * 3;
     }
-    if ((size_t)N > c->queue_cap) {
-        if (c->queue) (void)hipFree(c->queue);
-        c->queue = nullptr;
-        c->queue_cap = 0;
-        HIPCK(c, hipMalloc((void **)&c->queue, (size_t)N * sizeof(int)));
-        c->queue_cap = (size_t)N;
+    // visibility masks: 4 bytes per camera sample, kept when they fit
+    bool keep_vis = c->nl <= 32 && (size_t)N * sizeof(uint32_t) <= kVisBudgetBytes;
+    if (keep_vis && (size_t)N > c->vis_cap) {
+        if (c->vis) (void)hipFree(c->vis);
+        c->vis = nullptr;
+        c->vis_cap = 0;
+        HIPCK(c, hipMalloc((void **)&c->vis, (size_t)N * sizeof(uint32_t)));
+        c->vis_cap = (size_t)N;
     }
+    c->vis_valid = keep_vis;
+
     c->have_render = false;
     c->last = *p;
     c->last_seed = seed;
@@ -1277,7 +1359,8 @@ int fr_render(fr_ctx *c, const fr_params *p, uint64_t seed, int32_t spp, float *
     hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, c->stream, c->ctr, 32);
     size_t lds = (size_t)c->res * c->res * sizeof(float);
     ev_record(c, 9);
-    hipLaunchKernelGGL(k_render_fwd, dim3(nblk(N, 256)), dim3(256), lds, c->stream, S, seed, spp, N, c->samples, c->ctr);
+    hipLaunchKernelGGL(k_render_fwd, dim3(nblk(N, 256)), dim3(256), lds, c->stream, S, seed, spp, N, c->samples,
+                       c->vis_valid ? c->vis : nullptr, c->ctr);
     ev_record(c, 10);
     hipLaunchKernelGGL(k_pixel_mean, dim3(nblk((size_t)c->W * c->H, 256)), dim3(256), 0, c->stream,
                        c->W * c->H, spp, c->samples, out);
@@ -1304,23 +1387,24 @@ int fr_backward(fr_ctx *c, const float *dLdI, const fr_grads *g) {
     GradBufs G{c->g_light, c->g_spec, c->g_pos, c->g_nrm, c->g_alb};
     size_t lds = ((size_t)2 * c->res * c->res + 3 * c->nl) * sizeof(float);
     hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, c->stream, c->ctr + 8, 24);
-    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, c->stream, (unsigned int *)c->qcount, 1);
     ev_record(c, 7);
     if (c->terms & FR_TERM_INTERIOR)
         hipLaunchKernelGGL(k_render_adj, dim3(nblk(N, 256)), dim3(256), lds, c->stream, S, c->last_seed, c->last_spp, N,
-                           dLdI, G, c->queue, c->qcount, c->ctr + 8);
+                           dLdI, G, c->vis_valid ? c->vis : nullptr, c->ctr + 8);
     ev_record(c, 8);
     size_t lds1 = (size_t)c->res * c->res * sizeof(float);
-    if (c->terms & FR_TERM_INTERIOR)
-        hipLaunchKernelGGL(k_render_adj_f64, dim3(512), dim3(256), lds1, c->stream, S, c->last_seed, c->last_spp,
-                           dLdI, G, c->queue, c->qcount, c->ctr + 8);
     if (c->terms & FR_TERM_SECONDARY)
         hipLaunchKernelGGL(k_edge_secondary, dim3(nblk(N, 256)), dim3(256), lds1, c->stream, S, c->last_seed, c->last_spp, N,
                            dLdI, c->g_pos, c->ctr + 24);
     if (c->terms & FR_TERM_PRIMARY) {
         int M = c->W * c->H;
-        hipLaunchKernelGGL(k_edge_primary, dim3(nblk(M, 256)), dim3(256), lds1, c->stream,
-                           S, c->last_seed, M, dLdI, c->g_pos, c->ctr + 16);
+        hipLaunchKernelGGL(k_zero_d, dim3(nblk(6 * (size_t)M, 256)), dim3(256), 0, c->stream, c->pe_f, 6 * (size_t)M);
+        hipLaunchKernelGGL(k_edge_primary_setup, dim3(nblk(M, 256)), dim3(256), 0, c->stream,
+                           S, c->last_seed, M, c->pe_samples, c->pe_hits, c->ctr + 16);
+        hipLaunchKernelGGL(k_edge_primary_shade, dim3(nblk((size_t)M * 2 * c->nl, 256)), dim3(256), lds1, c->stream,
+                           S, c->last_seed, M, c->pe_samples, c->pe_hits, c->pe_f, c->ctr + 16);
+        hipLaunchKernelGGL(k_edge_primary_scatter, dim3(nblk(M, 256)), dim3(256), 0, c->stream,
+                           S, M, dLdI, c->pe_samples, c->pe_f, c->g_pos);
     }
     hipLaunchKernelGGL(k_normal_adj, dim3(nblk(c->V, 256)), dim3(256), 0, c->stream, c->V, c->nrm, c->nlen, c->g_nrm, c->g_N);
     hipLaunchKernelGGL(k_chain_gather, dim3(nblk(c->V, 256)), dim3(256), 0, c->stream, c->V, c->faces, c->vf_off, c->vf_idx,
@@ -1350,7 +1434,7 @@ int fr_loss_l2(fr_ctx *c, const float *img, const float *tgt, float *dL, float *
     size_t n = (size_t)c->W * c->H * 3;
     int nb = (int)nblk(n, 256);
     hipLaunchKernelGGL(k_loss_partial<256>, dim3(nb), dim3(256), 0, c->stream, n, img, tgt, dL, c->loss_partial);
-    if (loss) hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(64), 0, c->stream, nb, c->loss_partial, loss);
+    if (loss) hipLaunchKernelGGL(k_loss_final<256>, dim3(1), dim3(256), 0, c->stream, nb, c->loss_partial, loss);
     HIPCK(c, hipGetLastError());
     return FR_OK;
 }
@@ -1361,9 +1445,6 @@ int fr_stats(fr_ctx *c, fr_stats_t *out) {
     unsigned long long h[32];
     HIPCK(c, hipMemcpy(h, c->ctr, sizeof h, hipMemcpyDeviceToHost));
     memset(out, 0, sizeof *out);
-    int qn = 0;
-    HIPCK(c, hipMemcpy(&qn, c->qcount, sizeof qn, hipMemcpyDeviceToHost));
-    out->grazing_samples = (uint64_t)qn;
     for (int k = 0; k < 4; ++k) {
         const unsigned long long *q = h + 8 * k;
         out->rays_camera += q[0]; out->rays_shadow += q[1];
@@ -1401,7 +1482,7 @@ void fr_destroy(fr_ctx *c) {
                     c->lgeom, c->sorted_tri, c->leaf_node, c->parent, c->right, c->escape, c->arrive, c->nodes, c->tris,
                     c->vmodel, c->pos, c->nrm, c->nlen, c->alb, c->ew, c->ewmax, c->tbl_edge, c->tbl_prefix, c->tbl_n,
                     c->tbl_Q, c->samples, c->ctr, c->g_light, c->g_spec, c->g_pos, c->g_nrm, c->g_alb, c->g_N,
-                    c->g_vert, c->g_m, c->partial, c->loss_partial, c->queue, c->qcount};
+                    c->g_vert, c->g_m, c->partial, c->loss_partial, c->vis, c->pe_samples, c->pe_hits, c->pe_f};
     for (void *p : ptrs) if (p) (void)hipFree(p);
     for (auto &e : c->ev) if (e) (void)hipEventDestroy(e);
     delete c;

@@ -6,9 +6,9 @@
 //    edge a sample picks) is taken in fp32 with the operation order written
 //    below and no contraction (the library is built with -ffp-contract=off);
 //  * values: shading and its adjoint, templated on the scalar type.  The
-//    bulk runs in fp32; samples whose shading is ill-conditioned (grazing
-//    views) and the edge samples, which sit on silhouettes by construction,
-//    run in fp64, which MI355X issues at the fp32 (non-packed) rate.
+//    bulk runs in fp32; the edge samples, which sit on silhouettes by
+//    construction and shade at grazing angles, run in fp64, which MI355X
+//    issues at the fp32 (non-packed) rate.
 // The estimator is the Monte-Carlo lighting estimator F of the paper's
 // Optimization paragraph with the Cook-Torrance reflectance of its Face
 // Modeling paragraph; see include/facert.h.
@@ -29,10 +29,6 @@ constexpr double kBeckmannM = 0.35;
 constexpr double kPi = 3.14159265358979323846;
 constexpr float kSlabGrow = 1.0000004f;  // 1 + 2 gamma_3 (Ize 2013)
 constexpr int kMaxLights = 64;
-// A camera sample's adjoint runs in fp64 when its view is this close to
-// grazing (|cos| to the shading or geometric normal below it): the specular
-// term divides by cos_o, so fp32 error grows as 1/cos_o^2 in its gradient.
-constexpr float kGrazingCos = 0.1f;
 
 template <class T> struct vec3 { T x, y, z; };
 using v3 = vec3<float>;

@@ -58,7 +58,6 @@ class fr_stats_t(C.Structure):
                 ("traversal_overflow", C.c_uint64), ("box_tests", C.c_uint64), ("tri_tests", C.c_uint64),
                 ("kernel_rays", C.c_uint64 * 4), ("kernel_box_tests", C.c_uint64 * 4),
                 ("kernel_tri_tests", C.c_uint64 * 4), ("kernel_shades", C.c_uint64 * 4),
-                ("grazing_samples", C.c_uint64),
                 ("ms_blend", C.c_float), ("ms_bvh", C.c_float),
                 ("ms_edges", C.c_float), ("ms_render", C.c_float), ("ms_backward", C.c_float),
                 ("ms_kernel_fwd", C.c_float), ("ms_kernel_adj", C.c_float)]
