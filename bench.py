@@ -25,14 +25,34 @@ if ROOT not in sys.path:
 
 METRIC = "fwd+bwd ms/iter & Mrays/s at 256x256; denoised-2spp vs plain-256spp at equal PSNR"
 
-# Algorithmic fp32 operations per unit of work (VALU lane operations counted
-# from the kernels' own source: adds, multiplies, min/max, compares,
-# divides and square roots each count 1).
-OPS_BOX = 26          # one slab test of a BVH node
-OPS_TRI = 40          # one ray/triangle test up to the first barycentric reject
-OPS_SHADE_ADJ = 420   # one light sample's radiance and reverse-mode adjoint
-OPS_SHADE_FWD = 110   # one light sample's radiance
-PEAK_VALU = 39.3      # T lane-ops/s: 256 CU x 4 SIMD x 16 lanes x 2.4 GHz
+# Algorithmic VALU work per unit, counted as gfx950 VALU instructions (one
+# lane operation each) in the compiled code of each piece (probe kernels,
+# address arithmetic excluded): a slab test of one BVH node, one full
+# ray/triangle test with its hit-box check, one light sample's shading, and
+# one light sample's shading plus reverse-mode adjoint.
+OPS_BOX = 26
+OPS_TRI = 95
+OPS_SHADE_FWD = 215
+OPS_SHADE_ADJ = 590
+# fp32 VALU issue ceiling: 256 CU x 4 SIMD x 16 lanes x 2.4 GHz, one
+# non-packed, non-fused operation per lane per clock
+PEAK_VALU = 39.3      # T lane-ops/s
+
+
+def profiled_traffic(kernel: str, workload: str):
+    """HBM bytes per launch from the committed rocprofv3 PMC summary, or None
+    when the kernel sources changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.md")
+    if not os.path.exists(path):
+        return None
+    src = b"".join(open(os.path.join(ROOT, "paper_1910_05200_amd", "csrc", f), "rb").read()
+                   for f in ("facert.hip", "fr_device.hpp"))
+    fields = dict(l.split(": ", 1) for l in open(path).read().splitlines() if ": " in l and not l.startswith("|"))
+    if fields.get("kernel_source_sha256", "").strip() != hashlib.sha256(src).hexdigest():
+        return None
+    v = fields.get(f"{kernel}_traffic_bytes_per_launch")
+    return float(v) if v else None
 
 
 def parse():
@@ -132,8 +152,11 @@ def main():
         fwd_ops.append(st["kernel_box_tests"][0] * OPS_BOX + st["kernel_tri_tests"][0] * OPS_TRI
                        + st["kernel_shades"][0] * OPS_SHADE_FWD)
     rays_per_iter = float(np.mean(rays))
+    fwd_t = float(np.mean(fwd_ms)) * 1e-3
     adj_t = float(np.mean(adj_ms)) * 1e-3
-    achieved = float(np.mean(adj_ops)) / adj_t / 1e12
+    kernels = {"k_render_fwd": (float(np.mean(fwd_ops)), fwd_t), "k_render_adj": (float(np.mean(adj_ops)), adj_t)}
+    dom = max(kernels, key=lambda k: kernels[k][1])
+    achieved = kernels[dom][0] / kernels[dom][1] / 1e12
     out = {
         "metric": METRIC,
         "value": rays_per_iter / (ms * 1e-3) / 1e6,
@@ -151,8 +174,10 @@ def main():
                                          zip(per_step[-1]["kernel_box_tests"], per_step[-1]["kernel_rays"])],
                    "tri_tests_per_ray": [round(b / max(1, n), 2) for b, n in
                                          zip(per_step[-1]["kernel_tri_tests"], per_step[-1]["kernel_rays"])]},
-        "roofline": {"bound": "alu", "kernel": "k_render_adj", "achieved": achieved, "peak": PEAK_VALU,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_VALU, "traffic": None},
+        "roofline": {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": PEAK_VALU,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_VALU,
+                     "traffic": profiled_traffic(dom, args.workload),
+                     "ops_per_launch": kernels[dom][0], "ms_per_launch": kernels[dom][1] * 1e3},
     }
     if not args.no_cpu_baseline:
         threads = args.cpu_threads or min(16, os.cpu_count() or 1)
