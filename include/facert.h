@@ -110,12 +110,13 @@ typedef struct {
     uint64_t rays_camera, rays_shadow, rays_edge_primary, rays_edge_secondary;
     uint64_t traversal_overflow;     /* must be 0                              */
     uint64_t box_tests, tri_tests;   /* BVH node and triangle tests performed  */
-    /* per kernel: [0] forward render, [1] interior adjoint,
-       [2] camera-silhouette edges, [3] shadow-boundary edges */
-    uint64_t kernel_rays[4], kernel_box_tests[4], kernel_tri_tests[4], kernel_shades[4];
+    /* per kernel: [0] camera rays, [1] shadow rays, [2] shading (forward),
+       [3] interior adjoint (with any recomputation of hits and visibility),
+       [4] camera-silhouette edges, [5] shadow-boundary edges */
+    uint64_t kernel_rays[6], kernel_box_tests[6], kernel_tri_tests[6], kernel_shades[6];
     /* milliseconds of the last calls (when FR_TIMING was given)              */
     float ms_blend, ms_bvh, ms_edges, ms_render, ms_backward;
-    float ms_kernel_fwd, ms_kernel_adj;  /* the forward and adjoint kernels alone */
+    float ms_kernel[6];              /* the kernels above alone (last chunk)   */
 } fr_stats_t;
 
 #define FR_TIMING 1u                 /* fr_create flag: time phases with events */

@@ -282,38 +282,8 @@ __device__ __forceinline__ v3 camera_sample(const Scene &S, uint64_t seed, uint3
     return camera_dir(S, (float)px + u01(w0.x), (float)py + u01(w0.y));
 }
 
-// Full radiance through screen point (qx, qy) with lights drawn from rng;
-// decisions in fp32, values in T.
-template <class T>
-__device__ inline void radiance(const Scene &S, const Light *Ls, const float *spec_lds, v3 d,
-                                LightRng &rng, T out[3], uint32_t &n_shadow, Work &wk, uint32_t *vis = nullptr) {
-    out[0] = out[1] = out[2] = 0;
-    if (vis) *vis = 0u;
-    v3 o = mk(S.cam_x, S.cam_y, S.cam_z);
-    Hit h = trace_closest(S, o, d, wk);
-    if (h.tri < 0) return;
-    SurfDec sd;
-    surf_decide(S, o, h, sd);
-    Surf<T> sv;
-    surf_value<T>(S, spec_lds, o, d, h, sd, sv);
-    for (int j = 0; j < S.nl; ++j) {
-        float u, v;
-        rng.get(j, u, v);
-        const Light &L = Ls[j];
-        v3 y = light_point(L, u, v);
-        if (!above(sd, y)) continue;
-        ++n_shadow;
-        if (trace_any(S, sd.p, y - sd.p, h.tri, wk)) continue;
-        if (vis) *vis |= 1u << j;
-        T c[3];
-        shade_light<T>(sv, L, cvt<T>(y), light_branch(sd, L.n, y), nullptr, c, nullptr);
-        ++wk.shade;
-        out[0] += c[0]; out[1] += c[1]; out[2] += c[2];
-    }
-}
-
-// counters (8 per kernel): 0 camera, 1 shadow, 2 primary-edge, 3 secondary-edge
-// rays, 4 box tests, 5 triangle tests, 6 shaded light samples
+// counters, 8 per kernel: 0 camera rays, 1 shadow rays, 2 primary-edge rays,
+// 3 secondary-edge rays, 4 box tests, 5 triangle tests, 6 shaded light samples
 __device__ inline void flush_count(unsigned long long *ctr, int slot, uint32_t v) {
     unsigned long long s = v;
     for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
@@ -325,31 +295,114 @@ __device__ inline void flush_work(unsigned long long *ctr, const Work &w) {
     flush_count(ctr, 6, w.shade);
 }
 
-// One lane per camera sample.  With at most 32 lights each sample's light
-// visibility (horizon and shadow ray) is kept as a bit mask for the adjoint.
-__global__ __launch_bounds__(256) void k_render_fwd(Scene S, uint64_t seed, int spp, long long N,
-        float *__restrict__ samples, uint32_t *__restrict__ vis_out, unsigned long long *ctr) {
+// ------------------------------------------------ forward wavefront -----
+// The forward pass runs as three kernels over a chunk of camera samples:
+//   k_fwd_camera  one lane per sample: jittered pinhole ray, closest hit ->
+//                 16-byte hit record;
+//   k_fwd_shadow  one lane per (sample, light), a 2D grid with the light on
+//                 the y axis so that a wave traces 64 neighbouring samples
+//                 toward the same light: horizon test and shadow ray, one
+//                 bit per light in the sample's visibility mask;
+//   k_fwd_shade   one lane per sample: shading of the visible lights (no
+//                 traversal).
+// The adjoint and the shadow-boundary kernels read the same records; when a
+// render's samples exceed one chunk the backward recomputes them per chunk.
+struct HitRec { int tri; float b1, b2, det; };
+
+__device__ __forceinline__ Hit hit_of(HitRec r) {
+    Hit h; h.tri = r.tri; h.t = 0.0f; h.b1 = r.b1; h.b2 = r.b2; h.det = r.det;
+    return h;
+}
+
+__global__ __launch_bounds__(256) void k_fwd_camera(Scene S, uint64_t seed, int spp, long long s0, long long n,
+        HitRec *__restrict__ hits, unsigned long long *__restrict__ vis, unsigned long long *ctr) {
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t n_cam = 0;
+    Work wk;
+    if (i < n) {
+        int pix;
+        v3 o = mk(S.cam_x, S.cam_y, S.cam_z);
+        v3 d = camera_sample(S, seed, (uint32_t)(s0 + i), spp, pix);
+        Hit h = trace_closest(S, o, d, wk);
+        HitRec r; r.tri = h.tri; r.b1 = h.b1; r.b2 = h.b2; r.det = h.det;
+        hits[i] = r;
+        vis[i] = 0ull;
+        n_cam = 1;
+    }
+    flush_count(ctr, 0, n_cam);
+    flush_work(ctr, wk);
+}
+
+__global__ __launch_bounds__(256) void k_fwd_shadow(Scene S, uint64_t seed, long long s0, long long n,
+        const HitRec *__restrict__ hits, unsigned long long *__restrict__ vis, unsigned long long *ctr) {
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    int j = blockIdx.y;
+    uint32_t n_sh = 0;
+    Work wk;
+    if (i < n) {
+        HitRec rec = hits[i];
+        if (rec.tri >= 0) {
+            Hit h = hit_of(rec);
+            v3 o = mk(S.cam_x, S.cam_y, S.cam_z);
+            SurfDec sd;
+            surf_decide(S, o, h, sd);
+            const float *g = S.lgeom + 12 * j;
+            Light L;
+            L.c = mk(g[0], g[1], g[2]); L.e1 = mk(g[3], g[4], g[5]); L.e2 = mk(g[6], g[7], g[8]);
+            LightRng rng(seed, (uint32_t)(s0 + i), 0, 2);
+            float u, v;
+            rng.get(j, u, v);
+            v3 y = light_point(L, u, v);
+            if (above(sd, y)) {
+                ++n_sh;
+                if (!trace_any(S, sd.p, y - sd.p, h.tri, wk)) atomicOr(&vis[i], 1ull << j);
+            }
+        }
+    }
+    flush_count(ctr, 1, n_sh);
+    flush_work(ctr, wk);
+}
+
+__global__ __launch_bounds__(256) void k_fwd_shade(Scene S, uint64_t seed, int spp, long long s0, long long n,
+        const HitRec *__restrict__ hits, const unsigned long long *__restrict__ vis,
+        float *__restrict__ samples, unsigned long long *ctr) {
     extern __shared__ float dyn[];
     __shared__ Light Ls[kMaxLights];
     float *spec_lds = dyn;
     stage_tables(S, Ls, spec_lds);
     __syncthreads();
-    long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    uint32_t n_cam = 0, n_sh = 0;
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     Work wk;
-    if (s < N) {
-        int pix;
-        v3 d = camera_sample(S, seed, (uint32_t)s, spp, pix);
-        LightRng rng(seed, (uint32_t)s, 0, 2);
-        float c[3];
-        uint32_t vis;
-        radiance<float>(S, Ls, spec_lds, d, rng, c, n_sh, wk, &vis);
-        n_cam = 1;
-        samples[3 * s] = c[0]; samples[3 * s + 1] = c[1]; samples[3 * s + 2] = c[2];
-        if (vis_out) vis_out[s] = vis;
+    if (i < n) {
+        HitRec rec = hits[i];
+        float c[3] = {0.0f, 0.0f, 0.0f};
+        if (rec.tri >= 0) {
+            Hit h = hit_of(rec);
+            uint32_t s = (uint32_t)(s0 + i);
+            int pix;
+            v3 o = mk(S.cam_x, S.cam_y, S.cam_z);
+            v3 d = camera_sample(S, seed, s, spp, pix);
+            unsigned long long m = vis[i];
+            SurfDec sd;
+            surf_decide(S, o, h, sd);
+            Surf<float> sv;
+            surf_value<float>(S, spec_lds, o, d, h, sd, sv);
+            LightRng rng(seed, s, 0, 2);
+            while (m) {
+                int j = __ffsll((long long)m) - 1;
+                m &= m - 1;
+                float u, v;
+                rng.get(j, u, v);
+                const Light &L = Ls[j];
+                v3 y = light_point(L, u, v);
+                float cj[3];
+                shade_light<float>(sv, L, cvt<float>(y), light_branch(sd, L.n, y), nullptr, cj, nullptr);
+                ++wk.shade;
+                c[0] += cj[0]; c[1] += cj[1]; c[2] += cj[2];
+            }
+        }
+        samples[3 * (s0 + i)] = c[0]; samples[3 * (s0 + i) + 1] = c[1]; samples[3 * (s0 + i) + 2] = c[2];
     }
-    flush_count(ctr, 0, n_cam);
-    flush_count(ctr, 1, n_sh);
     flush_work(ctr, wk);
 }
 
@@ -400,24 +453,19 @@ template <class T>
 __device__ inline void adjoint_sample(const Scene &S, const Light *Ls, uint64_t seed, uint32_t s,
                                       const float *wf, const Hit &h, const SurfDec &sd, const Surf<T> &sv,
                                       float *g_light_lds, float *g_spec_lds, const GradBufs &G,
-                                      const uint32_t *vis, uint32_t &n_sh, Work &wk) {
+                                      unsigned long long vis, Work &wk) {
     int V = S.V;
     T w[3] = {(T)wf[0], (T)wf[1], (T)wf[2]};
     vec3<T> gp = vk<T>(0, 0, 0), gns = vk<T>(0, 0, 0), gwo = vk<T>(0, 0, 0);
     T gA[3] = {0, 0, 0}, gks = 0;
     LightRng rng(seed, s, 0, 2);
-    for (int j = 0; j < S.nl; ++j) {
+    while (vis) {               // the forward pass's visibility decisions
+        int j = __ffsll((long long)vis) - 1;
+        vis &= vis - 1;
         float u, v;
         rng.get(j, u, v);
         const Light &L = Ls[j];
         v3 y = light_point(L, u, v);
-        if (vis) {
-            if (!((*vis >> j) & 1u)) continue;     // the forward pass's decision
-        } else {
-            if (!above(sd, y)) continue;
-            ++n_sh;
-            if (trace_any(S, sd.p, y - sd.p, h.tri, wk)) continue;
-        }
         T c[3];
         LAdj<T> a;
         shade_light<T>(sv, L, cvt<T>(y), light_branch(sd, L.n, y), w, c, &a);
@@ -456,12 +504,11 @@ __device__ inline void adjoint_sample(const Scene &S, const Light *Ls, uint64_t 
     chain_hit<T>(V, sv, gp, gb[0], gb[1], gb[2], G.d_pos);
 }
 
-// Interior adjoint, fp32: one lane per camera sample.  The camera hit is
-// recomputed (no hit records are stored); light visibility comes from the
-// forward pass's bit masks when it kept them, else the shadow rays are
-// traced again.
-__global__ __launch_bounds__(256) void k_render_adj(Scene S, uint64_t seed, int spp, long long N,
-        const float *__restrict__ dLdI, GradBufs G, const uint32_t *__restrict__ vis_in, unsigned long long *ctr) {
+// Interior adjoint, fp32: one lane per camera sample of the chunk, reading
+// the sample's hit record and visibility mask.
+__global__ __launch_bounds__(256) void k_render_adj(Scene S, uint64_t seed, int spp, long long s0, long long n,
+        const float *__restrict__ dLdI, GradBufs G, const HitRec *__restrict__ hits,
+        const unsigned long long *__restrict__ vis, unsigned long long *ctr) {
     extern __shared__ float dyn[];
     __shared__ Light Ls[kMaxLights];
     float *spec_lds = dyn;
@@ -471,31 +518,25 @@ __global__ __launch_bounds__(256) void k_render_adj(Scene S, uint64_t seed, int 
     for (int k = threadIdx.x; k < S.res * S.res; k += blockDim.x) g_spec[k] = 0.0f;
     for (int k = threadIdx.x; k < 3 * S.nl; k += blockDim.x) g_light[k] = 0.0f;
     __syncthreads();
-    long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    uint32_t n_cam = 0, n_sh = 0;
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     Work wk;
-    if (s < N) {
+    if (i < n) {
+        HitRec rec = hits[i];
+        uint32_t s = (uint32_t)(s0 + i);
         int pix;
         v3 o = mk(S.cam_x, S.cam_y, S.cam_z);
-        v3 d = camera_sample(S, seed, (uint32_t)s, spp, pix);
-        Hit h = trace_closest(S, o, d, wk);
-        n_cam = 1;
-        if (h.tri >= 0) {
-            float inv = 1.0f / (float)spp;
-            float w[3] = {dLdI[3 * pix] * inv, dLdI[3 * pix + 1] * inv, dLdI[3 * pix + 2] * inv};
+        v3 d = camera_sample(S, seed, s, spp, pix);
+        float inv = 1.0f / (float)spp;
+        float w[3] = {dLdI[3 * pix] * inv, dLdI[3 * pix + 1] * inv, dLdI[3 * pix + 2] * inv};
+        if (rec.tri >= 0 && (w[0] != 0.0f || w[1] != 0.0f || w[2] != 0.0f)) {
+            Hit h = hit_of(rec);
             SurfDec sd;
             surf_decide(S, o, h, sd);
             Surf<float> sv;
             surf_value<float>(S, spec_lds, o, d, h, sd, sv);
-            if (w[0] != 0.0f || w[1] != 0.0f || w[2] != 0.0f) {
-                uint32_t vis = vis_in ? vis_in[s] : 0u;
-                adjoint_sample<float>(S, Ls, seed, (uint32_t)s, w, h, sd, sv, g_light, g_spec, G,
-                                      vis_in ? &vis : nullptr, n_sh, wk);
-            }
+            adjoint_sample<float>(S, Ls, seed, s, w, h, sd, sv, g_light, g_spec, G, vis[i], wk);
         }
     }
-    flush_count(ctr, 0, n_cam);
-    flush_count(ctr, 1, n_sh);
     flush_work(ctr, wk);
     __syncthreads();
     for (int k = threadIdx.x; k < S.res * S.res; k += blockDim.x)
@@ -580,35 +621,34 @@ __device__ inline void secondary_edge(const Scene &S, const Light &L, int j, uin
     chain_hit<ER>(S.V, sd, dpsi_p * W, (ER)0, (ER)0, (ER)0, d_pos);
 }
 
-// One lane per camera sample: one shadow-boundary sample per light.
-__global__ __launch_bounds__(256) void k_edge_secondary(Scene S, uint64_t seed, int spp, long long N,
-        const float *__restrict__ dLdI, double *d_pos, unsigned long long *ctr) {
+// One lane per (camera sample, light) of the chunk: the light's
+// shadow-boundary sample at the sample's shading point.
+__global__ __launch_bounds__(256) void k_edge_secondary(Scene S, uint64_t seed, int spp, long long s0, long long n,
+        const float *__restrict__ dLdI, const HitRec *__restrict__ hits, double *d_pos, unsigned long long *ctr) {
     extern __shared__ float dyn[];
     __shared__ Light Ls[kMaxLights];
     float *spec_lds = dyn;
     stage_tables(S, Ls, spec_lds);
     __syncthreads();
-    long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    uint32_t n_cam = 0, n_sec = 0;
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    int j = blockIdx.y;
+    uint32_t n_sec = 0;
     Work wk;
-    if (s < N) {
+    if (i < n) {
+        HitRec rec = hits[i];
+        uint32_t s = (uint32_t)(s0 + i);
         int pix;
         v3 o = mk(S.cam_x, S.cam_y, S.cam_z);
-        v3 d = camera_sample(S, seed, (uint32_t)s, spp, pix);
+        v3 d = camera_sample(S, seed, s, spp, pix);
         float inv = 1.0f / (float)spp;
         float w[3] = {dLdI[3 * pix] * inv, dLdI[3 * pix + 1] * inv, dLdI[3 * pix + 2] * inv};
-        if (w[0] != 0.0f || w[1] != 0.0f || w[2] != 0.0f) {
-            Hit h = trace_closest(S, o, d, wk);
-            n_cam = 1;
-            if (h.tri >= 0) {
-                SurfDec sd;
-                surf_decide(S, o, h, sd);
-                for (int j = 0; j < S.nl; ++j)
-                    secondary_edge(S, Ls[j], j, seed, (uint32_t)s, spec_lds, o, d, h, sd, w, d_pos, n_sec, wk);
-            }
+        if (rec.tri >= 0 && (w[0] != 0.0f || w[1] != 0.0f || w[2] != 0.0f)) {
+            Hit h = hit_of(rec);
+            SurfDec sd;
+            surf_decide(S, o, h, sd);
+            secondary_edge(S, Ls[j], j, seed, s, spec_lds, o, d, h, sd, w, d_pos, n_sec, wk);
         }
     }
-    flush_count(ctr, 0, n_cam);
     flush_count(ctr, 3, n_sec);
     flush_work(ctr, wk);
 }
@@ -934,6 +974,13 @@ __global__ __launch_bounds__(BS) void k_loss_final(int nb, const double *__restr
 //                               host side                                //
 // ====================================================================== //
 
+// Camera samples per chunk of the forward wavefront (24 B of records each).
+// A render that fits in one chunk leaves its records for the adjoint; a
+// larger one (very high spp) has them recomputed chunk by chunk.
+static constexpr long long kChunk = 1ll << 24;
+enum { kKernCamera, kKernShadow, kKernShade, kKernAdj, kKernPrimary, kKernSecondary, kNumKern };
+static constexpr int kNumEvents = 8 + 2 * kNumKern;
+
 struct fr_ctx {
     std::string err;
     hipStream_t stream = nullptr;
@@ -956,7 +1003,8 @@ struct fr_ctx {
     float *ew = nullptr; unsigned int *ewmax = nullptr;
     int *tbl_edge = nullptr, *tbl_n = nullptr; uint64_t *tbl_prefix = nullptr, *tbl_Q = nullptr;
     float *samples = nullptr; size_t samples_cap = 0;
-    uint32_t *vis = nullptr; size_t vis_cap = 0; bool vis_valid = false;
+    HitRec *hits = nullptr; unsigned long long *vis = nullptr; size_t rec_cap = 0;
+    bool records_valid = false;   // hits/vis hold every sample of the last render
     PeSample *pe_samples = nullptr; Hit *pe_hits = nullptr; double *pe_f = nullptr;
     unsigned long long *ctr = nullptr;
     // gradients scratch
@@ -972,13 +1020,11 @@ struct fr_ctx {
     PoseArgs pose{};
     DRotArgs drot{};
     // timing
-    hipEvent_t ev[12] = {};
+    hipEvent_t ev[kNumEvents] = {};
     float ms[5] = {0, 0, 0, 0, 0};
 };
 
 static const char *kNoCtx = "no context";
-// light-visibility masks are kept for the adjoint up to this size
-static constexpr size_t kVisBudgetBytes = (size_t)1 << 30;
 
 static int fail(fr_ctx *c, int code, const char *fmt, ...) {
     char buf[512];
@@ -1080,45 +1126,86 @@ static bool build_edges(int V, int F, const int *faces, std::vector<int> &out) {
     return true;
 }
 
-static uint32_t spread10(uint32_t x) {
-    x &= 1023u;
-    x = (x | (x << 16)) & 0x030000FFu;
-    x = (x | (x << 8)) & 0x0300F00Fu;
-    x = (x | (x << 4)) & 0x030C30C3u;
-    x = (x | (x << 2)) & 0x09249249u;
-    return x;
+static float box_area(const float *b) {
+    float dx = b[3] - b[0], dy = b[4] - b[1], dz = b[5] - b[2];
+    return dx < 0 ? 0.0f : 2.0f * (dx * dy + dy * dz + dz * dx);
+}
+static void box_grow(float *b, const float *t) {
+    for (int a = 0; a < 3; ++a) { b[a] = std::min(b[a], t[a]); b[3 + a] = std::max(b[3 + a], t[3 + a]); }
 }
 
-// Karras-style split of the sorted Morton codes: highest differing bit, or
-// the middle of a run of equal codes; laid out depth-first with escapes.
-static int layout_rec(const std::vector<uint64_t> &keys, int lo, int hi, int idx, int par, HostTopo &T) {
+// Binned SAH split of perm[lo, hi), laid out depth first: a node at index
+// idx covering n triangles is followed by its left subtree; its right child
+// starts after the left subtree's 2 n_left - 1 nodes; its escape link points
+// past its own subtree.  Leaves hold one triangle (leaf order = perm order).
+static void sah_rec(const std::vector<float> &bb, const std::vector<float> &cen, std::vector<int> &perm,
+                    int lo, int hi, int idx, int par, HostTopo &T) {
+    const int kBins = 32;
     T.parent[idx] = par;
-    int count = hi - lo + 1;
+    int count = hi - lo;
     T.escape[idx] = idx + 2 * count - 1;
     if (count == 1) {
         T.leaf_node[lo] = idx;
         T.right[idx] = -1;
-        return idx;
+        return;
     }
-    uint64_t a = keys[lo], b = keys[hi];
-    int split;
-    if (a == b) {
-        split = (lo + hi) / 2;
-    } else {
-        int common = __builtin_clzll(a ^ b);
-        split = lo;
-        int step = hi - lo;
-        do {
-            step = (step + 1) >> 1;
-            int ns = split + step;
-            if (ns < hi && __builtin_clzll(a ^ keys[ns]) > common) split = ns;
-        } while (step > 1);
+    float cmin[3] = {INFINITY, INFINITY, INFINITY}, cmax[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int i = lo; i < hi; ++i)
+        for (int a = 0; a < 3; ++a) {
+            cmin[a] = std::min(cmin[a], cen[3 * perm[i] + a]);
+            cmax[a] = std::max(cmax[a], cen[3 * perm[i] + a]);
+        }
+    float best = INFINITY;
+    int best_axis = -1, best_bin = 0;
+    for (int a = 0; a < 3; ++a) {
+        float ext = cmax[a] - cmin[a];
+        if (!(ext > 0.0f)) continue;
+        float bbox[kBins][6];
+        int bcnt[kBins] = {0};
+        for (int k = 0; k < kBins; ++k) {
+            bbox[k][0] = bbox[k][1] = bbox[k][2] = INFINITY;
+            bbox[k][3] = bbox[k][4] = bbox[k][5] = -INFINITY;
+        }
+        for (int i = lo; i < hi; ++i) {
+            int f = perm[i];
+            int k = std::min(kBins - 1, (int)((cen[3 * f + a] - cmin[a]) / ext * kBins));
+            bcnt[k]++;
+            box_grow(bbox[k], &bb[6 * f]);
+        }
+        float rarea[kBins];
+        int rcnt[kBins];
+        float acc[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+        int n = 0;
+        for (int k = kBins - 1; k > 0; --k) {
+            box_grow(acc, bbox[k]);
+            n += bcnt[k];
+            rarea[k] = box_area(acc);
+            rcnt[k] = n;
+        }
+        float lacc[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+        int nl = 0;
+        for (int k = 0; k < kBins - 1; ++k) {
+            box_grow(lacc, bbox[k]);
+            nl += bcnt[k];
+            if (nl == 0 || rcnt[k + 1] == 0) continue;
+            float cost = box_area(lacc) * (float)nl + rarea[k + 1] * (float)rcnt[k + 1];
+            if (cost < best) { best = cost; best_axis = a; best_bin = k; }
+        }
     }
-    int nl = split - lo + 1;
-    layout_rec(keys, lo, split, idx + 1, idx, T);
+    int mid = lo + count / 2;
+    if (best_axis >= 0) {
+        int a = best_axis;
+        float ext = cmax[a] - cmin[a];
+        auto it = std::stable_partition(perm.begin() + lo, perm.begin() + hi, [&](int f) {
+            return std::min(kBins - 1, (int)((cen[3 * f + a] - cmin[a]) / ext * kBins)) <= best_bin;
+        });
+        int m = (int)(it - perm.begin());
+        if (m > lo && m < hi) mid = m;
+    }
+    int nl = mid - lo;
+    sah_rec(bb, cen, perm, lo, mid, idx + 1, idx, T);
     T.right[idx] = idx + 2 * nl;
-    layout_rec(keys, split + 1, hi, idx + 2 * nl, idx, T);
-    return idx;
+    sah_rec(bb, cen, perm, mid, hi, idx + 2 * nl, idx, T);
 }
 
 static bool build_topology(const fr_model_desc *m, HostTopo &T) {
@@ -1138,39 +1225,24 @@ static bool build_topology(const fr_model_desc *m, HostTopo &T) {
             for (int q = T.vf_off[v]; q < fill[v]; ++q) dup |= T.vf_idx[q] == f;
             if (!dup) T.vf_idx[fill[v]++] = f;
         }
-    // Morton codes of the mean-shape face centroids (tree order only)
-    std::vector<float> cx(F), cy(F), cz(F);
-    float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-    for (int f = 0; f < F; ++f) {
-        float c[3];
+    // Tree order: binned-SAH top-down build over the mean shape's triangle
+    // boxes (once; every evaluation refits the boxes of this tree).
+    std::vector<float> bb(6 * (size_t)F), cen(3 * (size_t)F);
+    for (int f = 0; f < F; ++f)
         for (int a = 0; a < 3; ++a) {
-            c[a] = (m->mean[(size_t)a * V + m->faces[3 * f]] + m->mean[(size_t)a * V + m->faces[3 * f + 1]] +
-                    m->mean[(size_t)a * V + m->faces[3 * f + 2]]) / 3.0f;
-            lo[a] = std::min(lo[a], c[a]); hi[a] = std::max(hi[a], c[a]);
+            float x0 = m->mean[(size_t)a * V + m->faces[3 * f]], x1 = m->mean[(size_t)a * V + m->faces[3 * f + 1]],
+                  x2 = m->mean[(size_t)a * V + m->faces[3 * f + 2]];
+            bb[6 * f + a] = std::min(std::min(x0, x1), x2);
+            bb[6 * f + 3 + a] = std::max(std::max(x0, x1), x2);
+            cen[3 * f + a] = (x0 + x1 + x2) / 3.0f;
         }
-        cx[f] = c[0]; cy[f] = c[1]; cz[f] = c[2];
-    }
-    std::vector<uint64_t> key(F);
-    for (int f = 0; f < F; ++f) {
-        float c[3] = {cx[f], cy[f], cz[f]};
-        uint32_t q[3];
-        for (int a = 0; a < 3; ++a) {
-            float ext = hi[a] - lo[a];
-            float u = ext > 0 ? (c[a] - lo[a]) / ext : 0.5f;
-            q[a] = (uint32_t)std::min(1023.0f, std::max(0.0f, u * 1024.0f));
-        }
-        uint32_t code = (spread10(q[0]) << 2) | (spread10(q[1]) << 1) | spread10(q[2]);
-        key[f] = ((uint64_t)code << 32) | (uint32_t)f;
-    }
-    std::sort(key.begin(), key.end());
-    T.sorted_tri.resize(F);
-    for (int i = 0; i < F; ++i) T.sorted_tri[i] = (int)(key[i] & 0xffffffffu);
-    std::vector<uint64_t> codes(F);
-    for (int i = 0; i < F; ++i) codes[i] = key[i] >> 32;
+    std::vector<int> perm(F);
+    for (int f = 0; f < F; ++f) perm[f] = f;
     T.n_nodes = 2 * F - 1;
     T.parent.assign(T.n_nodes, -1); T.right.assign(T.n_nodes, -1); T.escape.assign(T.n_nodes, 0);
     T.leaf_node.assign(F, 0);
-    layout_rec(codes, 0, F - 1, 0, -1, T);
+    sah_rec(bb, cen, perm, 0, F, 0, -1, T);
+    T.sorted_tri = perm;
     return true;
 }
 
@@ -1239,7 +1311,7 @@ int fr_create(const fr_model_desc *m, const fr_scene_desc *s, uint32_t flags, fr
         R(dalloc(c, &c->ew, (size_t)(1 + c->nl) * c->E)) || R(dalloc(c, &c->ewmax, (size_t)(1 + c->nl))) ||
         R(dalloc(c, &c->tbl_edge, (size_t)(1 + c->nl) * c->E)) || R(dalloc(c, &c->tbl_prefix, (size_t)(1 + c->nl) * c->E)) ||
         R(dalloc(c, &c->tbl_n, (size_t)(1 + c->nl))) || R(dalloc(c, &c->tbl_Q, (size_t)(1 + c->nl))) ||
-        R(dalloc(c, &c->ctr, 32)) ||
+        R(dalloc(c, &c->ctr, 8 * kNumKern)) ||
         R(dalloc(c, &c->pe_samples, (size_t)c->W * c->H)) || R(dalloc(c, &c->pe_hits, 2 * (size_t)c->W * c->H)) ||
         R(dalloc(c, &c->pe_f, 6 * (size_t)c->W * c->H)) ||
         R(dalloc(c, &c->g_light, 3 * (size_t)c->nl)) || R(dalloc(c, &c->g_spec, (size_t)c->res * c->res)) ||
@@ -1258,9 +1330,9 @@ int fr_create(const fr_model_desc *m, const fr_scene_desc *s, uint32_t flags, fr
         return FR_ENOMEM;
     }
     (void)hipMemset(c->arrive, 0, sizeof(unsigned int) * c->n_nodes);
-    (void)hipMemset(c->ctr, 0, 32 * sizeof(unsigned long long));
+    (void)hipMemset(c->ctr, 0, 8 * kNumKern * sizeof(unsigned long long));
     if (flags & FR_TIMING)
-        for (int i = 0; i < 12; ++i) (void)hipEventCreate(&c->ev[i]);
+        for (int i = 0; i < kNumEvents; ++i) (void)hipEventCreate(&c->ev[i]);
     if (hipDeviceSynchronize() != hipSuccess) { fr_destroy(c); return FR_EDEVICE; }
     *out = c;
     return FR_OK;
@@ -1328,18 +1400,17 @@ int fr_render(fr_ctx *c, const fr_params *p, uint64_t seed, int32_t spp, float *
         HIPCK(c, hipMalloc((void **)&c->samples, (size_t)N * 3 * sizeof(float)));
         c->samples_cap = (size_t)N * 3;
     }
-    // visibility masks: 4 bytes per camera sample, kept when they fit
-    bool keep_vis = c->nl <= 32 && (size_t)N * sizeof(uint32_t) <= kVisBudgetBytes;
-    if (keep_vis && (size_t)N > c->vis_cap) {
+    size_t rec = (size_t)std::min(N, kChunk);
+    if (rec > c->rec_cap) {
+        if (c->hits) (void)hipFree(c->hits);
         if (c->vis) (void)hipFree(c->vis);
-        c->vis = nullptr;
-        c->vis_cap = 0;
-        HIPCK(c, hipMalloc((void **)&c->vis, (size_t)N * sizeof(uint32_t)));
-        c->vis_cap = (size_t)N;
+        c->hits = nullptr; c->vis = nullptr; c->rec_cap = 0;
+        HIPCK(c, hipMalloc((void **)&c->hits, rec * sizeof(HitRec)));
+        HIPCK(c, hipMalloc((void **)&c->vis, rec * sizeof(unsigned long long)));
+        c->rec_cap = rec;
     }
-    c->vis_valid = keep_vis;
-
     c->have_render = false;
+    c->records_valid = false;
     c->last = *p;
     c->last_seed = seed;
     c->last_spp = spp;
@@ -1356,17 +1427,30 @@ int fr_render(fr_ctx *c, const fr_params *p, uint64_t seed, int32_t spp, float *
     hipLaunchKernelGGL(k_edge_scan<1024>, dim3(1 + c->nl), dim3(1024), 0, c->stream, c->E, c->ew, c->ewmax,
                        c->tbl_edge, c->tbl_prefix, c->tbl_n, c->tbl_Q);
     ev_record(c, 3);
-    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, c->stream, c->ctr, 32);
+    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, c->stream, c->ctr, 8 * kKernAdj);
     size_t lds = (size_t)c->res * c->res * sizeof(float);
-    ev_record(c, 9);
-    hipLaunchKernelGGL(k_render_fwd, dim3(nblk(N, 256)), dim3(256), lds, c->stream, S, seed, spp, N, c->samples,
-                       c->vis_valid ? c->vis : nullptr, c->ctr);
-    ev_record(c, 10);
+    for (long long s0 = 0; s0 < N; s0 += kChunk) {
+        long long n = std::min(kChunk, N - s0);
+        ev_record(c, 8 + 2 * kKernCamera);
+        hipLaunchKernelGGL(k_fwd_camera, dim3(nblk(n, 256)), dim3(256), 0, c->stream, S, seed, spp, s0, n,
+                           c->hits, c->vis, c->ctr + 8 * kKernCamera);
+        ev_record(c, 9 + 2 * kKernCamera);
+        ev_record(c, 8 + 2 * kKernShadow);
+        hipLaunchKernelGGL(k_fwd_shadow, dim3(nblk(n, 256), c->nl), dim3(256), 0, c->stream, S, seed, s0, n,
+                           c->hits, c->vis, c->ctr + 8 * kKernShadow);
+        ev_record(c, 9 + 2 * kKernShadow);
+        ev_record(c, 8 + 2 * kKernShade);
+        hipLaunchKernelGGL(k_fwd_shade, dim3(nblk(n, 256)), dim3(256), lds, c->stream, S, seed, spp, s0, n,
+                           c->hits, c->vis, c->samples, c->ctr + 8 * kKernShade);
+        ev_record(c, 9 + 2 * kKernShade);
+    }
     hipLaunchKernelGGL(k_pixel_mean, dim3(nblk((size_t)c->W * c->H, 256)), dim3(256), 0, c->stream,
                        c->W * c->H, spp, c->samples, out);
     ev_record(c, 4);
     HIPCK(c, hipGetLastError());
+    c->records_valid = N <= kChunk;
     c->have_render = true;
+    c->have_backward = false;
     return FR_OK;
 }
 
@@ -1386,26 +1470,39 @@ int fr_backward(fr_ctx *c, const float *dLdI, const fr_grads *g) {
     long long N = (long long)c->W * c->H * c->last_spp;
     GradBufs G{c->g_light, c->g_spec, c->g_pos, c->g_nrm, c->g_alb};
     size_t lds = ((size_t)2 * c->res * c->res + 3 * c->nl) * sizeof(float);
-    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, c->stream, c->ctr + 8, 24);
-    ev_record(c, 7);
-    if (c->terms & FR_TERM_INTERIOR)
-        hipLaunchKernelGGL(k_render_adj, dim3(nblk(N, 256)), dim3(256), lds, c->stream, S, c->last_seed, c->last_spp, N,
-                           dLdI, G, c->vis_valid ? c->vis : nullptr, c->ctr + 8);
-    ev_record(c, 8);
+    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, c->stream, c->ctr + 8 * kKernAdj, 8 * (kNumKern - kKernAdj));
     size_t lds1 = (size_t)c->res * c->res * sizeof(float);
-    if (c->terms & FR_TERM_SECONDARY)
-        hipLaunchKernelGGL(k_edge_secondary, dim3(nblk(N, 256)), dim3(256), lds1, c->stream, S, c->last_seed, c->last_spp, N,
-                           dLdI, c->g_pos, c->ctr + 24);
+    for (long long s0 = 0; s0 < N; s0 += kChunk) {
+        long long n = std::min(kChunk, N - s0);
+        if (!c->records_valid) {   // recompute this chunk's hit records and visibility
+            hipLaunchKernelGGL(k_fwd_camera, dim3(nblk(n, 256)), dim3(256), 0, c->stream, S, c->last_seed,
+                               c->last_spp, s0, n, c->hits, c->vis, c->ctr + 8 * kKernAdj);
+            hipLaunchKernelGGL(k_fwd_shadow, dim3(nblk(n, 256), c->nl), dim3(256), 0, c->stream, S, c->last_seed,
+                               s0, n, c->hits, c->vis, c->ctr + 8 * kKernAdj);
+        }
+        ev_record(c, 8 + 2 * kKernAdj);
+        if (c->terms & FR_TERM_INTERIOR)
+            hipLaunchKernelGGL(k_render_adj, dim3(nblk(n, 256)), dim3(256), lds, c->stream, S, c->last_seed,
+                               c->last_spp, s0, n, dLdI, G, c->hits, c->vis, c->ctr + 8 * kKernAdj);
+        ev_record(c, 9 + 2 * kKernAdj);
+        ev_record(c, 8 + 2 * kKernSecondary);
+        if (c->terms & FR_TERM_SECONDARY)
+            hipLaunchKernelGGL(k_edge_secondary, dim3(nblk(n, 256), c->nl), dim3(256), lds1, c->stream, S,
+                               c->last_seed, c->last_spp, s0, n, dLdI, c->hits, c->g_pos, c->ctr + 8 * kKernSecondary);
+        ev_record(c, 9 + 2 * kKernSecondary);
+    }
+    ev_record(c, 8 + 2 * kKernPrimary);
     if (c->terms & FR_TERM_PRIMARY) {
         int M = c->W * c->H;
         hipLaunchKernelGGL(k_zero_d, dim3(nblk(6 * (size_t)M, 256)), dim3(256), 0, c->stream, c->pe_f, 6 * (size_t)M);
         hipLaunchKernelGGL(k_edge_primary_setup, dim3(nblk(M, 256)), dim3(256), 0, c->stream,
-                           S, c->last_seed, M, c->pe_samples, c->pe_hits, c->ctr + 16);
+                           S, c->last_seed, M, c->pe_samples, c->pe_hits, c->ctr + 8 * kKernPrimary);
         hipLaunchKernelGGL(k_edge_primary_shade, dim3(nblk((size_t)M * 2 * c->nl, 256)), dim3(256), lds1, c->stream,
-                           S, c->last_seed, M, c->pe_samples, c->pe_hits, c->pe_f, c->ctr + 16);
+                           S, c->last_seed, M, c->pe_samples, c->pe_hits, c->pe_f, c->ctr + 8 * kKernPrimary);
         hipLaunchKernelGGL(k_edge_primary_scatter, dim3(nblk(M, 256)), dim3(256), 0, c->stream,
                            S, M, dLdI, c->pe_samples, c->pe_f, c->g_pos);
     }
+    ev_record(c, 9 + 2 * kKernPrimary);
     hipLaunchKernelGGL(k_normal_adj, dim3(nblk(c->V, 256)), dim3(256), 0, c->stream, c->V, c->nrm, c->nlen, c->g_nrm, c->g_N);
     hipLaunchKernelGGL(k_chain_gather, dim3(nblk(c->V, 256)), dim3(256), 0, c->stream, c->V, c->faces, c->vf_off, c->vf_idx,
                        c->pos, c->g_N, c->g_pos, c->pose, c->g_vert, c->g_m);
@@ -1442,10 +1539,10 @@ int fr_loss_l2(fr_ctx *c, const float *img, const float *tgt, float *dL, float *
 int fr_stats(fr_ctx *c, fr_stats_t *out) {
     if (!c || !out) return FR_EINVAL;
     HIPCK(c, hipStreamSynchronize(c->stream));
-    unsigned long long h[32];
+    unsigned long long h[8 * kNumKern];
     HIPCK(c, hipMemcpy(h, c->ctr, sizeof h, hipMemcpyDeviceToHost));
     memset(out, 0, sizeof *out);
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < kNumKern; ++k) {
         const unsigned long long *q = h + 8 * k;
         out->rays_camera += q[0]; out->rays_shadow += q[1];
         out->rays_edge_primary += q[2]; out->rays_edge_secondary += q[3];
@@ -1455,18 +1552,19 @@ int fr_stats(fr_ctx *c, fr_stats_t *out) {
         out->kernel_shades[k] = q[6];
     }
     out->traversal_overflow = 0;
-    if (c->flags & FR_TIMING) {
+    if ((c->flags & FR_TIMING) && c->have_render) {
         float t;
-        // events of a phase that has not run yet are not queried
-        if (!c->have_render) return FR_OK;
+        // events of a phase that has not run since the last render are not queried
         if (hipEventElapsedTime(&t, c->ev[0], c->ev[1]) == hipSuccess) out->ms_blend = t;
         if (hipEventElapsedTime(&t, c->ev[1], c->ev[2]) == hipSuccess) out->ms_bvh = t;
         if (hipEventElapsedTime(&t, c->ev[2], c->ev[3]) == hipSuccess) out->ms_edges = t;
         if (hipEventElapsedTime(&t, c->ev[3], c->ev[4]) == hipSuccess) out->ms_render = t;
-        if (hipEventElapsedTime(&t, c->ev[9], c->ev[10]) == hipSuccess) out->ms_kernel_fwd = t;
+        for (int k = 0; k < kKernAdj; ++k)
+            if (hipEventElapsedTime(&t, c->ev[8 + 2 * k], c->ev[9 + 2 * k]) == hipSuccess) out->ms_kernel[k] = t;
         if (c->have_backward) {
             if (hipEventElapsedTime(&t, c->ev[5], c->ev[6]) == hipSuccess) out->ms_backward = t;
-            if (hipEventElapsedTime(&t, c->ev[7], c->ev[8]) == hipSuccess) out->ms_kernel_adj = t;
+            for (int k = kKernAdj; k < kNumKern; ++k)
+                if (hipEventElapsedTime(&t, c->ev[8 + 2 * k], c->ev[9 + 2 * k]) == hipSuccess) out->ms_kernel[k] = t;
         }
         (void)hipGetLastError();   // a failed query must not leak into later calls
     }
@@ -1482,7 +1580,8 @@ void fr_destroy(fr_ctx *c) {
                     c->lgeom, c->sorted_tri, c->leaf_node, c->parent, c->right, c->escape, c->arrive, c->nodes, c->tris,
                     c->vmodel, c->pos, c->nrm, c->nlen, c->alb, c->ew, c->ewmax, c->tbl_edge, c->tbl_prefix, c->tbl_n,
                     c->tbl_Q, c->samples, c->ctr, c->g_light, c->g_spec, c->g_pos, c->g_nrm, c->g_alb, c->g_N,
-                    c->g_vert, c->g_m, c->partial, c->loss_partial, c->vis, c->pe_samples, c->pe_hits, c->pe_f};
+                    c->g_vert, c->g_m, c->partial, c->loss_partial, c->hits, c->vis, c->pe_samples, c->pe_hits,
+                    c->pe_f};
     for (void *p : ptrs) if (p) (void)hipFree(p);
     for (auto &e : c->ev) if (e) (void)hipEventDestroy(e);
     delete c;

@@ -56,11 +56,14 @@ class fr_stats_t(C.Structure):
     _fields_ = [("rays_camera", C.c_uint64), ("rays_shadow", C.c_uint64),
                 ("rays_edge_primary", C.c_uint64), ("rays_edge_secondary", C.c_uint64),
                 ("traversal_overflow", C.c_uint64), ("box_tests", C.c_uint64), ("tri_tests", C.c_uint64),
-                ("kernel_rays", C.c_uint64 * 4), ("kernel_box_tests", C.c_uint64 * 4),
-                ("kernel_tri_tests", C.c_uint64 * 4), ("kernel_shades", C.c_uint64 * 4),
+                ("kernel_rays", C.c_uint64 * 6), ("kernel_box_tests", C.c_uint64 * 6),
+                ("kernel_tri_tests", C.c_uint64 * 6), ("kernel_shades", C.c_uint64 * 6),
                 ("ms_blend", C.c_float), ("ms_bvh", C.c_float),
                 ("ms_edges", C.c_float), ("ms_render", C.c_float), ("ms_backward", C.c_float),
-                ("ms_kernel_fwd", C.c_float), ("ms_kernel_adj", C.c_float)]
+                ("ms_kernel", C.c_float * 6)]
+
+
+KERNELS = ("k_fwd_camera", "k_fwd_shadow", "k_fwd_shade", "k_render_adj", "k_edge_primary", "k_edge_secondary")
 
 
 EXPORTS = ("fr_create", "fr_set_stream", "fr_set_terms", "fr_blend", "fr_render", "fr_backward",
