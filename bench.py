@@ -162,6 +162,7 @@ def main():
                                f"morphable face, {scene.width}x{scene.height}, {spp} spp, 20 area lights, "
                                "forward + adjoint (interior, camera-silhouette and shadow-boundary terms)",
                    "rays_per_iter": rays_per_iter,
+                   "traversal_overflow": int(last["traversal_overflow"]),
                    "ms_kernels": {n: round(kern[n][1] * 1e3, 3) for n in facert.KERNELS},
                    "box_tests_per_ray": {n: round(last["kernel_box_tests"][k] / max(1, last["kernel_rays"][k]), 2)
                                          for k, n in enumerate(facert.KERNELS)},

@@ -107,7 +107,7 @@ __global__ __launch_bounds__(256) void k_normals(int V, const int *__restrict__ 
 __global__ __launch_bounds__(256) void k_refit(int F, const int *__restrict__ faces, const float *__restrict__ pos, int V,
         const int *__restrict__ sorted_tri, const int *__restrict__ leaf_node,
         const int *__restrict__ parent, const int *__restrict__ right, const int *__restrict__ escape,
-        unsigned int *__restrict__ arrive, float4 *nodes, float4 *__restrict__ tris) {
+        unsigned int *__restrict__ arrive, uint4 *nodes, float4 *__restrict__ tris) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= F) return;
     int f = sorted_tri[i];
@@ -117,24 +117,23 @@ __global__ __launch_bounds__(256) void k_refit(int F, const int *__restrict__ fa
     tris[3 * i + 1] = make_float4(b.y, b.z, c.x, c.y);
     tris[3 * i + 2] = make_float4(c.z, __int_as_float(f), 0.0f, 0.0f);
     int n = leaf_node[i];
-    float4 lo = make_float4(fminf(fminf(a.x, b.x), c.x) - kBoxPad, fminf(fminf(a.y, b.y), c.y) - kBoxPad,
-                            fminf(fminf(a.z, b.z), c.z) - kBoxPad, __int_as_float(escape[n]));
-    float4 hi = make_float4(fmaxf(fmaxf(a.x, b.x), c.x) + kBoxPad, fmaxf(fmaxf(a.y, b.y), c.y) + kBoxPad,
-                            fmaxf(fmaxf(a.z, b.z), c.z) + kBoxPad, __int_as_float(i));
-    nodes[2 * n] = lo;
-    nodes[2 * n + 1] = hi;
+    nodes[n] = qnode(fminf(fminf(a.x, b.x), c.x) - kBoxPad, fminf(fminf(a.y, b.y), c.y) - kBoxPad,
+                     fminf(fminf(a.z, b.z), c.z) - kBoxPad, fmaxf(fmaxf(a.x, b.x), c.x) + kBoxPad,
+                     fmaxf(fmaxf(a.y, b.y), c.y) + kBoxPad, fmaxf(fmaxf(a.z, b.z), c.z) + kBoxPad, ~i);
     __threadfence();
     int p = parent[n];
     while (p >= 0) {
         unsigned int old = atomicAdd(&arrive[p], 1u);
         if ((old & 1u) == 0u) return;            // first child: the sibling continues
         __threadfence();
-        const volatile float4 *vn = nodes;
+        const volatile uint4 *vn = nodes;
         int l = p + 1, r = right[p];
-        float4 la = const_cast<const float4 &>(vn[2 * l]), lb = const_cast<const float4 &>(vn[2 * l + 1]);
-        float4 ra = const_cast<const float4 &>(vn[2 * r]), rb = const_cast<const float4 &>(vn[2 * r + 1]);
-        nodes[2 * p] = make_float4(fminf(la.x, ra.x), fminf(la.y, ra.y), fminf(la.z, ra.z), __int_as_float(escape[p]));
-        nodes[2 * p + 1] = make_float4(fmaxf(lb.x, rb.x), fmaxf(lb.y, rb.y), fmaxf(lb.z, rb.z), __int_as_float(-1));
+        uint4 ql, qr;
+        ql.x = vn[l].x; ql.y = vn[l].y; ql.z = vn[l].z;
+        qr.x = vn[r].x; qr.y = vn[r].y; qr.z = vn[r].z;
+        QBox L = qbox(ql), R = qbox(qr);   // binary16 values: the union re-encodes exactly
+        nodes[p] = qnode(fminf(L.lx, R.lx), fminf(L.ly, R.ly), fminf(L.lz, R.lz),
+                         fmaxf(L.hx, R.hx), fmaxf(L.hy, R.hy), fmaxf(L.hz, R.hz), escape[p]);
         __threadfence();
         p = parent[p];
     }
@@ -299,10 +298,10 @@ __device__ inline void flush_work(unsigned long long *ctr, const Work &w) {
 // The forward pass runs as three kernels over a chunk of camera samples:
 //   k_fwd_camera  one lane per sample: jittered pinhole ray, closest hit ->
 //                 16-byte hit record;
-//   k_fwd_shadow  one lane per (sample, light), a 2D grid with the light on
-//                 the y axis so that a wave traces 64 neighbouring samples
-//                 toward the same light: horizon test and shadow ray, one
-//                 bit per light in the sample's visibility mask;
+//   k_fwd_shadow  one block per (tile of samples, light), the light on the
+//                 grid's y axis so that a wave traces neighbouring samples
+//                 toward the same light: horizon test, compaction, shadow
+//                 ray, one bit per light in the sample's visibility mask;
 //   k_fwd_shade   one lane per sample: shading of the visible lights (no
 //                 traversal).
 // The adjoint and the shadow-boundary kernels read the same records; when a
@@ -333,30 +332,71 @@ __global__ __launch_bounds__(256) void k_fwd_camera(Scene S, uint64_t seed, int 
     flush_work(ctr, wk);
 }
 
+// Shadow rays are compacted before they are traced: a block takes a tile of
+// kShTile consecutive samples for one light, its lanes run the horizon test
+// and append the rays that need tracing to a list in LDS (one LDS atomic per
+// wave), and the block's waves then trace the list 64 entries at a time.
+// About a third of the (sample, light) pairs need a ray at the paper's
+// framing (camera misses and lights below the horizon need none), so
+// tracing in place would leave two lanes in three idle.
+constexpr int kShTile = 512;
+__device__ __forceinline__ int lanes_below(unsigned long long m) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0));
+}
+
 __global__ __launch_bounds__(256) void k_fwd_shadow(Scene S, uint64_t seed, long long s0, long long n,
         const HitRec *__restrict__ hits, unsigned long long *__restrict__ vis, unsigned long long *ctr) {
-    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    int j = blockIdx.y;
+    __shared__ float4 q_o[kShTile];   // origin p, hit triangle
+    __shared__ float4 q_d[kShTile];   // y - p, tile-local sample index
+    __shared__ int q_n;
+    if (threadIdx.x == 0) q_n = 0;
+    __syncthreads();
+    const int j = blockIdx.y;
+    const long long base = (long long)blockIdx.x * kShTile;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     uint32_t n_sh = 0;
     Work wk;
-    if (i < n) {
-        HitRec rec = hits[i];
-        if (rec.tri >= 0) {
-            Hit h = hit_of(rec);
-            v3 o = mk(S.cam_x, S.cam_y, S.cam_z);
-            SurfDec sd;
-            surf_decide(S, o, h, sd);
-            const float *g = S.lgeom + 12 * j;
-            Light L;
-            L.c = mk(g[0], g[1], g[2]); L.e1 = mk(g[3], g[4], g[5]); L.e2 = mk(g[6], g[7], g[8]);
-            LightRng rng(seed, (uint32_t)(s0 + i), 0, 2);
-            float u, v;
-            rng.get(j, u, v);
-            v3 y = light_point(L, u, v);
-            if (above(sd, y)) {
-                ++n_sh;
-                if (!trace_any(S, sd.p, y - sd.p, h.tri, wk)) atomicOr(&vis[i], 1ull << j);
+    const float *g = S.lgeom + 12 * j;
+    Light L;
+    L.c = mk(g[0], g[1], g[2]); L.e1 = mk(g[3], g[4], g[5]); L.e2 = mk(g[6], g[7], g[8]);
+    const v3 cam = mk(S.cam_x, S.cam_y, S.cam_z);
+    for (int k = 0; k < kShTile; k += 256) {
+        const int li = k + (int)threadIdx.x;
+        const long long i = base + li;
+        bool need = false;
+        v3 p, dd;
+        int tri = -1;
+        if (i < n) {
+            HitRec rec = hits[i];
+            if (rec.tri >= 0) {
+                Hit h = hit_of(rec);
+                SurfDec sd;
+                surf_decide(S, cam, h, sd);
+                LightRng rng(seed, (uint32_t)(s0 + i), 0, 2);
+                float u, v;
+                rng.get(j, u, v);
+                v3 y = light_point(L, u, v);
+                if (above(sd, y)) { need = true; p = sd.p; dd = y - sd.p; tri = h.tri; }
             }
+        }
+        unsigned long long m = __ballot(need);
+        int wbase = 0;
+        if (lane == 0 && m) wbase = atomicAdd(&q_n, __popcll(m));
+        wbase = __shfl(wbase, 0);
+        if (need) {
+            int slot = wbase + lanes_below(m);
+            q_o[slot] = make_float4(p.x, p.y, p.z, __int_as_float(tri));
+            q_d[slot] = make_float4(dd.x, dd.y, dd.z, __int_as_float(li));
+            ++n_sh;
+        }
+    }
+    __syncthreads();
+    const int nq = q_n;
+    for (int e = wave * 64 + lane; e - lane < nq; e += 256) {
+        if (e < nq) {
+            float4 o4 = q_o[e], d4 = q_d[e];
+            if (!trace_any(S, mk(o4.x, o4.y, o4.z), mk(d4.x, d4.y, d4.z), __float_as_int(o4.w), wk))
+                atomicOr(&vis[base + __float_as_int(d4.w)], 1ull << j);
         }
     }
     flush_count(ctr, 1, n_sh);
@@ -553,48 +593,52 @@ using e3 = vec3<ER>;
 
 // Shadow-boundary (secondary) edge sample of light j at a camera sample's
 // shading point; decisions fp32, values in ER.
-__device__ inline void secondary_edge(const Scene &S, const Light &L, int j, uint64_t seed, uint32_t sidx,
+// kTrace = false stops before the two shadow rays and only reports whether
+// the sample needs them; kTrace = true runs the whole sample.
+template <bool kTrace>
+__device__ inline bool secondary_edge(const Scene &S, const Light &L, int j, uint64_t seed, uint32_t sidx,
                                       const float *spec_lds, v3 o, v3 dcam, const Hit &h, const SurfDec &sf,
                                       const float *w, double *d_pos, uint32_t &n_rays, Work &steps) {
     int n = S.se_n[j];
     uint64_t Q = S.se_Q[j];
-    if (n == 0 || Q == 0) return;
+    if (n == 0 || Q == 0) return false;
     u4 wd = philox(seed, sidx, (uint32_t)j, 1, 0);
     const uint64_t *pre = S.se_prefix + (size_t)j * S.E;
     uint64_t target = __umul64hi(((uint64_t)wd.y << 32) | wd.x, Q);
     int i = cdf_pick(pre, n, target);
     int e = S.se_edge[(size_t)j * S.E + i];
     const int *ed = S.edges + 4 * e;
-    if (ed[2] == h.tri || ed[3] == h.tri) return;
+    if (ed[2] == h.tri || ed[3] == h.tri) return false;
     v3 p = sf.p;
     if (ed[3] >= 0) {
         float s1 = dot(face_normal(S, ed[2]), p - vpos(S, S.faces[3 * ed[2]]));
         float s2 = dot(face_normal(S, ed[3]), p - vpos(S, S.faces[3 * ed[3]]));
-        if ((s1 > 0.0f) == (s2 > 0.0f)) return;
+        if ((s1 > 0.0f) == (s2 > 0.0f)) return false;
     }
     float tu = u01(wd.z);
     v3 a = vpos(S, ed[0]), b = vpos(S, ed[1]);
     v3 sp = mk(a.x + tu * (b.x - a.x), a.y + tu * (b.y - a.y), a.z + tu * (b.z - a.z));
     float den = dot(L.n, sp - p);
-    if (den == 0.0f) return;
+    if (den == 0.0f) return false;
     float lam = dot(L.n, L.c - p) / den;
-    if (!(lam > 1.0f)) return;
+    if (!(lam > 1.0f)) return false;
     v3 y = mk(p.x + lam * (sp.x - p.x), p.y + lam * (sp.y - p.y), p.z + lam * (sp.z - p.z));
     v3 ql = y - L.c;
-    if (!(fabsf(dot(ql, L.e1)) <= 0.5f * dot(L.e1, L.e1) && fabsf(dot(ql, L.e2)) <= 0.5f * dot(L.e2, L.e2))) return;
-    if (!above(sf, y)) return;
+    if (!(fabsf(dot(ql, L.e1)) <= 0.5f * dot(L.e1, L.e1) && fabsf(dot(ql, L.e2)) <= 0.5f * dot(L.e2, L.e2))) return false;
+    if (!above(sf, y)) return false;
     v3 m = cross(a - p, b - p);
     float mn = dot(m, L.n);
     v3 mp = mk(m.x - mn * L.n.x, m.y - mn * L.n.y, m.z - mn * L.n.z);
     float lm = sqrtf(dot(mp, mp));
-    if (lm == 0.0f) return;
+    if (lm == 0.0f) return false;
     v3 un = mk(mp.x / lm, mp.y / lm, mp.z / lm);
     v3 yp = mk(y.x + kEdgeOffM * un.x, y.y + kEdgeOffM * un.y, y.z + kEdgeOffM * un.z);
     v3 ym = mk(y.x - kEdgeOffM * un.x, y.y - kEdgeOffM * un.y, y.z - kEdgeOffM * un.z);
+    if (!kTrace) return true;
     n_rays += 2;
     bool vp = !trace_any(S, p, yp - p, h.tri, steps);
     bool vm = !trace_any(S, p, ym - p, h.tri, steps);
-    if (vp == vm) return;
+    if (vp == vm) return false;
     // ---- value path
     Surf<ER> sd;
     surf_value<ER>(S, spec_lds, o, dcam, h, sf, sd);
@@ -619,34 +663,68 @@ __device__ inline void secondary_edge(const Scene &S, const Light &L, int j, uin
     atomic_v(d_pos, S.V, ed[1], dpsi_b * W);
     // the receiver point p moves along the fixed camera ray
     chain_hit<ER>(S.V, sd, dpsi_p * W, (ER)0, (ER)0, (ER)0, d_pos);
+    return true;
 }
 
-// One lane per (camera sample, light) of the chunk: the light's
-// shadow-boundary sample at the sample's shading point.
+// One block per (tile of kShTile camera samples, light).  The lanes first
+// run each sample's edge pick and acceptance tests (no rays) and compact the
+// accepted samples into an LDS list; the block's waves then run those
+// samples whole, two shadow rays each.  Most samples are rejected before
+// any ray, so tracing in place would leave most lanes idle.
+__device__ __forceinline__ void sec_setup(const Scene &S, uint64_t seed, int spp, long long s0, long long i,
+        const float *dLdI, const HitRec *hits, v3 &o, v3 &d, float w[3], Hit &h, SurfDec &sd, uint32_t &s,
+        bool &live) {
+    HitRec rec = hits[i];
+    s = (uint32_t)(s0 + i);
+    int pix;
+    o = mk(S.cam_x, S.cam_y, S.cam_z);
+    d = camera_sample(S, seed, s, spp, pix);
+    float inv = 1.0f / (float)spp;
+    w[0] = dLdI[3 * pix] * inv; w[1] = dLdI[3 * pix + 1] * inv; w[2] = dLdI[3 * pix + 2] * inv;
+    live = rec.tri >= 0 && (w[0] != 0.0f || w[1] != 0.0f || w[2] != 0.0f);
+    if (live) {
+        h = hit_of(rec);
+        surf_decide(S, o, h, sd);
+    }
+}
+
 __global__ __launch_bounds__(256) void k_edge_secondary(Scene S, uint64_t seed, int spp, long long s0, long long n,
         const float *__restrict__ dLdI, const HitRec *__restrict__ hits, double *d_pos, unsigned long long *ctr) {
     extern __shared__ float dyn[];
     __shared__ Light Ls[kMaxLights];
+    __shared__ int q_i[kShTile];
+    __shared__ int q_n;
     float *spec_lds = dyn;
     stage_tables(S, Ls, spec_lds);
+    if (threadIdx.x == 0) q_n = 0;
     __syncthreads();
-    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    int j = blockIdx.y;
+    const int j = blockIdx.y;
+    const long long base = (long long)blockIdx.x * kShTile;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     uint32_t n_sec = 0;
     Work wk;
-    if (i < n) {
-        HitRec rec = hits[i];
-        uint32_t s = (uint32_t)(s0 + i);
-        int pix;
-        v3 o = mk(S.cam_x, S.cam_y, S.cam_z);
-        v3 d = camera_sample(S, seed, s, spp, pix);
-        float inv = 1.0f / (float)spp;
-        float w[3] = {dLdI[3 * pix] * inv, dLdI[3 * pix + 1] * inv, dLdI[3 * pix + 2] * inv};
-        if (rec.tri >= 0 && (w[0] != 0.0f || w[1] != 0.0f || w[2] != 0.0f)) {
-            Hit h = hit_of(rec);
-            SurfDec sd;
-            surf_decide(S, o, h, sd);
-            secondary_edge(S, Ls[j], j, seed, s, spec_lds, o, d, h, sd, w, d_pos, n_sec, wk);
+    for (int k = 0; k < kShTile; k += 256) {
+        const int li = k + (int)threadIdx.x;
+        const long long i = base + li;
+        bool need = false;
+        if (i < n) {
+            v3 o, d; float w[3]; Hit h; SurfDec sd; uint32_t s; bool live;
+            sec_setup(S, seed, spp, s0, i, dLdI, hits, o, d, w, h, sd, s, live);
+            if (live) need = secondary_edge<false>(S, Ls[j], j, seed, s, spec_lds, o, d, h, sd, w, d_pos, n_sec, wk);
+        }
+        unsigned long long m = __ballot(need);
+        int wbase = 0;
+        if (lane == 0 && m) wbase = atomicAdd(&q_n, __popcll(m));
+        wbase = __shfl(wbase, 0);
+        if (need) q_i[wbase + lanes_below(m)] = li;
+    }
+    __syncthreads();
+    const int nq = q_n;
+    for (int e = wave * 64 + lane; e - lane < nq; e += 256) {
+        if (e < nq) {
+            v3 o, d; float w[3]; Hit h; SurfDec sd; uint32_t s; bool live;
+            sec_setup(S, seed, spp, s0, base + q_i[e], dLdI, hits, o, d, w, h, sd, s, live);
+            secondary_edge<true>(S, Ls[j], j, seed, s, spec_lds, o, d, h, sd, w, d_pos, n_sec, wk);
         }
     }
     flush_count(ctr, 3, n_sec);
@@ -655,12 +733,13 @@ __global__ __launch_bounds__(256) void k_edge_secondary(Scene S, uint64_t seed, 
 
 // ---------------------------------------------- camera silhouettes -----
 // M = W*H edge samples, in three passes so that the 40 shadow rays of a
-// sample run on 40 lanes:
+// sample run on separate lanes:
 //   k_edge_primary_setup  one lane per sample: pick the edge, the point q
 //                         on its projection, the two sides q +- offset; trace
 //                         both camera rays and keep the hits;
-//   k_edge_primary_shade  one lane per (sample, side, light): shadow ray and
-//                         fp64 radiance of that light, summed per side;
+//   k_edge_primary_shade  one block per (tile of sides, light): horizon
+//                         test, compaction, shadow ray and fp64 radiance of
+//                         that light, summed per side;
 //   k_edge_primary_scatter one lane per sample: (f+ - f-) times the boundary
 //                         Jacobian into the edge's two endpoints.
 struct PeSample { int e, i, pix; float qx, qy; };
@@ -725,44 +804,72 @@ __device__ __forceinline__ void pe_side_point(const Scene &S, const PeSample &ps
     py = ps.qy + sg * (kEdgeOffPx * ny);
 }
 
+// the light sample of side ms = 2 m + side toward light j; false when the
+// sample has no surface or the light point is below its horizon
+__device__ __forceinline__ bool pe_light(const Scene &S, uint64_t seed, const PeSample *ps_in, const Hit *hits,
+        const Light &L, int j, int ms, v3 &o, v3 &d, Hit &h, SurfDec &sd, v3 &y) {
+    int m = ms >> 1, side = ms & 1;
+    PeSample ps = ps_in[m];
+    h = hits[ms];
+    if (ps.e < 0 || h.tri < 0) return false;
+    float px, py;
+    pe_side_point(S, ps, side, px, py);
+    o = mk(S.cam_x, S.cam_y, S.cam_z);
+    d = camera_dir(S, px, py);
+    surf_decide(S, o, h, sd);
+    LightRng rng(seed, (uint32_t)m, 2, 4);
+    float u, v;
+    rng.get(j, u, v);
+    y = light_point(L, u, v);
+    return above(sd, y);
+}
+
+// One block per (tile of kShTile sides, light): horizon tests, compaction
+// into an LDS list, then one shadow ray and the fp64 radiance per entry.
 __global__ __launch_bounds__(256) void k_edge_primary_shade(Scene S, uint64_t seed, int M,
         const PeSample *__restrict__ ps_in, const Hit *__restrict__ hits, double *__restrict__ fbuf,
         unsigned long long *ctr) {
     extern __shared__ float dyn[];
     __shared__ Light Ls[kMaxLights];
+    __shared__ int q_i[kShTile];
+    __shared__ int q_n;
     float *spec_lds = dyn;
     stage_tables(S, Ls, spec_lds);
+    if (threadIdx.x == 0) q_n = 0;
     __syncthreads();
-    long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y;
+    const int base = blockIdx.x * kShTile;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const Light &L = Ls[j];
     uint32_t n_sh = 0;
     Work wk;
-    if (g < (long long)M * 2 * S.nl) {
-        int j = (int)(g % S.nl);
-        int ms = (int)(g / S.nl);           // 2 m + side
-        int m = ms >> 1, side = ms & 1;
-        PeSample ps = ps_in[m];
-        Hit h = hits[ms];
-        if (ps.e >= 0 && h.tri >= 0) {
-            float px, py;
-            pe_side_point(S, ps, side, px, py);
-            v3 o = mk(S.cam_x, S.cam_y, S.cam_z), d = camera_dir(S, px, py);
-            SurfDec sd;
-            surf_decide(S, o, h, sd);
-            LightRng rng(seed, (uint32_t)m, 2, 4);
-            float u, v;
-            rng.get(j, u, v);
-            const Light &L = Ls[j];
-            v3 y = light_point(L, u, v);
-            if (above(sd, y)) {
-                ++n_sh;
-                if (!trace_any(S, sd.p, y - sd.p, h.tri, wk)) {
-                    Surf<ER> sv;
-                    surf_value<ER>(S, spec_lds, o, d, h, sd, sv);
-                    ER c[3];
-                    shade_light<ER>(sv, L, cvt<ER>(y), light_branch(sd, L.n, y), nullptr, c, nullptr);
-                    ++wk.shade;
-                    for (int k = 0; k < 3; ++k) gadd(&fbuf[3 * ms + k], (double)c[k]);
-                }
+    for (int k = 0; k < kShTile; k += 256) {
+        const int li = k + (int)threadIdx.x;
+        bool need = false;
+        if (base + li < 2 * M) {
+            v3 o, d, y; Hit h; SurfDec sd;
+            need = pe_light(S, seed, ps_in, hits, L, j, base + li, o, d, h, sd, y);
+        }
+        unsigned long long m = __ballot(need);
+        int wbase = 0;
+        if (lane == 0 && m) wbase = atomicAdd(&q_n, __popcll(m));
+        wbase = __shfl(wbase, 0);
+        if (need) { q_i[wbase + lanes_below(m)] = li; ++n_sh; }
+    }
+    __syncthreads();
+    const int nq = q_n;
+    for (int e = wave * 64 + lane; e - lane < nq; e += 256) {
+        if (e < nq) {
+            const int ms = base + q_i[e];
+            v3 o, d, y; Hit h; SurfDec sd;
+            pe_light(S, seed, ps_in, hits, L, j, ms, o, d, h, sd, y);
+            if (!trace_any(S, sd.p, y - sd.p, h.tri, wk)) {
+                Surf<ER> sv;
+                surf_value<ER>(S, spec_lds, o, d, h, sd, sv);
+                ER c[3];
+                shade_light<ER>(sv, L, cvt<ER>(y), light_branch(sd, L.n, y), nullptr, c, nullptr);
+                ++wk.shade;
+                for (int k = 0; k < 3; ++k) gadd(&fbuf[3 * ms + k], (double)c[k]);
             }
         }
     }
@@ -997,7 +1104,8 @@ struct fr_ctx {
     // tree order (device)
     int *sorted_tri = nullptr, *leaf_node = nullptr, *parent = nullptr, *right = nullptr, *escape = nullptr;
     unsigned int *arrive = nullptr;
-    float4 *nodes = nullptr, *tris = nullptr;
+    uint4 *nodes = nullptr;
+    float4 *tris = nullptr;
     // per evaluation (device)
     float *vmodel = nullptr, *pos = nullptr, *nrm = nullptr, *nlen = nullptr, *alb = nullptr;
     float *ew = nullptr; unsigned int *ewmax = nullptr;
@@ -1304,7 +1412,7 @@ int fr_create(const fr_model_desc *m, const fr_scene_desc *s, uint32_t flags, fr
         R(upload(c, &c->parent, T.parent.data(), T.parent.size())) ||
         R(upload(c, &c->right, T.right.data(), T.right.size())) ||
         R(upload(c, &c->escape, T.escape.data(), T.escape.size())) ||
-        R(dalloc(c, &c->arrive, (size_t)c->n_nodes)) || R(dalloc(c, &c->nodes, 2 * (size_t)c->n_nodes)) ||
+        R(dalloc(c, &c->arrive, (size_t)c->n_nodes)) || R(dalloc(c, &c->nodes, (size_t)c->n_nodes)) ||
         R(dalloc(c, &c->tris, 3 * (size_t)c->F)) ||
         R(dalloc(c, &c->vmodel, V3)) || R(dalloc(c, &c->pos, V3)) || R(dalloc(c, &c->nrm, V3)) ||
         R(dalloc(c, &c->nlen, (size_t)c->V)) || R(dalloc(c, &c->alb, V3)) ||
@@ -1436,7 +1544,7 @@ int fr_render(fr_ctx *c, const fr_params *p, uint64_t seed, int32_t spp, float *
                            c->hits, c->vis, c->ctr + 8 * kKernCamera);
         ev_record(c, 9 + 2 * kKernCamera);
         ev_record(c, 8 + 2 * kKernShadow);
-        hipLaunchKernelGGL(k_fwd_shadow, dim3(nblk(n, 256), c->nl), dim3(256), 0, c->stream, S, seed, s0, n,
+        hipLaunchKernelGGL(k_fwd_shadow, dim3(nblk(n, kShTile), c->nl), dim3(256), 0, c->stream, S, seed, s0, n,
                            c->hits, c->vis, c->ctr + 8 * kKernShadow);
         ev_record(c, 9 + 2 * kKernShadow);
         ev_record(c, 8 + 2 * kKernShade);
@@ -1477,7 +1585,7 @@ int fr_backward(fr_ctx *c, const float *dLdI, const fr_grads *g) {
         if (!c->records_valid) {   // recompute this chunk's hit records and visibility
             hipLaunchKernelGGL(k_fwd_camera, dim3(nblk(n, 256)), dim3(256), 0, c->stream, S, c->last_seed,
                                c->last_spp, s0, n, c->hits, c->vis, c->ctr + 8 * kKernAdj);
-            hipLaunchKernelGGL(k_fwd_shadow, dim3(nblk(n, 256), c->nl), dim3(256), 0, c->stream, S, c->last_seed,
+            hipLaunchKernelGGL(k_fwd_shadow, dim3(nblk(n, kShTile), c->nl), dim3(256), 0, c->stream, S, c->last_seed,
                                s0, n, c->hits, c->vis, c->ctr + 8 * kKernAdj);
         }
         ev_record(c, 8 + 2 * kKernAdj);
@@ -1487,7 +1595,7 @@ int fr_backward(fr_ctx *c, const float *dLdI, const fr_grads *g) {
         ev_record(c, 9 + 2 * kKernAdj);
         ev_record(c, 8 + 2 * kKernSecondary);
         if (c->terms & FR_TERM_SECONDARY)
-            hipLaunchKernelGGL(k_edge_secondary, dim3(nblk(n, 256), c->nl), dim3(256), lds1, c->stream, S,
+            hipLaunchKernelGGL(k_edge_secondary, dim3(nblk(n, kShTile), c->nl), dim3(256), lds1, c->stream, S,
                                c->last_seed, c->last_spp, s0, n, dLdI, c->hits, c->g_pos, c->ctr + 8 * kKernSecondary);
         ev_record(c, 9 + 2 * kKernSecondary);
     }
@@ -1497,7 +1605,7 @@ int fr_backward(fr_ctx *c, const float *dLdI, const fr_grads *g) {
         hipLaunchKernelGGL(k_zero_d, dim3(nblk(6 * (size_t)M, 256)), dim3(256), 0, c->stream, c->pe_f, 6 * (size_t)M);
         hipLaunchKernelGGL(k_edge_primary_setup, dim3(nblk(M, 256)), dim3(256), 0, c->stream,
                            S, c->last_seed, M, c->pe_samples, c->pe_hits, c->ctr + 8 * kKernPrimary);
-        hipLaunchKernelGGL(k_edge_primary_shade, dim3(nblk((size_t)M * 2 * c->nl, 256)), dim3(256), lds1, c->stream,
+        hipLaunchKernelGGL(k_edge_primary_shade, dim3(nblk((size_t)2 * M, kShTile), c->nl), dim3(256), lds1, c->stream,
                            S, c->last_seed, M, c->pe_samples, c->pe_hits, c->pe_f, c->ctr + 8 * kKernPrimary);
         hipLaunchKernelGGL(k_edge_primary_scatter, dim3(nblk(M, 256)), dim3(256), 0, c->stream,
                            S, M, dLdI, c->pe_samples, c->pe_f, c->g_pos);

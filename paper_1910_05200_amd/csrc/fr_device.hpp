@@ -77,7 +77,7 @@ struct Scene {
     const float *nrm;          // [3][V]
     const float *alb;          // [3][V]
     const float *uv;           // [2][V]
-    const float4 *nodes;       // [2 n_nodes]: (lo, escape) (hi, leaf)
+    const uint4 *nodes;        // [n_nodes]: fp16 box + link (see QNode below)
     const float4 *tris;        // [3 F]: v0 v1 v2, original index
     const float *lgeom;        // [nl][12]
     const float *lrgb;         // [nl][3]
@@ -133,7 +133,42 @@ __device__ __forceinline__ bool ray_tri(v3 o, v3 d, v3 v0, v3 v1, v3 v2, float t
 // ---------------------------------------------------------- traversal ----
 // The BVH is stored in depth-first order with escape links: after an
 // internal node comes its left subtree; a miss (or a leaf) jumps to the
-// escape index.  No stack is needed.
+// escape index (a leaf's is the next node).  No stack is needed.
+//
+// A node is 16 bytes, one vector load: its box as six binary16 values,
+// lo rounded toward -inf and hi toward +inf so that the stored box always
+// contains the fp32 one, and a link word: >= 0 the escape index of an
+// internal node, < 0 the complement of a leaf's triangle slot.  Boxes only
+// cull, so a box that is slightly larger changes the work, never a result.
+__device__ __forceinline__ float h2f(uint32_t bits16) {
+    return (float)__builtin_bit_cast(_Float16, (uint16_t)bits16);
+}
+// binary16 bits of x rounded toward +inf (up) or -inf (down)
+__device__ __forceinline__ uint32_t f2h_dir(float x, bool up) {
+    _Float16 h = (_Float16)x;
+    float b = (float)h;
+    uint32_t u = __builtin_bit_cast(uint16_t, h);
+    bool neg = (u & 0x8000u) != 0;
+    if (up && b < x) u = neg ? u - 1u : u + 1u;              // b < x: x > 0 or |b| > |x|
+    else if (!up && b > x) u = neg ? u + 1u : (u == 0u ? 0x8001u : u - 1u);
+    return u;
+}
+struct QBox { float lx, ly, lz, hx, hy, hz; };
+__device__ __forceinline__ QBox qbox(uint4 q) {
+    QBox b;
+    b.lx = h2f(q.x & 0xffffu); b.ly = h2f(q.x >> 16); b.lz = h2f(q.y & 0xffffu);
+    b.hx = h2f(q.y >> 16); b.hy = h2f(q.z & 0xffffu); b.hz = h2f(q.z >> 16);
+    return b;
+}
+__device__ __forceinline__ uint4 qnode(float lx, float ly, float lz, float hx, float hy, float hz, int link) {
+    uint4 q;
+    q.x = f2h_dir(lx, false) | (f2h_dir(ly, false) << 16);
+    q.y = f2h_dir(lz, false) | (f2h_dir(hx, true) << 16);
+    q.z = f2h_dir(hy, true) | (f2h_dir(hz, true) << 16);
+    q.w = (uint32_t)link;
+    return q;
+}
+
 struct Ray {
     v3 o, d, id;   // origin, direction, 1/direction (tiny components clamped)
 };
@@ -144,10 +179,10 @@ __device__ __forceinline__ Ray make_ray(v3 o, v3 d) {
     Ray r; r.o = o; r.d = d; r.id = mk(safe_inv(d.x), safe_inv(d.y), safe_inv(d.z));
     return r;
 }
-__device__ __forceinline__ bool slab(const Ray &r, float4 a, float4 b, float thi) {
-    float tx0 = (a.x - r.o.x) * r.id.x, tx1 = (b.x - r.o.x) * r.id.x;
-    float ty0 = (a.y - r.o.y) * r.id.y, ty1 = (b.y - r.o.y) * r.id.y;
-    float tz0 = (a.z - r.o.z) * r.id.z, tz1 = (b.z - r.o.z) * r.id.z;
+__device__ __forceinline__ bool slab(const Ray &r, const QBox &b, float thi) {
+    float tx0 = (b.lx - r.o.x) * r.id.x, tx1 = (b.hx - r.o.x) * r.id.x;
+    float ty0 = (b.ly - r.o.y) * r.id.y, ty1 = (b.hy - r.o.y) * r.id.y;
+    float tz0 = (b.lz - r.o.z) * r.id.z, tz1 = (b.hz - r.o.z) * r.id.z;
     float tn = fmaxf(fmaxf(fminf(tx0, tx1), fminf(ty0, ty1)), fmaxf(fminf(tz0, tz1), 0.0f));
     float tf = fminf(fminf(fmaxf(tx0, tx1), fmaxf(ty0, ty1)), fminf(fmaxf(tz0, tz1), thi));
     return tn <= tf * kSlabGrow;
@@ -163,11 +198,12 @@ __device__ inline Hit trace_closest(const Scene &S, v3 o, v3 d, Work &wk) {
     Hit h; h.tri = -1; h.t = INFINITY; h.b1 = h.b2 = h.det = 0.0f;
     int node = 0;
     while (node < S.n_nodes) {
-        float4 a = S.nodes[2 * node], b = S.nodes[2 * node + 1];
-        int esc = __float_as_int(a.w), leaf = __float_as_int(b.w);
+        uint4 q = S.nodes[node];
+        int link = (int)q.w;
         ++wk.box;
-        if (slab(r, a, b, h.t)) {
-            if (leaf >= 0) {
+        if (slab(r, qbox(q), h.t)) {
+            if (link < 0) {
+                int leaf = ~link;
                 float4 q0 = S.tris[3 * leaf], q1 = S.tris[3 * leaf + 1], q2 = S.tris[3 * leaf + 2];
                 v3 v0 = mk(q0.x, q0.y, q0.z), v1 = mk(q0.w, q1.x, q1.y), v2 = mk(q1.z, q1.w, q2.x);
                 int id = __float_as_int(q2.y);
@@ -176,12 +212,10 @@ __device__ inline Hit trace_closest(const Scene &S, v3 o, v3 d, Work &wk) {
                 if (ray_tri(o, d, v0, v1, v2, 0.0f, INFINITY, t, b1, b2, det)) {
                     if (t < h.t || (t == h.t && id < h.tri)) { h.tri = id; h.t = t; h.b1 = b1; h.b2 = b2; h.det = det; }
                 }
-                node = esc;
-            } else {
-                node = node + 1;
             }
+            node = node + 1;
         } else {
-            node = esc;
+            node = link < 0 ? node + 1 : link;
         }
     }
     return h;
@@ -192,11 +226,12 @@ __device__ inline bool trace_any(const Scene &S, v3 o, v3 d, int skip, Work &wk)
     Ray r = make_ray(o, d);
     int node = 0;
     while (node < S.n_nodes) {
-        float4 a = S.nodes[2 * node], b = S.nodes[2 * node + 1];
-        int esc = __float_as_int(a.w), leaf = __float_as_int(b.w);
+        uint4 q = S.nodes[node];
+        int link = (int)q.w;
         ++wk.box;
-        if (slab(r, a, b, 1.0f)) {
-            if (leaf >= 0) {
+        if (slab(r, qbox(q), 1.0f)) {
+            if (link < 0) {
+                int leaf = ~link;
                 float4 q0 = S.tris[3 * leaf], q1 = S.tris[3 * leaf + 1], q2 = S.tris[3 * leaf + 2];
                 int id = __float_as_int(q2.y);
                 if (id != skip) {
@@ -205,12 +240,10 @@ __device__ inline bool trace_any(const Scene &S, v3 o, v3 d, int skip, Work &wk)
                     ++wk.tri;
                     if (ray_tri(o, d, v0, v1, v2, kShadowTmin, kShadowTmax, t, b1, b2, det)) return true;
                 }
-                node = esc;
-            } else {
-                node = node + 1;
             }
+            node = node + 1;
         } else {
-            node = esc;
+            node = link < 0 ? node + 1 : link;
         }
     }
     return false;
