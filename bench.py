@@ -26,11 +26,12 @@ if ROOT not in sys.path:
 METRIC = "fwd+bwd ms/iter & Mrays/s at 256x256; denoised-2spp vs plain-256spp at equal PSNR"
 
 # Algorithmic VALU work per unit, counted as gfx950 VALU instructions (one
-# lane operation each) in the compiled code of each piece (probe kernels,
-# address arithmetic excluded): a slab test of one BVH node, one full
-# ray/triangle test with its hit-box check, one light sample's shading, and
-# one light sample's shading plus reverse-mode adjoint.
-OPS_BOX = 26
+# lane operation each) in the compiled code of each piece (address
+# arithmetic excluded): one BVH node test (six binary16 -> fp32 conversions
+# and the slab test), one full ray/triangle test with its hit-box check, one
+# light sample's shading, and one light sample's shading plus reverse-mode
+# adjoint.
+OPS_BOX = 30
 OPS_TRI = 95
 OPS_SHADE_FWD = 215
 OPS_SHADE_ADJ = 590
@@ -43,7 +44,7 @@ def profiled_traffic(kernel: str, workload: str):
     """HBM bytes per launch from the committed rocprofv3 PMC summary, or None
     when the kernel sources changed since the counters were taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.md")
+    path = os.path.join(ROOT, "profiles", f"fwd_bwd_{workload}_traffic.md")
     if not os.path.exists(path):
         return None
     src = b"".join(open(os.path.join(ROOT, "paper_1910_05200_amd", "csrc", f), "rb").read()
