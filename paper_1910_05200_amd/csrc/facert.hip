@@ -6,9 +6,11 @@
 // on its own, see fr_device.hpp).
 //
 // Per evaluation (fr_render):
-//   k_blend          morphable model (Face Modeling paragraph), fp64 sums
+//   k_blend, k_pose  morphable model and pose (Face Modeling paragraph),
+//                    fp64 sums
 //   k_normals        vertex normals, fixed-order gather over incident faces
-//   k_refit          BVH boxes bottom-up (tree order fixed at creation)
+//   k_refit_sub, k_refit_top  BVH boxes bottom-up (tree shape fixed at
+//                    creation)
 //   k_edge_weights   camera-silhouette and per-light shadow-candidate edges
 //   k_edge_scan      integer CDFs of the edge weights (one block per table)
 //   k_render_fwd     one lane per camera sample: closest hit, 20 lights,
@@ -42,37 +44,49 @@ using namespace fr;
 
 // ---------------------------------------------------------- blend -------
 // v_model = mean + sum_k B_id[k] alpha_k + sum_k B_exp[k] beta_k  (fp64,
-// k ascending, identity first); v = R v_model + t (fp64); A = alb_mean +
-// sum_k B_alb[k] delta_k (fp64).  Rounded to fp32.  One thread per vertex;
-// the k-loop reads one row of each basis, coalesced across the wave.
+// k ascending, identity first); A = alb_mean + sum_k B_alb[k] delta_k
+// (fp64).  One thread per (row, vertex), rows x, y, z of the geometry and
+// r, g, b of the albedo on the grid's y axis, so that the 20k-vertex model
+// spreads over ~1900 blocks; each k step reads one contiguous basis row,
+// coalesced across the wave.  The geometry rows keep their fp64 sums for
+// k_pose: v = R v_model + t (fp64).  Everything is rounded to fp32 once.
 struct PoseArgs { double R[9]; double t[3]; };
 
-__global__ __launch_bounds__(256) void k_blend(int V, int n_id, int n_exp, int n_alb,
+__global__ __launch_bounds__(64) void k_blend(int V, int n_id, int n_exp, int n_alb,
         const float *__restrict__ mean, const float *__restrict__ b_id, const float *__restrict__ b_exp,
         const float *__restrict__ alb_mean, const float *__restrict__ b_alb,
         const float *__restrict__ alpha, const float *__restrict__ beta, const float *__restrict__ delta,
-        PoseArgs P, float *__restrict__ vmodel, float *__restrict__ pos, float *__restrict__ alb) {
+        double *__restrict__ vm_d, float *__restrict__ vmodel, float *__restrict__ alb) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int row = blockIdx.y;
     if (i >= V) return;
     size_t V3 = (size_t)3 * V;
-    double m[3];
-    for (int c = 0; c < 3; ++c) {
-        size_t e = (size_t)c * V + i;
+    if (row < 3) {
+        size_t e = (size_t)row * V + i;
         double acc = (double)mean[e];
+#pragma unroll 8
         for (int k = 0; k < n_id; ++k) acc = acc + (double)b_id[k * V3 + e] * (double)alpha[k];
+#pragma unroll 8
         for (int k = 0; k < n_exp; ++k) acc = acc + (double)b_exp[k * V3 + e] * (double)beta[k];
-        m[c] = acc;
+        vm_d[e] = acc;
         vmodel[e] = (float)acc;
+    } else {
+        size_t e = (size_t)(row - 3) * V + i;
+        double acc = (double)alb_mean[e];
+#pragma unroll 8
+        for (int k = 0; k < n_alb; ++k) acc = acc + (double)b_alb[k * V3 + e] * (double)delta[k];
+        alb[e] = (float)acc;
     }
+}
+
+__global__ __launch_bounds__(256) void k_pose(int V, const double *__restrict__ vm_d, PoseArgs P,
+                                              float *__restrict__ pos) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= V) return;
+    double m[3] = {vm_d[i], vm_d[V + i], vm_d[2 * (size_t)V + i]};
     for (int c = 0; c < 3; ++c) {
         double v = ((P.R[3 * c] * m[0] + P.R[3 * c + 1] * m[1]) + P.R[3 * c + 2] * m[2]) + P.t[c];
         pos[(size_t)c * V + i] = (float)v;
-    }
-    for (int c = 0; c < 3; ++c) {
-        size_t e = (size_t)c * V + i;
-        double acc = (double)alb_mean[e];
-        for (int k = 0; k < n_alb; ++k) acc = acc + (double)b_alb[k * V3 + e] * (double)delta[k];
-        alb[e] = (float)acc;
     }
 }
 
@@ -101,41 +115,54 @@ __global__ __launch_bounds__(256) void k_normals(int V, const int *__restrict__ 
 }
 
 // ------------------------------------------------------------ refit -----
-// Leaf boxes from the current triangles, then unions up the tree: the
-// second child to finish (odd arrival count; counts only grow, so no reset
-// is needed between evaluations) builds its parent's box.
-__global__ __launch_bounds__(256) void k_refit(int F, const int *__restrict__ faces, const float *__restrict__ pos, int V,
-        const int *__restrict__ sorted_tri, const int *__restrict__ leaf_node,
-        const int *__restrict__ parent, const int *__restrict__ right, const int *__restrict__ escape,
-        unsigned int *__restrict__ arrive, uint4 *nodes, float4 *__restrict__ tris) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= F) return;
-    int f = sorted_tri[i];
-    const int *t = faces + 3 * f;
-    v3 a = vpos_raw(pos, V, t[0]), b = vpos_raw(pos, V, t[1]), c = vpos_raw(pos, V, t[2]);
-    tris[3 * i] = make_float4(a.x, a.y, a.z, b.x);
-    tris[3 * i + 1] = make_float4(b.y, b.z, c.x, c.y);
-    tris[3 * i + 2] = make_float4(c.z, __int_as_float(f), 0.0f, 0.0f);
-    int n = leaf_node[i];
-    nodes[n] = qnode(fminf(fminf(a.x, b.x), c.x) - kBoxPad, fminf(fminf(a.y, b.y), c.y) - kBoxPad,
-                     fminf(fminf(a.z, b.z), c.z) - kBoxPad, fmaxf(fmaxf(a.x, b.x), c.x) + kBoxPad,
-                     fmaxf(fmaxf(a.y, b.y), c.y) + kBoxPad, fmaxf(fmaxf(a.z, b.z), c.z) + kBoxPad, ~i);
-    __threadfence();
-    int p = parent[n];
-    while (p >= 0) {
-        unsigned int old = atomicAdd(&arrive[p], 1u);
-        if ((old & 1u) == 0u) return;            // first child: the sibling continues
-        __threadfence();
-        const volatile uint4 *vn = nodes;
-        int l = p + 1, r = right[p];
-        uint4 ql, qr;
-        ql.x = vn[l].x; ql.y = vn[l].y; ql.z = vn[l].z;
-        qr.x = vn[r].x; qr.y = vn[r].y; qr.z = vn[r].z;
-        QBox L = qbox(ql), R = qbox(qr);   // binary16 values: the union re-encodes exactly
-        nodes[p] = qnode(fminf(L.lx, R.lx), fminf(L.ly, R.ly), fminf(L.lz, R.lz),
-                         fmaxf(L.hx, R.hx), fmaxf(L.hy, R.hy), fmaxf(L.hz, R.hz), escape[p]);
-        __threadfence();
-        p = parent[p];
+// The tree's shape is fixed at creation; every evaluation recomputes its
+// boxes.  The tree is cut into subtrees of at most kRefitLeaves leaves (a
+// node range and a slot range each, depth-first layout) and the few nodes
+// above them.  k_refit_sub: one block per subtree writes the triangle
+// records and leaf boxes of its slots, then the internal boxes one height
+// at a time with a block barrier between heights.  k_refit_top: one block,
+// the top nodes by height.  No atomics and no device-wide fences.
+constexpr int kRefitLeaves = 512;
+struct SubTree { int node, slot, count, height; };
+
+__device__ __forceinline__ void refit_union(uint4 *nodes, int n, int r, int esc) {
+    QBox L = qbox(nodes[n + 1]), R = qbox(nodes[r]);   // binary16 values: the union re-encodes exactly
+    nodes[n] = qnode(fminf(L.lx, R.lx), fminf(L.ly, R.ly), fminf(L.lz, R.lz),
+                     fmaxf(L.hx, R.hx), fmaxf(L.hy, R.hy), fmaxf(L.hz, R.hz), esc);
+}
+
+__global__ __launch_bounds__(256) void k_refit_sub(const SubTree *__restrict__ subs, const int *__restrict__ faces,
+        const float *__restrict__ pos, int V, const int *__restrict__ sorted_tri, const int *__restrict__ leaf_node,
+        const int *__restrict__ height, const int *__restrict__ right, const int *__restrict__ escape,
+        uint4 *nodes, float4 *__restrict__ tris) {
+    const SubTree st = subs[blockIdx.x];
+    for (int i = st.slot + threadIdx.x; i < st.slot + st.count; i += blockDim.x) {
+        int f = sorted_tri[i];
+        const int *t = faces + 3 * f;
+        v3 a = vpos_raw(pos, V, t[0]), b = vpos_raw(pos, V, t[1]), c = vpos_raw(pos, V, t[2]);
+        tris[3 * i] = make_float4(a.x, a.y, a.z, b.x);
+        tris[3 * i + 1] = make_float4(b.y, b.z, c.x, c.y);
+        tris[3 * i + 2] = make_float4(c.z, __int_as_float(f), 0.0f, 0.0f);
+        nodes[leaf_node[i]] = qnode(fminf(fminf(a.x, b.x), c.x) - kBoxPad, fminf(fminf(a.y, b.y), c.y) - kBoxPad,
+                                    fminf(fminf(a.z, b.z), c.z) - kBoxPad, fmaxf(fmaxf(a.x, b.x), c.x) + kBoxPad,
+                                    fmaxf(fmaxf(a.y, b.y), c.y) + kBoxPad, fmaxf(fmaxf(a.z, b.z), c.z) + kBoxPad, ~i);
+    }
+    const int n_end = st.node + 2 * st.count - 1;
+    for (int h = 1; h <= st.height; ++h) {
+        __syncthreads();
+        for (int n = st.node + threadIdx.x; n < n_end; n += blockDim.x)
+            if (height[n] == h) refit_union(nodes, n, right[n], escape[n]);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_refit_top(int n_top, const int *__restrict__ top, const int *__restrict__ top_off,
+        int top_levels, const int *__restrict__ right, const int *__restrict__ escape, uint4 *nodes) {
+    for (int lv = 0; lv < top_levels; ++lv) {
+        for (int k = top_off[lv] + threadIdx.x; k < top_off[lv + 1]; k += blockDim.x) {
+            int n = top[k];
+            refit_union(nodes, n, right[n], escape[n]);
+        }
+        __syncthreads();
     }
 }
 
@@ -150,11 +177,10 @@ __device__ __forceinline__ bool project(const Scene &S, v3 x, float &sx, float &
 }
 
 // weights: table 0 = camera silhouettes (screen length), table 1+j = shadow
-// candidates of light j (3D length); the max of each table via atomicMax
-// on the (non-negative) float bits.
+// candidates of light j (3D length).
 __global__ __launch_bounds__(256) void k_edge_weights(Scene S, const float *__restrict__ lgeom,
-        float *__restrict__ w, unsigned int *__restrict__ wmax) {
-    int e = blockIdx.x * blockDim.x + threadIdx.x;
+        float *__restrict__ w) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= S.E) return;
     const int *ed = S.edges + 4 * e;
     v3 a = vpos(S, ed[0]), b = vpos(S, ed[1]);
@@ -177,7 +203,6 @@ __global__ __launch_bounds__(256) void k_edge_weights(Scene S, const float *__re
         we = sqrtf(dx * dx + dy * dy);
     }
     w[e] = we;
-    atomicMax(&wmax[0], __float_as_uint(we));
     v3 ab = b - a;
     float l3 = sqrtf(dot(ab, ab));
     for (int j = 0; j < S.nl; ++j) {
@@ -194,57 +219,76 @@ __global__ __launch_bounds__(256) void k_edge_weights(Scene S, const float *__re
             }
             cand = posc > 0 && negc > 0;
         }
-        float wj = cand ? l3 : 0.0f;
-        w[(size_t)(1 + j) * E + e] = wj;
-        atomicMax(&wmax[1 + j], __float_as_uint(wj));
+        w[(size_t)(1 + j) * E + e] = cand ? l3 : 0.0f;
     }
 }
 
-// One block per table: quantise q = 1 + floor(w / wmax * 2^20) for w > 0,
-// exclusive uint64 prefix in edge order, compacted to (edge, prefix) pairs.
+// One block per table: the table's max weight wmax (block reduction), then
+// q = 1 + floor(w / wmax * 2^20) for w > 0, exclusive uint64 prefix in edge
+// order, compacted to (edge, prefix) pairs.
+// Each thread takes kScanIt consecutive edges; thread sums are scanned
+// within the wave by shuffles and across the block's waves in LDS (integer
+// sums: the grouping does not change them).
+constexpr int kScanIt = 4;
 template <int BS>
-__global__ __launch_bounds__(BS) void k_edge_scan(int E, const float *__restrict__ w, const unsigned int *__restrict__ wmax,
-        int *__restrict__ out_edge, uint64_t *__restrict__ out_prefix, int *__restrict__ out_n, uint64_t *__restrict__ out_Q) {
-    int tbl = blockIdx.x;
+__global__ __launch_bounds__(BS) void k_edge_scan(int E, const float *__restrict__ w, int *__restrict__ out_edge, uint64_t *__restrict__ out_prefix, int *__restrict__ out_n, uint64_t *__restrict__ out_Q) {
+    constexpr int NW = BS / 64;
+    const int tbl = blockIdx.x;
     const float *wt = w + (size_t)tbl * E;
     int *oe = out_edge + (size_t)tbl * E;
     uint64_t *op = out_prefix + (size_t)tbl * E;
-    float wm = __uint_as_float(wmax[tbl]);
-    __shared__ uint64_t s_sum[BS];
-    __shared__ int s_cnt[BS];
-    __shared__ uint64_t s_base;
-    __shared__ int s_nbase;
-    if (threadIdx.x == 0) { s_base = 0; s_nbase = 0; }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __shared__ uint64_t s_wsum[NW];
+    __shared__ int s_wcnt[NW];
+    __shared__ float s_wmax[NW];
+    float mx = 0.0f;
+    for (int e = threadIdx.x; e < E; e += BS) mx = fmaxf(mx, wt[e]);
+    for (int off = 32; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off));
+    if (lane == 0) s_wmax[wave] = mx;
     __syncthreads();
-    for (int start = 0; start < E; start += BS) {
-        int e = start + threadIdx.x;
-        uint64_t q = 0;
-        if (e < E) {
-            float we = wt[e];
-            if (we > 0.0f && wm > 0.0f) q = 1u + (uint32_t)floorf((we / wm) * kQScale);
+    float wm = 0.0f;
+    for (int k = 0; k < NW; ++k) wm = fmaxf(wm, s_wmax[k]);
+    uint64_t base = 0;    // running totals, identical in every thread
+    int nbase = 0;
+    for (int start = 0; start < E; start += BS * kScanIt) {
+        const int e0 = start + threadIdx.x * kScanIt;
+        uint32_t q[kScanIt];
+        uint64_t tsum = 0;
+        int tcnt = 0;
+        for (int k = 0; k < kScanIt; ++k) {
+            q[k] = 0;
+            int e = e0 + k;
+            if (e < E) {
+                float we = wt[e];
+                if (we > 0.0f && wm > 0.0f) q[k] = 1u + (uint32_t)floorf((we / wm) * kQScale);
+            }
+            tsum += q[k];
+            tcnt += q[k] > 0;
         }
-        s_sum[threadIdx.x] = q;
-        s_cnt[threadIdx.x] = q > 0;
+        uint64_t isum = tsum;
+        int icnt = tcnt;
+        for (int off = 1; off < 64; off <<= 1) {
+            uint64_t vs = __shfl_up(isum, off);
+            int vc = __shfl_up(icnt, off);
+            if (lane >= off) { isum += vs; icnt += vc; }
+        }
+        if (lane == 63) { s_wsum[wave] = isum; s_wcnt[wave] = icnt; }
         __syncthreads();
-        // inclusive Hillis-Steele scan (integers: order-independent)
-        for (int off = 1; off < BS; off <<= 1) {
-            uint64_t v = threadIdx.x >= off ? s_sum[threadIdx.x - off] : 0;
-            int c = threadIdx.x >= off ? s_cnt[threadIdx.x - off] : 0;
-            __syncthreads();
-            s_sum[threadIdx.x] += v;
-            s_cnt[threadIdx.x] += c;
-            __syncthreads();
+        uint64_t wsum = 0, total = 0;
+        int wcnt = 0, tc = 0;
+        for (int k = 0; k < NW; ++k) {
+            if (k < wave) { wsum += s_wsum[k]; wcnt += s_wcnt[k]; }
+            total += s_wsum[k]; tc += s_wcnt[k];
         }
-        if (q > 0) {
-            int slot = s_nbase + s_cnt[threadIdx.x] - 1;
-            oe[slot] = e;
-            op[slot] = s_base + s_sum[threadIdx.x] - q;
-        }
-        __syncthreads();
-        if (threadIdx.x == BS - 1) { s_base += s_sum[BS - 1]; s_nbase += s_cnt[BS - 1]; }
+        uint64_t pre = base + wsum + isum - tsum;
+        int slot = nbase + wcnt + icnt - tcnt;
+        for (int k = 0; k < kScanIt; ++k)
+            if (q[k] > 0) { oe[slot] = e0 + k; op[slot] = pre; pre += q[k]; ++slot; }
+        base += total;
+        nbase += tc;
         __syncthreads();
     }
-    if (threadIdx.x == 0) { out_n[tbl] = s_nbase; out_Q[tbl] = s_base; }
+    if (threadIdx.x == 0) { out_n[tbl] = nbase; out_Q[tbl] = base; }
 }
 
 // ------------------------------------------------------ LDS staging -----
@@ -1102,13 +1146,15 @@ struct fr_ctx {
     float *mean = nullptr, *b_id = nullptr, *b_exp = nullptr, *alb_mean = nullptr, *b_alb = nullptr, *uv = nullptr;
     float *lgeom = nullptr;
     // tree order (device)
-    int *sorted_tri = nullptr, *leaf_node = nullptr, *parent = nullptr, *right = nullptr, *escape = nullptr;
-    unsigned int *arrive = nullptr;
+    int *sorted_tri = nullptr, *leaf_node = nullptr, *right = nullptr, *escape = nullptr;
+    SubTree *subs = nullptr; int n_subs = 0;
+    int *height = nullptr, *top = nullptr, *top_off = nullptr; int n_top = 0, top_levels = 0;
     uint4 *nodes = nullptr;
     float4 *tris = nullptr;
     // per evaluation (device)
+    double *vm_d = nullptr;
     float *vmodel = nullptr, *pos = nullptr, *nrm = nullptr, *nlen = nullptr, *alb = nullptr;
-    float *ew = nullptr; unsigned int *ewmax = nullptr;
+    float *ew = nullptr;
     int *tbl_edge = nullptr, *tbl_n = nullptr; uint64_t *tbl_prefix = nullptr, *tbl_Q = nullptr;
     float *samples = nullptr; size_t samples_cap = 0;
     HitRec *hits = nullptr; unsigned long long *vis = nullptr; size_t rec_cap = 0;
@@ -1204,6 +1250,8 @@ static void drotation(const float pose[6], double out[27]) {
 // ---- topology: edges, vertex->face lists, LBVH tree order -------------
 struct HostTopo {
     std::vector<int> edges, vf_off, vf_idx, sorted_tri, leaf_node, parent, right, escape;
+    std::vector<int> height, top, top_off;   // refit schedule
+    std::vector<SubTree> subs;
     int n_nodes = 0;
 };
 
@@ -1351,6 +1399,35 @@ static bool build_topology(const fr_model_desc *m, HostTopo &T) {
     T.leaf_node.assign(F, 0);
     sah_rec(bb, cen, perm, 0, F, 0, -1, T);
     T.sorted_tri = perm;
+    // refit schedule: heights, leaf counts and first slots (children follow
+    // their parent in depth-first order, so one backward pass suffices)
+    int NN = T.n_nodes;
+    std::vector<int> lcnt(NN, 1), slo(NN, 0);
+    T.height.assign(NN, 0);
+    for (int i = 0; i < F; ++i) slo[T.leaf_node[i]] = i;
+    for (int n = NN - 1; n >= 0; --n)
+        if (T.right[n] >= 0) {
+            int l = n + 1, r = T.right[n];
+            T.height[n] = 1 + std::max(T.height[l], T.height[r]);
+            lcnt[n] = lcnt[l] + lcnt[r];
+            slo[n] = slo[l];
+        }
+    std::vector<std::vector<int>> lv;
+    for (int n = 0; n < NN; ++n) {
+        int p = T.parent[n];
+        if (lcnt[n] <= kRefitLeaves && (p < 0 || lcnt[p] > kRefitLeaves))
+            T.subs.push_back(SubTree{n, slo[n], lcnt[n], T.height[n]});
+        else if (lcnt[n] > kRefitLeaves) {
+            if ((int)lv.size() <= T.height[n]) lv.resize(T.height[n] + 1);
+            lv[T.height[n]].push_back(n);
+        }
+    }
+    T.top_off.assign(1, 0);
+    for (auto &l : lv) {
+        if (l.empty()) continue;
+        T.top.insert(T.top.end(), l.begin(), l.end());
+        T.top_off.push_back((int)T.top.size());
+    }
     return true;
 }
 
@@ -1393,6 +1470,7 @@ int fr_create(const fr_model_desc *m, const fr_scene_desc *s, uint32_t flags, fr
     c->V = m->n_vertices; c->F = m->n_faces; c->E = (int)(T.edges.size() / 4);
     c->n_id = m->n_id; c->n_exp = m->n_exp; c->n_alb = m->n_alb;
     c->W = s->width; c->H = s->height; c->nl = s->n_lights; c->res = s->spec_res; c->n_nodes = T.n_nodes;
+    c->n_subs = (int)T.subs.size(); c->n_top = (int)T.top.size(); c->top_levels = (int)T.top_off.size() - 1;
     for (int a = 0; a < 3; ++a) c->cam[a] = s->cam[a];
     c->ps = s->pix_scale;
     size_t V3 = 3 * (size_t)c->V;
@@ -1409,14 +1487,16 @@ int fr_create(const fr_model_desc *m, const fr_scene_desc *s, uint32_t flags, fr
         R(upload(c, &c->lgeom, s->light_geom, 12 * (size_t)c->nl)) ||
         R(upload(c, &c->sorted_tri, T.sorted_tri.data(), T.sorted_tri.size())) ||
         R(upload(c, &c->leaf_node, T.leaf_node.data(), T.leaf_node.size())) ||
-        R(upload(c, &c->parent, T.parent.data(), T.parent.size())) ||
         R(upload(c, &c->right, T.right.data(), T.right.size())) ||
         R(upload(c, &c->escape, T.escape.data(), T.escape.size())) ||
-        R(dalloc(c, &c->arrive, (size_t)c->n_nodes)) || R(dalloc(c, &c->nodes, (size_t)c->n_nodes)) ||
+        R(upload(c, &c->subs, T.subs.data(), T.subs.size())) || R(upload(c, &c->height, T.height.data(), T.height.size())) ||
+        R(upload(c, &c->top, T.top.empty() ? T.height.data() : T.top.data(), std::max<size_t>(1, T.top.size()))) ||
+        R(upload(c, &c->top_off, T.top_off.data(), T.top_off.size())) ||
+        R(dalloc(c, &c->nodes, (size_t)c->n_nodes)) ||
         R(dalloc(c, &c->tris, 3 * (size_t)c->F)) ||
-        R(dalloc(c, &c->vmodel, V3)) || R(dalloc(c, &c->pos, V3)) || R(dalloc(c, &c->nrm, V3)) ||
+        R(dalloc(c, &c->vmodel, V3)) || R(dalloc(c, &c->vm_d, V3)) || R(dalloc(c, &c->pos, V3)) || R(dalloc(c, &c->nrm, V3)) ||
         R(dalloc(c, &c->nlen, (size_t)c->V)) || R(dalloc(c, &c->alb, V3)) ||
-        R(dalloc(c, &c->ew, (size_t)(1 + c->nl) * c->E)) || R(dalloc(c, &c->ewmax, (size_t)(1 + c->nl))) ||
+        R(dalloc(c, &c->ew, (size_t)(1 + c->nl) * c->E)) ||
         R(dalloc(c, &c->tbl_edge, (size_t)(1 + c->nl) * c->E)) || R(dalloc(c, &c->tbl_prefix, (size_t)(1 + c->nl) * c->E)) ||
         R(dalloc(c, &c->tbl_n, (size_t)(1 + c->nl))) || R(dalloc(c, &c->tbl_Q, (size_t)(1 + c->nl))) ||
         R(dalloc(c, &c->ctr, 8 * kNumKern)) ||
@@ -1437,7 +1517,6 @@ int fr_create(const fr_model_desc *m, const fr_scene_desc *s, uint32_t flags, fr
         fr_destroy(c);
         return FR_ENOMEM;
     }
-    (void)hipMemset(c->arrive, 0, sizeof(unsigned int) * c->n_nodes);
     (void)hipMemset(c->ctr, 0, 8 * kNumKern * sizeof(unsigned long long));
     if (flags & FR_TIMING)
         for (int i = 0; i < kNumEvents; ++i) (void)hipEventCreate(&c->ev[i]);
@@ -1464,9 +1543,10 @@ static int blend_impl(fr_ctx *c, const float *alpha, const float *beta, const fl
     rotation(pose, c->pose.R);
     for (int k = 0; k < 3; ++k) c->pose.t[k] = (double)pose[3 + k];
     drotation(pose, c->drot.dR);
-    hipLaunchKernelGGL(k_blend, dim3(nblk(c->V, 256)), dim3(256), 0, c->stream, c->V, c->n_id, c->n_exp, c->n_alb,
-                       c->mean, c->b_id, c->b_exp, c->alb_mean, c->b_alb, alpha, beta, delta, c->pose,
-                       c->vmodel, c->pos, c->alb);
+    hipLaunchKernelGGL(k_blend, dim3(nblk(c->V, 64), 6), dim3(64), 0, c->stream, c->V, c->n_id, c->n_exp, c->n_alb,
+                       c->mean, c->b_id, c->b_exp, c->alb_mean, c->b_alb, alpha, beta, delta,
+                       c->vm_d, c->vmodel, c->alb);
+    hipLaunchKernelGGL(k_pose, dim3(nblk(c->V, 256)), dim3(256), 0, c->stream, c->V, c->vm_d, c->pose, c->pos);
     hipLaunchKernelGGL(k_normals, dim3(nblk(c->V, 256)), dim3(256), 0, c->stream, c->V, c->faces, c->vf_off, c->vf_idx,
                        c->pos, c->nrm, c->nlen);
     HIPCK(c, hipGetLastError());
@@ -1526,13 +1606,15 @@ int fr_render(fr_ctx *c, const fr_params *p, uint64_t seed, int32_t spp, float *
     int r = blend_impl(c, p->alpha, p->beta, p->delta, p->pose);
     if (r) return r;
     ev_record(c, 1);
-    hipLaunchKernelGGL(k_refit, dim3(nblk(c->F, 256)), dim3(256), 0, c->stream, c->F, c->faces, c->pos, c->V,
-                       c->sorted_tri, c->leaf_node, c->parent, c->right, c->escape, c->arrive, c->nodes, c->tris);
+    hipLaunchKernelGGL(k_refit_sub, dim3(c->n_subs), dim3(256), 0, c->stream, c->subs, c->faces, c->pos, c->V,
+                       c->sorted_tri, c->leaf_node, c->height, c->right, c->escape, c->nodes, c->tris);
+    if (c->n_top > 0)
+        hipLaunchKernelGGL(k_refit_top, dim3(1), dim3(256), 0, c->stream, c->n_top, c->top, c->top_off,
+                           c->top_levels, c->right, c->escape, c->nodes);
     ev_record(c, 2);
     Scene S = make_scene(c);
-    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(128), 0, c->stream, c->ewmax, 1 + c->nl);
-    hipLaunchKernelGGL(k_edge_weights, dim3(nblk(c->E, 256)), dim3(256), 0, c->stream, S, c->lgeom, c->ew, c->ewmax);
-    hipLaunchKernelGGL(k_edge_scan<1024>, dim3(1 + c->nl), dim3(1024), 0, c->stream, c->E, c->ew, c->ewmax,
+    hipLaunchKernelGGL(k_edge_weights, dim3(nblk(c->E, 256)), dim3(256), 0, c->stream, S, c->lgeom, c->ew);
+    hipLaunchKernelGGL(k_edge_scan<1024>, dim3(1 + c->nl), dim3(1024), 0, c->stream, c->E, c->ew,
                        c->tbl_edge, c->tbl_prefix, c->tbl_n, c->tbl_Q);
     ev_record(c, 3);
     hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, c->stream, c->ctr, 8 * kKernAdj);
@@ -1685,8 +1767,8 @@ void fr_destroy(fr_ctx *c) {
     if (!c) return;
     if (c->stream) (void)hipStreamSynchronize(c->stream); else (void)hipDeviceSynchronize();
     void *ptrs[] = {c->faces, c->edges, c->vf_off, c->vf_idx, c->mean, c->b_id, c->b_exp, c->alb_mean, c->b_alb, c->uv,
-                    c->lgeom, c->sorted_tri, c->leaf_node, c->parent, c->right, c->escape, c->arrive, c->nodes, c->tris,
-                    c->vmodel, c->pos, c->nrm, c->nlen, c->alb, c->ew, c->ewmax, c->tbl_edge, c->tbl_prefix, c->tbl_n,
+                    c->lgeom, c->sorted_tri, c->leaf_node, c->right, c->escape, c->subs, c->height, c->top, c->top_off, c->nodes, c->tris,
+                    c->vmodel, c->vm_d, c->pos, c->nrm, c->nlen, c->alb, c->ew, c->tbl_edge, c->tbl_prefix, c->tbl_n,
                     c->tbl_Q, c->samples, c->ctr, c->g_light, c->g_spec, c->g_pos, c->g_nrm, c->g_alb, c->g_N,
                     c->g_vert, c->g_m, c->partial, c->loss_partial, c->hits, c->vis, c->pe_samples, c->pe_hits,
                     c->pe_f};
