@@ -637,12 +637,18 @@ using e3 = vec3<ER>;
 
 // Shadow-boundary (secondary) edge sample of light j at a camera sample's
 // shading point; decisions fp32, values in ER.
-// kTrace = false stops before the two shadow rays and only reports whether
-// the sample needs them; kTrace = true runs the whole sample.
-template <bool kTrace>
+// The shadow-boundary sample of light j at one camera sample, in one of
+// three modes that share the decisions:
+//   kSecPropose  stops before the two shadow rays; true when the sample
+//                needs them;
+//   kSecTrace    traces them; true when they disagree (the sample then has
+//                a value), vp = whether the + side sees the light;
+//   kSecValue    takes vp as given and scatters the sample's value.
+enum { kSecPropose, kSecTrace, kSecValue };
+template <int kMode>
 __device__ inline bool secondary_edge(const Scene &S, const Light &L, int j, uint64_t seed, uint32_t sidx,
                                       const float *spec_lds, v3 o, v3 dcam, const Hit &h, const SurfDec &sf,
-                                      const float *w, double *d_pos, uint32_t &n_rays, Work &steps) {
+                                      const float *w, double *d_pos, bool &vp, uint32_t &n_rays, Work &steps) {
     int n = S.se_n[j];
     uint64_t Q = S.se_Q[j];
     if (n == 0 || Q == 0) return false;
@@ -678,11 +684,13 @@ __device__ inline bool secondary_edge(const Scene &S, const Light &L, int j, uin
     v3 un = mk(mp.x / lm, mp.y / lm, mp.z / lm);
     v3 yp = mk(y.x + kEdgeOffM * un.x, y.y + kEdgeOffM * un.y, y.z + kEdgeOffM * un.z);
     v3 ym = mk(y.x - kEdgeOffM * un.x, y.y - kEdgeOffM * un.y, y.z - kEdgeOffM * un.z);
-    if (!kTrace) return true;
-    n_rays += 2;
-    bool vp = !trace_any(S, p, yp - p, h.tri, steps);
-    bool vm = !trace_any(S, p, ym - p, h.tri, steps);
-    if (vp == vm) return false;
+    if (kMode == kSecPropose) return true;
+    if (kMode == kSecTrace) {
+        n_rays += 2;
+        vp = !trace_any(S, p, yp - p, h.tri, steps);
+        bool vm = !trace_any(S, p, ym - p, h.tri, steps);
+        return vp != vm;
+    }
     // ---- value path
     Surf<ER> sd;
     surf_value<ER>(S, spec_lds, o, dcam, h, sf, sd);
@@ -732,14 +740,24 @@ __device__ __forceinline__ void sec_setup(const Scene &S, uint64_t seed, int spp
     }
 }
 
+// k_edge_secondary: decisions and the two shadow rays of each accepted
+// sample (compacted per block as above); the samples whose rays disagree
+// go to a global list as (chunk index | light << 24 | vp << 30).
+// k_edge_secondary_value: the value path of each listed sample.  Splitting
+// them keeps the fp64 value code's registers out of the traversal kernel.
 __global__ __launch_bounds__(256) void k_edge_secondary(Scene S, uint64_t seed, int spp, long long s0, long long n,
-        const float *__restrict__ dLdI, const HitRec *__restrict__ hits, double *d_pos, unsigned long long *ctr) {
-    extern __shared__ float dyn[];
+        const float *__restrict__ dLdI, const HitRec *__restrict__ hits, uint32_t *__restrict__ out,
+        uint32_t *__restrict__ out_n, unsigned long long *ctr) {
     __shared__ Light Ls[kMaxLights];
     __shared__ int q_i[kShTile];
     __shared__ int q_n;
-    float *spec_lds = dyn;
-    stage_tables(S, Ls, spec_lds);
+    for (int k = threadIdx.x; k < S.nl; k += blockDim.x) {
+        const float *g = S.lgeom + 12 * k;
+        Light L;
+        L.c = mk(g[0], g[1], g[2]); L.e1 = mk(g[3], g[4], g[5]); L.e2 = mk(g[6], g[7], g[8]);
+        L.n = mk(g[9], g[10], g[11]);
+        Ls[k] = L;
+    }
     if (threadIdx.x == 0) q_n = 0;
     __syncthreads();
     const int j = blockIdx.y;
@@ -747,6 +765,7 @@ __global__ __launch_bounds__(256) void k_edge_secondary(Scene S, uint64_t seed, 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     uint32_t n_sec = 0;
     Work wk;
+    bool vp = false;
     for (int k = 0; k < kShTile; k += 256) {
         const int li = k + (int)threadIdx.x;
         const long long i = base + li;
@@ -754,7 +773,8 @@ __global__ __launch_bounds__(256) void k_edge_secondary(Scene S, uint64_t seed, 
         if (i < n) {
             v3 o, d; float w[3]; Hit h; SurfDec sd; uint32_t s; bool live;
             sec_setup(S, seed, spp, s0, i, dLdI, hits, o, d, w, h, sd, s, live);
-            if (live) need = secondary_edge<false>(S, Ls[j], j, seed, s, spec_lds, o, d, h, sd, w, d_pos, n_sec, wk);
+            if (live)
+                need = secondary_edge<kSecPropose>(S, Ls[j], j, seed, s, nullptr, o, d, h, sd, w, nullptr, vp, n_sec, wk);
         }
         unsigned long long m = __ballot(need);
         int wbase = 0;
@@ -765,14 +785,44 @@ __global__ __launch_bounds__(256) void k_edge_secondary(Scene S, uint64_t seed, 
     __syncthreads();
     const int nq = q_n;
     for (int e = wave * 64 + lane; e - lane < nq; e += 256) {
+        bool val = false;
+        long long i = 0;
         if (e < nq) {
+            i = base + q_i[e];
             v3 o, d; float w[3]; Hit h; SurfDec sd; uint32_t s; bool live;
-            sec_setup(S, seed, spp, s0, base + q_i[e], dLdI, hits, o, d, w, h, sd, s, live);
-            secondary_edge<true>(S, Ls[j], j, seed, s, spec_lds, o, d, h, sd, w, d_pos, n_sec, wk);
+            sec_setup(S, seed, spp, s0, i, dLdI, hits, o, d, w, h, sd, s, live);
+            val = secondary_edge<kSecTrace>(S, Ls[j], j, seed, s, nullptr, o, d, h, sd, w, nullptr, vp, n_sec, wk);
         }
+        unsigned long long m = __ballot(val);
+        uint32_t obase = 0;
+        if (lane == 0 && m) obase = atomicAdd(out_n, (uint32_t)__popcll(m));
+        obase = (uint32_t)__shfl((int)obase, 0);
+        if (val) out[obase + lanes_below(m)] = (uint32_t)i | ((uint32_t)j << 24) | (vp ? 1u << 30 : 0u);
     }
     flush_count(ctr, 3, n_sec);
     flush_work(ctr, wk);
+}
+
+__global__ __launch_bounds__(256) void k_edge_secondary_value(Scene S, uint64_t seed, int spp, long long s0,
+        const float *__restrict__ dLdI, const HitRec *__restrict__ hits, const uint32_t *__restrict__ list,
+        const uint32_t *__restrict__ list_n, double *d_pos) {
+    extern __shared__ float dyn[];
+    __shared__ Light Ls[kMaxLights];
+    float *spec_lds = dyn;
+    stage_tables(S, Ls, spec_lds);
+    __syncthreads();
+    const uint32_t cnt = *list_n;
+    uint32_t n_dummy = 0;
+    Work wk;
+    for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < cnt; k += gridDim.x * blockDim.x) {
+        uint32_t q = list[k];
+        long long i = q & 0xffffffu;
+        int j = (q >> 24) & 63;
+        bool vp = (q >> 30) & 1u;
+        v3 o, d; float w[3]; Hit h; SurfDec sd; uint32_t s; bool live;
+        sec_setup(S, seed, spp, s0, i, dLdI, hits, o, d, w, h, sd, s, live);
+        secondary_edge<kSecValue>(S, Ls[j], j, seed, s, spec_lds, o, d, h, sd, w, d_pos, vp, n_dummy, wk);
+    }
 }
 
 // ---------------------------------------------- camera silhouettes -----
@@ -781,15 +831,17 @@ __global__ __launch_bounds__(256) void k_edge_secondary(Scene S, uint64_t seed, 
 //   k_edge_primary_setup  one lane per sample: pick the edge, the point q
 //                         on its projection, the two sides q +- offset; trace
 //                         both camera rays and keep the hits;
-//   k_edge_primary_shade  one block per (tile of sides, light): horizon
-//                         test, compaction, shadow ray and fp64 radiance of
-//                         that light, summed per side;
+//   k_edge_primary_vis    one block per (tile of sides, light): horizon
+//                         test, compaction, shadow ray, visibility bit;
+//   k_edge_primary_shade  one lane per side: fp64 radiance of its visible
+//                         lights;
 //   k_edge_primary_scatter one lane per sample: (f+ - f-) times the boundary
 //                         Jacobian into the edge's two endpoints.
 struct PeSample { int e, i, pix; float qx, qy; };
 
 __global__ __launch_bounds__(256) void k_edge_primary_setup(Scene S, uint64_t seed, int M,
-        PeSample *__restrict__ ps_out, Hit *__restrict__ hits, unsigned long long *ctr) {
+        PeSample *__restrict__ ps_out, Hit *__restrict__ hits, unsigned long long *__restrict__ pvis,
+        unsigned long long *ctr) {
     int m = blockIdx.x * blockDim.x + threadIdx.x;
     uint32_t n_cam = 0;
     Work wk;
@@ -830,6 +882,8 @@ __global__ __launch_bounds__(256) void k_edge_primary_setup(Scene S, uint64_t se
         ps_out[m] = ps;
         hits[2 * m] = hs[0];
         hits[2 * m + 1] = hs[1];
+        pvis[2 * m] = 0ull;
+        pvis[2 * m + 1] = 0ull;
     }
     flush_count(ctr, 0, n_cam);
     flush_work(ctr, wk);
@@ -868,17 +922,24 @@ __device__ __forceinline__ bool pe_light(const Scene &S, uint64_t seed, const Pe
     return above(sd, y);
 }
 
-// One block per (tile of kShTile sides, light): horizon tests, compaction
-// into an LDS list, then one shadow ray and the fp64 radiance per entry.
-__global__ __launch_bounds__(256) void k_edge_primary_shade(Scene S, uint64_t seed, int M,
-        const PeSample *__restrict__ ps_in, const Hit *__restrict__ hits, double *__restrict__ fbuf,
+// k_edge_primary_vis: one block per (tile of kShTile sides, light):
+// horizon tests, compaction into an LDS list, one shadow ray per entry, one
+// visibility bit per light in the side's mask.  k_edge_primary_shade: one
+// lane per side, the fp64 radiance of its visible lights summed in light
+// order (no atomics; the fp64 shading registers stay out of the traversal
+// kernel).
+__global__ __launch_bounds__(256) void k_edge_primary_vis(Scene S, uint64_t seed, int M,
+        const PeSample *__restrict__ ps_in, const Hit *__restrict__ hits, unsigned long long *__restrict__ pvis,
         unsigned long long *ctr) {
-    extern __shared__ float dyn[];
     __shared__ Light Ls[kMaxLights];
     __shared__ int q_i[kShTile];
     __shared__ int q_n;
-    float *spec_lds = dyn;
-    stage_tables(S, Ls, spec_lds);
+    for (int k = threadIdx.x; k < S.nl; k += blockDim.x) {
+        const float *g = S.lgeom + 12 * k;
+        Light L;
+        L.c = mk(g[0], g[1], g[2]); L.e1 = mk(g[3], g[4], g[5]); L.e2 = mk(g[6], g[7], g[8]);
+        Ls[k] = L;
+    }
     if (threadIdx.x == 0) q_n = 0;
     __syncthreads();
     const int j = blockIdx.y;
@@ -907,17 +968,47 @@ __global__ __launch_bounds__(256) void k_edge_primary_shade(Scene S, uint64_t se
             const int ms = base + q_i[e];
             v3 o, d, y; Hit h; SurfDec sd;
             pe_light(S, seed, ps_in, hits, L, j, ms, o, d, h, sd, y);
-            if (!trace_any(S, sd.p, y - sd.p, h.tri, wk)) {
-                Surf<ER> sv;
-                surf_value<ER>(S, spec_lds, o, d, h, sd, sv);
-                ER c[3];
-                shade_light<ER>(sv, L, cvt<ER>(y), light_branch(sd, L.n, y), nullptr, c, nullptr);
-                ++wk.shade;
-                for (int k = 0; k < 3; ++k) gadd(&fbuf[3 * ms + k], (double)c[k]);
-            }
+            if (!trace_any(S, sd.p, y - sd.p, h.tri, wk)) atomicOr(&pvis[ms], 1ull << j);
         }
     }
     flush_count(ctr, 2, n_sh);
+    flush_work(ctr, wk);
+}
+
+__global__ __launch_bounds__(256) void k_edge_primary_shade(Scene S, uint64_t seed, int M,
+        const PeSample *__restrict__ ps_in, const Hit *__restrict__ hits, const unsigned long long *__restrict__ pvis,
+        double *__restrict__ fbuf, unsigned long long *ctr) {
+    extern __shared__ float dyn[];
+    __shared__ Light Ls[kMaxLights];
+    float *spec_lds = dyn;
+    stage_tables(S, Ls, spec_lds);
+    __syncthreads();
+    const int ms = blockIdx.x * blockDim.x + threadIdx.x;
+    Work wk;
+    if (ms < 2 * M) {
+        unsigned long long mask = pvis[ms];
+        ER acc[3] = {(ER)0, (ER)0, (ER)0};
+        if (mask) {
+            v3 o, d, y; Hit h; SurfDec sd;
+            pe_light(S, seed, ps_in, hits, Ls[0], 0, ms, o, d, h, sd, y);   // o, d, h, sd
+            Surf<ER> sv;
+            surf_value<ER>(S, spec_lds, o, d, h, sd, sv);
+            LightRng rng(seed, (uint32_t)(ms >> 1), 2, 4);
+            while (mask) {
+                int j = __ffsll((long long)mask) - 1;
+                mask &= mask - 1;
+                float u, v;
+                rng.get(j, u, v);
+                const Light &L = Ls[j];
+                v3 yj = light_point(L, u, v);
+                ER c[3];
+                shade_light<ER>(sv, L, cvt<ER>(yj), light_branch(sd, L.n, yj), nullptr, c, nullptr);
+                ++wk.shade;
+                for (int k = 0; k < 3; ++k) acc[k] += c[k];
+            }
+        }
+        for (int k = 0; k < 3; ++k) fbuf[3 * ms + k] = (double)acc[k];
+    }
     flush_work(ctr, wk);
 }
 
@@ -1129,6 +1220,9 @@ __global__ __launch_bounds__(BS) void k_loss_final(int nb, const double *__restr
 // A render that fits in one chunk leaves its records for the adjoint; a
 // larger one (very high spp) has them recomputed chunk by chunk.
 static constexpr long long kChunk = 1ll << 24;
+// shadow-boundary samples are listed per sub-range of a chunk (list size
+// bounded by kSecSub * lights entries)
+static constexpr long long kSecSub = 1ll << 21;
 enum { kKernCamera, kKernShadow, kKernShade, kKernAdj, kKernPrimary, kKernSecondary, kNumKern };
 static constexpr int kNumEvents = 8 + 2 * kNumKern;
 
@@ -1158,8 +1252,10 @@ struct fr_ctx {
     int *tbl_edge = nullptr, *tbl_n = nullptr; uint64_t *tbl_prefix = nullptr, *tbl_Q = nullptr;
     float *samples = nullptr; size_t samples_cap = 0;
     HitRec *hits = nullptr; unsigned long long *vis = nullptr; size_t rec_cap = 0;
+    uint32_t *sec_list = nullptr, *sec_n = nullptr; size_t sec_cap = 0;
     bool records_valid = false;   // hits/vis hold every sample of the last render
     PeSample *pe_samples = nullptr; Hit *pe_hits = nullptr; double *pe_f = nullptr;
+    unsigned long long *pe_vis = nullptr;
     unsigned long long *ctr = nullptr;
     // gradients scratch
     double *g_light = nullptr, *g_spec = nullptr, *g_pos = nullptr, *g_nrm = nullptr, *g_alb = nullptr;
@@ -1499,9 +1595,9 @@ int fr_create(const fr_model_desc *m, const fr_scene_desc *s, uint32_t flags, fr
         R(dalloc(c, &c->ew, (size_t)(1 + c->nl) * c->E)) ||
         R(dalloc(c, &c->tbl_edge, (size_t)(1 + c->nl) * c->E)) || R(dalloc(c, &c->tbl_prefix, (size_t)(1 + c->nl) * c->E)) ||
         R(dalloc(c, &c->tbl_n, (size_t)(1 + c->nl))) || R(dalloc(c, &c->tbl_Q, (size_t)(1 + c->nl))) ||
-        R(dalloc(c, &c->ctr, 8 * kNumKern)) ||
+        R(dalloc(c, &c->ctr, 8 * kNumKern)) || R(dalloc(c, &c->sec_n, 1)) ||
         R(dalloc(c, &c->pe_samples, (size_t)c->W * c->H)) || R(dalloc(c, &c->pe_hits, 2 * (size_t)c->W * c->H)) ||
-        R(dalloc(c, &c->pe_f, 6 * (size_t)c->W * c->H)) ||
+        R(dalloc(c, &c->pe_f, 6 * (size_t)c->W * c->H)) || R(dalloc(c, &c->pe_vis, 2 * (size_t)c->W * c->H)) ||
         R(dalloc(c, &c->g_light, 3 * (size_t)c->nl)) || R(dalloc(c, &c->g_spec, (size_t)c->res * c->res)) ||
         R(dalloc(c, &c->g_pos, V3)) || R(dalloc(c, &c->g_nrm, V3)) || R(dalloc(c, &c->g_alb, V3)) ||
         R(dalloc(c, &c->g_N, V3)) || R(dalloc(c, &c->g_vert, V3)) || R(dalloc(c, &c->g_m, V3))) {
@@ -1597,6 +1693,13 @@ int fr_render(fr_ctx *c, const fr_params *p, uint64_t seed, int32_t spp, float *
         HIPCK(c, hipMalloc((void **)&c->vis, rec * sizeof(unsigned long long)));
         c->rec_cap = rec;
     }
+    size_t sec = (size_t)std::min(N, kSecSub) * c->nl;
+    if (sec > c->sec_cap) {
+        if (c->sec_list) (void)hipFree(c->sec_list);
+        c->sec_list = nullptr; c->sec_cap = 0;
+        HIPCK(c, hipMalloc((void **)&c->sec_list, sec * sizeof(uint32_t)));
+        c->sec_cap = sec;
+    }
     c->have_render = false;
     c->records_valid = false;
     c->last = *p;
@@ -1677,18 +1780,26 @@ int fr_backward(fr_ctx *c, const float *dLdI, const fr_grads *g) {
         ev_record(c, 9 + 2 * kKernAdj);
         ev_record(c, 8 + 2 * kKernSecondary);
         if (c->terms & FR_TERM_SECONDARY)
-            hipLaunchKernelGGL(k_edge_secondary, dim3(nblk(n, kShTile), c->nl), dim3(256), lds1, c->stream, S,
-                               c->last_seed, c->last_spp, s0, n, dLdI, c->hits, c->g_pos, c->ctr + 8 * kKernSecondary);
+            for (long long o = 0; o < n; o += kSecSub) {
+                long long m = std::min(kSecSub, n - o);
+                hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, c->stream, c->sec_n, 1);
+                hipLaunchKernelGGL(k_edge_secondary, dim3(nblk(m, kShTile), c->nl), dim3(256), 0, c->stream, S,
+                                   c->last_seed, c->last_spp, s0 + o, m, dLdI, c->hits + o, c->sec_list, c->sec_n,
+                                   c->ctr + 8 * kKernSecondary);
+                hipLaunchKernelGGL(k_edge_secondary_value, dim3(1024), dim3(256), lds1, c->stream, S, c->last_seed,
+                                   c->last_spp, s0 + o, dLdI, c->hits + o, c->sec_list, c->sec_n, c->g_pos);
+            }
         ev_record(c, 9 + 2 * kKernSecondary);
     }
     ev_record(c, 8 + 2 * kKernPrimary);
     if (c->terms & FR_TERM_PRIMARY) {
         int M = c->W * c->H;
-        hipLaunchKernelGGL(k_zero_d, dim3(nblk(6 * (size_t)M, 256)), dim3(256), 0, c->stream, c->pe_f, 6 * (size_t)M);
         hipLaunchKernelGGL(k_edge_primary_setup, dim3(nblk(M, 256)), dim3(256), 0, c->stream,
-                           S, c->last_seed, M, c->pe_samples, c->pe_hits, c->ctr + 8 * kKernPrimary);
-        hipLaunchKernelGGL(k_edge_primary_shade, dim3(nblk((size_t)2 * M, kShTile), c->nl), dim3(256), lds1, c->stream,
-                           S, c->last_seed, M, c->pe_samples, c->pe_hits, c->pe_f, c->ctr + 8 * kKernPrimary);
+                           S, c->last_seed, M, c->pe_samples, c->pe_hits, c->pe_vis, c->ctr + 8 * kKernPrimary);
+        hipLaunchKernelGGL(k_edge_primary_vis, dim3(nblk((size_t)2 * M, kShTile), c->nl), dim3(256), 0, c->stream,
+                           S, c->last_seed, M, c->pe_samples, c->pe_hits, c->pe_vis, c->ctr + 8 * kKernPrimary);
+        hipLaunchKernelGGL(k_edge_primary_shade, dim3(nblk((size_t)2 * M, 256)), dim3(256), lds1, c->stream,
+                           S, c->last_seed, M, c->pe_samples, c->pe_hits, c->pe_vis, c->pe_f, c->ctr + 8 * kKernPrimary);
         hipLaunchKernelGGL(k_edge_primary_scatter, dim3(nblk(M, 256)), dim3(256), 0, c->stream,
                            S, M, dLdI, c->pe_samples, c->pe_f, c->g_pos);
     }
@@ -1770,8 +1881,8 @@ void fr_destroy(fr_ctx *c) {
                     c->lgeom, c->sorted_tri, c->leaf_node, c->right, c->escape, c->subs, c->height, c->top, c->top_off, c->nodes, c->tris,
                     c->vmodel, c->vm_d, c->pos, c->nrm, c->nlen, c->alb, c->ew, c->tbl_edge, c->tbl_prefix, c->tbl_n,
                     c->tbl_Q, c->samples, c->ctr, c->g_light, c->g_spec, c->g_pos, c->g_nrm, c->g_alb, c->g_N,
-                    c->g_vert, c->g_m, c->partial, c->loss_partial, c->hits, c->vis, c->pe_samples, c->pe_hits,
-                    c->pe_f};
+                    c->g_vert, c->g_m, c->partial, c->loss_partial, c->hits, c->vis, c->sec_list, c->sec_n, c->pe_samples, c->pe_hits,
+                    c->pe_f, c->pe_vis};
     for (void *p : ptrs) if (p) (void)hipFree(p);
     for (auto &e : c->ev) if (e) (void)hipEventDestroy(e);
     delete c;
