@@ -139,6 +139,15 @@ int fr_set_stream(fr_ctx *ctx, void *hip_stream);
 /* Select the backward terms (bit set of FR_TERM_*). */
 int fr_set_terms(fr_ctx *ctx, uint32_t terms);
 
+/* Camera samples per chunk (1 <= samples <= FR_CHUNK_MAX, default
+ * FR_CHUNK_MAX).  fr_render keeps each camera sample's hit record (16 B) and
+ * light-visibility mask (8 B) for fr_backward when the whole render fits in
+ * one chunk; a larger render (high spp) keeps none and fr_backward
+ * recomputes them chunk by chunk.  Takes effect at the next fr_render.
+ * Errors: FR_EINVAL. */
+#define FR_CHUNK_MAX (1 << 22)
+int fr_set_chunk(fr_ctx *ctx, int32_t samples);
+
 /* Morphable blend (Face Modeling paragraph): v_model = mean + B_id alpha +
  * B_exp beta, v = R v_model + t, A = alb_mean + B_alb delta, vertex normals.
  * Sums run over k in ascending order in double precision; positions and

@@ -1219,7 +1219,7 @@ __global__ __launch_bounds__(BS) void k_loss_final(int nb, const double *__restr
 // Camera samples per chunk of the forward wavefront (24 B of records each).
 // A render that fits in one chunk leaves its records for the adjoint; a
 // larger one (very high spp) has them recomputed chunk by chunk.
-static constexpr long long kChunk = 1ll << 24;
+static constexpr long long kChunkMax = FR_CHUNK_MAX;
 // shadow-boundary samples are listed per sub-range of a chunk (list size
 // bounded by kSecSub * lights entries)
 static constexpr long long kSecSub = 1ll << 21;
@@ -1267,6 +1267,7 @@ struct fr_ctx {
     bool have_render = false, have_backward = false;
     fr_params last{};
     uint64_t last_seed = 0; int last_spp = 0;
+    long long cam_chunk = kChunkMax, last_cam_chunk = kChunkMax;   // camera samples per chunk (set / of the last render)
     PoseArgs pose{};
     DRotArgs drot{};
     // timing
@@ -1627,6 +1628,12 @@ int fr_set_stream(fr_ctx *c, void *stream) {
     return FR_OK;
 }
 
+int fr_set_chunk(fr_ctx *c, int32_t samples) {
+    if (!c || samples < 1 || samples > FR_CHUNK_MAX) return FR_EINVAL;
+    c->cam_chunk = samples;
+    return FR_OK;
+}
+
 int fr_set_terms(fr_ctx *c, uint32_t terms) {
     if (!c || (terms & ~7u)) return FR_EINVAL;
     c->terms = terms;
@@ -1684,6 +1691,7 @@ int fr_render(fr_ctx *c, const fr_params *p, uint64_t seed, int32_t spp, float *
         HIPCK(c, hipMalloc((void **)&c->samples, (size_t)N * 3 * sizeof(float)));
         c->samples_cap = (size_t)N * 3;
     }
+    const long long kChunk = c->cam_chunk;
     size_t rec = (size_t)std::min(N, kChunk);
     if (rec > c->rec_cap) {
         if (c->hits) (void)hipFree(c->hits);
@@ -1702,6 +1710,7 @@ int fr_render(fr_ctx *c, const fr_params *p, uint64_t seed, int32_t spp, float *
     }
     c->have_render = false;
     c->records_valid = false;
+    c->last_cam_chunk = kChunk;
     c->last = *p;
     c->last_seed = seed;
     c->last_spp = spp;
@@ -1762,6 +1771,7 @@ int fr_backward(fr_ctx *c, const float *dLdI, const fr_grads *g) {
     Scene S = make_scene(c);
     long long N = (long long)c->W * c->H * c->last_spp;
     GradBufs G{c->g_light, c->g_spec, c->g_pos, c->g_nrm, c->g_alb};
+    const long long kChunk = c->last_cam_chunk;
     size_t lds = ((size_t)2 * c->res * c->res + 3 * c->nl) * sizeof(float);
     hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, c->stream, c->ctr + 8 * kKernAdj, 8 * (kNumKern - kKernAdj));
     size_t lds1 = (size_t)c->res * c->res * sizeof(float);

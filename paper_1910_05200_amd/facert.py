@@ -66,7 +66,7 @@ class fr_stats_t(C.Structure):
 KERNELS = ("k_fwd_camera", "k_fwd_shadow", "k_fwd_shade", "k_render_adj", "k_edge_primary", "k_edge_secondary")
 
 
-EXPORTS = ("fr_create", "fr_set_stream", "fr_set_terms", "fr_blend", "fr_render", "fr_backward",
+EXPORTS = ("fr_create", "fr_set_stream", "fr_set_terms", "fr_set_chunk", "fr_blend", "fr_render", "fr_backward",
            "fr_loss_l2", "fr_stats", "fr_last_error", "fr_destroy")
 
 _lib = None
@@ -84,6 +84,7 @@ def load():
         L.fr_create.argtypes = [C.POINTER(fr_model_desc), C.POINTER(fr_scene_desc), u32, C.POINTER(vp)]
         L.fr_set_stream.argtypes = [vp, vp]
         L.fr_set_terms.argtypes = [vp, u32]
+        L.fr_set_chunk.argtypes = [vp, i32]
         L.fr_blend.argtypes = [vp] * 7
         L.fr_render.argtypes = [vp, C.POINTER(fr_params), u64, i32, vp]
         L.fr_backward.argtypes = [vp, vp, C.POINTER(fr_grads)]
@@ -168,6 +169,9 @@ class Renderer:
 
     def set_terms(self, terms: int):
         _check(self.ctx, load().fr_set_terms(self.ctx, terms))
+
+    def set_chunk(self, samples: int):
+        _check(self.ctx, load().fr_set_chunk(self.ctx, samples))
 
     # -- calls
     def blend(self, alpha, beta, delta, pose):

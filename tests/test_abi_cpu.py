@@ -16,7 +16,7 @@ def _declared():
 def test_header_declares_the_boundary():
     names = _declared()
     for n in ("fr_create", "fr_set_stream", "fr_blend", "fr_render", "fr_backward", "fr_stats",
-              "fr_last_error", "fr_destroy", "fr_loss_l2", "fr_set_terms"):
+              "fr_last_error", "fr_destroy", "fr_loss_l2", "fr_set_terms", "fr_set_chunk"):
         assert n in names
 
 
@@ -38,6 +38,7 @@ def test_null_context_and_argument_errors_without_gpu():
     assert lib.fr_set_stream(None, None) == -1
     assert lib.fr_render(None, None, 0, 1, None) == -1
     assert lib.fr_backward(None, None, None) == -1
+    assert lib.fr_set_chunk(None, 1024) == -1
     assert lib.fr_last_error(None) == b"no context"
     lib.fr_destroy(None)
     # invalid model: zero vertices

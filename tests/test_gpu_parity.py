@@ -97,7 +97,7 @@ def test_render_parity_paper_sampled(torch, orc):
     assert_image_parity(img.reshape(-1, 3)[pix], ref)
 
 
-def _grad_case(torch, orc, name, terms):
+def _grad_case(torch, orc, name, terms, chunk=None):
     from paper_1910_05200_amd import facert
     model, scene, params, spp = _case(name)
     tosc, _, _ = orc.scene_from_model(model, scene, synth.make_params(synth.TARGET_SCENE_SEED))
@@ -107,6 +107,8 @@ def _grad_case(torch, orc, name, terms):
     dL = (2 * (ref_img - target)).astype(np.float32)
     r = _renderer(torch, model, scene)
     r.set_terms(terms)
+    if chunk:
+        r.set_chunk(chunk)
     img, p = _gpu_render(torch, r, params, SEED, spp)
     g = r.backward(torch.from_numpy(dL).cuda())
     torch.cuda.synchronize()
@@ -142,6 +144,15 @@ def test_backward_all_terms_tiny(torch, orc):
     st = r.stats()
     assert st["rays_edge_secondary"] > 0 and st["rays_edge_primary"] > 0
     _compare(g, ref, pg)
+
+
+def test_backward_all_terms_tiny_chunked(torch, orc):
+    """Render larger than a chunk: no records are kept, the backward
+    recomputes hits and visibility chunk by chunk (ragged last chunk)."""
+    g, ref, pg, r = _grad_case(torch, orc, "tiny", 7, chunk=5000)
+    _compare(g, ref, pg)
+    with pytest.raises(Exception):
+        r.set_chunk(0)
 
 
 def test_backward_all_terms_paper(torch, orc):
