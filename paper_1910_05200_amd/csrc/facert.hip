@@ -13,14 +13,17 @@
 //                    creation)
 //   k_edge_weights   camera-silhouette and per-light shadow-candidate edges
 //   k_edge_scan      integer CDFs of the edge weights (one block per table)
-//   k_render_fwd     one lane per camera sample: closest hit, 20 lights,
-//                    shadow rays, Cook-Torrance (Optimization paragraph: F)
+//   k_fwd_camera, k_fwd_shadow, k_fwd_shade
+//                    Monte-Carlo estimator F (Optimization paragraph): hit
+//                    records, compacted shadow rays, Cook-Torrance shading
 //   k_pixel_mean     fixed-order mean of each pixel's samples
-// Adjoint (fr_backward):
-//   k_render_adj     recomputes each camera sample, reverse mode through the
-//                    shading, scatters to lights/texels/albedo/normals/vertices,
-//                    plus the shadow-boundary edge sample of each light
-//   k_edge_primary   camera-silhouette edge samples
+// Adjoint (fr_backward), chunk by chunk over the camera samples:
+//   k_render_adj     reverse mode of each camera sample's shading, scattered
+//                    to lights/texels/albedo/normals/vertices
+//   k_edge_secondary, k_edge_secondary_value
+//                    shadow-boundary edge samples
+//   k_edge_primary_{setup,vis,shade,scatter}
+//                    camera-silhouette edge samples
 //   k_normal_adj, k_chain_gather, k_param_partial, k_param_final
 //                    normal chain, transposed blend and pose reductions
 #include <hip/hip_runtime.h>
