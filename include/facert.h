@@ -180,6 +180,24 @@ int fr_backward(fr_ctx *ctx, const float *dL_dimage, const fr_grads *grads);
 int fr_loss_l2(fr_ctx *ctx, const float *image, const float *target,
                float *dL_dimage, float *loss_dev);
 
+/* Light regulariser of the objective, Eq. 1 (w2 E_light): E_light =
+ * sum_j |l_j - m_j|^2 over the context's n lights, m_j the mean of light j's
+ * three channels.  lights [n][3] (device).  grad_lights [n][3] (device,
+ * may be NULL): 2 w2 (l_j - m_j) is ADDED to it, e.g. to fr_backward's
+ * d_lights.  *loss_dev (device float, may be NULL) = w2 E_light.
+ * Errors: FR_EINVAL (null lights, non-finite w2). */
+int fr_light_reg(fr_ctx *ctx, const float *lights, float w2, float *grad_lights, float *loss_dev);
+
+/* One Adam step (Kingma and Ba 2015) on n floats, in place, on the context's
+ * stream; the paper leaves the optimiser of Eq. 1 open.  param, grad, m, v
+ * [n] (device): m <- beta1 m + (1 - beta1) grad, v <- beta2 v + (1 - beta2)
+ * grad^2, param <- param - lr (m / (1 - beta1^step)) / (sqrt(v / (1 -
+ * beta2^step)) + eps).  m and v start at zero; step counts from 1.
+ * Errors: FR_EINVAL (null array with n > 0, n < 0, step < 1, beta outside
+ * [0, 1), eps <= 0, non-finite lr). */
+int fr_adam(fr_ctx *ctx, float *param, const float *grad, float *m, float *v, int32_t n, int32_t step,
+            float lr, float beta1, float beta2, float eps);
+
 /* Counters and phase times of the last render/backward (synchronises). */
 int fr_stats(fr_ctx *ctx, fr_stats_t *out);
 

@@ -1222,6 +1222,43 @@ __global__ __launch_bounds__(BS) void k_loss_final(int nb, const double *__restr
 // Camera samples per chunk of the forward wavefront (24 B of records each).
 // A render that fits in one chunk leaves its records for the adjoint; a
 // larger one (very high spp) has them recomputed chunk by chunk.
+// ------------------------------------------------------------ fitting --
+// Light regulariser of the objective (Eq. 1): E_light = sum_j |l_j - m_j|^2
+// with m_j the mean of light j's three channels, times w2.  Its gradient
+// 2 w2 (l_j - m_j) holds whether m_j is treated as a constant or not, since
+// the deviations of one light sum to zero.  One block, one lane per light.
+__global__ __launch_bounds__(64) void k_light_reg(int nl, const float *__restrict__ lights, float w2,
+                                                  float *__restrict__ grad, float *__restrict__ loss) {
+    double e = 0.0;
+    for (int j = threadIdx.x; j < nl; j += 64) {
+        float r = lights[3 * j], g = lights[3 * j + 1], b = lights[3 * j + 2];
+        float m = ((r + g) + b) / 3.0f;
+        float d[3] = {r - m, g - m, b - m};
+        for (int c = 0; c < 3; ++c) {
+            e += (double)d[c] * (double)d[c];
+            if (grad) grad[3 * j + c] += 2.0f * w2 * d[c];
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) e += __shfl_xor(e, off);
+    if (threadIdx.x == 0 && loss) *loss = (float)((double)w2 * e);
+}
+
+// Adam (Kingma and Ba 2015), one thread per element:
+//   m <- b1 m + (1 - b1) g,  v <- b2 v + (1 - b2) g^2,
+//   p <- p - lr (m / c1) / (sqrt(v / c2) + eps),  c1 = 1 - b1^t, c2 = 1 - b2^t
+// (c1, c2 computed on the host in double and rounded to float).
+__global__ __launch_bounds__(256) void k_adam(int n, float *__restrict__ p, const float *__restrict__ g,
+        float *__restrict__ m, float *__restrict__ v, float lr, float b1, float b2, float c1, float c2, float eps) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float gi = g[i];
+    float mi = b1 * m[i] + (1.0f - b1) * gi;
+    float vi = b2 * v[i] + (1.0f - b2) * (gi * gi);
+    m[i] = mi;
+    v[i] = vi;
+    p[i] = p[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
 static constexpr long long kChunkMax = FR_CHUNK_MAX;
 // shadow-boundary samples are listed per sub-range of a chunk (list size
 // bounded by kSecSub * lights entries)
@@ -1835,6 +1872,34 @@ int fr_backward(fr_ctx *c, const float *dLdI, const fr_grads *g) {
     ev_record(c, 6);
     HIPCK(c, hipGetLastError());
     c->have_backward = true;
+    return FR_OK;
+}
+
+int fr_light_reg(fr_ctx *c, const float *lights, float w2, float *grad_lights, float *loss) {
+    if (!c) return FR_EINVAL;
+    c->err.clear();
+    if (!lights) return fail(c, FR_EINVAL, "fr_light_reg: null lights");
+    if (!std::isfinite(w2)) return fail(c, FR_EINVAL, "fr_light_reg: non-finite w2");
+    hipLaunchKernelGGL(k_light_reg, dim3(1), dim3(64), 0, c->stream, c->nl, lights, w2, grad_lights, loss);
+    HIPCK(c, hipGetLastError());
+    return FR_OK;
+}
+
+int fr_adam(fr_ctx *c, float *param, const float *grad, float *m, float *v, int32_t n, int32_t step,
+            float lr, float beta1, float beta2, float eps) {
+    if (!c) return FR_EINVAL;
+    c->err.clear();
+    if (n < 0 || (n > 0 && (!param || !grad || !m || !v)))
+        return fail(c, FR_EINVAL, "fr_adam: null array or negative size");
+    if (step < 1 || !(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps > 0.0f) ||
+        !std::isfinite(lr))
+        return fail(c, FR_EINVAL, "fr_adam: step >= 1, 0 <= beta < 1, eps > 0, finite lr required");
+    if (n == 0) return FR_OK;
+    float c1 = (float)(1.0 - std::pow((double)beta1, (double)step));
+    float c2 = (float)(1.0 - std::pow((double)beta2, (double)step));
+    hipLaunchKernelGGL(k_adam, dim3(nblk(n, 256)), dim3(256), 0, c->stream, n, param, grad, m, v, lr, beta1, beta2,
+                       c1, c2, eps);
+    HIPCK(c, hipGetLastError());
     return FR_OK;
 }
 

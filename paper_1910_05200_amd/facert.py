@@ -67,7 +67,7 @@ KERNELS = ("k_fwd_camera", "k_fwd_shadow", "k_fwd_shade", "k_render_adj", "k_edg
 
 
 EXPORTS = ("fr_create", "fr_set_stream", "fr_set_terms", "fr_set_chunk", "fr_blend", "fr_render", "fr_backward",
-           "fr_loss_l2", "fr_stats", "fr_last_error", "fr_destroy")
+           "fr_loss_l2", "fr_light_reg", "fr_adam", "fr_stats", "fr_last_error", "fr_destroy")
 
 _lib = None
 
@@ -89,6 +89,8 @@ def load():
         L.fr_render.argtypes = [vp, C.POINTER(fr_params), u64, i32, vp]
         L.fr_backward.argtypes = [vp, vp, C.POINTER(fr_grads)]
         L.fr_loss_l2.argtypes = [vp] * 5
+        L.fr_light_reg.argtypes = [vp, vp, C.c_float, vp, vp]
+        L.fr_adam.argtypes = [vp, vp, vp, vp, vp, i32, i32, C.c_float, C.c_float, C.c_float, C.c_float]
         L.fr_stats.argtypes = [vp, C.POINTER(fr_stats_t)]
         L.fr_last_error.argtypes = [vp]
         L.fr_last_error.restype = C.c_char_p
@@ -217,6 +219,24 @@ class Renderer:
         loss = t.empty((), device=image.device, dtype=t.float32)
         _check(self.ctx, load().fr_loss_l2(self.ctx, _ptr(image), _ptr(target), _ptr(dL), _ptr(loss)))
         return dL, loss
+
+    def light_reg(self, lights, w2: float, grad=None):
+        """w2 E_light (device scalar); adds its gradient to grad when given."""
+        t = self.torch
+        self._stream()
+        loss = t.empty((), device=lights.device, dtype=t.float32)
+        _check(self.ctx, load().fr_light_reg(self.ctx, _ptr(lights), float(w2), _ptr(grad), _ptr(loss)))
+        return loss
+
+    def adam(self, param, grad, m, v, step: int, lr: float, beta1=0.9, beta2=0.999, eps=1e-8):
+        """One in-place Adam step on float32 device tensors of equal size."""
+        self._stream()
+        n = param.numel()
+        for x in (grad, m, v):
+            assert x.numel() == n and x.is_contiguous() and x.dtype == param.dtype
+        assert param.is_contiguous()
+        _check(self.ctx, load().fr_adam(self.ctx, _ptr(param), _ptr(grad), _ptr(m), _ptr(v), n, step,
+                                        float(lr), float(beta1), float(beta2), float(eps)))
 
     def stats(self) -> dict:
         s = fr_stats_t()

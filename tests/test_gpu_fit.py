@@ -1,0 +1,100 @@
+"""Fitting loop on the GPU: fr_adam and fr_light_reg against the oracle's
+plain float64 definitions, and a short fit that must reduce the error."""
+import numpy as np
+import pytest
+
+from oracle import fitting
+from paper_1910_05200_amd import synth
+from parity import assert_group_parity
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as T
+    if not T.cuda.is_available():
+        pytest.skip("no HIP device")
+    return T
+
+
+@pytest.fixture(scope="module")
+def renderer(torch):
+    from paper_1910_05200_amd import facert
+    model, scene, _, _ = synth.workload("tiny")
+    return facert.Renderer(model, scene)
+
+
+@pytest.mark.parametrize("n", [1, 255, 1000, 4099])
+def test_adam_parity(torch, renderer, n):
+    rng = np.random.default_rng(n)
+    p0 = rng.normal(size=n).astype(np.float32)
+    scales = [1e-3, 1.0, 30.0, 0.0, 1e-6, 2.0, 0.5]
+    grads = [(rng.normal(size=n) * s).astype(np.float32) for s in scales]
+    p = torch.from_numpy(p0.copy()).cuda()
+    m, v = torch.zeros_like(p), torch.zeros_like(p)
+    rp, rm, rv = p0.astype(np.float64), np.zeros(n), np.zeros(n)
+    for t, g in enumerate(grads, start=1):
+        renderer.adam(p, torch.from_numpy(g).cuda(), m, v, t, 0.01, 0.9, 0.999, 1e-8)
+        rp, rm, rv = fitting.adam(rp, g.astype(np.float64), rm, rv, t, 0.01, 0.9, 0.999, 1e-8)
+    torch.cuda.synchronize()
+    # The updates carry the test: compare p - p0 at the 1e-4 bar.  The GPU
+    # stores p in fp32 after each step, which adds up to half an ulp of |p|
+    # per step on top of that bar.
+    got = p.cpu().numpy().astype(np.float64)
+    ulp = np.spacing(np.abs(rp).astype(np.float32)).astype(np.float64)
+    ref_d = rp - p0
+    floor = 1e-2 * np.abs(ref_d).max()
+    tol = 1e-4 * np.maximum(np.abs(ref_d), floor) + 0.5 * len(grads) * ulp
+    assert np.all(np.abs(got - rp) <= tol), float(np.max(np.abs(got - rp) / tol))
+    assert_group_parity(m.cpu().numpy(), rm, "adam m")
+    assert_group_parity(v.cpu().numpy(), rv, "adam v")
+
+
+def test_adam_rejects_bad_arguments(torch, renderer):
+    from paper_1910_05200_amd import facert
+    p = torch.zeros(4, device="cuda")
+    with pytest.raises(facert.FrError):
+        renderer.adam(p, p.clone(), p.clone(), p.clone(), 0, 0.1)        # step counts from 1
+    with pytest.raises(facert.FrError):
+        renderer.adam(p, p.clone(), p.clone(), p.clone(), 1, 0.1, beta1=1.0)
+
+
+def test_light_reg_parity(torch, renderer):
+    rng = np.random.default_rng(5)
+    L = rng.uniform(0, 1, (20, 3)).astype(np.float32)
+    L[3] = 0.0
+    lights = torch.from_numpy(L).cuda()
+    grad = torch.zeros((20, 3), device="cuda")
+    loss = renderer.light_reg(lights, 1e-3, grad)
+    # the gradient is added to what the buffer holds: one fp32 rounding
+    g0 = rng.normal(size=(20, 3)).astype(np.float32)
+    acc = torch.from_numpy(g0.copy()).cuda()
+    renderer.light_reg(lights, 1e-3, acc)
+    torch.cuda.synchronize()
+    e, ge = fitting.light_reg(L.astype(np.float64), 1e-3)
+    assert abs(float(loss) - e) <= 1e-4 * abs(e)
+    assert_group_parity(grad.cpu().numpy(), ge, "E_light gradient")
+    want = g0.astype(np.float64) + ge
+    assert np.all(np.abs(acc.cpu().numpy() - want) <= 1e-4 * np.abs(ge) + np.spacing(np.abs(want).astype(np.float32)))
+
+
+def test_short_fit_reduces_error(torch, renderer):
+    """40 iterations from the perturbed start on the tiny workload: the data
+    term falls, the fitted render moves toward the target (PSNR) and so does
+    the pose.  Lights, albedo and texels are not checked one by one: light
+    colour times albedo is ambiguous in the image, E_light only tilts it."""
+    from paper_1910_05200_amd import facert, fit
+    truth = synth.make_params(synth.TARGET_SCENE_SEED)
+    start = synth.perturb(truth, fit.START_SEED)
+    target = renderer.render(facert.params_to_device(truth), synth.TARGET_RENDER_SEED, 64).clone()
+    tgt = target.cpu().numpy()
+    psnr0 = fit.psnr(renderer.render(facert.params_to_device(start), 99, 64).cpu().numpy(), tgt)
+    p, losses, _ = fit.fit(renderer, target, start, 40, 4)
+    psnr1 = fit.psnr(renderer.render(p, 99, 64).cpu().numpy(), tgt)
+    e0 = fit.param_errors(facert.params_to_device(start), truth)
+    e1 = fit.param_errors(p, truth)
+    print({k: (round(e0[k], 4), round(e1[k], 4)) for k in e0}, losses[0], np.mean(losses[-5:]), psnr0, psnr1)
+    assert np.mean(losses[-5:]) < 0.5 * losses[0]
+    assert psnr1 > psnr0 + 2.0
+    assert e1["rot_deg"] < e0["rot_deg"]
