@@ -31,8 +31,11 @@ if __package__ in (None, ""):
 from paper_1910_05200_amd import facert, synth
 
 # initial Adam step sizes, in each group's own units (coefficients, light
-# intensity, texel value, radians, metres); they decay by DECAY over the run
-LR = {"alpha": 0.05, "beta": 0.05, "delta": 0.05, "lights": 0.02, "spec": 0.02, "rot": 2e-3, "trans": 5e-4}
+# intensity, texel value, radians, metres); they decay by DECAY over the run.
+# Adam turns Monte-Carlo gradient noise into a random walk of about
+# lr * sqrt(iterations) on parameters the image barely constrains (the
+# specular texels), hence their small step.
+LR = {"alpha": 0.03, "beta": 0.03, "delta": 0.02, "lights": 0.01, "spec": 0.004, "rot": 1e-3, "trans": 2.5e-4}
 DECAY = 0.1
 W2 = 1e-3          # weight of E_light
 START_SEED = 3     # seed of the perturbation that gives the fitting start
@@ -103,7 +106,16 @@ def main():
     ap.add_argument("--spp", type=int, default=0, help="samples per pixel while fitting (default: the workload's)")
     ap.add_argument("--eval-spp", type=int, default=synth.TARGET_SPP)
     ap.add_argument("--log-every", type=int, default=20)
+    ap.add_argument("--lr", action="append", default=[], metavar="GROUP=VALUE",
+                    help=f"override an initial step size (groups: {', '.join(LR)})")
+    ap.add_argument("--decay", type=float, default=DECAY)
     args = ap.parse_args()
+    lr = dict(LR)
+    for kv in args.lr:
+        k, v = kv.split("=")
+        if k not in lr:
+            ap.error(f"unknown group {k}")
+        lr[k] = float(v)
     import torch
     assert torch.cuda.is_available(), "the fitting loop needs a HIP device"
     model, scene, _, spp = synth.workload(args.workload)
@@ -116,7 +128,7 @@ def main():
     p0 = facert.params_to_device(start)
     psnr0 = psnr(r.render(p0, 99, args.eval_spp).cpu().numpy(), tgt)
     err0 = param_errors(p0, truth)
-    p, losses, sec = fit(r, target, start, args.iters, spp, log_every=args.log_every)
+    p, losses, sec = fit(r, target, start, args.iters, spp, lr=lr, decay=args.decay, log_every=args.log_every)
     psnr1 = psnr(r.render(p, 99, args.eval_spp).cpu().numpy(), tgt)
     err1 = param_errors(p, truth)
     # reference point: the target parameters themselves, rendered with another seed
@@ -124,7 +136,7 @@ def main():
     out = {"workload": args.workload, "iters": args.iters, "spp": spp, "ms_per_iter": sec * 1e3,
            "E_data_first": losses[0], "E_data_last": float(np.mean(losses[-10:])),
            "psnr_db": {"start": psnr0, "fitted": psnr1, "target_params": psnr_truth, "eval_spp": args.eval_spp},
-           "param_rms_error": {"start": err0, "fitted": err1}, "w2": W2, "lr": LR, "decay": DECAY}
+           "param_rms_error": {"start": err0, "fitted": err1}, "w2": W2, "lr": lr, "decay": args.decay}
     print(json.dumps(out))
 
 
