@@ -524,13 +524,67 @@ template <class T> __device__ __forceinline__ void atomic_v(double *a, int V, in
 // p = o + t d moves only along the ray: dt/dv_k = b_k N / (N . d), N = e1 x e2.
 // The barycentrics follow v0 + b1 e1 + b2 e2 = o + t d:
 // d(b1, b2) -> z = -(g1 (d x e2) + g2 (e1 x d)) / det, dv_k += b_k z.
+// Vertex k of the hit triangle receives u * b_k.
 template <class T>
-__device__ inline void chain_hit(int V, const Surf<T> &s, vec3<T> gp, T gb0, T gb1, T gb2, double *d_pos) {
+__device__ __forceinline__ vec3<T> chain_u(const Surf<T> &s, vec3<T> gp, T gb0, T gb1, T gb2) {
     T gt = dot(gp, s.dir) / s.ndotd;
     T g1 = gb1 - gb0, g2 = gb2 - gb0;
     vec3<T> z = (s.pv * g1 + s.e1xd * g2) * ((T)-1 / s.det);
-    vec3<T> u = s.N * gt + z;
+    return s.N * gt + z;
+}
+template <class T>
+__device__ inline void chain_hit(int V, const Surf<T> &s, vec3<T> gp, T gb0, T gb1, T gb2, double *d_pos) {
+    vec3<T> u = chain_u(s, gp, gb0, gb1, gb2);
     for (int k = 0; k < 3; ++k) atomic_v(d_pos, V, s.i[k], u * s.b[k]);
+}
+
+// Per-block vertex accumulator in LDS: the adjoints of a vertex's position,
+// normal and albedo (9 values) from all the block's samples are summed in
+// fp64 LDS atomics and leave the block as one set of global atomics.  The
+// block's 256 samples span a few pixels, so they touch a few dozen
+// vertices; a vertex that finds no slot within kVtxProbe probes goes
+// straight to the global buffers.
+constexpr int kVtxSlots = 512;
+constexpr int kVtxProbe = 8;
+struct VtxAcc { int *key; double *val; };   // key [slots], val [9][slots]
+__device__ __forceinline__ int vtx_slot(const VtxAcc &a, int v) {
+    uint32_t h = ((uint32_t)v * 2654435761u) >> 23;     // 9 bits
+    for (int p = 0; p < kVtxProbe; ++p) {
+        int s = (int)((h + (uint32_t)p) & (kVtxSlots - 1));
+        int k = atomicCAS(&a.key[s], -1, v);
+        if (k == -1 || k == v) return s;
+    }
+    return -1;
+}
+// add (pos, nrm, alb) adjoints of vertex v
+template <class T>
+__device__ __forceinline__ void vtx_add(const VtxAcc &a, const GradBufs &G, int V, int v, vec3<T> gpos, vec3<T> gnrm,
+                                        const T galb[3]) {
+    int s = vtx_slot(a, v);
+    if (s < 0) {
+        atomic_v(G.d_pos, V, v, gpos);
+        atomic_v(G.d_nrm, V, v, gnrm);
+        for (int c = 0; c < 3; ++c) gadd(&G.d_alb[c * V + v], (double)galb[c]);
+        return;
+    }
+    double x[9] = {(double)gpos.x, (double)gpos.y, (double)gpos.z, (double)gnrm.x, (double)gnrm.y, (double)gnrm.z,
+                   (double)galb[0], (double)galb[1], (double)galb[2]};
+    for (int c = 0; c < 9; ++c) atomicAdd(&a.val[c * kVtxSlots + s], x[c]);
+}
+__device__ inline void vtx_clear(const VtxAcc &a) {
+    for (int k = threadIdx.x; k < kVtxSlots; k += blockDim.x) a.key[k] = -1;
+    for (int k = threadIdx.x; k < 9 * kVtxSlots; k += blockDim.x) a.val[k] = 0.0;
+}
+__device__ inline void vtx_flush(const VtxAcc &a, const GradBufs &G, int V) {
+    for (int s = threadIdx.x; s < kVtxSlots; s += blockDim.x) {
+        int v = a.key[s];
+        if (v < 0) continue;
+        double *dst[3] = {G.d_pos, G.d_nrm, G.d_alb};
+        for (int c = 0; c < 9; ++c) {
+            double x = a.val[c * kVtxSlots + s];
+            if (x != 0.0) gadd(&dst[c / 3][(c % 3) * V + v], x);
+        }
+    }
 }
 
 // Interior adjoint of one camera sample (decisions fp32, values T).
@@ -539,8 +593,8 @@ __device__ inline void chain_hit(int V, const Surf<T> &s, vec3<T> gp, T gb0, T g
 template <class T>
 __device__ inline void adjoint_sample(const Scene &S, const Light *Ls, uint64_t seed, uint32_t s,
                                       const float *wf, const Hit &h, const SurfDec &sd, const Surf<T> &sv,
-                                      float *g_light_lds, float *g_spec_lds, const GradBufs &G,
-                                      unsigned long long vis, Work &wk) {
+                                      float *g_light_lds, float *g_spec_lds, const VtxAcc &acc,
+                                      const GradBufs &G, unsigned long long vis, Work &wk) {
     int V = S.V;
     T w[3] = {(T)wf[0], (T)wf[1], (T)wf[2]};
     vec3<T> gp = vk<T>(0, 0, 0), gns = vk<T>(0, 0, 0), gwo = vk<T>(0, 0, 0);
@@ -575,20 +629,20 @@ __device__ inline void adjoint_sample(const Scene &S, const Light *Ls, uint64_t 
     for (int k = 0; k < 3; ++k) {
         int vi = sv.i[k];
         gb[k] += guvx * (T)S.uv[vi] + guvy * (T)S.uv[V + vi];
-        for (int c = 0; c < 3; ++c) {
-            gadd(&G.d_alb[c * V + vi], (double)(sv.b[k] * gA[c]));
-            gb[k] += gA[c] * (T)S.alb[c * V + vi];
-        }
+        for (int c = 0; c < 3; ++c) gb[k] += gA[c] * (T)S.alb[c * V + vi];
     }
     gp = gp - norm_adj(gwo, sv.wo, sv.olen);
     vec3<T> nt = sv.nu * ((T)1 / sv.nlen);
     vec3<T> gnu = norm_adj(gns * sv.sg, nt, sv.nlen);
     for (int k = 0; k < 3; ++k) {
         int vi = sv.i[k];
-        atomic_v(G.d_nrm, V, vi, gnu * sv.b[k]);
         gb[k] += dot(vk<T>((T)S.nrm[vi], (T)S.nrm[V + vi], (T)S.nrm[2 * V + vi]), gnu);
     }
-    chain_hit<T>(V, sv, gp, gb[0], gb[1], gb[2], G.d_pos);
+    vec3<T> u = chain_u(sv, gp, gb[0], gb[1], gb[2]);
+    for (int k = 0; k < 3; ++k) {
+        T ga[3] = {sv.b[k] * gA[0], sv.b[k] * gA[1], sv.b[k] * gA[2]};
+        vtx_add<T>(acc, G, V, sv.i[k], u * sv.b[k], gnu * sv.b[k], ga);
+    }
 }
 
 // Interior adjoint, fp32: one lane per camera sample of the chunk, reading
@@ -601,9 +655,13 @@ __global__ __launch_bounds__(256) void k_render_adj(Scene S, uint64_t seed, int 
     float *spec_lds = dyn;
     float *g_spec = dyn + S.res * S.res;        // [res^2]
     float *g_light = g_spec + S.res * S.res;    // [nl*3]
+    __shared__ int vt_key[kVtxSlots];
+    __shared__ double vt_val[9 * kVtxSlots];
+    const VtxAcc acc{vt_key, vt_val};
     stage_tables(S, Ls, spec_lds);
     for (int k = threadIdx.x; k < S.res * S.res; k += blockDim.x) g_spec[k] = 0.0f;
     for (int k = threadIdx.x; k < 3 * S.nl; k += blockDim.x) g_light[k] = 0.0f;
+    vtx_clear(acc);
     __syncthreads();
     long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     Work wk;
@@ -621,7 +679,7 @@ __global__ __launch_bounds__(256) void k_render_adj(Scene S, uint64_t seed, int 
             surf_decide(S, o, h, sd);
             Surf<float> sv;
             surf_value<float>(S, spec_lds, o, d, h, sd, sv);
-            adjoint_sample<float>(S, Ls, seed, s, w, h, sd, sv, g_light, g_spec, G, vis[i], wk);
+            adjoint_sample<float>(S, Ls, seed, s, w, h, sd, sv, g_light, g_spec, acc, G, vis[i], wk);
         }
     }
     flush_work(ctr, wk);
@@ -630,6 +688,7 @@ __global__ __launch_bounds__(256) void k_render_adj(Scene S, uint64_t seed, int 
         if (g_spec[k] != 0.0f) gadd(&G.d_spec[k], (double)g_spec[k]);
     for (int k = threadIdx.x; k < 3 * S.nl; k += blockDim.x)
         if (g_light[k] != 0.0f) gadd(&G.d_light[k], (double)g_light[k]);
+    vtx_flush(acc, G, S.V);
 }
 
 #ifndef FR_EDGE_REAL
