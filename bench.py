@@ -62,6 +62,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="paper", choices=["paper", "tiny"])
+    ap.add_argument("--bvh", default="lbvh", choices=["lbvh", "refit"],
+                    help="lbvh: Morton-code tree rebuilt from the posed mesh every step; refit: tree shape built "
+                         "once over the mean shape, boxes refitted every step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -106,7 +109,7 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     model, scene, params, spp = synth.workload(args.workload)
-    r = facert.Renderer(model, scene, timing=True)
+    r = facert.Renderer(model, scene, timing=True, refit=args.bvh == "refit")
     p = facert.params_to_device(params)
     pt = facert.params_to_device(synth.make_params(synth.TARGET_SCENE_SEED))
     target = r.render(pt, synth.TARGET_RENDER_SEED, synth.TARGET_SPP).clone()
@@ -162,6 +165,8 @@ def main():
         "config": {"workload": f"{args.workload}: {model.n_vertices}-vertex / {model.n_faces}-triangle "
                                f"morphable face, {scene.width}x{scene.height}, {spp} spp, 20 area lights, "
                                "forward + adjoint (interior, camera-silhouette and shadow-boundary terms)",
+                   "bvh": args.bvh,
+                   "ms_bvh": round(float(np.mean([st["ms_bvh"] for st in per_step])), 4),
                    "rays_per_iter": rays_per_iter,
                    "traversal_overflow": int(last["traversal_overflow"]),
                    "ms_kernels": {n: round(kern[n][1] * 1e3, 3) for n in facert.KERNELS},

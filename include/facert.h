@@ -120,6 +120,13 @@ typedef struct {
 } fr_stats_t;
 
 #define FR_TIMING 1u                 /* fr_create flag: time phases with events */
+#define FR_REFIT  2u                 /* fr_create flag: build the BVH's shape
+                                        once, over the model's mean shape, and
+                                        only refit its boxes per evaluation,
+                                        instead of rebuilding a Morton-code
+                                        tree from the posed mesh every
+                                        evaluation (the default); results are
+                                        identical, only the work differs    */
 
 /* Backward terms (fr_set_terms); all on by default. */
 #define FR_TERM_INTERIOR  1u
@@ -127,7 +134,8 @@ typedef struct {
 #define FR_TERM_SECONDARY 4u         /* shadow-boundary edges                   */
 
 /* Create a context: copies the model and scene to the device, builds the
- * topology (edges, vertex-to-face lists, BVH tree order).  flags: FR_TIMING.
+ * topology (edges, vertex-to-face lists, and the BVH shape when FR_REFIT is
+ * given).  flags: FR_TIMING, FR_REFIT.
  * Errors: FR_EINVAL (sizes <= 0, null arrays, non-manifold mesh, index out
  * of range, n_lights > 64), FR_ENOMEM, FR_EDEVICE.  *out is NULL on error. */
 int fr_create(const fr_model_desc *model, const fr_scene_desc *scene,

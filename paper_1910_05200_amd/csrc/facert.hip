@@ -169,6 +169,8 @@ __global__ __launch_bounds__(256) void k_refit_top(int n_top, const int *__restr
     }
 }
 
+#include "fr_lbvh.hpp"
+
 // ------------------------------------------------------- edge tables ----
 __device__ __forceinline__ bool project(const Scene &S, v3 x, float &sx, float &sy) {
     v3 r = x - mk(S.cam_x, S.cam_y, S.cam_z);
@@ -1341,6 +1343,7 @@ struct fr_ctx {
     // tree order (device)
     int *sorted_tri = nullptr, *leaf_node = nullptr, *right = nullptr, *escape = nullptr;
     SubTree *subs = nullptr; int n_subs = 0;
+    LbvhBufs lb{};                 // per-evaluation build (without FR_REFIT)
     int *height = nullptr, *top = nullptr, *top_off = nullptr; int n_top = 0, top_levels = 0;
     uint4 *nodes = nullptr;
     float4 *tris = nullptr;
@@ -1705,6 +1708,21 @@ int fr_create(const fr_model_desc *m, const fr_scene_desc *s, uint32_t flags, fr
         fr_destroy(c);
         return code;
     }
+    if (!(flags & FR_REFIT)) {
+        int F = c->F, nb = (int)nblk(F, kSortTile);
+        LbvhBufs &L = c->lb;
+        L.nb = nb;
+        if (dalloc(c, &L.key[0], F) || dalloc(c, &L.key[1], F) || dalloc(c, &L.val[0], F) || dalloc(c, &L.val[1], F) ||
+            dalloc(c, &L.hist, (size_t)256 * nb) || dalloc(c, &L.bounds, 6) || dalloc(c, &L.child, 2 * (size_t)F) ||
+            dalloc(c, &L.parent, 2 * (size_t)F) || dalloc(c, &L.first, (size_t)F) || dalloc(c, &L.last, (size_t)F) ||
+            dalloc(c, &L.pre, 2 * (size_t)F) || dalloc(c, &L.arrive, (size_t)F) || dalloc(c, &L.box, 12 * (size_t)F) ||
+            dalloc(c, &L.roots, (size_t)F) || dalloc(c, &L.n_roots, 1) || dalloc(c, &L.top_idx, (size_t)F) ||
+            dalloc(c, &L.n_top, 1)) {
+            fr_destroy(c);
+            return FR_ENOMEM;
+        }
+        (void)hipMemset(L.arrive, 0, sizeof(unsigned int) * F);
+    }
     c->chunk = 16384;
     c->nchunks = (int)((V3 + c->chunk - 1) / c->chunk);
     int rows = c->n_id + c->n_exp + c->n_alb + 12;
@@ -1737,6 +1755,35 @@ int fr_set_terms(fr_ctx *c, uint32_t terms) {
     if (!c || (terms & ~7u)) return FR_EINVAL;
     c->terms = terms;
     return FR_OK;
+}
+
+static void lbvh_build(fr_ctx *c) {
+    const int F = c->F, nb = c->lb.nb;
+    LbvhBufs &L = c->lb;
+    hipLaunchKernelGGL(k_lbvh_bounds_init, dim3(1), dim3(64), 0, c->stream, L.bounds);
+    hipLaunchKernelGGL(k_lbvh_bounds, dim3(nblk(F, 256)), dim3(256), 0, c->stream, F, c->pos, c->V, c->faces, L.bounds);
+    hipLaunchKernelGGL(k_lbvh_morton, dim3(nblk(F, 256)), dim3(256), 0, c->stream, F, c->pos, c->V, c->faces, L.bounds,
+                       L.key[0], L.val[0]);
+    for (int pass = 0; pass < 4; ++pass) {
+        int in = pass & 1, out = in ^ 1;
+        hipLaunchKernelGGL(k_sort_hist, dim3(nb), dim3(256), 0, c->stream, F, 8 * pass, L.key[in], L.hist, nb);
+        hipLaunchKernelGGL(k_scan_u32, dim3(1), dim3(1024), 0, c->stream, 256 * nb, L.hist);
+        hipLaunchKernelGGL(k_sort_scatter, dim3(nb), dim3(256), 0, c->stream, F, 8 * pass, L.key[in], L.val[in], L.hist,
+                           nb, L.key[out], L.val[out]);
+    }
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, c->stream, (unsigned int *)L.n_top, 1);
+    if (F > 1)
+        hipLaunchKernelGGL(k_lbvh_karras, dim3(nblk(F - 1, 256)), dim3(256), 0, c->stream, F, L.key[0], L.child,
+                           L.parent, L.first, L.last, L.top_idx, L.n_top);
+    hipLaunchKernelGGL(k_lbvh_layout, dim3(nblk(2 * (size_t)F - 1, 256)), dim3(256), 0, c->stream, F, L.child, L.parent,
+                       L.first, L.pre);
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, c->stream, (unsigned int *)L.n_roots, 1);
+    hipLaunchKernelGGL(k_lbvh_boxes, dim3(nblk(F, kBoxTile)), dim3(kBoxTile), 0, c->stream, F, c->faces, c->pos, c->V,
+                       L.val[0], L.child, L.parent, L.first, L.last, L.pre, L.box, c->nodes, c->tris,
+                       L.roots, L.n_roots);
+    if (F > 1)
+        hipLaunchKernelGGL(k_lbvh_boxes_top, dim3(1), dim3(1024), 0, c->stream, F, L.child, L.parent, L.first, L.last,
+                           L.pre, L.top_idx, L.arrive, L.box, c->nodes, L.roots, L.n_roots);
 }
 
 static int blend_impl(fr_ctx *c, const float *alpha, const float *beta, const float *delta, const float *pose) {
@@ -1817,11 +1864,15 @@ int fr_render(fr_ctx *c, const fr_params *p, uint64_t seed, int32_t spp, float *
     int r = blend_impl(c, p->alpha, p->beta, p->delta, p->pose);
     if (r) return r;
     ev_record(c, 1);
-    hipLaunchKernelGGL(k_refit_sub, dim3(c->n_subs), dim3(256), 0, c->stream, c->subs, c->faces, c->pos, c->V,
-                       c->sorted_tri, c->leaf_node, c->height, c->right, c->escape, c->nodes, c->tris);
-    if (c->n_top > 0)
-        hipLaunchKernelGGL(k_refit_top, dim3(1), dim3(256), 0, c->stream, c->n_top, c->top, c->top_off,
-                           c->top_levels, c->right, c->escape, c->nodes);
+    if (!(c->flags & FR_REFIT)) {
+        lbvh_build(c);
+    } else {
+        hipLaunchKernelGGL(k_refit_sub, dim3(c->n_subs), dim3(256), 0, c->stream, c->subs, c->faces, c->pos, c->V,
+                           c->sorted_tri, c->leaf_node, c->height, c->right, c->escape, c->nodes, c->tris);
+        if (c->n_top > 0)
+            hipLaunchKernelGGL(k_refit_top, dim3(1), dim3(256), 0, c->stream, c->n_top, c->top, c->top_off,
+                               c->top_levels, c->right, c->escape, c->nodes);
+    }
     ev_record(c, 2);
     Scene S = make_scene(c);
     hipLaunchKernelGGL(k_edge_weights, dim3(nblk(c->E, 256)), dim3(256), 0, c->stream, S, c->lgeom, c->ew);
@@ -2019,7 +2070,8 @@ void fr_destroy(fr_ctx *c) {
                     c->vmodel, c->vm_d, c->pos, c->nrm, c->nlen, c->alb, c->ew, c->tbl_edge, c->tbl_prefix, c->tbl_n,
                     c->tbl_Q, c->samples, c->ctr, c->g_light, c->g_spec, c->g_pos, c->g_nrm, c->g_alb, c->g_N,
                     c->g_vert, c->g_m, c->partial, c->loss_partial, c->hits, c->vis, c->sec_list, c->sec_n, c->pe_samples, c->pe_hits,
-                    c->pe_f, c->pe_vis};
+                    c->pe_f, c->pe_vis, c->lb.key[0], c->lb.key[1], c->lb.val[0], c->lb.val[1], c->lb.hist,
+                    c->lb.bounds, c->lb.child, c->lb.parent, c->lb.first, c->lb.last, c->lb.pre, c->lb.arrive, c->lb.box, c->lb.roots, c->lb.n_roots, c->lb.top_idx, c->lb.n_top};
     for (void *p : ptrs) if (p) (void)hipFree(p);
     for (auto &e : c->ev) if (e) (void)hipEventDestroy(e);
     delete c;

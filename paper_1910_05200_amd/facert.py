@@ -20,6 +20,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libfacert.so")
 
 FR_TIMING = 1
+FR_REFIT = 2
 FR_TERM_INTERIOR, FR_TERM_PRIMARY, FR_TERM_SECONDARY = 1, 2, 4
 STATUS = {0: "FR_OK", -1: "FR_EINVAL", -2: "FR_ENOMEM", -3: "FR_EDEVICE", -4: "FR_ESTATE"}
 
@@ -125,7 +126,7 @@ class Renderer:
     ``pose`` (6 floats, host).
     """
 
-    def __init__(self, model, scene, timing: bool = False):
+    def __init__(self, model, scene, timing: bool = False, refit: bool = False):
         import torch
         self.torch = torch
         L = load()
@@ -142,7 +143,8 @@ class Renderer:
         sd = fr_scene_desc(scene.width, scene.height, (C.c_float * 3)(*[float(x) for x in scene.cam]),
                            float(scene.pix_scale), self._lg.shape[0], self._lg.ctypes.data, scene.spec_res)
         ctx = C.c_void_p()
-        code = L.fr_create(C.byref(md), C.byref(sd), FR_TIMING if timing else 0, C.byref(ctx))
+        flags = (FR_TIMING if timing else 0) | (FR_REFIT if refit else 0)
+        code = L.fr_create(C.byref(md), C.byref(sd), flags, C.byref(ctx))
         if code != 0:
             raise FrError(code, "fr_create failed")
         self.ctx = ctx

@@ -28,9 +28,9 @@ def _case(name):
     return model, scene, params, spp
 
 
-def _renderer(torch, model, scene):
+def _renderer(torch, model, scene, refit=False):
     from paper_1910_05200_amd import facert
-    return facert.Renderer(model, scene, timing=True)
+    return facert.Renderer(model, scene, timing=True, refit=refit)
 
 
 def _gpu_render(torch, r, params, seed, spp):
@@ -53,9 +53,10 @@ def test_blend_bitwise(torch, orc, name):
     assert np.array_equal(a.cpu().numpy(), Ao.astype(np.float32))
 
 
-def test_render_parity_tiny(torch, orc):
+@pytest.mark.parametrize("refit", [False, True])
+def test_render_parity_tiny(torch, orc, refit):
     model, scene, params, spp = _case("tiny")
-    r = _renderer(torch, model, scene)
+    r = _renderer(torch, model, scene, refit)
     img, _ = _gpu_render(torch, r, params, SEED, spp)
     osc, _, _ = orc.scene_from_model(model, scene, params)
     ref, cnt = orc.render(osc, SEED, spp, counts=True)
@@ -75,19 +76,21 @@ def test_render_deterministic(torch):
 
 
 @pytest.mark.parametrize("nx,ny,W,H,spp", [(7, 11, 37, 23, 3), (20, 9, 1, 1, 1), (16, 16, 300, 5, 2)])
-def test_render_parity_ragged(torch, orc, nx, ny, W, H, spp):
+@pytest.mark.parametrize("refit", [False, True])
+def test_render_parity_ragged(torch, orc, nx, ny, W, H, spp, refit):
     model = synth.make_model(nx, ny)
     scene = synth.make_scene(W, H)
     params = synth.make_params(5)
-    r = _renderer(torch, model, scene)
+    r = _renderer(torch, model, scene, refit)
     img, _ = _gpu_render(torch, r, params, 77, spp)
     osc, _, _ = orc.scene_from_model(model, scene, params)
     assert_image_parity(img, orc.render(osc, 77, spp))
 
 
-def test_render_parity_paper_sampled(torch, orc):
+@pytest.mark.parametrize("refit", [False, True])
+def test_render_parity_paper_sampled(torch, orc, refit):
     model, scene, params, spp = _case("paper")
-    r = _renderer(torch, model, scene)
+    r = _renderer(torch, model, scene, refit)
     img, _ = _gpu_render(torch, r, params, SEED, spp)
     osc, _, _ = orc.scene_from_model(model, scene, params)
     rng = np.random.default_rng(0)
@@ -97,7 +100,17 @@ def test_render_parity_paper_sampled(torch, orc):
     assert_image_parity(img.reshape(-1, 3)[pix], ref)
 
 
-def _grad_case(torch, orc, name, terms, chunk=None):
+def test_lbvh_and_refit_trees_render_identically(torch):
+    """The per-evaluation Morton-code tree (default) and the refitted SAH
+    tree (FR_REFIT) give the same hits and shadow decisions, hence
+    bit-identical images."""
+    model, scene, params, spp = _case("paper")
+    a, _ = _gpu_render(torch, _renderer(torch, model, scene, False), params, SEED, spp)
+    b, _ = _gpu_render(torch, _renderer(torch, model, scene, True), params, SEED, spp)
+    assert np.array_equal(a, b)
+
+
+def _grad_case(torch, orc, name, terms, chunk=None, refit=False):
     from paper_1910_05200_amd import facert
     model, scene, params, spp = _case(name)
     tosc, _, _ = orc.scene_from_model(model, scene, synth.make_params(synth.TARGET_SCENE_SEED))
@@ -105,7 +118,7 @@ def _grad_case(torch, orc, name, terms, chunk=None):
     osc, vm, R = orc.scene_from_model(model, scene, params)
     ref_img = orc.render(osc, SEED, spp)
     dL = (2 * (ref_img - target)).astype(np.float32)
-    r = _renderer(torch, model, scene)
+    r = _renderer(torch, model, scene, refit)
     r.set_terms(terms)
     if chunk:
         r.set_chunk(chunk)
@@ -143,6 +156,11 @@ def test_backward_all_terms_tiny(torch, orc):
     g, ref, pg, r = _grad_case(torch, orc, "tiny", 7)
     st = r.stats()
     assert st["rays_edge_secondary"] > 0 and st["rays_edge_primary"] > 0
+    _compare(g, ref, pg)
+
+
+def test_backward_all_terms_tiny_refit(torch, orc):
+    g, ref, pg, _ = _grad_case(torch, orc, "tiny", 7, refit=True)
     _compare(g, ref, pg)
 
 
