@@ -188,6 +188,15 @@ int fr_backward(fr_ctx *ctx, const float *dL_dimage, const fr_grads *grads);
 int fr_loss_l2(fr_ctx *ctx, const float *image, const float *target,
                float *dL_dimage, float *loss_dev);
 
+/* Auxiliary buffers of the last render, for the denoiser (fadenoise.h):
+ * out [H][W][7] (device) = per pixel, the mean over its samples of the
+ * first hit's albedo (RGB), unit shading normal turned toward the camera
+ * (xyz) and distance from the camera; misses contribute zeros.  Needs the
+ * last fr_render's hit records (a render of at most one chunk, see
+ * fr_set_chunk).  Errors: FR_EINVAL (null out), FR_ESTATE (no render, or
+ * its records were not kept). */
+int fr_aov(fr_ctx *ctx, float *out);
+
 /* Light regulariser of the objective, Eq. 1 (w2 E_light): E_light =
  * sum_j |l_j - m_j|^2 over the context's n lights, m_j the mean of light j's
  * three channels.  lights [n][3] (device).  grad_lights [n][3] (device,

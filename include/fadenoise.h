@@ -1,0 +1,81 @@
+/*
+ * fadenoise: learned denoiser for low-sample renders of the light-stage face
+ * renderer, on AMD Instinct MI355X.
+ *
+ * The paper names the sampling rate as the limitation of its method (Results
+ * and Conclusion paragraph: more ray-traced samples cost more time).  This
+ * library trades samples for a small convolutional encoder-decoder: a
+ * 4-level U-Net (32, 64, 128, 256 channels; two 3x3 convolutions with leaky
+ * ReLU per level; 2x2 average pooling down, nearest 2x upsampling and
+ * channel concatenation of the skip up; a 1x1 output convolution) that maps
+ * a low-spp render plus its albedo, normal and depth buffers to an estimate
+ * of the converged image.  Radiance enters and leaves in log(1 + x).
+ *
+ * Convolutions run as implicit GEMMs on the matrix cores in bfloat16 with
+ * fp32 accumulation (activations and their gradients bfloat16, weights kept
+ * in fp32 with bfloat16 copies); training uses Adam on a squared-error loss
+ * in log(1 + x).
+ *
+ * Conventions: status 0 on success, negative on failure (FD_EINVAL -1,
+ * FD_ENOMEM -2, FD_EDEVICE -3), message in fd_last_error; nothing throws.
+ * Array arguments are DEVICE pointers (fp32, row-major [H][W][c]) read and
+ * written on the stream set with fd_set_stream; calls return without
+ * waiting.  The network owns its weights and scratch.  One network must not
+ * be used from two host threads at once.
+ */
+#ifndef FADENOISE_H
+#define FADENOISE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fd_net fd_net;
+
+#define FD_IN_AUX 7   /* auxiliary channels: albedo rgb, normal xyz, depth */
+
+/* Create a network for H x W images (H and W multiples of 8, at most 4096).
+ * Weights start at zero; load them with fd_set_params.  Errors: FD_EINVAL,
+ * FD_ENOMEM, FD_EDEVICE. */
+int fd_create(int32_t height, int32_t width, fd_net **out);
+
+/* Enqueue all later work on this HIP stream (hipStream_t). */
+int fd_set_stream(fd_net *net, void *hip_stream);
+
+/* Number of fp32 parameters (weights and biases of all layers). */
+int64_t fd_num_params(const fd_net *net);
+
+/* Parameter layout: for each layer in order (14 3x3 convolutions, then the
+ * 1x1 output), weights [Cout][k*k][Cin] then bias [Cout]; the first layer's
+ * Cin is 16 (10 used: log(1 + rgb), albedo, normal, depth; the rest zero).
+ * fd_layer_shape gives layer i's (Cin, Cout, k) and returns 0, or FD_EINVAL
+ * past the last layer. */
+int fd_layer_shape(const fd_net *net, int32_t i, int32_t *cin, int32_t *cout, int32_t *k);
+
+/* Copy all parameters in (params [fd_num_params], device) or out. Setting
+ * them also resets the Adam moments and step count. */
+int fd_set_params(fd_net *net, const float *params);
+int fd_get_params(const fd_net *net, float *params);
+
+/* Denoise: rgb [H][W][3] (the low-spp render), aux [H][W][7] (albedo,
+ * normal, depth of the first hits, averaged over the pixel's samples) ->
+ * out [H][W][3] radiance.  out may alias neither input. */
+int fd_forward(fd_net *net, const float *rgb, const float *aux, float *out);
+
+/* One training step on one image pair: forward, loss
+ * mean over pixels and channels of (pred - log(1 + target))^2 with pred the
+ * network's log-radiance, backward, one Adam step (lr, betas 0.9 / 0.999,
+ * eps 1e-8) on all parameters.  *loss_dev (device float, may be NULL) gets
+ * the loss before the update.  grads (device, [fd_num_params], may be NULL)
+ * gets the parameter gradient of this step. */
+int fd_train_step(fd_net *net, const float *rgb, const float *aux, const float *target, float lr,
+                  float *loss_dev, float *grads);
+
+const char *fd_last_error(const fd_net *net);
+void fd_destroy(fd_net *net);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

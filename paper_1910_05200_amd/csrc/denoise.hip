@@ -1,0 +1,581 @@
+// fadenoise: U-Net denoiser for low-spp renders on MI355X (gfx950).
+//
+// Layout: activations NHWC bfloat16 [H*W][C] (bf16 stored as its 16 high
+// bits), weights [Cout][9][Cin].  Every 3x3 convolution is an implicit GEMM
+// (rows = pixels, columns = output channels, reduction = 9 taps x input
+// channels) on v_mfma_f32_32x32x8bf16_1k with fp32 accumulation: a block of
+// four waves owns a 64-pixel x 64-channel tile, each wave a 32 x 32 quarter,
+// and the reduction runs in steps of 16 channels of one tap staged in LDS.
+// The gradient with respect to a convolution's input is the same kernel on
+// the flipped, transposed weights; the weight gradient is a second GEMM
+// (rows = output channels, columns = input channels of one tap, reduction =
+// pixels) split over pixel chunks and summed with fp32 atomics.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "../../include/fadenoise.h"
+
+typedef uint16_t bf16;
+typedef short s4v __attribute__((ext_vector_type(4)));
+typedef float f16v __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ float bf2f(bf16 h) { return __uint_as_float((uint32_t)h << 16); }
+__device__ __forceinline__ bf16 f2bf(float f) {        // round to nearest even
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (bf16)(u >> 16);   // inf / nan
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (bf16)(u >> 16);
+}
+
+constexpr float kSlope = 0.01f;    // leaky ReLU
+constexpr int kTM = 64, kTN = 64, kKC = 16;   // GEMM tile, reduction step (channels)
+
+// ------------------------------------------------------------ conv 3x3 --
+// Y[p][co] = act(bias[co] + sum_{t, ci} W[co][t][ci] X[nbr(p, t)][ci]), zero
+// outside the image; act = leaky ReLU when relu, else identity (bias may be
+// NULL).  Cin multiple of 16; Y has ldy channels per pixel starting at
+// channel yoff (so a result can land inside a concatenation).
+// four consecutive values as bf16 (8 bytes)
+__device__ __forceinline__ uint2 load4(const bf16 *p) { return *(const uint2 *)p; }
+__device__ __forceinline__ uint2 load4(const float *p) {
+    float4 f = *(const float4 *)p;
+    return make_uint2((uint32_t)f2bf(f.x) | ((uint32_t)f2bf(f.y) << 16), (uint32_t)f2bf(f.z) | ((uint32_t)f2bf(f.w) << 16));
+}
+__device__ __forceinline__ void store1(bf16 *p, float v) { *p = f2bf(v); }
+__device__ __forceinline__ void store1(float *p, float v) { *p = v; }
+
+template <class TX, class TY>
+__global__ __launch_bounds__(256) void k_conv3x3(int H, int W, int Cin, int Cout, const TX *__restrict__ X,
+        const bf16 *__restrict__ Wt, const float *__restrict__ bias, int relu, TY *__restrict__ Y, int ldy,
+        int yoff) {
+    __shared__ bf16 As[kTM][kKC + 4];
+    __shared__ bf16 Bs[kTN][kKC + 4];
+    const int P = H * W;
+    const int p0 = blockIdx.x * kTM, co0 = blockIdx.y * kTN;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int lr = tid >> 2, lq = (tid & 3) * 4;        // loader: row, 4-channel quad
+    const int lp = p0 + lr, ly = lp / W, lx = lp - ly * W;
+    f16v acc;
+    for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
+    for (int t = 0; t < 9; ++t) {
+        const int dy = t / 3 - 1, dx = t % 3 - 1;
+        const int sy = ly + dy, sx = lx + dx;
+        const bool in = lp < P && sy >= 0 && sy < H && sx >= 0 && sx < W;
+        const TX *xa = X + (in ? (size_t)(sy * W + sx) * Cin : 0);
+        const bool wn_ok = co0 + lr < Cout;
+        const bf16 *wb = Wt + ((size_t)(co0 + lr) * 9 + t) * Cin;
+        for (int c0 = 0; c0 < Cin; c0 += kKC) {
+            uint2 va = make_uint2(0u, 0u), vb = make_uint2(0u, 0u);
+            if (in) va = load4(xa + c0 + lq);
+            if (wn_ok) vb = load4(wb + c0 + lq);
+            __syncthreads();
+            *(uint2 *)&As[lr][lq] = va;
+            *(uint2 *)&Bs[lr][lq] = vb;
+            __syncthreads();
+            for (int kk = 0; kk < kKC; kk += 8) {
+                const int k = kk + (lane >> 5) * 4;
+                s4v a = *(const s4v *)&As[wm * 32 + (lane & 31)][k];
+                s4v b = *(const s4v *)&Bs[wn * 32 + (lane & 31)][k];
+                acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc, 0, 0, 0);
+            }
+        }
+    }
+    const int co = co0 + wn * 32 + (lane & 31);
+    if (co >= Cout) return;
+    const float bv = bias ? bias[co] : 0.0f;
+    for (int r = 0; r < 16; ++r) {
+        const int p = p0 + wm * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        if (p >= P) continue;
+        float v = acc[r] + bv;
+        if (relu) v = v > 0.0f ? v : kSlope * v;
+        store1(&Y[(size_t)p * ldy + yoff + co], v);
+    }
+}
+
+// Weight gradient of one tap, one chunk of pixels:
+// dW[co][t][ci] += sum_{p in chunk} G[p][co] X[nbr(p, t)][ci]  (fp32 atomics).
+constexpr int kWChunk = 512;
+__global__ __launch_bounds__(256) void k_conv3x3_wgrad(int H, int W, int Cin, int Cout, const bf16 *__restrict__ X,
+        const float *__restrict__ G, float *__restrict__ dW) {
+    __shared__ bf16 As[kTN][kKC + 4];   // [co][px]
+    __shared__ bf16 Bs[kTN][kKC + 4];   // [ci][px]
+    const int P = H * W;
+    const int co0 = blockIdx.x * kTN, ci0 = blockIdx.y * kTN;
+    const int t = blockIdx.z % 9, chunk = blockIdx.z / 9;
+    const int dy = t / 3 - 1, dx = t % 3 - 1;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int lpx = tid >> 4, lc = (tid & 15) * 4;      // loader: pixel of the step, 4 channels
+    f16v acc;
+    for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
+    const int pbeg = chunk * kWChunk, pend = min(P, pbeg + kWChunk);
+    for (int pb = pbeg; pb < pend; pb += kKC) {
+        const int p = pb + lpx;
+        const int y = p / W, x = p - (p / W) * W;
+        const int sy = y + dy, sx = x + dx;
+        uint2 vg = make_uint2(0u, 0u), vx = make_uint2(0u, 0u);
+        if (p < pend) {
+            if (co0 + lc < Cout) vg = load4(G + (size_t)p * Cout + co0 + lc);
+            if (ci0 + lc < Cin && sy >= 0 && sy < H && sx >= 0 && sx < W)
+                vx = *(const uint2 *)(X + (size_t)(sy * W + sx) * Cin + ci0 + lc);
+        }
+        __syncthreads();
+        const bf16 *g4 = (const bf16 *)&vg, *x4 = (const bf16 *)&vx;
+        for (int q = 0; q < 4; ++q) { As[lc + q][lpx] = g4[q]; Bs[lc + q][lpx] = x4[q]; }
+        __syncthreads();
+        for (int kk = 0; kk < kKC; kk += 8) {
+            const int k = kk + (lane >> 5) * 4;
+            s4v a = *(const s4v *)&As[wm * 32 + (lane & 31)][k];
+            s4v b = *(const s4v *)&Bs[wn * 32 + (lane & 31)][k];
+            acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc, 0, 0, 0);
+        }
+    }
+    const int ci = ci0 + wn * 32 + (lane & 31);
+    if (ci >= Cin) return;
+    for (int r = 0; r < 16; ++r) {
+        const int co = co0 + wm * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        if (co < Cout && acc[r] != 0.0f) atomicAdd(&dW[((size_t)co * 9 + t) * Cin + ci], acc[r]);
+    }
+}
+
+// bias gradient: db[c] += sum_p G[p][c] (one block per 256 pixels)
+__global__ __launch_bounds__(256) void k_bias_grad(int P, int C, const float *__restrict__ G, float *__restrict__ db) {
+    for (int c = threadIdx.x; c < C; c += blockDim.x) {
+        float s = 0.0f;
+        for (int p = blockIdx.x * 256; p < min(P, blockIdx.x * 256 + 256); ++p) s += G[(size_t)p * C + c];
+        if (s != 0.0f) atomicAdd(&db[c], s);
+    }
+}
+
+// flipped, transposed bf16 weights for the input gradient:
+// Wt'[ci][t][co] = W[co][8 - t][ci]
+__global__ __launch_bounds__(256) void k_flip_weights(int Cin, int Cout, const float *__restrict__ w, bf16 *__restrict__ wf) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= Cin * 9 * Cout) return;
+    int co = i % Cout, t = (i / Cout) % 9, ci = i / (9 * Cout);
+    wf[i] = f2bf(w[((size_t)co * 9 + (8 - t)) * Cin + ci]);
+}
+
+// ------------------------------------------------------- elementwise ----
+__global__ void k_to_bf16(size_t n, const float *__restrict__ a, bf16 *__restrict__ b) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = f2bf(a[i]);
+}
+__global__ void k_zero_f(size_t n, float *a) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] = 0.0f;
+}
+
+// network input: log(1 + rgb), albedo, normal, depth, zeros -> 16 channels
+__global__ void k_pack_input(int P, const float *__restrict__ rgb, const float *__restrict__ aux, bf16 *__restrict__ x) {
+    int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    bf16 *o = x + (size_t)p * 16;
+    for (int c = 0; c < 3; ++c) o[c] = f2bf(log1pf(fmaxf(rgb[3 * p + c], 0.0f)));
+    for (int c = 0; c < FD_IN_AUX; ++c) o[3 + c] = f2bf(aux[FD_IN_AUX * p + c]);
+    for (int c = 3 + FD_IN_AUX; c < 16; ++c) o[c] = 0;
+}
+
+// 2x2 average pool: [H][W][C] (ld channels, offset off) -> [H/2][W/2][C]
+__global__ void k_pool2(int H, int W, int C, const bf16 *__restrict__ x, int ldx, bf16 *__restrict__ y) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int Ho = H / 2, Wo = W / 2;
+    if (i >= Ho * Wo * C) return;
+    int c = i % C, q = i / C, ox = q % Wo, oy = q / Wo;
+    float s = 0.0f;
+    for (int k = 0; k < 4; ++k) s += bf2f(x[((size_t)(2 * oy + (k >> 1)) * W + 2 * ox + (k & 1)) * ldx + c]);
+    y[i] = f2bf(0.25f * s);
+}
+// gradient of the pool, added: gx[p][c] += gy[p/2][c] / 4
+__global__ void k_pool2_bwd_add(int H, int W, int C, const float *__restrict__ gy, float *__restrict__ gx) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= H * W * C) return;
+    int c = i % C, q = i / C, x = q % W, y = q / W;
+    gx[i] += 0.25f * gy[((size_t)(y / 2) * (W / 2) + x / 2) * C + c];
+}
+// nearest 2x upsample of x [H/2][W/2][C] into y [H][W][ldy], channels from 0
+__global__ void k_up2(int H, int W, int C, const bf16 *__restrict__ x, bf16 *__restrict__ y, int ldy) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= H * W * C) return;
+    int c = i % C, q = i / C, px = q % W, py = q / W;
+    y[(size_t)q * ldy + c] = x[((size_t)(py / 2) * (W / 2) + px / 2) * C + c];
+}
+// gradient of the upsample: gx[q][c] = sum of the four gy[.][c] (gy [H][W][ldy])
+__global__ void k_up2_bwd(int H, int W, int C, const float *__restrict__ gy, int ldy, float *__restrict__ gx) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int Ho = H / 2, Wo = W / 2;
+    if (i >= Ho * Wo * C) return;
+    int c = i % C, q = i / C, ox = q % Wo, oy = q / Wo;
+    float s = 0.0f;
+    for (int k = 0; k < 4; ++k) s += gy[((size_t)(2 * oy + (k >> 1)) * W + 2 * ox + (k & 1)) * ldy + c];
+    gx[i] = s;
+}
+// copy C channels between tensors with different channel strides / offsets
+template <class T>
+__global__ void k_copy_ch(int P, int C, const T *__restrict__ x, int ldx, int xoff, T *__restrict__ y, int ldy,
+                          int yoff) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= P * C) return;
+    int c = i % C, p = i / C;
+    y[(size_t)p * ldy + yoff + c] = x[(size_t)p * ldx + xoff + c];
+}
+// leaky-ReLU backward in place: g *= (y > 0 ? 1 : slope)
+__global__ void k_act_bwd(size_t n, const bf16 *__restrict__ y, float *__restrict__ g) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    if (!(bf2f(y[i]) > 0.0f)) g[i] *= kSlope;
+}
+
+// 1x1 output convolution (fp32): pred[p][k] = b[k] + sum_c w[k][c] x[p][c]
+__global__ void k_out_fwd(int P, int C, const bf16 *__restrict__ x, const float *__restrict__ w, const float *__restrict__ b,
+                          float *__restrict__ pred) {
+    int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    for (int k = 0; k < 3; ++k) {
+        float s = b[k];
+        for (int c = 0; c < C; ++c) s += w[k * C + c] * bf2f(x[(size_t)p * C + c]);
+        pred[3 * p + k] = s;
+    }
+}
+__global__ void k_expm1(int n, const float *__restrict__ pred, float *__restrict__ out) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = expm1f(pred[i]);
+}
+// loss and its gradient: d = pred - log(1 + target); loss += d^2 / n; dpred = 2 d / n
+__global__ __launch_bounds__(256) void k_loss(int n, const float *__restrict__ pred, const float *__restrict__ tgt,
+                                             float *__restrict__ dpred, float *__restrict__ loss) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    float e = 0.0f;
+    if (i < n) {
+        float d = pred[i] - log1pf(fmaxf(tgt[i], 0.0f));
+        dpred[i] = 2.0f * d / (float)n;
+        e = d * d / (float)n;
+    }
+    for (int off = 32; off > 0; off >>= 1) e += __shfl_xor(e, off);
+    if ((threadIdx.x & 63) == 0 && e != 0.0f) atomicAdd(loss, e);
+}
+// output layer backward: dw[k][c] += sum_p dpred[p][k] x[p][c]; db[k] += sum_p dpred;
+// gx[p][c] = sum_k dpred[p][k] w[k][c]
+__global__ __launch_bounds__(256) void k_out_bwd(int P, int C, const bf16 *__restrict__ x, const float *__restrict__ w,
+        const float *__restrict__ dpred, float *__restrict__ dw, float *__restrict__ db, float *__restrict__ gx) {
+    __shared__ float sw[3 * 64 + 3];
+    for (int k = threadIdx.x; k < 3 * C + 3; k += blockDim.x) sw[k] = 0.0f;
+    __syncthreads();
+    int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < P) {
+        float d[3] = {dpred[3 * p], dpred[3 * p + 1], dpred[3 * p + 2]};
+        for (int c = 0; c < C; ++c) {
+            float xv = bf2f(x[(size_t)p * C + c]);
+            gx[(size_t)p * C + c] = d[0] * w[c] + d[1] * w[C + c] + d[2] * w[2 * C + c];
+            for (int k = 0; k < 3; ++k) atomicAdd(&sw[k * C + c], d[k] * xv);
+        }
+        for (int k = 0; k < 3; ++k) atomicAdd(&sw[3 * C + k], d[k]);
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < 3 * C; k += blockDim.x) if (sw[k] != 0.0f) atomicAdd(&dw[k], sw[k]);
+    for (int k = threadIdx.x; k < 3; k += blockDim.x) if (sw[3 * C + k] != 0.0f) atomicAdd(&db[k], sw[3 * C + k]);
+}
+
+// Adam (Kingma and Ba 2015) over all parameters
+__global__ void k_adam(size_t n, float *__restrict__ p, const float *__restrict__ g, float *__restrict__ m,
+                       float *__restrict__ v, float lr, float c1, float c2) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+    float gi = g[i];
+    float mi = b1 * m[i] + (1.0f - b1) * gi;
+    float vi = b2 * v[i] + (1.0f - b2) * (gi * gi);
+    m[i] = mi;
+    v[i] = vi;
+    p[i] = p[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// ====================================================================== //
+//                                  host                                   //
+// ====================================================================== //
+namespace {
+struct Layer { int cin, cout, k, level; size_t woff, boff; };
+struct Act { bf16 *y = nullptr; float *g = nullptr; int c = 0, level = 0; };   // values bf16, gradients fp32
+inline unsigned nblk(size_t n, unsigned b) { return (unsigned)((n + b - 1) / b); }
+}
+
+struct fd_net {
+    std::string err;
+    hipStream_t stream = nullptr;
+    int H = 0, W = 0;
+    std::vector<Layer> L;
+    size_t nparam = 0;
+    float *params = nullptr, *grads = nullptr, *m = nullptr, *v = nullptr;
+    bf16 *wbf = nullptr, *wflip = nullptr;      // bf16 copies of all conv weights, flipped scratch
+    int step = 0;
+    // activations (see build()), index by name
+    Act x0, e0a, e0, p1, e1a, e1, p2, e2a, e2, p3, e3a, e3, c2, d2a, d2, c1, d1a, d1, c0, d0a, d0;
+    float *pred = nullptr, *dpred = nullptr, *loss_s = nullptr;
+    std::vector<void *> allocs;
+};
+
+static int fail(fd_net *n, int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (n) n->err = buf;
+    return code;
+}
+#define HIPCK(n, x) do { hipError_t e_ = (x); if (e_ != hipSuccess) return fail(n, -3, "%s: %s", #x, hipGetErrorString(e_)); } while (0)
+
+template <class T> static int dalloc(fd_net *n, T **p, size_t count) {
+    if (hipMalloc((void **)p, std::max<size_t>(count, 1) * sizeof(T)) != hipSuccess) return -2;
+    n->allocs.push_back(*p);
+    return 0;
+}
+
+static int pix(const fd_net *n, int level) { return (n->H >> level) * (n->W >> level); }
+
+static int conv(fd_net *n, int li, const Act &x, bf16 *y, int ldy, int yoff, bool relu) {
+    const Layer &l = n->L[li];
+    int H = n->H >> l.level, W = n->W >> l.level, P = H * W;
+    dim3 grid(nblk(P, kTM), nblk(l.cout, kTN));
+    hipLaunchKernelGGL((k_conv3x3<bf16, bf16>), grid, dim3(256), 0, n->stream, H, W, l.cin, l.cout, x.y,
+                       n->wbf + l.woff, n->params + l.boff, relu ? 1 : 0, y, ldy, yoff);
+    return 0;
+}
+
+// backward of conv layer li: g_out (bf16 [P][cout], already multiplied by
+// the activation's derivative) -> weight and bias gradients, and (when gx)
+// the input gradient gx [P][cin].
+static void conv_bwd(fd_net *n, int li, const Act &x, const float *gout, float *gx) {
+    const Layer &l = n->L[li];
+    int H = n->H >> l.level, W = n->W >> l.level, P = H * W;
+    dim3 gw(nblk(l.cout, kTN), nblk(l.cin, kTN), 9 * nblk(P, kWChunk));
+    hipLaunchKernelGGL(k_conv3x3_wgrad, gw, dim3(256), 0, n->stream, H, W, l.cin, l.cout, x.y, gout, n->grads + l.woff);
+    hipLaunchKernelGGL(k_bias_grad, dim3(nblk(P, 256)), dim3(256), 0, n->stream, P, l.cout, gout, n->grads + l.boff);
+    if (gx) {
+        hipLaunchKernelGGL(k_flip_weights, dim3(nblk((size_t)l.cin * 9 * l.cout, 256)), dim3(256), 0, n->stream,
+                           l.cin, l.cout, n->params + l.woff, n->wflip);
+        dim3 grid(nblk(P, kTM), nblk(l.cin, kTN));
+        hipLaunchKernelGGL((k_conv3x3<float, float>), grid, dim3(256), 0, n->stream, H, W, l.cout, l.cin, gout,
+                           n->wflip, (const float *)nullptr, 0, gx, l.cin, 0);
+    }
+}
+
+static void act_bwd(fd_net *n, const Act &a) {
+    size_t cnt = (size_t)pix(n, a.level) * a.c;
+    hipLaunchKernelGGL(k_act_bwd, dim3(nblk(cnt, 256)), dim3(256), 0, n->stream, cnt, a.y, a.g);
+}
+
+static void forward(fd_net *n, const float *rgb, const float *aux) {
+    const int P0 = pix(n, 0);
+    hipStream_t s = n->stream;
+    hipLaunchKernelGGL(k_to_bf16, dim3(nblk(n->nparam, 256)), dim3(256), 0, s, n->nparam, n->params, n->wbf);
+    hipLaunchKernelGGL(k_pack_input, dim3(nblk(P0, 256)), dim3(256), 0, s, P0, rgb, aux, n->x0.y);
+    auto pool = [&](const Act &x, const Act &y) {
+        int H = n->H >> x.level, W = n->W >> x.level;
+        hipLaunchKernelGGL(k_pool2, dim3(nblk((size_t)(H / 2) * (W / 2) * x.c, 256)), dim3(256), 0, s, H, W, x.c, x.y,
+                           x.c, y.y);
+    };
+    auto upcat = [&](const Act &lo, const Act &skip, const Act &cat) {
+        int H = n->H >> cat.level, W = n->W >> cat.level;
+        hipLaunchKernelGGL(k_up2, dim3(nblk((size_t)H * W * lo.c, 256)), dim3(256), 0, s, H, W, lo.c, lo.y, cat.y, cat.c);
+        hipLaunchKernelGGL(k_copy_ch<bf16>, dim3(nblk((size_t)H * W * skip.c, 256)), dim3(256), 0, s, H * W, skip.c,
+                           skip.y, skip.c, 0, cat.y, cat.c, lo.c);
+    };
+    conv(n, 0, n->x0, n->e0a.y, 32, 0, true);
+    conv(n, 1, n->e0a, n->e0.y, 32, 0, true);
+    pool(n->e0, n->p1);
+    conv(n, 2, n->p1, n->e1a.y, 64, 0, true);
+    conv(n, 3, n->e1a, n->e1.y, 64, 0, true);
+    pool(n->e1, n->p2);
+    conv(n, 4, n->p2, n->e2a.y, 128, 0, true);
+    conv(n, 5, n->e2a, n->e2.y, 128, 0, true);
+    pool(n->e2, n->p3);
+    conv(n, 6, n->p3, n->e3a.y, 256, 0, true);
+    conv(n, 7, n->e3a, n->e3.y, 256, 0, true);
+    upcat(n->e3, n->e2, n->c2);
+    conv(n, 8, n->c2, n->d2a.y, 128, 0, true);
+    conv(n, 9, n->d2a, n->d2.y, 128, 0, true);
+    upcat(n->d2, n->e1, n->c1);
+    conv(n, 10, n->c1, n->d1a.y, 64, 0, true);
+    conv(n, 11, n->d1a, n->d1.y, 64, 0, true);
+    upcat(n->d1, n->e0, n->c0);
+    conv(n, 12, n->c0, n->d0a.y, 32, 0, true);
+    conv(n, 13, n->d0a, n->d0.y, 32, 0, true);
+    const Layer &lo = n->L[14];
+    hipLaunchKernelGGL(k_out_fwd, dim3(nblk(P0, 256)), dim3(256), 0, s, P0, 32, n->d0.y, n->params + lo.woff,
+                       n->params + lo.boff, n->pred);
+}
+
+static void backward(fd_net *n) {
+    const int P0 = pix(n, 0);
+    hipStream_t s = n->stream;
+    hipLaunchKernelGGL(k_zero_f, dim3(nblk(n->nparam, 256)), dim3(256), 0, s, n->nparam, n->grads);
+    const Layer &lo = n->L[14];
+    hipLaunchKernelGGL(k_out_bwd, dim3(nblk(P0, 256)), dim3(256), 0, s, P0, 32, n->d0.y, n->params + lo.woff, n->dpred,
+                       n->grads + lo.woff, n->grads + lo.boff, n->d0.g);
+    auto split = [&](const Act &cat, const Act &lo_, const Act &skip) {   // cat grad -> lo grad, skip grad (set)
+        int H = n->H >> cat.level, W = n->W >> cat.level;
+        hipLaunchKernelGGL(k_up2_bwd, dim3(nblk((size_t)(H / 2) * (W / 2) * lo_.c, 256)), dim3(256), 0, s, H, W, lo_.c,
+                           cat.g, cat.c, lo_.g);
+        hipLaunchKernelGGL(k_copy_ch<float>, dim3(nblk((size_t)H * W * skip.c, 256)), dim3(256), 0, s, H * W, skip.c,
+                           cat.g, cat.c, lo_.c, skip.g, skip.c, 0);
+    };
+    auto pool_bwd = [&](const Act &py, const Act &x) {   // x.g += pool gradient
+        int H = n->H >> x.level, W = n->W >> x.level;
+        hipLaunchKernelGGL(k_pool2_bwd_add, dim3(nblk((size_t)H * W * x.c, 256)), dim3(256), 0, s, H, W, x.c, py.g, x.g);
+    };
+    act_bwd(n, n->d0);  conv_bwd(n, 13, n->d0a, n->d0.g, n->d0a.g);
+    act_bwd(n, n->d0a); conv_bwd(n, 12, n->c0, n->d0a.g, n->c0.g);
+    split(n->c0, n->d1, n->e0);
+    act_bwd(n, n->d1);  conv_bwd(n, 11, n->d1a, n->d1.g, n->d1a.g);
+    act_bwd(n, n->d1a); conv_bwd(n, 10, n->c1, n->d1a.g, n->c1.g);
+    split(n->c1, n->d2, n->e1);
+    act_bwd(n, n->d2);  conv_bwd(n, 9, n->d2a, n->d2.g, n->d2a.g);
+    act_bwd(n, n->d2a); conv_bwd(n, 8, n->c2, n->d2a.g, n->c2.g);
+    split(n->c2, n->e3, n->e2);
+    act_bwd(n, n->e3);  conv_bwd(n, 7, n->e3a, n->e3.g, n->e3a.g);
+    act_bwd(n, n->e3a); conv_bwd(n, 6, n->p3, n->e3a.g, n->p3.g);
+    pool_bwd(n->p3, n->e2);
+    act_bwd(n, n->e2);  conv_bwd(n, 5, n->e2a, n->e2.g, n->e2a.g);
+    act_bwd(n, n->e2a); conv_bwd(n, 4, n->p2, n->e2a.g, n->p2.g);
+    pool_bwd(n->p2, n->e1);
+    act_bwd(n, n->e1);  conv_bwd(n, 3, n->e1a, n->e1.g, n->e1a.g);
+    act_bwd(n, n->e1a); conv_bwd(n, 2, n->p1, n->e1a.g, n->p1.g);
+    pool_bwd(n->p1, n->e0);
+    act_bwd(n, n->e0);  conv_bwd(n, 1, n->e0a, n->e0.g, n->e0a.g);
+    act_bwd(n, n->e0a); conv_bwd(n, 0, n->x0, n->e0a.g, nullptr);
+}
+
+extern "C" {
+
+int fd_create(int32_t H, int32_t W, fd_net **out) {
+    if (!out) return -1;
+    *out = nullptr;
+    if (H <= 0 || W <= 0 || H % 8 || W % 8 || H > 4096 || W > 4096) return -1;
+    fd_net *n = new fd_net();
+    n->H = H; n->W = W;
+    const int cin[15] = {16, 32, 32, 64, 64, 128, 128, 256, 384, 128, 192, 64, 96, 32, 32};
+    const int cout[15] = {32, 32, 64, 64, 128, 128, 256, 256, 128, 128, 64, 64, 32, 32, 3};
+    const int lev[15] = {0, 0, 1, 1, 2, 2, 3, 3, 2, 2, 1, 1, 0, 0, 0};
+    size_t off = 0;
+    for (int i = 0; i < 15; ++i) {
+        Layer l{cin[i], cout[i], i < 14 ? 3 : 1, lev[i], 0, 0};
+        l.woff = off; off += (size_t)l.cout * l.k * l.k * l.cin;
+        l.boff = off; off += (size_t)l.cout;
+        n->L.push_back(l);
+    }
+    n->nparam = off;
+    int rc = 0;
+    auto A = [&](Act &a, int c, int level) {
+        a.c = c; a.level = level;
+        size_t cnt = (size_t)((H >> level) * (W >> level)) * c;
+        if (!rc) rc = dalloc(n, &a.y, cnt);
+        if (!rc) rc = dalloc(n, &a.g, cnt);
+    };
+    A(n->x0, 16, 0); A(n->e0a, 32, 0); A(n->e0, 32, 0); A(n->p1, 32, 1); A(n->e1a, 64, 1); A(n->e1, 64, 1);
+    A(n->p2, 64, 2); A(n->e2a, 128, 2); A(n->e2, 128, 2); A(n->p3, 128, 3); A(n->e3a, 256, 3); A(n->e3, 256, 3);
+    A(n->c2, 384, 2); A(n->d2a, 128, 2); A(n->d2, 128, 2); A(n->c1, 192, 1); A(n->d1a, 64, 1); A(n->d1, 64, 1);
+    A(n->c0, 96, 0); A(n->d0a, 32, 0); A(n->d0, 32, 0);
+    size_t P0 = (size_t)H * W;
+    if (!rc) rc = dalloc(n, &n->params, n->nparam);
+    if (!rc) rc = dalloc(n, &n->grads, n->nparam);
+    if (!rc) rc = dalloc(n, &n->m, n->nparam);
+    if (!rc) rc = dalloc(n, &n->v, n->nparam);
+    if (!rc) rc = dalloc(n, &n->wbf, n->nparam);
+    size_t wmax = 0;
+    for (const Layer &l : n->L) wmax = std::max(wmax, (size_t)l.cin * l.k * l.k * l.cout);
+    if (!rc) rc = dalloc(n, &n->wflip, wmax);
+    if (!rc) rc = dalloc(n, &n->loss_s, 1);
+    if (!rc) rc = dalloc(n, &n->pred, 3 * P0);
+    if (!rc) rc = dalloc(n, &n->dpred, 3 * P0);
+    if (rc) { fd_destroy(n); return -2; }
+    (void)hipMemset(n->params, 0, n->nparam * sizeof(float));
+    (void)hipMemset(n->m, 0, n->nparam * sizeof(float));
+    (void)hipMemset(n->v, 0, n->nparam * sizeof(float));
+    if (hipDeviceSynchronize() != hipSuccess) { fd_destroy(n); return -3; }
+    *out = n;
+    return 0;
+}
+
+int fd_set_stream(fd_net *n, void *s) {
+    if (!n) return -1;
+    n->stream = (hipStream_t)s;
+    return 0;
+}
+
+int64_t fd_num_params(const fd_net *n) { return n ? (int64_t)n->nparam : -1; }
+
+int fd_layer_shape(const fd_net *n, int32_t i, int32_t *cin, int32_t *cout, int32_t *k) {
+    if (!n || i < 0 || i >= (int)n->L.size()) return -1;
+    if (cin) *cin = n->L[i].cin;
+    if (cout) *cout = n->L[i].cout;
+    if (k) *k = n->L[i].k;
+    return 0;
+}
+
+int fd_set_params(fd_net *n, const float *p) {
+    if (!n) return -1;
+    n->err.clear();
+    if (!p) return fail(n, -1, "fd_set_params: null params");
+    HIPCK(n, hipMemcpyAsync(n->params, p, n->nparam * sizeof(float), hipMemcpyDeviceToDevice, n->stream));
+    HIPCK(n, hipMemsetAsync(n->m, 0, n->nparam * sizeof(float), n->stream));
+    HIPCK(n, hipMemsetAsync(n->v, 0, n->nparam * sizeof(float), n->stream));
+    n->step = 0;
+    return 0;
+}
+
+int fd_get_params(const fd_net *n, float *p) {
+    if (!n || !p) return -1;
+    if (hipMemcpyAsync(p, n->params, n->nparam * sizeof(float), hipMemcpyDeviceToDevice, n->stream) != hipSuccess) return -3;
+    return 0;
+}
+
+int fd_forward(fd_net *n, const float *rgb, const float *aux, float *out) {
+    if (!n) return -1;
+    n->err.clear();
+    if (!rgb || !aux || !out) return fail(n, -1, "fd_forward: null argument");
+    forward(n, rgb, aux);
+    int cnt = 3 * pix(n, 0);
+    hipLaunchKernelGGL(k_expm1, dim3(nblk(cnt, 256)), dim3(256), 0, n->stream, cnt, n->pred, out);
+    HIPCK(n, hipGetLastError());
+    return 0;
+}
+
+int fd_train_step(fd_net *n, const float *rgb, const float *aux, const float *target, float lr, float *loss,
+                  float *grads) {
+    if (!n) return -1;
+    n->err.clear();
+    if (!rgb || !aux || !target) return fail(n, -1, "fd_train_step: null argument");
+    if (!std::isfinite(lr)) return fail(n, -1, "fd_train_step: non-finite lr");
+    forward(n, rgb, aux);
+    int cnt = 3 * pix(n, 0);
+    float *lp = loss ? loss : n->loss_s;
+    hipLaunchKernelGGL(k_zero_f, dim3(1), dim3(64), 0, n->stream, (size_t)1, lp);
+    hipLaunchKernelGGL(k_loss, dim3(nblk(cnt, 256)), dim3(256), 0, n->stream, cnt, n->pred, target, n->dpred, lp);
+    backward(n);
+    if (grads) HIPCK(n, hipMemcpyAsync(grads, n->grads, n->nparam * sizeof(float), hipMemcpyDeviceToDevice, n->stream));
+    ++n->step;
+    float c1 = (float)(1.0 - std::pow(0.9, n->step)), c2 = (float)(1.0 - std::pow(0.999, n->step));
+    hipLaunchKernelGGL(k_adam, dim3(nblk(n->nparam, 256)), dim3(256), 0, n->stream, n->nparam, n->params, n->grads, n->m,
+                       n->v, lr, c1, c2);
+    HIPCK(n, hipGetLastError());
+    return 0;
+}
+
+const char *fd_last_error(const fd_net *n) { return n ? n->err.c_str() : "null network"; }
+
+void fd_destroy(fd_net *n) {
+    if (!n) return;
+    if (n->stream) (void)hipStreamSynchronize(n->stream); else (void)hipDeviceSynchronize();
+    for (void *p : n->allocs) (void)hipFree(p);
+    delete n;
+}
+
+}  // extern "C"

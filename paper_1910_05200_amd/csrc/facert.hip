@@ -1283,6 +1283,38 @@ __global__ __launch_bounds__(BS) void k_loss_final(int nb, const double *__restr
 // Camera samples per chunk of the forward wavefront (24 B of records each).
 // A render that fits in one chunk leaves its records for the adjoint; a
 // larger one (very high spp) has them recomputed chunk by chunk.
+// -------------------------------------------------- auxiliary buffers --
+// Per pixel, the mean over its samples of the first hit's albedo (RGB, the
+// interpolated vertex albedo), unit shading normal (turned toward the
+// camera) and distance from the camera; a miss contributes zeros.  One lane
+// per pixel, reading the render's hit records (its samples are adjacent).
+__global__ __launch_bounds__(256) void k_aov(Scene S, int spp, const HitRec *__restrict__ hits, float *__restrict__ out) {
+    int pix = blockIdx.x * blockDim.x + threadIdx.x;
+    if (pix >= S.W * S.H) return;
+    const v3 cam = mk(S.cam_x, S.cam_y, S.cam_z);
+    float acc[7] = {0, 0, 0, 0, 0, 0, 0};
+    for (int k = 0; k < spp; ++k) {
+        HitRec rec = hits[(size_t)pix * spp + k];
+        if (rec.tri < 0) continue;
+        Hit h = hit_of(rec);
+        SurfDec sd;
+        surf_decide(S, cam, h, sd);
+        const int *tr = S.faces + 3 * h.tri;
+        float b1 = h.b1, b2 = h.b2, b0 = (1.0f - b1) - b2;
+        for (int c = 0; c < 3; ++c) {
+            const float *A = S.alb + (size_t)c * S.V;
+            acc[c] += (b0 * A[tr[0]] + b1 * A[tr[1]]) + b2 * A[tr[2]];
+        }
+        float nl = sqrtf(dot(sd.nu, sd.nu));
+        float sg = sd.front ? 1.0f : -1.0f;
+        if (nl > 0.0f) { acc[3] += sg * sd.nu.x / nl; acc[4] += sg * sd.nu.y / nl; acc[5] += sg * sd.nu.z / nl; }
+        v3 r = sd.p - cam;
+        acc[6] += sqrtf(dot(r, r));
+    }
+    float inv = 1.0f / (float)spp;
+    for (int c = 0; c < 7; ++c) out[(size_t)pix * 7 + c] = acc[c] * inv;
+}
+
 // ------------------------------------------------------------ fitting --
 // Light regulariser of the objective (Eq. 1): E_light = sum_j |l_j - m_j|^2
 // with m_j the mean of light j's three channels, times w2.  Its gradient
@@ -1982,6 +2014,18 @@ int fr_backward(fr_ctx *c, const float *dLdI, const fr_grads *g) {
     ev_record(c, 6);
     HIPCK(c, hipGetLastError());
     c->have_backward = true;
+    return FR_OK;
+}
+
+int fr_aov(fr_ctx *c, float *out) {
+    if (!c) return FR_EINVAL;
+    c->err.clear();
+    if (!out) return fail(c, FR_EINVAL, "fr_aov: null output");
+    if (!c->have_render || !c->records_valid)
+        return fail(c, FR_ESTATE, "fr_aov: needs a prior fr_render whose samples fit one chunk");
+    Scene S = make_scene(c);
+    hipLaunchKernelGGL(k_aov, dim3(nblk((size_t)c->W * c->H, 256)), dim3(256), 0, c->stream, S, c->last_spp, c->hits, out);
+    HIPCK(c, hipGetLastError());
     return FR_OK;
 }
 

@@ -1,0 +1,269 @@
+"""Learned denoiser for low-spp renders (binding of libfadenoise.so, training
+and evaluation driver).
+
+The paper names the ray tracer's sampling rate as its limitation: few
+samples give a noisy render, many give slow optimisation (Results and
+Conclusion paragraph).  The denoiser maps a low-spp render plus its albedo,
+normal and depth buffers (fr_aov) to an estimate of the converged image.
+Training pairs come from the renderer itself: a low-spp render of a random
+scene and a high-spp render of the same scene.
+
+    python -m paper_1910_05200_amd.denoise --pairs 400 --epochs 6
+
+trains from a seeded initialisation and prints one JSON line: training time,
+loss curve, and for held-out scenes the PSNR (against a 1024-spp reference)
+of the denoised 2-spp image beside plain renders at 2..256 spp, with the
+time each takes.
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes as C
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+if __package__ in (None, ""):
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+
+from paper_1910_05200_amd import facert, synth
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfadenoise.so")
+EXPORTS = ("fd_create", "fd_set_stream", "fd_num_params", "fd_layer_shape", "fd_set_params", "fd_get_params",
+           "fd_forward", "fd_train_step", "fd_last_error", "fd_destroy")
+
+_lib = None
+
+
+def load():
+    """Load libfadenoise.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise FileNotFoundError(f"{LIB_PATH} is missing: build it with `python -m paper_1910_05200_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        vp, i32 = C.c_void_p, C.c_int32
+        L.fd_create.argtypes = [i32, i32, C.POINTER(vp)]
+        L.fd_set_stream.argtypes = [vp, vp]
+        L.fd_num_params.argtypes = [vp]
+        L.fd_num_params.restype = C.c_int64
+        L.fd_layer_shape.argtypes = [vp, i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]
+        L.fd_set_params.argtypes = [vp, vp]
+        L.fd_get_params.argtypes = [vp, vp]
+        L.fd_forward.argtypes = [vp, vp, vp, vp]
+        L.fd_train_step.argtypes = [vp, vp, vp, vp, C.c_float, vp, vp]
+        L.fd_last_error.argtypes = [vp]
+        L.fd_last_error.restype = C.c_char_p
+        L.fd_destroy.argtypes = [vp]
+        L.fd_destroy.restype = None
+        for n in ("fd_create", "fd_set_stream", "fd_layer_shape", "fd_set_params", "fd_get_params", "fd_forward",
+                  "fd_train_step"):
+            getattr(L, n).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+class FdError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"fadenoise error {code}: {msg}")
+        self.code = code
+
+
+def _ptr(t):
+    return None if t is None else t.data_ptr()
+
+
+class Denoiser:
+    """One network for H x W images; tensors are float32 on the device."""
+
+    def __init__(self, height: int, width: int):
+        import torch
+        self.torch = torch
+        self.H, self.W = height, width
+        net = C.c_void_p()
+        code = load().fd_create(height, width, C.byref(net))
+        if code != 0:
+            raise FdError(code, "fd_create failed")
+        self.net = net
+        self.n_params = int(load().fd_num_params(net))
+
+    def close(self):
+        if getattr(self, "net", None):
+            load().fd_destroy(self.net)
+            self.net = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, code):
+        if code != 0:
+            raise FdError(code, load().fd_last_error(self.net).decode())
+
+    def _stream(self):
+        self._check(load().fd_set_stream(self.net, C.c_void_p(self.torch.cuda.current_stream().cuda_stream)))
+
+    def layer_shapes(self):
+        out, i = [], 0
+        ci, co, k = C.c_int32(), C.c_int32(), C.c_int32()
+        while load().fd_layer_shape(self.net, i, C.byref(ci), C.byref(co), C.byref(k)) == 0:
+            out.append((ci.value, co.value, k.value))
+            i += 1
+        return out
+
+    def set_params(self, params):
+        self._stream()
+        p = params.contiguous()
+        assert p.numel() == self.n_params and p.dtype == self.torch.float32 and p.is_cuda
+        self._check(load().fd_set_params(self.net, _ptr(p)))
+
+    def get_params(self):
+        self._stream()
+        p = self.torch.empty(self.n_params, device="cuda", dtype=self.torch.float32)
+        self._check(load().fd_get_params(self.net, _ptr(p)))
+        return p
+
+    def forward(self, rgb, aux, out=None):
+        self._stream()
+        if out is None:
+            out = self.torch.empty((self.H, self.W, 3), device="cuda", dtype=self.torch.float32)
+        self._check(load().fd_forward(self.net, _ptr(rgb.contiguous()), _ptr(aux.contiguous()), _ptr(out)))
+        return out
+
+    def train_step(self, rgb, aux, target, lr: float, want_grads: bool = False):
+        self._stream()
+        loss = self.torch.empty((), device="cuda", dtype=self.torch.float32)
+        g = self.torch.empty(self.n_params, device="cuda", dtype=self.torch.float32) if want_grads else None
+        self._check(load().fd_train_step(self.net, _ptr(rgb.contiguous()), _ptr(aux.contiguous()),
+                                         _ptr(target.contiguous()), float(lr), _ptr(loss), _ptr(g)))
+        return (loss, g) if want_grads else loss
+
+
+def init_params(shapes, seed: int = 0) -> np.ndarray:
+    """He-normal weights (fan-in k*k*Cin), zero biases; the first layer's
+    weights on the six unused input channels are zero."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for i, (ci, co, k) in enumerate(shapes):
+        w = rng.normal(0.0, math.sqrt(2.0 / (k * k * ci)), (co, k * k, ci))
+        if i == len(shapes) - 1:
+            w *= 0.1                        # start the output near zero
+        if i == 0:
+            w[:, :, 10:] = 0.0
+        parts += [w.ravel(), np.zeros(co)]
+    return np.concatenate(parts).astype(np.float32)
+
+
+def psnr(img, ref) -> float:
+    img = np.asarray(img, np.float64)
+    ref = np.asarray(ref, np.float64)
+    mse = float(np.mean((img - ref) ** 2))
+    peak = float(ref.max())
+    return float("inf") if mse == 0 else 10.0 * math.log10(peak * peak / mse)
+
+
+def scene_params(i: int) -> synth.Params:
+    """Training/evaluation scene i: a fresh identity, expression, albedo,
+    pose and light set from the generator's parameter distribution."""
+    return synth.make_params(10_000 + i)
+
+
+def render_pair(r: facert.Renderer, i: int, spp_in: int, spp_ref: int, seed: int):
+    """(low-spp render, its auxiliary buffers, high-spp render) of scene i."""
+    p = facert.params_to_device(scene_params(i))
+    ref = r.render(p, seed + 1, spp_ref).clone()
+    rgb = r.render(p, seed, spp_in).clone()
+    aux = r.aov()
+    return rgb, aux, ref
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--pairs", type=int, default=400)
+    ap.add_argument("--epochs", type=int, default=6)
+    ap.add_argument("--spp-in", type=int, default=2)
+    ap.add_argument("--spp-target", type=int, default=256)
+    ap.add_argument("--spp-ref", type=int, default=1024)
+    ap.add_argument("--eval", type=int, default=4, help="held-out scenes")
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--seed", type=int, default=0)
+    args = ap.parse_args()
+    import torch
+    assert torch.cuda.is_available(), "the denoiser needs a HIP device"
+    model, scene, _, _ = synth.workload("paper")
+    r = facert.Renderer(model, scene)
+    dn = Denoiser(scene.height, scene.width)
+    dn.set_params(torch.from_numpy(init_params(dn.layer_shapes(), args.seed)).cuda())
+    t0 = time.perf_counter()
+    pairs = [render_pair(r, i, args.spp_in, args.spp_target, 50_000 + 7 * i) for i in range(args.pairs)]
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t0
+    rng = np.random.default_rng(args.seed)
+    losses = []
+    steps = args.epochs * args.pairs
+    t0 = time.perf_counter()
+    for ep in range(args.epochs):
+        for k in rng.permutation(args.pairs):
+            step = len(losses)
+            lr = args.lr * 0.5 * (1.0 + math.cos(math.pi * step / steps))      # cosine decay
+            rgb, aux, ref = pairs[k]
+            losses.append(dn.train_step(rgb, aux, ref, lr))
+        print(f"epoch {ep}: loss {float(torch.stack(losses[-args.pairs:]).mean()):.5f}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    curve = [float(x) for x in torch.stack(losses).reshape(args.epochs, -1).mean(1)]
+    del pairs
+
+    # held-out evaluation against a 1024-spp reference
+    spps = [2, 4, 8, 16, 32, 64, 128, 256]
+    res = {"plain": {s: [] for s in spps}, "denoised": []}
+    timing = {}
+
+    def timed(fn, reps=5):
+        fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) / reps * 1e3
+
+    for e in range(args.eval):
+        i = 1_000_000 + e
+        p = facert.params_to_device(scene_params(i))
+        ref = r.render(p, 7, args.spp_ref).cpu().numpy()
+        for s in spps:
+            res["plain"][s].append(psnr(r.render(p, 99, s).cpu().numpy(), ref))
+        rgb = r.render(p, 99, args.spp_in).clone()
+        aux = r.aov()
+        res["denoised"].append(psnr(dn.forward(rgb, aux).cpu().numpy(), ref))
+        if e == 0:
+            for s in spps:
+                timing[f"render_{s}spp_ms"] = timed(lambda: r.render(p, 99, s))
+            timing["denoise_ms"] = timed(lambda: dn.forward(rgb, aux))
+            timing["aov_ms"] = timed(lambda: r.aov())
+    plain = {s: float(np.mean(v)) for s, v in res["plain"].items()}
+    den = float(np.mean(res["denoised"]))
+    # the plain sample count whose PSNR the denoised 2-spp image matches (log-linear interpolation)
+    equiv = None
+    for a, b in zip(spps, spps[1:]):
+        if plain[a] <= den <= plain[b]:
+            f = (den - plain[a]) / (plain[b] - plain[a])
+            equiv = float(2 ** (math.log2(a) + f * (math.log2(b) - math.log2(a))))
+    if equiv is None and den > plain[spps[-1]]:
+        equiv = f">{spps[-1]}"
+    out = {"pairs": args.pairs, "epochs": args.epochs, "spp_in": args.spp_in, "spp_target": args.spp_target,
+           "data_s": t_data, "train_s": t_train, "ms_per_train_step": t_train / steps * 1e3, "loss_per_epoch": curve,
+           "psnr_db": {"denoised_2spp": den, "plain": plain}, "equal_psnr_plain_spp": equiv, "timing": timing}
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

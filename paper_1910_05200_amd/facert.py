@@ -68,7 +68,7 @@ KERNELS = ("k_fwd_camera", "k_fwd_shadow", "k_fwd_shade", "k_render_adj", "k_edg
 
 
 EXPORTS = ("fr_create", "fr_set_stream", "fr_set_terms", "fr_set_chunk", "fr_blend", "fr_render", "fr_backward",
-           "fr_loss_l2", "fr_light_reg", "fr_adam", "fr_stats", "fr_last_error", "fr_destroy")
+           "fr_loss_l2", "fr_aov", "fr_light_reg", "fr_adam", "fr_stats", "fr_last_error", "fr_destroy")
 
 _lib = None
 
@@ -90,6 +90,7 @@ def load():
         L.fr_render.argtypes = [vp, C.POINTER(fr_params), u64, i32, vp]
         L.fr_backward.argtypes = [vp, vp, C.POINTER(fr_grads)]
         L.fr_loss_l2.argtypes = [vp] * 5
+        L.fr_aov.argtypes = [vp, vp]
         L.fr_light_reg.argtypes = [vp, vp, C.c_float, vp, vp]
         L.fr_adam.argtypes = [vp, vp, vp, vp, vp, i32, i32, C.c_float, C.c_float, C.c_float, C.c_float]
         L.fr_stats.argtypes = [vp, C.POINTER(fr_stats_t)]
@@ -221,6 +222,15 @@ class Renderer:
         loss = t.empty((), device=image.device, dtype=t.float32)
         _check(self.ctx, load().fr_loss_l2(self.ctx, _ptr(image), _ptr(target), _ptr(dL), _ptr(loss)))
         return dL, loss
+
+    def aov(self, out=None):
+        """Albedo, shading normal and depth of the last render, [H][W][7]."""
+        t = self.torch
+        self._stream()
+        if out is None:
+            out = t.empty((self.H, self.W, 7), device="cuda", dtype=t.float32)
+        _check(self.ctx, load().fr_aov(self.ctx, _ptr(out)))
+        return out
 
     def light_reg(self, lights, w2: float, grad=None):
         """w2 E_light (device scalar); adds its gradient to grad when given."""

@@ -1,0 +1,127 @@
+"""Denoiser on the GPU (libfadenoise through its C-ABI) against the oracle
+network.
+
+Two references.  The oracle in its bfloat16 mode rounds where the library
+rounds, so the two differ only in the order and precision of fp32 sums;
+such a difference can move a stored value across a bfloat16 rounding
+boundary (one ulp, 2^-8 relative) now and then, and the change travels on.
+Forward: the bar against it is BAR_EMU of the largest output magnitude,
+element by element.  Gradients are more sensitive: perturbing the oracle's
+own parameters by 1e-7 relative (fp32-level noise) moves its bfloat16-mode
+gradients by up to about 10% in the deepest layers.  So the bar for each
+layer's gradient is relative L2 error <= 3 x that measured self-sensitivity
++ 1e-2.  Against the float64 oracle the bar is BAR_F64: what bfloat16
+storage costs in all.
+"""
+import numpy as np
+import pytest
+
+from oracle import unet
+
+pytestmark = pytest.mark.gpu
+BAR_EMU = 1e-2
+BAR_F64 = 2e-1
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as T
+    if not T.cuda.is_available():
+        pytest.skip("no HIP device")
+    return T
+
+
+def _inputs(H, W, seed):
+    rng = np.random.default_rng(seed)
+    rgb = rng.gamma(0.6, 0.3, (H, W, 3)).astype(np.float32)
+    aux = np.concatenate([rng.uniform(0.2, 0.7, (H, W, 3)), rng.normal(size=(H, W, 3)) * 0.5,
+                          rng.uniform(0.4, 0.6, (H, W, 1))], axis=2).astype(np.float32)
+    tgt = np.clip(rgb + rng.normal(0, 0.05, rgb.shape), 0, None).astype(np.float32)
+    return rgb, aux, tgt
+
+
+def _net(torch, H, W, seed=0):
+    from paper_1910_05200_amd import denoise
+    dn = denoise.Denoiser(H, W)
+    p = denoise.init_params(dn.layer_shapes(), seed)
+    # nonzero biases so that the bias paths are exercised
+    p = p + np.random.default_rng(seed + 1).normal(0, 0.02, p.shape).astype(np.float32)
+    dn.set_params(torch.from_numpy(p).cuda())
+    return dn, p
+
+
+def _rel(got, want):
+    got = np.asarray(got, np.float64)
+    want = np.asarray(want, np.float64)
+    return float(np.abs(got - want).max() / max(np.abs(want).max(), 1e-30))
+
+
+@pytest.mark.parametrize("H,W", [(32, 32), (40, 24), (64, 128)])
+def test_forward_parity(torch, H, W):
+    dn, p = _net(torch, H, W)
+    rgb, aux, _ = _inputs(H, W, H + W)
+    out = dn.forward(torch.from_numpy(rgb).cuda(), torch.from_numpy(aux).cuda())
+    torch.cuda.synchronize()
+    got = np.log1p(out.cpu().numpy())
+    r_emu = _rel(got, np.log1p(unet.denoise(p, rgb, aux, bf16=True)))
+    r_f64 = _rel(got, np.log1p(unet.denoise(p, rgb, aux)))
+    print(f"forward {H}x{W}: max error / max |ref|: bf16 oracle {r_emu:.2e}, fp64 oracle {r_f64:.2e}")
+    assert r_emu <= BAR_EMU and r_f64 <= BAR_F64
+
+
+def _layers():
+    off = 0
+    for i, (ci, co, k) in enumerate(zip(unet.CIN, unet.COUT, unet.KS)):
+        n = co * k * k * ci
+        yield f"{i}w", slice(off, off + n)
+        yield f"{i}b", slice(off + n, off + n + co)
+        off += n + co
+
+
+def _l2(got, want):
+    return float(np.linalg.norm(np.asarray(got, np.float64) - want) / max(np.linalg.norm(want), 1e-30))
+
+
+def test_gradient_parity(torch):
+    H, W = 32, 32
+    dn, p = _net(torch, H, W, seed=3)
+    rgb, aux, tgt = _inputs(H, W, 9)
+    T = lambda a: torch.from_numpy(a).cuda()
+    loss, g = dn.train_step(T(rgb), T(aux), T(tgt), 0.0, want_grads=True)
+    torch.cuda.synchronize()
+    g = g.cpu().numpy()
+    l_emu, g_emu = unet.loss_and_grad(p, rgb, aux, tgt, bf16=True)
+    noise = np.random.default_rng(1).normal(size=p.shape) * 1e-7
+    _, g_pert = unet.loss_and_grad(p.astype(np.float64) * (1 + noise), rgb, aux, tgt, bf16=True)
+    l_f64, g_f64 = unet.loss_and_grad(p, rgb, aux, tgt)
+    assert abs(float(loss) - l_emu) <= BAR_EMU * l_emu and abs(float(loss) - l_f64) <= BAR_F64 * l_f64
+    rows, bad = [], []
+    for name, sl in _layers():
+        sens = _l2(g_pert[sl], g_emu[sl])
+        e_emu, e_f64 = _l2(g[sl], g_emu[sl]), _l2(g[sl], g_f64[sl])
+        rows.append(f"{name}:{e_emu:.1e}/{sens:.1e}/{e_f64:.1e}")
+        if e_emu > 3 * sens + 1e-2 or e_f64 > BAR_F64:
+            bad.append(rows[-1])
+    print("relative L2 error per layer (vs bf16 oracle / oracle self-sensitivity / vs fp64):", " ".join(rows))
+    assert not bad, bad
+
+
+def test_training_reduces_the_loss(torch):
+    H, W = 64, 64
+    dn, _ = _net(torch, H, W, seed=5)
+    rgb, aux, tgt = _inputs(H, W, 11)
+    T = lambda a: torch.from_numpy(a).cuda()
+    losses = [float(dn.train_step(T(rgb), T(aux), T(tgt), 1e-3)) for _ in range(40)]
+    assert losses[-1] < 0.7 * losses[0], losses[::8]
+
+
+def test_bad_arguments(torch):
+    from paper_1910_05200_amd import denoise
+    import ctypes as C
+    lib = denoise.load()
+    out = C.c_void_p()
+    assert lib.fd_create(30, 32, C.byref(out)) == -1 and not out.value       # not a multiple of 8
+    dn = denoise.Denoiser(16, 16)
+    with pytest.raises(denoise.FdError):
+        dn.train_step(torch.zeros(16, 16, 3, device="cuda"), torch.zeros(16, 16, 7, device="cuda"),
+                      torch.zeros(16, 16, 3, device="cuda"), float("nan"))
