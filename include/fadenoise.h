@@ -9,12 +9,14 @@
  * ReLU per level; 2x2 average pooling down, nearest 2x upsampling and
  * channel concatenation of the skip up; a 1x1 output convolution) that maps
  * a low-spp render plus its albedo, normal and depth buffers to an estimate
- * of the converged image.  Radiance enters and leaves in log(1 + x).
+ * of the converged image.  Radiance enters as log(1 + 16 x) (a fixed
+ * exposure that brings the light stage's pixel values to order one), and
+ * the output convolution predicts a correction of that input log-radiance.
  *
  * Convolutions run as implicit GEMMs on the matrix cores in bfloat16 with
- * fp32 accumulation (activations and their gradients bfloat16, weights kept
- * in fp32 with bfloat16 copies); training uses Adam on a squared-error loss
- * in log(1 + x).
+ * fp32 accumulation (activations bfloat16, their gradients fp32 and rounded
+ * to bfloat16 where they enter a product, weights kept in fp32 with bfloat16
+ * copies); training uses Adam on a squared-error loss in log(1 + 16 x).
  *
  * Conventions: status 0 on success, negative on failure (FD_EINVAL -1,
  * FD_ENOMEM -2, FD_EDEVICE -3), message in fd_last_error; nothing throws.
@@ -64,7 +66,7 @@ int fd_get_params(const fd_net *net, float *params);
 int fd_forward(fd_net *net, const float *rgb, const float *aux, float *out);
 
 /* One training step on one image pair: forward, loss
- * mean over pixels and channels of (pred - log(1 + target))^2 with pred the
+ * mean over pixels and channels of (pred - log(1 + 16 target))^2 with pred the
  * network's log-radiance, backward, one Adam step (lr, betas 0.9 / 0.999,
  * eps 1e-8) on all parameters.  *loss_dev (device float, may be NULL) gets
  * the loss before the update.  grads (device, [fd_num_params], may be NULL)

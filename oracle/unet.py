@@ -15,11 +15,13 @@ gradients stay unrounded).  Sums are exact (float64) in both modes.  This
 is the network at the precision the library computes in, so the library can
 be held to it tightly; the float64 mode bounds what bfloat16 costs.
 
-Network: input channels log(1 + rgb), albedo, normal, depth, zero-padded to
-16; per level two 3x3 convolutions (zero padding) with leaky ReLU (slope
+Network: input channels log(1 + 16 rgb), albedo, normal, depth, zero-padded
+to 16; per level two 3x3 convolutions (zero padding) with leaky ReLU (slope
 0.01), channels 32, 64, 128, 256; 2x2 average pooling down; nearest 2x
 upsampling, then concatenation [upsampled, skip] up; a 1x1 output
-convolution gives log-radiance.  Loss: mean of (pred - log(1 + target))^2.
+convolution gives a correction added to the input's log(1 + 16 rgb).
+Output radiance expm1(pred) / 16.  Loss: mean of (pred - log(1 + 16
+target))^2.
 """
 from __future__ import annotations
 
@@ -28,6 +30,7 @@ import torch
 import torch.nn.functional as F
 
 SLOPE = 0.01
+EXPOSURE = 16.0
 CIN = [16, 32, 32, 64, 64, 128, 128, 256, 384, 128, 192, 64, 96, 32, 32]
 COUT = [32, 32, 64, 64, 128, 128, 256, 256, 128, 128, 64, 64, 32, 32, 3]
 KS = [3] * 14 + [1]
@@ -54,7 +57,7 @@ def pack_input(rgb, aux):
     aux = torch.as_tensor(np.asarray(aux, np.float64))
     H, W = rgb.shape[:2]
     x = torch.zeros(1, 16, H, W, dtype=torch.float64)
-    x[0, :3] = torch.log1p(rgb.clamp(min=0)).permute(2, 0, 1)
+    x[0, :3] = torch.log1p(EXPOSURE * rgb.clamp(min=0)).permute(2, 0, 1)
     x[0, 3:10] = aux.permute(2, 0, 1)
     return x
 
@@ -98,7 +101,9 @@ class _PoolBF16(torch.autograd.Function):
 
 
 def forward(layers, x, bf16=False):
-    """log-radiance [1][3][H][W] for input x [1][16][H][W]."""
+    """log-radiance [1][3][H][W] for input x [1][16][H][W] (its first three
+    channels, unrounded, are the log-radiance the output corrects)."""
+    x_log = x[:, :3]
     def conv(i, t, act=True):
         w, b = layers[i]
         if bf16 and act:
@@ -117,14 +122,14 @@ def forward(layers, x, bf16=False):
     d2 = conv(9, conv(8, torch.cat([up(e3), e2], 1)))
     d1 = conv(11, conv(10, torch.cat([up(d2), e1], 1)))
     d0 = conv(13, conv(12, torch.cat([up(d1), e0], 1)))
-    return conv(14, d0, act=False)
+    return x_log + conv(14, d0, act=False)
 
 
 def denoise(params, rgb, aux, bf16=False):
     """Radiance [H][W][3] (numpy float64)."""
     with torch.no_grad():
         pred = forward(unpack(params), pack_input(rgb, aux), bf16)
-    return torch.expm1(pred)[0].permute(1, 2, 0).numpy()
+    return (torch.expm1(pred) / EXPOSURE)[0].permute(1, 2, 0).numpy()
 
 
 def loss_and_grad(params, rgb, aux, target, bf16=False):
@@ -138,7 +143,7 @@ def loss_and_grad(params, rgb, aux, target, bf16=False):
         layers.append((w, p[off:off + co]))
         off += co
     pred = forward(layers, pack_input(rgb, aux), bf16)
-    tgt = torch.log1p(torch.as_tensor(np.asarray(target, np.float64)).clamp(min=0)).permute(2, 0, 1)[None]
+    tgt = torch.log1p(EXPOSURE * torch.as_tensor(np.asarray(target, np.float64)).clamp(min=0)).permute(2, 0, 1)[None]
     loss = ((pred - tgt) ** 2).mean()
     loss.backward()
     return float(loss), p.grad.numpy().copy()

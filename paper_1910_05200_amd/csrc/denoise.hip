@@ -34,6 +34,9 @@ __device__ __forceinline__ bf16 f2bf(float f) {        // round to nearest even
 }
 
 constexpr float kSlope = 0.01f;    // leaky ReLU
+// Radiance enters as log(1 + kExposure x): the light stage's pixel values
+// are a few hundredths, and this brings them to order one.
+constexpr float kExposure = 16.0f;
 constexpr int kTM = 64, kTN = 64, kKC = 16;   // GEMM tile, reduction step (channels)
 
 // ------------------------------------------------------------ conv 3x3 --
@@ -178,7 +181,7 @@ __global__ void k_pack_input(int P, const float *__restrict__ rgb, const float *
     int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= P) return;
     bf16 *o = x + (size_t)p * 16;
-    for (int c = 0; c < 3; ++c) o[c] = f2bf(log1pf(fmaxf(rgb[3 * p + c], 0.0f)));
+    for (int c = 0; c < 3; ++c) o[c] = f2bf(log1pf(kExposure * fmaxf(rgb[3 * p + c], 0.0f)));
     for (int c = 0; c < FD_IN_AUX; ++c) o[3 + c] = f2bf(aux[FD_IN_AUX * p + c]);
     for (int c = 3 + FD_IN_AUX; c < 16; ++c) o[c] = 0;
 }
@@ -233,28 +236,29 @@ __global__ void k_act_bwd(size_t n, const bf16 *__restrict__ y, float *__restric
     if (!(bf2f(y[i]) > 0.0f)) g[i] *= kSlope;
 }
 
-// 1x1 output convolution (fp32): pred[p][k] = b[k] + sum_c w[k][c] x[p][c]
+// 1x1 output convolution (fp32) as a correction of the input's
+// log-radiance: pred[p][k] = log(1 + kExposure rgb[p][k]) + b[k] + sum_c w[k][c] x[p][c]
 __global__ void k_out_fwd(int P, int C, const bf16 *__restrict__ x, const float *__restrict__ w, const float *__restrict__ b,
-                          float *__restrict__ pred) {
+                          const float *__restrict__ rgb, float *__restrict__ pred) {
     int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= P) return;
     for (int k = 0; k < 3; ++k) {
         float s = b[k];
         for (int c = 0; c < C; ++c) s += w[k * C + c] * bf2f(x[(size_t)p * C + c]);
-        pred[3 * p + k] = s;
+        pred[3 * p + k] = log1pf(kExposure * fmaxf(rgb[3 * p + k], 0.0f)) + s;
     }
 }
 __global__ void k_expm1(int n, const float *__restrict__ pred, float *__restrict__ out) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) out[i] = expm1f(pred[i]);
+    if (i < n) out[i] = expm1f(pred[i]) / kExposure;
 }
-// loss and its gradient: d = pred - log(1 + target); loss += d^2 / n; dpred = 2 d / n
+// loss and its gradient: d = pred - log(1 + kExposure target); loss += d^2 / n; dpred = 2 d / n
 __global__ __launch_bounds__(256) void k_loss(int n, const float *__restrict__ pred, const float *__restrict__ tgt,
                                              float *__restrict__ dpred, float *__restrict__ loss) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     float e = 0.0f;
     if (i < n) {
-        float d = pred[i] - log1pf(fmaxf(tgt[i], 0.0f));
+        float d = pred[i] - log1pf(kExposure * fmaxf(tgt[i], 0.0f));
         dpred[i] = 2.0f * d / (float)n;
         e = d * d / (float)n;
     }
@@ -410,7 +414,7 @@ static void forward(fd_net *n, const float *rgb, const float *aux) {
     conv(n, 13, n->d0a, n->d0.y, 32, 0, true);
     const Layer &lo = n->L[14];
     hipLaunchKernelGGL(k_out_fwd, dim3(nblk(P0, 256)), dim3(256), 0, s, P0, 32, n->d0.y, n->params + lo.woff,
-                       n->params + lo.boff, n->pred);
+                       n->params + lo.boff, rgb, n->pred);
 }
 
 static void backward(fd_net *n) {

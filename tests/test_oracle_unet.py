@@ -47,7 +47,7 @@ def test_pool_upsample_concat_semantics():
 
 
 def test_input_packing():
-    rgb = np.full((8, 8, 3), np.e - 1)
+    rgb = np.full((8, 8, 3), (np.e - 1) / unet.EXPOSURE)
     aux = np.arange(7.0)[None, None, :] * np.ones((8, 8, 1))
     x = unet.pack_input(rgb, aux)
     assert x.shape == (1, 16, 8, 8)
