@@ -74,6 +74,15 @@ int fd_forward(fd_net *net, const float *rgb, const float *aux, float *out);
 int fd_train_step(fd_net *net, const float *rgb, const float *aux, const float *target, float lr,
                   float *loss_dev, float *grads);
 
+/* Gradient through the denoiser of the last fd_forward: dL_dout [H][W][3]
+ * (the loss gradient with respect to that call's output radiance) ->
+ * dL_drgb [H][W][3] (with respect to its rgb input, which must be passed
+ * again, unchanged).  Parameters do not change.  This lets a fitting loop
+ * take its data term on the denoised image and hand the renderer's adjoint
+ * the gradient on the low-spp render.  Errors: -1 null argument, -4 no
+ * prior fd_forward. */
+int fd_backward_input(fd_net *net, const float *rgb, const float *dL_dout, float *dL_drgb);
+
 const char *fd_last_error(const fd_net *net);
 void fd_destroy(fd_net *net);
 

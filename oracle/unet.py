@@ -21,7 +21,9 @@ to 16; per level two 3x3 convolutions (zero padding) with leaky ReLU (slope
 upsampling, then concatenation [upsampled, skip] up; a 1x1 output
 convolution gives a correction added to the input's log(1 + 16 rgb).
 Output radiance expm1(pred) / 16.  Loss: mean of (pred - log(1 + 16
-target))^2.
+target))^2.  input_grad is the gradient of a loss on the output with
+respect to the rgb input (the packed input's rounding passed straight
+through, as the library does).
 """
 from __future__ import annotations
 
@@ -113,7 +115,7 @@ def forward(layers, x, bf16=False):
 
     pool = _PoolBF16.apply if bf16 else (lambda t: F.avg_pool2d(t, 2))
     if bf16:
-        x = bf16_round(x)
+        x = x + (bf16_round(x) - x).detach()     # rounded value, gradient passed straight through
     e0 = conv(1, conv(0, x))
     e1 = conv(3, conv(2, pool(e0)))
     e2 = conv(5, conv(4, pool(e1)))
@@ -147,3 +149,15 @@ def loss_and_grad(params, rgb, aux, target, bf16=False):
     loss = ((pred - tgt) ** 2).mean()
     loss.backward()
     return float(loss), p.grad.numpy().copy()
+
+
+def input_grad(params, rgb, aux, dL_dout, bf16=False):
+    """d/d rgb of sum(dL_dout * denoised radiance), [H][W][3] float64."""
+    rgb_t = torch.tensor(np.asarray(rgb, np.float64), requires_grad=True)
+    x = torch.zeros(1, 16, *rgb_t.shape[:2], dtype=torch.float64)
+    x = torch.cat([torch.log1p(EXPOSURE * rgb_t.clamp(min=0)).permute(2, 0, 1)[None],
+                   torch.as_tensor(np.asarray(aux, np.float64)).permute(2, 0, 1)[None], x[:, 10:]], 1)
+    pred = forward(unpack(params), x, bf16)
+    out = (torch.expm1(pred) / EXPOSURE)[0].permute(1, 2, 0)
+    (out * torch.as_tensor(np.asarray(dL_dout, np.float64))).sum().backward()
+    return rgb_t.grad.numpy().copy()

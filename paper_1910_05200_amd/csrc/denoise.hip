@@ -287,6 +287,22 @@ __global__ __launch_bounds__(256) void k_out_bwd(int P, int C, const bf16 *__res
     for (int k = threadIdx.x; k < 3; k += blockDim.x) if (sw[3 * C + k] != 0.0f) atomicAdd(&db[k], sw[3 * C + k]);
 }
 
+// d loss / d pred from d loss / d out, out = expm1(pred) / kExposure
+__global__ void k_dout_dpred(int n, const float *__restrict__ pred, const float *__restrict__ gout, float *__restrict__ dpred) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dpred[i] = gout[i] * expf(pred[i]) / kExposure;
+}
+// d loss / d rgb: the residual path and the packed input's first three
+// channels, through log(1 + kExposure rgb) (zero where rgb < 0)
+__global__ void k_drgb(int P, const float *__restrict__ rgb, const float *__restrict__ dpred, const float *__restrict__ gx0,
+                       float *__restrict__ drgb) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= 3 * P) return;
+    int p = i / 3, k = i % 3;
+    float x = rgb[i];
+    drgb[i] = x < 0.0f ? 0.0f : (dpred[i] + gx0[(size_t)p * 16 + k]) * kExposure / (1.0f + kExposure * x);
+}
+
 // Adam (Kingma and Ba 2015) over all parameters
 __global__ void k_adam(size_t n, float *__restrict__ p, const float *__restrict__ g, float *__restrict__ m,
                        float *__restrict__ v, float lr, float c1, float c2) {
@@ -319,6 +335,7 @@ struct fd_net {
     float *params = nullptr, *grads = nullptr, *m = nullptr, *v = nullptr;
     bf16 *wbf = nullptr, *wflip = nullptr;      // bf16 copies of all conv weights, flipped scratch
     int step = 0;
+    bool have_forward = false;
     // activations (see build()), index by name
     Act x0, e0a, e0, p1, e1a, e1, p2, e2a, e2, p3, e3a, e3, c2, d2a, d2, c1, d1a, d1, c0, d0a, d0;
     float *pred = nullptr, *dpred = nullptr, *loss_s = nullptr;
@@ -356,12 +373,15 @@ static int conv(fd_net *n, int li, const Act &x, bf16 *y, int ldy, int yoff, boo
 // backward of conv layer li: g_out (bf16 [P][cout], already multiplied by
 // the activation's derivative) -> weight and bias gradients, and (when gx)
 // the input gradient gx [P][cin].
-static void conv_bwd(fd_net *n, int li, const Act &x, const float *gout, float *gx) {
+static void conv_bwd(fd_net *n, int li, const Act &x, const float *gout, float *gx, bool wgrad) {
     const Layer &l = n->L[li];
     int H = n->H >> l.level, W = n->W >> l.level, P = H * W;
-    dim3 gw(nblk(l.cout, kTN), nblk(l.cin, kTN), 9 * nblk(P, kWChunk));
-    hipLaunchKernelGGL(k_conv3x3_wgrad, gw, dim3(256), 0, n->stream, H, W, l.cin, l.cout, x.y, gout, n->grads + l.woff);
-    hipLaunchKernelGGL(k_bias_grad, dim3(nblk(P, 256)), dim3(256), 0, n->stream, P, l.cout, gout, n->grads + l.boff);
+    if (wgrad) {
+        dim3 gw(nblk(l.cout, kTN), nblk(l.cin, kTN), 9 * nblk(P, kWChunk));
+        hipLaunchKernelGGL(k_conv3x3_wgrad, gw, dim3(256), 0, n->stream, H, W, l.cin, l.cout, x.y, gout,
+                           n->grads + l.woff);
+        hipLaunchKernelGGL(k_bias_grad, dim3(nblk(P, 256)), dim3(256), 0, n->stream, P, l.cout, gout, n->grads + l.boff);
+    }
     if (gx) {
         hipLaunchKernelGGL(k_flip_weights, dim3(nblk((size_t)l.cin * 9 * l.cout, 256)), dim3(256), 0, n->stream,
                            l.cin, l.cout, n->params + l.woff, n->wflip);
@@ -417,7 +437,9 @@ static void forward(fd_net *n, const float *rgb, const float *aux) {
                        n->params + lo.boff, rgb, n->pred);
 }
 
-static void backward(fd_net *n) {
+// wgrad: parameter gradients into n->grads; input: the input's gradient
+// into x0.g (channels of the packed input)
+static void backward(fd_net *n, bool wgrad, bool input) {
     const int P0 = pix(n, 0);
     hipStream_t s = n->stream;
     hipLaunchKernelGGL(k_zero_f, dim3(nblk(n->nparam, 256)), dim3(256), 0, s, n->nparam, n->grads);
@@ -435,26 +457,26 @@ static void backward(fd_net *n) {
         int H = n->H >> x.level, W = n->W >> x.level;
         hipLaunchKernelGGL(k_pool2_bwd_add, dim3(nblk((size_t)H * W * x.c, 256)), dim3(256), 0, s, H, W, x.c, py.g, x.g);
     };
-    act_bwd(n, n->d0);  conv_bwd(n, 13, n->d0a, n->d0.g, n->d0a.g);
-    act_bwd(n, n->d0a); conv_bwd(n, 12, n->c0, n->d0a.g, n->c0.g);
+    act_bwd(n, n->d0);  conv_bwd(n, 13, n->d0a, n->d0.g, n->d0a.g, wgrad);
+    act_bwd(n, n->d0a); conv_bwd(n, 12, n->c0, n->d0a.g, n->c0.g, wgrad);
     split(n->c0, n->d1, n->e0);
-    act_bwd(n, n->d1);  conv_bwd(n, 11, n->d1a, n->d1.g, n->d1a.g);
-    act_bwd(n, n->d1a); conv_bwd(n, 10, n->c1, n->d1a.g, n->c1.g);
+    act_bwd(n, n->d1);  conv_bwd(n, 11, n->d1a, n->d1.g, n->d1a.g, wgrad);
+    act_bwd(n, n->d1a); conv_bwd(n, 10, n->c1, n->d1a.g, n->c1.g, wgrad);
     split(n->c1, n->d2, n->e1);
-    act_bwd(n, n->d2);  conv_bwd(n, 9, n->d2a, n->d2.g, n->d2a.g);
-    act_bwd(n, n->d2a); conv_bwd(n, 8, n->c2, n->d2a.g, n->c2.g);
+    act_bwd(n, n->d2);  conv_bwd(n, 9, n->d2a, n->d2.g, n->d2a.g, wgrad);
+    act_bwd(n, n->d2a); conv_bwd(n, 8, n->c2, n->d2a.g, n->c2.g, wgrad);
     split(n->c2, n->e3, n->e2);
-    act_bwd(n, n->e3);  conv_bwd(n, 7, n->e3a, n->e3.g, n->e3a.g);
-    act_bwd(n, n->e3a); conv_bwd(n, 6, n->p3, n->e3a.g, n->p3.g);
+    act_bwd(n, n->e3);  conv_bwd(n, 7, n->e3a, n->e3.g, n->e3a.g, wgrad);
+    act_bwd(n, n->e3a); conv_bwd(n, 6, n->p3, n->e3a.g, n->p3.g, wgrad);
     pool_bwd(n->p3, n->e2);
-    act_bwd(n, n->e2);  conv_bwd(n, 5, n->e2a, n->e2.g, n->e2a.g);
-    act_bwd(n, n->e2a); conv_bwd(n, 4, n->p2, n->e2a.g, n->p2.g);
+    act_bwd(n, n->e2);  conv_bwd(n, 5, n->e2a, n->e2.g, n->e2a.g, wgrad);
+    act_bwd(n, n->e2a); conv_bwd(n, 4, n->p2, n->e2a.g, n->p2.g, wgrad);
     pool_bwd(n->p2, n->e1);
-    act_bwd(n, n->e1);  conv_bwd(n, 3, n->e1a, n->e1.g, n->e1a.g);
-    act_bwd(n, n->e1a); conv_bwd(n, 2, n->p1, n->e1a.g, n->p1.g);
+    act_bwd(n, n->e1);  conv_bwd(n, 3, n->e1a, n->e1.g, n->e1a.g, wgrad);
+    act_bwd(n, n->e1a); conv_bwd(n, 2, n->p1, n->e1a.g, n->p1.g, wgrad);
     pool_bwd(n->p1, n->e0);
-    act_bwd(n, n->e0);  conv_bwd(n, 1, n->e0a, n->e0.g, n->e0a.g);
-    act_bwd(n, n->e0a); conv_bwd(n, 0, n->x0, n->e0a.g, nullptr);
+    act_bwd(n, n->e0);  conv_bwd(n, 1, n->e0a, n->e0.g, n->e0a.g, wgrad);
+    act_bwd(n, n->e0a); conv_bwd(n, 0, n->x0, n->e0a.g, input ? n->x0.g : nullptr, wgrad);
 }
 
 extern "C" {
@@ -546,6 +568,7 @@ int fd_forward(fd_net *n, const float *rgb, const float *aux, float *out) {
     n->err.clear();
     if (!rgb || !aux || !out) return fail(n, -1, "fd_forward: null argument");
     forward(n, rgb, aux);
+    n->have_forward = true;
     int cnt = 3 * pix(n, 0);
     hipLaunchKernelGGL(k_expm1, dim3(nblk(cnt, 256)), dim3(256), 0, n->stream, cnt, n->pred, out);
     HIPCK(n, hipGetLastError());
@@ -559,16 +582,30 @@ int fd_train_step(fd_net *n, const float *rgb, const float *aux, const float *ta
     if (!rgb || !aux || !target) return fail(n, -1, "fd_train_step: null argument");
     if (!std::isfinite(lr)) return fail(n, -1, "fd_train_step: non-finite lr");
     forward(n, rgb, aux);
+    n->have_forward = false;     // activations now belong to this step, not to an fd_forward
     int cnt = 3 * pix(n, 0);
     float *lp = loss ? loss : n->loss_s;
     hipLaunchKernelGGL(k_zero_f, dim3(1), dim3(64), 0, n->stream, (size_t)1, lp);
     hipLaunchKernelGGL(k_loss, dim3(nblk(cnt, 256)), dim3(256), 0, n->stream, cnt, n->pred, target, n->dpred, lp);
-    backward(n);
+    backward(n, true, false);
     if (grads) HIPCK(n, hipMemcpyAsync(grads, n->grads, n->nparam * sizeof(float), hipMemcpyDeviceToDevice, n->stream));
     ++n->step;
     float c1 = (float)(1.0 - std::pow(0.9, n->step)), c2 = (float)(1.0 - std::pow(0.999, n->step));
     hipLaunchKernelGGL(k_adam, dim3(nblk(n->nparam, 256)), dim3(256), 0, n->stream, n->nparam, n->params, n->grads, n->m,
                        n->v, lr, c1, c2);
+    HIPCK(n, hipGetLastError());
+    return 0;
+}
+
+int fd_backward_input(fd_net *n, const float *rgb, const float *dL_dout, float *dL_drgb) {
+    if (!n) return -1;
+    n->err.clear();
+    if (!rgb || !dL_dout || !dL_drgb) return fail(n, -1, "fd_backward_input: null argument");
+    if (!n->have_forward) return fail(n, -4, "fd_backward_input: no prior fd_forward");
+    int P = pix(n, 0), cnt = 3 * P;
+    hipLaunchKernelGGL(k_dout_dpred, dim3(nblk(cnt, 256)), dim3(256), 0, n->stream, cnt, n->pred, dL_dout, n->dpred);
+    backward(n, false, true);
+    hipLaunchKernelGGL(k_drgb, dim3(nblk(cnt, 256)), dim3(256), 0, n->stream, P, rgb, n->dpred, n->x0.g, dL_drgb);
     HIPCK(n, hipGetLastError());
     return 0;
 }

@@ -35,7 +35,7 @@ from paper_1910_05200_amd import facert, synth
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libfadenoise.so")
 EXPORTS = ("fd_create", "fd_set_stream", "fd_num_params", "fd_layer_shape", "fd_set_params", "fd_get_params",
-           "fd_forward", "fd_train_step", "fd_last_error", "fd_destroy")
+           "fd_forward", "fd_train_step", "fd_backward_input", "fd_last_error", "fd_destroy")
 
 _lib = None
 
@@ -57,12 +57,13 @@ def load():
         L.fd_get_params.argtypes = [vp, vp]
         L.fd_forward.argtypes = [vp, vp, vp, vp]
         L.fd_train_step.argtypes = [vp, vp, vp, vp, C.c_float, vp, vp]
+        L.fd_backward_input.argtypes = [vp, vp, vp, vp]
         L.fd_last_error.argtypes = [vp]
         L.fd_last_error.restype = C.c_char_p
         L.fd_destroy.argtypes = [vp]
         L.fd_destroy.restype = None
         for n in ("fd_create", "fd_set_stream", "fd_layer_shape", "fd_set_params", "fd_get_params", "fd_forward",
-                  "fd_train_step"):
+                  "fd_train_step", "fd_backward_input"):
             getattr(L, n).restype = C.c_int
         _lib = L
     return _lib
@@ -135,6 +136,14 @@ class Denoiser:
         if out is None:
             out = self.torch.empty((self.H, self.W, 3), device="cuda", dtype=self.torch.float32)
         self._check(load().fd_forward(self.net, _ptr(rgb.contiguous()), _ptr(aux.contiguous()), _ptr(out)))
+        return out
+
+    def backward_input(self, rgb, dL_dout, out=None):
+        """Gradient with respect to the rgb input of the last forward."""
+        self._stream()
+        if out is None:
+            out = self.torch.empty((self.H, self.W, 3), device="cuda", dtype=self.torch.float32)
+        self._check(load().fd_backward_input(self.net, _ptr(rgb.contiguous()), _ptr(dL_dout.contiguous()), _ptr(out)))
         return out
 
     def train_step(self, rgb, aux, target, lr: float, want_grads: bool = False):

@@ -120,6 +120,22 @@ def test_training_reduces_the_loss(torch):
     assert losses[-1] < 0.8 * losses[0] and losses[-1] < min(losses[:10]), losses[::8]
 
 
+def test_input_gradient_parity(torch):
+    """fd_backward_input against the oracle's gradient with respect to the
+    rgb input (relative L2; the chain runs through every layer)."""
+    H, W = 32, 32
+    dn, p = _net(torch, H, W, seed=7)
+    rgb, aux, _ = _inputs(H, W, 13)
+    gout = np.random.default_rng(2).normal(size=(H, W, 3)).astype(np.float32)
+    T = lambda a: torch.from_numpy(a).cuda()
+    dn.forward(T(rgb), T(aux))
+    g = dn.backward_input(T(rgb), T(gout)).cpu().numpy()
+    e_emu = _l2(g, unet.input_grad(p, rgb, aux, gout, bf16=True))
+    e_f64 = _l2(g, unet.input_grad(p, rgb, aux, gout))
+    print(f"input gradient relative L2: bf16 oracle {e_emu:.2e}, fp64 oracle {e_f64:.2e}")
+    assert e_emu <= 5e-2 and e_f64 <= BAR_F64
+
+
 def test_bad_arguments(torch):
     from paper_1910_05200_amd import denoise
     import ctypes as C
@@ -130,3 +146,6 @@ def test_bad_arguments(torch):
     with pytest.raises(denoise.FdError):
         dn.train_step(torch.zeros(16, 16, 3, device="cuda"), torch.zeros(16, 16, 7, device="cuda"),
                       torch.zeros(16, 16, 3, device="cuda"), float("nan"))
+    with pytest.raises(denoise.FdError) as e:            # no fd_forward yet
+        dn.backward_input(torch.zeros(16, 16, 3, device="cuda"), torch.zeros(16, 16, 3, device="cuda"))
+    assert e.value.code == -4
