@@ -193,6 +193,33 @@ def render_pair(r: facert.Renderer, i: int, spp_in: int, spp_ref: int, seed: int
     return rgb, aux, ref
 
 
+def train(r: facert.Renderer, dn: Denoiser, pairs: int, epochs: int, spp_in: int = 2, spp_target: int = 256,
+          lr: float = 1e-3, seed: int = 0, log=sys.stderr):
+    """Seeded initialisation, renderer-generated pairs, Adam with a cosine
+    decaying step.  Returns (data seconds, training seconds, loss per epoch)."""
+    import torch
+    dn.set_params(torch.from_numpy(init_params(dn.layer_shapes(), seed)).cuda())
+    t0 = time.perf_counter()
+    data = [render_pair(r, i, spp_in, spp_target, 50_000 + 7 * i) for i in range(pairs)]
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t0
+    rng = np.random.default_rng(seed)
+    losses = []
+    steps = epochs * pairs
+    t0 = time.perf_counter()
+    for ep in range(epochs):
+        for k in rng.permutation(pairs):
+            step = len(losses)
+            rgb, aux, ref = data[k]
+            losses.append(dn.train_step(rgb, aux, ref, lr * 0.5 * (1.0 + math.cos(math.pi * step / steps))))
+        if log:
+            print(f"epoch {ep}: loss {float(torch.stack(losses[-pairs:]).mean()):.5f}", file=log, flush=True)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    curve = [float(x) for x in torch.stack(losses).reshape(epochs, -1).mean(1)]
+    return t_data, t_train, curve
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--pairs", type=int, default=400)
@@ -209,26 +236,8 @@ def main():
     model, scene, _, _ = synth.workload("paper")
     r = facert.Renderer(model, scene)
     dn = Denoiser(scene.height, scene.width)
-    dn.set_params(torch.from_numpy(init_params(dn.layer_shapes(), args.seed)).cuda())
-    t0 = time.perf_counter()
-    pairs = [render_pair(r, i, args.spp_in, args.spp_target, 50_000 + 7 * i) for i in range(args.pairs)]
-    torch.cuda.synchronize()
-    t_data = time.perf_counter() - t0
-    rng = np.random.default_rng(args.seed)
-    losses = []
+    t_data, t_train, curve = train(r, dn, args.pairs, args.epochs, args.spp_in, args.spp_target, args.lr, args.seed)
     steps = args.epochs * args.pairs
-    t0 = time.perf_counter()
-    for ep in range(args.epochs):
-        for k in rng.permutation(args.pairs):
-            step = len(losses)
-            lr = args.lr * 0.5 * (1.0 + math.cos(math.pi * step / steps))      # cosine decay
-            rgb, aux, ref = pairs[k]
-            losses.append(dn.train_step(rgb, aux, ref, lr))
-        print(f"epoch {ep}: loss {float(torch.stack(losses[-args.pairs:]).mean()):.5f}", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    t_train = time.perf_counter() - t0
-    curve = [float(x) for x in torch.stack(losses).reshape(args.epochs, -1).mean(1)]
-    del pairs
 
     # held-out evaluation against a 1024-spp reference
     spps = [2, 4, 8, 16, 32, 64, 128, 256]

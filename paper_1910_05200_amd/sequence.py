@@ -1,0 +1,189 @@
+"""Sequence fitting: several frames of one face share identity alpha, albedo
+delta, the light colours and the specular texels; each frame has its own
+expression beta and pose (a random walk over the sequence in the synthetic
+truth).  The objective is Eq. 1 without E_prior summed over frames; Adam on
+the shared groups with the frames' gradients summed, and on each frame's
+own groups.
+
+Three ways to get each frame's data-term gradient:
+  plain        render at N spp, E_data against the target, fr_backward;
+  denoised     render at 2 spp, its auxiliary buffers (fr_aov), the
+               denoiser, E_data on the denoised image, the gradient through
+               the denoiser to the 2-spp render (fd_backward_input),
+               fr_backward;
+  denoised-st  as denoised, but the image gradient of E_data on the
+               denoised image goes to the 2-spp render's adjoint as it is
+               (the denoiser treated as the identity in the backward pass).
+The denoiser is trained first on renderer-generated pairs (denoise.py).
+
+    python -m paper_1910_05200_amd.sequence --frames 8 --iters 150 --modes plain:256,plain:16,denoised:2
+
+prints one JSON line per mode: seconds per iteration, parameter errors and
+the frames' mean PSNR (256 spp evaluation) against their targets, logged
+along the run, so that the modes can be compared at equal error.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+if __package__ in (None, ""):
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+
+from paper_1910_05200_amd import denoise, facert, fit, synth
+
+SHARED = ("alpha", "delta", "lights", "spec")
+LR = dict(fit.LR)
+
+
+def make_truth(n_frames: int, seed: int = synth.TARGET_SCENE_SEED):
+    """Shared parameters of one face, and per-frame (beta, pose) on a random walk."""
+    base = synth.make_params(seed)
+    rng = np.random.default_rng(4242 + seed)
+    d2r = math.pi / 180.0
+    frames, beta, pose = [], base.beta.astype(np.float64), base.pose.astype(np.float64)
+    for _ in range(n_frames):
+        frames.append((beta.astype(np.float32), pose.astype(np.float32)))
+        beta = beta + rng.normal(0, 0.15, beta.shape)
+        pose = pose + np.concatenate([rng.normal(0, 1.0, 3) * d2r, rng.normal(0, 0.001, 3)])
+    return base, frames
+
+
+def make_start(base: synth.Params, frames, seed: int = fit.START_SEED):
+    """Perturbed shared parameters and per-frame (beta, pose), as synth.perturb."""
+    start = synth.perturb(base, seed)
+    out = []
+    for f, (beta, pose) in enumerate(frames):
+        q = base.copy()
+        q.beta, q.pose = beta.copy(), pose.copy()
+        q = synth.perturb(q, 1000 + 17 * seed + f)
+        out.append((q.beta, q.pose))
+    return start, out
+
+
+def frame_params(shared: dict, beta, pose) -> dict:
+    d = dict(shared)
+    d["beta"] = beta
+    d["pose"] = pose
+    return d
+
+
+def errors(shared: dict, betas, poses, base: synth.Params, frames) -> dict:
+    e = {}
+    for k in SHARED:
+        a = shared[k].detach().cpu().numpy() if hasattr(shared[k], "detach") else np.asarray(shared[k])
+        e[k] = float(np.sqrt(np.mean((a - getattr(base, k)) ** 2)))
+    b = np.concatenate([np.asarray(x.cpu().numpy() if hasattr(x, "cpu") else x) - t[0] for x, t in zip(betas, frames)])
+    e["beta"] = float(np.sqrt(np.mean(b ** 2)))
+    P = np.array([np.asarray(p.cpu().numpy() if hasattr(p, "cpu") else p, np.float64) for p in poses])
+    T = np.array([t[1] for t in frames], np.float64)
+    e["rot_deg"] = float(np.degrees(np.sqrt(np.mean((P[:, :3] - T[:, :3]) ** 2))))
+    e["trans_mm"] = float(1e3 * np.sqrt(np.mean((P[:, 3:] - T[:, 3:]) ** 2)))
+    return e
+
+
+def run(r: facert.Renderer, targets, base, frames, start, start_frames, iters: int, mode: str, spp: int,
+        dn: denoise.Denoiser = None, eval_spp: int = synth.TARGET_SPP, log_every: int = 25, decay: float = fit.DECAY):
+    import torch
+    shared = facert.params_to_device(start)
+    shared.pop("beta"), shared.pop("pose")
+    betas = [torch.from_numpy(b.copy()).cuda() for b, _ in start_frames]
+    poses = [torch.from_numpy(np.asarray(p, np.float32).copy()).cuda() for _, p in start_frames]
+    st = {k: (torch.zeros_like(shared[k]), torch.zeros_like(shared[k])) for k in SHARED}
+    stf = [((torch.zeros_like(b), torch.zeros_like(b)), (torch.zeros(6, device="cuda"), torch.zeros(6, device="cuda")))
+           for b in betas]
+    want = ("d_alpha", "d_beta", "d_delta", "d_lights", "d_spec", "d_pose")
+    n = len(targets)
+    log, elapsed = [], 0.0
+
+    def evaluate(it):
+        psnrs = []
+        for f in range(n):
+            img = r.render(frame_params(shared, betas[f], poses[f].cpu().numpy()), 99, eval_spp)
+            psnrs.append(fit.psnr(img.cpu().numpy(), targets[f].cpu().numpy()))
+        e = errors(shared, betas, poses, base, frames)
+        log.append({"iter": it, "seconds": elapsed, "psnr_db": float(np.mean(psnrs)), "errors": e})
+
+    evaluate(0)
+    for it in range(iters):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        acc = {k: torch.zeros_like(shared[k]) for k in SHARED}
+        f_lr = decay ** (it / max(1, iters - 1))
+        for f in range(n):
+            p = frame_params(shared, betas[f], poses[f].cpu().numpy())
+            seed = 1000 + it * n + f
+            if mode in ("denoised", "denoised-st"):
+                img = r.render(p, seed, spp)
+                aux = r.aov()
+                den = dn.forward(img, aux)
+                dL, _ = r.loss_l2(den, targets[f])
+                if mode == "denoised":
+                    dL = dn.backward_input(img, dL)
+            else:
+                img = r.render(p, seed, spp)
+                dL, _ = r.loss_l2(img, targets[f])
+            g = r.backward(dL, want=want)
+            for k in SHARED:
+                acc[k] += g["d_" + k].reshape(acc[k].shape)
+            (mb, vb), (mp, vp) = stf[f]
+            r.adam(betas[f], g["d_beta"], mb, vb, it + 1, LR["beta"] * f_lr)
+            r.adam(poses[f][:3], g["d_pose"][:3], mp[:3], vp[:3], it + 1, LR["rot"] * f_lr)
+            r.adam(poses[f][3:], g["d_pose"][3:], mp[3:], vp[3:], it + 1, LR["trans"] * f_lr)
+        r.light_reg(shared["lights"], fit.W2, acc["lights"])
+        for k in SHARED:
+            m, v = st[k]
+            r.adam(shared[k], acc[k], m, v, it + 1, LR[k] * f_lr)
+        torch.cuda.synchronize()
+        elapsed += time.perf_counter() - t0
+        if (it + 1) % log_every == 0 or it == iters - 1:
+            evaluate(it + 1)
+    return {"mode": mode, "spp": spp, "frames": n, "iters": iters, "s_per_iter": elapsed / iters, "log": log}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--frames", type=int, default=8)
+    ap.add_argument("--iters", type=int, default=150)
+    ap.add_argument("--modes", default="plain:256,plain:16,plain:2,denoised:2")
+    ap.add_argument("--workload", default="paper", choices=["paper", "tiny"])
+    ap.add_argument("--dn-pairs", type=int, default=2000)
+    ap.add_argument("--dn-epochs", type=int, default=10)
+    ap.add_argument("--log-every", type=int, default=25)
+    args = ap.parse_args()
+    import torch
+    assert torch.cuda.is_available(), "sequence fitting needs a HIP device"
+    model, scene, _, _ = synth.workload(args.workload)
+    r = facert.Renderer(model, scene)
+    base, frames = make_truth(args.frames)
+    start, start_frames = make_start(base, frames)
+    targets = [r.render(facert.params_to_device(frame_params_np(base, b, p)), synth.TARGET_RENDER_SEED + f,
+                        synth.TARGET_SPP).clone() for f, (b, p) in enumerate(frames)]
+    dn = None
+    modes = [(m.split(":")[0], int(m.split(":")[1])) for m in args.modes.split(",")]
+    if any(m.startswith("denoised") for m, _ in modes):
+        t0 = time.perf_counter()
+        dn = denoise.Denoiser(scene.height, scene.width)
+        denoise.train(r, dn, args.dn_pairs, args.dn_epochs, spp_in=2, spp_target=synth.TARGET_SPP)
+        torch.cuda.synchronize()
+        print(json.dumps({"denoiser_training_s": time.perf_counter() - t0, "pairs": args.dn_pairs,
+                          "epochs": args.dn_epochs}), flush=True)
+    for m, spp in modes:
+        out = run(r, targets, base, frames, start, start_frames, args.iters, m, spp, dn, log_every=args.log_every)
+        print(json.dumps(out), flush=True)
+
+
+def frame_params_np(base: synth.Params, beta, pose) -> synth.Params:
+    q = base.copy()
+    q.beta, q.pose = beta, pose
+    return q
+
+
+if __name__ == "__main__":
+    main()

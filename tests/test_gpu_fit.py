@@ -98,3 +98,23 @@ def test_short_fit_reduces_error(torch, renderer):
     assert np.mean(losses[-5:]) < 0.5 * losses[0]
     assert psnr1 > psnr0 + 2.0
     assert e1["rot_deg"] < e0["rot_deg"]
+
+
+def test_sequence_fit_runs_every_mode(torch):
+    """Two frames with shared identity/albedo/lights, 12 iterations on the
+    tiny workload, plain and both denoised modes: the frames' PSNR rises."""
+    from paper_1910_05200_amd import denoise, facert, sequence
+    model, scene, _, _ = synth.workload("tiny")
+    r = facert.Renderer(model, scene)
+    base, frames = sequence.make_truth(2)
+    start, start_frames = sequence.make_start(base, frames)
+    targets = [r.render(facert.params_to_device(sequence.frame_params_np(base, b, p)), 7 + f, 64).clone()
+               for f, (b, p) in enumerate(frames)]
+    dn = denoise.Denoiser(scene.height, scene.width)
+    denoise.train(r, dn, 8, 1, log=None)
+    for mode, spp in (("plain", 4), ("denoised", 2), ("denoised-st", 2)):
+        out = sequence.run(r, targets, base, frames, start, start_frames, 12, mode, spp, dn, eval_spp=16,
+                           log_every=12)
+        first, last = out["log"][0]["psnr_db"], out["log"][-1]["psnr_db"]
+        print(mode, spp, first, last)
+        assert last > first + 1.0, (mode, first, last)
