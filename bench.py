@@ -61,7 +61,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="paper", choices=["paper", "tiny"])
+    ap.add_argument("--workload", default="paper", choices=["paper", "tiny", "batch"],
+                    help="paper / tiny: one face per step; batch: 32 faces of 5k-40k vertices at 128^2-512^2 and "
+                         "4-16 spp per step, one launch per kernel for all of them")
     ap.add_argument("--bvh", default="lbvh", choices=["lbvh", "refit"],
                     help="lbvh: Morton-code tree rebuilt from the posed mesh every step; refit: tree shape built "
                          "once over the mean shape, boxes refitted every step")
@@ -90,12 +92,130 @@ def cpu_baseline(model, scene, params, target, seed, spp, threads):
                       "same seed and spp"}
 
 
+def _rays(st) -> int:
+    return st["rays_camera"] + st["rays_shadow"] + st["rays_edge_primary"] + st["rays_edge_secondary"]
+
+
+def bench_batch(args):
+    """Many faces per step (fr_batch_*): render, per-face loss, adjoint.
+    Timed four ways: eager batched calls; a HIP graph captured per step (the
+    reported value); replay of one captured step; the single-context calls
+    one face after another (the same work without batching)."""
+    import ctypes as C
+    import torch
+    from paper_1910_05200_amd import facert, synth
+    lib = facert.load()
+    inst = synth.batch_workload()
+    n = len(inst)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        rs = [facert.Renderer(m, sc) for m, sc, _, _ in inst]
+        ps = [facert.params_to_device(p) for _, _, p, _ in inst]
+        spps = [spp for *_, spp in inst]
+        batch = facert.Batch(rs, timing=True)
+        tg = [facert.params_to_device(synth.make_params(900 + i)) for i in range(n)]
+        tgts = [t.clone() for t in batch.render(tg, [77 + i for i in range(n)], spps)]
+        imgs = [torch.empty_like(t) for t in tgts]
+        dls = [torch.empty_like(t) for t in tgts]
+        losses = [torch.empty((), device="cuda") for _ in range(n)]
+        grads = [{k: torch.empty(v, device="cuda") for k, v in
+                  {"d_lights": (r.n_lights, 3), "d_spec": (r.spec_res ** 2,), "d_vertices": (3, r.V),
+                   "d_albedo": (3, r.V), "d_alpha": (r.n_id,), "d_beta": (r.n_exp,), "d_delta": (r.n_alb,),
+                   "d_pose": (6,)}.items()} for r in rs]
+
+        def step(it):
+            batch.render(ps, [1000 + 97 * it + i for i in range(n)], spps, outs=imgs)
+            for r, im, t, d, l in zip(rs, imgs, tgts, dls, losses):
+                facert._check(r.ctx, lib.fr_loss_l2(r.ctx, im.data_ptr(), t.data_ptr(), d.data_ptr(), l.data_ptr()))
+            batch.backward(dls, outs=grads)
+
+        for it in range(args.warmup):
+            step(it)
+        tuned = batch.tune(trials=2)
+        step(0)
+        tm = batch.timing()
+        rays = sum(_rays(r.stats()) for r in rs)
+        stats = [r.stats() for r in rs]
+
+        def timed(fn, k):
+            stream.synchronize()
+            t0 = time.perf_counter()
+            for it in range(k):
+                fn(it)
+            stream.synchronize()
+            return (time.perf_counter() - t0) / k * 1e3
+
+        ms_eager = timed(lambda it: step(args.warmup + it), args.steps)
+
+        def graph_step(it):
+            batch.capture_begin()
+            step(args.warmup + args.steps + it)
+            batch.capture_end()
+            batch.graph_launch()
+
+        graph_step(0)
+        ms_graph = timed(graph_step, args.steps)
+        ms_replay = timed(lambda it: batch.graph_launch(), args.steps)
+
+        def sequential(it):
+            for i, r in enumerate(rs):
+                img = r.render(ps[i], 5000 + 97 * it + i, spps[i], out=imgs[i])
+                facert._check(r.ctx, lib.fr_loss_l2(r.ctx, img.data_ptr(), tgts[i].data_ptr(), dls[i].data_ptr(),
+                                                    losses[i].data_ptr()))
+                r.backward(dls[i])
+
+        sequential(0)
+        ms_seq = timed(sequential, max(2, args.steps // 4))
+    k_sh = facert.KERNELS.index("k_fwd_shadow")
+    ops_sh = sum(st["kernel_box_tests"][k_sh] * OPS_BOX + st["kernel_tri_tests"][k_sh] * OPS_TRI for st in stats)
+    ms_sh = tm["fwd_shadow"]
+    achieved = ops_sh / (ms_sh * 1e-3) / 1e12
+    V = [m.n_vertices for m, *_ in inst]
+    out = {
+        "metric": METRIC,
+        "value": rays / (ms_graph * 1e-3) / 1e6,
+        "unit": "Mrays/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_graph,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"batch: {n} faces per step ({min(V)}-{max(V)} vertices, images "
+                               f"{min(sc.width for _, sc, _, _ in inst)}^2-{max(sc.width for _, sc, _, _ in inst)}^2, "
+                               f"{min(spps)}-{max(spps)} spp, 20 area lights each), render + per-face loss + "
+                               "adjoint (all terms), HIP graph captured per step",
+                   "samples_per_step": int(sum(sc.width * sc.height * spp for _, sc, _, spp in inst)),
+                   "rays_per_step": rays,
+                   "ms_eager": round(ms_eager, 3), "ms_graph_per_step_capture": round(ms_graph, 3),
+                   "ms_graph_replay": round(ms_replay, 3), "ms_sequential_single_context": round(ms_seq, 3),
+                   "batching_speedup_vs_sequential": round(ms_seq / ms_graph, 3),
+                   "ms_render": round(tm["render"], 3), "ms_backward": round(tm["backward"], 3),
+                   "ms_kinds": {k: round(v, 3) for k, v in tm.items() if v > 0.05 and k not in ("render", "backward")},
+                   "tuned": {k: {"mode": ["flat", "xcd"][v[0][0]], "tile": v[0][1], "ms": round(v[1], 3)}
+                             for k, v in tuned.items()}},
+        "roofline": {"bound": "alu", "kernel": "fwd_shadow (batched)", "achieved": achieved, "peak": PEAK_VALU,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_VALU, "traffic": None,
+                     "ops_per_launch": ops_sh, "ms_per_launch": ms_sh},
+    }
+    if not args.no_cpu_baseline:
+        threads = args.cpu_threads or min(16, os.cpu_count() or 1)
+        i = min(range(n), key=lambda k: inst[k][1].width * inst[k][1].height * inst[k][3])
+        m, sc, p, spp = inst[i]
+        cb = cpu_baseline(m, sc, p, np.zeros((sc.height, sc.width, 3)), 1000, spp, threads)
+        cb["sample"] = (f"one full forward+adjoint iteration (all terms) of the batch's smallest face "
+                        f"({m.n_vertices} vertices, {sc.width}x{sc.height}, {spp} spp), same seed and spp")
+        out["cpu_baseline"] = cb
+    batch.close()
+    print(json.dumps(out))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the path shards by image "
               "rows with one gradient all-reduce, which this build does not run)", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "batch":
+        return bench_batch(args)
     import torch
     from paper_1910_05200_amd import facert, synth
 

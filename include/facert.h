@@ -225,6 +225,100 @@ const char *fr_last_error(const fr_ctx *ctx);
 /* Release all device memory of the context (synchronises its stream). */
 void fr_destroy(fr_ctx *ctx);
 
+/* ---- batched evaluation ------------------------------------------------
+ * Many faces at once: fr_render / fr_backward (the estimator F of the
+ * Optimization paragraph and its adjoint) for several contexts together,
+ * each with its own mesh, image size, light stage, parameters, seed and
+ * spp, with one kernel launch per pipeline step for all of them (the
+ * fitting of the paper evaluates one face per iteration; a batch serves a
+ * set of subjects or the frames of a sequence).  Results equal those of
+ * fr_render / fr_backward on each context: images bitwise, gradients up to
+ * the summation order of their atomics.
+ *
+ * A batch borrows its contexts (they must outlive it and must not be used
+ * on their own while a batched call is in flight); after fr_batch_render,
+ * fr_backward and fr_aov on one of its contexts also follow that render.
+ * All work runs on one stream: the contexts' common stream, or the one set
+ * with fr_batch_set_stream (which sets it on every context too).
+ *
+ * Launch modes per kernel kind (kinds 0 .. fr_batch_num_kinds() - 1, named
+ * by fr_batch_kind_name): FR_LAUNCH_FLAT, one block per tile, the tiles in
+ * order; FR_LAUNCH_XCD, one block per tile, the tiles dealt to the eight
+ * XCDs in contiguous eighths.  The shadow-ray kinds also take a tile size
+ * (samples per block: 256 or 512).  fr_batch_tune picks them by
+ * measurement. */
+typedef struct fr_batch fr_batch;
+
+#define FR_LAUNCH_FLAT 0
+#define FR_LAUNCH_XCD 1
+typedef struct {
+    int32_t mode;                    /* FR_LAUNCH_*                            */
+    int32_t tile;                    /* shadow-ray kinds (fwd_shadow,
+                                        edge_secondary, edge_primary_vis): 256
+                                        or 512; 0 for the others               */
+} fr_launch;
+
+/* n contexts (1..4096, distinct, created without FR_REFIT).  flags:
+ * FR_TIMING (per-kind times, needed by fr_batch_timing / fr_batch_tune).
+ * Errors: FR_EINVAL, FR_ENOMEM.  *out is NULL on error. */
+int fr_batch_create(int32_t n, fr_ctx *const *ctx, uint32_t flags, fr_batch **out);
+int fr_batch_set_stream(fr_batch *batch, void *hip_stream);
+
+/* Render every instance: params[n], seeds[n] (host), spp[n] (host, each
+ * with W*H*spp <= FR_CHUNK_MAX), out[n] image pointers (host array of
+ * device pointers, [H][W][3] each).  A new set of spp values reallocates
+ * scratch and synchronises; the same set again does not.  Errors: FR_EINVAL
+ * (null or out-of-range arguments, a context on another stream), FR_ESTATE
+ * (new spp values during graph capture), FR_ENOMEM. */
+int fr_batch_render(fr_batch *batch, const fr_params *params, const uint64_t *seeds, const int32_t *spp,
+                    float *const *out);
+
+/* Adjoint of the last fr_batch_render: dL_dimage[n] (host array of device
+ * pointers), grads[n] (as fr_backward's, each output nullable).  Errors:
+ * FR_ESTATE (no batched render, or a context rendered on its own since),
+ * FR_EINVAL (null arguments). */
+int fr_batch_backward(fr_batch *batch, const float *const *dL_dimage, const fr_grads *grads);
+
+int32_t fr_batch_num_kinds(void);
+const char *fr_batch_kind_name(int32_t kind);   /* NULL out of range */
+int fr_batch_get_launch(const fr_batch *batch, int32_t kind, fr_launch *out);
+/* Errors: FR_EINVAL (kind, mode or tile out of range), FR_ESTATE (during
+ * graph capture). */
+int fr_batch_set_launch(fr_batch *batch, int32_t kind, const fr_launch *launch);
+
+/* Autotuner: replays the last fr_batch_render + fr_batch_backward (same
+ * inputs and outputs, which the caller keeps alive; the outputs are written
+ * again with the same values up to atomics order) once per candidate
+ * launch of each tunable kind, 'trials' times (1..16), and keeps the
+ * fastest candidate of each.  ms_best [fr_batch_num_kinds()] (host,
+ * nullable) gets each kind's best time (0 for kinds not tuned).
+ * Synchronises.  Errors: FR_ESTATE (no FR_TIMING, no prior backward,
+ * during capture), FR_EINVAL. */
+int fr_batch_tune(fr_batch *batch, int32_t trials, float *ms_best);
+
+/* Times of the last batched calls (synchronises): ms_kind
+ * [fr_batch_num_kinds()] (host, nullable) per kind from its first to its
+ * last launch; whole render and backward.  Errors: FR_ESTATE without
+ * FR_TIMING. */
+int fr_batch_timing(fr_batch *batch, float *ms_kind, float *ms_render, float *ms_backward);
+
+/* HIP graph of one iteration: between fr_batch_capture_begin and
+ * fr_batch_capture_end, batched calls (and fr_loss_l2 / fr_adam /
+ * fr_light_reg on the batch's contexts, which share its stream) are
+ * recorded instead of run; capture_end instantiates the graph, or updates
+ * the previous one in place when only arguments changed, and
+ * fr_batch_graph_launch runs it.  A graph holds its calls' arguments
+ * (seeds, poses, pointers) by value.  The batch must have run once with the
+ * same spp values before a capture, on a stream other than the null
+ * stream.  Errors: FR_ESTATE (order of calls), FR_EDEVICE. */
+int fr_batch_capture_begin(fr_batch *batch);
+int fr_batch_capture_end(fr_batch *batch);
+int fr_batch_graph_launch(fr_batch *batch);
+
+const char *fr_batch_last_error(const fr_batch *batch);
+/* Release the batch (synchronises its stream); its contexts stay. */
+void fr_batch_destroy(fr_batch *batch);
+
 #ifdef __cplusplus
 }
 #endif

@@ -55,13 +55,15 @@ using namespace fr;
 // k_pose: v = R v_model + t (fp64).  Everything is rounded to fp32 once.
 struct PoseArgs { double R[9]; double t[3]; };
 
-__global__ __launch_bounds__(64) void k_blend(int V, int n_id, int n_exp, int n_alb,
+// Every kernel's work is a body over one block-sized tile (bx, by): the
+// __global__ wrappers below run one instance with the tile taken from the
+// grid, the multi-instance launcher (k_multi) runs the tiles of many.
+__device__ __forceinline__ void blend_body(int V, int n_id, int n_exp, int n_alb,
         const float *__restrict__ mean, const float *__restrict__ b_id, const float *__restrict__ b_exp,
         const float *__restrict__ alb_mean, const float *__restrict__ b_alb,
         const float *__restrict__ alpha, const float *__restrict__ beta, const float *__restrict__ delta,
-        double *__restrict__ vm_d, float *__restrict__ vmodel, float *__restrict__ alb) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    int row = blockIdx.y;
+        double *__restrict__ vm_d, float *__restrict__ vmodel, float *__restrict__ alb, int bx, int row) {
+    int i = bx * blockDim.x + threadIdx.x;
     if (i >= V) return;
     size_t V3 = (size_t)3 * V;
     if (row < 3) {
@@ -81,10 +83,18 @@ __global__ __launch_bounds__(64) void k_blend(int V, int n_id, int n_exp, int n_
         alb[e] = (float)acc;
     }
 }
+__global__ __launch_bounds__(64) void k_blend(int V, int n_id, int n_exp, int n_alb,
+        const float *__restrict__ mean, const float *__restrict__ b_id, const float *__restrict__ b_exp,
+        const float *__restrict__ alb_mean, const float *__restrict__ b_alb,
+        const float *__restrict__ alpha, const float *__restrict__ beta, const float *__restrict__ delta,
+        double *__restrict__ vm_d, float *__restrict__ vmodel, float *__restrict__ alb) {
+    blend_body(V, n_id, n_exp, n_alb, mean, b_id, b_exp, alb_mean, b_alb, alpha, beta, delta, vm_d, vmodel, alb,
+               blockIdx.x, blockIdx.y);
+}
 
-__global__ __launch_bounds__(256) void k_pose(int V, const double *__restrict__ vm_d, PoseArgs P,
-                                              float *__restrict__ pos) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void pose_body(int V, const double *__restrict__ vm_d, const PoseArgs &P,
+                                          float *__restrict__ pos, int bx) {
+    int i = bx * blockDim.x + threadIdx.x;
     if (i >= V) return;
     double m[3] = {vm_d[i], vm_d[V + i], vm_d[2 * (size_t)V + i]};
     for (int c = 0; c < 3; ++c) {
@@ -92,14 +102,18 @@ __global__ __launch_bounds__(256) void k_pose(int V, const double *__restrict__ 
         pos[(size_t)c * V + i] = (float)v;
     }
 }
+__global__ __launch_bounds__(256) void k_pose(int V, const double *__restrict__ vm_d, PoseArgs P,
+                                              float *__restrict__ pos) {
+    pose_body(V, vm_d, P, pos, blockIdx.x);
+}
 
 // ---------------------------------------------------------- normals -----
 // n_k = normalize(sum over incident faces, ascending index, of
 // (v1 - v0) x (v2 - v0)), fp64 from the fp32 positions, rounded to fp32.
-__global__ __launch_bounds__(256) void k_normals(int V, const int *__restrict__ faces,
+__device__ __forceinline__ void normals_body(int V, const int *__restrict__ faces,
         const int *__restrict__ vf_off, const int *__restrict__ vf_idx,
-        const float *__restrict__ pos, float *__restrict__ nrm, float *__restrict__ nlen) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+        const float *__restrict__ pos, float *__restrict__ nrm, float *__restrict__ nlen, int bx) {
+    int i = bx * blockDim.x + threadIdx.x;
     if (i >= V) return;
     double sx = 0.0, sy = 0.0, sz = 0.0;
     for (int q = vf_off[i]; q < vf_off[i + 1]; ++q) {
@@ -115,6 +129,11 @@ __global__ __launch_bounds__(256) void k_normals(int V, const int *__restrict__ 
     if (l > 0.0) { sx = sx / l; sy = sy / l; sz = sz / l; }
     nrm[i] = (float)sx; nrm[V + i] = (float)sy; nrm[2 * V + i] = (float)sz;
     nlen[i] = (float)l;
+}
+__global__ __launch_bounds__(256) void k_normals(int V, const int *__restrict__ faces,
+        const int *__restrict__ vf_off, const int *__restrict__ vf_idx,
+        const float *__restrict__ pos, float *__restrict__ nrm, float *__restrict__ nlen) {
+    normals_body(V, faces, vf_off, vf_idx, pos, nrm, nlen, blockIdx.x);
 }
 
 // ------------------------------------------------------------ refit -----
@@ -183,9 +202,9 @@ __device__ __forceinline__ bool project(const Scene &S, v3 x, float &sx, float &
 
 // weights: table 0 = camera silhouettes (screen length), table 1+j = shadow
 // candidates of light j (3D length).
-__global__ __launch_bounds__(256) void k_edge_weights(Scene S, const float *__restrict__ lgeom,
-        float *__restrict__ w) {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void edge_weights_body(const Scene &S, const float *__restrict__ lgeom,
+        float *__restrict__ w, int tb) {
+    const int e = tb * blockDim.x + threadIdx.x;
     if (e >= S.E) return;
     const int *ed = S.edges + 4 * e;
     v3 a = vpos(S, ed[0]), b = vpos(S, ed[1]);
@@ -227,6 +246,10 @@ __global__ __launch_bounds__(256) void k_edge_weights(Scene S, const float *__re
         w[(size_t)(1 + j) * E + e] = cand ? l3 : 0.0f;
     }
 }
+__global__ __launch_bounds__(256) void k_edge_weights(Scene S, const float *__restrict__ lgeom,
+        float *__restrict__ w) {
+    edge_weights_body(S, lgeom, w, blockIdx.x);
+}
 
 // One block per table: the table's max weight wmax (block reduction), then
 // q = 1 + floor(w / wmax * 2^20) for w > 0, exclusive uint64 prefix in edge
@@ -236,9 +259,9 @@ __global__ __launch_bounds__(256) void k_edge_weights(Scene S, const float *__re
 // sums: the grouping does not change them).
 constexpr int kScanIt = 4;
 template <int BS>
-__global__ __launch_bounds__(BS) void k_edge_scan(int E, const float *__restrict__ w, int *__restrict__ out_edge, uint64_t *__restrict__ out_prefix, int *__restrict__ out_n, uint64_t *__restrict__ out_Q) {
+__device__ __forceinline__ void edge_scan_body(int E, const float *__restrict__ w, int *__restrict__ out_edge,
+        uint64_t *__restrict__ out_prefix, int *__restrict__ out_n, uint64_t *__restrict__ out_Q, int tbl) {
     constexpr int NW = BS / 64;
-    const int tbl = blockIdx.x;
     const float *wt = w + (size_t)tbl * E;
     int *oe = out_edge + (size_t)tbl * E;
     uint64_t *op = out_prefix + (size_t)tbl * E;
@@ -294,6 +317,10 @@ __global__ __launch_bounds__(BS) void k_edge_scan(int E, const float *__restrict
         __syncthreads();
     }
     if (threadIdx.x == 0) { out_n[tbl] = nbase; out_Q[tbl] = base; }
+}
+template <int BS>
+__global__ __launch_bounds__(BS) void k_edge_scan(int E, const float *__restrict__ w, int *__restrict__ out_edge, uint64_t *__restrict__ out_prefix, int *__restrict__ out_n, uint64_t *__restrict__ out_Q) {
+    edge_scan_body<BS>(E, w, out_edge, out_prefix, out_n, out_Q, blockIdx.x);
 }
 
 // ------------------------------------------------------ LDS staging -----
@@ -362,9 +389,9 @@ __device__ __forceinline__ Hit hit_of(HitRec r) {
     return h;
 }
 
-__global__ __launch_bounds__(256) void k_fwd_camera(Scene S, uint64_t seed, int spp, long long s0, long long n,
-        HitRec *__restrict__ hits, unsigned long long *__restrict__ vis, unsigned long long *ctr) {
-    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void fwd_camera_body(const Scene &S, uint64_t seed, int spp, long long s0, long long n,
+        HitRec *__restrict__ hits, unsigned long long *__restrict__ vis, unsigned long long *ctr, int bx) {
+    long long i = (long long)bx * blockDim.x + threadIdx.x;
     uint32_t n_cam = 0;
     Work wk;
     if (i < n) {
@@ -380,6 +407,10 @@ __global__ __launch_bounds__(256) void k_fwd_camera(Scene S, uint64_t seed, int 
     flush_count(ctr, 0, n_cam);
     flush_work(ctr, wk);
 }
+__global__ __launch_bounds__(256) void k_fwd_camera(Scene S, uint64_t seed, int spp, long long s0, long long n,
+        HitRec *__restrict__ hits, unsigned long long *__restrict__ vis, unsigned long long *ctr) {
+    fwd_camera_body(S, seed, spp, s0, n, hits, vis, ctr, blockIdx.x);
+}
 
 // Shadow rays are compacted before they are traced: a block takes a tile of
 // kShTile consecutive samples for one light, its lanes run the horizon test
@@ -387,21 +418,23 @@ __global__ __launch_bounds__(256) void k_fwd_camera(Scene S, uint64_t seed, int 
 // wave), and the block's waves then trace the list 64 entries at a time.
 // About a third of the (sample, light) pairs need a ray at the paper's
 // framing (camera misses and lights below the horizon need none), so
-// tracing in place would leave two lanes in three idle.
+// tracing in place would leave two lanes in three idle.  The tile size is a
+// template parameter of the bodies (single-instance launches use kShTile;
+// the batched launcher may pick another).
 constexpr int kShTile = 512;
 __device__ __forceinline__ int lanes_below(unsigned long long m) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0));
 }
 
-__global__ __launch_bounds__(256) void k_fwd_shadow(Scene S, uint64_t seed, long long s0, long long n,
-        const HitRec *__restrict__ hits, unsigned long long *__restrict__ vis, unsigned long long *ctr) {
-    __shared__ float4 q_o[kShTile];   // origin p, hit triangle
-    __shared__ float4 q_d[kShTile];   // y - p, tile-local sample index
+template <int TS>
+__device__ __forceinline__ void fwd_shadow_body(const Scene &S, uint64_t seed, long long s0, long long n,
+        const HitRec *__restrict__ hits, unsigned long long *__restrict__ vis, unsigned long long *ctr, int bx, int j) {
+    __shared__ float4 q_o[TS];   // origin p, hit triangle
+    __shared__ float4 q_d[TS];   // y - p, tile-local sample index
     __shared__ int q_n;
     if (threadIdx.x == 0) q_n = 0;
     __syncthreads();
-    const int j = blockIdx.y;
-    const long long base = (long long)blockIdx.x * kShTile;
+    const long long base = (long long)bx * TS;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     uint32_t n_sh = 0;
     Work wk;
@@ -409,7 +442,7 @@ __global__ __launch_bounds__(256) void k_fwd_shadow(Scene S, uint64_t seed, long
     Light L;
     L.c = mk(g[0], g[1], g[2]); L.e1 = mk(g[3], g[4], g[5]); L.e2 = mk(g[6], g[7], g[8]);
     const v3 cam = mk(S.cam_x, S.cam_y, S.cam_z);
-    for (int k = 0; k < kShTile; k += 256) {
+    for (int k = 0; k < TS; k += 256) {
         const int li = k + (int)threadIdx.x;
         const long long i = base + li;
         bool need = false;
@@ -451,16 +484,20 @@ __global__ __launch_bounds__(256) void k_fwd_shadow(Scene S, uint64_t seed, long
     flush_count(ctr, 1, n_sh);
     flush_work(ctr, wk);
 }
+__global__ __launch_bounds__(256) void k_fwd_shadow(Scene S, uint64_t seed, long long s0, long long n,
+        const HitRec *__restrict__ hits, unsigned long long *__restrict__ vis, unsigned long long *ctr) {
+    fwd_shadow_body<kShTile>(S, seed, s0, n, hits, vis, ctr, blockIdx.x, blockIdx.y);
+}
 
-__global__ __launch_bounds__(256) void k_fwd_shade(Scene S, uint64_t seed, int spp, long long s0, long long n,
+__device__ __forceinline__ void fwd_shade_body(const Scene &S, uint64_t seed, int spp, long long s0, long long n,
         const HitRec *__restrict__ hits, const unsigned long long *__restrict__ vis,
-        float *__restrict__ samples, unsigned long long *ctr) {
+        float *__restrict__ samples, unsigned long long *ctr, int bx) {
     extern __shared__ float dyn[];
     __shared__ Light Ls[kMaxLights];
     float *spec_lds = dyn;
     stage_tables(S, Ls, spec_lds);
     __syncthreads();
-    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    long long i = (long long)bx * blockDim.x + threadIdx.x;
     Work wk;
     if (i < n) {
         HitRec rec = hits[i];
@@ -494,15 +531,24 @@ __global__ __launch_bounds__(256) void k_fwd_shade(Scene S, uint64_t seed, int s
     }
     flush_work(ctr, wk);
 }
+__global__ __launch_bounds__(256) void k_fwd_shade(Scene S, uint64_t seed, int spp, long long s0, long long n,
+        const HitRec *__restrict__ hits, const unsigned long long *__restrict__ vis,
+        float *__restrict__ samples, unsigned long long *ctr) {
+    fwd_shade_body(S, seed, spp, s0, n, hits, vis, samples, ctr, blockIdx.x);
+}
 
-__global__ __launch_bounds__(256) void k_pixel_mean(int npix, int spp, const float *__restrict__ samples, float *__restrict__ img) {
-    int p = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void pixel_mean_body(int npix, int spp, const float *__restrict__ samples,
+                                                float *__restrict__ img, int bx) {
+    int p = bx * blockDim.x + threadIdx.x;
     if (p >= npix) return;
     float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f;
     const float *q = samples + (size_t)3 * p * spp;
     for (int k = 0; k < spp; ++k) { a0 += q[3 * k]; a1 += q[3 * k + 1]; a2 += q[3 * k + 2]; }
     float inv = (float)spp;
     img[3 * p] = a0 / inv; img[3 * p + 1] = a1 / inv; img[3 * p + 2] = a2 / inv;
+}
+__global__ __launch_bounds__(256) void k_pixel_mean(int npix, int spp, const float *__restrict__ samples, float *__restrict__ img) {
+    pixel_mean_body(npix, spp, samples, img, blockIdx.x);
 }
 
 // ------------------------------------------------------------ adjoint ---
@@ -649,9 +695,9 @@ __device__ inline void adjoint_sample(const Scene &S, const Light *Ls, uint64_t 
 
 // Interior adjoint, fp32: one lane per camera sample of the chunk, reading
 // the sample's hit record and visibility mask.
-__global__ __launch_bounds__(256) void k_render_adj(Scene S, uint64_t seed, int spp, long long s0, long long n,
-        const float *__restrict__ dLdI, GradBufs G, const HitRec *__restrict__ hits,
-        const unsigned long long *__restrict__ vis, unsigned long long *ctr) {
+__device__ __forceinline__ void render_adj_body(const Scene &S, uint64_t seed, int spp, long long s0, long long n,
+        const float *__restrict__ dLdI, const GradBufs &G, const HitRec *__restrict__ hits,
+        const unsigned long long *__restrict__ vis, unsigned long long *ctr, int bx) {
     extern __shared__ float dyn[];
     __shared__ Light Ls[kMaxLights];
     float *spec_lds = dyn;
@@ -665,7 +711,7 @@ __global__ __launch_bounds__(256) void k_render_adj(Scene S, uint64_t seed, int 
     for (int k = threadIdx.x; k < 3 * S.nl; k += blockDim.x) g_light[k] = 0.0f;
     vtx_clear(acc);
     __syncthreads();
-    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    long long i = (long long)bx * blockDim.x + threadIdx.x;
     Work wk;
     if (i < n) {
         HitRec rec = hits[i];
@@ -691,6 +737,11 @@ __global__ __launch_bounds__(256) void k_render_adj(Scene S, uint64_t seed, int 
     for (int k = threadIdx.x; k < 3 * S.nl; k += blockDim.x)
         if (g_light[k] != 0.0f) gadd(&G.d_light[k], (double)g_light[k]);
     vtx_flush(acc, G, S.V);
+}
+__global__ __launch_bounds__(256) void k_render_adj(Scene S, uint64_t seed, int spp, long long s0, long long n,
+        const float *__restrict__ dLdI, GradBufs G, const HitRec *__restrict__ hits,
+        const unsigned long long *__restrict__ vis, unsigned long long *ctr) {
+    render_adj_body(S, seed, spp, s0, n, dLdI, G, hits, vis, ctr, blockIdx.x);
 }
 
 #ifndef FR_EDGE_REAL
@@ -809,11 +860,12 @@ __device__ __forceinline__ void sec_setup(const Scene &S, uint64_t seed, int spp
 // go to a global list as (chunk index | light << 24 | vp << 30).
 // k_edge_secondary_value: the value path of each listed sample.  Splitting
 // them keeps the fp64 value code's registers out of the traversal kernel.
-__global__ __launch_bounds__(256) void k_edge_secondary(Scene S, uint64_t seed, int spp, long long s0, long long n,
+template <int TS>
+__device__ __forceinline__ void edge_secondary_body(const Scene &S, uint64_t seed, int spp, long long s0, long long n,
         const float *__restrict__ dLdI, const HitRec *__restrict__ hits, uint32_t *__restrict__ out,
-        uint32_t *__restrict__ out_n, unsigned long long *ctr) {
+        uint32_t *__restrict__ out_n, unsigned long long *ctr, int bx, int j) {
     __shared__ Light Ls[kMaxLights];
-    __shared__ int q_i[kShTile];
+    __shared__ int q_i[TS];
     __shared__ int q_n;
     for (int k = threadIdx.x; k < S.nl; k += blockDim.x) {
         const float *g = S.lgeom + 12 * k;
@@ -824,13 +876,12 @@ __global__ __launch_bounds__(256) void k_edge_secondary(Scene S, uint64_t seed, 
     }
     if (threadIdx.x == 0) q_n = 0;
     __syncthreads();
-    const int j = blockIdx.y;
-    const long long base = (long long)blockIdx.x * kShTile;
+    const long long base = (long long)bx * TS;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     uint32_t n_sec = 0;
     Work wk;
     bool vp = false;
-    for (int k = 0; k < kShTile; k += 256) {
+    for (int k = 0; k < TS; k += 256) {
         const int li = k + (int)threadIdx.x;
         const long long i = base + li;
         bool need = false;
@@ -866,10 +917,16 @@ __global__ __launch_bounds__(256) void k_edge_secondary(Scene S, uint64_t seed, 
     flush_count(ctr, 3, n_sec);
     flush_work(ctr, wk);
 }
+__global__ __launch_bounds__(256) void k_edge_secondary(Scene S, uint64_t seed, int spp, long long s0, long long n,
+        const float *__restrict__ dLdI, const HitRec *__restrict__ hits, uint32_t *__restrict__ out,
+        uint32_t *__restrict__ out_n, unsigned long long *ctr) {
+    edge_secondary_body<kShTile>(S, seed, spp, s0, n, dLdI, hits, out, out_n, ctr, blockIdx.x, blockIdx.y);
+}
 
-__global__ __launch_bounds__(256) void k_edge_secondary_value(Scene S, uint64_t seed, int spp, long long s0,
+// gx blocks stride over the list
+__device__ __forceinline__ void edge_secondary_value_body(const Scene &S, uint64_t seed, int spp, long long s0,
         const float *__restrict__ dLdI, const HitRec *__restrict__ hits, const uint32_t *__restrict__ list,
-        const uint32_t *__restrict__ list_n, double *d_pos) {
+        const uint32_t *__restrict__ list_n, double *d_pos, int bx, int gx) {
     extern __shared__ float dyn[];
     __shared__ Light Ls[kMaxLights];
     float *spec_lds = dyn;
@@ -878,7 +935,7 @@ __global__ __launch_bounds__(256) void k_edge_secondary_value(Scene S, uint64_t 
     const uint32_t cnt = *list_n;
     uint32_t n_dummy = 0;
     Work wk;
-    for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < cnt; k += gridDim.x * blockDim.x) {
+    for (uint32_t k = bx * blockDim.x + threadIdx.x; k < cnt; k += gx * blockDim.x) {
         uint32_t q = list[k];
         long long i = q & 0xffffffu;
         int j = (q >> 24) & 63;
@@ -887,6 +944,11 @@ __global__ __launch_bounds__(256) void k_edge_secondary_value(Scene S, uint64_t 
         sec_setup(S, seed, spp, s0, i, dLdI, hits, o, d, w, h, sd, s, live);
         secondary_edge<kSecValue>(S, Ls[j], j, seed, s, spec_lds, o, d, h, sd, w, d_pos, vp, n_dummy, wk);
     }
+}
+__global__ __launch_bounds__(256) void k_edge_secondary_value(Scene S, uint64_t seed, int spp, long long s0,
+        const float *__restrict__ dLdI, const HitRec *__restrict__ hits, const uint32_t *__restrict__ list,
+        const uint32_t *__restrict__ list_n, double *d_pos) {
+    edge_secondary_value_body(S, seed, spp, s0, dLdI, hits, list, list_n, d_pos, blockIdx.x, gridDim.x);
 }
 
 // ---------------------------------------------- camera silhouettes -----
@@ -903,10 +965,10 @@ __global__ __launch_bounds__(256) void k_edge_secondary_value(Scene S, uint64_t 
 //                         Jacobian into the edge's two endpoints.
 struct PeSample { int e, i, pix; float qx, qy; };
 
-__global__ __launch_bounds__(256) void k_edge_primary_setup(Scene S, uint64_t seed, int M,
+__device__ __forceinline__ void edge_primary_setup_body(const Scene &S, uint64_t seed, int M,
         PeSample *__restrict__ ps_out, Hit *__restrict__ hits, unsigned long long *__restrict__ pvis,
-        unsigned long long *ctr) {
-    int m = blockIdx.x * blockDim.x + threadIdx.x;
+        unsigned long long *ctr, int bx) {
+    int m = bx * blockDim.x + threadIdx.x;
     uint32_t n_cam = 0;
     Work wk;
     int n = S.pe_n[0];
@@ -952,6 +1014,11 @@ __global__ __launch_bounds__(256) void k_edge_primary_setup(Scene S, uint64_t se
     flush_count(ctr, 0, n_cam);
     flush_work(ctr, wk);
 }
+__global__ __launch_bounds__(256) void k_edge_primary_setup(Scene S, uint64_t seed, int M,
+        PeSample *__restrict__ ps_out, Hit *__restrict__ hits, unsigned long long *__restrict__ pvis,
+        unsigned long long *ctr) {
+    edge_primary_setup_body(S, seed, M, ps_out, hits, pvis, ctr, blockIdx.x);
+}
 
 // screen point of side 'side' of a primary sample (same fp32 ops as setup)
 __device__ __forceinline__ void pe_side_point(const Scene &S, const PeSample &ps, int side, float &px, float &py) {
@@ -992,11 +1059,12 @@ __device__ __forceinline__ bool pe_light(const Scene &S, uint64_t seed, const Pe
 // lane per side, the fp64 radiance of its visible lights summed in light
 // order (no atomics; the fp64 shading registers stay out of the traversal
 // kernel).
-__global__ __launch_bounds__(256) void k_edge_primary_vis(Scene S, uint64_t seed, int M,
+template <int TS>
+__device__ __forceinline__ void edge_primary_vis_body(const Scene &S, uint64_t seed, int M,
         const PeSample *__restrict__ ps_in, const Hit *__restrict__ hits, unsigned long long *__restrict__ pvis,
-        unsigned long long *ctr) {
+        unsigned long long *ctr, int bx, int j) {
     __shared__ Light Ls[kMaxLights];
-    __shared__ int q_i[kShTile];
+    __shared__ int q_i[TS];
     __shared__ int q_n;
     for (int k = threadIdx.x; k < S.nl; k += blockDim.x) {
         const float *g = S.lgeom + 12 * k;
@@ -1006,13 +1074,12 @@ __global__ __launch_bounds__(256) void k_edge_primary_vis(Scene S, uint64_t seed
     }
     if (threadIdx.x == 0) q_n = 0;
     __syncthreads();
-    const int j = blockIdx.y;
-    const int base = blockIdx.x * kShTile;
+    const int base = bx * TS;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const Light &L = Ls[j];
     uint32_t n_sh = 0;
     Work wk;
-    for (int k = 0; k < kShTile; k += 256) {
+    for (int k = 0; k < TS; k += 256) {
         const int li = k + (int)threadIdx.x;
         bool need = false;
         if (base + li < 2 * M) {
@@ -1038,16 +1105,21 @@ __global__ __launch_bounds__(256) void k_edge_primary_vis(Scene S, uint64_t seed
     flush_count(ctr, 2, n_sh);
     flush_work(ctr, wk);
 }
+__global__ __launch_bounds__(256) void k_edge_primary_vis(Scene S, uint64_t seed, int M,
+        const PeSample *__restrict__ ps_in, const Hit *__restrict__ hits, unsigned long long *__restrict__ pvis,
+        unsigned long long *ctr) {
+    edge_primary_vis_body<kShTile>(S, seed, M, ps_in, hits, pvis, ctr, blockIdx.x, blockIdx.y);
+}
 
-__global__ __launch_bounds__(256) void k_edge_primary_shade(Scene S, uint64_t seed, int M,
+__device__ __forceinline__ void edge_primary_shade_body(const Scene &S, uint64_t seed, int M,
         const PeSample *__restrict__ ps_in, const Hit *__restrict__ hits, const unsigned long long *__restrict__ pvis,
-        double *__restrict__ fbuf, unsigned long long *ctr) {
+        double *__restrict__ fbuf, unsigned long long *ctr, int bx) {
     extern __shared__ float dyn[];
     __shared__ Light Ls[kMaxLights];
     float *spec_lds = dyn;
     stage_tables(S, Ls, spec_lds);
     __syncthreads();
-    const int ms = blockIdx.x * blockDim.x + threadIdx.x;
+    const int ms = bx * blockDim.x + threadIdx.x;
     Work wk;
     if (ms < 2 * M) {
         unsigned long long mask = pvis[ms];
@@ -1075,10 +1147,15 @@ __global__ __launch_bounds__(256) void k_edge_primary_shade(Scene S, uint64_t se
     }
     flush_work(ctr, wk);
 }
+__global__ __launch_bounds__(256) void k_edge_primary_shade(Scene S, uint64_t seed, int M,
+        const PeSample *__restrict__ ps_in, const Hit *__restrict__ hits, const unsigned long long *__restrict__ pvis,
+        double *__restrict__ fbuf, unsigned long long *ctr) {
+    edge_primary_shade_body(S, seed, M, ps_in, hits, pvis, fbuf, ctr, blockIdx.x);
+}
 
-__global__ __launch_bounds__(256) void k_edge_primary_scatter(Scene S, int M, const float *__restrict__ dLdI,
-        const PeSample *__restrict__ ps_in, const double *__restrict__ fbuf, double *d_pos) {
-    int m = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void edge_primary_scatter_body(const Scene &S, int M, const float *__restrict__ dLdI,
+        const PeSample *__restrict__ ps_in, const double *__restrict__ fbuf, double *d_pos, int bx) {
+    int m = bx * blockDim.x + threadIdx.x;
     if (m < M) do {
         PeSample ps = ps_in[m];
         if (ps.e < 0) break;
@@ -1106,12 +1183,16 @@ __global__ __launch_bounds__(256) void k_edge_primary_scatter(Scene S, int M, co
         atomic_v(d_pos, S.V, ed[1], cross(dq, ra) * W);
     } while (0);
 }
+__global__ __launch_bounds__(256) void k_edge_primary_scatter(Scene S, int M, const float *__restrict__ dLdI,
+        const PeSample *__restrict__ ps_in, const double *__restrict__ fbuf, double *d_pos) {
+    edge_primary_scatter_body(S, M, dLdI, ps_in, fbuf, d_pos, blockIdx.x);
+}
 
 // ------------------------------------------------------- reductions ----
 // gN_k = d n_k / d N_k applied to the vertex-normal adjoint
-__global__ __launch_bounds__(256) void k_normal_adj(int V, const float *__restrict__ nrm, const float *__restrict__ nlen,
-        const double *__restrict__ d_nrm, double *__restrict__ gN) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void normal_adj_body(int V, const float *__restrict__ nrm, const float *__restrict__ nlen,
+        const double *__restrict__ d_nrm, double *__restrict__ gN, int bx) {
+    int i = bx * blockDim.x + threadIdx.x;
     if (i >= V) return;
     double r[3] = {0.0, 0.0, 0.0};
     if (nlen[i] > 0.0f) {
@@ -1122,15 +1203,19 @@ __global__ __launch_bounds__(256) void k_normal_adj(int V, const float *__restri
     }
     gN[i] = r[0]; gN[V + i] = r[1]; gN[2 * V + i] = r[2];
 }
+__global__ __launch_bounds__(256) void k_normal_adj(int V, const float *__restrict__ nrm, const float *__restrict__ nlen,
+        const double *__restrict__ d_nrm, double *__restrict__ gN) {
+    normal_adj_body(V, nrm, nlen, d_nrm, gN, blockIdx.x);
+}
 
 // d_vertices = d_pos + sum over incident faces of the cross-product adjoint
 // of N_f = (v1 - v0) x (v2 - v0) with gN_f = gN_i0 + gN_i1 + gN_i2;
 // also gm = R^T d_vertices for the blend transposes.
-__global__ __launch_bounds__(256) void k_chain_gather(int V, const int *__restrict__ faces,
+__device__ __forceinline__ void chain_gather_body(int V, const int *__restrict__ faces,
         const int *__restrict__ vf_off, const int *__restrict__ vf_idx, const float *__restrict__ pos,
-        const double *__restrict__ gN, const double *__restrict__ d_pos, PoseArgs P,
-        float *__restrict__ d_vert, float *__restrict__ gm) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+        const double *__restrict__ gN, const double *__restrict__ d_pos, const PoseArgs &P,
+        float *__restrict__ d_vert, float *__restrict__ gm, int bx) {
+    int i = bx * blockDim.x + threadIdx.x;
     if (i >= V) return;
     double acc[3] = {d_pos[i], d_pos[V + i], d_pos[2 * V + i]};
     for (int q = vf_off[i]; q < vf_off[i + 1]; ++q) {
@@ -1155,16 +1240,21 @@ __global__ __launch_bounds__(256) void k_chain_gather(int V, const int *__restri
     for (int c = 0; c < 3; ++c)
         gm[(size_t)c * V + i] = (float)((P.R[c] * acc[0] + P.R[3 + c] * acc[1]) + P.R[6 + c] * acc[2]);
 }
+__global__ __launch_bounds__(256) void k_chain_gather(int V, const int *__restrict__ faces,
+        const int *__restrict__ vf_off, const int *__restrict__ vf_idx, const float *__restrict__ pos,
+        const double *__restrict__ gN, const double *__restrict__ d_pos, PoseArgs P,
+        float *__restrict__ d_vert, float *__restrict__ gm) {
+    chain_gather_body(V, faces, vf_off, vf_idx, pos, gN, d_pos, P, d_vert, gm, blockIdx.x);
+}
 
 // rows: [0, n_id) B_id . gm; [n_id, +n_exp) B_exp . gm; [.., +n_alb) B_alb . d_alb;
 // then 9 rows dR[a][b] = sum d_v[a] vmodel[b] and 3 rows dt[a] = sum d_v[a].
 // Grid (rows, chunks); each block writes one partial.
 template <int BS>
-__global__ __launch_bounds__(BS) void k_param_partial(int V, int n_id, int n_exp, int n_alb, int chunk,
+__device__ __forceinline__ void param_partial_body(int V, int n_id, int n_exp, int n_alb, int chunk,
         const float *__restrict__ b_id, const float *__restrict__ b_exp, const float *__restrict__ b_alb,
         const float *__restrict__ gm, const double *__restrict__ d_alb, const float *__restrict__ d_vert,
-        const float *__restrict__ vmodel, double *__restrict__ partial) {
-    int row = blockIdx.x, ch = blockIdx.y;
+        const float *__restrict__ vmodel, double *__restrict__ partial, int row, int ch, int nchunks) {
     size_t L = (size_t)3 * V;
     const float *x, *y = nullptr;
     const double *yd = nullptr;
@@ -1186,14 +1276,23 @@ __global__ __launch_bounds__(BS) void k_param_partial(int V, int n_id, int n_exp
         if (threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
         __syncthreads();
     }
-    if (threadIdx.x == 0) partial[(size_t)row * gridDim.y + ch] = sh[0];
+    if (threadIdx.x == 0) partial[(size_t)row * nchunks + ch] = sh[0];
+}
+template <int BS>
+__global__ __launch_bounds__(BS) void k_param_partial(int V, int n_id, int n_exp, int n_alb, int chunk,
+        const float *__restrict__ b_id, const float *__restrict__ b_exp, const float *__restrict__ b_alb,
+        const float *__restrict__ gm, const double *__restrict__ d_alb, const float *__restrict__ d_vert,
+        const float *__restrict__ vmodel, double *__restrict__ partial) {
+    param_partial_body<BS>(V, n_id, n_exp, n_alb, chunk, b_id, b_exp, b_alb, gm, d_alb, d_vert, vmodel, partial,
+                           blockIdx.x, blockIdx.y, gridDim.y);
 }
 
 struct DRotArgs { double dR[27]; };   // dR/drx, dR/dry, dR/drz, row-major
 
-__global__ void k_param_final(int n_id, int n_exp, int n_alb, int nchunks, const double *__restrict__ partial,
-        DRotArgs D, float *d_alpha, float *d_beta, float *d_delta, float *d_pose) {
-    int row = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void param_final_body(int n_id, int n_exp, int n_alb, int nchunks,
+        const double *__restrict__ partial, const DRotArgs &D, float *d_alpha, float *d_beta, float *d_delta,
+        float *d_pose, int bx) {
+    int row = bx * blockDim.x + threadIdx.x;
     int kb = n_id + n_exp + n_alb;
     if (row < kb) {
         double s = 0.0;
@@ -1216,6 +1315,10 @@ __global__ void k_param_final(int n_id, int n_exp, int n_alb, int nchunks, const
         }
         for (int a = 0; a < 3; ++a) d_pose[3 + a] = (float)dt[a];
     }
+}
+__global__ void k_param_final(int n_id, int n_exp, int n_alb, int nchunks, const double *__restrict__ partial,
+        DRotArgs D, float *d_alpha, float *d_beta, float *d_delta, float *d_pose) {
+    param_final_body(n_id, n_exp, n_alb, nchunks, partial, D, d_alpha, d_beta, d_delta, d_pose, blockIdx.x);
 }
 
 __global__ __launch_bounds__(256) void k_zero(float *a, size_t n) {
@@ -1399,6 +1502,7 @@ struct fr_ctx {
     double *loss_partial = nullptr; int loss_nb = 0;
     // last render
     bool have_render = false, have_backward = false;
+    uint64_t gen = 0;              // renders so far (single or batched)
     fr_params last{};
     uint64_t last_seed = 0; int last_spp = 0;
     long long cam_chunk = kChunkMax, last_cam_chunk = kChunkMax;   // camera samples per chunk (set / of the last render)
@@ -1935,6 +2039,7 @@ int fr_render(fr_ctx *c, const fr_params *p, uint64_t seed, int32_t spp, float *
     c->records_valid = N <= kChunk;
     c->have_render = true;
     c->have_backward = false;
+    ++c->gen;
     return FR_OK;
 }
 
@@ -2122,3 +2227,5 @@ void fr_destroy(fr_ctx *c) {
 }
 
 }  // extern "C"
+
+#include "fr_batch.hpp"

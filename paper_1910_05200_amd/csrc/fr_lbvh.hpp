@@ -58,14 +58,15 @@ __device__ __forceinline__ v3 tri_centroid(const float *pos, int V, const int *f
     return mk(((a.x + b.x) + c.x) / 3.0f, ((a.y + b.y) + c.y) / 3.0f, ((a.z + b.z) + c.z) / 3.0f);
 }
 
-__global__ __launch_bounds__(256) void k_lbvh_bounds_init(unsigned int *bounds) {
+__device__ __forceinline__ void lbvh_bounds_init_body(unsigned int *bounds) {
     if (threadIdx.x < 3) bounds[threadIdx.x] = 0xffffffffu;
     else if (threadIdx.x < 6) bounds[threadIdx.x] = 0u;
 }
+__global__ __launch_bounds__(256) void k_lbvh_bounds_init(unsigned int *bounds) { lbvh_bounds_init_body(bounds); }
 
-__global__ __launch_bounds__(256) void k_lbvh_bounds(int F, const float *__restrict__ pos, int V,
-        const int *__restrict__ faces, unsigned int *bounds) {
-    int f = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void lbvh_bounds_body(int F, const float *__restrict__ pos, int V,
+        const int *__restrict__ faces, unsigned int *bounds, int bx) {
+    int f = bx * blockDim.x + threadIdx.x;
     unsigned int mn[3] = {0xffffffffu, 0xffffffffu, 0xffffffffu}, mx[3] = {0u, 0u, 0u};
     if (f < F) {
         v3 c = tri_centroid(pos, V, faces, f);
@@ -88,6 +89,10 @@ __global__ __launch_bounds__(256) void k_lbvh_bounds(int F, const float *__restr
         if (threadIdx.x < 3) atomicMin(&bounds[threadIdx.x], r); else atomicMax(&bounds[threadIdx.x], r);
     }
 }
+__global__ __launch_bounds__(256) void k_lbvh_bounds(int F, const float *__restrict__ pos, int V,
+        const int *__restrict__ faces, unsigned int *bounds) {
+    lbvh_bounds_body(F, pos, V, faces, bounds, blockIdx.x);
+}
 
 __device__ __forceinline__ uint32_t spread10(uint32_t x) {   // 10 bits -> every third bit
     x &= 0x3ffu;
@@ -98,10 +103,10 @@ __device__ __forceinline__ uint32_t spread10(uint32_t x) {   // 10 bits -> every
     return x;
 }
 
-__global__ __launch_bounds__(256) void k_lbvh_morton(int F, const float *__restrict__ pos, int V,
+__device__ __forceinline__ void lbvh_morton_body(int F, const float *__restrict__ pos, int V,
         const int *__restrict__ faces, const unsigned int *__restrict__ bounds, uint32_t *__restrict__ key,
-        int *__restrict__ val) {
-    int f = blockIdx.x * blockDim.x + threadIdx.x;
+        int *__restrict__ val, int bx) {
+    int f = bx * blockDim.x + threadIdx.x;
     if (f >= F) return;
     v3 c = tri_centroid(pos, V, faces, f);
     float cc[3] = {c.x, c.y, c.z};
@@ -116,24 +121,33 @@ __global__ __launch_bounds__(256) void k_lbvh_morton(int F, const float *__restr
     key[f] = (spread10(q[0]) << 2) | (spread10(q[1]) << 1) | spread10(q[2]);
     val[f] = f;
 }
+__global__ __launch_bounds__(256) void k_lbvh_morton(int F, const float *__restrict__ pos, int V,
+        const int *__restrict__ faces, const unsigned int *__restrict__ bounds, uint32_t *__restrict__ key,
+        int *__restrict__ val) {
+    lbvh_morton_body(F, pos, V, faces, bounds, key, val, blockIdx.x);
+}
 
 // radix sort, 8-bit digit at 'shift'; kSortTile elements per block of 256
 constexpr int kSortTile = 1024;
-__global__ __launch_bounds__(256) void k_sort_hist(int n, int shift, const uint32_t *__restrict__ key,
-                                                   uint32_t *__restrict__ hist, int nb) {
+__device__ __forceinline__ void sort_hist_body(int n, int shift, const uint32_t *__restrict__ key,
+                                               uint32_t *__restrict__ hist, int nb, int bx) {
     __shared__ uint32_t h[256];
     h[threadIdx.x] = 0;
     __syncthreads();
     for (int k = 0; k < kSortTile; k += 256) {
-        int i = blockIdx.x * kSortTile + k + threadIdx.x;
+        int i = bx * kSortTile + k + threadIdx.x;
         if (i < n) atomicAdd(&h[(key[i] >> shift) & 255u], 1u);
     }
     __syncthreads();
-    hist[threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
+    hist[threadIdx.x * nb + bx] = h[threadIdx.x];
+}
+__global__ __launch_bounds__(256) void k_sort_hist(int n, int shift, const uint32_t *__restrict__ key,
+                                                   uint32_t *__restrict__ hist, int nb) {
+    sort_hist_body(n, shift, key, hist, nb, blockIdx.x);
 }
 
 // exclusive scan of n counts in place, one block of 1024 threads
-__global__ __launch_bounds__(1024) void k_scan_u32(int n, uint32_t *a) {
+__device__ __forceinline__ void scan_u32_body(int n, uint32_t *a) {
     __shared__ uint32_t s_w[16];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     uint32_t base = 0;
@@ -153,19 +167,20 @@ __global__ __launch_bounds__(1024) void k_scan_u32(int n, uint32_t *a) {
         __syncthreads();
     }
 }
+__global__ __launch_bounds__(1024) void k_scan_u32(int n, uint32_t *a) { scan_u32_body(n, a); }
 
 // stable: within a block, elements keep their order (sub-tile, wave, lane)
-__global__ __launch_bounds__(256) void k_sort_scatter(int n, int shift, const uint32_t *__restrict__ key_in,
+__device__ __forceinline__ void sort_scatter_body(int n, int shift, const uint32_t *__restrict__ key_in,
         const int *__restrict__ val_in, const uint32_t *__restrict__ offs, int nb, uint32_t *__restrict__ key_out,
-        int *__restrict__ val_out) {
+        int *__restrict__ val_out, int bx) {
     __shared__ uint32_t cnt[4][256];
     __shared__ uint32_t run[256];       // elements of each digit placed by earlier sub-tiles
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    run[threadIdx.x] = offs[threadIdx.x * nb + blockIdx.x];
+    run[threadIdx.x] = offs[threadIdx.x * nb + bx];
     for (int k = 0; k < kSortTile; k += 256) {
         for (int q = threadIdx.x; q < 4 * 256; q += 256) cnt[q >> 8][q & 255] = 0;
         __syncthreads();
-        int i = blockIdx.x * kSortTile + k + threadIdx.x;
+        int i = bx * kSortTile + k + threadIdx.x;
         bool valid = i < n;
         uint32_t kv = valid ? key_in[i] : 0u;
         uint32_t d = (kv >> shift) & 255u;
@@ -189,6 +204,11 @@ __global__ __launch_bounds__(256) void k_sort_scatter(int n, int shift, const ui
         __syncthreads();
     }
 }
+__global__ __launch_bounds__(256) void k_sort_scatter(int n, int shift, const uint32_t *__restrict__ key_in,
+        const int *__restrict__ val_in, const uint32_t *__restrict__ offs, int nb, uint32_t *__restrict__ key_out,
+        int *__restrict__ val_out) {
+    sort_scatter_body(n, shift, key_in, val_in, offs, nb, key_out, val_out, blockIdx.x);
+}
 
 __device__ __forceinline__ int lbvh_delta(const uint32_t *key, int F, int i, int j) {
     if (j < 0 || j >= F) return -1;
@@ -196,10 +216,10 @@ __device__ __forceinline__ int lbvh_delta(const uint32_t *key, int F, int i, int
     return a == b ? 32 + __clz((uint32_t)(i ^ j)) : __clz(a ^ b);
 }
 
-__global__ __launch_bounds__(256) void k_lbvh_karras(int F, const uint32_t *__restrict__ key, int *__restrict__ child,
+__device__ __forceinline__ void lbvh_karras_body(int F, const uint32_t *__restrict__ key, int *__restrict__ child,
         int *__restrict__ parent, int *__restrict__ first, int *__restrict__ last, int *__restrict__ top_idx,
-        int *__restrict__ n_top) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+        int *__restrict__ n_top, int bx) {
+    int i = bx * blockDim.x + threadIdx.x;
     if (i >= F - 1) return;
     int d = lbvh_delta(key, F, i, i + 1) > lbvh_delta(key, F, i, i - 1) ? 1 : -1;
     int dmin = lbvh_delta(key, F, i, i - d);
@@ -229,16 +249,25 @@ __global__ __launch_bounds__(256) void k_lbvh_karras(int F, const uint32_t *__re
     top_idx[i] = lo / kBoxTile != hi / kBoxTile ? atomicAdd(n_top, 1) : -1;
     if (i == 0) parent[0] = -1;
 }
+__global__ __launch_bounds__(256) void k_lbvh_karras(int F, const uint32_t *__restrict__ key, int *__restrict__ child,
+        int *__restrict__ parent, int *__restrict__ first, int *__restrict__ last, int *__restrict__ top_idx,
+        int *__restrict__ n_top) {
+    lbvh_karras_body(F, key, child, parent, first, last, top_idx, n_top, blockIdx.x);
+}
 
-__global__ __launch_bounds__(256) void k_lbvh_layout(int F, const int *__restrict__ child, const int *__restrict__ parent,
-        const int *__restrict__ first, int *__restrict__ pre) {
-    int x = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void lbvh_layout_body(int F, const int *__restrict__ child, const int *__restrict__ parent,
+        const int *__restrict__ first, int *__restrict__ pre, int bx) {
+    int x = bx * blockDim.x + threadIdx.x;
     if (x >= 2 * F - 1) return;
     int a = x >= F - 1 ? x - (F - 1) : first[x];
     int left_turns = 0, cur = x;
     for (int p = (F > 1 ? parent[cur] : -1); p >= 0; cur = p, p = parent[cur])
         if (child[2 * p] == cur) ++left_turns;
     pre[x] = 2 * a + left_turns;
+}
+__global__ __launch_bounds__(256) void k_lbvh_layout(int F, const int *__restrict__ child, const int *__restrict__ parent,
+        const int *__restrict__ first, int *__restrict__ pre) {
+    lbvh_layout_body(F, child, parent, first, pre, blockIdx.x);
 }
 
 // Boxes bottom-up in two passes without device-wide fences or global
@@ -266,15 +295,15 @@ __device__ __forceinline__ void lbvh_union_write(int F, int p, const int *child,
     nodes[pp] = qnode(u[0], u[1], u[2], u[3], u[4], u[5], pp + 2 * (last[p] - first[p] + 1) - 1);
 }
 
-__global__ __launch_bounds__(kBoxTile) void k_lbvh_boxes(int F, const int *__restrict__ faces, const float *__restrict__ pos,
+__device__ __forceinline__ void lbvh_boxes_body(int F, const int *__restrict__ faces, const float *__restrict__ pos,
         int V, const int *__restrict__ sorted, const int *__restrict__ child, const int *__restrict__ parent,
         const int *__restrict__ first, const int *__restrict__ last, const int *__restrict__ pre,
         float *box, uint4 *__restrict__ nodes, float4 *__restrict__ tris, int *__restrict__ roots,
-        int *__restrict__ n_roots) {
+        int *__restrict__ n_roots, int tb) {
     __shared__ unsigned int arr[kBoxTile];
     arr[threadIdx.x] = 0u;
     __syncthreads();
-    const int lo = blockIdx.x * kBoxTile, hi = min(F, lo + kBoxTile) - 1;
+    const int lo = tb * kBoxTile, hi = min(F, lo + kBoxTile) - 1;
     int l = lo + (int)threadIdx.x;
     if (l >= F) return;
     int f = sorted[l];
@@ -306,8 +335,16 @@ __global__ __launch_bounds__(kBoxTile) void k_lbvh_boxes(int F, const int *__res
         x = p;
     }
 }
+__global__ __launch_bounds__(kBoxTile) void k_lbvh_boxes(int F, const int *__restrict__ faces, const float *__restrict__ pos,
+        int V, const int *__restrict__ sorted, const int *__restrict__ child, const int *__restrict__ parent,
+        const int *__restrict__ first, const int *__restrict__ last, const int *__restrict__ pre,
+        float *box, uint4 *__restrict__ nodes, float4 *__restrict__ tris, int *__restrict__ roots,
+        int *__restrict__ n_roots) {
+    lbvh_boxes_body(F, faces, pos, V, sorted, child, parent, first, last, pre, box, nodes, tris, roots, n_roots,
+                    blockIdx.x);
+}
 
-__global__ __launch_bounds__(1024) void k_lbvh_boxes_top(int F, const int *__restrict__ child,
+__device__ __forceinline__ void lbvh_boxes_top_body(int F, const int *__restrict__ child,
         const int *__restrict__ parent, const int *__restrict__ first, const int *__restrict__ last,
         const int *__restrict__ pre, const int *__restrict__ top_idx, unsigned int *__restrict__ arrive, float *box,
         uint4 *__restrict__ nodes, const int *__restrict__ roots, const int *__restrict__ n_roots) {
@@ -329,4 +366,10 @@ __global__ __launch_bounds__(1024) void k_lbvh_boxes_top(int F, const int *__res
             x = p;
         }
     }
+}
+__global__ __launch_bounds__(1024) void k_lbvh_boxes_top(int F, const int *__restrict__ child,
+        const int *__restrict__ parent, const int *__restrict__ first, const int *__restrict__ last,
+        const int *__restrict__ pre, const int *__restrict__ top_idx, unsigned int *__restrict__ arrive, float *box,
+        uint4 *__restrict__ nodes, const int *__restrict__ roots, const int *__restrict__ n_roots) {
+    lbvh_boxes_top_body(F, child, parent, first, last, pre, top_idx, arrive, box, nodes, roots, n_roots);
 }

@@ -67,8 +67,18 @@ class fr_stats_t(C.Structure):
 KERNELS = ("k_fwd_camera", "k_fwd_shadow", "k_fwd_shade", "k_render_adj", "k_edge_primary", "k_edge_secondary")
 
 
+class fr_launch(C.Structure):
+    _fields_ = [("mode", C.c_int32), ("tile", C.c_int32)]
+
+
+FR_LAUNCH_FLAT, FR_LAUNCH_XCD = 0, 1
+
 EXPORTS = ("fr_create", "fr_set_stream", "fr_set_terms", "fr_set_chunk", "fr_blend", "fr_render", "fr_backward",
-           "fr_loss_l2", "fr_aov", "fr_light_reg", "fr_adam", "fr_stats", "fr_last_error", "fr_destroy")
+           "fr_loss_l2", "fr_aov", "fr_light_reg", "fr_adam", "fr_stats", "fr_last_error", "fr_destroy",
+           "fr_batch_create", "fr_batch_set_stream", "fr_batch_render", "fr_batch_backward", "fr_batch_num_kinds",
+           "fr_batch_kind_name", "fr_batch_get_launch", "fr_batch_set_launch", "fr_batch_tune", "fr_batch_timing",
+           "fr_batch_capture_begin", "fr_batch_capture_end", "fr_batch_graph_launch", "fr_batch_last_error",
+           "fr_batch_destroy")
 
 _lib = None
 
@@ -98,8 +108,26 @@ def load():
         L.fr_last_error.restype = C.c_char_p
         L.fr_destroy.argtypes = [vp]
         L.fr_destroy.restype = None
+        L.fr_batch_create.argtypes = [i32, vp, u32, C.POINTER(vp)]
+        L.fr_batch_set_stream.argtypes = [vp, vp]
+        L.fr_batch_render.argtypes = [vp, vp, vp, vp, vp]
+        L.fr_batch_backward.argtypes = [vp, vp, vp]
+        L.fr_batch_num_kinds.argtypes = []
+        L.fr_batch_kind_name.argtypes = [i32]
+        L.fr_batch_kind_name.restype = C.c_char_p
+        L.fr_batch_get_launch.argtypes = [vp, i32, C.POINTER(fr_launch)]
+        L.fr_batch_set_launch.argtypes = [vp, i32, C.POINTER(fr_launch)]
+        L.fr_batch_tune.argtypes = [vp, i32, vp]
+        L.fr_batch_timing.argtypes = [vp, vp, vp, vp]
+        for n in ("fr_batch_capture_begin", "fr_batch_capture_end", "fr_batch_graph_launch"):
+            getattr(L, n).argtypes = [vp]
+        L.fr_batch_last_error.argtypes = [vp]
+        L.fr_batch_last_error.restype = C.c_char_p
+        L.fr_batch_destroy.argtypes = [vp]
+        L.fr_batch_destroy.restype = None
         for n in EXPORTS:
-            if n != "fr_last_error" and n != "fr_destroy":
+            if n not in ("fr_last_error", "fr_destroy", "fr_batch_kind_name", "fr_batch_last_error",
+                         "fr_batch_destroy"):
                 getattr(L, n).restype = C.c_int
         _lib = L
     return _lib
@@ -258,6 +286,125 @@ class Renderer:
             v = getattr(s, k)
             out[k] = list(v) if isinstance(v, C.Array) else v
         return out
+
+
+def _bcheck(batch, code: int):
+    if code != 0:
+        msg = load().fr_batch_last_error(batch)
+        raise FrError(code, msg.decode() if msg else "")
+
+
+GRAD_KEYS = ("d_lights", "d_spec", "d_vertices", "d_albedo", "d_alpha", "d_beta", "d_delta", "d_pose")
+
+
+class Batch:
+    """Several Renderers evaluated together (fr_batch_*): one kernel launch
+    per pipeline step for all of them.  Work runs on torch's current stream,
+    which becomes the stream of every renderer of the batch."""
+
+    def __init__(self, renderers, timing: bool = False):
+        import torch
+        self.torch = torch
+        self.rs = list(renderers)
+        n = len(self.rs)
+        arr = (C.c_void_p * n)(*[r.ctx.value for r in self.rs])
+        b = C.c_void_p()
+        code = load().fr_batch_create(n, arr, FR_TIMING if timing else 0, C.byref(b))
+        if code != 0:
+            raise FrError(code, "fr_batch_create failed")
+        self.b = b
+        self.n = n
+        self._keep = None
+        self.kinds = [load().fr_batch_kind_name(k).decode() for k in range(load().fr_batch_num_kinds())]
+
+    def _stream(self):
+        _bcheck(self.b, load().fr_batch_set_stream(self.b, self.torch.cuda.current_stream().cuda_stream))
+
+    def close(self):
+        if getattr(self, "b", None):
+            load().fr_batch_destroy(self.b)
+            self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def render(self, params, seeds, spps, outs=None):
+        """params: list of dicts as Renderer.render takes; returns the images
+        (written into outs when given)."""
+        t = self.torch
+        self._stream()
+        n = self.n
+        if outs is None:
+            outs = [t.empty((r.H, r.W, 3), device="cuda", dtype=t.float32) for r in self.rs]
+        poses = [np.ascontiguousarray(np.asarray(p["pose"], np.float32).reshape(6)) for p in params]
+        fp = (fr_params * n)(*[fr_params(_ptr(p["alpha"]), _ptr(p["beta"]), _ptr(p["delta"]), ph.ctypes.data,
+                                         _ptr(p["lights"]), _ptr(p["spec"])) for p, ph in zip(params, poses)])
+        sd = (C.c_uint64 * n)(*[int(s) for s in seeds])
+        sp = (C.c_int32 * n)(*[int(s) for s in spps])
+        op = (C.c_void_p * n)(*[_ptr(o) for o in outs])
+        _bcheck(self.b, load().fr_batch_render(self.b, fp, sd, sp, op))
+        for r in self.rs:
+            r.render_token += 1
+        self._keep = (params, poses, outs)
+        return outs
+
+    def backward(self, dLs, want=GRAD_KEYS, outs=None):
+        """dLs: image gradients; returns one dict of gradients per instance
+        (written into outs, a list of such dicts, when given)."""
+        t = self.torch
+        self._stream()
+        if outs is None:
+            outs = []
+            for r in self.rs:
+                shapes = {"d_lights": (r.n_lights, 3), "d_spec": (r.spec_res ** 2,), "d_vertices": (3, r.V),
+                          "d_albedo": (3, r.V), "d_alpha": (r.n_id,), "d_beta": (r.n_exp,), "d_delta": (r.n_alb,),
+                          "d_pose": (6,)}
+                outs.append({k: t.empty(shapes[k], device="cuda", dtype=t.float32) for k in want})
+        g = (fr_grads * self.n)(*[fr_grads(*[_ptr(o.get(k)) for k, _ in fr_grads._fields_]) for o in outs])
+        dp = (C.c_void_p * self.n)(*[_ptr(d) for d in dLs])
+        _bcheck(self.b, load().fr_batch_backward(self.b, dp, g))
+        self._keep_bwd = (dLs, outs)
+        return outs
+
+    def get_launch(self, kind) -> tuple:
+        k = self.kinds.index(kind) if isinstance(kind, str) else kind
+        L = fr_launch()
+        _bcheck(self.b, load().fr_batch_get_launch(self.b, k, C.byref(L)))
+        return L.mode, L.tile
+
+    def set_launch(self, kind, mode: int, tile: int = 0):
+        k = self.kinds.index(kind) if isinstance(kind, str) else kind
+        L = fr_launch(mode, tile)
+        _bcheck(self.b, load().fr_batch_set_launch(self.b, k, C.byref(L)))
+
+    def tune(self, trials: int = 2) -> dict:
+        """Autotune the launch of each tunable kind on the last render and
+        backward; returns {kind: (launch, best ms)} of the tuned kinds."""
+        ms = (C.c_float * len(self.kinds))()
+        _bcheck(self.b, load().fr_batch_tune(self.b, trials, ms))
+        return {k: (self.get_launch(i), ms[i]) for i, k in enumerate(self.kinds) if ms[i] > 0}
+
+    def timing(self) -> dict:
+        ms = (C.c_float * len(self.kinds))()
+        r, b = C.c_float(), C.c_float()
+        _bcheck(self.b, load().fr_batch_timing(self.b, ms, C.byref(r), C.byref(b)))
+        out = {k: ms[i] for i, k in enumerate(self.kinds)}
+        out["render"], out["backward"] = r.value, b.value
+        return out
+
+    def capture_begin(self):
+        self._stream()
+        _bcheck(self.b, load().fr_batch_capture_begin(self.b))
+
+    def capture_end(self):
+        _bcheck(self.b, load().fr_batch_capture_end(self.b))
+
+    def graph_launch(self):
+        self._stream()
+        _bcheck(self.b, load().fr_batch_graph_launch(self.b))
 
 
 def params_to_device(params, device="cuda"):

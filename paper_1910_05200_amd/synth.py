@@ -272,6 +272,37 @@ def workload(name: str):
     return model, scene, make_params(EVAL_SCENE_SEED), cfg["spp"]
 
 
+# ------------------------------------------------------ batched faces ----
+# Many faces per launch: each instance draws its mesh size, its (square)
+# image size and its sample count, and has its own parameters and light
+# colours (make_params at its own seed) in the common light stage.
+BATCH_GRIDS = ((62, 80), (88, 114), (125, 160), (153, 196), (177, 226))   # 5k, 10k, 20k, 30k, 40k vertices
+BATCH_RES = (128, 192, 256, 384, 512)
+BATCH_SPP = (4, 8, 16)
+BATCH_N = 32
+
+
+def model_cached(nx: int, ny: int) -> Model:
+    key = (nx, ny)
+    if key not in _MODEL_CACHE:
+        _MODEL_CACHE[key] = make_model(nx, ny)
+    return _MODEL_CACHE[key]
+
+
+def batch_workload(n: int = BATCH_N, seed: int = 0, grids=BATCH_GRIDS, res=BATCH_RES, spps=BATCH_SPP):
+    """n instances (model, scene, params, spp), drawn from a seeded generator."""
+    rng = np.random.default_rng(4711 + seed)
+    out = []
+    for i in range(n):
+        g = grids[int(rng.integers(len(grids)))]
+        r = res[int(rng.integers(len(res)))]
+        if isinstance(r, int):
+            r = (r, r)
+        spp = int(spps[int(rng.integers(len(spps)))])
+        out.append((model_cached(*g), make_scene(r[0], r[1]), make_params(100 + 7 * seed + i), spp))
+    return out
+
+
 # ------------------------------------------------------ simple scenes ----
 # Small hand-built scenes for closed-form checks (flat receivers, single
 # occluders, a closed box of emitters).  They bypass the morphable model.

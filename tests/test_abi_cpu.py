@@ -10,14 +10,18 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def _declared():
     src = open(os.path.join(ROOT, "include", "facert.h")).read()
-    return sorted(set(re.findall(r"^(?:int|void|const char \*)\s*\*?\s*(fr_\w+)\s*\(", src, re.M)))
+    return sorted(set(re.findall(r"^(?:int|int32_t|void|const char \*)\s*\*?\s*(fr_\w+)\s*\(", src, re.M)))
 
 
 def test_header_declares_the_boundary():
     names = _declared()
     for n in ("fr_create", "fr_set_stream", "fr_blend", "fr_render", "fr_backward", "fr_stats",
-              "fr_last_error", "fr_destroy", "fr_loss_l2", "fr_set_terms", "fr_set_chunk"):
+              "fr_last_error", "fr_destroy", "fr_loss_l2", "fr_set_terms", "fr_set_chunk",
+              "fr_batch_create", "fr_batch_render", "fr_batch_backward", "fr_batch_tune", "fr_batch_capture_begin",
+              "fr_batch_capture_end", "fr_batch_graph_launch", "fr_batch_num_kinds"):
         assert n in names
+    from paper_1910_05200_amd import facert
+    assert set(names) == set(facert.EXPORTS)
 
 
 def test_library_loads_and_exports_every_declared_symbol():
@@ -45,3 +49,23 @@ def test_null_context_and_argument_errors_without_gpu():
     md = facert.fr_model_desc()
     sd = facert.fr_scene_desc()
     assert lib.fr_create(C.byref(md), C.byref(sd), 0, C.byref(out)) == -1
+
+
+def test_batch_argument_errors_without_gpu():
+    from paper_1910_05200_amd import facert
+    lib = facert.load()
+    out = C.c_void_p()
+    assert lib.fr_batch_create(0, None, 0, C.byref(out)) == -1 and not out.value
+    assert lib.fr_batch_create(1, None, 0, C.byref(out)) == -1
+    ctxs = (C.c_void_p * 2)(None, None)
+    assert lib.fr_batch_create(2, ctxs, 0, C.byref(out)) == -1
+    assert lib.fr_batch_render(None, None, None, None, None) == -1
+    assert lib.fr_batch_backward(None, None, None) == -1
+    assert lib.fr_batch_tune(None, 1, None) == -1
+    assert lib.fr_batch_capture_begin(None) == -1
+    assert lib.fr_batch_last_error(None) == b"no context"
+    n = lib.fr_batch_num_kinds()
+    names = [lib.fr_batch_kind_name(k).decode() for k in range(n)]
+    assert len(set(names)) == n and "fwd_shadow" in names and "render_adj" in names
+    assert lib.fr_batch_kind_name(n) is None and lib.fr_batch_kind_name(-1) is None
+    lib.fr_batch_destroy(None)
