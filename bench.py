@@ -38,6 +38,8 @@ OPS_SHADE_ADJ = 590
 # fp32 VALU issue ceiling: 256 CU x 4 SIMD x 16 lanes x 2.4 GHz, one
 # non-packed, non-fused operation per lane per clock
 PEAK_VALU = 39.3      # T lane-ops/s
+# the renderer's kernel sources (a traffic figure is valid while they hash as when it was taken)
+KERNEL_SOURCES = ("facert.hip", "fr_device.hpp", "fr_lbvh.hpp", "fr_batch.hpp")
 
 
 def profiled_traffic(kernel: str, workload: str):
@@ -48,7 +50,7 @@ def profiled_traffic(kernel: str, workload: str):
     if not os.path.exists(path):
         return None
     src = b"".join(open(os.path.join(ROOT, "paper_1910_05200_amd", "csrc", f), "rb").read()
-                   for f in ("facert.hip", "fr_device.hpp"))
+                   for f in KERNEL_SOURCES)
     fields = dict(l.split(": ", 1) for l in open(path).read().splitlines() if ": " in l and not l.startswith("|"))
     if fields.get("kernel_source_sha256", "").strip() != hashlib.sha256(src).hexdigest():
         return None
@@ -105,6 +107,12 @@ def bench_batch(args):
     import torch
     from paper_1910_05200_amd import facert, synth
     lib = facert.load()
+    if args.calibrate_copy:
+        src = torch.ones(64 << 20, device="cuda", dtype=torch.float32)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     inst = synth.batch_workload()
     n = len(inst)
     stream = torch.cuda.Stream()
@@ -193,7 +201,9 @@ def bench_batch(args):
                    "tuned": {k: {"mode": ["flat", "xcd"][v[0][0]], "tile": v[0][1], "ms": round(v[1], 3)}
                              for k, v in tuned.items()}},
         "roofline": {"bound": "alu", "kernel": "fwd_shadow (batched)", "achieved": achieved, "peak": PEAK_VALU,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_VALU, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_VALU,
+                     "traffic": profiled_traffic(f"k_multi_KShadow_{tuned.get('fwd_shadow', ((0, 512),))[0][1]}",
+                                                 "batch"),
                      "ops_per_launch": ops_sh, "ms_per_launch": ms_sh},
     }
     if not args.no_cpu_baseline:
