@@ -802,9 +802,10 @@ __device__ inline bool secondary_edge(const Scene &S, const Light &L, int j, uin
     if (kMode == kSecPropose) return true;
     if (kMode == kSecTrace) {
         n_rays += 2;
-        vp = !trace_any(S, p, yp - p, h.tri, steps);
-        bool vm = !trace_any(S, p, ym - p, h.tri, steps);
-        return vp != vm;
+        bool bp, bm;
+        trace_any2(S, p, yp - p, ym - p, h.tri, bp, bm, steps);
+        vp = !bp;
+        return bp != bm;
     }
     // ---- value path
     Surf<ER> sd;
@@ -997,11 +998,11 @@ __device__ __forceinline__ void edge_primary_setup_body(const Scene &S, uint64_t
             float gl = sqrtf(gx * gx + gy * gy);
             if (gl == 0.0f) break;
             float nx = gx / gl, ny = gy / gl;
-            for (int side = 0; side < 2; ++side) {
-                float sg = side == 0 ? 1.0f : -1.0f;
-                float px = qx + sg * (kEdgeOffPx * nx), py = qy + sg * (kEdgeOffPx * ny);
-                hs[side] = trace_closest(S, cam, camera_dir(S, px, py), wk);
-                ++n_cam;
+            {
+                const float px0 = qx + kEdgeOffPx * nx, py0 = qy + kEdgeOffPx * ny;
+                const float px1 = qx + -1.0f * (kEdgeOffPx * nx), py1 = qy + -1.0f * (kEdgeOffPx * ny);
+                trace_closest2(S, cam, camera_dir(S, px0, py0), camera_dir(S, px1, py1), hs[0], hs[1], wk);
+                n_cam += 2;
             }
             ps.e = e; ps.i = i; ps.pix = (int)fpy * S.W + (int)fpx; ps.qx = qx; ps.qy = qy;
         } while (0);
