@@ -21,6 +21,7 @@ LIB_PATH = os.path.join(HERE, "libfacert.so")
 
 FR_TIMING = 1
 FR_REFIT = 2
+FR_CHUNK_MAX = 1 << 22
 FR_TERM_INTERIOR, FR_TERM_PRIMARY, FR_TERM_SECONDARY = 1, 2, 4
 STATUS = {0: "FR_OK", -1: "FR_EINVAL", -2: "FR_ENOMEM", -3: "FR_EDEVICE", -4: "FR_ESTATE"}
 

@@ -16,6 +16,11 @@ Three ways to get each frame's data-term gradient:
                (the denoiser treated as the identity in the backward pass).
 The denoiser is trained first on renderer-generated pairs (denoise.py).
 
+With one renderer per frame (``frame_renderers``), an iteration renders
+all frames in one batched call and differentiates them in another
+(fr_batch_*, the same results as one frame after another); a frame count
+and spp whose frames exceed one chunk of samples each run frame by frame.
+
     python -m paper_1910_05200_amd.sequence --frames 8 --iters 150 --modes plain:256,plain:16,denoised:2
 
 prints one JSON line per mode: seconds per iteration, parameter errors and
@@ -88,8 +93,14 @@ def errors(shared: dict, betas, poses, base: synth.Params, frames) -> dict:
     return e
 
 
+def frame_renderers(model, scene, n: int):
+    """One renderer (context) per frame, for batched iterations."""
+    return [facert.Renderer(model, scene) for _ in range(n)]
+
+
 def run(r: facert.Renderer, targets, base, frames, start, start_frames, iters: int, mode: str, spp: int,
-        dn: denoise.Denoiser = None, eval_spp: int = synth.TARGET_SPP, log_every: int = 25, decay: float = fit.DECAY):
+        dn: denoise.Denoiser = None, eval_spp: int = synth.TARGET_SPP, log_every: int = 25, decay: float = fit.DECAY,
+        rs=None):
     import torch
     shared = facert.params_to_device(start)
     shared.pop("beta"), shared.pop("pose")
@@ -101,6 +112,9 @@ def run(r: facert.Renderer, targets, base, frames, start, start_frames, iters: i
     want = ("d_alpha", "d_beta", "d_delta", "d_lights", "d_spec", "d_pose")
     n = len(targets)
     log, elapsed = [], 0.0
+    batch = None
+    if rs is not None and len(rs) == n and r.W * r.H * spp <= facert.FR_CHUNK_MAX:
+        batch = facert.Batch(rs)
 
     def evaluate(it):
         psnrs = []
@@ -116,20 +130,27 @@ def run(r: facert.Renderer, targets, base, frames, start, start_frames, iters: i
         t0 = time.perf_counter()
         acc = {k: torch.zeros_like(shared[k]) for k in SHARED}
         f_lr = decay ** (it / max(1, iters - 1))
-        for f in range(n):
-            p = frame_params(shared, betas[f], poses[f].cpu().numpy())
-            seed = 1000 + it * n + f
+        pose_h = torch.stack(poses).cpu().numpy()
+        ps = [frame_params(shared, betas[f], pose_h[f]) for f in range(n)]
+        seeds = [1000 + it * n + f for f in range(n)]
+
+        def data_grad(rf, img, f):
             if mode in ("denoised", "denoised-st"):
-                img = r.render(p, seed, spp)
-                aux = r.aov()
-                den = dn.forward(img, aux)
-                dL, _ = r.loss_l2(den, targets[f])
-                if mode == "denoised":
-                    dL = dn.backward_input(img, dL)
-            else:
-                img = r.render(p, seed, spp)
-                dL, _ = r.loss_l2(img, targets[f])
-            g = r.backward(dL, want=want)
+                den = dn.forward(img, rf.aov())
+                dL, _ = rf.loss_l2(den, targets[f])
+                return dn.backward_input(img, dL) if mode == "denoised" else dL
+            return rf.loss_l2(img, targets[f])[0]
+
+        if batch is not None:
+            imgs = batch.render(ps, seeds, [spp] * n)
+            gs = batch.backward([data_grad(rs[f], imgs[f], f) for f in range(n)], want=want)
+        else:
+            gs = []
+            for f in range(n):
+                img = r.render(ps[f], seeds[f], spp)
+                gs.append(r.backward(data_grad(r, img, f), want=want))
+        for f in range(n):
+            g = gs[f]
             for k in SHARED:
                 acc[k] += g["d_" + k].reshape(acc[k].shape)
             (mb, vb), (mp, vp) = stf[f]
@@ -144,7 +165,10 @@ def run(r: facert.Renderer, targets, base, frames, start, start_frames, iters: i
         elapsed += time.perf_counter() - t0
         if (it + 1) % log_every == 0 or it == iters - 1:
             evaluate(it + 1)
-    return {"mode": mode, "spp": spp, "frames": n, "iters": iters, "s_per_iter": elapsed / iters, "log": log}
+    if batch is not None:
+        batch.close()
+    return {"mode": mode, "spp": spp, "frames": n, "iters": iters, "s_per_iter": elapsed / iters,
+            "batched": batch is not None, "log": log}
 
 
 def main():
@@ -156,11 +180,13 @@ def main():
     ap.add_argument("--dn-pairs", type=int, default=2000)
     ap.add_argument("--dn-epochs", type=int, default=10)
     ap.add_argument("--log-every", type=int, default=25)
+    ap.add_argument("--sequential", action="store_true", help="render and differentiate frame by frame")
     args = ap.parse_args()
     import torch
     assert torch.cuda.is_available(), "sequence fitting needs a HIP device"
     model, scene, _, _ = synth.workload(args.workload)
     r = facert.Renderer(model, scene)
+    rs = None if args.sequential else frame_renderers(model, scene, args.frames)
     base, frames = make_truth(args.frames)
     start, start_frames = make_start(base, frames)
     targets = [r.render(facert.params_to_device(frame_params_np(base, b, p)), synth.TARGET_RENDER_SEED + f,
@@ -175,7 +201,8 @@ def main():
         print(json.dumps({"denoiser_training_s": time.perf_counter() - t0, "pairs": args.dn_pairs,
                           "epochs": args.dn_epochs}), flush=True)
     for m, spp in modes:
-        out = run(r, targets, base, frames, start, start_frames, args.iters, m, spp, dn, log_every=args.log_every)
+        out = run(r, targets, base, frames, start, start_frames, args.iters, m, spp, dn, log_every=args.log_every,
+                  rs=rs)
         print(json.dumps(out), flush=True)
 
 

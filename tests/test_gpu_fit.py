@@ -112,9 +112,16 @@ def test_sequence_fit_runs_every_mode(torch):
                for f, (b, p) in enumerate(frames)]
     dn = denoise.Denoiser(scene.height, scene.width)
     denoise.train(r, dn, 8, 1, log=None)
+    rs = sequence.frame_renderers(model, scene, 2)
     for mode, spp in (("plain", 4), ("denoised", 2), ("denoised-st", 2)):
         out = sequence.run(r, targets, base, frames, start, start_frames, 12, mode, spp, dn, eval_spp=16,
-                           log_every=12)
+                           log_every=12, rs=rs)
         first, last = out["log"][0]["psnr_db"], out["log"][-1]["psnr_db"]
         print(mode, spp, first, last)
-        assert last > first + 1.0, (mode, first, last)
+        assert out["batched"] and last > first + 1.0, (mode, first, last)
+    # frame by frame: the same images and, up to atomics order, the same gradients: the same fit
+    a = sequence.run(r, targets, base, frames, start, start_frames, 6, "plain", 4, dn, eval_spp=16, log_every=6,
+                     rs=rs)
+    b = sequence.run(r, targets, base, frames, start, start_frames, 6, "plain", 4, dn, eval_spp=16, log_every=6)
+    assert a["batched"] and not b["batched"]
+    assert abs(a["log"][-1]["psnr_db"] - b["log"][-1]["psnr_db"]) < 0.05, (a["log"][-1], b["log"][-1])
