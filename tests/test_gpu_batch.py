@@ -3,8 +3,11 @@
 A batch must give, for every instance, what fr_render / fr_backward give on
 that instance's context alone (themselves held to the oracle by
 test_gpu_parity): images bitwise, in every launch mode and tile size;
-gradients up to the order of their fp64 atomic sums (bar: 1e-6 of the
-group's largest magnitude).  One instance is also held to the oracle
+gradients up to the order of their atomic sums.  Bars, of the group's
+largest magnitude: 1e-6 for the groups summed in fp64; 2e-5 for the light
+and texel adjoints, which each block first sums in fp32 LDS atomics (their
+rounding changes with the order in which lanes arrive, from one run to the
+next even on one context).  One instance is also held to the oracle
 directly, and the full batched workload (32 faces of 5k-40k vertices at
 128^2-512^2 and 4-16 spp) to the single-context path after autotuning.
 """
@@ -18,10 +21,13 @@ from parity import assert_group_parity, assert_image_parity
 
 pytestmark = pytest.mark.gpu
 
-# (nx, ny, W, H, spp, lights): meshes of 108 to 360 vertices, ragged image
-# sizes, 1 to 4 spp, two light-stage sizes
-SMALL = [(12, 14, 32, 32, 2, 20), (16, 16, 40, 24, 3, 12), (20, 18, 48, 48, 4, 20), (9, 11, 24, 40, 1, 20)]
+# (nx, ny, W, H, spp, lights): meshes of 6 to 360 vertices, ragged image
+# sizes down to one pixel, 1 to 4 spp, two light-stage sizes
+SMALL = [(12, 14, 32, 32, 2, 20), (16, 16, 40, 24, 3, 12), (20, 18, 48, 48, 4, 20), (9, 11, 24, 40, 1, 20),
+         (3, 2, 1, 1, 1, 12)]
 GRAD_BAR = 1e-6
+GRAD_BAR_LDS32 = 2e-5
+LDS32 = ("d_lights", "d_spec")
 # A persistent work-queue mode (a fixed grid taking tiles from an atomic
 # counter; its run also used tile size 1024) hung on its first GPU run, and
 # again after a change that did not find its cause; it is switched off in the
@@ -84,7 +90,7 @@ def test_batch_render_bitwise_matches_single(torch, name, mode, tile):
     imgs = [x.cpu().numpy() for x in batch.render(ps, seeds, spps)]
     for i, r in enumerate(rs):
         ref = r.render(ps[i], seeds[i], spps[i]).cpu().numpy()
-        assert imgs[i].shape == ref.shape and (ref.sum(-1) > 0).mean() > 0.1
+        assert imgs[i].shape == ref.shape and (ref.size < 64 * 3 or (ref.sum(-1) > 0).mean() > 0.1)
         assert np.array_equal(imgs[i], ref), f"instance {i}: max diff {np.abs(imgs[i] - ref).max()}"
 
 
@@ -92,7 +98,8 @@ def _assert_grads_close(gb, gs, where):
     for k in gs:
         scale = float(np.abs(gs[k]).max())
         err = float(np.abs(gb[k].astype(np.float64) - gs[k]).max())
-        assert err <= GRAD_BAR * scale + 1e-30, f"{where} {k}: max err {err:.3g}, scale {scale:.3g}"
+        bar = GRAD_BAR_LDS32 if k in LDS32 else GRAD_BAR
+        assert err <= bar * scale + 1e-30, f"{where} {k}: max err {err:.3g}, scale {scale:.3g}"
 
 
 @pytest.mark.parametrize("name,mode,tile", [MODES[0], MODES[1], MODES[4]])
@@ -108,7 +115,7 @@ def test_batch_backward_matches_single(torch, name, mode, tile):
     for i, r in enumerate(rs):
         r.render(ps[i], seeds[i], spps[i])
         gs = _np(r.backward(dls[i]))
-        assert any(np.abs(v).max() > 0 for v in gs.values())
+        assert rs[i].W * rs[i].H < 64 or any(np.abs(v).max() > 0 for v in gs.values())
         _assert_grads_close(gb[i], gs, f"instance {i}")
 
 
@@ -227,7 +234,7 @@ def test_batch_errors(torch):
     from paper_1910_05200_amd import facert
     inst = _small()
     rs, ps, batch = _setup(torch, inst)
-    seeds = [1, 2, 3, 4]
+    seeds = [1, 2, 3, 4, 5]
     spps = [spp for *_, spp in inst]
     with pytest.raises(facert.FrError) as e:
         batch.backward(_dls(torch, inst))
@@ -239,7 +246,7 @@ def test_batch_errors(torch):
     with pytest.raises(facert.FrError):
         facert.Batch([rr, rs[1]])
     with pytest.raises(facert.FrError) as e:
-        batch.render(ps, seeds, [1, 1, 1, 4097])
+        batch.render(ps, seeds, [1, 1, 1, 1, 4097])
     assert e.value.code == -1
     m, sc, p, _ = inst[0]
     big = synth.make_scene(64, 64)
