@@ -422,6 +422,9 @@ __global__ __launch_bounds__(256) void k_fwd_camera(Scene S, uint64_t seed, int 
 // template parameter of the bodies (single-instance launches use kShTile;
 // the batched launcher may pick another).
 constexpr int kShTile = 512;
+// The shadow-boundary kernel keeps its accepted samples' two side rays in
+// LDS (48 bytes each), so its tile is smaller: 256 samples.
+constexpr int kSecTile = 256;
 __device__ __forceinline__ int lanes_below(unsigned long long m) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0));
 }
@@ -763,7 +766,8 @@ enum { kSecPropose, kSecTrace, kSecValue };
 template <int kMode>
 __device__ inline bool secondary_edge(const Scene &S, const Light &L, int j, uint64_t seed, uint32_t sidx,
                                       const float *spec_lds, v3 o, v3 dcam, const Hit &h, const SurfDec &sf,
-                                      const float *w, double *d_pos, bool &vp, uint32_t &n_rays, Work &steps) {
+                                      const float *w, double *d_pos, bool &vp, uint32_t &n_rays, Work &steps,
+                                      v3 *d_sides = nullptr) {
     int n = S.se_n[j];
     uint64_t Q = S.se_Q[j];
     if (n == 0 || Q == 0) return false;
@@ -799,7 +803,10 @@ __device__ inline bool secondary_edge(const Scene &S, const Light &L, int j, uin
     v3 un = mk(mp.x / lm, mp.y / lm, mp.z / lm);
     v3 yp = mk(y.x + kEdgeOffM * un.x, y.y + kEdgeOffM * un.y, y.z + kEdgeOffM * un.z);
     v3 ym = mk(y.x - kEdgeOffM * un.x, y.y - kEdgeOffM * un.y, y.z - kEdgeOffM * un.z);
-    if (kMode == kSecPropose) return true;
+    if (kMode == kSecPropose) {
+        if (d_sides) { d_sides[0] = yp - p; d_sides[1] = ym - p; }
+        return true;
+    }
     if (kMode == kSecTrace) {
         n_rays += 2;
         bool bp, bm;
@@ -834,11 +841,13 @@ __device__ inline bool secondary_edge(const Scene &S, const Light &L, int j, uin
     return true;
 }
 
-// One block per (tile of kShTile camera samples, light).  The lanes first
+// One block per (tile of kSecTile camera samples, light).  The lanes first
 // run each sample's edge pick and acceptance tests (no rays) and compact the
-// accepted samples into an LDS list; the block's waves then run those
-// samples whole, two shadow rays each.  Most samples are rejected before
-// any ray, so tracing in place would leave most lanes idle.
+// accepted samples' shading point and two side rays into an LDS list; the
+// block's waves then trace each entry's two rays in one walk.  Most samples
+// are rejected before any ray, so tracing in place would leave most lanes
+// idle, and keeping the rays spares the trace phase a second run of the
+// edge pick (a binary search over the CDF) and the acceptance tests.
 __device__ __forceinline__ void sec_setup(const Scene &S, uint64_t seed, int spp, long long s0, long long i,
         const float *dLdI, const HitRec *hits, v3 &o, v3 &d, float w[3], Hit &h, SurfDec &sd, uint32_t &s,
         bool &live) {
@@ -866,7 +875,9 @@ __device__ __forceinline__ void edge_secondary_body(const Scene &S, uint64_t see
         const float *__restrict__ dLdI, const HitRec *__restrict__ hits, uint32_t *__restrict__ out,
         uint32_t *__restrict__ out_n, unsigned long long *ctr, int bx, int j) {
     __shared__ Light Ls[kMaxLights];
-    __shared__ int q_i[TS];
+    __shared__ float4 q_a[TS];   // shading point, its triangle
+    __shared__ float4 q_b[TS];   // toward the + side point, tile-local sample index
+    __shared__ float4 q_c[TS];   // toward the - side point
     __shared__ int q_n;
     for (int k = threadIdx.x; k < S.nl; k += blockDim.x) {
         const float *g = S.lgeom + 12 * k;
@@ -886,17 +897,28 @@ __device__ __forceinline__ void edge_secondary_body(const Scene &S, uint64_t see
         const int li = k + (int)threadIdx.x;
         const long long i = base + li;
         bool need = false;
+        v3 sides[2], p0;
+        int tri = -1;
         if (i < n) {
             v3 o, d; float w[3]; Hit h; SurfDec sd; uint32_t s; bool live;
             sec_setup(S, seed, spp, s0, i, dLdI, hits, o, d, w, h, sd, s, live);
-            if (live)
-                need = secondary_edge<kSecPropose>(S, Ls[j], j, seed, s, nullptr, o, d, h, sd, w, nullptr, vp, n_sec, wk);
+            if (live) {
+                need = secondary_edge<kSecPropose>(S, Ls[j], j, seed, s, nullptr, o, d, h, sd, w, nullptr, vp, n_sec,
+                                                   wk, sides);
+                p0 = sd.p;
+                tri = h.tri;
+            }
         }
         unsigned long long m = __ballot(need);
         int wbase = 0;
         if (lane == 0 && m) wbase = atomicAdd(&q_n, __popcll(m));
         wbase = __shfl(wbase, 0);
-        if (need) q_i[wbase + lanes_below(m)] = li;
+        if (need) {
+            const int slot = wbase + lanes_below(m);
+            q_a[slot] = make_float4(p0.x, p0.y, p0.z, __int_as_float(tri));
+            q_b[slot] = make_float4(sides[0].x, sides[0].y, sides[0].z, __int_as_float(li));
+            q_c[slot] = make_float4(sides[1].x, sides[1].y, sides[1].z, 0.0f);
+        }
     }
     __syncthreads();
     const int nq = q_n;
@@ -904,10 +926,14 @@ __device__ __forceinline__ void edge_secondary_body(const Scene &S, uint64_t see
         bool val = false;
         long long i = 0;
         if (e < nq) {
-            i = base + q_i[e];
-            v3 o, d; float w[3]; Hit h; SurfDec sd; uint32_t s; bool live;
-            sec_setup(S, seed, spp, s0, i, dLdI, hits, o, d, w, h, sd, s, live);
-            val = secondary_edge<kSecTrace>(S, Ls[j], j, seed, s, nullptr, o, d, h, sd, w, nullptr, vp, n_sec, wk);
+            // the two side rays as the proposal computed them
+            const float4 a = q_a[e], b = q_b[e], c = q_c[e];
+            i = base + __float_as_int(b.w);
+            bool bp, bm;
+            n_sec += 2;
+            trace_any2(S, mk(a.x, a.y, a.z), mk(b.x, b.y, b.z), mk(c.x, c.y, c.z), __float_as_int(a.w), bp, bm, wk);
+            vp = !bp;
+            val = bp != bm;
         }
         unsigned long long m = __ballot(val);
         uint32_t obase = 0;
@@ -921,7 +947,7 @@ __device__ __forceinline__ void edge_secondary_body(const Scene &S, uint64_t see
 __global__ __launch_bounds__(256) void k_edge_secondary(Scene S, uint64_t seed, int spp, long long s0, long long n,
         const float *__restrict__ dLdI, const HitRec *__restrict__ hits, uint32_t *__restrict__ out,
         uint32_t *__restrict__ out_n, unsigned long long *ctr) {
-    edge_secondary_body<kShTile>(S, seed, spp, s0, n, dLdI, hits, out, out_n, ctr, blockIdx.x, blockIdx.y);
+    edge_secondary_body<kSecTile>(S, seed, spp, s0, n, dLdI, hits, out, out_n, ctr, blockIdx.x, blockIdx.y);
 }
 
 // gx blocks stride over the list
@@ -2081,7 +2107,7 @@ int fr_backward(fr_ctx *c, const float *dLdI, const fr_grads *g) {
             for (long long o = 0; o < n; o += kSecSub) {
                 long long m = std::min(kSecSub, n - o);
                 hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, c->stream, c->sec_n, 1);
-                hipLaunchKernelGGL(k_edge_secondary, dim3(nblk(m, kShTile), c->nl), dim3(256), 0, c->stream, S,
+                hipLaunchKernelGGL(k_edge_secondary, dim3(nblk(m, kSecTile), c->nl), dim3(256), 0, c->stream, S,
                                    c->last_seed, c->last_spp, s0 + o, m, dLdI, c->hits + o, c->sec_list, c->sec_n,
                                    c->ctr + 8 * kKernSecondary);
                 hipLaunchKernelGGL(k_edge_secondary_value, dim3(1024), dim3(256), lds1, c->stream, S, c->last_seed,
