@@ -269,7 +269,9 @@ int fr_batch_set_stream(fr_batch *batch, void *hip_stream);
  * device pointers, [H][W][3] each).  A new set of spp values reallocates
  * scratch and synchronises; the same set again does not.  Errors: FR_EINVAL
  * (null or out-of-range arguments, a context on another stream), FR_ESTATE
- * (new spp values during graph capture), FR_ENOMEM. */
+ * (new spp values during graph capture), FR_ENOMEM.  A call after new spp
+ * values or a changed launch (fr_batch_set_launch) first waits for the
+ * batch's enqueued work, which reads the tables it rewrites. */
 int fr_batch_render(fr_batch *batch, const fr_params *params, const uint64_t *seeds, const int32_t *spp,
                     float *const *out);
 
@@ -288,12 +290,13 @@ int fr_batch_set_launch(fr_batch *batch, int32_t kind, const fr_launch *launch);
 
 /* Autotuner: replays the last fr_batch_render + fr_batch_backward (same
  * inputs and outputs, which the caller keeps alive; the outputs are written
- * again with the same values up to atomics order) once per candidate
- * launch of each tunable kind, 'trials' times (1..16), and keeps the
- * fastest candidate of each.  ms_best [fr_batch_num_kinds()] (host,
- * nullable) gets each kind's best time (0 for kinds not tuned).
- * Synchronises.  Errors: FR_ESTATE (no FR_TIMING, no prior backward,
- * during capture), FR_EINVAL. */
+ * again with the same values up to atomics order) and picks the launches
+ * by coordinate descent on the whole replay's time: each tunable kind in
+ * turn tries its candidates ('trials' replays each, 1..16, median) with the
+ * other kinds at their current choice and keeps the fastest.  ms_best
+ * [fr_batch_num_kinds()] (host, nullable) gets each tuned kind's own time
+ * in the final choice (0 for kinds not tuned).  Synchronises.  Errors:
+ * FR_ESTATE (no FR_TIMING, no prior backward, during capture), FR_EINVAL. */
 int fr_batch_tune(fr_batch *batch, int32_t trials, float *ms_best);
 
 /* Times of the last batched calls (synchronises): ms_kind

@@ -281,7 +281,7 @@ struct fr_batch {
     bool capturing = false;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    hipEvent_t ev[2 * bkNum + 4] = {};
+    hipEvent_t ev[2 * bkNum + 6] = {};   // per kind; render, backward; the tuner's replays
     bool timed[bkNum] = {};
     float ms[bkNum] = {};
     float ms_render = 0, ms_backward = 0;
@@ -349,6 +349,9 @@ static void kind_grid(const fr_batch *b, int k, int i, int &gx, int &gy) {
 }
 
 static int build_plan(fr_batch *b) {
+    // batched work already enqueued reads the current plan: let it finish
+    // before the host overwrites it
+    BHIPCK(b, hipStreamSynchronize(b->stream));
     std::vector<int> h;
     for (int k = 0; k < bkNum; ++k) {
         KindPlan &p = b->kp[k];
@@ -501,6 +504,9 @@ static void seq_backward(fr_batch *b) {
 // buffers sized for the sample counts, static descriptors, tile plan
 static int configure(fr_batch *b, const int32_t *spp) {
     if (b->capturing) return bfail(b, FR_ESTATE, "fr_batch: sample counts changed during graph capture");
+    // batched work already enqueued reads the descriptor table and the
+    // contexts' scratch: let it finish before either changes
+    BHIPCK(b, hipStreamSynchronize(b->stream));
     b->spp.assign(spp, spp + b->n);
     b->N.resize(b->n);
     b->host.resize(b->n);
@@ -755,8 +761,30 @@ int fr_batch_timing(fr_batch *b, float *ms_kind, float *ms_render, float *ms_bac
 }
 
 // Autotuner: replays the last render and backward (same parameters, seeds,
-// inputs and outputs) once per candidate launch and keeps, for each tunable
-// kind, the candidate of least time (minimum over 'trials' replays).
+// inputs and outputs) and chooses the launches by coordinate descent on the
+// whole step's time: for each tunable kind in turn, each of its candidates
+// with every other kind at its current choice, 'trials' replays each, the
+// fastest (by its median) kept before the next kind.  Kinds interact through
+// the placement of their tiles on the XCDs (a kind reads in its L2 what the
+// kind before it wrote there), so a kind's own time alone can mislead.
+// ms_best receives each kind's own time in the final choice.
+static int replay_ms(fr_batch *b, int trials, float *ms) {
+    std::vector<float> t(trials);
+    for (int tr = 0; tr < trials; ++tr) {
+        if (b->plan_dirty) { int rc = build_plan(b); if (rc) return rc; }
+        BHIPCK(b, hipEventRecord(b->ev[2 * bkNum + 4], b->stream));
+        seq_forward(b);
+        seq_backward(b);
+        BHIPCK(b, hipEventRecord(b->ev[2 * bkNum + 5], b->stream));
+        BHIPCK(b, hipGetLastError());
+        BHIPCK(b, hipStreamSynchronize(b->stream));
+        BHIPCK(b, hipEventElapsedTime(&t[tr], b->ev[2 * bkNum + 4], b->ev[2 * bkNum + 5]));
+    }
+    std::sort(t.begin(), t.end());
+    *ms = t[trials / 2];
+    return FR_OK;
+}
+
 int fr_batch_tune(fr_batch *b, int32_t trials, float *ms_best) {
     if (!b) return FR_EINVAL;
     b->err.clear();
@@ -764,52 +792,36 @@ int fr_batch_tune(fr_batch *b, int32_t trials, float *ms_best) {
     if (!b->have_backward) return bfail(b, FR_ESTATE, "fr_batch_tune: needs a prior render and backward");
     if (b->capturing) return bfail(b, FR_ESTATE, "fr_batch_tune: graph capture in progress");
     if (trials < 1 || trials > 16) return bfail(b, FR_EINVAL, "fr_batch_tune: trials %d out of [1, 16]", trials);
-    std::vector<fr_launch> cand[bkNum];
+    BHIPCK(b, hipStreamSynchronize(b->stream));
+    float ms;
+    int rc = replay_ms(b, 1, &ms);      // one untimed warm replay
+    if (rc) return rc;
     for (int k = 0; k < bkNum; ++k) {
         if (!kind_tunable(k)) continue;
+        std::vector<fr_launch> cand;
         const int nt = kind_tiled(k) ? 2 : 1;
         for (int t = 0; t < nt; ++t) {
             const int ts = kind_tiled(k) ? kTiles[t] : 0;
-            cand[k].push_back(fr_launch{FR_LAUNCH_FLAT, ts});
-            cand[k].push_back(fr_launch{FR_LAUNCH_XCD, ts});
+            cand.push_back(fr_launch{FR_LAUNCH_FLAT, ts});
+            cand.push_back(fr_launch{FR_LAUNCH_XCD, ts});
         }
+        fr_launch best = b->launch[k];
+        float best_ms = INFINITY;
+        for (const fr_launch &L : cand) {
+            if (L.tile != b->launch[k].tile) b->plan_dirty = true;
+            b->launch[k] = L;
+            if ((rc = replay_ms(b, trials, &ms))) return rc;
+            if (ms < best_ms) { best_ms = ms; best = L; }
+        }
+        if (best.tile != b->launch[k].tile) b->plan_dirty = true;
+        b->launch[k] = best;
     }
-    size_t rounds = 0;
-    for (auto &c : cand) rounds = std::max(rounds, c.size());
-    std::vector<std::vector<float>> best(bkNum);
-    for (int k = 0; k < bkNum; ++k) best[k].assign(cand[k].size(), INFINITY);
-    for (size_t r = 0; r < rounds; ++r)
-        for (int tr = 0; tr < trials; ++tr) {
-            for (int k = 0; k < bkNum; ++k)
-                if (!cand[k].empty()) {
-                    const fr_launch &L = cand[k][r % cand[k].size()];
-                    if (L.tile != b->launch[k].tile) b->plan_dirty = true;
-                    b->launch[k] = L;
-                }
-            if (b->plan_dirty) { int rc = build_plan(b); if (rc) return rc; }
-            seq_forward(b);
-            seq_backward(b);
-            BHIPCK(b, hipGetLastError());
-            BHIPCK(b, hipStreamSynchronize(b->stream));
-            for (int k = 0; k < bkNum; ++k) {
-                float t;
-                if (!cand[k].empty() && b->timed[k] &&
-                    hipEventElapsedTime(&t, b->ev[2 * k], b->ev[2 * k + 1]) == hipSuccess) {
-                    float &slot = best[k][r % cand[k].size()];
-                    slot = std::min(slot, t);
-                }
-            }
-        }
+    if ((rc = replay_ms(b, 1, &ms))) return rc;   // per-kind times of the choice
     for (int k = 0; k < bkNum; ++k) {
-        if (cand[k].empty()) { if (ms_best) ms_best[k] = 0.0f; continue; }
-        size_t bi = 0;
-        for (size_t q = 1; q < cand[k].size(); ++q)
-            if (best[k][q] < best[k][bi]) bi = q;
-        if (cand[k][bi].tile != b->launch[k].tile) b->plan_dirty = true;
-        b->launch[k] = cand[k][bi];
-        if (ms_best) ms_best[k] = best[k][bi];
+        float t = 0.0f;
+        if (kind_tunable(k) && b->timed[k]) (void)hipEventElapsedTime(&t, b->ev[2 * k], b->ev[2 * k + 1]);
+        if (ms_best) ms_best[k] = kind_tunable(k) ? t : 0.0f;
     }
-    if (b->plan_dirty) { int rc = build_plan(b); if (rc) return rc; }
     (void)hipGetLastError();
     return FR_OK;
 }

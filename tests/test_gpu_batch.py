@@ -230,6 +230,38 @@ def test_batch_tune_keeps_results(torch):
         _assert_grads_close(gb[i], _np(r.backward(dls[i])), f"tuned instance {i}")
 
 
+def test_batch_relaunch_does_not_disturb_enqueued_work(torch):
+    """New tile sizes while a batched render is still queued (behind a long
+    matrix product on the same stream), then new sample counts: each queued
+    render keeps the tile maps and descriptors it was enqueued with.  (The
+    first change must not rewrite the tile maps under the queued render: the
+    sample counts stay, so no reallocation synchronises the device.)"""
+    inst = _small()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        rs, ps, batch = _setup(torch, inst)
+        seeds = [6000 + i for i in range(len(inst))]
+        spps = [spp for *_, spp in inst]
+        batch.render(ps, seeds, spps)                    # configure once
+        s.synchronize()
+        a = torch.randn(6144, 6144, device="cuda")
+        for _ in range(4):
+            a = a @ a * 1e-3                             # keeps the stream busy
+        first = batch.render(ps, seeds, spps)
+        batch.set_launch("fwd_shadow", 0, 256)
+        batch.set_launch("edge_primary_vis", 1, 256)
+        second = batch.render(ps, [x + 1 for x in seeds], spps)
+        for _ in range(4):
+            a = a @ a * 1e-3
+        batch.set_launch("fwd_shadow", 1, 512)
+        third = batch.render(ps, [x + 2 for x in seeds], [x + 1 for x in spps])
+        s.synchronize()
+        for i, r in enumerate(rs):
+            assert torch.equal(first[i], r.render(ps[i], seeds[i], spps[i])), f"first render, instance {i}"
+            assert torch.equal(second[i], r.render(ps[i], seeds[i] + 1, spps[i])), f"second render, instance {i}"
+            assert torch.equal(third[i], r.render(ps[i], seeds[i] + 2, spps[i] + 1)), f"third render, instance {i}"
+
+
 def test_batch_errors(torch):
     from paper_1910_05200_amd import facert
     inst = _small()
