@@ -22,9 +22,11 @@ from parity import assert_group_parity, assert_image_parity
 pytestmark = pytest.mark.gpu
 
 # (nx, ny, W, H, spp, lights): meshes of 6 to 360 vertices, ragged image
-# sizes down to one pixel, 1 to 4 spp, two light-stage sizes
+# sizes down to one pixel, 1 to 4 spp, two light-stage sizes; the last face
+# is moved out of view (an empty image: no hits, no silhouettes)
 SMALL = [(12, 14, 32, 32, 2, 20), (16, 16, 40, 24, 3, 12), (20, 18, 48, 48, 4, 20), (9, 11, 24, 40, 1, 20),
-         (3, 2, 1, 1, 1, 12)]
+         (3, 2, 1, 1, 1, 12), (10, 10, 24, 24, 2, 20)]
+OUT_OF_VIEW = len(SMALL) - 1
 GRAD_BAR = 1e-6
 GRAD_BAR_LDS32 = 2e-5
 LDS32 = ("d_lights", "d_spec")
@@ -53,7 +55,10 @@ def _small():
         model = synth.make_model(nx, ny, seed=10 + i)
         scene = synth.make_scene(W, H)
         scene.light_geom = synth.light_stage(nl)
-        out.append((model, scene, synth.make_params(50 + i, n_lights=nl), spp))
+        params = synth.make_params(50 + i, n_lights=nl)
+        if i == OUT_OF_VIEW:
+            params.pose[3] = 5.0
+        out.append((model, scene, params, spp))
     return out
 
 
@@ -90,7 +95,10 @@ def test_batch_render_bitwise_matches_single(torch, name, mode, tile):
     imgs = [x.cpu().numpy() for x in batch.render(ps, seeds, spps)]
     for i, r in enumerate(rs):
         ref = r.render(ps[i], seeds[i], spps[i]).cpu().numpy()
-        assert imgs[i].shape == ref.shape and (ref.size < 64 * 3 or (ref.sum(-1) > 0).mean() > 0.1)
+        if i == OUT_OF_VIEW:
+            assert not ref.any()
+        else:
+            assert imgs[i].shape == ref.shape and (ref.size < 64 * 3 or (ref.sum(-1) > 0).mean() > 0.1)
         assert np.array_equal(imgs[i], ref), f"instance {i}: max diff {np.abs(imgs[i] - ref).max()}"
 
 
@@ -115,7 +123,10 @@ def test_batch_backward_matches_single(torch, name, mode, tile):
     for i, r in enumerate(rs):
         r.render(ps[i], seeds[i], spps[i])
         gs = _np(r.backward(dls[i]))
-        assert rs[i].W * rs[i].H < 64 or any(np.abs(v).max() > 0 for v in gs.values())
+        if i == OUT_OF_VIEW:
+            assert not any(np.abs(v).max() > 0 for k, v in gs.items() if k != "d_lights")
+        else:
+            assert rs[i].W * rs[i].H < 64 or any(np.abs(v).max() > 0 for v in gs.values())
         _assert_grads_close(gb[i], gs, f"instance {i}")
 
 
@@ -266,7 +277,7 @@ def test_batch_errors(torch):
     from paper_1910_05200_amd import facert
     inst = _small()
     rs, ps, batch = _setup(torch, inst)
-    seeds = [1, 2, 3, 4, 5]
+    seeds = [1, 2, 3, 4, 5, 6]
     spps = [spp for *_, spp in inst]
     with pytest.raises(facert.FrError) as e:
         batch.backward(_dls(torch, inst))
@@ -278,7 +289,7 @@ def test_batch_errors(torch):
     with pytest.raises(facert.FrError):
         facert.Batch([rr, rs[1]])
     with pytest.raises(facert.FrError) as e:
-        batch.render(ps, seeds, [1, 1, 1, 1, 4097])
+        batch.render(ps, seeds, [1, 1, 1, 1, 1, 4097])
     assert e.value.code == -1
     m, sc, p, _ = inst[0]
     big = synth.make_scene(64, 64)
