@@ -10,8 +10,10 @@ instead of falling back to anything else.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import os
+import weakref
 from typing import Optional
 
 import numpy as np
@@ -82,6 +84,20 @@ EXPORTS = ("fr_create", "fr_set_stream", "fr_set_terms", "fr_set_chunk", "fr_ble
            "fr_batch_destroy")
 
 _lib = None
+
+# Contexts and batches still open at interpreter exit are closed by an exit
+# handler registered after torch's, so it runs first: destroying them later,
+# once the HIP runtime is being torn down, can stall the process.
+_live = weakref.WeakSet()
+
+
+@atexit.register
+def _close_all():
+    for obj in list(_live):
+        try:
+            obj.close()
+        except Exception:
+            pass
 
 
 def load():
@@ -185,6 +201,7 @@ class Renderer:
         self.n_id, self.n_exp, self.n_alb = md.n_id, md.n_exp, md.n_alb
         self.render_token = 0
         self._last = None
+        _live.add(self)
 
     # -- plumbing
     def _stream(self):
@@ -316,6 +333,7 @@ class Batch:
         self.b = b
         self.n = n
         self._keep = None
+        _live.add(self)
         self.kinds = [load().fr_batch_kind_name(k).decode() for k in range(load().fr_batch_num_kinds())]
 
     def _stream(self):

@@ -41,6 +41,22 @@ W2 = 1e-3          # weight of E_light
 START_SEED = 3     # seed of the perturbation that gives the fitting start
 
 
+def finite_groups(named, counts: dict) -> dict:
+    """{name: every component finite} for (name, tensor) pairs, read back
+    with one synchronisation; a non-finite group's count goes up (a fitting
+    loop then leaves that group unchanged for the iteration: one non-finite
+    component would make Adam's moments, and so the parameters, non-finite
+    for good)."""
+    import torch
+    flags = torch.stack([torch.isfinite(t).all() for _, t in named]).cpu().tolist()
+    out = {}
+    for (name, _), ok in zip(named, flags):
+        out[name] = bool(ok)
+        if not ok:
+            counts[name] = counts.get(name, 0) + 1
+    return out
+
+
 def psnr(img, ref) -> float:
     """Peak signal-to-noise ratio in dB, peak = max of the reference."""
     img = np.asarray(img, np.float64)
@@ -74,6 +90,7 @@ def fit(r: facert.Renderer, target, start: synth.Params, iters: int, spp: int, w
     state = {k: (torch.zeros_like(p[k]), torch.zeros_like(p[k])) for k in groups}
     state["pose"] = (torch.zeros_like(pose_d), torch.zeros_like(pose_d))
     losses = []
+    nonfinite = {}
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for it in range(iters):
@@ -84,18 +101,23 @@ def fit(r: facert.Renderer, target, start: synth.Params, iters: int, spp: int, w
         r.light_reg(p["lights"], w2, g["d_lights"])
         f = decay ** (it / max(1, iters - 1))
         step = it + 1
+        ok = finite_groups([(k, g["d_" + k]) for k in groups + ("pose",)], nonfinite)
         for k in groups:
             m, v = state[k]
-            r.adam(p[k], g["d_" + k].reshape(p[k].shape), m, v, step, lr[k] * f)
+            if ok[k]:
+                r.adam(p[k], g["d_" + k].reshape(p[k].shape), m, v, step, lr[k] * f)
         m, v = state["pose"]
-        r.adam(pose_d[:3], g["d_pose"][:3], m[:3], v[:3], step, lr["rot"] * f)
-        r.adam(pose_d[3:], g["d_pose"][3:], m[3:], v[3:], step, lr["trans"] * f)
+        if ok["pose"]:
+            r.adam(pose_d[:3], g["d_pose"][:3], m[:3], v[:3], step, lr["rot"] * f)
+            r.adam(pose_d[3:], g["d_pose"][3:], m[3:], v[3:], step, lr["trans"] * f)
         losses.append(loss)
         if log_every and (it % log_every == 0 or it == iters - 1):
             print(f"it {it:4d}  E_data {float(loss):.6g}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     sec = (time.perf_counter() - t0) / max(1, iters)
     p["pose"] = pose_d.cpu().numpy()
+    if nonfinite:
+        print(f"updates skipped for non-finite gradients: {nonfinite}", file=sys.stderr, flush=True)
     return p, [float(x) for x in losses], sec
 
 

@@ -112,6 +112,7 @@ def run(r: facert.Renderer, targets, base, frames, start, start_frames, iters: i
     want = ("d_alpha", "d_beta", "d_delta", "d_lights", "d_spec", "d_pose")
     n = len(targets)
     log, elapsed = [], 0.0
+    nonfinite = {}                       # parameter group -> skipped updates
     batch = None
     if rs is not None and len(rs) == n and r.W * r.H * spp <= facert.FR_CHUNK_MAX:
         batch = facert.Batch(rs)
@@ -123,6 +124,7 @@ def run(r: facert.Renderer, targets, base, frames, start, start_frames, iters: i
             psnrs.append(fit.psnr(img.cpu().numpy(), targets[f].cpu().numpy()))
         e = errors(shared, betas, poses, base, frames)
         log.append({"iter": it, "seconds": elapsed, "psnr_db": float(np.mean(psnrs)), "errors": e})
+        print(f"{mode}:{spp} iteration {it}: {elapsed:.2f} s, {log[-1]['psnr_db']:.2f} dB", file=sys.stderr, flush=True)
 
     evaluate(0)
     for it in range(iters):
@@ -150,17 +152,25 @@ def run(r: facert.Renderer, targets, base, frames, start, start_frames, iters: i
                 img = r.render(ps[f], seeds[f], spp)
                 gs.append(r.backward(data_grad(r, img, f), want=want))
         for f in range(n):
-            g = gs[f]
             for k in SHARED:
-                acc[k] += g["d_" + k].reshape(acc[k].shape)
-            (mb, vb), (mp, vp) = stf[f]
-            r.adam(betas[f], g["d_beta"], mb, vb, it + 1, LR["beta"] * f_lr)
-            r.adam(poses[f][:3], g["d_pose"][:3], mp[:3], vp[:3], it + 1, LR["rot"] * f_lr)
-            r.adam(poses[f][3:], g["d_pose"][3:], mp[3:], vp[3:], it + 1, LR["trans"] * f_lr)
+                acc[k] += gs[f]["d_" + k].reshape(acc[k].shape)
         r.light_reg(shared["lights"], fit.W2, acc["lights"])
+        named = [(k, acc[k]) for k in SHARED]
+        for f in range(n):
+            named += [(f"beta{f}", gs[f]["d_beta"]), (f"pose{f}", gs[f]["d_pose"])]
+        ok = fit.finite_groups(named, nonfinite)
+        for f in range(n):
+            g = gs[f]
+            (mb, vb), (mp, vp) = stf[f]
+            if ok[f"beta{f}"]:
+                r.adam(betas[f], g["d_beta"], mb, vb, it + 1, LR["beta"] * f_lr)
+            if ok[f"pose{f}"]:
+                r.adam(poses[f][:3], g["d_pose"][:3], mp[:3], vp[:3], it + 1, LR["rot"] * f_lr)
+                r.adam(poses[f][3:], g["d_pose"][3:], mp[3:], vp[3:], it + 1, LR["trans"] * f_lr)
         for k in SHARED:
             m, v = st[k]
-            r.adam(shared[k], acc[k], m, v, it + 1, LR[k] * f_lr)
+            if ok[k]:
+                r.adam(shared[k], acc[k], m, v, it + 1, LR[k] * f_lr)
         torch.cuda.synchronize()
         elapsed += time.perf_counter() - t0
         if (it + 1) % log_every == 0 or it == iters - 1:
@@ -168,7 +178,7 @@ def run(r: facert.Renderer, targets, base, frames, start, start_frames, iters: i
     if batch is not None:
         batch.close()
     return {"mode": mode, "spp": spp, "frames": n, "iters": iters, "s_per_iter": elapsed / iters,
-            "batched": batch is not None, "log": log}
+            "batched": batch is not None, "nonfinite_updates_skipped": nonfinite, "log": log}
 
 
 def main():
@@ -176,7 +186,10 @@ def main():
     ap.add_argument("--frames", type=int, default=8)
     ap.add_argument("--iters", type=int, default=150)
     ap.add_argument("--modes", default="plain:256,plain:16,plain:2,denoised:2")
-    ap.add_argument("--workload", default="paper", choices=["paper", "tiny"])
+    ap.add_argument("--workload", default="paper", choices=["paper", "tiny", "sequence512"])
+    ap.add_argument("--dn-workload", default=None, choices=["paper", "tiny", "sequence512"],
+                    help="train the denoiser on this workload's scenes (default: --workload); the network is "
+                         "convolutional, so its parameters then serve the fit's image size")
     ap.add_argument("--dn-pairs", type=int, default=2000)
     ap.add_argument("--dn-epochs", type=int, default=10)
     ap.add_argument("--log-every", type=int, default=25)
@@ -196,10 +209,20 @@ def main():
     if any(m.startswith("denoised") for m, _ in modes):
         t0 = time.perf_counter()
         dn = denoise.Denoiser(scene.height, scene.width)
-        denoise.train(r, dn, args.dn_pairs, args.dn_epochs, spp_in=2, spp_target=synth.TARGET_SPP)
+        dw = args.dn_workload or args.workload
+        if dw == args.workload:
+            denoise.train(r, dn, args.dn_pairs, args.dn_epochs, spp_in=2, spp_target=synth.TARGET_SPP)
+        else:
+            m2, s2, _, _ = synth.workload(dw)
+            r2 = facert.Renderer(m2, s2)
+            dn2 = denoise.Denoiser(s2.height, s2.width)
+            denoise.train(r2, dn2, args.dn_pairs, args.dn_epochs, spp_in=2, spp_target=synth.TARGET_SPP)
+            dn.set_params(dn2.get_params())
+            dn2.close()
+            r2.close()
         torch.cuda.synchronize()
         print(json.dumps({"denoiser_training_s": time.perf_counter() - t0, "pairs": args.dn_pairs,
-                          "epochs": args.dn_epochs}), flush=True)
+                          "epochs": args.dn_epochs, "trained_on": dw}), flush=True)
     for m, spp in modes:
         out = run(r, targets, base, frames, start, start_frames, args.iters, m, spp, dn, log_every=args.log_every,
                   rs=rs)

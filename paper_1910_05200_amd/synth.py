@@ -37,6 +37,8 @@ CONFIGS = {
     "tiny": dict(nx=32, ny=32, width=64, height=64, spp=4),
     # paper scale: 20,000 vertices / 39,432 triangles, 256x256, 16 spp
     "paper": dict(nx=125, ny=160, width=256, height=256, spp=16),
+    # sequence fitting at full size: 60,000 vertices / 119,022 triangles, 512x512
+    "sequence512": dict(nx=240, ny=250, width=512, height=512, spp=4),
 }
 
 GEN_SEED = 0        # mesh and bases
