@@ -71,6 +71,7 @@ def parse():
                          "once over the mean shape, boxes refitted every step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0)
+    ap.add_argument("--no-cpu-single", action="store_true", help="skip the one-thread oracle timing")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one plain 256 MiB device copy first (scale for HBM byte counters)")
     return ap.parse_args()
@@ -312,8 +313,11 @@ def main():
     if not args.no_cpu_baseline:
         threads = args.cpu_threads or min(16, os.cpu_count() or 1)
         # the oracle gets its own inputs only: a zero target (dL/dI = 2 I)
-        out["cpu_baseline"] = cpu_baseline(model, scene, params, np.zeros((scene.height, scene.width, 3)),
-                                           1000, spp, threads)
+        zero = np.zeros((scene.height, scene.width, 3))
+        out["cpu_baseline"] = cpu_baseline(model, scene, params, zero, 1000, spp, threads)
+        if threads > 1 and not args.no_cpu_single:
+            one = cpu_baseline(model, scene, params, zero, 1000, spp, 1)
+            out["cpu_baseline"]["one_thread"] = {"value": one["value"], "ms_per_iter": one["ms_per_iter"]}
     print(json.dumps(out))
 
 

@@ -517,22 +517,30 @@ __device__ inline void shade_light(const Surf<T> &s, const Light &L, vec3<T> y, 
     T cl_raw = -dot(ln, wi), cos_l = br.cl ? cl_raw : zero;
     T cs_raw = dot(s.ns, wi), cos_s = br.cs ? cs_raw : zero;
     T g = cos_l * area / d2;
-    T Sv = 0, D = 0, Gv = 0, ch = 0, oh = 0, lh = 1;
+    T D = 0, Fs = 0, ch = 0, oh = 0, lh = 1;   // Fs = S / ks
     int gsel = br.gsel;
     vec3<T> h = vk<T>(0, 0, 0);
-    bool spec = s.spec_on && br.cs;
-    if (spec) {
+    if (s.spec_on && br.cs) {
         vec3<T> hv = wi + s.wo;
         lh = len(hv);
         h = hv * (one / lh);
         ch = dot(s.ns, h);
         oh = dot(s.wo, h);
         T m2 = (T)(kBeckmannM * kBeckmannM), c2 = ch * ch;
-        D = exp(-(one - c2) / (c2 * m2)) / (pi * m2 * c2 * c2);
-        T G1 = two * ch * s.cos_o / oh, G2 = two * ch * cos_s / oh;
-        Gv = gsel == 0 ? one : (gsel == 1 ? G1 : G2);
-        Sv = s.ks * D * Gv / (four * s.cos_o);
+        // Below the cut the exponent is under -790, where exp is exactly 0 in
+        // fp32 and fp64 alike; testing first keeps 0/0 (c2^2 underflowing)
+        // out of the grazing corner.  A NaN ch fails the test too.
+        if (c2 * m2 > (T)1.25e-3) {
+            D = exp(-(one - c2) / (c2 * m2)) / (pi * m2 * c2 * c2);
+            // G/(4 cos_o) per branch of min(1, G1, G2), with cos_o cancelled
+            // in the G1 branch: there the value cos_o can round to 0 at
+            // grazing views while the fp32 decision still says "above".
+            if (gsel == 0) Fs = D / (four * s.cos_o);
+            else if (gsel == 1) Fs = D * ch / (two * oh);
+            else Fs = D * ch * cos_s / (two * oh * s.cos_o);
+        }
     }
+    T Sv = s.ks * Fs;
     T lc[3] = {(T)L.r, (T)L.g, (T)L.b};
     for (int c = 0; c < 3; ++c) out[c] = lc[c] * (s.A[c] / pi * cos_s + Sv) * g;
     if (!adj) return;
@@ -546,27 +554,22 @@ __device__ inline void shade_light(const Surf<T> &s, const Light &L, vec3<T> y, 
     T g_cos_s = Ld * g;
     T g_S = Lw * g;
     T g_g = Ld * cos_s + Lw * Sv;
-    adj->gks = spec ? g_S * D * Gv / (four * s.cos_o) : zero;
+    adj->gks = g_S * Fs;
     T g_cos_l = g_g * area / d2;
     T g_d2 = -g_g * g / d2;
     vec3<T> g_wi = vk<T>(0, 0, 0), g_ns = vk<T>(0, 0, 0), g_wo = vk<T>(0, 0, 0);
     T g_cos_o = 0;
-    if (spec) {
-        T g_G = g_S * s.ks * D / (four * s.cos_o);
-        g_cos_o += -g_S * Sv / s.cos_o;
+    if (D != zero) {   // where D is 0 every slope of S is 0 too
         T m2 = (T)(kBeckmannM * kBeckmannM);
         // dS/dD dD/dch = S (2/(m^2 ch^3) - 4/ch)
         T g_ch = g_S * Sv * (two / (m2 * ch * ch * ch) - four / ch);
         T g_oh = 0;
-        if (gsel == 1) {
-            g_ch += g_G * two * s.cos_o / oh;
-            g_cos_o += g_G * two * ch / oh;
-            g_oh += -g_G * Gv / oh;
-        } else if (gsel == 2) {
-            g_ch += g_G * two * cos_s / oh;
-            g_cos_s += g_G * two * ch / oh;
-            g_oh += -g_G * Gv / oh;
+        if (gsel != 0) {   // S carries ch/oh in the G1 and G2 branches
+            g_ch += g_S * Sv / ch;
+            g_oh += -g_S * Sv / oh;
         }
+        if (gsel != 1) g_cos_o += -g_S * Sv / s.cos_o;   // and 1/cos_o in the other two
+        if (gsel == 2) g_cos_s += g_S * s.ks * D * ch / (two * oh * s.cos_o);
         g_ns = g_ns + h * g_ch;
         g_wo = g_wo + h * g_oh;
         vec3<T> g_h = s.ns * g_ch + s.wo * g_oh;
