@@ -109,7 +109,9 @@ typedef struct {
     /* rays traced by the last fr_render + fr_backward */
     uint64_t rays_camera, rays_shadow, rays_edge_primary, rays_edge_secondary;
     uint64_t traversal_overflow;     /* must be 0                              */
-    uint64_t box_tests, tri_tests;   /* BVH node and triangle tests performed  */
+    uint64_t box_tests, tri_tests;   /* BVH node and ray/triangle tests (the
+                                        camera step tests the triangles whose
+                                        screen footprint holds the sample)     */
     /* per kernel: [0] camera rays, [1] shadow rays, [2] shading (forward),
        [3] interior adjoint (with any recomputation of hits and visibility),
        [4] camera-silhouette edges, [5] shadow-boundary edges */

@@ -13,7 +13,7 @@
 //                    creation)
 //   k_edge_weights   camera-silhouette and per-light shadow-candidate edges
 //   k_edge_scan      integer CDFs of the edge weights (one block per table)
-//   k_fwd_camera, k_fwd_shadow, k_fwd_shade
+//   k_cam_init, k_cam_raster, k_cam_resolve, k_fwd_shadow, k_fwd_shade
 //                    Monte-Carlo estimator F (Optimization paragraph): hit
 //                    records, compacted shadow rays, Cook-Torrance shading
 //   k_pixel_mean     fixed-order mean of each pixel's samples
@@ -358,11 +358,18 @@ __device__ __forceinline__ v3 camera_sample(const Scene &S, uint64_t seed, uint3
 }
 
 // counters, 8 per kernel: 0 camera rays, 1 shadow rays, 2 primary-edge rays,
-// 3 secondary-edge rays, 4 box tests, 5 triangle tests, 6 shaded light samples
+// 3 secondary-edge rays, 4 box tests, 5 triangle tests, 6 shaded light samples.
+// Each counter is spread over kCtrSpread copies one 128-byte line apart,
+// picked by the wave's index: device-scope atomics to one word serialise
+// (about 12 ns apiece here), which held back kernels whose every wave added
+// to the same few words.  fr_stats sums the copies.
+constexpr int kCtrSpread = 64, kCtrPad = 16;
+constexpr int kCtrPerKern = 8 * kCtrSpread * kCtrPad;   // words per kernel
 __device__ inline void flush_count(unsigned long long *ctr, int slot, uint32_t v) {
     unsigned long long s = v;
     for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
-    if ((threadIdx.x & 63) == 0 && s) atomicAdd(&ctr[slot], s);
+    const unsigned r = (blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) & (kCtrSpread - 1);
+    if ((threadIdx.x & 63) == 0 && s) atomicAdd(&ctr[(slot * kCtrSpread + r) * kCtrPad], s);
 }
 __device__ inline void flush_work(unsigned long long *ctr, const Work &w) {
     flush_count(ctr, 4, w.box);
@@ -371,9 +378,10 @@ __device__ inline void flush_work(unsigned long long *ctr, const Work &w) {
 }
 
 // ------------------------------------------------ forward wavefront -----
-// The forward pass runs as three kernels over a chunk of camera samples:
-//   k_fwd_camera  one lane per sample: jittered pinhole ray, closest hit ->
-//                 16-byte hit record;
+// The forward pass runs in three steps over a chunk of camera samples:
+//   camera        jittered pinhole ray, closest hit -> 16-byte hit record
+//                 (k_cam_* below; the batched path walks the tree per
+//                 sample, fwd_camera_body);
 //   k_fwd_shadow  one block per (tile of samples, light), the light on the
 //                 grid's y axis so that a wave traces neighbouring samples
 //                 toward the same light: horizon test, compaction, shadow
@@ -407,9 +415,125 @@ __device__ __forceinline__ void fwd_camera_body(const Scene &S, uint64_t seed, i
     flush_count(ctr, 0, n_cam);
     flush_work(ctr, wk);
 }
-__global__ __launch_bounds__(256) void k_fwd_camera(Scene S, uint64_t seed, int spp, long long s0, long long n,
-        HitRec *__restrict__ hits, unsigned long long *__restrict__ vis, unsigned long long *ctr) {
-    fwd_camera_body(S, seed, spp, s0, n, hits, vis, ctr, blockIdx.x);
+
+// Camera rays without the tree.  A camera sample's hit is the minimum of
+// (t, triangle id) over the triangles whose ray/triangle test accepts its
+// ray: the rule the closest-hit walk applies, so both give the same record
+// bit for bit.  An accepted hit point lies in the triangle's box widened by
+// the hit margin, so the screen footprint of that box (plus a rounding
+// margin) holds every sample the triangle can be hit by.  Three passes over
+// a chunk:
+//   k_cam_init     the sample's screen position (into its hit record) and an
+//                  empty key (into its visibility word);
+//   k_cam_raster   one lane per (triangle, sample index within the pixel):
+//                  the ray/triangle test for that sample of every pixel of
+//                  the footprint, accepted hits folded into the key with a
+//                  64-bit atomic min (t > 0 orders like its bit pattern, the
+//                  low word is the triangle id, so equal t keeps the lowest);
+//   k_cam_resolve  the key back into a hit record (the winner's test run
+//                  again for its barycentrics) and a cleared visibility mask.
+__global__ __launch_bounds__(256) void k_cam_init(Scene S, uint64_t seed, int spp, long long s0, long long n,
+        HitRec *__restrict__ hits, unsigned long long *__restrict__ key) {
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t s = (uint32_t)(s0 + i);
+    const int pix = (int)(s / (uint32_t)spp);
+    const int px = pix % S.W, py = pix / S.W;
+    const u4 w0 = philox(seed, s, 0, 0, 0);
+    HitRec r;
+    r.tri = -1; r.b1 = (float)px + u01(w0.x); r.b2 = (float)py + u01(w0.y); r.det = 0.0f;
+    hits[i] = r;
+    key[i] = ~0ull;
+}
+
+// Inclusive pixel range that holds the screen positions of every point of
+// the triangle's widened box (the whole image when the box reaches the
+// camera's plane).  Projection in fp64; the margin covers the fp32 rounding
+// of the sample's direction and of the hit point.
+__device__ inline void cam_footprint(const Scene &S, v3 v0, v3 v1, v3 v2, int &x0, int &x1, int &y0, int &y1) {
+    x0 = 0; x1 = S.W - 1; y0 = 0; y1 = S.H - 1;
+    const double lo[3] = {(double)fminf(fminf(v0.x, v1.x), v2.x) - 2.0 * kHitMargin,
+                          (double)fminf(fminf(v0.y, v1.y), v2.y) - 2.0 * kHitMargin,
+                          (double)fminf(fminf(v0.z, v1.z), v2.z) - 2.0 * kHitMargin};
+    const double hi[3] = {(double)fmaxf(fmaxf(v0.x, v1.x), v2.x) + 2.0 * kHitMargin,
+                          (double)fmaxf(fmaxf(v0.y, v1.y), v2.y) + 2.0 * kHitMargin,
+                          (double)fmaxf(fmaxf(v0.z, v1.z), v2.z) + 2.0 * kHitMargin};
+    const double cx = S.cam_x, cy = S.cam_y, cz = S.cam_z, ps = S.ps;
+    const double dmin = cz - hi[2];                    // the camera looks along -z: depth = t
+    const double ext = fmax(fmax(fabs(cx), fabs(cy)), fabs(cz)) +
+                       fmax(fmax(fmax(fabs(lo[0]), fabs(hi[0])), fmax(fabs(lo[1]), fabs(hi[1]))),
+                            fmax(fabs(lo[2]), fabs(hi[2])));
+    if (!(dmin > 1e-4 * (ext + 1.0))) return;         // reaches the camera's plane: every pixel
+    // fp32 error of the hit point (a few ulp of its magnitude) seen through
+    // the projection, plus that of the sample's direction, with room to spare
+    const double sc_far = 1.0 / ((cz - lo[2]) * ps), sc_near = 1.0 / (dmin * ps);   // pixels per metre
+    const double eps = 0.125 + 8.0 * 1.2e-7 * ext * sc_near + 8.0 * 1.2e-7 * (double)max(S.W, S.H);
+    double qx0 = 1e300, qx1 = -1e300, qy0 = 1e300, qy1 = -1e300;
+    for (int k = 0; k < 8; ++k) {
+        const double x = (k & 1) ? hi[0] : lo[0], y = (k & 2) ? hi[1] : lo[1];
+        const double sc = (k & 4) ? sc_near : sc_far;
+        const double qx = 0.5 * S.W + (x - cx) * sc, qy = 0.5 * S.H - (y - cy) * sc;
+        qx0 = fmin(qx0, qx); qx1 = fmax(qx1, qx); qy0 = fmin(qy0, qy); qy1 = fmax(qy1, qy);
+    }
+    // clamped before the conversion (an off-screen box gives an empty range)
+    x0 = (int)fmin(fmax(0.0, floor(qx0 - eps)), (double)S.W);
+    x1 = (int)fmax(fmin((double)(S.W - 1), floor(qx1 + eps)), -1.0);
+    y0 = (int)fmin(fmax(0.0, floor(qy0 - eps)), (double)S.H);
+    y1 = (int)fmax(fmin((double)(S.H - 1), floor(qy1 + eps)), -1.0);
+}
+
+__global__ __launch_bounds__(256) void k_cam_raster(Scene S, int spp, long long s0, long long n,
+        const HitRec *__restrict__ hits, unsigned long long *__restrict__ key, unsigned long long *ctr) {
+    const long long g = (long long)blockIdx.x * 256 + threadIdx.x;
+    uint32_t n_tri = 0;
+    if (g < (long long)S.F * spp) {
+        const int f = (int)(g / spp), k = (int)(g % spp);
+        const int *t = S.faces + 3 * f;
+        const v3 v0 = vpos(S, t[0]), v1 = vpos(S, t[1]), v2 = vpos(S, t[2]);
+        int x0, x1, y0, y1;
+        cam_footprint(S, v0, v1, v2, x0, x1, y0, y1);
+        // rows of this chunk
+        y0 = max(y0, (int)((s0 / spp) / S.W));
+        y1 = min(y1, (int)(((s0 + n - 1) / spp) / S.W));
+        const v3 o = mk(S.cam_x, S.cam_y, S.cam_z);
+        for (int py = y0; py <= y1; ++py)
+            for (int px = x0; px <= x1; ++px) {
+                const long long i = ((long long)py * S.W + px) * spp + k - s0;
+                if (i < 0 || i >= n) continue;
+                const HitRec q = hits[i];
+                const v3 d = camera_dir(S, q.b1, q.b2);
+                float tt, b1, b2, det;
+                ++n_tri;
+                if (ray_tri(o, d, v0, v1, v2, 0.0f, INFINITY, tt, b1, b2, det))
+                    atomicMin(&key[i], ((unsigned long long)__float_as_uint(tt) << 32) | (unsigned)f);
+            }
+    }
+    flush_count(ctr, 5, n_tri);
+}
+
+__global__ __launch_bounds__(256) void k_cam_resolve(Scene S, long long n, HitRec *__restrict__ hits,
+        unsigned long long *__restrict__ vis, unsigned long long *ctr) {
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    uint32_t n_cam = 0;
+    if (i < n) {
+        const unsigned long long kv = vis[i];
+        HitRec r = hits[i];
+        const v3 d = camera_dir(S, r.b1, r.b2);
+        r.tri = -1; r.b1 = r.b2 = r.det = 0.0f;
+        if (kv != ~0ull) {
+            const int f = (int)(uint32_t)kv;
+            const int *t = S.faces + 3 * f;
+            float tt, b1, b2, det;
+            if (ray_tri(mk(S.cam_x, S.cam_y, S.cam_z), d, vpos(S, t[0]), vpos(S, t[1]), vpos(S, t[2]), 0.0f,
+                        INFINITY, tt, b1, b2, det)) {
+                r.tri = f; r.b1 = b1; r.b2 = b2; r.det = det;
+            }
+        }
+        hits[i] = r;
+        vis[i] = 0ull;
+        n_cam = 1;
+    }
+    flush_count(ctr, 0, n_cam);
 }
 
 // Shadow rays are compacted before they are traced: a block takes a tile of
@@ -1368,6 +1492,11 @@ __global__ void k_zero_u64(unsigned long long *a, int n) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) a[i] = 0ull;
 }
+// the counters of kernels [k0, k1) (every copy)
+__global__ void k_zero_ctr(unsigned long long *ctr, int k0, int k1) {
+    int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < 8 * kCtrSpread * (k1 - k0)) ctr[(8 * kCtrSpread * k0 + e) * kCtrPad] = 0ull;
+}
 __global__ __launch_bounds__(256) void k_copy(const float *__restrict__ a, float *__restrict__ b, size_t n) {
     size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) b[i] = a[i];
@@ -1808,6 +1937,16 @@ static Scene make_scene(fr_ctx *c) {
 
 static inline unsigned nblk(size_t n, unsigned bs) { return (unsigned)((n + bs - 1) / bs); }
 
+// camera hit records and cleared visibility masks of samples [s0, s0 + n)
+static void camera_pass(fr_ctx *c, const Scene &S, uint64_t seed, int spp, long long s0, long long n,
+                        unsigned long long *ctr) {
+    hipLaunchKernelGGL(k_cam_init, dim3(nblk(n, 256)), dim3(256), 0, c->stream, S, seed, spp, s0, n, c->hits, c->vis);
+    if (S.F > 0)
+        hipLaunchKernelGGL(k_cam_raster, dim3(nblk((size_t)S.F * spp, 256)), dim3(256), 0, c->stream, S, spp, s0, n,
+                           c->hits, c->vis, ctr);
+    hipLaunchKernelGGL(k_cam_resolve, dim3(nblk(n, 256)), dim3(256), 0, c->stream, S, n, c->hits, c->vis, ctr);
+}
+
 extern "C" {
 
 int fr_create(const fr_model_desc *m, const fr_scene_desc *s, uint32_t flags, fr_ctx **out) {
@@ -1861,7 +2000,7 @@ int fr_create(const fr_model_desc *m, const fr_scene_desc *s, uint32_t flags, fr
         R(dalloc(c, &c->ew, (size_t)(1 + c->nl) * c->E)) ||
         R(dalloc(c, &c->tbl_edge, (size_t)(1 + c->nl) * c->E)) || R(dalloc(c, &c->tbl_prefix, (size_t)(1 + c->nl) * c->E)) ||
         R(dalloc(c, &c->tbl_n, (size_t)(1 + c->nl))) || R(dalloc(c, &c->tbl_Q, (size_t)(1 + c->nl))) ||
-        R(dalloc(c, &c->ctr, 8 * kNumKern)) || R(dalloc(c, &c->sec_n, 1)) ||
+        R(dalloc(c, &c->ctr, (size_t)kCtrPerKern * kNumKern)) || R(dalloc(c, &c->sec_n, 1)) ||
         R(dalloc(c, &c->pe_samples, (size_t)c->W * c->H)) || R(dalloc(c, &c->pe_hits, 2 * (size_t)c->W * c->H)) ||
         R(dalloc(c, &c->pe_f, 6 * (size_t)c->W * c->H)) || R(dalloc(c, &c->pe_vis, 2 * (size_t)c->W * c->H)) ||
         R(dalloc(c, &c->g_light, 3 * (size_t)c->nl)) || R(dalloc(c, &c->g_spec, (size_t)c->res * c->res)) ||
@@ -1894,7 +2033,7 @@ int fr_create(const fr_model_desc *m, const fr_scene_desc *s, uint32_t flags, fr
         fr_destroy(c);
         return FR_ENOMEM;
     }
-    (void)hipMemset(c->ctr, 0, 8 * kNumKern * sizeof(unsigned long long));
+    (void)hipMemset(c->ctr, 0, (size_t)kCtrPerKern * kNumKern * sizeof(unsigned long long));
     if (flags & FR_TIMING)
         for (int i = 0; i < kNumEvents; ++i) (void)hipEventCreate(&c->ev[i]);
     if (hipDeviceSynchronize() != hipSuccess) { fr_destroy(c); return FR_EDEVICE; }
@@ -2042,21 +2181,20 @@ int fr_render(fr_ctx *c, const fr_params *p, uint64_t seed, int32_t spp, float *
     hipLaunchKernelGGL(k_edge_scan<1024>, dim3(1 + c->nl), dim3(1024), 0, c->stream, c->E, c->ew,
                        c->tbl_edge, c->tbl_prefix, c->tbl_n, c->tbl_Q);
     ev_record(c, 3);
-    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, c->stream, c->ctr, 8 * kKernAdj);
+    hipLaunchKernelGGL(k_zero_ctr, dim3(nblk(8 * kCtrSpread * kKernAdj, 256)), dim3(256), 0, c->stream, c->ctr, 0, kKernAdj);
     size_t lds = (size_t)c->res * c->res * sizeof(float);
     for (long long s0 = 0; s0 < N; s0 += kChunk) {
         long long n = std::min(kChunk, N - s0);
         ev_record(c, 8 + 2 * kKernCamera);
-        hipLaunchKernelGGL(k_fwd_camera, dim3(nblk(n, 256)), dim3(256), 0, c->stream, S, seed, spp, s0, n,
-                           c->hits, c->vis, c->ctr + 8 * kKernCamera);
+        camera_pass(c, S, seed, spp, s0, n, c->ctr + kCtrPerKern * kKernCamera);
         ev_record(c, 9 + 2 * kKernCamera);
         ev_record(c, 8 + 2 * kKernShadow);
         hipLaunchKernelGGL(k_fwd_shadow, dim3(nblk(n, kShTile), c->nl), dim3(256), 0, c->stream, S, seed, s0, n,
-                           c->hits, c->vis, c->ctr + 8 * kKernShadow);
+                           c->hits, c->vis, c->ctr + kCtrPerKern * kKernShadow);
         ev_record(c, 9 + 2 * kKernShadow);
         ev_record(c, 8 + 2 * kKernShade);
         hipLaunchKernelGGL(k_fwd_shade, dim3(nblk(n, 256)), dim3(256), lds, c->stream, S, seed, spp, s0, n,
-                           c->hits, c->vis, c->samples, c->ctr + 8 * kKernShade);
+                           c->hits, c->vis, c->samples, c->ctr + kCtrPerKern * kKernShade);
         ev_record(c, 9 + 2 * kKernShade);
     }
     hipLaunchKernelGGL(k_pixel_mean, dim3(nblk((size_t)c->W * c->H, 256)), dim3(256), 0, c->stream,
@@ -2087,20 +2225,20 @@ int fr_backward(fr_ctx *c, const float *dLdI, const fr_grads *g) {
     GradBufs G{c->g_light, c->g_spec, c->g_pos, c->g_nrm, c->g_alb};
     const long long kChunk = c->last_cam_chunk;
     size_t lds = ((size_t)2 * c->res * c->res + 3 * c->nl) * sizeof(float);
-    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, c->stream, c->ctr + 8 * kKernAdj, 8 * (kNumKern - kKernAdj));
+    hipLaunchKernelGGL(k_zero_ctr, dim3(nblk(8 * kCtrSpread * (kNumKern - kKernAdj), 256)), dim3(256), 0, c->stream, c->ctr,
+                       kKernAdj, kNumKern);
     size_t lds1 = (size_t)c->res * c->res * sizeof(float);
     for (long long s0 = 0; s0 < N; s0 += kChunk) {
         long long n = std::min(kChunk, N - s0);
         if (!c->records_valid) {   // recompute this chunk's hit records and visibility
-            hipLaunchKernelGGL(k_fwd_camera, dim3(nblk(n, 256)), dim3(256), 0, c->stream, S, c->last_seed,
-                               c->last_spp, s0, n, c->hits, c->vis, c->ctr + 8 * kKernAdj);
+            camera_pass(c, S, c->last_seed, c->last_spp, s0, n, c->ctr + kCtrPerKern * kKernAdj);
             hipLaunchKernelGGL(k_fwd_shadow, dim3(nblk(n, kShTile), c->nl), dim3(256), 0, c->stream, S, c->last_seed,
-                               s0, n, c->hits, c->vis, c->ctr + 8 * kKernAdj);
+                               s0, n, c->hits, c->vis, c->ctr + kCtrPerKern * kKernAdj);
         }
         ev_record(c, 8 + 2 * kKernAdj);
         if (c->terms & FR_TERM_INTERIOR)
             hipLaunchKernelGGL(k_render_adj, dim3(nblk(n, 256)), dim3(256), lds, c->stream, S, c->last_seed,
-                               c->last_spp, s0, n, dLdI, G, c->hits, c->vis, c->ctr + 8 * kKernAdj);
+                               c->last_spp, s0, n, dLdI, G, c->hits, c->vis, c->ctr + kCtrPerKern * kKernAdj);
         ev_record(c, 9 + 2 * kKernAdj);
         ev_record(c, 8 + 2 * kKernSecondary);
         if (c->terms & FR_TERM_SECONDARY)
@@ -2109,7 +2247,7 @@ int fr_backward(fr_ctx *c, const float *dLdI, const fr_grads *g) {
                 hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, c->stream, c->sec_n, 1);
                 hipLaunchKernelGGL(k_edge_secondary, dim3(nblk(m, kSecTile), c->nl), dim3(256), 0, c->stream, S,
                                    c->last_seed, c->last_spp, s0 + o, m, dLdI, c->hits + o, c->sec_list, c->sec_n,
-                                   c->ctr + 8 * kKernSecondary);
+                                   c->ctr + kCtrPerKern * kKernSecondary);
                 hipLaunchKernelGGL(k_edge_secondary_value, dim3(1024), dim3(256), lds1, c->stream, S, c->last_seed,
                                    c->last_spp, s0 + o, dLdI, c->hits + o, c->sec_list, c->sec_n, c->g_pos);
             }
@@ -2119,11 +2257,11 @@ int fr_backward(fr_ctx *c, const float *dLdI, const fr_grads *g) {
     if (c->terms & FR_TERM_PRIMARY) {
         int M = c->W * c->H;
         hipLaunchKernelGGL(k_edge_primary_setup, dim3(nblk(M, 256)), dim3(256), 0, c->stream,
-                           S, c->last_seed, M, c->pe_samples, c->pe_hits, c->pe_vis, c->ctr + 8 * kKernPrimary);
+                           S, c->last_seed, M, c->pe_samples, c->pe_hits, c->pe_vis, c->ctr + kCtrPerKern * kKernPrimary);
         hipLaunchKernelGGL(k_edge_primary_vis, dim3(nblk((size_t)2 * M, kShTile), c->nl), dim3(256), 0, c->stream,
-                           S, c->last_seed, M, c->pe_samples, c->pe_hits, c->pe_vis, c->ctr + 8 * kKernPrimary);
+                           S, c->last_seed, M, c->pe_samples, c->pe_hits, c->pe_vis, c->ctr + kCtrPerKern * kKernPrimary);
         hipLaunchKernelGGL(k_edge_primary_shade, dim3(nblk((size_t)2 * M, 256)), dim3(256), lds1, c->stream,
-                           S, c->last_seed, M, c->pe_samples, c->pe_hits, c->pe_vis, c->pe_f, c->ctr + 8 * kKernPrimary);
+                           S, c->last_seed, M, c->pe_samples, c->pe_hits, c->pe_vis, c->pe_f, c->ctr + kCtrPerKern * kKernPrimary);
         hipLaunchKernelGGL(k_edge_primary_scatter, dim3(nblk(M, 256)), dim3(256), 0, c->stream,
                            S, M, dLdI, c->pe_samples, c->pe_f, c->g_pos);
     }
@@ -2204,11 +2342,14 @@ int fr_loss_l2(fr_ctx *c, const float *img, const float *tgt, float *dL, float *
 int fr_stats(fr_ctx *c, fr_stats_t *out) {
     if (!c || !out) return FR_EINVAL;
     HIPCK(c, hipStreamSynchronize(c->stream));
-    unsigned long long h[8 * kNumKern];
-    HIPCK(c, hipMemcpy(h, c->ctr, sizeof h, hipMemcpyDeviceToHost));
+    std::vector<unsigned long long> all((size_t)kCtrPerKern * kNumKern);
+    HIPCK(c, hipMemcpy(all.data(), c->ctr, all.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost));
     memset(out, 0, sizeof *out);
     for (int k = 0; k < kNumKern; ++k) {
-        const unsigned long long *q = h + 8 * k;
+        unsigned long long q[8] = {};
+        for (int slot = 0; slot < 8; ++slot)
+            for (int r = 0; r < kCtrSpread; ++r)
+                q[slot] += all[(size_t)k * kCtrPerKern + (size_t)(slot * kCtrSpread + r) * kCtrPad];
         out->rays_camera += q[0]; out->rays_shadow += q[1];
         out->rays_edge_primary += q[2]; out->rays_edge_secondary += q[3];
         out->box_tests += q[4]; out->tri_tests += q[5];

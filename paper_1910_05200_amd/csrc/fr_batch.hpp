@@ -143,16 +143,16 @@ FR_KIND(KEdgeScan, 1024) {
     edge_scan_body<1024>(I.S.E, I.ew, I.tbl_edge, I.tbl_prefix, I.tbl_n, I.tbl_Q, bx);
 }};
 FR_KIND(KZeroFwd, 64) {
-    if ((int)threadIdx.x < 8 * kKernAdj) I.ctr[threadIdx.x] = 0ull;
+    for (int e = (int)threadIdx.x; e < 8 * kCtrSpread * kKernAdj; e += 64) I.ctr[e * kCtrPad] = 0ull;
 }};
 FR_KIND(KCamera, 256) {
-    fwd_camera_body(I.S, I.d.seed, I.d.spp, 0, I.N, I.hits, I.vis, I.ctr + 8 * kKernCamera, bx);
+    fwd_camera_body(I.S, I.d.seed, I.d.spp, 0, I.N, I.hits, I.vis, I.ctr + kCtrPerKern * kKernCamera, bx);
 }};
 template <int TS> FR_KIND(KShadow, 256) {
-    fwd_shadow_body<TS>(I.S, I.d.seed, 0, I.N, I.hits, I.vis, I.ctr + 8 * kKernShadow, bx, by);
+    fwd_shadow_body<TS>(I.S, I.d.seed, 0, I.N, I.hits, I.vis, I.ctr + kCtrPerKern * kKernShadow, bx, by);
 }};
 FR_KIND(KShade, 256) {
-    fwd_shade_body(I.S, I.d.seed, I.d.spp, 0, I.N, I.hits, I.vis, I.samples, I.ctr + 8 * kKernShade, bx);
+    fwd_shade_body(I.S, I.d.seed, I.d.spp, 0, I.N, I.hits, I.vis, I.samples, I.ctr + kCtrPerKern * kKernShade, bx);
 }};
 FR_KIND(KPixelMean, 256) { pixel_mean_body(I.M, I.d.spp, I.samples, I.d.img, bx); }};
 FR_KIND(KZeroBwd, 256) {
@@ -160,17 +160,17 @@ FR_KIND(KZeroBwd, 256) {
     if (i < 3 * I.S.nl) I.G.d_light[i] = 0.0;
     if (i < I.S.res * I.S.res) I.G.d_spec[i] = 0.0;
     if (i < V3) { I.G.d_pos[i] = 0.0; I.G.d_nrm[i] = 0.0; I.G.d_alb[i] = 0.0; }
-    if (i < 8 * (kNumKern - kKernAdj)) I.ctr[8 * kKernAdj + i] = 0ull;
+    if (i < 8 * kCtrSpread * (kNumKern - kKernAdj)) I.ctr[(8 * kCtrSpread * kKernAdj + i) * kCtrPad] = 0ull;
     if (i == 0) *I.sec_n = 0u;
 }};
 FR_KIND(KAdj, 256) {
     if (!(I.d.terms & FR_TERM_INTERIOR)) return;
-    render_adj_body(I.S, I.d.seed, I.d.spp, 0, I.N, I.d.dLdI, I.G, I.hits, I.vis, I.ctr + 8 * kKernAdj, bx);
+    render_adj_body(I.S, I.d.seed, I.d.spp, 0, I.N, I.d.dLdI, I.G, I.hits, I.vis, I.ctr + kCtrPerKern * kKernAdj, bx);
 }};
 template <int TS> FR_KIND(KSecondary, 256) {
     if (!(I.d.terms & FR_TERM_SECONDARY)) return;
     edge_secondary_body<TS>(I.S, I.d.seed, I.d.spp, 0, I.N, I.d.dLdI, I.hits, I.sec_list, I.sec_n,
-                            I.ctr + 8 * kKernSecondary, bx, by);
+                            I.ctr + kCtrPerKern * kKernSecondary, bx, by);
 }};
 FR_KIND(KSecValue, 256) {
     if (!(I.d.terms & FR_TERM_SECONDARY)) return;
@@ -178,15 +178,15 @@ FR_KIND(KSecValue, 256) {
 }};
 FR_KIND(KPrimarySetup, 256) {
     if (!(I.d.terms & FR_TERM_PRIMARY)) return;
-    edge_primary_setup_body(I.S, I.d.seed, I.M, I.pe_samples, I.pe_hits, I.pe_vis, I.ctr + 8 * kKernPrimary, bx);
+    edge_primary_setup_body(I.S, I.d.seed, I.M, I.pe_samples, I.pe_hits, I.pe_vis, I.ctr + kCtrPerKern * kKernPrimary, bx);
 }};
 template <int TS> FR_KIND(KPrimaryVis, 256) {
     if (!(I.d.terms & FR_TERM_PRIMARY)) return;
-    edge_primary_vis_body<TS>(I.S, I.d.seed, I.M, I.pe_samples, I.pe_hits, I.pe_vis, I.ctr + 8 * kKernPrimary, bx, by);
+    edge_primary_vis_body<TS>(I.S, I.d.seed, I.M, I.pe_samples, I.pe_hits, I.pe_vis, I.ctr + kCtrPerKern * kKernPrimary, bx, by);
 }};
 FR_KIND(KPrimaryShade, 256) {
     if (!(I.d.terms & FR_TERM_PRIMARY)) return;
-    edge_primary_shade_body(I.S, I.d.seed, I.M, I.pe_samples, I.pe_hits, I.pe_vis, I.pe_f, I.ctr + 8 * kKernPrimary, bx);
+    edge_primary_shade_body(I.S, I.d.seed, I.M, I.pe_samples, I.pe_hits, I.pe_vis, I.pe_f, I.ctr + kCtrPerKern * kKernPrimary, bx);
 }};
 FR_KIND(KPrimaryScatter, 256) {
     if (!(I.d.terms & FR_TERM_PRIMARY)) return;
@@ -337,7 +337,7 @@ static void kind_grid(const fr_batch *b, int k, int i, int &gx, int &gy) {
     case bkCamera: case bkShade: case bkAdj: gx = (int)nblk(N, 256); break;
     case bkShadow: case bkSecondary: gx = (int)nblk(N, ts); gy = nl; break;
     case bkPixelMean: case bkPrimarySetup: case bkPrimaryScatter: gx = (int)nblk(M, 256); break;
-    case bkZeroBwd: gx = (int)nblk(std::max({3 * V, rr, 3 * nl, 8 * kNumKern}), 256); break;
+    case bkZeroBwd: gx = (int)nblk(std::max({3 * V, rr, 3 * nl, 8 * kCtrSpread * kNumKern}), 256); break;
     case bkSecValue: gx = (int)std::min<long long>(1024, std::max<long long>(1, (N + 1023) / 1024)); break;
     case bkPrimaryVis: gx = (int)nblk(2 * (size_t)M, ts); gy = nl; break;
     case bkPrimaryShade: gx = (int)nblk(2 * (size_t)M, 256); break;
