@@ -1105,9 +1105,9 @@ __global__ __launch_bounds__(256) void k_edge_secondary_value(Scene S, uint64_t 
 // ---------------------------------------------- camera silhouettes -----
 // M = W*H edge samples, in three passes so that the 40 shadow rays of a
 // sample run on separate lanes:
-//   k_edge_primary_setup  one lane per sample: pick the edge, the point q
-//                         on its projection, the two sides q +- offset; trace
-//                         both camera rays and keep the hits;
+//   k_edge_primary_setup  two lanes per sample: pick the edge, the point q
+//                         on its projection, the two sides q +- offset; each
+//                         lane traces one side's camera ray and keeps the hit;
 //   k_edge_primary_vis    one block per (tile of sides, light): horizon
 //                         test, compaction, shadow ray, visibility bit;
 //   k_edge_primary_shade  one lane per side: fp64 radiance of its visible
@@ -1119,15 +1119,17 @@ struct PeSample { int e, i, pix; float qx, qy; };
 __device__ __forceinline__ void edge_primary_setup_body(const Scene &S, uint64_t seed, int M,
         PeSample *__restrict__ ps_out, Hit *__restrict__ hits, unsigned long long *__restrict__ pvis,
         unsigned long long *ctr, int bx) {
-    int m = bx * blockDim.x + threadIdx.x;
+    // two lanes per sample, one per side of the edge: both pick the same
+    // edge and point, each traces its own side's ray
+    const int g = bx * blockDim.x + threadIdx.x;
+    const int m = g >> 1, side = g & 1;
     uint32_t n_cam = 0;
     Work wk;
     int n = S.pe_n[0];
     uint64_t Q = S.pe_Q[0];
     if (m < M) {
         PeSample ps; ps.e = -1; ps.i = 0; ps.pix = -1; ps.qx = ps.qy = 0.0f;
-        Hit h0; h0.tri = -1; h0.t = 0.0f; h0.b1 = h0.b2 = h0.det = 0.0f;
-        Hit hs[2] = {h0, h0};
+        Hit h; h.tri = -1; h.t = 0.0f; h.b1 = h.b2 = h.det = 0.0f;
         do {
             if (n <= 0 || Q == 0) break;
             u4 wd = philox(seed, (uint32_t)m, 0, 2, 0);
@@ -1148,19 +1150,15 @@ __device__ __forceinline__ void edge_primary_setup_body(const Scene &S, uint64_t
             float gl = sqrtf(gx * gx + gy * gy);
             if (gl == 0.0f) break;
             float nx = gx / gl, ny = gy / gl;
-            {
-                const float px0 = qx + kEdgeOffPx * nx, py0 = qy + kEdgeOffPx * ny;
-                const float px1 = qx + -1.0f * (kEdgeOffPx * nx), py1 = qy + -1.0f * (kEdgeOffPx * ny);
-                trace_closest2(S, cam, camera_dir(S, px0, py0), camera_dir(S, px1, py1), hs[0], hs[1], wk);
-                n_cam += 2;
-            }
+            const float px = side == 0 ? qx + kEdgeOffPx * nx : qx + -1.0f * (kEdgeOffPx * nx);
+            const float py = side == 0 ? qy + kEdgeOffPx * ny : qy + -1.0f * (kEdgeOffPx * ny);
+            h = trace_closest(S, cam, camera_dir(S, px, py), wk);
+            n_cam = 1;
             ps.e = e; ps.i = i; ps.pix = (int)fpy * S.W + (int)fpx; ps.qx = qx; ps.qy = qy;
         } while (0);
-        ps_out[m] = ps;
-        hits[2 * m] = hs[0];
-        hits[2 * m + 1] = hs[1];
-        pvis[2 * m] = 0ull;
-        pvis[2 * m + 1] = 0ull;
+        if (side == 0) ps_out[m] = ps;
+        hits[2 * m + side] = h;
+        pvis[2 * m + side] = 0ull;
     }
     flush_count(ctr, 0, n_cam);
     flush_work(ctr, wk);
@@ -2256,7 +2254,7 @@ int fr_backward(fr_ctx *c, const float *dLdI, const fr_grads *g) {
     ev_record(c, 8 + 2 * kKernPrimary);
     if (c->terms & FR_TERM_PRIMARY) {
         int M = c->W * c->H;
-        hipLaunchKernelGGL(k_edge_primary_setup, dim3(nblk(M, 256)), dim3(256), 0, c->stream,
+        hipLaunchKernelGGL(k_edge_primary_setup, dim3(nblk(2 * (size_t)M, 256)), dim3(256), 0, c->stream,
                            S, c->last_seed, M, c->pe_samples, c->pe_hits, c->pe_vis, c->ctr + kCtrPerKern * kKernPrimary);
         hipLaunchKernelGGL(k_edge_primary_vis, dim3(nblk((size_t)2 * M, kShTile), c->nl), dim3(256), 0, c->stream,
                            S, c->last_seed, M, c->pe_samples, c->pe_hits, c->pe_vis, c->ctr + kCtrPerKern * kKernPrimary);

@@ -336,7 +336,8 @@ static void kind_grid(const fr_batch *b, int k, int i, int &gx, int &gy) {
     case bkEdgeScan: gx = 1 + nl; break;
     case bkCamera: case bkShade: case bkAdj: gx = (int)nblk(N, 256); break;
     case bkShadow: case bkSecondary: gx = (int)nblk(N, ts); gy = nl; break;
-    case bkPixelMean: case bkPrimarySetup: case bkPrimaryScatter: gx = (int)nblk(M, 256); break;
+    case bkPixelMean: case bkPrimaryScatter: gx = (int)nblk(M, 256); break;
+    case bkPrimarySetup: gx = (int)nblk(2 * (size_t)M, 256); break;
     case bkZeroBwd: gx = (int)nblk(std::max({3 * V, rr, 3 * nl, 8 * kCtrSpread * kNumKern}), 256); break;
     case bkSecValue: gx = (int)std::min<long long>(1024, std::max<long long>(1, (N + 1023) / 1024)); break;
     case bkPrimaryVis: gx = (int)nblk(2 * (size_t)M, ts); gy = nl; break;
