@@ -1213,7 +1213,8 @@ __device__ __forceinline__ void edge_primary_vis_body(const Scene &S, uint64_t s
         const PeSample *__restrict__ ps_in, const Hit *__restrict__ hits, unsigned long long *__restrict__ pvis,
         unsigned long long *ctr, int bx, int j) {
     __shared__ Light Ls[kMaxLights];
-    __shared__ int q_i[TS];
+    __shared__ float4 q_o[TS];   // origin p, hit triangle
+    __shared__ float4 q_d[TS];   // y - p, side index within the tile
     __shared__ int q_n;
     for (int k = threadIdx.x; k < S.nl; k += blockDim.x) {
         const float *g = S.lgeom + 12 * k;
@@ -1231,24 +1232,31 @@ __device__ __forceinline__ void edge_primary_vis_body(const Scene &S, uint64_t s
     for (int k = 0; k < TS; k += 256) {
         const int li = k + (int)threadIdx.x;
         bool need = false;
+        v3 p, dd;
+        int tri = -1;
         if (base + li < 2 * M) {
             v3 o, d, y; Hit h; SurfDec sd;
             need = pe_light(S, seed, ps_in, hits, L, j, base + li, o, d, h, sd, y);
+            if (need) { p = sd.p; dd = y - sd.p; tri = h.tri; }
         }
         unsigned long long m = __ballot(need);
         int wbase = 0;
         if (lane == 0 && m) wbase = atomicAdd(&q_n, __popcll(m));
         wbase = __shfl(wbase, 0);
-        if (need) { q_i[wbase + lanes_below(m)] = li; ++n_sh; }
+        if (need) {
+            const int slot = wbase + lanes_below(m);
+            q_o[slot] = make_float4(p.x, p.y, p.z, __int_as_float(tri));
+            q_d[slot] = make_float4(dd.x, dd.y, dd.z, __int_as_float(li));
+            ++n_sh;
+        }
     }
     __syncthreads();
     const int nq = q_n;
     for (int e = wave * 64 + lane; e - lane < nq; e += 256) {
         if (e < nq) {
-            const int ms = base + q_i[e];
-            v3 o, d, y; Hit h; SurfDec sd;
-            pe_light(S, seed, ps_in, hits, L, j, ms, o, d, h, sd, y);
-            if (!trace_any(S, sd.p, y - sd.p, h.tri, wk)) atomicOr(&pvis[ms], 1ull << j);
+            const float4 o4 = q_o[e], d4 = q_d[e];
+            if (!trace_any(S, mk(o4.x, o4.y, o4.z), mk(d4.x, d4.y, d4.z), __float_as_int(o4.w), wk))
+                atomicOr(&pvis[base + __float_as_int(d4.w)], 1ull << j);
         }
     }
     flush_count(ctr, 2, n_sh);
