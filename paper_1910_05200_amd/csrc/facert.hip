@@ -1105,9 +1105,10 @@ __global__ __launch_bounds__(256) void k_edge_secondary_value(Scene S, uint64_t 
 // ---------------------------------------------- camera silhouettes -----
 // M = W*H edge samples, in three passes so that the 40 shadow rays of a
 // sample run on separate lanes:
-//   k_edge_primary_setup  two lanes per sample: pick the edge, the point q
-//                         on its projection, the two sides q +- offset; each
-//                         lane traces one side's camera ray and keeps the hit;
+//   k_edge_primary_setup  two lanes per sample (the batched path: one):
+//                         pick the edge, the point q on its projection, the
+//                         two sides q +- offset; trace the camera rays and
+//                         keep the hits;
 //   k_edge_primary_vis    one block per (tile of sides, light): horizon
 //                         test, compaction, shadow ray, visibility bit;
 //   k_edge_primary_shade  one lane per side: fp64 radiance of its visible
@@ -1116,13 +1117,15 @@ __global__ __launch_bounds__(256) void k_edge_secondary_value(Scene S, uint64_t 
 //                         Jacobian into the edge's two endpoints.
 struct PeSample { int e, i, pix; float qx, qy; };
 
+// SPLIT: two lanes per sample, one per side of the edge (both pick the same
+// edge and point, each traces its own side's ray), for launches too small to
+// fill the chip; else one lane traces both sides in one walk.
+template <bool SPLIT>
 __device__ __forceinline__ void edge_primary_setup_body(const Scene &S, uint64_t seed, int M,
         PeSample *__restrict__ ps_out, Hit *__restrict__ hits, unsigned long long *__restrict__ pvis,
         unsigned long long *ctr, int bx) {
-    // two lanes per sample, one per side of the edge: both pick the same
-    // edge and point, each traces its own side's ray
     const int g = bx * blockDim.x + threadIdx.x;
-    const int m = g >> 1, side = g & 1;
+    const int m = SPLIT ? g >> 1 : g, side = SPLIT ? g & 1 : 0;
     uint32_t n_cam = 0;
     Work wk;
     int n = S.pe_n[0];
@@ -1130,6 +1133,7 @@ __device__ __forceinline__ void edge_primary_setup_body(const Scene &S, uint64_t
     if (m < M) {
         PeSample ps; ps.e = -1; ps.i = 0; ps.pix = -1; ps.qx = ps.qy = 0.0f;
         Hit h; h.tri = -1; h.t = 0.0f; h.b1 = h.b2 = h.det = 0.0f;
+        Hit h2 = h;
         do {
             if (n <= 0 || Q == 0) break;
             u4 wd = philox(seed, (uint32_t)m, 0, 2, 0);
@@ -1150,15 +1154,25 @@ __device__ __forceinline__ void edge_primary_setup_body(const Scene &S, uint64_t
             float gl = sqrtf(gx * gx + gy * gy);
             if (gl == 0.0f) break;
             float nx = gx / gl, ny = gy / gl;
-            const float px = side == 0 ? qx + kEdgeOffPx * nx : qx + -1.0f * (kEdgeOffPx * nx);
-            const float py = side == 0 ? qy + kEdgeOffPx * ny : qy + -1.0f * (kEdgeOffPx * ny);
-            h = trace_closest(S, cam, camera_dir(S, px, py), wk);
-            n_cam = 1;
+            const float px0 = qx + kEdgeOffPx * nx, py0 = qy + kEdgeOffPx * ny;
+            const float px1 = qx + -1.0f * (kEdgeOffPx * nx), py1 = qy + -1.0f * (kEdgeOffPx * ny);
+            if (SPLIT) {
+                h = side == 0 ? trace_closest(S, cam, camera_dir(S, px0, py0), wk)
+                              : trace_closest(S, cam, camera_dir(S, px1, py1), wk);
+                n_cam = 1;
+            } else {
+                trace_closest2(S, cam, camera_dir(S, px0, py0), camera_dir(S, px1, py1), h, h2, wk);
+                n_cam = 2;
+            }
             ps.e = e; ps.i = i; ps.pix = (int)fpy * S.W + (int)fpx; ps.qx = qx; ps.qy = qy;
         } while (0);
         if (side == 0) ps_out[m] = ps;
         hits[2 * m + side] = h;
         pvis[2 * m + side] = 0ull;
+        if (!SPLIT) {
+            hits[2 * m + 1] = h2;
+            pvis[2 * m + 1] = 0ull;
+        }
     }
     flush_count(ctr, 0, n_cam);
     flush_work(ctr, wk);
@@ -1166,7 +1180,7 @@ __device__ __forceinline__ void edge_primary_setup_body(const Scene &S, uint64_t
 __global__ __launch_bounds__(256) void k_edge_primary_setup(Scene S, uint64_t seed, int M,
         PeSample *__restrict__ ps_out, Hit *__restrict__ hits, unsigned long long *__restrict__ pvis,
         unsigned long long *ctr) {
-    edge_primary_setup_body(S, seed, M, ps_out, hits, pvis, ctr, blockIdx.x);
+    edge_primary_setup_body<true>(S, seed, M, ps_out, hits, pvis, ctr, blockIdx.x);
 }
 
 // screen point of side 'side' of a primary sample (same fp32 ops as setup)

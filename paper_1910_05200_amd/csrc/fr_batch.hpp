@@ -178,7 +178,7 @@ FR_KIND(KSecValue, 256) {
 }};
 FR_KIND(KPrimarySetup, 256) {
     if (!(I.d.terms & FR_TERM_PRIMARY)) return;
-    edge_primary_setup_body(I.S, I.d.seed, I.M, I.pe_samples, I.pe_hits, I.pe_vis, I.ctr + kCtrPerKern * kKernPrimary, bx);
+    edge_primary_setup_body<false>(I.S, I.d.seed, I.M, I.pe_samples, I.pe_hits, I.pe_vis, I.ctr + kCtrPerKern * kKernPrimary, bx);
 }};
 template <int TS> FR_KIND(KPrimaryVis, 256) {
     if (!(I.d.terms & FR_TERM_PRIMARY)) return;
@@ -336,8 +336,7 @@ static void kind_grid(const fr_batch *b, int k, int i, int &gx, int &gy) {
     case bkEdgeScan: gx = 1 + nl; break;
     case bkCamera: case bkShade: case bkAdj: gx = (int)nblk(N, 256); break;
     case bkShadow: case bkSecondary: gx = (int)nblk(N, ts); gy = nl; break;
-    case bkPixelMean: case bkPrimaryScatter: gx = (int)nblk(M, 256); break;
-    case bkPrimarySetup: gx = (int)nblk(2 * (size_t)M, 256); break;
+    case bkPixelMean: case bkPrimarySetup: case bkPrimaryScatter: gx = (int)nblk(M, 256); break;
     case bkZeroBwd: gx = (int)nblk(std::max({3 * V, rr, 3 * nl, 8 * kCtrSpread * kNumKern}), 256); break;
     case bkSecValue: gx = (int)std::min<long long>(1024, std::max<long long>(1, (N + 1023) / 1024)); break;
     case bkPrimaryVis: gx = (int)nblk(2 * (size_t)M, ts); gy = nl; break;

@@ -249,6 +249,45 @@ __device__ inline bool trace_any(const Scene &S, v3 o, v3 d, int skip, Work &wk)
     return false;
 }
 
+// Closest hits of two rays from one origin in one traversal (the two sides
+// of a camera-silhouette sample), each with its own nearest t as the slab
+// bound; each result is that of trace_closest for the ray alone.
+__device__ inline void trace_closest2(const Scene &S, v3 o, v3 d1, v3 d2, Hit &h1, Hit &h2, Work &wk) {
+    const Ray r1 = make_ray(o, d1), r2 = make_ray(o, d2);
+    h1.tri = -1; h1.t = INFINITY; h1.b1 = h1.b2 = h1.det = 0.0f;
+    h2 = h1;
+    int node = 0;
+    while (node < S.n_nodes) {
+        const uint4 q = S.nodes[node];
+        const int link = (int)q.w;
+        const QBox b = qbox(q);
+        const bool e1 = slab(r1, b, h1.t), e2 = slab(r2, b, h2.t);
+        wk.box += 2;
+        if (e1 || e2) {
+            if (link < 0) {
+                const int leaf = ~link;
+                const float4 q0 = S.tris[3 * leaf], q1 = S.tris[3 * leaf + 1], q2 = S.tris[3 * leaf + 2];
+                const v3 v0 = mk(q0.x, q0.y, q0.z), v1 = mk(q0.w, q1.x, q1.y), v2 = mk(q1.z, q1.w, q2.x);
+                const int id = __float_as_int(q2.y);
+                float t, b1, b2, det;
+                if (e1) {
+                    ++wk.tri;
+                    if (ray_tri(r1.o, r1.d, v0, v1, v2, 0.0f, INFINITY, t, b1, b2, det) &&
+                        (t < h1.t || (t == h1.t && id < h1.tri))) { h1.tri = id; h1.t = t; h1.b1 = b1; h1.b2 = b2; h1.det = det; }
+                }
+                if (e2) {
+                    ++wk.tri;
+                    if (ray_tri(r2.o, r2.d, v0, v1, v2, 0.0f, INFINITY, t, b1, b2, det) &&
+                        (t < h2.t || (t == h2.t && id < h2.tri))) { h2.tri = id; h2.t = t; h2.b1 = b1; h2.b2 = b2; h2.det = det; }
+                }
+            }
+            node = node + 1;
+        } else {
+            node = link < 0 ? node + 1 : link;
+        }
+    }
+}
+
 // Two rays from one origin in one traversal (the two sides of an edge
 // sample: nearly the same direction).  Each node is loaded and decoded once
 // and tested against each ray that is still open; the walk descends when

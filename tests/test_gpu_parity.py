@@ -173,6 +173,19 @@ def test_backward_all_terms_tiny_chunked(torch, orc):
         r.set_chunk(0)
 
 
+def test_chunks_that_end_inside_a_pixel(torch, orc):
+    """Chunks of 4,999 samples at 4 spp end inside pixels and inside rows:
+    the chunked camera step, forward and backward recomputation give the
+    unchunked image bit for bit and the oracle's gradients."""
+    model, scene, params, spp = _case("tiny")
+    assert 4999 % spp != 0
+    whole, _ = _gpu_render(torch, _renderer(torch, model, scene), params, SEED, spp)
+    g, ref, pg, r = _grad_case(torch, orc, "tiny", 7, chunk=4999)
+    _compare(g, ref, pg)
+    part, _ = _gpu_render(torch, r, params, SEED, spp)
+    assert np.array_equal(whole, part)
+
+
 def test_backward_all_terms_paper(torch, orc):
     g, ref, pg, _ = _grad_case(torch, orc, "paper", 7)
     _compare(g, ref, pg)
