@@ -1156,9 +1156,9 @@ __device__ __forceinline__ void edge_primary_setup_body(const Scene &S, uint64_t
             float nx = gx / gl, ny = gy / gl;
             const float px0 = qx + kEdgeOffPx * nx, py0 = qy + kEdgeOffPx * ny;
             const float px1 = qx + -1.0f * (kEdgeOffPx * nx), py1 = qy + -1.0f * (kEdgeOffPx * ny);
-            if (SPLIT) {
-                h = side == 0 ? trace_closest(S, cam, camera_dir(S, px0, py0), wk)
-                              : trace_closest(S, cam, camera_dir(S, px1, py1), wk);
+            if (SPLIT) {   // one call site: the lanes of a wave take both sides
+                const float px = side == 0 ? px0 : px1, py = side == 0 ? py0 : py1;
+                h = trace_closest(S, cam, camera_dir(S, px, py), wk);
                 n_cam = 1;
             } else {
                 trace_closest2(S, cam, camera_dir(S, px0, py0), camera_dir(S, px1, py1), h, h2, wk);
