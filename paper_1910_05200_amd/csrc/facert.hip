@@ -549,6 +549,9 @@ constexpr int kShTile = 512;
 // The shadow-boundary kernel keeps its accepted samples' two side rays in
 // LDS (48 bytes each), so its tile is smaller: 256 samples.
 constexpr int kSecTile = 256;
+// Camera-silhouette sides: most of a tile's sides trace nothing (the side
+// that misses the face), so a smaller tile keeps more blocks in flight.
+constexpr int kPvTile = 256;
 __device__ __forceinline__ int lanes_below(unsigned long long m) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0));
 }
@@ -1216,7 +1219,7 @@ __device__ __forceinline__ bool pe_light(const Scene &S, uint64_t seed, const Pe
     return above(sd, y);
 }
 
-// k_edge_primary_vis: one block per (tile of kShTile sides, light):
+// k_edge_primary_vis: one block per (tile of kPvTile sides, light):
 // horizon tests, compaction into an LDS list, one shadow ray per entry, one
 // visibility bit per light in the side's mask.  k_edge_primary_shade: one
 // lane per side, the fp64 radiance of its visible lights summed in light
@@ -1279,7 +1282,7 @@ __device__ __forceinline__ void edge_primary_vis_body(const Scene &S, uint64_t s
 __global__ __launch_bounds__(256) void k_edge_primary_vis(Scene S, uint64_t seed, int M,
         const PeSample *__restrict__ ps_in, const Hit *__restrict__ hits, unsigned long long *__restrict__ pvis,
         unsigned long long *ctr) {
-    edge_primary_vis_body<kShTile>(S, seed, M, ps_in, hits, pvis, ctr, blockIdx.x, blockIdx.y);
+    edge_primary_vis_body<kPvTile>(S, seed, M, ps_in, hits, pvis, ctr, blockIdx.x, blockIdx.y);
 }
 
 __device__ __forceinline__ void edge_primary_shade_body(const Scene &S, uint64_t seed, int M,
@@ -2278,7 +2281,7 @@ int fr_backward(fr_ctx *c, const float *dLdI, const fr_grads *g) {
         int M = c->W * c->H;
         hipLaunchKernelGGL(k_edge_primary_setup, dim3(nblk(2 * (size_t)M, 256)), dim3(256), 0, c->stream,
                            S, c->last_seed, M, c->pe_samples, c->pe_hits, c->pe_vis, c->ctr + kCtrPerKern * kKernPrimary);
-        hipLaunchKernelGGL(k_edge_primary_vis, dim3(nblk((size_t)2 * M, kShTile), c->nl), dim3(256), 0, c->stream,
+        hipLaunchKernelGGL(k_edge_primary_vis, dim3(nblk((size_t)2 * M, kPvTile), c->nl), dim3(256), 0, c->stream,
                            S, c->last_seed, M, c->pe_samples, c->pe_hits, c->pe_vis, c->ctr + kCtrPerKern * kKernPrimary);
         hipLaunchKernelGGL(k_edge_primary_shade, dim3(nblk((size_t)2 * M, 256)), dim3(256), lds1, c->stream,
                            S, c->last_seed, M, c->pe_samples, c->pe_hits, c->pe_vis, c->pe_f, c->ctr + kCtrPerKern * kKernPrimary);

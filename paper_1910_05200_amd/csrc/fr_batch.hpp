@@ -591,7 +591,8 @@ int fr_batch_create(int32_t n, fr_ctx *const *ctx, uint32_t flags, fr_batch **ou
     b->dyn.assign(n, InstDyn{});
     b->gen.assign(n, 0);
     for (int k = 0; k < bkNum; ++k)
-        b->launch[k] = fr_launch{FR_LAUNCH_FLAT, k == bkSecondary ? kSecTile : (kind_tiled(k) ? kShTile : 0)};
+        b->launch[k] = fr_launch{FR_LAUNCH_FLAT, k == bkSecondary ? kSecTile
+                                                 : k == bkPrimaryVis ? kPvTile : (kind_tiled(k) ? kShTile : 0)};
     b->stream = ctx[0]->stream;
     if (hipMalloc((void **)&b->tab, sizeof(Inst) * n) != hipSuccess) {
         fr_batch_destroy(b);
