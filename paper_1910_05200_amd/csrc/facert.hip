@@ -258,9 +258,22 @@ __global__ __launch_bounds__(256) void k_edge_weights(Scene S, const float *__re
 // within the wave by shuffles and across the block's waves in LDS (integer
 // sums: the grouping does not change them).
 constexpr int kScanIt = 4;
+// Cut-point guide of a table with n entries and total Q (n buckets): the
+// least bucket b whose first target ceil(b Q / n) reaches p is
+// floor((p - 1) n / Q) + 1 (0 for p = 0).  fp64 estimate, then exact
+// integer steps: (p - 1) n < 2^63 for tables of up to 2^21 edges.
+__device__ __forceinline__ int cut_bucket(uint64_t p, int n, uint64_t Q) {
+    if (p == 0) return 0;
+    const uint64_t num = (p - 1) * (uint64_t)n;
+    uint64_t b = (uint64_t)((double)num / (double)Q);
+    while (b > 0 && b * Q > num) --b;
+    while ((b + 1) * Q <= num) ++b;
+    return (int)b + 1;
+}
 template <int BS>
 __device__ __forceinline__ void edge_scan_body(int E, const float *__restrict__ w, int *__restrict__ out_edge,
-        uint64_t *__restrict__ out_prefix, int *__restrict__ out_n, uint64_t *__restrict__ out_Q, int tbl) {
+        uint64_t *__restrict__ out_prefix, int *__restrict__ out_n, uint64_t *__restrict__ out_Q,
+        int *__restrict__ out_guide, int tbl) {
     constexpr int NW = BS / 64;
     const float *wt = w + (size_t)tbl * E;
     int *oe = out_edge + (size_t)tbl * E;
@@ -317,10 +330,22 @@ __device__ __forceinline__ void edge_scan_body(int E, const float *__restrict__ 
         __syncthreads();
     }
     if (threadIdx.x == 0) { out_n[tbl] = nbase; out_Q[tbl] = base; }
+    // guide[b], b in [0, n]: the entry that target ceil(b Q / n) picks.
+    // Entry i holds the buckets from cut_bucket(p_i) up to cut_bucket(p_i+1)
+    // (the last entry up to n), so every bucket is written once.
+    int *og = out_guide + (size_t)tbl * (E + 1);
+    const int n = nbase;
+    for (int i = threadIdx.x; i < n; i += BS) {
+        const int b0 = cut_bucket(op[i], n, base);
+        const int b1 = i + 1 < n ? cut_bucket(op[i + 1], n, base) : n + 1;
+        for (int b = b0; b < b1; ++b) og[b] = i;
+    }
 }
 template <int BS>
-__global__ __launch_bounds__(BS) void k_edge_scan(int E, const float *__restrict__ w, int *__restrict__ out_edge, uint64_t *__restrict__ out_prefix, int *__restrict__ out_n, uint64_t *__restrict__ out_Q) {
-    edge_scan_body<BS>(E, w, out_edge, out_prefix, out_n, out_Q, blockIdx.x);
+__global__ __launch_bounds__(BS) void k_edge_scan(int E, const float *__restrict__ w, int *__restrict__ out_edge,
+        uint64_t *__restrict__ out_prefix, int *__restrict__ out_n, uint64_t *__restrict__ out_Q,
+        int *__restrict__ out_guide) {
+    edge_scan_body<BS>(E, w, out_edge, out_prefix, out_n, out_Q, out_guide, blockIdx.x);
 }
 
 // ------------------------------------------------------ LDS staging -----
@@ -901,7 +926,7 @@ __device__ inline bool secondary_edge(const Scene &S, const Light &L, int j, uin
     u4 wd = philox(seed, sidx, (uint32_t)j, 1, 0);
     const uint64_t *pre = S.se_prefix + (size_t)j * S.E;
     uint64_t target = __umul64hi(((uint64_t)wd.y << 32) | wd.x, Q);
-    int i = cdf_pick(pre, n, target);
+    int i = cdf_pick_guided(pre, S.se_guide + (size_t)j * (S.E + 1), n, Q, target);
     int e = S.se_edge[(size_t)j * S.E + i];
     const int *ed = S.edges + 4 * e;
     if (ed[2] == h.tri || ed[3] == h.tri) return false;
@@ -1141,7 +1166,7 @@ __device__ __forceinline__ void edge_primary_setup_body(const Scene &S, uint64_t
             if (n <= 0 || Q == 0) break;
             u4 wd = philox(seed, (uint32_t)m, 0, 2, 0);
             uint64_t target = __umul64hi(((uint64_t)wd.y << 32) | wd.x, Q);
-            int i = cdf_pick(S.pe_prefix, n, target);
+            int i = cdf_pick_guided(S.pe_prefix, S.pe_guide, n, Q, target);
             int e = S.pe_edge[i];
             const int *ed = S.edges + 4 * e;
             float tu = u01(wd.z);
@@ -1666,6 +1691,7 @@ struct fr_ctx {
     float *vmodel = nullptr, *pos = nullptr, *nrm = nullptr, *nlen = nullptr, *alb = nullptr;
     float *ew = nullptr;
     int *tbl_edge = nullptr, *tbl_n = nullptr; uint64_t *tbl_prefix = nullptr, *tbl_Q = nullptr;
+    int *tbl_guide = nullptr;        // [1 + nl][E + 1] cut-point guides of the tables
     float *samples = nullptr; size_t samples_cap = 0;
     HitRec *hits = nullptr; unsigned long long *vis = nullptr; size_t rec_cap = 0;
     uint32_t *sec_list = nullptr, *sec_n = nullptr; size_t sec_cap = 0;
@@ -1955,6 +1981,7 @@ static Scene make_scene(fr_ctx *c) {
     size_t E = (size_t)c->E;
     S.pe_edge = c->tbl_edge; S.pe_prefix = c->tbl_prefix; S.pe_n = c->tbl_n; S.pe_Q = c->tbl_Q;
     S.se_edge = c->tbl_edge + E; S.se_prefix = c->tbl_prefix + E; S.se_n = c->tbl_n + 1; S.se_Q = c->tbl_Q + 1;
+    S.pe_guide = c->tbl_guide; S.se_guide = c->tbl_guide + (E + 1);
     return S;
 }
 
@@ -1991,6 +2018,7 @@ int fr_create(const fr_model_desc *m, const fr_scene_desc *s, uint32_t flags, fr
     c->flags = flags;
     HostTopo T;
     if (!build_topology(m, T)) { delete c; return FR_EINVAL; }
+    if (T.edges.size() / 4 > (size_t)1 << 21) { delete c; return FR_EINVAL; }   // edge-table integer range
     c->V = m->n_vertices; c->F = m->n_faces; c->E = (int)(T.edges.size() / 4);
     c->n_id = m->n_id; c->n_exp = m->n_exp; c->n_alb = m->n_alb;
     c->W = s->width; c->H = s->height; c->nl = s->n_lights; c->res = s->spec_res; c->n_nodes = T.n_nodes;
@@ -2023,6 +2051,7 @@ int fr_create(const fr_model_desc *m, const fr_scene_desc *s, uint32_t flags, fr
         R(dalloc(c, &c->ew, (size_t)(1 + c->nl) * c->E)) ||
         R(dalloc(c, &c->tbl_edge, (size_t)(1 + c->nl) * c->E)) || R(dalloc(c, &c->tbl_prefix, (size_t)(1 + c->nl) * c->E)) ||
         R(dalloc(c, &c->tbl_n, (size_t)(1 + c->nl))) || R(dalloc(c, &c->tbl_Q, (size_t)(1 + c->nl))) ||
+        R(dalloc(c, &c->tbl_guide, (size_t)(1 + c->nl) * (c->E + 1))) ||
         R(dalloc(c, &c->ctr, (size_t)kCtrPerKern * kNumKern)) || R(dalloc(c, &c->sec_n, 1)) ||
         R(dalloc(c, &c->pe_samples, (size_t)c->W * c->H)) || R(dalloc(c, &c->pe_hits, 2 * (size_t)c->W * c->H)) ||
         R(dalloc(c, &c->pe_f, 6 * (size_t)c->W * c->H)) || R(dalloc(c, &c->pe_vis, 2 * (size_t)c->W * c->H)) ||
@@ -2202,7 +2231,7 @@ int fr_render(fr_ctx *c, const fr_params *p, uint64_t seed, int32_t spp, float *
     Scene S = make_scene(c);
     hipLaunchKernelGGL(k_edge_weights, dim3(nblk(c->E, 256)), dim3(256), 0, c->stream, S, c->lgeom, c->ew);
     hipLaunchKernelGGL(k_edge_scan<1024>, dim3(1 + c->nl), dim3(1024), 0, c->stream, c->E, c->ew,
-                       c->tbl_edge, c->tbl_prefix, c->tbl_n, c->tbl_Q);
+                       c->tbl_edge, c->tbl_prefix, c->tbl_n, c->tbl_Q, c->tbl_guide);
     ev_record(c, 3);
     hipLaunchKernelGGL(k_zero_ctr, dim3(nblk(8 * kCtrSpread * kKernAdj, 256)), dim3(256), 0, c->stream, c->ctr, 0, kKernAdj);
     size_t lds = (size_t)c->res * c->res * sizeof(float);
@@ -2408,7 +2437,7 @@ void fr_destroy(fr_ctx *c) {
     void *ptrs[] = {c->faces, c->edges, c->vf_off, c->vf_idx, c->mean, c->b_id, c->b_exp, c->alb_mean, c->b_alb, c->uv,
                     c->lgeom, c->sorted_tri, c->leaf_node, c->right, c->escape, c->subs, c->height, c->top, c->top_off, c->nodes, c->tris,
                     c->vmodel, c->vm_d, c->pos, c->nrm, c->nlen, c->alb, c->ew, c->tbl_edge, c->tbl_prefix, c->tbl_n,
-                    c->tbl_Q, c->samples, c->ctr, c->g_light, c->g_spec, c->g_pos, c->g_nrm, c->g_alb, c->g_N,
+                    c->tbl_Q, c->tbl_guide, c->samples, c->ctr, c->g_light, c->g_spec, c->g_pos, c->g_nrm, c->g_alb, c->g_N,
                     c->g_vert, c->g_m, c->partial, c->loss_partial, c->hits, c->vis, c->sec_list, c->sec_n, c->pe_samples, c->pe_hits,
                     c->pe_f, c->pe_vis, c->lb.key[0], c->lb.key[1], c->lb.val[0], c->lb.val[1], c->lb.hist,
                     c->lb.bounds, c->lb.child, c->lb.parent, c->lb.first, c->lb.last, c->lb.pre, c->lb.arrive, c->lb.box, c->lb.roots, c->lb.n_roots, c->lb.top_idx, c->lb.n_top};

@@ -50,7 +50,7 @@ struct Inst {
     const float *mean, *b_id, *b_exp, *alb_mean, *b_alb;
     double *vm_d;
     float *vmodel, *pos, *nrm, *nlen, *alb, *ew;
-    int *tbl_edge, *tbl_n;
+    int *tbl_edge, *tbl_n, *tbl_guide;
     uint64_t *tbl_prefix, *tbl_Q;
     uint4 *nodes;
     float4 *tris;
@@ -140,7 +140,7 @@ FR_KIND(KBoxesTop, 1024) {
 }};
 FR_KIND(KEdgeWeights, 256) { edge_weights_body(I.S, I.S.lgeom, I.ew, bx); }};
 FR_KIND(KEdgeScan, 1024) {
-    edge_scan_body<1024>(I.S.E, I.ew, I.tbl_edge, I.tbl_prefix, I.tbl_n, I.tbl_Q, bx);
+    edge_scan_body<1024>(I.S.E, I.ew, I.tbl_edge, I.tbl_prefix, I.tbl_n, I.tbl_Q, I.tbl_guide, bx);
 }};
 FR_KIND(KZeroFwd, 64) {
     for (int e = (int)threadIdx.x; e < 8 * kCtrSpread * kKernAdj; e += 64) I.ctr[e * kCtrPad] = 0ull;
@@ -549,6 +549,7 @@ static int configure(fr_batch *b, const int32_t *spp) {
         I.vm_d = c->vm_d; I.vmodel = c->vmodel; I.pos = c->pos; I.nrm = c->nrm; I.nlen = c->nlen; I.alb = c->alb;
         I.ew = c->ew;
         I.tbl_edge = c->tbl_edge; I.tbl_n = c->tbl_n; I.tbl_prefix = c->tbl_prefix; I.tbl_Q = c->tbl_Q;
+        I.tbl_guide = c->tbl_guide;
         I.nodes = c->nodes; I.tris = c->tris;
         I.lb = c->lb;
         I.hits = c->hits; I.vis = c->vis; I.samples = c->samples; I.ctr = c->ctr;

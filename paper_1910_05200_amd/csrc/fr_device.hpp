@@ -86,6 +86,7 @@ struct Scene {
     // sampling tables (compacted positive-weight entries)
     const int *pe_edge; const uint64_t *pe_prefix; const int *pe_n; const uint64_t *pe_Q;
     const int *se_edge; const uint64_t *se_prefix; const int *se_n; const uint64_t *se_Q;  // [nl][E]
+    const int *pe_guide, *se_guide;   // cut-point guides: [E + 1], [nl][E + 1]
 };
 
 __device__ __forceinline__ v3 vpos_raw(const float *pos, int V, int i) {
@@ -334,6 +335,23 @@ __device__ __forceinline__ v3 light_point(const Light &L, float u, float v) {
     float a = u - 0.5f, b = v - 0.5f;
     return mk((L.c.x + a * L.e1.x) + b * L.e2.x, (L.c.y + a * L.e1.y) + b * L.e2.y,
               (L.c.z + a * L.e1.z) + b * L.e2.z);
+}
+
+// cdf_pick through a cut-point guide (guide[b] = cdf_pick(ceil(b Q / n)),
+// b in [0, n]): the target's bucket floor(target n / Q) is estimated in
+// fp64 (off by at most one), and the answer lies between the guide entries
+// one bucket below and two above it, so the short search there returns
+// cdf_pick's index exactly.
+__device__ __forceinline__ int cdf_pick_guided(const uint64_t *prefix, const int *guide, int n, uint64_t Q,
+                                               uint64_t target) {
+    int b = (int)((double)target * (double)n / (double)Q);
+    b = min(max(b, 0), n);
+    int lo = guide[max(b - 1, 0)], hi = guide[min(b + 2, n)];
+    while (lo < hi) {
+        int mid = lo + (hi - lo + 1) / 2;
+        if (prefix[mid] <= target) lo = mid; else hi = mid - 1;
+    }
+    return lo;
 }
 
 // largest i < n with prefix[i] <= target (prefix[0] = 0, non-decreasing)
