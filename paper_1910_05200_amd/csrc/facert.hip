@@ -203,7 +203,7 @@ __device__ __forceinline__ bool project(const Scene &S, v3 x, float &sx, float &
 // weights: table 0 = camera silhouettes (screen length), table 1+j = shadow
 // candidates of light j (3D length).
 __device__ __forceinline__ void edge_weights_body(const Scene &S, const float *__restrict__ lgeom,
-        float *__restrict__ w, int tb) {
+        float *__restrict__ w, float4 *__restrict__ rec, int tb) {
     const int e = tb * blockDim.x + threadIdx.x;
     if (e >= S.E) return;
     const int *ed = S.edges + 4 * e;
@@ -214,6 +214,12 @@ __device__ __forceinline__ void edge_weights_body(const Scene &S, const float *_
         n1 = face_normal(S, ed[2]); n2 = face_normal(S, ed[3]);
         o1 = vpos(S, S.faces[3 * ed[2]]); o2 = vpos(S, S.faces[3 * ed[3]]);
     }
+    // the edge's geometry for the shadow-boundary proposals, in one record
+    rec[5 * e] = make_float4(a.x, a.y, a.z, b.x);
+    rec[5 * e + 1] = make_float4(b.y, b.z, n1.x, n1.y);
+    rec[5 * e + 2] = make_float4(n1.z, o1.x, o1.y, o1.z);
+    rec[5 * e + 3] = make_float4(n2.x, n2.y, n2.z, o2.x);
+    rec[5 * e + 4] = make_float4(o2.y, o2.z, __int_as_float(ed[2]), __int_as_float(ed[3]));
     size_t E = (size_t)S.E;
     v3 cam = mk(S.cam_x, S.cam_y, S.cam_z);
     bool sil = true;
@@ -247,8 +253,8 @@ __device__ __forceinline__ void edge_weights_body(const Scene &S, const float *_
     }
 }
 __global__ __launch_bounds__(256) void k_edge_weights(Scene S, const float *__restrict__ lgeom,
-        float *__restrict__ w) {
-    edge_weights_body(S, lgeom, w, blockIdx.x);
+        float *__restrict__ w, float4 *__restrict__ rec) {
+    edge_weights_body(S, lgeom, w, rec, blockIdx.x);
 }
 
 // One block per table: the table's max weight wmax (block reduction), then
@@ -928,16 +934,20 @@ __device__ inline bool secondary_edge(const Scene &S, const Light &L, int j, uin
     uint64_t target = __umul64hi(((uint64_t)wd.y << 32) | wd.x, Q);
     int i = cdf_pick_guided(pre, S.se_guide + (size_t)j * (S.E + 1), n, Q, target);
     int e = S.se_edge[(size_t)j * S.E + i];
-    const int *ed = S.edges + 4 * e;
-    if (ed[2] == h.tri || ed[3] == h.tri) return false;
+    // the edge's endpoints, its faces' normals and first vertices (the
+    // values face_normal and vpos give), and the face ids
+    const float4 *er = S.edge_rec + 5 * (size_t)e;
+    const float4 r0 = er[0], r1 = er[1], r2 = er[2], r3 = er[3], r4 = er[4];
+    const int f1 = __float_as_int(r4.z), f2 = __float_as_int(r4.w);
+    if (f1 == h.tri || f2 == h.tri) return false;
     v3 p = sf.p;
-    if (ed[3] >= 0) {
-        float s1 = dot(face_normal(S, ed[2]), p - vpos(S, S.faces[3 * ed[2]]));
-        float s2 = dot(face_normal(S, ed[3]), p - vpos(S, S.faces[3 * ed[3]]));
+    if (f2 >= 0) {
+        float s1 = dot(mk(r1.z, r1.w, r2.x), p - mk(r2.y, r2.z, r2.w));
+        float s2 = dot(mk(r3.x, r3.y, r3.z), p - mk(r3.w, r4.x, r4.y));
         if ((s1 > 0.0f) == (s2 > 0.0f)) return false;
     }
     float tu = u01(wd.z);
-    v3 a = vpos(S, ed[0]), b = vpos(S, ed[1]);
+    v3 a = mk(r0.x, r0.y, r0.z), b = mk(r0.w, r1.x, r1.y);
     v3 sp = mk(a.x + tu * (b.x - a.x), a.y + tu * (b.y - a.y), a.z + tu * (b.z - a.z));
     float den = dot(L.n, sp - p);
     if (den == 0.0f) return false;
@@ -986,6 +996,7 @@ __device__ inline bool secondary_edge(const Scene &S, const Light &L, int j, uin
     uint64_t qe = (i + 1 < n ? pre[i + 1] : Q) - pre[i];
     ER pe = (ER)((double)qe / (double)Q);
     ER W = hw * (vp ? (ER)1 : (ER)-1) * len(dydt) / (len(mpar) * pe);
+    const int *ed = S.edges + 4 * e;
     atomic_v(d_pos, S.V, ed[0], dpsi_a * W);
     atomic_v(d_pos, S.V, ed[1], dpsi_b * W);
     // the receiver point p moves along the fixed camera ray
@@ -1692,6 +1703,7 @@ struct fr_ctx {
     float *ew = nullptr;
     int *tbl_edge = nullptr, *tbl_n = nullptr; uint64_t *tbl_prefix = nullptr, *tbl_Q = nullptr;
     int *tbl_guide = nullptr;        // [1 + nl][E + 1] cut-point guides of the tables
+    float4 *edge_rec = nullptr;      // [E][5] edge geometry for the shadow-boundary proposals
     float *samples = nullptr; size_t samples_cap = 0;
     HitRec *hits = nullptr; unsigned long long *vis = nullptr; size_t rec_cap = 0;
     uint32_t *sec_list = nullptr, *sec_n = nullptr; size_t sec_cap = 0;
@@ -1982,6 +1994,7 @@ static Scene make_scene(fr_ctx *c) {
     S.pe_edge = c->tbl_edge; S.pe_prefix = c->tbl_prefix; S.pe_n = c->tbl_n; S.pe_Q = c->tbl_Q;
     S.se_edge = c->tbl_edge + E; S.se_prefix = c->tbl_prefix + E; S.se_n = c->tbl_n + 1; S.se_Q = c->tbl_Q + 1;
     S.pe_guide = c->tbl_guide; S.se_guide = c->tbl_guide + (E + 1);
+    S.edge_rec = c->edge_rec;
     return S;
 }
 
@@ -2051,7 +2064,7 @@ int fr_create(const fr_model_desc *m, const fr_scene_desc *s, uint32_t flags, fr
         R(dalloc(c, &c->ew, (size_t)(1 + c->nl) * c->E)) ||
         R(dalloc(c, &c->tbl_edge, (size_t)(1 + c->nl) * c->E)) || R(dalloc(c, &c->tbl_prefix, (size_t)(1 + c->nl) * c->E)) ||
         R(dalloc(c, &c->tbl_n, (size_t)(1 + c->nl))) || R(dalloc(c, &c->tbl_Q, (size_t)(1 + c->nl))) ||
-        R(dalloc(c, &c->tbl_guide, (size_t)(1 + c->nl) * (c->E + 1))) ||
+        R(dalloc(c, &c->tbl_guide, (size_t)(1 + c->nl) * (c->E + 1))) || R(dalloc(c, &c->edge_rec, (size_t)5 * c->E)) ||
         R(dalloc(c, &c->ctr, (size_t)kCtrPerKern * kNumKern)) || R(dalloc(c, &c->sec_n, 1)) ||
         R(dalloc(c, &c->pe_samples, (size_t)c->W * c->H)) || R(dalloc(c, &c->pe_hits, 2 * (size_t)c->W * c->H)) ||
         R(dalloc(c, &c->pe_f, 6 * (size_t)c->W * c->H)) || R(dalloc(c, &c->pe_vis, 2 * (size_t)c->W * c->H)) ||
@@ -2229,7 +2242,7 @@ int fr_render(fr_ctx *c, const fr_params *p, uint64_t seed, int32_t spp, float *
     }
     ev_record(c, 2);
     Scene S = make_scene(c);
-    hipLaunchKernelGGL(k_edge_weights, dim3(nblk(c->E, 256)), dim3(256), 0, c->stream, S, c->lgeom, c->ew);
+    hipLaunchKernelGGL(k_edge_weights, dim3(nblk(c->E, 256)), dim3(256), 0, c->stream, S, c->lgeom, c->ew, c->edge_rec);
     hipLaunchKernelGGL(k_edge_scan<1024>, dim3(1 + c->nl), dim3(1024), 0, c->stream, c->E, c->ew,
                        c->tbl_edge, c->tbl_prefix, c->tbl_n, c->tbl_Q, c->tbl_guide);
     ev_record(c, 3);
@@ -2437,7 +2450,7 @@ void fr_destroy(fr_ctx *c) {
     void *ptrs[] = {c->faces, c->edges, c->vf_off, c->vf_idx, c->mean, c->b_id, c->b_exp, c->alb_mean, c->b_alb, c->uv,
                     c->lgeom, c->sorted_tri, c->leaf_node, c->right, c->escape, c->subs, c->height, c->top, c->top_off, c->nodes, c->tris,
                     c->vmodel, c->vm_d, c->pos, c->nrm, c->nlen, c->alb, c->ew, c->tbl_edge, c->tbl_prefix, c->tbl_n,
-                    c->tbl_Q, c->tbl_guide, c->samples, c->ctr, c->g_light, c->g_spec, c->g_pos, c->g_nrm, c->g_alb, c->g_N,
+                    c->tbl_Q, c->tbl_guide, c->edge_rec, c->samples, c->ctr, c->g_light, c->g_spec, c->g_pos, c->g_nrm, c->g_alb, c->g_N,
                     c->g_vert, c->g_m, c->partial, c->loss_partial, c->hits, c->vis, c->sec_list, c->sec_n, c->pe_samples, c->pe_hits,
                     c->pe_f, c->pe_vis, c->lb.key[0], c->lb.key[1], c->lb.val[0], c->lb.val[1], c->lb.hist,
                     c->lb.bounds, c->lb.child, c->lb.parent, c->lb.first, c->lb.last, c->lb.pre, c->lb.arrive, c->lb.box, c->lb.roots, c->lb.n_roots, c->lb.top_idx, c->lb.n_top};

@@ -51,6 +51,7 @@ struct Inst {
     double *vm_d;
     float *vmodel, *pos, *nrm, *nlen, *alb, *ew;
     int *tbl_edge, *tbl_n, *tbl_guide;
+    float4 *edge_rec;
     uint64_t *tbl_prefix, *tbl_Q;
     uint4 *nodes;
     float4 *tris;
@@ -138,7 +139,7 @@ FR_KIND(KBoxesTop, 1024) {
     lbvh_boxes_top_body(I.S.F, I.lb.child, I.lb.parent, I.lb.first, I.lb.last, I.lb.pre, I.lb.top_idx, I.lb.arrive,
                         I.lb.box, I.nodes, I.lb.roots, I.lb.n_roots);
 }};
-FR_KIND(KEdgeWeights, 256) { edge_weights_body(I.S, I.S.lgeom, I.ew, bx); }};
+FR_KIND(KEdgeWeights, 256) { edge_weights_body(I.S, I.S.lgeom, I.ew, I.edge_rec, bx); }};
 FR_KIND(KEdgeScan, 1024) {
     edge_scan_body<1024>(I.S.E, I.ew, I.tbl_edge, I.tbl_prefix, I.tbl_n, I.tbl_Q, I.tbl_guide, bx);
 }};
@@ -547,7 +548,7 @@ static int configure(fr_batch *b, const int32_t *spp) {
         I.vf_off = c->vf_off; I.vf_idx = c->vf_idx;
         I.mean = c->mean; I.b_id = c->b_id; I.b_exp = c->b_exp; I.alb_mean = c->alb_mean; I.b_alb = c->b_alb;
         I.vm_d = c->vm_d; I.vmodel = c->vmodel; I.pos = c->pos; I.nrm = c->nrm; I.nlen = c->nlen; I.alb = c->alb;
-        I.ew = c->ew;
+        I.ew = c->ew; I.edge_rec = c->edge_rec;
         I.tbl_edge = c->tbl_edge; I.tbl_n = c->tbl_n; I.tbl_prefix = c->tbl_prefix; I.tbl_Q = c->tbl_Q;
         I.tbl_guide = c->tbl_guide;
         I.nodes = c->nodes; I.tris = c->tris;

@@ -87,6 +87,7 @@ struct Scene {
     const int *pe_edge; const uint64_t *pe_prefix; const int *pe_n; const uint64_t *pe_Q;
     const int *se_edge; const uint64_t *se_prefix; const int *se_n; const uint64_t *se_Q;  // [nl][E]
     const int *pe_guide, *se_guide;   // cut-point guides: [E + 1], [nl][E + 1]
+    const float4 *edge_rec;           // [E][5]: endpoints, face normals and first vertices, face ids
 };
 
 __device__ __forceinline__ v3 vpos_raw(const float *pos, int V, int i) {
