@@ -139,7 +139,8 @@ typedef struct {
  * topology (edges, vertex-to-face lists, and the BVH shape when FR_REFIT is
  * given).  flags: FR_TIMING, FR_REFIT.
  * Errors: FR_EINVAL (sizes <= 0, null arrays, non-manifold mesh, index out
- * of range, n_lights > 64), FR_ENOMEM, FR_EDEVICE.  *out is NULL on error. */
+ * of range, n_lights > 64, more than 2^21 edges), FR_ENOMEM, FR_EDEVICE.
+ * *out is NULL on error. */
 int fr_create(const fr_model_desc *model, const fr_scene_desc *scene,
               uint32_t flags, fr_ctx **out);
 
