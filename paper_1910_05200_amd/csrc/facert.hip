@@ -481,8 +481,12 @@ __global__ __launch_bounds__(256) void k_cam_init(Scene S, uint64_t seed, int sp
 // the triangle's widened box (the whole image when the box reaches the
 // camera's plane).  Projection in fp64; the margin covers the fp32 rounding
 // of the sample's direction and of the hit point.
-__device__ inline void cam_footprint(const Scene &S, v3 v0, v3 v1, v3 v2, int &x0, int &x1, int &y0, int &y1) {
-    x0 = 0; x1 = S.W - 1; y0 = 0; y1 = S.H - 1;
+__device__ inline void cam_footprint(const Scene &S, v3 v0, v3 v1, v3 v2, int border, int &x0, int &x1, int &y0,
+                                     int &y1) {
+    // pixels -border .. W - 1 + border (a border of 1 holds screen points
+    // just outside the image)
+    const int lx = -border, hx = S.W - 1 + border, ly = -border, hy = S.H - 1 + border;
+    x0 = lx; x1 = hx; y0 = ly; y1 = hy;
     const double lo[3] = {(double)fminf(fminf(v0.x, v1.x), v2.x) - 2.0 * kHitMargin,
                           (double)fminf(fminf(v0.y, v1.y), v2.y) - 2.0 * kHitMargin,
                           (double)fminf(fminf(v0.z, v1.z), v2.z) - 2.0 * kHitMargin};
@@ -507,10 +511,10 @@ __device__ inline void cam_footprint(const Scene &S, v3 v0, v3 v1, v3 v2, int &x
         qx0 = fmin(qx0, qx); qx1 = fmax(qx1, qx); qy0 = fmin(qy0, qy); qy1 = fmax(qy1, qy);
     }
     // clamped before the conversion (an off-screen box gives an empty range)
-    x0 = (int)fmin(fmax(0.0, floor(qx0 - eps)), (double)S.W);
-    x1 = (int)fmax(fmin((double)(S.W - 1), floor(qx1 + eps)), -1.0);
-    y0 = (int)fmin(fmax(0.0, floor(qy0 - eps)), (double)S.H);
-    y1 = (int)fmax(fmin((double)(S.H - 1), floor(qy1 + eps)), -1.0);
+    x0 = (int)fmin(fmax((double)lx, floor(qx0 - eps)), (double)(hx + 1));
+    x1 = (int)fmax(fmin((double)hx, floor(qx1 + eps)), (double)(lx - 1));
+    y0 = (int)fmin(fmax((double)ly, floor(qy0 - eps)), (double)(hy + 1));
+    y1 = (int)fmax(fmin((double)hy, floor(qy1 + eps)), (double)(ly - 1));
 }
 
 __global__ __launch_bounds__(256) void k_cam_raster(Scene S, int spp, long long s0, long long n,
@@ -522,7 +526,7 @@ __global__ __launch_bounds__(256) void k_cam_raster(Scene S, int spp, long long 
         const int *t = S.faces + 3 * f;
         const v3 v0 = vpos(S, t[0]), v1 = vpos(S, t[1]), v2 = vpos(S, t[2]);
         int x0, x1, y0, y1;
-        cam_footprint(S, v0, v1, v2, x0, x1, y0, y1);
+        cam_footprint(S, v0, v1, v2, 0, x0, x1, y0, y1);
         // rows of this chunk
         y0 = max(y0, (int)((s0 / spp) / S.W));
         y1 = min(y1, (int)(((s0 + n - 1) / spp) / S.W));
@@ -1144,10 +1148,10 @@ __global__ __launch_bounds__(256) void k_edge_secondary_value(Scene S, uint64_t 
 // ---------------------------------------------- camera silhouettes -----
 // M = W*H edge samples, in three passes so that the 40 shadow rays of a
 // sample run on separate lanes:
-//   k_edge_primary_setup  two lanes per sample (the batched path: one):
-//                         pick the edge, the point q on its projection, the
-//                         two sides q +- offset; trace the camera rays and
-//                         keep the hits;
+//   setup                 pick the edge, the point q on its projection, the
+//                         two sides q +- offset; find the sides' camera-ray
+//                         hits (k_pe_* in the single context, a walk per
+//                         sample in the batched path);
 //   k_edge_primary_vis    one block per (tile of sides, light): horizon
 //                         test, compaction, shadow ray, visibility bit;
 //   k_edge_primary_shade  one lane per side: fp64 radiance of its visible
@@ -1156,70 +1160,184 @@ __global__ __launch_bounds__(256) void k_edge_secondary_value(Scene S, uint64_t 
 //                         Jacobian into the edge's two endpoints.
 struct PeSample { int e, i, pix; float qx, qy; };
 
-// SPLIT: two lanes per sample, one per side of the edge (both pick the same
-// edge and point, each traces its own side's ray), for launches too small to
-// fill the chip; else one lane traces both sides in one walk.
-template <bool SPLIT>
+// The sample's edge (CDF pick), its point q on the edge's projection and the
+// two side points q +- offset along the projected edge's normal, in pixels;
+// false (ps.e = -1) when the sample has none.
+__device__ __forceinline__ bool pe_pick(const Scene &S, uint64_t seed, int m, PeSample &ps, float &px0, float &py0,
+                                        float &px1, float &py1) {
+    ps.e = -1; ps.i = 0; ps.pix = -1; ps.qx = ps.qy = 0.0f;
+    const int n = S.pe_n[0];
+    const uint64_t Q = S.pe_Q[0];
+    if (n <= 0 || Q == 0) return false;
+    u4 wd = philox(seed, (uint32_t)m, 0, 2, 0);
+    uint64_t target = __umul64hi(((uint64_t)wd.y << 32) | wd.x, Q);
+    int i = cdf_pick_guided(S.pe_prefix, S.pe_guide, n, Q, target);
+    int e = S.pe_edge[i];
+    const int *ed = S.edges + 4 * e;
+    float tu = u01(wd.z);
+    v3 a = vpos(S, ed[0]), b = vpos(S, ed[1]);
+    float ax, ay, bx, by;
+    if (!project(S, a, ax, ay) || !project(S, b, bx, by)) return false;
+    float qx = ax + tu * (bx - ax), qy = ay + tu * (by - ay);
+    float fpx = floorf(qx), fpy = floorf(qy);
+    if (!(fpx >= 0.0f && fpx < (float)S.W && fpy >= 0.0f && fpy < (float)S.H)) return false;
+    v3 cam = mk(S.cam_x, S.cam_y, S.cam_z);
+    v3 mv = cross(a - cam, b - cam);
+    float gx = mv.x, gy = -mv.y;
+    float gl = sqrtf(gx * gx + gy * gy);
+    if (gl == 0.0f) return false;
+    float nx = gx / gl, ny = gy / gl;
+    px0 = qx + kEdgeOffPx * nx; py0 = qy + kEdgeOffPx * ny;
+    px1 = qx + -1.0f * (kEdgeOffPx * nx); py1 = qy + -1.0f * (kEdgeOffPx * ny);
+    ps.e = e; ps.i = i; ps.pix = (int)fpy * S.W + (int)fpx; ps.qx = qx; ps.qy = qy;
+    return true;
+}
+
+// Batched path: one lane per sample traces both sides' camera rays in one
+// walk.
 __device__ __forceinline__ void edge_primary_setup_body(const Scene &S, uint64_t seed, int M,
         PeSample *__restrict__ ps_out, Hit *__restrict__ hits, unsigned long long *__restrict__ pvis,
         unsigned long long *ctr, int bx) {
-    const int g = bx * blockDim.x + threadIdx.x;
-    const int m = SPLIT ? g >> 1 : g, side = SPLIT ? g & 1 : 0;
+    const int m = bx * blockDim.x + threadIdx.x;
     uint32_t n_cam = 0;
     Work wk;
-    int n = S.pe_n[0];
-    uint64_t Q = S.pe_Q[0];
     if (m < M) {
-        PeSample ps; ps.e = -1; ps.i = 0; ps.pix = -1; ps.qx = ps.qy = 0.0f;
-        Hit h; h.tri = -1; h.t = 0.0f; h.b1 = h.b2 = h.det = 0.0f;
-        Hit h2 = h;
-        do {
-            if (n <= 0 || Q == 0) break;
-            u4 wd = philox(seed, (uint32_t)m, 0, 2, 0);
-            uint64_t target = __umul64hi(((uint64_t)wd.y << 32) | wd.x, Q);
-            int i = cdf_pick_guided(S.pe_prefix, S.pe_guide, n, Q, target);
-            int e = S.pe_edge[i];
-            const int *ed = S.edges + 4 * e;
-            float tu = u01(wd.z);
-            v3 a = vpos(S, ed[0]), b = vpos(S, ed[1]);
-            float ax, ay, bx, by;
-            if (!project(S, a, ax, ay) || !project(S, b, bx, by)) break;
-            float qx = ax + tu * (bx - ax), qy = ay + tu * (by - ay);
-            float fpx = floorf(qx), fpy = floorf(qy);
-            if (!(fpx >= 0.0f && fpx < (float)S.W && fpy >= 0.0f && fpy < (float)S.H)) break;
-            v3 cam = mk(S.cam_x, S.cam_y, S.cam_z);
-            v3 mv = cross(a - cam, b - cam);
-            float gx = mv.x, gy = -mv.y;
-            float gl = sqrtf(gx * gx + gy * gy);
-            if (gl == 0.0f) break;
-            float nx = gx / gl, ny = gy / gl;
-            const float px0 = qx + kEdgeOffPx * nx, py0 = qy + kEdgeOffPx * ny;
-            const float px1 = qx + -1.0f * (kEdgeOffPx * nx), py1 = qy + -1.0f * (kEdgeOffPx * ny);
-            if (SPLIT) {   // one call site: the lanes of a wave take both sides
-                const float px = side == 0 ? px0 : px1, py = side == 0 ? py0 : py1;
-                h = trace_closest(S, cam, camera_dir(S, px, py), wk);
-                n_cam = 1;
-            } else {
-                trace_closest2(S, cam, camera_dir(S, px0, py0), camera_dir(S, px1, py1), h, h2, wk);
-                n_cam = 2;
-            }
-            ps.e = e; ps.i = i; ps.pix = (int)fpy * S.W + (int)fpx; ps.qx = qx; ps.qy = qy;
-        } while (0);
-        if (side == 0) ps_out[m] = ps;
-        hits[2 * m + side] = h;
-        pvis[2 * m + side] = 0ull;
-        if (!SPLIT) {
-            hits[2 * m + 1] = h2;
-            pvis[2 * m + 1] = 0ull;
+        PeSample ps;
+        Hit h0; h0.tri = -1; h0.t = 0.0f; h0.b1 = h0.b2 = h0.det = 0.0f;
+        Hit hs[2] = {h0, h0};
+        float px0, py0, px1, py1;
+        if (pe_pick(S, seed, m, ps, px0, py0, px1, py1)) {
+            const v3 cam = mk(S.cam_x, S.cam_y, S.cam_z);
+            trace_closest2(S, cam, camera_dir(S, px0, py0), camera_dir(S, px1, py1), hs[0], hs[1], wk);
+            n_cam = 2;
         }
+        ps_out[m] = ps;
+        hits[2 * m] = hs[0];
+        hits[2 * m + 1] = hs[1];
+        pvis[2 * m] = 0ull;
+        pvis[2 * m + 1] = 0ull;
     }
     flush_count(ctr, 0, n_cam);
     flush_work(ctr, wk);
 }
-__global__ __launch_bounds__(256) void k_edge_primary_setup(Scene S, uint64_t seed, int M,
-        PeSample *__restrict__ ps_out, Hit *__restrict__ hits, unsigned long long *__restrict__ pvis,
-        unsigned long long *ctr) {
-    edge_primary_setup_body<true>(S, seed, M, ps_out, hits, pvis, ctr, blockIdx.x);
+
+// Single context: the side rays are camera rays through arbitrary screen
+// points, too few (2 W H) to keep the chip busy walking the tree.  Their
+// hits are the minimum of (t, triangle id) over the triangles whose test
+// accepts the ray, bit for bit the walk's hit, found through a screen grid:
+//   k_pe_tri_count  one lane per triangle: the cells (kPeCell^2 pixels, with
+//                   a one-pixel border around the image for side points just
+//                   outside it) that its camera footprint covers;
+//   k_scan_u32      cell counts -> offsets;
+//   k_pe_tri_fill   each cell's triangles as 48-byte vertex records;
+//   k_pe_pick       one lane per sample: edge, point, side points;
+//   k_pe_resolve    one lane per side: the tests against its cell's
+//                   triangles, the minimum kept as the walk keeps it.
+// The records have a fixed capacity; past it the sides walk the tree.
+constexpr int kPeCell = 2;
+constexpr int kPeRecPerTri = 16;     // record capacity: this many per triangle, plus one per cell
+__device__ __forceinline__ int pe_cell_1d(int px) { return (px >= 0 ? px / kPeCell : -1) + 1; }   // px >= -1
+__device__ __forceinline__ int pe_cell(const Scene &S, float px, float py, int ncx) {
+    const int ix = min(max((int)floorf(px), -1), S.W), iy = min(max((int)floorf(py), -1), S.H);
+    return pe_cell_1d(iy) * ncx + pe_cell_1d(ix);
+}
+// cell range of a triangle's footprint; false when empty
+__device__ __forceinline__ bool pe_tri_cells(const Scene &S, int f, v3 &v0, v3 &v1, v3 &v2, int &cx0, int &cx1,
+                                             int &cy0, int &cy1) {
+    const int *t = S.faces + 3 * f;
+    v0 = vpos(S, t[0]); v1 = vpos(S, t[1]); v2 = vpos(S, t[2]);
+    int x0, x1, y0, y1;
+    cam_footprint(S, v0, v1, v2, 1, x0, x1, y0, y1);
+    if (x0 > x1 || y0 > y1) return false;
+    cx0 = pe_cell_1d(x0); cx1 = pe_cell_1d(x1); cy0 = pe_cell_1d(y0); cy1 = pe_cell_1d(y1);
+    return true;
+}
+__global__ __launch_bounds__(256) void k_pe_tri_count(Scene S, int ncx, uint32_t *__restrict__ cell_n) {
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= S.F) return;
+    v3 v0, v1, v2;
+    int cx0, cx1, cy0, cy1;
+    if (!pe_tri_cells(S, f, v0, v1, v2, cx0, cx1, cy0, cy1)) return;
+    for (int cy = cy0; cy <= cy1; ++cy)
+        for (int cx = cx0; cx <= cx1; ++cx) atomicAdd(&cell_n[cy * ncx + cx], 1u);
+}
+__global__ __launch_bounds__(256) void k_pe_tri_fill(Scene S, int ncx, const uint32_t *__restrict__ off,
+        uint32_t *__restrict__ fill, float4 *__restrict__ rec, uint32_t cap) {
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= S.F) return;
+    v3 v0, v1, v2;
+    int cx0, cx1, cy0, cy1;
+    if (!pe_tri_cells(S, f, v0, v1, v2, cx0, cx1, cy0, cy1)) return;
+    for (int cy = cy0; cy <= cy1; ++cy)
+        for (int cx = cx0; cx <= cx1; ++cx) {
+            const int c = cy * ncx + cx;
+            const uint32_t slot = off[c] + atomicAdd(&fill[c], 1u);
+            if (slot < cap) {
+                rec[3 * (size_t)slot] = make_float4(v0.x, v0.y, v0.z, v1.x);
+                rec[3 * (size_t)slot + 1] = make_float4(v1.y, v1.z, v2.x, v2.y);
+                rec[3 * (size_t)slot + 2] = make_float4(v2.z, __int_as_float(f), 0.0f, 0.0f);
+            }
+        }
+}
+__global__ __launch_bounds__(256) void k_pe_pick(Scene S, uint64_t seed, int M, PeSample *__restrict__ ps_out,
+        float2 *__restrict__ q) {
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= M) return;
+    PeSample ps;
+    float px[2], py[2];
+    if (pe_pick(S, seed, m, ps, px[0], py[0], px[1], py[1])) {
+        q[2 * m] = make_float2(px[0], py[0]);
+        q[2 * m + 1] = make_float2(px[1], py[1]);
+    }
+    ps_out[m] = ps;
+}
+__global__ __launch_bounds__(256) void k_pe_resolve(Scene S, int M, int ncx, int nc, const PeSample *__restrict__ ps,
+        const float2 *__restrict__ q, const uint32_t *__restrict__ off, const float4 *__restrict__ rec, uint32_t cap,
+        Hit *__restrict__ hits, unsigned long long *__restrict__ pvis, unsigned long long *ctr) {
+    const int side = blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t n_cam = 0;
+    Work wk;
+    if (side < 2 * M) {
+        Hit h; h.tri = -1; h.t = 0.0f; h.b1 = h.b2 = h.det = 0.0f;
+        if (ps[side >> 1].e >= 0) {
+            n_cam = 1;
+            const float2 p = q[side];
+            const v3 o = mk(S.cam_x, S.cam_y, S.cam_z), d = camera_dir(S, p.x, p.y);
+            if (off[nc] > cap) {
+                h = trace_closest(S, o, d, wk);   // records overflowed: walk the tree
+            } else {
+                h.t = INFINITY;
+                const int c = pe_cell(S, p.x, p.y, ncx);
+                const uint32_t end = off[c + 1];
+                // four records loaded before they are tested, so that their
+                // loads overlap
+                for (uint32_t k = off[c]; k < end; k += 4) {
+                    float4 r[4][3];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+                        if (k + u < end)
+                            for (int w = 0; w < 3; ++w) r[u][w] = rec[3 * (size_t)(k + u) + w];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        if (k + u >= end) break;
+                        const float4 r0 = r[u][0], r1 = r[u][1], r2 = r[u][2];
+                        const int f = __float_as_int(r2.y);
+                        float t, b1, b2, det;
+                        ++wk.tri;
+                        if (ray_tri(o, d, mk(r0.x, r0.y, r0.z), mk(r0.w, r1.x, r1.y), mk(r1.z, r1.w, r2.x), 0.0f,
+                                    INFINITY, t, b1, b2, det) &&
+                            (t < h.t || (t == h.t && f < h.tri))) {
+                            h.tri = f; h.t = t; h.b1 = b1; h.b2 = b2; h.det = det;
+                        }
+                    }
+                }
+            }
+        }
+        hits[side] = h;
+        pvis[side] = 0ull;
+    }
+    flush_count(ctr, 0, n_cam);
+    flush_work(ctr, wk);
 }
 
 // screen point of side 'side' of a primary sample (same fp32 ops as setup)
@@ -1704,6 +1822,10 @@ struct fr_ctx {
     int *tbl_edge = nullptr, *tbl_n = nullptr; uint64_t *tbl_prefix = nullptr, *tbl_Q = nullptr;
     int *tbl_guide = nullptr;        // [1 + nl][E + 1] cut-point guides of the tables
     float4 *edge_rec = nullptr;      // [E][5] edge geometry for the shadow-boundary proposals
+    float2 *pe_q = nullptr;          // [2 W H] silhouette sides' screen points
+    uint32_t *pe_cell_n = nullptr;   // [2 cells + 1]: triangle counts, then offsets; fill counters
+    float4 *pe_rec = nullptr;        // [pe_cap][3] triangle vertex records in cell order
+    uint32_t pe_cap = 0;
     float *samples = nullptr; size_t samples_cap = 0;
     HitRec *hits = nullptr; unsigned long long *vis = nullptr; size_t rec_cap = 0;
     uint32_t *sec_list = nullptr, *sec_n = nullptr; size_t sec_cap = 0;
@@ -2068,6 +2190,9 @@ int fr_create(const fr_model_desc *m, const fr_scene_desc *s, uint32_t flags, fr
         R(dalloc(c, &c->ctr, (size_t)kCtrPerKern * kNumKern)) || R(dalloc(c, &c->sec_n, 1)) ||
         R(dalloc(c, &c->pe_samples, (size_t)c->W * c->H)) || R(dalloc(c, &c->pe_hits, 2 * (size_t)c->W * c->H)) ||
         R(dalloc(c, &c->pe_f, 6 * (size_t)c->W * c->H)) || R(dalloc(c, &c->pe_vis, 2 * (size_t)c->W * c->H)) ||
+        R(dalloc(c, &c->pe_q, 2 * (size_t)c->W * c->H)) ||
+        R(dalloc(c, &c->pe_cell_n, 2 * (size_t)(c->W / kPeCell + 2) * (c->H / kPeCell + 2) + 1)) ||
+        R(dalloc(c, &c->pe_rec, 3 * ((size_t)kPeRecPerTri * c->F + (size_t)(c->W / kPeCell + 2) * (c->H / kPeCell + 2)))) ||
         R(dalloc(c, &c->g_light, 3 * (size_t)c->nl)) || R(dalloc(c, &c->g_spec, (size_t)c->res * c->res)) ||
         R(dalloc(c, &c->g_pos, V3)) || R(dalloc(c, &c->g_nrm, V3)) || R(dalloc(c, &c->g_alb, V3)) ||
         R(dalloc(c, &c->g_N, V3)) || R(dalloc(c, &c->g_vert, V3)) || R(dalloc(c, &c->g_m, V3))) {
@@ -2321,8 +2446,19 @@ int fr_backward(fr_ctx *c, const float *dLdI, const fr_grads *g) {
     ev_record(c, 8 + 2 * kKernPrimary);
     if (c->terms & FR_TERM_PRIMARY) {
         int M = c->W * c->H;
-        hipLaunchKernelGGL(k_edge_primary_setup, dim3(nblk(2 * (size_t)M, 256)), dim3(256), 0, c->stream,
-                           S, c->last_seed, M, c->pe_samples, c->pe_hits, c->pe_vis, c->ctr + kCtrPerKern * kKernPrimary);
+        unsigned long long *pctr = c->ctr + kCtrPerKern * kKernPrimary;
+        const int ncx = c->W / kPeCell + 2, nc = ncx * (c->H / kPeCell + 2);
+        const uint32_t cap = (uint32_t)((size_t)kPeRecPerTri * c->F + nc);
+        hipLaunchKernelGGL(k_zero_u32, dim3(nblk(2 * (size_t)nc + 1, 256)), dim3(256), 0, c->stream, c->pe_cell_n,
+                           2 * nc + 1);
+        hipLaunchKernelGGL(k_pe_tri_count, dim3(nblk(c->F, 256)), dim3(256), 0, c->stream, S, ncx, c->pe_cell_n);
+        hipLaunchKernelGGL(k_scan_u32, dim3(1), dim3(1024), 0, c->stream, nc + 1, c->pe_cell_n);
+        hipLaunchKernelGGL(k_pe_tri_fill, dim3(nblk(c->F, 256)), dim3(256), 0, c->stream, S, ncx, c->pe_cell_n,
+                           c->pe_cell_n + nc + 1, c->pe_rec, cap);
+        hipLaunchKernelGGL(k_pe_pick, dim3(nblk(M, 256)), dim3(256), 0, c->stream, S, c->last_seed, M, c->pe_samples,
+                           c->pe_q);
+        hipLaunchKernelGGL(k_pe_resolve, dim3(nblk(2 * (size_t)M, 256)), dim3(256), 0, c->stream, S, M, ncx, nc,
+                           c->pe_samples, c->pe_q, c->pe_cell_n, c->pe_rec, cap, c->pe_hits, c->pe_vis, pctr);
         hipLaunchKernelGGL(k_edge_primary_vis, dim3(nblk((size_t)2 * M, kPvTile), c->nl), dim3(256), 0, c->stream,
                            S, c->last_seed, M, c->pe_samples, c->pe_hits, c->pe_vis, c->ctr + kCtrPerKern * kKernPrimary);
         hipLaunchKernelGGL(k_edge_primary_shade, dim3(nblk((size_t)2 * M, 256)), dim3(256), lds1, c->stream,
@@ -2451,7 +2587,7 @@ void fr_destroy(fr_ctx *c) {
                     c->lgeom, c->sorted_tri, c->leaf_node, c->right, c->escape, c->subs, c->height, c->top, c->top_off, c->nodes, c->tris,
                     c->vmodel, c->vm_d, c->pos, c->nrm, c->nlen, c->alb, c->ew, c->tbl_edge, c->tbl_prefix, c->tbl_n,
                     c->tbl_Q, c->tbl_guide, c->edge_rec, c->samples, c->ctr, c->g_light, c->g_spec, c->g_pos, c->g_nrm, c->g_alb, c->g_N,
-                    c->g_vert, c->g_m, c->partial, c->loss_partial, c->hits, c->vis, c->sec_list, c->sec_n, c->pe_samples, c->pe_hits,
+                    c->g_vert, c->g_m, c->partial, c->loss_partial, c->hits, c->vis, c->pe_q, c->pe_cell_n, c->pe_rec, c->sec_list, c->sec_n, c->pe_samples, c->pe_hits,
                     c->pe_f, c->pe_vis, c->lb.key[0], c->lb.key[1], c->lb.val[0], c->lb.val[1], c->lb.hist,
                     c->lb.bounds, c->lb.child, c->lb.parent, c->lb.first, c->lb.last, c->lb.pre, c->lb.arrive, c->lb.box, c->lb.roots, c->lb.n_roots, c->lb.top_idx, c->lb.n_top};
     for (void *p : ptrs) if (p) (void)hipFree(p);

@@ -179,7 +179,7 @@ FR_KIND(KSecValue, 256) {
 }};
 FR_KIND(KPrimarySetup, 256) {
     if (!(I.d.terms & FR_TERM_PRIMARY)) return;
-    edge_primary_setup_body<false>(I.S, I.d.seed, I.M, I.pe_samples, I.pe_hits, I.pe_vis, I.ctr + kCtrPerKern * kKernPrimary, bx);
+    edge_primary_setup_body(I.S, I.d.seed, I.M, I.pe_samples, I.pe_hits, I.pe_vis, I.ctr + kCtrPerKern * kKernPrimary, bx);
 }};
 template <int TS> FR_KIND(KPrimaryVis, 256) {
     if (!(I.d.terms & FR_TERM_PRIMARY)) return;
