@@ -800,6 +800,13 @@ __device__ inline void vtx_flush(const VtxAcc &a, const GradBufs &G, int V) {
     }
 }
 
+// The block's light sums have kLightCopies copies, a lane adding into copy
+// (lane mod kLightCopies): the lanes of a wave add to the same few words,
+// and LDS atomics to one word serialise.  The copies lie an odd number of
+// words apart (light_stride), so a word's copies fall in different banks;
+// the flush sums them.
+constexpr int kLightCopies = 8;
+__host__ __device__ __forceinline__ int light_stride(int nl) { return 3 * nl | 1; }
 // Interior adjoint of one camera sample (decisions fp32, values T).
 // Light and texel adjoints go to block-shared fp32 accumulators when given,
 // else straight to the fp64 buffers.
@@ -825,7 +832,9 @@ __device__ inline void adjoint_sample(const Scene &S, const Light *Ls, uint64_t 
         shade_light<T>(sv, L, cvt<T>(y), light_branch(sd, L.n, y), w, c, &a);
         ++wk.shade;
         for (int k = 0; k < 3; ++k) {
-            if (g_light_lds) atomicAdd(&g_light_lds[3 * j + k], (float)a.gl[k]);
+            if (g_light_lds)   // this lane's copy of the block's light sums
+                atomicAdd(&g_light_lds[(threadIdx.x & (kLightCopies - 1)) * light_stride(S.nl) + 3 * j + k],
+                          (float)a.gl[k]);
             else gadd(&G.d_light[3 * j + k], (double)a.gl[k]);
             gA[k] += a.gA[k];
         }
@@ -867,13 +876,13 @@ __device__ __forceinline__ void render_adj_body(const Scene &S, uint64_t seed, i
     __shared__ Light Ls[kMaxLights];
     float *spec_lds = dyn;
     float *g_spec = dyn + S.res * S.res;        // [res^2]
-    float *g_light = g_spec + S.res * S.res;    // [nl*3]
+    float *g_light = g_spec + S.res * S.res;    // [kLightCopies][light_stride(nl)]
     __shared__ int vt_key[kVtxSlots];
     __shared__ double vt_val[9 * kVtxSlots];
     const VtxAcc acc{vt_key, vt_val};
     stage_tables(S, Ls, spec_lds);
     for (int k = threadIdx.x; k < S.res * S.res; k += blockDim.x) g_spec[k] = 0.0f;
-    for (int k = threadIdx.x; k < 3 * S.nl; k += blockDim.x) g_light[k] = 0.0f;
+    for (int k = threadIdx.x; k < kLightCopies * light_stride(S.nl); k += blockDim.x) g_light[k] = 0.0f;
     vtx_clear(acc);
     __syncthreads();
     long long i = (long long)bx * blockDim.x + threadIdx.x;
@@ -899,8 +908,11 @@ __device__ __forceinline__ void render_adj_body(const Scene &S, uint64_t seed, i
     __syncthreads();
     for (int k = threadIdx.x; k < S.res * S.res; k += blockDim.x)
         if (g_spec[k] != 0.0f) gadd(&G.d_spec[k], (double)g_spec[k]);
-    for (int k = threadIdx.x; k < 3 * S.nl; k += blockDim.x)
-        if (g_light[k] != 0.0f) gadd(&G.d_light[k], (double)g_light[k]);
+    for (int k = threadIdx.x; k < 3 * S.nl; k += blockDim.x) {
+        float x = 0.0f;
+        for (int r = 0; r < kLightCopies; ++r) x += g_light[r * light_stride(S.nl) + k];
+        if (x != 0.0f) gadd(&G.d_light[k], (double)x);
+    }
     vtx_flush(acc, G, S.V);
 }
 __global__ __launch_bounds__(256) void k_render_adj(Scene S, uint64_t seed, int spp, long long s0, long long n,
@@ -2414,7 +2426,7 @@ int fr_backward(fr_ctx *c, const float *dLdI, const fr_grads *g) {
     long long N = (long long)c->W * c->H * c->last_spp;
     GradBufs G{c->g_light, c->g_spec, c->g_pos, c->g_nrm, c->g_alb};
     const long long kChunk = c->last_cam_chunk;
-    size_t lds = ((size_t)2 * c->res * c->res + 3 * c->nl) * sizeof(float);
+    size_t lds = ((size_t)2 * c->res * c->res + (size_t)kLightCopies * light_stride(c->nl)) * sizeof(float);
     hipLaunchKernelGGL(k_zero_ctr, dim3(nblk(8 * kCtrSpread * (kNumKern - kKernAdj), 256)), dim3(256), 0, c->stream, c->ctr,
                        kKernAdj, kNumKern);
     size_t lds1 = (size_t)c->res * c->res * sizeof(float);

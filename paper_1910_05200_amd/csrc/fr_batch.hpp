@@ -560,7 +560,7 @@ static int configure(fr_batch *b, const int32_t *spp) {
         I.g_N = c->g_N; I.g_vert = c->g_vert; I.g_m = c->g_m; I.partial = c->partial;
         const size_t rr = (size_t)c->res * c->res;
         b->lds_res2 = std::max(b->lds_res2, rr * sizeof(float));
-        b->lds_adj = std::max(b->lds_adj, (2 * rr + 3 * (size_t)c->nl) * sizeof(float));
+        b->lds_adj = std::max(b->lds_adj, (2 * rr + (size_t)kLightCopies * light_stride(c->nl)) * sizeof(float));
     }
     b->order.resize(b->n);
     for (int i = 0; i < b->n; ++i) b->order[i] = i;
