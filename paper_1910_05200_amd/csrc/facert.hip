@@ -354,6 +354,119 @@ __global__ __launch_bounds__(BS) void k_edge_scan(int E, const float *__restrict
     edge_scan_body<BS>(E, w, out_edge, out_prefix, out_n, out_Q, out_guide, blockIdx.x);
 }
 
+// Single context: the same tables, each split over kEsChunk-edge chunks so
+// that a table is not one block's sequential walk (the batched path runs a
+// block per table of every face, which fills the chip).  The outputs are
+// edge_scan_body's bit for bit: the maximum and the integer sums are exact,
+// and the chunks and their threads keep edge order.
+constexpr int kEsPer = 8, kEsChunk = 256 * kEsPer;
+__device__ __forceinline__ uint32_t es_quant(float we, float wm) {
+    return (we > 0.0f && wm > 0.0f) ? 1u + (uint32_t)floorf((we / wm) * kQScale) : 0u;
+}
+// per table: the largest weight (non-negative floats order as their bits)
+__global__ __launch_bounds__(256) void k_es_max(int E, const float *__restrict__ w, uint32_t *__restrict__ wmax) {
+    __shared__ float s_m[4];
+    const float *wt = w + (size_t)blockIdx.y * E;
+    const int e1 = min(E, (int)(blockIdx.x + 1) * kEsChunk);
+    float mx = 0.0f;
+    for (int e = blockIdx.x * kEsChunk + threadIdx.x; e < e1; e += 256) mx = fmaxf(mx, wt[e]);
+    for (int off = 32; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off));
+    if ((threadIdx.x & 63) == 0) s_m[threadIdx.x >> 6] = mx;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const float m = fmaxf(fmaxf(s_m[0], s_m[1]), fmaxf(s_m[2], s_m[3]));
+        if (m > 0.0f) atomicMax(&wmax[blockIdx.y], __float_as_uint(m));
+    }
+}
+// per (table, chunk): the quantised weights' sum and positive count
+__global__ __launch_bounds__(256) void k_es_sum(int E, const float *__restrict__ w, const uint32_t *__restrict__ wmax,
+        uint64_t *__restrict__ csum, uint32_t *__restrict__ ccnt) {
+    __shared__ uint64_t s_s[4];
+    __shared__ uint32_t s_c[4];
+    const float *wt = w + (size_t)blockIdx.y * E;
+    const float wm = __uint_as_float(wmax[blockIdx.y]);
+    const int e0 = blockIdx.x * kEsChunk + threadIdx.x * kEsPer;
+    uint64_t sum = 0;
+    uint32_t cnt = 0;
+    for (int k = 0; k < kEsPer; ++k)
+        if (e0 + k < E) { const uint32_t q = es_quant(wt[e0 + k], wm); sum += q; cnt += q > 0; }
+    for (int off = 32; off > 0; off >>= 1) { sum += __shfl_xor(sum, off); cnt += __shfl_xor(cnt, off); }
+    if ((threadIdx.x & 63) == 0) { s_s[threadIdx.x >> 6] = sum; s_c[threadIdx.x >> 6] = cnt; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        csum[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = s_s[0] + s_s[1] + s_s[2] + s_s[3];
+        ccnt[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = s_c[0] + s_c[1] + s_c[2] + s_c[3];
+    }
+}
+// per (table, chunk): offsets from the earlier chunks, then the chunk's
+// exclusive scan and compaction; the last chunk writes n and Q
+__global__ __launch_bounds__(256) void k_es_scan(int E, const float *__restrict__ w,
+        const uint32_t *__restrict__ wmax, const uint64_t *__restrict__ csum, const uint32_t *__restrict__ ccnt,
+        int *__restrict__ out_edge, uint64_t *__restrict__ out_prefix, int *__restrict__ out_n,
+        uint64_t *__restrict__ out_Q) {
+    __shared__ uint64_t s_s[4];
+    __shared__ uint32_t s_c[4];
+    const int tbl = blockIdx.y, nch = gridDim.x, ch = blockIdx.x;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    // offsets: the sums of chunks 0 .. ch-1
+    uint64_t b = 0;
+    uint32_t nb = 0;
+    for (int c = threadIdx.x; c < ch; c += 256) { b += csum[(size_t)tbl * nch + c]; nb += ccnt[(size_t)tbl * nch + c]; }
+    for (int off = 32; off > 0; off >>= 1) { b += __shfl_xor(b, off); nb += __shfl_xor(nb, off); }
+    if (lane == 0) { s_s[wave] = b; s_c[wave] = nb; }
+    __syncthreads();
+    const uint64_t base = s_s[0] + s_s[1] + s_s[2] + s_s[3];
+    const uint32_t nbase = s_c[0] + s_c[1] + s_c[2] + s_c[3];
+    __syncthreads();
+    const float *wt = w + (size_t)tbl * E;
+    const float wm = __uint_as_float(wmax[tbl]);
+    const int e0 = ch * kEsChunk + threadIdx.x * kEsPer;
+    uint32_t q[kEsPer];
+    uint64_t tsum = 0;
+    uint32_t tcnt = 0;
+    for (int k = 0; k < kEsPer; ++k) {
+        q[k] = e0 + k < E ? es_quant(wt[e0 + k], wm) : 0u;
+        tsum += q[k];
+        tcnt += q[k] > 0;
+    }
+    uint64_t isum = tsum;
+    uint32_t icnt = tcnt;
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint64_t vs = __shfl_up(isum, off);
+        const uint32_t vc = __shfl_up(icnt, off);
+        if (lane >= off) { isum += vs; icnt += vc; }
+    }
+    if (lane == 63) { s_s[wave] = isum; s_c[wave] = icnt; }
+    __syncthreads();
+    uint64_t wsum = 0, total = 0;
+    uint32_t wcnt = 0, tc = 0;
+    for (int k = 0; k < 4; ++k) {
+        if (k < wave) { wsum += s_s[k]; wcnt += s_c[k]; }
+        total += s_s[k]; tc += s_c[k];
+    }
+    uint64_t pre = base + wsum + isum - tsum;
+    uint32_t slot = nbase + wcnt + icnt - tcnt;
+    int *oe = out_edge + (size_t)tbl * E;
+    uint64_t *op = out_prefix + (size_t)tbl * E;
+    for (int k = 0; k < kEsPer; ++k)
+        if (q[k] > 0) { oe[slot] = e0 + k; op[slot] = pre; pre += q[k]; ++slot; }
+    if (ch == nch - 1 && threadIdx.x == 0) { out_n[tbl] = (int)(nbase + tc); out_Q[tbl] = base + total; }
+}
+// per (table, range of entries): the cut-point guide, as edge_scan_body
+__global__ __launch_bounds__(256) void k_es_guide(int E, const uint64_t *__restrict__ out_prefix,
+        const int *__restrict__ out_n, const uint64_t *__restrict__ out_Q, int *__restrict__ out_guide) {
+    const int tbl = blockIdx.y, n = out_n[tbl];
+    const uint64_t Q = out_Q[tbl];
+    const uint64_t *op = out_prefix + (size_t)tbl * E;
+    int *og = out_guide + (size_t)tbl * (E + 1);
+    const int i1 = min(n, (int)(blockIdx.x + 1) * kEsChunk);
+    for (int i = blockIdx.x * kEsChunk + threadIdx.x; i < i1; i += 256) {
+        const int b0 = cut_bucket(op[i], n, Q);
+        const int b1 = i + 1 < n ? cut_bucket(op[i + 1], n, Q) : n + 1;
+        for (int bb = b0; bb < b1; ++bb) og[bb] = i;
+    }
+}
+
 // ------------------------------------------------------ LDS staging -----
 __device__ inline void stage_tables(const Scene &S, Light *Ls, float *spec_lds) {
     for (int j = threadIdx.x; j < S.nl; j += blockDim.x) {
@@ -1833,6 +1946,9 @@ struct fr_ctx {
     float *ew = nullptr;
     int *tbl_edge = nullptr, *tbl_n = nullptr; uint64_t *tbl_prefix = nullptr, *tbl_Q = nullptr;
     int *tbl_guide = nullptr;        // [1 + nl][E + 1] cut-point guides of the tables
+    uint32_t *es_wmax = nullptr;     // [1 + nl] largest weight per table (bits)
+    uint64_t *es_csum = nullptr;     // [1 + nl][chunks] quantised sums per chunk
+    uint32_t *es_ccnt = nullptr;     // [1 + nl][chunks] positive counts per chunk
     float4 *edge_rec = nullptr;      // [E][5] edge geometry for the shadow-boundary proposals
     float2 *pe_q = nullptr;          // [2 W H] silhouette sides' screen points
     uint32_t *pe_cell_n = nullptr;   // [2 cells + 1]: triangle counts, then offsets; fill counters
@@ -2198,7 +2314,10 @@ int fr_create(const fr_model_desc *m, const fr_scene_desc *s, uint32_t flags, fr
         R(dalloc(c, &c->ew, (size_t)(1 + c->nl) * c->E)) ||
         R(dalloc(c, &c->tbl_edge, (size_t)(1 + c->nl) * c->E)) || R(dalloc(c, &c->tbl_prefix, (size_t)(1 + c->nl) * c->E)) ||
         R(dalloc(c, &c->tbl_n, (size_t)(1 + c->nl))) || R(dalloc(c, &c->tbl_Q, (size_t)(1 + c->nl))) ||
-        R(dalloc(c, &c->tbl_guide, (size_t)(1 + c->nl) * (c->E + 1))) || R(dalloc(c, &c->edge_rec, (size_t)5 * c->E)) ||
+        R(dalloc(c, &c->tbl_guide, (size_t)(1 + c->nl) * (c->E + 1))) ||
+        R(dalloc(c, &c->es_wmax, (size_t)(1 + c->nl))) ||
+        R(dalloc(c, &c->es_csum, (size_t)(1 + c->nl) * nblk(c->E, kEsChunk))) ||
+        R(dalloc(c, &c->es_ccnt, (size_t)(1 + c->nl) * nblk(c->E, kEsChunk))) || R(dalloc(c, &c->edge_rec, (size_t)5 * c->E)) ||
         R(dalloc(c, &c->ctr, (size_t)kCtrPerKern * kNumKern)) || R(dalloc(c, &c->sec_n, 1)) ||
         R(dalloc(c, &c->pe_samples, (size_t)c->W * c->H)) || R(dalloc(c, &c->pe_hits, 2 * (size_t)c->W * c->H)) ||
         R(dalloc(c, &c->pe_f, 6 * (size_t)c->W * c->H)) || R(dalloc(c, &c->pe_vis, 2 * (size_t)c->W * c->H)) ||
@@ -2380,8 +2499,16 @@ int fr_render(fr_ctx *c, const fr_params *p, uint64_t seed, int32_t spp, float *
     ev_record(c, 2);
     Scene S = make_scene(c);
     hipLaunchKernelGGL(k_edge_weights, dim3(nblk(c->E, 256)), dim3(256), 0, c->stream, S, c->lgeom, c->ew, c->edge_rec);
-    hipLaunchKernelGGL(k_edge_scan<1024>, dim3(1 + c->nl), dim3(1024), 0, c->stream, c->E, c->ew,
-                       c->tbl_edge, c->tbl_prefix, c->tbl_n, c->tbl_Q, c->tbl_guide);
+    {
+        const dim3 g(nblk(c->E, kEsChunk), 1 + c->nl);
+        hipLaunchKernelGGL(k_zero_u32, dim3(nblk(1 + c->nl, 64)), dim3(64), 0, c->stream, c->es_wmax, 1 + c->nl);
+        hipLaunchKernelGGL(k_es_max, g, dim3(256), 0, c->stream, c->E, c->ew, c->es_wmax);
+        hipLaunchKernelGGL(k_es_sum, g, dim3(256), 0, c->stream, c->E, c->ew, c->es_wmax, c->es_csum, c->es_ccnt);
+        hipLaunchKernelGGL(k_es_scan, g, dim3(256), 0, c->stream, c->E, c->ew, c->es_wmax, c->es_csum, c->es_ccnt,
+                           c->tbl_edge, c->tbl_prefix, c->tbl_n, c->tbl_Q);
+        hipLaunchKernelGGL(k_es_guide, g, dim3(256), 0, c->stream, c->E, c->tbl_prefix, c->tbl_n, c->tbl_Q,
+                           c->tbl_guide);
+    }
     ev_record(c, 3);
     hipLaunchKernelGGL(k_zero_ctr, dim3(nblk(8 * kCtrSpread * kKernAdj, 256)), dim3(256), 0, c->stream, c->ctr, 0, kKernAdj);
     size_t lds = (size_t)c->res * c->res * sizeof(float);
@@ -2598,7 +2725,7 @@ void fr_destroy(fr_ctx *c) {
     void *ptrs[] = {c->faces, c->edges, c->vf_off, c->vf_idx, c->mean, c->b_id, c->b_exp, c->alb_mean, c->b_alb, c->uv,
                     c->lgeom, c->sorted_tri, c->leaf_node, c->right, c->escape, c->subs, c->height, c->top, c->top_off, c->nodes, c->tris,
                     c->vmodel, c->vm_d, c->pos, c->nrm, c->nlen, c->alb, c->ew, c->tbl_edge, c->tbl_prefix, c->tbl_n,
-                    c->tbl_Q, c->tbl_guide, c->edge_rec, c->samples, c->ctr, c->g_light, c->g_spec, c->g_pos, c->g_nrm, c->g_alb, c->g_N,
+                    c->tbl_Q, c->tbl_guide, c->es_wmax, c->es_csum, c->es_ccnt, c->edge_rec, c->samples, c->ctr, c->g_light, c->g_spec, c->g_pos, c->g_nrm, c->g_alb, c->g_N,
                     c->g_vert, c->g_m, c->partial, c->loss_partial, c->hits, c->vis, c->pe_q, c->pe_cell_n, c->pe_rec, c->sec_list, c->sec_n, c->pe_samples, c->pe_hits,
                     c->pe_f, c->pe_vis, c->lb.key[0], c->lb.key[1], c->lb.val[0], c->lb.val[1], c->lb.hist,
                     c->lb.bounds, c->lb.child, c->lb.parent, c->lb.first, c->lb.last, c->lb.pre, c->lb.arrive, c->lb.box, c->lb.roots, c->lb.n_roots, c->lb.top_idx, c->lb.n_top};
