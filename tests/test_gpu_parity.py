@@ -186,6 +186,52 @@ def test_chunks_that_end_inside_a_pixel(torch, orc):
     assert np.array_equal(whole, part)
 
 
+def _footprint_cells(osc, faces, W, H, cell=2):
+    """Screen cells (cell x cell pixels, a one-pixel border around the
+    image) that the triangles' projected bounding boxes cover, summed over
+    the triangles: a lower bound of the silhouette setup's cell records."""
+    pos = np.asarray(osc.pos, np.float64).T
+    cam = np.asarray(osc.cam, np.float64)
+    depth = cam[2] - pos[:, 2]
+    assert (depth > 0).all()
+    qx = W / 2 + (pos[:, 0] - cam[0]) / (depth * osc.pix_scale)
+    qy = H / 2 - (pos[:, 1] - cam[1]) / (depth * osc.pix_scale)
+    c = lambda p: (p // cell if p >= 0 else -1) + 1
+    total = 0
+    for f in np.asarray(faces):
+        x0, x1 = max(-1, int(np.floor(qx[f].min()))), min(W, int(np.floor(qx[f].max())))
+        y0, y1 = max(-1, int(np.floor(qy[f].min()))), min(H, int(np.floor(qy[f].max())))
+        total += max(0, c(x1) - c(x0) + 1) * max(0, c(y1) - c(y0) + 1)
+    return total
+
+
+def test_silhouette_sides_walk_the_tree_when_cell_records_overflow(torch, orc):
+    """One quad (two triangles) close to the camera, rolled so that a
+    boundary edge crosses the image: the triangles' screen footprints need
+    more cell records than the store holds (16 per triangle plus one per
+    cell), so the silhouette sides are traced through the tree instead.
+    Image and gradients still match the oracle."""
+    W, H, spp = 40, 36, 2
+    model, scene = synth.make_model(2, 2, seed=3), synth.make_scene(W, H)
+    params = synth.make_params(5)
+    params.pose = np.array([0.0, 0.0, 0.8, -0.02, -0.03, 0.3], np.float32)
+    osc, vm, R = orc.scene_from_model(model, scene, params)
+    cells = (W // 2 + 2) * (H // 2 + 2)
+    assert _footprint_cells(osc, model.faces, W, H) > 16 * model.n_faces + cells
+    r = _renderer(torch, model, scene)
+    img, _ = _gpu_render(torch, r, params, SEED, spp)
+    ref_img = orc.render(osc, SEED, spp)
+    assert_image_parity(img, ref_img)
+    dL = np.random.default_rng(4).normal(size=ref_img.shape).astype(np.float32)
+    g = r.backward(torch.from_numpy(dL).cuda())
+    torch.cuda.synchronize()
+    g = {k: v.cpu().numpy() for k, v in g.items()}
+    ref = orc.backward(osc, SEED, spp, dL.astype(np.float64), flags=7)
+    pg = orc.parameter_grads(model, params, vm, R, ref["d_pos"], ref["d_alb"])
+    assert r.stats()["rays_edge_primary"] > 0
+    _compare(g, ref, pg)
+
+
 def test_backward_all_terms_paper(torch, orc):
     g, ref, pg, _ = _grad_case(torch, orc, "paper", 7)
     _compare(g, ref, pg)
