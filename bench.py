@@ -175,7 +175,7 @@ def bench_batch(args):
 
         sequential(0)
         ms_seq = timed(sequential, max(2, args.steps // 4))
-    k_sh = facert.KERNELS.index("k_fwd_shadow")
+    k_sh = facert.KERNELS.index("k_sh_trace")
     ops_sh = sum(st["kernel_box_tests"][k_sh] * OPS_BOX + st["kernel_tri_tests"][k_sh] * OPS_TRI for st in stats)
     ms_sh = tm["fwd_shadow"]
     achieved = ops_sh / (ms_sh * 1e-3) / 1e12

@@ -762,9 +762,85 @@ __device__ __forceinline__ void fwd_shadow_body(const Scene &S, uint64_t seed, l
     flush_count(ctr, 1, n_sh);
     flush_work(ctr, wk);
 }
-__global__ __launch_bounds__(256) void k_fwd_shadow(Scene S, uint64_t seed, long long s0, long long n,
-        const HitRec *__restrict__ hits, unsigned long long *__restrict__ vis, unsigned long long *ctr) {
-    fwd_shadow_body<kShTile>(S, seed, s0, n, hits, vis, ctr, blockIdx.x, blockIdx.y);
+
+// Single context: the shadow rays in two kernels.  After a fused block's
+// compaction only about a third of its lanes have a ray (most pairs fail
+// the horizon test), so most of its waves sit idle while the rest trace.
+//   k_sh_propose  one block per (tile of samples, light): each sample's
+//                 horizon test; the accepted samples' indices go to the
+//                 light's queue (one atomic per block on that light's
+//                 counter);
+//   k_sh_trace    one lane per queued ray, rebuilt from the sample's hit
+//                 record and light sample as k_sh_propose built it, traced.
+// Every resident wave of k_sh_trace traces.  The batched path keeps the
+// fused kernel.
+__device__ __forceinline__ bool sh_ray(const Scene &S, const Light &L, uint64_t seed, long long s0, long long i,
+                                       const HitRec *__restrict__ hits, int j, v3 &p, v3 &dd, int &tri) {
+    const HitRec rec = hits[i];
+    if (rec.tri < 0) return false;
+    const Hit h = hit_of(rec);
+    SurfDec sd;
+    surf_decide(S, mk(S.cam_x, S.cam_y, S.cam_z), h, sd);
+    LightRng rng(seed, (uint32_t)(s0 + i), 0, 2);
+    float u, v;
+    rng.get(j, u, v);
+    const v3 y = light_point(L, u, v);
+    if (!above(sd, y)) return false;
+    p = sd.p; dd = y - sd.p; tri = h.tri;
+    return true;
+}
+__device__ __forceinline__ Light light_geom(const Scene &S, int j) {
+    const float *g = S.lgeom + 12 * j;
+    Light L;
+    L.c = mk(g[0], g[1], g[2]); L.e1 = mk(g[3], g[4], g[5]); L.e2 = mk(g[6], g[7], g[8]);
+    return L;
+}
+__global__ __launch_bounds__(256) void k_sh_propose(Scene S, uint64_t seed, long long s0, long long n,
+        const HitRec *__restrict__ hits, uint32_t *__restrict__ queue, uint32_t qcap, uint32_t *__restrict__ cnt,
+        unsigned long long *ctr) {
+    __shared__ uint32_t q[kShTile];
+    __shared__ int q_n;
+    __shared__ uint32_t q_base;
+    const int j = blockIdx.y, lane = threadIdx.x & 63;
+    if (threadIdx.x == 0) q_n = 0;
+    __syncthreads();
+    const Light L = light_geom(S, j);
+    const long long base = (long long)blockIdx.x * kShTile;
+    uint32_t n_sh = 0;
+    for (int k = 0; k < kShTile; k += 256) {
+        const int li = k + (int)threadIdx.x;
+        const long long i = base + li;
+        v3 p, dd;
+        int tri;
+        const bool need = i < n && sh_ray(S, L, seed, s0, i, hits, j, p, dd, tri);
+        const unsigned long long m = __ballot(need);
+        int wbase = 0;
+        if (lane == 0 && m) wbase = atomicAdd(&q_n, __popcll(m));
+        wbase = __shfl(wbase, 0);
+        if (need) { q[wbase + lanes_below(m)] = (uint32_t)i; ++n_sh; }
+    }
+    __syncthreads();
+    const int nq = q_n;
+    if (threadIdx.x == 0 && nq > 0) q_base = atomicAdd(&cnt[j], (uint32_t)nq);
+    __syncthreads();
+    for (int e = threadIdx.x; e < nq; e += 256) queue[(size_t)j * qcap + q_base + e] = q[e];
+    flush_count(ctr, 1, n_sh);
+}
+__global__ __launch_bounds__(256) void k_sh_trace(Scene S, uint64_t seed, long long s0,
+        const HitRec *__restrict__ hits, const uint32_t *__restrict__ queue, uint32_t qcap,
+        const uint32_t *__restrict__ cnt, unsigned long long *__restrict__ vis, unsigned long long *ctr) {
+    const int j = blockIdx.y;
+    const uint32_t e = blockIdx.x * 256 + threadIdx.x;
+    if (blockIdx.x * 256 >= cnt[j]) return;   // the whole block is past the queue
+    Work wk;
+    if (e < cnt[j]) {
+        const uint32_t i = queue[(size_t)j * qcap + e];
+        v3 p, dd;
+        int tri;
+        if (sh_ray(S, light_geom(S, j), seed, s0, i, hits, j, p, dd, tri) && !trace_any(S, p, dd, tri, wk))
+            atomicOr(&vis[i], 1ull << j);
+    }
+    flush_work(ctr, wk);
 }
 
 __device__ __forceinline__ void fwd_shade_body(const Scene &S, uint64_t seed, int spp, long long s0, long long n,
@@ -1950,6 +2026,9 @@ struct fr_ctx {
     uint64_t *es_csum = nullptr;     // [1 + nl][chunks] quantised sums per chunk
     uint32_t *es_ccnt = nullptr;     // [1 + nl][chunks] positive counts per chunk
     float4 *edge_rec = nullptr;      // [E][5] edge geometry for the shadow-boundary proposals
+    uint32_t *sh_queue = nullptr;    // [nl][sh_cap] queued shadow rays (sample index) per light
+    size_t sh_cap = 0;               // its capacity per light (samples of one chunk); fr_render only
+    uint32_t *sh_cnt = nullptr;      // [nl] queue lengths
     float2 *pe_q = nullptr;          // [2 W H] silhouette sides' screen points
     uint32_t *pe_cell_n = nullptr;   // [2 cells + 1]: triangle counts, then offsets; fill counters
     float4 *pe_rec = nullptr;        // [pe_cap][3] triangle vertex records in cell order
@@ -2250,6 +2329,21 @@ static Scene make_scene(fr_ctx *c) {
 
 static inline unsigned nblk(size_t n, unsigned bs) { return (unsigned)((n + bs - 1) / bs); }
 
+static void ev_record(fr_ctx *c, int i);
+// visibility masks of samples [s0, s0 + n) (after camera_pass); the events
+// ev0, ev1 (when >= 0) bracket the trace kernel, which holds all the
+// traversal work
+static void shadow_pass(fr_ctx *c, const Scene &S, uint64_t seed, long long s0, long long n, unsigned long long *ctr,
+                        int ev0 = -1, int ev1 = -1) {
+    const uint32_t qcap = (uint32_t)c->sh_cap;   // >= n: fr_render sized it for this chunk size
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, c->stream, c->sh_cnt, c->nl);
+    hipLaunchKernelGGL(k_sh_propose, dim3(nblk(n, kShTile), c->nl), dim3(256), 0, c->stream, S, seed, s0, n, c->hits,
+                       c->sh_queue, qcap, c->sh_cnt, ctr);
+    if (ev0 >= 0) ev_record(c, ev0);
+    hipLaunchKernelGGL(k_sh_trace, dim3(nblk(n, 256), c->nl), dim3(256), 0, c->stream, S, seed, s0, c->hits,
+                       c->sh_queue, qcap, c->sh_cnt, c->vis, ctr);
+    if (ev1 >= 0) ev_record(c, ev1);
+}
 // camera hit records and cleared visibility masks of samples [s0, s0 + n)
 static void camera_pass(fr_ctx *c, const Scene &S, uint64_t seed, int spp, long long s0, long long n,
                         unsigned long long *ctr) {
@@ -2315,7 +2409,7 @@ int fr_create(const fr_model_desc *m, const fr_scene_desc *s, uint32_t flags, fr
         R(dalloc(c, &c->tbl_edge, (size_t)(1 + c->nl) * c->E)) || R(dalloc(c, &c->tbl_prefix, (size_t)(1 + c->nl) * c->E)) ||
         R(dalloc(c, &c->tbl_n, (size_t)(1 + c->nl))) || R(dalloc(c, &c->tbl_Q, (size_t)(1 + c->nl))) ||
         R(dalloc(c, &c->tbl_guide, (size_t)(1 + c->nl) * (c->E + 1))) ||
-        R(dalloc(c, &c->es_wmax, (size_t)(1 + c->nl))) ||
+        R(dalloc(c, &c->es_wmax, (size_t)(1 + c->nl))) || R(dalloc(c, &c->sh_cnt, (size_t)c->nl)) ||
         R(dalloc(c, &c->es_csum, (size_t)(1 + c->nl) * nblk(c->E, kEsChunk))) ||
         R(dalloc(c, &c->es_ccnt, (size_t)(1 + c->nl) * nblk(c->E, kEsChunk))) || R(dalloc(c, &c->edge_rec, (size_t)5 * c->E)) ||
         R(dalloc(c, &c->ctr, (size_t)kCtrPerKern * kNumKern)) || R(dalloc(c, &c->sec_n, 1)) ||
@@ -2470,6 +2564,14 @@ int fr_render(fr_ctx *c, const fr_params *p, uint64_t seed, int32_t spp, float *
         HIPCK(c, hipMalloc((void **)&c->vis, rec * sizeof(unsigned long long)));
         c->rec_cap = rec;
     }
+    // the shadow-ray queue has its own capacity: the batched path enlarges
+    // the hit records (rec_cap) without it
+    if (rec > c->sh_cap) {
+        if (c->sh_queue) (void)hipFree(c->sh_queue);
+        c->sh_queue = nullptr; c->sh_cap = 0;
+        HIPCK(c, hipMalloc((void **)&c->sh_queue, rec * c->nl * sizeof(uint32_t)));
+        c->sh_cap = rec;
+    }
     size_t sec = (size_t)std::min(N, kSecSub) * c->nl;
     if (sec > c->sec_cap) {
         if (c->sec_list) (void)hipFree(c->sec_list);
@@ -2517,10 +2619,7 @@ int fr_render(fr_ctx *c, const fr_params *p, uint64_t seed, int32_t spp, float *
         ev_record(c, 8 + 2 * kKernCamera);
         camera_pass(c, S, seed, spp, s0, n, c->ctr + kCtrPerKern * kKernCamera);
         ev_record(c, 9 + 2 * kKernCamera);
-        ev_record(c, 8 + 2 * kKernShadow);
-        hipLaunchKernelGGL(k_fwd_shadow, dim3(nblk(n, kShTile), c->nl), dim3(256), 0, c->stream, S, seed, s0, n,
-                           c->hits, c->vis, c->ctr + kCtrPerKern * kKernShadow);
-        ev_record(c, 9 + 2 * kKernShadow);
+        shadow_pass(c, S, seed, s0, n, c->ctr + kCtrPerKern * kKernShadow, 8 + 2 * kKernShadow, 9 + 2 * kKernShadow);
         ev_record(c, 8 + 2 * kKernShade);
         hipLaunchKernelGGL(k_fwd_shade, dim3(nblk(n, 256)), dim3(256), lds, c->stream, S, seed, spp, s0, n,
                            c->hits, c->vis, c->samples, c->ctr + kCtrPerKern * kKernShade);
@@ -2561,8 +2660,7 @@ int fr_backward(fr_ctx *c, const float *dLdI, const fr_grads *g) {
         long long n = std::min(kChunk, N - s0);
         if (!c->records_valid) {   // recompute this chunk's hit records and visibility
             camera_pass(c, S, c->last_seed, c->last_spp, s0, n, c->ctr + kCtrPerKern * kKernAdj);
-            hipLaunchKernelGGL(k_fwd_shadow, dim3(nblk(n, kShTile), c->nl), dim3(256), 0, c->stream, S, c->last_seed,
-                               s0, n, c->hits, c->vis, c->ctr + kCtrPerKern * kKernAdj);
+            shadow_pass(c, S, c->last_seed, s0, n, c->ctr + kCtrPerKern * kKernAdj);
         }
         ev_record(c, 8 + 2 * kKernAdj);
         if (c->terms & FR_TERM_INTERIOR)
@@ -2726,7 +2824,7 @@ void fr_destroy(fr_ctx *c) {
                     c->lgeom, c->sorted_tri, c->leaf_node, c->right, c->escape, c->subs, c->height, c->top, c->top_off, c->nodes, c->tris,
                     c->vmodel, c->vm_d, c->pos, c->nrm, c->nlen, c->alb, c->ew, c->tbl_edge, c->tbl_prefix, c->tbl_n,
                     c->tbl_Q, c->tbl_guide, c->es_wmax, c->es_csum, c->es_ccnt, c->edge_rec, c->samples, c->ctr, c->g_light, c->g_spec, c->g_pos, c->g_nrm, c->g_alb, c->g_N,
-                    c->g_vert, c->g_m, c->partial, c->loss_partial, c->hits, c->vis, c->pe_q, c->pe_cell_n, c->pe_rec, c->sec_list, c->sec_n, c->pe_samples, c->pe_hits,
+                    c->g_vert, c->g_m, c->partial, c->loss_partial, c->hits, c->vis, c->sh_queue, c->sh_cnt, c->pe_q, c->pe_cell_n, c->pe_rec, c->sec_list, c->sec_n, c->pe_samples, c->pe_hits,
                     c->pe_f, c->pe_vis, c->lb.key[0], c->lb.key[1], c->lb.val[0], c->lb.val[1], c->lb.hist,
                     c->lb.bounds, c->lb.child, c->lb.parent, c->lb.first, c->lb.last, c->lb.pre, c->lb.arrive, c->lb.box, c->lb.roots, c->lb.n_roots, c->lb.top_idx, c->lb.n_top};
     for (void *p : ptrs) if (p) (void)hipFree(p);

@@ -67,7 +67,7 @@ class fr_stats_t(C.Structure):
                 ("ms_kernel", C.c_float * 6)]
 
 
-KERNELS = ("k_cam", "k_fwd_shadow", "k_fwd_shade", "k_render_adj", "k_edge_primary", "k_edge_secondary")
+KERNELS = ("k_cam", "k_sh_trace", "k_fwd_shade", "k_render_adj", "k_edge_primary", "k_edge_secondary")
 
 
 class fr_launch(C.Structure):
