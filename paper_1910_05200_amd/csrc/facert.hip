@@ -13,7 +13,7 @@
 //                    creation)
 //   k_edge_weights   camera-silhouette and per-light shadow-candidate edges
 //   k_edge_scan      integer CDFs of the edge weights (one block per table)
-//   k_cam_init, k_cam_raster, k_cam_resolve, k_fwd_shadow, k_fwd_shade
+//   k_cam_init, k_cam_raster, k_cam_resolve, k_sh_propose, k_sh_trace, k_fwd_shade
 //                    Monte-Carlo estimator F (Optimization paragraph): hit
 //                    records, compacted shadow rays, Cook-Torrance shading
 //   k_pixel_mean     fixed-order mean of each pixel's samples
@@ -526,10 +526,12 @@ __device__ inline void flush_work(unsigned long long *ctr, const Work &w) {
 //   camera        jittered pinhole ray, closest hit -> 16-byte hit record
 //                 (k_cam_* below; the batched path walks the tree per
 //                 sample, fwd_camera_body);
-//   k_fwd_shadow  one block per (tile of samples, light), the light on the
-//                 grid's y axis so that a wave traces neighbouring samples
-//                 toward the same light: horizon test, compaction, shadow
-//                 ray, one bit per light in the sample's visibility mask;
+//   shadow rays   per (sample, light): horizon test, shadow ray, one bit
+//                 per light in the sample's visibility mask (k_sh_propose
+//                 and k_sh_trace below; the batched path runs the fused
+//                 fwd_shadow_body: one block per (tile, light), the light on
+//                 the grid's y axis so that a wave traces neighbouring
+//                 samples toward the same light, compaction in LDS);
 //   k_fwd_shade   one lane per sample: shading of the visible lights (no
 //                 traversal).
 // The adjoint and the shadow-boundary kernels read the same records; when a
