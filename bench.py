@@ -177,7 +177,7 @@ def bench_batch(args):
         ms_seq = timed(sequential, max(2, args.steps // 4))
     k_sh = facert.KERNELS.index("k_sh_trace")
     ops_sh = sum(st["kernel_box_tests"][k_sh] * OPS_BOX + st["kernel_tri_tests"][k_sh] * OPS_TRI for st in stats)
-    ms_sh = tm["fwd_shadow"]
+    ms_sh = tm["sh_trace"]
     achieved = ops_sh / (ms_sh * 1e-3) / 1e12
     V = [m.n_vertices for m, *_ in inst]
     out = {
@@ -201,10 +201,9 @@ def bench_batch(args):
                    "ms_kinds": {k: round(v, 3) for k, v in tm.items() if v > 0.05 and k not in ("render", "backward")},
                    "tuned": {k: {"mode": ["flat", "xcd"][v[0][0]], "tile": v[0][1], "ms": round(v[1], 3)}
                              for k, v in tuned.items()}},
-        "roofline": {"bound": "alu", "kernel": "fwd_shadow (batched)", "achieved": achieved, "peak": PEAK_VALU,
+        "roofline": {"bound": "alu", "kernel": "sh_trace (batched)", "achieved": achieved, "peak": PEAK_VALU,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_VALU,
-                     "traffic": profiled_traffic(f"k_multi_KShadow_{tuned.get('fwd_shadow', ((0, 512),))[0][1]}",
-                                                 "batch"),
+                     "traffic": profiled_traffic("k_multi_KShTrace", "batch"),
                      "ops_per_launch": ops_sh, "ms_per_launch": ms_sh},
     }
     if not args.no_cpu_baseline:

@@ -247,16 +247,16 @@ void fr_destroy(fr_ctx *ctx);
  * Launch modes per kernel kind (kinds 0 .. fr_batch_num_kinds() - 1, named
  * by fr_batch_kind_name): FR_LAUNCH_FLAT, one block per tile, the tiles in
  * order; FR_LAUNCH_XCD, one block per tile, the tiles dealt to the eight
- * XCDs in contiguous eighths.  The shadow-ray kinds also take a tile size
- * (samples per block: 256 or 512).  fr_batch_tune picks them by
- * measurement. */
+ * XCDs in contiguous eighths.  The kinds that compact rays per (tile,
+ * light) also take a tile size (samples per block: 256 or 512).
+ * fr_batch_tune picks them by measurement. */
 typedef struct fr_batch fr_batch;
 
 #define FR_LAUNCH_FLAT 0
 #define FR_LAUNCH_XCD 1
 typedef struct {
     int32_t mode;                    /* FR_LAUNCH_*                            */
-    int32_t tile;                    /* shadow-ray kinds (fwd_shadow,
+    int32_t tile;                    /* compacting kinds (sh_propose,
                                         edge_secondary, edge_primary_vis): 256
                                         or 512; 0 for the others               */
 } fr_launch;

@@ -528,10 +528,7 @@ __device__ inline void flush_work(unsigned long long *ctr, const Work &w) {
 //                 sample, fwd_camera_body);
 //   shadow rays   per (sample, light): horizon test, shadow ray, one bit
 //                 per light in the sample's visibility mask (k_sh_propose
-//                 and k_sh_trace below; the batched path runs the fused
-//                 fwd_shadow_body: one block per (tile, light), the light on
-//                 the grid's y axis so that a wave traces neighbouring
-//                 samples toward the same light, compaction in LDS);
+//                 and k_sh_trace below);
 //   k_fwd_shade   one lane per sample: shading of the visible lights (no
 //                 traversal).
 // The adjoint and the shadow-boundary kernels read the same records; when a
@@ -686,10 +683,9 @@ __global__ __launch_bounds__(256) void k_cam_resolve(Scene S, long long n, HitRe
     flush_count(ctr, 0, n_cam);
 }
 
-// Shadow rays are compacted before they are traced: a block takes a tile of
-// kShTile consecutive samples for one light, its lanes run the horizon test
-// and append the rays that need tracing to a list in LDS (one LDS atomic per
-// wave), and the block's waves then trace the list 64 entries at a time.
+// Rays are compacted before they are traced: a block takes a tile of
+// consecutive samples for one light, its lanes run the horizon test and
+// append the rays that need tracing to a list (one LDS atomic per wave).
 // About a third of the (sample, light) pairs need a ray at the paper's
 // framing (camera misses and lights below the horizon need none), so
 // tracing in place would leave two lanes in three idle.  The tile size is a
@@ -706,65 +702,6 @@ __device__ __forceinline__ int lanes_below(unsigned long long m) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0));
 }
 
-template <int TS>
-__device__ __forceinline__ void fwd_shadow_body(const Scene &S, uint64_t seed, long long s0, long long n,
-        const HitRec *__restrict__ hits, unsigned long long *__restrict__ vis, unsigned long long *ctr, int bx, int j) {
-    __shared__ float4 q_o[TS];   // origin p, hit triangle
-    __shared__ float4 q_d[TS];   // y - p, tile-local sample index
-    __shared__ int q_n;
-    if (threadIdx.x == 0) q_n = 0;
-    __syncthreads();
-    const long long base = (long long)bx * TS;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    uint32_t n_sh = 0;
-    Work wk;
-    const float *g = S.lgeom + 12 * j;
-    Light L;
-    L.c = mk(g[0], g[1], g[2]); L.e1 = mk(g[3], g[4], g[5]); L.e2 = mk(g[6], g[7], g[8]);
-    const v3 cam = mk(S.cam_x, S.cam_y, S.cam_z);
-    for (int k = 0; k < TS; k += 256) {
-        const int li = k + (int)threadIdx.x;
-        const long long i = base + li;
-        bool need = false;
-        v3 p, dd;
-        int tri = -1;
-        if (i < n) {
-            HitRec rec = hits[i];
-            if (rec.tri >= 0) {
-                Hit h = hit_of(rec);
-                SurfDec sd;
-                surf_decide(S, cam, h, sd);
-                LightRng rng(seed, (uint32_t)(s0 + i), 0, 2);
-                float u, v;
-                rng.get(j, u, v);
-                v3 y = light_point(L, u, v);
-                if (above(sd, y)) { need = true; p = sd.p; dd = y - sd.p; tri = h.tri; }
-            }
-        }
-        unsigned long long m = __ballot(need);
-        int wbase = 0;
-        if (lane == 0 && m) wbase = atomicAdd(&q_n, __popcll(m));
-        wbase = __shfl(wbase, 0);
-        if (need) {
-            int slot = wbase + lanes_below(m);
-            q_o[slot] = make_float4(p.x, p.y, p.z, __int_as_float(tri));
-            q_d[slot] = make_float4(dd.x, dd.y, dd.z, __int_as_float(li));
-            ++n_sh;
-        }
-    }
-    __syncthreads();
-    const int nq = q_n;
-    for (int e = wave * 64 + lane; e - lane < nq; e += 256) {
-        if (e < nq) {
-            float4 o4 = q_o[e], d4 = q_d[e];
-            if (!trace_any(S, mk(o4.x, o4.y, o4.z), mk(d4.x, d4.y, d4.z), __float_as_int(o4.w), wk))
-                atomicOr(&vis[base + __float_as_int(d4.w)], 1ull << j);
-        }
-    }
-    flush_count(ctr, 1, n_sh);
-    flush_work(ctr, wk);
-}
-
 // Single context: the shadow rays in two kernels.  After a fused block's
 // compaction only about a third of its lanes have a ray (most pairs fail
 // the horizon test), so most of its waves sit idle while the rest trace.
@@ -774,8 +711,8 @@ __device__ __forceinline__ void fwd_shadow_body(const Scene &S, uint64_t seed, l
 //                 counter);
 //   k_sh_trace    one lane per queued ray, rebuilt from the sample's hit
 //                 record and light sample as k_sh_propose built it, traced.
-// Every resident wave of k_sh_trace traces.  The batched path keeps the
-// fused kernel.
+// Every resident wave of k_sh_trace traces.  The batched path runs the same
+// bodies (sh_propose_body with a tile of 256 or 512 samples).
 __device__ __forceinline__ bool sh_ray(const Scene &S, const Light &L, uint64_t seed, long long s0, long long i,
                                        const HitRec *__restrict__ hits, int j, v3 &p, v3 &dd, int &tri) {
     const HitRec rec = hits[i];
@@ -797,19 +734,20 @@ __device__ __forceinline__ Light light_geom(const Scene &S, int j) {
     L.c = mk(g[0], g[1], g[2]); L.e1 = mk(g[3], g[4], g[5]); L.e2 = mk(g[6], g[7], g[8]);
     return L;
 }
-__global__ __launch_bounds__(256) void k_sh_propose(Scene S, uint64_t seed, long long s0, long long n,
+template <int TS>
+__device__ __forceinline__ void sh_propose_body(const Scene &S, uint64_t seed, long long s0, long long n,
         const HitRec *__restrict__ hits, uint32_t *__restrict__ queue, uint32_t qcap, uint32_t *__restrict__ cnt,
-        unsigned long long *ctr) {
-    __shared__ uint32_t q[kShTile];
+        unsigned long long *ctr, int bx, int j) {
+    __shared__ uint32_t q[TS];
     __shared__ int q_n;
     __shared__ uint32_t q_base;
-    const int j = blockIdx.y, lane = threadIdx.x & 63;
+    const int lane = threadIdx.x & 63;
     if (threadIdx.x == 0) q_n = 0;
     __syncthreads();
     const Light L = light_geom(S, j);
-    const long long base = (long long)blockIdx.x * kShTile;
+    const long long base = (long long)bx * TS;
     uint32_t n_sh = 0;
-    for (int k = 0; k < kShTile; k += 256) {
+    for (int k = 0; k < TS; k += 256) {
         const int li = k + (int)threadIdx.x;
         const long long i = base + li;
         v3 p, dd;
@@ -828,12 +766,17 @@ __global__ __launch_bounds__(256) void k_sh_propose(Scene S, uint64_t seed, long
     for (int e = threadIdx.x; e < nq; e += 256) queue[(size_t)j * qcap + q_base + e] = q[e];
     flush_count(ctr, 1, n_sh);
 }
-__global__ __launch_bounds__(256) void k_sh_trace(Scene S, uint64_t seed, long long s0,
+__global__ __launch_bounds__(256) void k_sh_propose(Scene S, uint64_t seed, long long s0, long long n,
+        const HitRec *__restrict__ hits, uint32_t *__restrict__ queue, uint32_t qcap, uint32_t *__restrict__ cnt,
+        unsigned long long *ctr) {
+    sh_propose_body<kShTile>(S, seed, s0, n, hits, queue, qcap, cnt, ctr, blockIdx.x, blockIdx.y);
+}
+__device__ __forceinline__ void sh_trace_body(const Scene &S, uint64_t seed, long long s0,
         const HitRec *__restrict__ hits, const uint32_t *__restrict__ queue, uint32_t qcap,
-        const uint32_t *__restrict__ cnt, unsigned long long *__restrict__ vis, unsigned long long *ctr) {
-    const int j = blockIdx.y;
-    const uint32_t e = blockIdx.x * 256 + threadIdx.x;
-    if (blockIdx.x * 256 >= cnt[j]) return;   // the whole block is past the queue
+        const uint32_t *__restrict__ cnt, unsigned long long *__restrict__ vis, unsigned long long *ctr, int bx,
+        int j) {
+    const uint32_t e = bx * 256 + threadIdx.x;
+    if ((uint32_t)bx * 256 >= cnt[j]) return;   // the whole block is past the queue
     Work wk;
     if (e < cnt[j]) {
         const uint32_t i = queue[(size_t)j * qcap + e];
@@ -843,6 +786,11 @@ __global__ __launch_bounds__(256) void k_sh_trace(Scene S, uint64_t seed, long l
             atomicOr(&vis[i], 1ull << j);
     }
     flush_work(ctr, wk);
+}
+__global__ __launch_bounds__(256) void k_sh_trace(Scene S, uint64_t seed, long long s0,
+        const HitRec *__restrict__ hits, const uint32_t *__restrict__ queue, uint32_t qcap,
+        const uint32_t *__restrict__ cnt, unsigned long long *__restrict__ vis, unsigned long long *ctr) {
+    sh_trace_body(S, seed, s0, hits, queue, qcap, cnt, vis, ctr, blockIdx.x, blockIdx.y);
 }
 
 __device__ __forceinline__ void fwd_shade_body(const Scene &S, uint64_t seed, int spp, long long s0, long long n,

@@ -58,6 +58,8 @@ struct Inst {
     LbvhBufs lb;
     HitRec *hits;
     unsigned long long *vis;
+    uint32_t *sh_queue, *sh_cnt;      // shadow-ray queue [nl][sh_qcap] and its lengths [nl]
+    uint32_t sh_qcap;
     float *samples;
     unsigned long long *ctr;
     uint32_t *sec_list, *sec_n;
@@ -89,14 +91,15 @@ __global__ __launch_bounds__(256) void k_put_dyn(DynBlob b, Inst *tab, int first
 // ---- kernel kinds: the instance's arguments for each body ---------------
 enum {
     bkBlend, bkPose, bkNormals, bkLbvhInit, bkBounds, bkMorton, bkSortHist, bkScan, bkSortScatter, bkKarras,
-    bkLayout, bkBoxes, bkBoxesTop, bkEdgeWeights, bkEdgeScan, bkZeroFwd, bkCamera, bkShadow, bkShade, bkPixelMean,
+    bkLayout, bkBoxes, bkBoxesTop, bkEdgeWeights, bkEdgeScan, bkZeroFwd, bkCamera, bkShPropose, bkShTrace, bkShade,
+    bkPixelMean,
     bkZeroBwd, bkAdj, bkSecondary, bkSecValue, bkPrimarySetup, bkPrimaryVis, bkPrimaryShade, bkPrimaryScatter,
     bkNormalAdj, bkChainGather, bkParamPartial, bkParamFinal, bkGradOut, bkNum
 };
 static const char *const kKindName[bkNum] = {
     "blend", "pose", "normals", "lbvh_init", "lbvh_bounds", "lbvh_morton", "sort_hist", "sort_scan", "sort_scatter",
     "lbvh_karras", "lbvh_layout", "lbvh_boxes", "lbvh_boxes_top", "edge_weights", "edge_scan", "zero_fwd",
-    "fwd_camera", "fwd_shadow", "fwd_shade", "pixel_mean", "zero_bwd", "render_adj", "edge_secondary",
+    "fwd_camera", "sh_propose", "sh_trace", "fwd_shade", "pixel_mean", "zero_bwd", "render_adj", "edge_secondary",
     "edge_secondary_value", "edge_primary_setup", "edge_primary_vis", "edge_primary_shade", "edge_primary_scatter",
     "normal_adj", "chain_gather", "param_partial", "param_final", "grad_out"};
 
@@ -145,12 +148,18 @@ FR_KIND(KEdgeScan, 1024) {
 }};
 FR_KIND(KZeroFwd, 64) {
     for (int e = (int)threadIdx.x; e < 8 * kCtrSpread * kKernAdj; e += 64) I.ctr[e * kCtrPad] = 0ull;
+    for (int e = (int)threadIdx.x; e < I.S.nl; e += 64) I.sh_cnt[e] = 0u;
 }};
 FR_KIND(KCamera, 256) {
     fwd_camera_body(I.S, I.d.seed, I.d.spp, 0, I.N, I.hits, I.vis, I.ctr + kCtrPerKern * kKernCamera, bx);
 }};
-template <int TS> FR_KIND(KShadow, 256) {
-    fwd_shadow_body<TS>(I.S, I.d.seed, 0, I.N, I.hits, I.vis, I.ctr + kCtrPerKern * kKernShadow, bx, by);
+template <int TS> FR_KIND(KShPropose, 256) {
+    sh_propose_body<TS>(I.S, I.d.seed, 0, I.N, I.hits, I.sh_queue, I.sh_qcap, I.sh_cnt,
+                        I.ctr + kCtrPerKern * kKernShadow, bx, by);
+}};
+FR_KIND(KShTrace, 256) {
+    sh_trace_body(I.S, I.d.seed, 0, I.hits, I.sh_queue, I.sh_qcap, I.sh_cnt, I.vis, I.ctr + kCtrPerKern * kKernShadow,
+                  bx, by);
 }};
 FR_KIND(KShade, 256) {
     fwd_shade_body(I.S, I.d.seed, I.d.spp, 0, I.N, I.hits, I.vis, I.samples, I.ctr + kCtrPerKern * kKernShade, bx);
@@ -253,9 +262,9 @@ __global__ __launch_bounds__(K::kThreads) void k_multi(const Inst *__restrict__ 
 
 static const int kTiles[2] = {256, 512};
 
-static bool kind_tiled(int k) { return k == bkShadow || k == bkSecondary || k == bkPrimaryVis; }
+static bool kind_tiled(int k) { return k == bkShPropose || k == bkSecondary || k == bkPrimaryVis; }
 static bool kind_tunable(int k) {
-    return k == bkCamera || k == bkShadow || k == bkShade || k == bkAdj || k == bkSecondary || k == bkSecValue ||
+    return k == bkCamera || k == bkShPropose || k == bkShTrace || k == bkShade || k == bkAdj || k == bkSecondary || k == bkSecValue ||
            k == bkPrimarySetup || k == bkPrimaryVis || k == bkPrimaryShade;
 }
 
@@ -336,7 +345,8 @@ static void kind_grid(const fr_batch *b, int k, int i, int &gx, int &gy) {
     case bkEdgeWeights: gx = (int)nblk(c->E, 256); break;
     case bkEdgeScan: gx = 1 + nl; break;
     case bkCamera: case bkShade: case bkAdj: gx = (int)nblk(N, 256); break;
-    case bkShadow: case bkSecondary: gx = (int)nblk(N, ts); gy = nl; break;
+    case bkShPropose: case bkSecondary: gx = (int)nblk(N, ts); gy = nl; break;
+    case bkShTrace: gx = (int)nblk(N, 256); gy = nl; break;
     case bkPixelMean: case bkPrimarySetup: case bkPrimaryScatter: gx = (int)nblk(M, 256); break;
     case bkZeroBwd: gx = (int)nblk(std::max({3 * V, rr, 3 * nl, 8 * kCtrSpread * kNumKern}), 256); break;
     case bkSecValue: gx = (int)std::min<long long>(1024, std::max<long long>(1, (N + 1023) / 1024)); break;
@@ -424,9 +434,11 @@ static void launch_kind(fr_batch *b, int k, int arg = 0) {
     case bkEdgeScan: launch_k<KEdgeScan>(b, m, arg, grid, 0); break;
     case bkZeroFwd: launch_k<KZeroFwd>(b, m, arg, grid, 0); break;
     case bkCamera: launch_k<KCamera>(b, m, arg, grid, 0); break;
-    case bkShadow:
-        if (ts == 256) launch_k<KShadow<256>>(b, m, arg, grid, 0);
-        else launch_k<KShadow<512>>(b, m, arg, grid, 0);
+    case bkShPropose:
+        if (ts == 256) launch_k<KShPropose<256>>(b, m, arg, grid, 0);
+        else launch_k<KShPropose<512>>(b, m, arg, grid, 0);
+        break;
+    case bkShTrace: launch_k<KShTrace>(b, m, arg, grid, 0);
         break;
     case bkShade: launch_k<KShade>(b, m, arg, grid, b->lds_res2); break;
     case bkPixelMean: launch_k<KPixelMean>(b, m, arg, grid, 0); break;
@@ -491,7 +503,8 @@ static void seq_forward(fr_batch *b) {
     launch_kind(b, bkEdgeScan);
     launch_kind(b, bkZeroFwd);
     launch_kind(b, bkCamera);
-    launch_kind(b, bkShadow);
+    launch_kind(b, bkShPropose);
+    launch_kind(b, bkShTrace);
     launch_kind(b, bkShade);
     launch_kind(b, bkPixelMean);
 }
@@ -530,6 +543,12 @@ static int configure(fr_batch *b, const int32_t *spp) {
             BHIPCK(b, hipMalloc((void **)&c->vis, (size_t)N * sizeof(unsigned long long)));
             c->rec_cap = (size_t)N;
         }
+        if ((size_t)N > c->sh_cap) {
+            if (c->sh_queue) (void)hipFree(c->sh_queue);
+            c->sh_queue = nullptr; c->sh_cap = 0;
+            BHIPCK(b, hipMalloc((void **)&c->sh_queue, (size_t)N * c->nl * sizeof(uint32_t)));
+            c->sh_cap = (size_t)N;
+        }
         const size_t sec = (size_t)N * c->nl;     // every (sample, light) pair at most once
         if (sec > c->sec_cap) {
             if (c->sec_list) (void)hipFree(c->sec_list);
@@ -554,6 +573,7 @@ static int configure(fr_batch *b, const int32_t *spp) {
         I.nodes = c->nodes; I.tris = c->tris;
         I.lb = c->lb;
         I.hits = c->hits; I.vis = c->vis; I.samples = c->samples; I.ctr = c->ctr;
+        I.sh_queue = c->sh_queue; I.sh_cnt = c->sh_cnt; I.sh_qcap = (uint32_t)c->sh_cap;
         I.sec_list = c->sec_list; I.sec_n = c->sec_n;
         I.pe_samples = c->pe_samples; I.pe_hits = c->pe_hits; I.pe_f = c->pe_f; I.pe_vis = c->pe_vis;
         I.G = GradBufs{c->g_light, c->g_spec, c->g_pos, c->g_nrm, c->g_alb};
@@ -666,7 +686,8 @@ int fr_batch_render(fr_batch *b, const fr_params *params, const uint64_t *seeds,
     for (int i = 0; i < b->n && !stale; ++i) {   // a context's own render may have moved its scratch
         const fr_ctx *c = b->ctx[i];
         const Inst &I = b->host[i];
-        stale = c->hits != I.hits || c->vis != I.vis || c->samples != I.samples || c->sec_list != I.sec_list;
+        stale = c->hits != I.hits || c->vis != I.vis || c->samples != I.samples || c->sec_list != I.sec_list ||
+                c->sh_queue != I.sh_queue || (uint32_t)c->sh_cap != I.sh_qcap;
     }
     if (stale) {
         int r = configure(b, spp);

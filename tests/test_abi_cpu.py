@@ -66,6 +66,6 @@ def test_batch_argument_errors_without_gpu():
     assert lib.fr_batch_last_error(None) == b"no context"
     n = lib.fr_batch_num_kinds()
     names = [lib.fr_batch_kind_name(k).decode() for k in range(n)]
-    assert len(set(names)) == n and "fwd_shadow" in names and "render_adj" in names
+    assert len(set(names)) == n and "sh_trace" in names and "render_adj" in names
     assert lib.fr_batch_kind_name(n) is None and lib.fr_batch_kind_name(-1) is None
     lib.fr_batch_destroy(None)

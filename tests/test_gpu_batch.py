@@ -71,7 +71,7 @@ def _setup(torch, inst, timing=False):
 
 def _set_mode(batch, mode, tile):
     for k in batch.kinds:
-        tiled = k in ("fwd_shadow", "edge_secondary", "edge_primary_vis")
+        tiled = k in ("sh_propose", "edge_secondary", "edge_primary_vis")
         batch.set_launch(k, mode, tile if tiled else 0)
 
 
@@ -231,7 +231,7 @@ def test_batch_tune_keeps_results(torch):
     batch.render(ps, seeds, spps)
     batch.backward(dls)
     chosen = batch.tune(trials=1)
-    assert "fwd_shadow" in chosen and "render_adj" in chosen
+    assert "sh_propose" in chosen and "render_adj" in chosen
     t = batch.timing()
     assert t["render"] > 0 and t["backward"] > 0
     imgs = [x.cpu().numpy() for x in batch.render(ps, seeds, spps)]
@@ -259,12 +259,12 @@ def test_batch_relaunch_does_not_disturb_enqueued_work(torch):
         for _ in range(4):
             a = a @ a * 1e-3                             # keeps the stream busy
         first = batch.render(ps, seeds, spps)
-        batch.set_launch("fwd_shadow", 0, 256)
+        batch.set_launch("sh_propose", 0, 256)
         batch.set_launch("edge_primary_vis", 1, 256)
         second = batch.render(ps, [x + 1 for x in seeds], spps)
         for _ in range(4):
             a = a @ a * 1e-3
-        batch.set_launch("fwd_shadow", 1, 512)
+        batch.set_launch("sh_propose", 1, 512)
         third = batch.render(ps, [x + 2 for x in seeds], [x + 1 for x in spps])
         s.synchronize()
         for i, r in enumerate(rs):
@@ -301,7 +301,7 @@ def test_batch_errors(torch):
     assert e.value.code == -1
     for bad in [(0, 300), (0, 1024), (2, 512), (-1, 256)]:
         with pytest.raises(facert.FrError):
-            batch.set_launch("fwd_shadow", *bad)
+            batch.set_launch("sh_propose", *bad)
     batch.render(ps, seeds, spps)
     rs[1].render(ps[1], 9, spps[1])           # instance 1 rendered on its own since
     with pytest.raises(facert.FrError) as e:
