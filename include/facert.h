@@ -257,7 +257,7 @@ typedef struct fr_batch fr_batch;
 typedef struct {
     int32_t mode;                    /* FR_LAUNCH_*                            */
     int32_t tile;                    /* compacting kinds (sh_propose,
-                                        edge_secondary, edge_primary_vis): 256
+                                        edge_secondary, pv_propose): 256
                                         or 512; 0 for the others               */
 } fr_launch;
 

@@ -734,36 +734,50 @@ __device__ __forceinline__ Light light_geom(const Scene &S, int j) {
     L.c = mk(g[0], g[1], g[2]); L.e1 = mk(g[3], g[4], g[5]); L.e2 = mk(g[6], g[7], g[8]);
     return L;
 }
-template <int TS>
-__device__ __forceinline__ void sh_propose_body(const Scene &S, uint64_t seed, long long s0, long long n,
-        const HitRec *__restrict__ hits, uint32_t *__restrict__ queue, uint32_t qcap, uint32_t *__restrict__ cnt,
-        unsigned long long *ctr, int bx, int j) {
+// For the indices i in [bx TS, (bx + 1) TS) ∩ [0, n) that accept(i, v)
+// takes, appends their values v to queue j (row j of a [nl][qcap] array):
+// the block gathers them in LDS, reserves its slots with one atomic on
+// cnt[j], then writes them out.  Returns how many of this thread's indices
+// were taken.
+template <int TS, class Accept>
+__device__ __forceinline__ uint32_t propose_body(long long n, uint32_t *__restrict__ queue, uint32_t qcap,
+                                                 uint32_t *__restrict__ cnt, int bx, int j, Accept accept) {
     __shared__ uint32_t q[TS];
     __shared__ int q_n;
     __shared__ uint32_t q_base;
     const int lane = threadIdx.x & 63;
     if (threadIdx.x == 0) q_n = 0;
     __syncthreads();
-    const Light L = light_geom(S, j);
     const long long base = (long long)bx * TS;
-    uint32_t n_sh = 0;
+    uint32_t taken = 0;
     for (int k = 0; k < TS; k += 256) {
-        const int li = k + (int)threadIdx.x;
-        const long long i = base + li;
-        v3 p, dd;
-        int tri;
-        const bool need = i < n && sh_ray(S, L, seed, s0, i, hits, j, p, dd, tri);
+        const long long i = base + k + (int)threadIdx.x;
+        uint32_t v = 0;
+        const bool need = i < n && accept(i, v);
         const unsigned long long m = __ballot(need);
         int wbase = 0;
         if (lane == 0 && m) wbase = atomicAdd(&q_n, __popcll(m));
         wbase = __shfl(wbase, 0);
-        if (need) { q[wbase + lanes_below(m)] = (uint32_t)i; ++n_sh; }
+        if (need) { q[wbase + lanes_below(m)] = v; ++taken; }
     }
     __syncthreads();
     const int nq = q_n;
     if (threadIdx.x == 0 && nq > 0) q_base = atomicAdd(&cnt[j], (uint32_t)nq);
     __syncthreads();
     for (int e = threadIdx.x; e < nq; e += 256) queue[(size_t)j * qcap + q_base + e] = q[e];
+    return taken;
+}
+template <int TS>
+__device__ __forceinline__ void sh_propose_body(const Scene &S, uint64_t seed, long long s0, long long n,
+        const HitRec *__restrict__ hits, uint32_t *__restrict__ queue, uint32_t qcap, uint32_t *__restrict__ cnt,
+        unsigned long long *ctr, int bx, int j) {
+    const Light L = light_geom(S, j);
+    const uint32_t n_sh = propose_body<TS>(n, queue, qcap, cnt, bx, j, [&](long long i, uint32_t &v) {
+        v3 p, dd;
+        int tri;
+        v = (uint32_t)i;
+        return sh_ray(S, L, seed, s0, i, hits, j, p, dd, tri);
+    });
     flush_count(ctr, 1, n_sh);
 }
 __global__ __launch_bounds__(256) void k_sh_propose(Scene S, uint64_t seed, long long s0, long long n,
@@ -1303,8 +1317,9 @@ __global__ __launch_bounds__(256) void k_edge_secondary_value(Scene S, uint64_t 
 //                         two sides q +- offset; find the sides' camera-ray
 //                         hits (k_pe_* in the single context, a walk per
 //                         sample in the batched path);
-//   k_edge_primary_vis    one block per (tile of sides, light): horizon
-//                         test, compaction, shadow ray, visibility bit;
+//   k_pv_propose, k_pv_trace  per light, the sides whose light sample is
+//                         above their horizon, queued, then one shadow ray
+//                         per queued side and its visibility bit;
 //   k_edge_primary_shade  one lane per side: fp64 radiance of its visible
 //                         lights;
 //   k_edge_primary_scatter one lane per sample: (f+ - f-) times the boundary
@@ -1344,11 +1359,43 @@ __device__ __forceinline__ bool pe_pick(const Scene &S, uint64_t seed, int m, Pe
     return true;
 }
 
+// Samples in screen order.  The samples pick their edges at random, so sides
+// adjacent in sample order lie far apart on the face and their shadow rays
+// walk unrelated parts of the tree.  A counting sort of the samples by screen
+// tile (kPvSortPx^2 pixels; the tile of the pixel of q) gives k_pv_propose an
+// order in which the queued rays of a wave start close together; the
+// visibility bits do not depend on it.  The sort's counters (pv_aux):
+//   [nt + 1]  samples per tile, then (k_scan_u32) offsets: entry nt is the
+//             number of samples with an edge;
+//   [nt + 1]  each tile's fill counter (k_pv_order);
+//   [nl]      the light queues' lengths (k_pv_propose).
+// The samples are counted where they are picked (k_pe_pick, the batched
+// setup); k_pv_order writes each one's index at its tile's next free slot.
+constexpr int kPvSortPx = 8;
+__host__ __device__ inline int pv_tiles_x(int W) { return (W + kPvSortPx - 1) / kPvSortPx; }
+__host__ __device__ inline int pv_tiles(int W, int H) { return pv_tiles_x(W) * ((H + kPvSortPx - 1) / kPvSortPx); }
+__host__ __device__ inline int pv_aux_len(int W, int H, int nl) { return 2 * (pv_tiles(W, H) + 1) + nl; }
+__device__ __forceinline__ int pv_tile(const Scene &S, int pix) {
+    const int py = pix / S.W, px = pix - py * S.W;
+    return (py / kPvSortPx) * pv_tiles_x(S.W) + px / kPvSortPx;
+}
+__device__ __forceinline__ void pv_order_body(const Scene &S, int M, const PeSample *__restrict__ ps,
+        uint32_t *__restrict__ aux, uint32_t *__restrict__ perm, int bx) {
+    const int m = bx * 256 + threadIdx.x;
+    if (m >= M || ps[m].e < 0) return;
+    const int t = pv_tile(S, ps[m].pix);
+    perm[aux[t] + atomicAdd(&aux[pv_tiles(S.W, S.H) + 1 + t], 1u)] = (uint32_t)m;
+}
+__global__ __launch_bounds__(256) void k_pv_order(Scene S, int M, const PeSample *__restrict__ ps,
+        uint32_t *__restrict__ aux, uint32_t *__restrict__ perm) {
+    pv_order_body(S, M, ps, aux, perm, blockIdx.x);
+}
+
 // Batched path: one lane per sample traces both sides' camera rays in one
 // walk.
 __device__ __forceinline__ void edge_primary_setup_body(const Scene &S, uint64_t seed, int M,
         PeSample *__restrict__ ps_out, Hit *__restrict__ hits, unsigned long long *__restrict__ pvis,
-        unsigned long long *ctr, int bx) {
+        uint32_t *__restrict__ pv_aux, unsigned long long *ctr, int bx) {
     const int m = bx * blockDim.x + threadIdx.x;
     uint32_t n_cam = 0;
     Work wk;
@@ -1361,6 +1408,7 @@ __device__ __forceinline__ void edge_primary_setup_body(const Scene &S, uint64_t
             const v3 cam = mk(S.cam_x, S.cam_y, S.cam_z);
             trace_closest2(S, cam, camera_dir(S, px0, py0), camera_dir(S, px1, py1), hs[0], hs[1], wk);
             n_cam = 2;
+            atomicAdd(&pv_aux[pv_tile(S, ps.pix)], 1u);
         }
         ps_out[m] = ps;
         hits[2 * m] = hs[0];
@@ -1431,7 +1479,7 @@ __global__ __launch_bounds__(256) void k_pe_tri_fill(Scene S, int ncx, const uin
         }
 }
 __global__ __launch_bounds__(256) void k_pe_pick(Scene S, uint64_t seed, int M, PeSample *__restrict__ ps_out,
-        float2 *__restrict__ q) {
+        float2 *__restrict__ q, uint32_t *__restrict__ pv_aux) {
     const int m = blockIdx.x * blockDim.x + threadIdx.x;
     if (m >= M) return;
     PeSample ps;
@@ -1439,6 +1487,7 @@ __global__ __launch_bounds__(256) void k_pe_pick(Scene S, uint64_t seed, int M, 
     if (pe_pick(S, seed, m, ps, px[0], py[0], px[1], py[1])) {
         q[2 * m] = make_float2(px[0], py[0]);
         q[2 * m + 1] = make_float2(px[1], py[1]);
+        atomicAdd(&pv_aux[pv_tile(S, ps.pix)], 1u);
     }
     ps_out[m] = ps;
 }
@@ -1524,70 +1573,64 @@ __device__ __forceinline__ bool pe_light(const Scene &S, uint64_t seed, const Pe
     return above(sd, y);
 }
 
-// k_edge_primary_vis: one block per (tile of kPvTile sides, light):
-// horizon tests, compaction into an LDS list, one shadow ray per entry, one
-// visibility bit per light in the side's mask.  k_edge_primary_shade: one
-// lane per side, the fp64 radiance of its visible lights summed in light
-// order (no atomics; the fp64 shading registers stay out of the traversal
-// kernel).
+// The sides' shadow rays in two kernels, as the pixel samples' (most sides
+// trace nothing: the side off the face has no hit, and about half of the
+// rest have the light below their horizon):
+//   k_pv_propose  one block per (tile of kPvTile sides, light): the horizon
+//                 test; the accepted sides' indices go to the light's queue;
+//   k_pv_trace    one lane per queued side, its ray rebuilt as k_pv_propose
+//                 built it, traced; a clear path sets the light's bit in the
+//                 side's mask.
+// k_edge_primary_shade: one lane per side, the fp64 radiance of its visible
+// lights summed in light order (no atomics; the fp64 shading registers stay
+// out of the traversal kernel).
+// k_pv_propose walks the sides in screen order: position k is side k & 1 of
+// sample perm[k >> 1]; the queue holds side indices.
 template <int TS>
-__device__ __forceinline__ void edge_primary_vis_body(const Scene &S, uint64_t seed, int M,
-        const PeSample *__restrict__ ps_in, const Hit *__restrict__ hits, unsigned long long *__restrict__ pvis,
-        unsigned long long *ctr, int bx, int j) {
-    __shared__ Light Ls[kMaxLights];
-    __shared__ float4 q_o[TS];   // origin p, hit triangle
-    __shared__ float4 q_d[TS];   // y - p, side index within the tile
-    __shared__ int q_n;
-    for (int k = threadIdx.x; k < S.nl; k += blockDim.x) {
-        const float *g = S.lgeom + 12 * k;
-        Light L;
-        L.c = mk(g[0], g[1], g[2]); L.e1 = mk(g[3], g[4], g[5]); L.e2 = mk(g[6], g[7], g[8]);
-        Ls[k] = L;
-    }
-    if (threadIdx.x == 0) q_n = 0;
-    __syncthreads();
-    const int base = bx * TS;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const Light &L = Ls[j];
-    uint32_t n_sh = 0;
-    Work wk;
-    for (int k = 0; k < TS; k += 256) {
-        const int li = k + (int)threadIdx.x;
-        bool need = false;
-        v3 p, dd;
-        int tri = -1;
-        if (base + li < 2 * M) {
-            v3 o, d, y; Hit h; SurfDec sd;
-            need = pe_light(S, seed, ps_in, hits, L, j, base + li, o, d, h, sd, y);
-            if (need) { p = sd.p; dd = y - sd.p; tri = h.tri; }
-        }
-        unsigned long long m = __ballot(need);
-        int wbase = 0;
-        if (lane == 0 && m) wbase = atomicAdd(&q_n, __popcll(m));
-        wbase = __shfl(wbase, 0);
-        if (need) {
-            const int slot = wbase + lanes_below(m);
-            q_o[slot] = make_float4(p.x, p.y, p.z, __int_as_float(tri));
-            q_d[slot] = make_float4(dd.x, dd.y, dd.z, __int_as_float(li));
-            ++n_sh;
-        }
-    }
-    __syncthreads();
-    const int nq = q_n;
-    for (int e = wave * 64 + lane; e - lane < nq; e += 256) {
-        if (e < nq) {
-            const float4 o4 = q_o[e], d4 = q_d[e];
-            if (!trace_any(S, mk(o4.x, o4.y, o4.z), mk(d4.x, d4.y, d4.z), __float_as_int(o4.w), wk))
-                atomicOr(&pvis[base + __float_as_int(d4.w)], 1ull << j);
-        }
-    }
+__device__ __forceinline__ void pv_propose_body(const Scene &S, uint64_t seed, int M,
+        const PeSample *__restrict__ ps_in, const Hit *__restrict__ hits, const uint32_t *__restrict__ perm,
+        uint32_t *__restrict__ aux, uint32_t *__restrict__ queue, uint32_t qcap, unsigned long long *ctr, int bx,
+        int j) {
+    const Light L = light_geom(S, j);
+    const int nt = pv_tiles(S.W, S.H);
+    const long long n = 2 * (long long)aux[nt];   // sides of the samples with an edge
+    const uint32_t n_sh = propose_body<TS>(n, queue, qcap, aux + 2 * (nt + 1), bx, j, [&](long long k, uint32_t &v) {
+        v3 o, d, y;
+        Hit h;
+        SurfDec sd;
+        const int ms = 2 * (int)perm[k >> 1] + (int)(k & 1);
+        v = (uint32_t)ms;
+        return pe_light(S, seed, ps_in, hits, L, j, ms, o, d, h, sd, y);
+    });
     flush_count(ctr, 2, n_sh);
+}
+__global__ __launch_bounds__(256) void k_pv_propose(Scene S, uint64_t seed, int M,
+        const PeSample *__restrict__ ps_in, const Hit *__restrict__ hits, const uint32_t *__restrict__ perm,
+        uint32_t *__restrict__ aux, uint32_t *__restrict__ queue, uint32_t qcap, unsigned long long *ctr) {
+    pv_propose_body<kPvTile>(S, seed, M, ps_in, hits, perm, aux, queue, qcap, ctr, blockIdx.x, blockIdx.y);
+}
+__device__ __forceinline__ void pv_trace_body(const Scene &S, uint64_t seed, const PeSample *__restrict__ ps_in,
+        const Hit *__restrict__ hits, const uint32_t *__restrict__ queue, uint32_t qcap,
+        const uint32_t *__restrict__ cnt, unsigned long long *__restrict__ pvis, unsigned long long *ctr, int bx,
+        int j) {
+    const uint32_t e = bx * 256 + threadIdx.x;
+    if ((uint32_t)bx * 256 >= cnt[j]) return;   // the whole block is past the queue
+    Work wk;
+    if (e < cnt[j]) {
+        const int ms = (int)queue[(size_t)j * qcap + e];
+        v3 o, d, y;
+        Hit h;
+        SurfDec sd;
+        if (pe_light(S, seed, ps_in, hits, light_geom(S, j), j, ms, o, d, h, sd, y) &&
+            !trace_any(S, sd.p, y - sd.p, h.tri, wk))
+            atomicOr(&pvis[ms], 1ull << j);
+    }
     flush_work(ctr, wk);
 }
-__global__ __launch_bounds__(256) void k_edge_primary_vis(Scene S, uint64_t seed, int M,
-        const PeSample *__restrict__ ps_in, const Hit *__restrict__ hits, unsigned long long *__restrict__ pvis,
-        unsigned long long *ctr) {
-    edge_primary_vis_body<kPvTile>(S, seed, M, ps_in, hits, pvis, ctr, blockIdx.x, blockIdx.y);
+__global__ __launch_bounds__(256) void k_pv_trace(Scene S, uint64_t seed, const PeSample *__restrict__ ps_in,
+        const Hit *__restrict__ hits, const uint32_t *__restrict__ queue, uint32_t qcap,
+        const uint32_t *__restrict__ cnt, unsigned long long *__restrict__ pvis, unsigned long long *ctr) {
+    pv_trace_body(S, seed, ps_in, hits, queue, qcap, cnt, pvis, ctr, blockIdx.x, blockIdx.y);
 }
 
 __device__ __forceinline__ void edge_primary_shade_body(const Scene &S, uint64_t seed, int M,
@@ -1949,6 +1992,8 @@ static constexpr int kNumEvents = 8 + 2 * kNumKern;
 struct fr_ctx {
     std::string err;
     hipStream_t stream = nullptr;
+    hipStream_t side = nullptr;           // the camera-silhouette term's stream (fr_backward)
+    hipEvent_t fork_ev = nullptr, join_ev = nullptr;
     uint32_t flags = 0, terms = FR_TERM_INTERIOR | FR_TERM_PRIMARY | FR_TERM_SECONDARY;
     int device = 0;
     // sizes
@@ -1989,6 +2034,9 @@ struct fr_ctx {
     bool records_valid = false;   // hits/vis hold every sample of the last render
     PeSample *pe_samples = nullptr; Hit *pe_hits = nullptr; double *pe_f = nullptr;
     unsigned long long *pe_vis = nullptr;
+    uint32_t *pv_queue = nullptr;    // [nl][2 W H] sides with a shadow ray toward each light
+    uint32_t *pv_aux = nullptr;      // [pv_aux_len]: screen-order sort counters, queue lengths
+    uint32_t *pv_perm = nullptr;     // [W H] samples in screen order
     unsigned long long *ctr = nullptr;
     // gradients scratch
     double *g_light = nullptr, *g_spec = nullptr, *g_pos = nullptr, *g_nrm = nullptr, *g_alb = nullptr;
@@ -2366,6 +2414,8 @@ int fr_create(const fr_model_desc *m, const fr_scene_desc *s, uint32_t flags, fr
         R(dalloc(c, &c->pe_samples, (size_t)c->W * c->H)) || R(dalloc(c, &c->pe_hits, 2 * (size_t)c->W * c->H)) ||
         R(dalloc(c, &c->pe_f, 6 * (size_t)c->W * c->H)) || R(dalloc(c, &c->pe_vis, 2 * (size_t)c->W * c->H)) ||
         R(dalloc(c, &c->pe_q, 2 * (size_t)c->W * c->H)) ||
+        R(dalloc(c, &c->pv_queue, 2 * (size_t)c->W * c->H * c->nl)) ||
+        R(dalloc(c, &c->pv_aux, (size_t)pv_aux_len(c->W, c->H, c->nl))) || R(dalloc(c, &c->pv_perm, (size_t)c->W * c->H)) ||
         R(dalloc(c, &c->pe_cell_n, 2 * (size_t)(c->W / kPeCell + 2) * (c->H / kPeCell + 2) + 1)) ||
         R(dalloc(c, &c->pe_rec, 3 * ((size_t)kPeRecPerTri * c->F + (size_t)(c->W / kPeCell + 2) * (c->H / kPeCell + 2)))) ||
         R(dalloc(c, &c->g_light, 3 * (size_t)c->nl)) || R(dalloc(c, &c->g_spec, (size_t)c->res * c->res)) ||
@@ -2401,6 +2451,12 @@ int fr_create(const fr_model_desc *m, const fr_scene_desc *s, uint32_t flags, fr
     (void)hipMemset(c->ctr, 0, (size_t)kCtrPerKern * kNumKern * sizeof(unsigned long long));
     if (flags & FR_TIMING)
         for (int i = 0; i < kNumEvents; ++i) (void)hipEventCreate(&c->ev[i]);
+    if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->join_ev, hipEventDisableTiming) != hipSuccess) {
+        fr_destroy(c);
+        return FR_EDEVICE;
+    }
     if (hipDeviceSynchronize() != hipSuccess) { fr_destroy(c); return FR_EDEVICE; }
     *out = c;
     return FR_OK;
@@ -2586,6 +2642,43 @@ int fr_render(fr_ctx *c, const fr_params *p, uint64_t seed, int32_t spp, float *
     return FR_OK;
 }
 
+// The camera-silhouette term on stream st (every kernel of it, between the
+// phase's events).
+static void primary_pass(fr_ctx *c, const Scene &S, const float *dLdI, hipStream_t st) {
+    if (c->flags & FR_TIMING) (void)hipEventRecord(c->ev[8 + 2 * kKernPrimary], st);
+    const size_t lds1 = (size_t)c->res * c->res * sizeof(float);
+    int M = c->W * c->H;
+    unsigned long long *pctr = c->ctr + kCtrPerKern * kKernPrimary;
+    const int ncx = c->W / kPeCell + 2, nc = ncx * (c->H / kPeCell + 2);
+    const uint32_t cap = (uint32_t)((size_t)kPeRecPerTri * c->F + nc);
+    hipLaunchKernelGGL(k_zero_u32, dim3(nblk(2 * (size_t)nc + 1, 256)), dim3(256), 0, st, c->pe_cell_n,
+                       2 * nc + 1);
+    hipLaunchKernelGGL(k_pe_tri_count, dim3(nblk(c->F, 256)), dim3(256), 0, st, S, ncx, c->pe_cell_n);
+    hipLaunchKernelGGL(k_scan_u32, dim3(1), dim3(1024), 0, st, nc + 1, c->pe_cell_n);
+    hipLaunchKernelGGL(k_pe_tri_fill, dim3(nblk(c->F, 256)), dim3(256), 0, st, S, ncx, c->pe_cell_n,
+                       c->pe_cell_n + nc + 1, c->pe_rec, cap);
+    const int pv_n = pv_aux_len(c->W, c->H, c->nl), pv_nt = pv_tiles(c->W, c->H);
+    hipLaunchKernelGGL(k_zero_u32, dim3(nblk(pv_n, 256)), dim3(256), 0, st, c->pv_aux, pv_n);
+    hipLaunchKernelGGL(k_pe_pick, dim3(nblk(M, 256)), dim3(256), 0, st, S, c->last_seed, M, c->pe_samples,
+                       c->pe_q, c->pv_aux);
+    hipLaunchKernelGGL(k_scan_u32, dim3(1), dim3(1024), 0, st, pv_nt + 1, c->pv_aux);
+    hipLaunchKernelGGL(k_pv_order, dim3(nblk(M, 256)), dim3(256), 0, st, S, M, c->pe_samples, c->pv_aux,
+                       c->pv_perm);
+    hipLaunchKernelGGL(k_pe_resolve, dim3(nblk(2 * (size_t)M, 256)), dim3(256), 0, st, S, M, ncx, nc,
+                       c->pe_samples, c->pe_q, c->pe_cell_n, c->pe_rec, cap, c->pe_hits, c->pe_vis, pctr);
+    const uint32_t pv_cap = 2 * (uint32_t)M;
+    hipLaunchKernelGGL(k_pv_propose, dim3(nblk((size_t)pv_cap, kPvTile), c->nl), dim3(256), 0, st, S,
+                       c->last_seed, M, c->pe_samples, c->pe_hits, c->pv_perm, c->pv_aux, c->pv_queue, pv_cap, pctr);
+    hipLaunchKernelGGL(k_pv_trace, dim3(nblk((size_t)pv_cap, 256), c->nl), dim3(256), 0, st, S,
+                       c->last_seed, c->pe_samples, c->pe_hits, c->pv_queue, pv_cap, c->pv_aux + 2 * (pv_nt + 1),
+                       c->pe_vis, pctr);
+    hipLaunchKernelGGL(k_edge_primary_shade, dim3(nblk((size_t)2 * M, 256)), dim3(256), lds1, st,
+                       S, c->last_seed, M, c->pe_samples, c->pe_hits, c->pe_vis, c->pe_f, pctr);
+    hipLaunchKernelGGL(k_edge_primary_scatter, dim3(nblk(M, 256)), dim3(256), 0, st,
+                       S, M, dLdI, c->pe_samples, c->pe_f, c->g_pos);
+    if (c->flags & FR_TIMING) (void)hipEventRecord(c->ev[9 + 2 * kKernPrimary], st);
+}
+
 int fr_backward(fr_ctx *c, const float *dLdI, const fr_grads *g) {
     if (!c) return FR_EINVAL;
     c->err.clear();
@@ -2606,6 +2699,17 @@ int fr_backward(fr_ctx *c, const float *dLdI, const fr_grads *g) {
     hipLaunchKernelGGL(k_zero_ctr, dim3(nblk(8 * kCtrSpread * (kNumKern - kKernAdj), 256)), dim3(256), 0, c->stream, c->ctr,
                        kKernAdj, kNumKern);
     size_t lds1 = (size_t)c->res * c->res * sizeof(float);
+    // The silhouette term reads none of the other terms' scratch and adds
+    // into the vertex gradient with atomics, as they do: it runs on the
+    // context's second stream beside them.  Its rays are too few to fill the
+    // chip, and the other terms' kernels fill what it leaves idle.
+    const bool side = (c->terms & FR_TERM_PRIMARY) != 0;
+    if (side) {
+        (void)hipEventRecord(c->fork_ev, c->stream);
+        (void)hipStreamWaitEvent(c->side, c->fork_ev, 0);
+        primary_pass(c, S, dLdI, c->side);
+        (void)hipEventRecord(c->join_ev, c->side);
+    }
     for (long long s0 = 0; s0 < N; s0 += kChunk) {
         long long n = std::min(kChunk, N - s0);
         if (!c->records_valid) {   // recompute this chunk's hit records and visibility
@@ -2630,30 +2734,7 @@ int fr_backward(fr_ctx *c, const float *dLdI, const fr_grads *g) {
             }
         ev_record(c, 9 + 2 * kKernSecondary);
     }
-    ev_record(c, 8 + 2 * kKernPrimary);
-    if (c->terms & FR_TERM_PRIMARY) {
-        int M = c->W * c->H;
-        unsigned long long *pctr = c->ctr + kCtrPerKern * kKernPrimary;
-        const int ncx = c->W / kPeCell + 2, nc = ncx * (c->H / kPeCell + 2);
-        const uint32_t cap = (uint32_t)((size_t)kPeRecPerTri * c->F + nc);
-        hipLaunchKernelGGL(k_zero_u32, dim3(nblk(2 * (size_t)nc + 1, 256)), dim3(256), 0, c->stream, c->pe_cell_n,
-                           2 * nc + 1);
-        hipLaunchKernelGGL(k_pe_tri_count, dim3(nblk(c->F, 256)), dim3(256), 0, c->stream, S, ncx, c->pe_cell_n);
-        hipLaunchKernelGGL(k_scan_u32, dim3(1), dim3(1024), 0, c->stream, nc + 1, c->pe_cell_n);
-        hipLaunchKernelGGL(k_pe_tri_fill, dim3(nblk(c->F, 256)), dim3(256), 0, c->stream, S, ncx, c->pe_cell_n,
-                           c->pe_cell_n + nc + 1, c->pe_rec, cap);
-        hipLaunchKernelGGL(k_pe_pick, dim3(nblk(M, 256)), dim3(256), 0, c->stream, S, c->last_seed, M, c->pe_samples,
-                           c->pe_q);
-        hipLaunchKernelGGL(k_pe_resolve, dim3(nblk(2 * (size_t)M, 256)), dim3(256), 0, c->stream, S, M, ncx, nc,
-                           c->pe_samples, c->pe_q, c->pe_cell_n, c->pe_rec, cap, c->pe_hits, c->pe_vis, pctr);
-        hipLaunchKernelGGL(k_edge_primary_vis, dim3(nblk((size_t)2 * M, kPvTile), c->nl), dim3(256), 0, c->stream,
-                           S, c->last_seed, M, c->pe_samples, c->pe_hits, c->pe_vis, c->ctr + kCtrPerKern * kKernPrimary);
-        hipLaunchKernelGGL(k_edge_primary_shade, dim3(nblk((size_t)2 * M, 256)), dim3(256), lds1, c->stream,
-                           S, c->last_seed, M, c->pe_samples, c->pe_hits, c->pe_vis, c->pe_f, c->ctr + kCtrPerKern * kKernPrimary);
-        hipLaunchKernelGGL(k_edge_primary_scatter, dim3(nblk(M, 256)), dim3(256), 0, c->stream,
-                           S, M, dLdI, c->pe_samples, c->pe_f, c->g_pos);
-    }
-    ev_record(c, 9 + 2 * kKernPrimary);
+    if (side) (void)hipStreamWaitEvent(c->stream, c->join_ev, 0);
     hipLaunchKernelGGL(k_normal_adj, dim3(nblk(c->V, 256)), dim3(256), 0, c->stream, c->V, c->nrm, c->nlen, c->g_nrm, c->g_N);
     hipLaunchKernelGGL(k_chain_gather, dim3(nblk(c->V, 256)), dim3(256), 0, c->stream, c->V, c->faces, c->vf_off, c->vf_idx,
                        c->pos, c->g_N, c->g_pos, c->pose, c->g_vert, c->g_m);
@@ -2775,10 +2856,13 @@ void fr_destroy(fr_ctx *c) {
                     c->vmodel, c->vm_d, c->pos, c->nrm, c->nlen, c->alb, c->ew, c->tbl_edge, c->tbl_prefix, c->tbl_n,
                     c->tbl_Q, c->tbl_guide, c->es_wmax, c->es_csum, c->es_ccnt, c->edge_rec, c->samples, c->ctr, c->g_light, c->g_spec, c->g_pos, c->g_nrm, c->g_alb, c->g_N,
                     c->g_vert, c->g_m, c->partial, c->loss_partial, c->hits, c->vis, c->sh_queue, c->sh_cnt, c->pe_q, c->pe_cell_n, c->pe_rec, c->sec_list, c->sec_n, c->pe_samples, c->pe_hits,
-                    c->pe_f, c->pe_vis, c->lb.key[0], c->lb.key[1], c->lb.val[0], c->lb.val[1], c->lb.hist,
+                    c->pe_f, c->pe_vis, c->pv_queue, c->pv_aux, c->pv_perm, c->lb.key[0], c->lb.key[1], c->lb.val[0], c->lb.val[1], c->lb.hist,
                     c->lb.bounds, c->lb.child, c->lb.parent, c->lb.first, c->lb.last, c->lb.pre, c->lb.arrive, c->lb.box, c->lb.roots, c->lb.n_roots, c->lb.top_idx, c->lb.n_top};
     for (void *p : ptrs) if (p) (void)hipFree(p);
     for (auto &e : c->ev) if (e) (void)hipEventDestroy(e);
+    if (c->side) { (void)hipStreamSynchronize(c->side); (void)hipStreamDestroy(c->side); }
+    if (c->fork_ev) (void)hipEventDestroy(c->fork_ev);
+    if (c->join_ev) (void)hipEventDestroy(c->join_ev);
     delete c;
 }
 

@@ -67,6 +67,8 @@ struct Inst {
     Hit *pe_hits;
     double *pe_f;
     unsigned long long *pe_vis;
+    uint32_t *pv_queue;               // silhouette sides' shadow-ray queue [nl][2 M]
+    uint32_t *pv_aux, *pv_perm;       // screen-order sort counters and queue lengths; samples in screen order
     GradBufs G;
     double *g_N;
     float *g_vert, *g_m;
@@ -93,14 +95,14 @@ enum {
     bkBlend, bkPose, bkNormals, bkLbvhInit, bkBounds, bkMorton, bkSortHist, bkScan, bkSortScatter, bkKarras,
     bkLayout, bkBoxes, bkBoxesTop, bkEdgeWeights, bkEdgeScan, bkZeroFwd, bkCamera, bkShPropose, bkShTrace, bkShade,
     bkPixelMean,
-    bkZeroBwd, bkAdj, bkSecondary, bkSecValue, bkPrimarySetup, bkPrimaryVis, bkPrimaryShade, bkPrimaryScatter,
+    bkZeroBwd, bkAdj, bkSecondary, bkSecValue, bkPrimarySetup, bkPvScan, bkPvOrder, bkPvPropose, bkPvTrace, bkPrimaryShade, bkPrimaryScatter,
     bkNormalAdj, bkChainGather, bkParamPartial, bkParamFinal, bkGradOut, bkNum
 };
 static const char *const kKindName[bkNum] = {
     "blend", "pose", "normals", "lbvh_init", "lbvh_bounds", "lbvh_morton", "sort_hist", "sort_scan", "sort_scatter",
     "lbvh_karras", "lbvh_layout", "lbvh_boxes", "lbvh_boxes_top", "edge_weights", "edge_scan", "zero_fwd",
     "fwd_camera", "sh_propose", "sh_trace", "fwd_shade", "pixel_mean", "zero_bwd", "render_adj", "edge_secondary",
-    "edge_secondary_value", "edge_primary_setup", "edge_primary_vis", "edge_primary_shade", "edge_primary_scatter",
+    "edge_secondary_value", "edge_primary_setup", "pv_scan", "pv_order", "pv_propose", "pv_trace", "edge_primary_shade", "edge_primary_scatter",
     "normal_adj", "chain_gather", "param_partial", "param_final", "grad_out"};
 
 #define FR_KIND(NAME, THREADS) struct NAME { static constexpr int kThreads = THREADS; \
@@ -172,6 +174,7 @@ FR_KIND(KZeroBwd, 256) {
     if (i < V3) { I.G.d_pos[i] = 0.0; I.G.d_nrm[i] = 0.0; I.G.d_alb[i] = 0.0; }
     if (i < 8 * kCtrSpread * (kNumKern - kKernAdj)) I.ctr[(8 * kCtrSpread * kKernAdj + i) * kCtrPad] = 0ull;
     if (i == 0) *I.sec_n = 0u;
+    if (i < pv_aux_len(I.S.W, I.S.H, I.S.nl)) I.pv_aux[i] = 0u;
 }};
 FR_KIND(KAdj, 256) {
     if (!(I.d.terms & FR_TERM_INTERIOR)) return;
@@ -188,11 +191,26 @@ FR_KIND(KSecValue, 256) {
 }};
 FR_KIND(KPrimarySetup, 256) {
     if (!(I.d.terms & FR_TERM_PRIMARY)) return;
-    edge_primary_setup_body(I.S, I.d.seed, I.M, I.pe_samples, I.pe_hits, I.pe_vis, I.ctr + kCtrPerKern * kKernPrimary, bx);
+    edge_primary_setup_body(I.S, I.d.seed, I.M, I.pe_samples, I.pe_hits, I.pe_vis, I.pv_aux,
+                            I.ctr + kCtrPerKern * kKernPrimary, bx);
 }};
-template <int TS> FR_KIND(KPrimaryVis, 256) {
+FR_KIND(KPvScan, 1024) {
     if (!(I.d.terms & FR_TERM_PRIMARY)) return;
-    edge_primary_vis_body<TS>(I.S, I.d.seed, I.M, I.pe_samples, I.pe_hits, I.pe_vis, I.ctr + kCtrPerKern * kKernPrimary, bx, by);
+    scan_u32_body(pv_tiles(I.S.W, I.S.H) + 1, I.pv_aux);
+}};
+FR_KIND(KPvOrder, 256) {
+    if (!(I.d.terms & FR_TERM_PRIMARY)) return;
+    pv_order_body(I.S, I.M, I.pe_samples, I.pv_aux, I.pv_perm, bx);
+}};
+template <int TS> FR_KIND(KPvPropose, 256) {
+    if (!(I.d.terms & FR_TERM_PRIMARY)) return;
+    pv_propose_body<TS>(I.S, I.d.seed, I.M, I.pe_samples, I.pe_hits, I.pv_perm, I.pv_aux, I.pv_queue,
+                        2 * (uint32_t)I.M, I.ctr + kCtrPerKern * kKernPrimary, bx, by);
+}};
+FR_KIND(KPvTrace, 256) {
+    if (!(I.d.terms & FR_TERM_PRIMARY)) return;
+    pv_trace_body(I.S, I.d.seed, I.pe_samples, I.pe_hits, I.pv_queue, 2 * (uint32_t)I.M,
+                  I.pv_aux + 2 * (pv_tiles(I.S.W, I.S.H) + 1), I.pe_vis, I.ctr + kCtrPerKern * kKernPrimary, bx, by);
 }};
 FR_KIND(KPrimaryShade, 256) {
     if (!(I.d.terms & FR_TERM_PRIMARY)) return;
@@ -262,10 +280,10 @@ __global__ __launch_bounds__(K::kThreads) void k_multi(const Inst *__restrict__ 
 
 static const int kTiles[2] = {256, 512};
 
-static bool kind_tiled(int k) { return k == bkShPropose || k == bkSecondary || k == bkPrimaryVis; }
+static bool kind_tiled(int k) { return k == bkShPropose || k == bkSecondary || k == bkPvPropose; }
 static bool kind_tunable(int k) {
     return k == bkCamera || k == bkShPropose || k == bkShTrace || k == bkShade || k == bkAdj || k == bkSecondary || k == bkSecValue ||
-           k == bkPrimarySetup || k == bkPrimaryVis || k == bkPrimaryShade;
+           k == bkPrimarySetup || k == bkPvPropose || k == bkPvTrace || k == bkPrimaryShade;
 }
 
 struct KindPlan { int off, n, total; };
@@ -319,7 +337,7 @@ static int bfail(fr_batch *b, int code, const char *fmt, ...) {
 static int kind_threads(int k) {
     switch (k) {
     case bkBlend: case bkLbvhInit: case bkZeroFwd: case bkParamFinal: return 64;
-    case bkScan: case bkBoxes: case bkBoxesTop: case bkEdgeScan: return 1024;
+    case bkScan: case bkBoxes: case bkBoxesTop: case bkEdgeScan: case bkPvScan: return 1024;
     default: return 256;
     }
 }
@@ -335,7 +353,7 @@ static void kind_grid(const fr_batch *b, int k, int i, int &gx, int &gy) {
     switch (k) {
     case bkBlend: gx = (int)nblk(V, 64); gy = 6; break;
     case bkPose: case bkNormals: case bkNormalAdj: case bkChainGather: gx = (int)nblk(V, 256); break;
-    case bkLbvhInit: case bkScan: case bkZeroFwd: gx = 1; break;
+    case bkLbvhInit: case bkScan: case bkZeroFwd: case bkPvScan: gx = 1; break;
     case bkBounds: case bkMorton: gx = (int)nblk(F, 256); break;
     case bkSortHist: case bkSortScatter: gx = c->lb.nb; break;
     case bkKarras: gx = F > 1 ? (int)nblk(F - 1, 256) : 0; break;
@@ -347,10 +365,13 @@ static void kind_grid(const fr_batch *b, int k, int i, int &gx, int &gy) {
     case bkCamera: case bkShade: case bkAdj: gx = (int)nblk(N, 256); break;
     case bkShPropose: case bkSecondary: gx = (int)nblk(N, ts); gy = nl; break;
     case bkShTrace: gx = (int)nblk(N, 256); gy = nl; break;
-    case bkPixelMean: case bkPrimarySetup: case bkPrimaryScatter: gx = (int)nblk(M, 256); break;
-    case bkZeroBwd: gx = (int)nblk(std::max({3 * V, rr, 3 * nl, 8 * kCtrSpread * kNumKern}), 256); break;
+    case bkPixelMean: case bkPrimarySetup: case bkPvOrder: case bkPrimaryScatter: gx = (int)nblk(M, 256); break;
+    case bkZeroBwd:
+        gx = (int)nblk(std::max({3 * V, rr, 3 * nl, 8 * kCtrSpread * kNumKern, pv_aux_len(c->W, c->H, nl)}), 256);
+        break;
     case bkSecValue: gx = (int)std::min<long long>(1024, std::max<long long>(1, (N + 1023) / 1024)); break;
-    case bkPrimaryVis: gx = (int)nblk(2 * (size_t)M, ts); gy = nl; break;
+    case bkPvPropose: gx = (int)nblk(2 * (size_t)M, ts); gy = nl; break;
+    case bkPvTrace: gx = (int)nblk(2 * (size_t)M, 256); gy = nl; break;
     case bkPrimaryShade: gx = (int)nblk(2 * (size_t)M, 256); break;
     case bkParamPartial: gx = rows; gy = c->nchunks; break;
     case bkParamFinal: gx = (int)nblk(rows, 64); break;
@@ -450,10 +471,13 @@ static void launch_kind(fr_batch *b, int k, int arg = 0) {
         break;
     case bkSecValue: launch_k<KSecValue>(b, m, arg, grid, b->lds_res2); break;
     case bkPrimarySetup: launch_k<KPrimarySetup>(b, m, arg, grid, 0); break;
-    case bkPrimaryVis:
-        if (ts == 256) launch_k<KPrimaryVis<256>>(b, m, arg, grid, 0);
-        else launch_k<KPrimaryVis<512>>(b, m, arg, grid, 0);
+    case bkPvPropose:
+        if (ts == 256) launch_k<KPvPropose<256>>(b, m, arg, grid, 0);
+        else launch_k<KPvPropose<512>>(b, m, arg, grid, 0);
         break;
+    case bkPvTrace: launch_k<KPvTrace>(b, m, arg, grid, 0); break;
+    case bkPvScan: launch_k<KPvScan>(b, m, arg, grid, 0); break;
+    case bkPvOrder: launch_k<KPvOrder>(b, m, arg, grid, 0); break;
     case bkPrimaryShade: launch_k<KPrimaryShade>(b, m, arg, grid, b->lds_res2); break;
     case bkPrimaryScatter: launch_k<KPrimaryScatter>(b, m, arg, grid, 0); break;
     case bkNormalAdj: launch_k<KNormalAdj>(b, m, arg, grid, 0); break;
@@ -576,6 +600,7 @@ static int configure(fr_batch *b, const int32_t *spp) {
         I.sh_queue = c->sh_queue; I.sh_cnt = c->sh_cnt; I.sh_qcap = (uint32_t)c->sh_cap;
         I.sec_list = c->sec_list; I.sec_n = c->sec_n;
         I.pe_samples = c->pe_samples; I.pe_hits = c->pe_hits; I.pe_f = c->pe_f; I.pe_vis = c->pe_vis;
+        I.pv_queue = c->pv_queue; I.pv_aux = c->pv_aux; I.pv_perm = c->pv_perm;
         I.G = GradBufs{c->g_light, c->g_spec, c->g_pos, c->g_nrm, c->g_alb};
         I.g_N = c->g_N; I.g_vert = c->g_vert; I.g_m = c->g_m; I.partial = c->partial;
         const size_t rr = (size_t)c->res * c->res;
@@ -614,7 +639,7 @@ int fr_batch_create(int32_t n, fr_ctx *const *ctx, uint32_t flags, fr_batch **ou
     b->gen.assign(n, 0);
     for (int k = 0; k < bkNum; ++k)
         b->launch[k] = fr_launch{FR_LAUNCH_FLAT, k == bkSecondary ? kSecTile
-                                                 : k == bkPrimaryVis ? kPvTile : (kind_tiled(k) ? kShTile : 0)};
+                                                 : k == bkPvPropose ? kPvTile : (kind_tiled(k) ? kShTile : 0)};
     b->stream = ctx[0]->stream;
     if (hipMalloc((void **)&b->tab, sizeof(Inst) * n) != hipSuccess) {
         fr_batch_destroy(b);

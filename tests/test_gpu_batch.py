@@ -71,7 +71,7 @@ def _setup(torch, inst, timing=False):
 
 def _set_mode(batch, mode, tile):
     for k in batch.kinds:
-        tiled = k in ("sh_propose", "edge_secondary", "edge_primary_vis")
+        tiled = k in ("sh_propose", "edge_secondary", "pv_propose")
         batch.set_launch(k, mode, tile if tiled else 0)
 
 
@@ -260,7 +260,7 @@ def test_batch_relaunch_does_not_disturb_enqueued_work(torch):
             a = a @ a * 1e-3                             # keeps the stream busy
         first = batch.render(ps, seeds, spps)
         batch.set_launch("sh_propose", 0, 256)
-        batch.set_launch("edge_primary_vis", 1, 256)
+        batch.set_launch("pv_propose", 1, 256)
         second = batch.render(ps, [x + 1 for x in seeds], spps)
         for _ in range(4):
             a = a @ a * 1e-3
