@@ -1364,27 +1364,32 @@ __device__ __forceinline__ bool pe_pick(const Scene &S, uint64_t seed, int m, Pe
 // walk unrelated parts of the tree.  A counting sort of the samples by screen
 // tile (kPvSortPx^2 pixels; the tile of the pixel of q) gives k_pv_propose an
 // order in which the queued rays of a wave start close together; the
-// visibility bits do not depend on it.  The sort's counters (pv_aux):
-//   [nt + 1]  samples per tile, then (k_scan_u32) offsets: entry nt is the
-//             number of samples with an edge;
-//   [nt + 1]  each tile's fill counter (k_pv_order);
-//   [nl]      the light queues' lengths (k_pv_propose).
+// visibility bits do not depend on it.  Each tile has kPvSortCopies
+// counters, sample m counting on copy (m / 64) mod kPvSortCopies: device
+// atomics on one word serialise, and the silhouette tiles are few.  The
+// sort's counters (pv_aux), with key = tile kPvSortCopies + copy:
+//   [(nt + 1) C]  samples per key, then (k_scan_u32) offsets: entry nt C is
+//                 the number of samples with an edge;
+//   [(nt + 1) C]  each key's fill counter (k_pv_order);
+//   [nl]          the light queues' lengths (k_pv_propose).
 // The samples are counted where they are picked (k_pe_pick, the batched
-// setup); k_pv_order writes each one's index at its tile's next free slot.
-constexpr int kPvSortPx = 8;
+// setup); k_pv_order writes each one's index at its key's next free slot.
+constexpr int kPvSortPx = 8, kPvSortCopies = 8;
 __host__ __device__ inline int pv_tiles_x(int W) { return (W + kPvSortPx - 1) / kPvSortPx; }
 __host__ __device__ inline int pv_tiles(int W, int H) { return pv_tiles_x(W) * ((H + kPvSortPx - 1) / kPvSortPx); }
-__host__ __device__ inline int pv_aux_len(int W, int H, int nl) { return 2 * (pv_tiles(W, H) + 1) + nl; }
-__device__ __forceinline__ int pv_tile(const Scene &S, int pix) {
+__host__ __device__ inline int pv_keys(int W, int H) { return (pv_tiles(W, H) + 1) * kPvSortCopies; }
+__host__ __device__ inline int pv_aux_len(int W, int H, int nl) { return 2 * pv_keys(W, H) + nl; }
+__device__ __forceinline__ int pv_key(const Scene &S, int m, int pix) {
     const int py = pix / S.W, px = pix - py * S.W;
-    return (py / kPvSortPx) * pv_tiles_x(S.W) + px / kPvSortPx;
+    const int t = (py / kPvSortPx) * pv_tiles_x(S.W) + px / kPvSortPx;
+    return t * kPvSortCopies + ((m >> 6) & (kPvSortCopies - 1));
 }
 __device__ __forceinline__ void pv_order_body(const Scene &S, int M, const PeSample *__restrict__ ps,
         uint32_t *__restrict__ aux, uint32_t *__restrict__ perm, int bx) {
     const int m = bx * 256 + threadIdx.x;
     if (m >= M || ps[m].e < 0) return;
-    const int t = pv_tile(S, ps[m].pix);
-    perm[aux[t] + atomicAdd(&aux[pv_tiles(S.W, S.H) + 1 + t], 1u)] = (uint32_t)m;
+    const int key = pv_key(S, m, ps[m].pix);
+    perm[aux[key] + atomicAdd(&aux[pv_keys(S.W, S.H) + key], 1u)] = (uint32_t)m;
 }
 __global__ __launch_bounds__(256) void k_pv_order(Scene S, int M, const PeSample *__restrict__ ps,
         uint32_t *__restrict__ aux, uint32_t *__restrict__ perm) {
@@ -1408,7 +1413,7 @@ __device__ __forceinline__ void edge_primary_setup_body(const Scene &S, uint64_t
             const v3 cam = mk(S.cam_x, S.cam_y, S.cam_z);
             trace_closest2(S, cam, camera_dir(S, px0, py0), camera_dir(S, px1, py1), hs[0], hs[1], wk);
             n_cam = 2;
-            atomicAdd(&pv_aux[pv_tile(S, ps.pix)], 1u);
+            atomicAdd(&pv_aux[pv_key(S, m, ps.pix)], 1u);
         }
         ps_out[m] = ps;
         hits[2 * m] = hs[0];
@@ -1487,7 +1492,7 @@ __global__ __launch_bounds__(256) void k_pe_pick(Scene S, uint64_t seed, int M, 
     if (pe_pick(S, seed, m, ps, px[0], py[0], px[1], py[1])) {
         q[2 * m] = make_float2(px[0], py[0]);
         q[2 * m + 1] = make_float2(px[1], py[1]);
-        atomicAdd(&pv_aux[pv_tile(S, ps.pix)], 1u);
+        atomicAdd(&pv_aux[pv_key(S, m, ps.pix)], 1u);
     }
     ps_out[m] = ps;
 }
@@ -1592,9 +1597,9 @@ __device__ __forceinline__ void pv_propose_body(const Scene &S, uint64_t seed, i
         uint32_t *__restrict__ aux, uint32_t *__restrict__ queue, uint32_t qcap, unsigned long long *ctr, int bx,
         int j) {
     const Light L = light_geom(S, j);
-    const int nt = pv_tiles(S.W, S.H);
-    const long long n = 2 * (long long)aux[nt];   // sides of the samples with an edge
-    const uint32_t n_sh = propose_body<TS>(n, queue, qcap, aux + 2 * (nt + 1), bx, j, [&](long long k, uint32_t &v) {
+    const int nk = pv_keys(S.W, S.H);
+    const long long n = 2 * (long long)aux[nk - kPvSortCopies];   // sides of the samples with an edge
+    const uint32_t n_sh = propose_body<TS>(n, queue, qcap, aux + 2 * nk, bx, j, [&](long long k, uint32_t &v) {
         v3 o, d, y;
         Hit h;
         SurfDec sd;
@@ -2657,11 +2662,11 @@ static void primary_pass(fr_ctx *c, const Scene &S, const float *dLdI, hipStream
     hipLaunchKernelGGL(k_scan_u32, dim3(1), dim3(1024), 0, st, nc + 1, c->pe_cell_n);
     hipLaunchKernelGGL(k_pe_tri_fill, dim3(nblk(c->F, 256)), dim3(256), 0, st, S, ncx, c->pe_cell_n,
                        c->pe_cell_n + nc + 1, c->pe_rec, cap);
-    const int pv_n = pv_aux_len(c->W, c->H, c->nl), pv_nt = pv_tiles(c->W, c->H);
+    const int pv_n = pv_aux_len(c->W, c->H, c->nl), pv_nk = pv_keys(c->W, c->H);
     hipLaunchKernelGGL(k_zero_u32, dim3(nblk(pv_n, 256)), dim3(256), 0, st, c->pv_aux, pv_n);
     hipLaunchKernelGGL(k_pe_pick, dim3(nblk(M, 256)), dim3(256), 0, st, S, c->last_seed, M, c->pe_samples,
                        c->pe_q, c->pv_aux);
-    hipLaunchKernelGGL(k_scan_u32, dim3(1), dim3(1024), 0, st, pv_nt + 1, c->pv_aux);
+    hipLaunchKernelGGL(k_scan_u32, dim3(1), dim3(1024), 0, st, pv_nk, c->pv_aux);
     hipLaunchKernelGGL(k_pv_order, dim3(nblk(M, 256)), dim3(256), 0, st, S, M, c->pe_samples, c->pv_aux,
                        c->pv_perm);
     hipLaunchKernelGGL(k_pe_resolve, dim3(nblk(2 * (size_t)M, 256)), dim3(256), 0, st, S, M, ncx, nc,
@@ -2670,7 +2675,7 @@ static void primary_pass(fr_ctx *c, const Scene &S, const float *dLdI, hipStream
     hipLaunchKernelGGL(k_pv_propose, dim3(nblk((size_t)pv_cap, kPvTile), c->nl), dim3(256), 0, st, S,
                        c->last_seed, M, c->pe_samples, c->pe_hits, c->pv_perm, c->pv_aux, c->pv_queue, pv_cap, pctr);
     hipLaunchKernelGGL(k_pv_trace, dim3(nblk((size_t)pv_cap, 256), c->nl), dim3(256), 0, st, S,
-                       c->last_seed, c->pe_samples, c->pe_hits, c->pv_queue, pv_cap, c->pv_aux + 2 * (pv_nt + 1),
+                       c->last_seed, c->pe_samples, c->pe_hits, c->pv_queue, pv_cap, c->pv_aux + 2 * pv_nk,
                        c->pe_vis, pctr);
     hipLaunchKernelGGL(k_edge_primary_shade, dim3(nblk((size_t)2 * M, 256)), dim3(256), lds1, st,
                        S, c->last_seed, M, c->pe_samples, c->pe_hits, c->pe_vis, c->pe_f, pctr);

@@ -196,7 +196,7 @@ FR_KIND(KPrimarySetup, 256) {
 }};
 FR_KIND(KPvScan, 1024) {
     if (!(I.d.terms & FR_TERM_PRIMARY)) return;
-    scan_u32_body(pv_tiles(I.S.W, I.S.H) + 1, I.pv_aux);
+    scan_u32_body(pv_keys(I.S.W, I.S.H), I.pv_aux);
 }};
 FR_KIND(KPvOrder, 256) {
     if (!(I.d.terms & FR_TERM_PRIMARY)) return;
@@ -210,7 +210,7 @@ template <int TS> FR_KIND(KPvPropose, 256) {
 FR_KIND(KPvTrace, 256) {
     if (!(I.d.terms & FR_TERM_PRIMARY)) return;
     pv_trace_body(I.S, I.d.seed, I.pe_samples, I.pe_hits, I.pv_queue, 2 * (uint32_t)I.M,
-                  I.pv_aux + 2 * (pv_tiles(I.S.W, I.S.H) + 1), I.pe_vis, I.ctr + kCtrPerKern * kKernPrimary, bx, by);
+                  I.pv_aux + 2 * pv_keys(I.S.W, I.S.H), I.pe_vis, I.ctr + kCtrPerKern * kKernPrimary, bx, by);
 }};
 FR_KIND(KPrimaryShade, 256) {
     if (!(I.d.terms & FR_TERM_PRIMARY)) return;

@@ -159,6 +159,31 @@ def test_backward_all_terms_tiny(torch, orc):
     _compare(g, ref, pg)
 
 
+def test_backward_on_a_busy_user_stream(torch):
+    """The silhouette term runs on the context's second stream, forked from
+    and joined back into the caller's stream: on a busy user stream, two
+    backward calls queued back to back give the default stream's gradients."""
+    model, scene, params, spp = _case("tiny")
+    r = _renderer(torch, model, scene)
+    dL = torch.from_numpy(np.random.default_rng(5).normal(0, 1, (scene.height, scene.width, 3)).astype(np.float32)).cuda()
+    _gpu_render(torch, r, params, SEED, spp)
+    g0 = {k: v.cpu().numpy() for k, v in r.backward(dL).items()}
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        a = torch.randn(4096, 4096, device="cuda")
+        for _ in range(4):
+            a = a @ a * 1e-3                            # keeps the stream busy
+        dL2 = dL * 1.0                                  # written on s, read by the backward calls
+        g1 = r.backward(dL2)
+        g2 = r.backward(dL2)
+    s.synchronize()
+    for g in (g1, g2):
+        for k, v in g0.items():
+            got = g[k].cpu().numpy()
+            scale = max(float(np.abs(v).max()), 1e-30)
+            assert np.abs(got - v).max() <= 1e-6 * scale, k
+
+
 def test_backward_all_terms_tiny_refit(torch, orc):
     g, ref, pg, _ = _grad_case(torch, orc, "tiny", 7, refit=True)
     _compare(g, ref, pg)
