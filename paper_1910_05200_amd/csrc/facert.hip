@@ -780,10 +780,61 @@ __device__ __forceinline__ void sh_propose_body(const Scene &S, uint64_t seed, l
     });
     flush_count(ctr, 1, n_sh);
 }
+// Single context: one block per 256 samples for every light.  Each sample's
+// surface is decided once, then each light's horizon test runs on the same
+// lanes; a light's accepted samples gather in the block's byte list for that
+// light (the lane index), and each list goes to the light's queue with one
+// atomic.  The accepted samples and the queues' contents are those of
+// sh_propose_body; only the order of the blocks' appends differs.
+__device__ __forceinline__ void sh_propose_all_body(const Scene &S, uint64_t seed, long long s0, long long n,
+        const HitRec *__restrict__ hits, uint32_t *__restrict__ queue, uint32_t qcap, uint32_t *__restrict__ cnt,
+        unsigned long long *ctr, int bx) {
+    __shared__ uint8_t ql[kMaxLights * 256];
+    __shared__ Light Ls[kMaxLights];
+    __shared__ int q_n[kMaxLights];
+    __shared__ uint32_t q_base[kMaxLights];
+    for (int k = threadIdx.x; k < S.nl; k += 256) { Ls[k] = light_geom(S, k); q_n[k] = 0; }
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const long long base = (long long)bx * 256, i = base + threadIdx.x;
+    bool have = false;
+    SurfDec sd;
+    if (i < n) {
+        const HitRec rec = hits[i];
+        if (rec.tri >= 0) {
+            surf_decide(S, mk(S.cam_x, S.cam_y, S.cam_z), hit_of(rec), sd);
+            have = true;
+        }
+    }
+    LightRng rng(seed, (uint32_t)(s0 + i), 0, 2);
+    uint32_t n_sh = 0;
+    for (int j = 0; j < S.nl; ++j) {
+        bool need = false;
+        if (have) {
+            float u, v;
+            rng.get(j, u, v);
+            need = above(sd, light_point(Ls[j], u, v));
+        }
+        const unsigned long long m = __ballot(need);
+        if (m) {   // the same for every lane of the wave
+            int wbase = 0;
+            if (lane == 0) wbase = atomicAdd(&q_n[j], __popcll(m));
+            wbase = __shfl(wbase, 0);
+            if (need) { ql[j * 256 + wbase + lanes_below(m)] = (uint8_t)threadIdx.x; ++n_sh; }
+        }
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < S.nl; j += 256) q_base[j] = q_n[j] > 0 ? atomicAdd(&cnt[j], (uint32_t)q_n[j]) : 0u;
+    __syncthreads();
+    for (int j = 0; j < S.nl; ++j)
+        for (int e = threadIdx.x; e < q_n[j]; e += 256)
+            queue[(size_t)j * qcap + q_base[j] + e] = (uint32_t)(base + ql[j * 256 + e]);
+    flush_count(ctr, 1, n_sh);
+}
 __global__ __launch_bounds__(256) void k_sh_propose(Scene S, uint64_t seed, long long s0, long long n,
         const HitRec *__restrict__ hits, uint32_t *__restrict__ queue, uint32_t qcap, uint32_t *__restrict__ cnt,
         unsigned long long *ctr) {
-    sh_propose_body<kShTile>(S, seed, s0, n, hits, queue, qcap, cnt, ctr, blockIdx.x, blockIdx.y);
+    sh_propose_all_body(S, seed, s0, n, hits, queue, qcap, cnt, ctr, blockIdx.x);
 }
 __device__ __forceinline__ void sh_trace_body(const Scene &S, uint64_t seed, long long s0,
         const HitRec *__restrict__ hits, const uint32_t *__restrict__ queue, uint32_t qcap,
@@ -2340,7 +2391,7 @@ static void shadow_pass(fr_ctx *c, const Scene &S, uint64_t seed, long long s0, 
                         int ev0 = -1, int ev1 = -1) {
     const uint32_t qcap = (uint32_t)c->sh_cap;   // >= n: fr_render sized it for this chunk size
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, c->stream, c->sh_cnt, c->nl);
-    hipLaunchKernelGGL(k_sh_propose, dim3(nblk(n, kShTile), c->nl), dim3(256), 0, c->stream, S, seed, s0, n, c->hits,
+    hipLaunchKernelGGL(k_sh_propose, dim3(nblk(n, 256)), dim3(256), 0, c->stream, S, seed, s0, n, c->hits,
                        c->sh_queue, qcap, c->sh_cnt, ctr);
     if (ev0 >= 0) ev_record(c, ev0);
     hipLaunchKernelGGL(k_sh_trace, dim3(nblk(n, 256), c->nl), dim3(256), 0, c->stream, S, seed, s0, c->hits,

@@ -110,9 +110,11 @@ def test_lbvh_and_refit_trees_render_identically(torch):
     assert np.array_equal(a, b)
 
 
-def _grad_case(torch, orc, name, terms, chunk=None, refit=False):
+def _grad_case(torch, orc, name, terms, chunk=None, refit=False, size=None):
     from paper_1910_05200_amd import facert
     model, scene, params, spp = _case(name)
+    if size:
+        scene = synth.make_scene(*size)
     tosc, _, _ = orc.scene_from_model(model, scene, synth.make_params(synth.TARGET_SCENE_SEED))
     target = orc.render(tosc, synth.TARGET_RENDER_SEED, 16)
     osc, vm, R = orc.scene_from_model(model, scene, params)
@@ -156,6 +158,14 @@ def test_backward_all_terms_tiny(torch, orc):
     g, ref, pg, r = _grad_case(torch, orc, "tiny", 7)
     st = r.stats()
     assert st["rays_edge_secondary"] > 0 and st["rays_edge_primary"] > 0
+    _compare(g, ref, pg)
+
+
+def test_backward_all_terms_ragged_image(torch, orc):
+    """An image whose sides are not multiples of the silhouette sort's
+    8x8-pixel tiles or of the screen grid's cells."""
+    g, ref, pg, r = _grad_case(torch, orc, "tiny", 7, size=(53, 37))
+    assert r.stats()["rays_edge_primary"] > 0
     _compare(g, ref, pg)
 
 
