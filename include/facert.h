@@ -256,8 +256,8 @@ typedef struct fr_batch fr_batch;
 #define FR_LAUNCH_XCD 1
 typedef struct {
     int32_t mode;                    /* FR_LAUNCH_*                            */
-    int32_t tile;                    /* compacting kinds (sh_propose,
-                                        edge_secondary, pv_propose): 256
+    int32_t tile;                    /* per-light compacting kinds
+                                        (edge_secondary, pv_propose): 256
                                         or 512; 0 for the others               */
 } fr_launch;
 

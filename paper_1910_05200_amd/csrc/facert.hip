@@ -683,15 +683,13 @@ __global__ __launch_bounds__(256) void k_cam_resolve(Scene S, long long n, HitRe
     flush_count(ctr, 0, n_cam);
 }
 
-// Rays are compacted before they are traced: a block takes a tile of
-// consecutive samples for one light, its lanes run the horizon test and
-// append the rays that need tracing to a list (one LDS atomic per wave).
-// About a third of the (sample, light) pairs need a ray at the paper's
-// framing (camera misses and lights below the horizon need none), so
-// tracing in place would leave two lanes in three idle.  The tile size is a
-// template parameter of the bodies (single-instance launches use kShTile;
-// the batched launcher may pick another).
-constexpr int kShTile = 512;
+// Rays are compacted before they are traced: the lanes run the horizon
+// tests and append the rays that need tracing to lists (one LDS atomic per
+// wave and list).  About a third of the (sample, light) pairs need a ray at
+// the paper's framing (camera misses and lights below the horizon need
+// none), so tracing in place would leave two lanes in three idle.  Where a
+// block takes a tile of samples for one light, the tile size is a template
+// parameter of the body (the batched launcher may pick 256 or 512).
 // The shadow-boundary kernel keeps its accepted samples' two side rays in
 // LDS (48 bytes each), so its tile is smaller: 256 samples.
 constexpr int kSecTile = 256;
@@ -712,7 +710,7 @@ __device__ __forceinline__ int lanes_below(unsigned long long m) {
 //   k_sh_trace    one lane per queued ray, rebuilt from the sample's hit
 //                 record and light sample as k_sh_propose built it, traced.
 // Every resident wave of k_sh_trace traces.  The batched path runs the same
-// bodies (sh_propose_body with a tile of 256 or 512 samples).
+// bodies.
 __device__ __forceinline__ bool sh_ray(const Scene &S, const Light &L, uint64_t seed, long long s0, long long i,
                                        const HitRec *__restrict__ hits, int j, v3 &p, v3 &dd, int &tri) {
     const HitRec rec = hits[i];
@@ -767,25 +765,11 @@ __device__ __forceinline__ uint32_t propose_body(long long n, uint32_t *__restri
     for (int e = threadIdx.x; e < nq; e += 256) queue[(size_t)j * qcap + q_base + e] = q[e];
     return taken;
 }
-template <int TS>
-__device__ __forceinline__ void sh_propose_body(const Scene &S, uint64_t seed, long long s0, long long n,
-        const HitRec *__restrict__ hits, uint32_t *__restrict__ queue, uint32_t qcap, uint32_t *__restrict__ cnt,
-        unsigned long long *ctr, int bx, int j) {
-    const Light L = light_geom(S, j);
-    const uint32_t n_sh = propose_body<TS>(n, queue, qcap, cnt, bx, j, [&](long long i, uint32_t &v) {
-        v3 p, dd;
-        int tri;
-        v = (uint32_t)i;
-        return sh_ray(S, L, seed, s0, i, hits, j, p, dd, tri);
-    });
-    flush_count(ctr, 1, n_sh);
-}
-// Single context: one block per 256 samples for every light.  Each sample's
+// k_sh_propose: one block per 256 samples for every light.  Each sample's
 // surface is decided once, then each light's horizon test runs on the same
 // lanes; a light's accepted samples gather in the block's byte list for that
 // light (the lane index), and each list goes to the light's queue with one
-// atomic.  The accepted samples and the queues' contents are those of
-// sh_propose_body; only the order of the blocks' appends differs.
+// atomic.  The batched path runs the same body.
 __device__ __forceinline__ void sh_propose_all_body(const Scene &S, uint64_t seed, long long s0, long long n,
         const HitRec *__restrict__ hits, uint32_t *__restrict__ queue, uint32_t qcap, uint32_t *__restrict__ cnt,
         unsigned long long *ctr, int bx) {

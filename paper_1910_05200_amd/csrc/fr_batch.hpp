@@ -17,9 +17,9 @@
 //               contiguous eighths (the dispatcher issues block b to XCD
 //               b mod 8), so that each XCD's L2 serves a few instances at a
 //               time instead of all of them.
-// The shadow-ray kinds (forward visibility, shadow-boundary edges,
-// silhouette visibility) also take their tile size (samples compacted per
-// block: 256 or 512).  Every mode computes the same per-sample values:
+// The per-light proposal kinds (shadow-boundary edges, silhouette
+// visibility) also take their tile size (samples compacted per block: 256
+// or 512).  Every mode computes the same per-sample values:
 // images are bitwise those of single-context renders; gradients differ only
 // by the order of their fp64 atomic sums.
 //
@@ -155,9 +155,9 @@ FR_KIND(KZeroFwd, 64) {
 FR_KIND(KCamera, 256) {
     fwd_camera_body(I.S, I.d.seed, I.d.spp, 0, I.N, I.hits, I.vis, I.ctr + kCtrPerKern * kKernCamera, bx);
 }};
-template <int TS> FR_KIND(KShPropose, 256) {
-    sh_propose_body<TS>(I.S, I.d.seed, 0, I.N, I.hits, I.sh_queue, I.sh_qcap, I.sh_cnt,
-                        I.ctr + kCtrPerKern * kKernShadow, bx, by);
+FR_KIND(KShPropose, 256) {
+    sh_propose_all_body(I.S, I.d.seed, 0, I.N, I.hits, I.sh_queue, I.sh_qcap, I.sh_cnt,
+                        I.ctr + kCtrPerKern * kKernShadow, bx);
 }};
 FR_KIND(KShTrace, 256) {
     sh_trace_body(I.S, I.d.seed, 0, I.hits, I.sh_queue, I.sh_qcap, I.sh_cnt, I.vis, I.ctr + kCtrPerKern * kKernShadow,
@@ -280,7 +280,7 @@ __global__ __launch_bounds__(K::kThreads) void k_multi(const Inst *__restrict__ 
 
 static const int kTiles[2] = {256, 512};
 
-static bool kind_tiled(int k) { return k == bkShPropose || k == bkSecondary || k == bkPvPropose; }
+static bool kind_tiled(int k) { return k == bkSecondary || k == bkPvPropose; }
 static bool kind_tunable(int k) {
     return k == bkCamera || k == bkShPropose || k == bkShTrace || k == bkShade || k == bkAdj || k == bkSecondary || k == bkSecValue ||
            k == bkPrimarySetup || k == bkPvPropose || k == bkPvTrace || k == bkPrimaryShade;
@@ -363,7 +363,8 @@ static void kind_grid(const fr_batch *b, int k, int i, int &gx, int &gy) {
     case bkEdgeWeights: gx = (int)nblk(c->E, 256); break;
     case bkEdgeScan: gx = 1 + nl; break;
     case bkCamera: case bkShade: case bkAdj: gx = (int)nblk(N, 256); break;
-    case bkShPropose: case bkSecondary: gx = (int)nblk(N, ts); gy = nl; break;
+    case bkSecondary: gx = (int)nblk(N, ts); gy = nl; break;
+    case bkShPropose: gx = (int)nblk(N, 256); break;
     case bkShTrace: gx = (int)nblk(N, 256); gy = nl; break;
     case bkPixelMean: case bkPrimarySetup: case bkPvOrder: case bkPrimaryScatter: gx = (int)nblk(M, 256); break;
     case bkZeroBwd:
@@ -455,10 +456,7 @@ static void launch_kind(fr_batch *b, int k, int arg = 0) {
     case bkEdgeScan: launch_k<KEdgeScan>(b, m, arg, grid, 0); break;
     case bkZeroFwd: launch_k<KZeroFwd>(b, m, arg, grid, 0); break;
     case bkCamera: launch_k<KCamera>(b, m, arg, grid, 0); break;
-    case bkShPropose:
-        if (ts == 256) launch_k<KShPropose<256>>(b, m, arg, grid, 0);
-        else launch_k<KShPropose<512>>(b, m, arg, grid, 0);
-        break;
+    case bkShPropose: launch_k<KShPropose>(b, m, arg, grid, 0); break;
     case bkShTrace: launch_k<KShTrace>(b, m, arg, grid, 0);
         break;
     case bkShade: launch_k<KShade>(b, m, arg, grid, b->lds_res2); break;
@@ -638,8 +636,7 @@ int fr_batch_create(int32_t n, fr_ctx *const *ctx, uint32_t flags, fr_batch **ou
     b->dyn.assign(n, InstDyn{});
     b->gen.assign(n, 0);
     for (int k = 0; k < bkNum; ++k)
-        b->launch[k] = fr_launch{FR_LAUNCH_FLAT, k == bkSecondary ? kSecTile
-                                                 : k == bkPvPropose ? kPvTile : (kind_tiled(k) ? kShTile : 0)};
+        b->launch[k] = fr_launch{FR_LAUNCH_FLAT, k == bkSecondary ? kSecTile : k == bkPvPropose ? kPvTile : 0};
     b->stream = ctx[0]->stream;
     if (hipMalloc((void **)&b->tab, sizeof(Inst) * n) != hipSuccess) {
         fr_batch_destroy(b);

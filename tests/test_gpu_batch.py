@@ -71,7 +71,7 @@ def _setup(torch, inst, timing=False):
 
 def _set_mode(batch, mode, tile):
     for k in batch.kinds:
-        tiled = k in ("sh_propose", "edge_secondary", "pv_propose")
+        tiled = k in ("edge_secondary", "pv_propose")
         batch.set_launch(k, mode, tile if tiled else 0)
 
 
@@ -242,9 +242,10 @@ def test_batch_tune_keeps_results(torch):
 
 
 def test_batch_relaunch_does_not_disturb_enqueued_work(torch):
-    """New tile sizes while a batched render is still queued (behind a long
-    matrix product on the same stream), then new sample counts: each queued
-    render keeps the tile maps and descriptors it was enqueued with.  (The
+    """New launch modes and tile sizes while batched work is still queued
+    (behind a long matrix product on the same stream), then new sample
+    counts: each queued render and backward keeps the tile maps and
+    descriptors it was enqueued with.  (The
     first change must not rewrite the tile maps under the queued render: the
     sample counts stay, so no reallocation synchronises the device.)"""
     inst = _small()
@@ -259,14 +260,21 @@ def test_batch_relaunch_does_not_disturb_enqueued_work(torch):
         for _ in range(4):
             a = a @ a * 1e-3                             # keeps the stream busy
         first = batch.render(ps, seeds, spps)
-        batch.set_launch("sh_propose", 0, 256)
+        dls = _dls(torch, inst)
+        g_first = batch.backward(dls)
+        batch.set_launch("sh_propose", 1, 0)
+        batch.set_launch("edge_secondary", 0, 512)
         batch.set_launch("pv_propose", 1, 256)
         second = batch.render(ps, [x + 1 for x in seeds], spps)
         for _ in range(4):
             a = a @ a * 1e-3
-        batch.set_launch("sh_propose", 1, 512)
+        batch.set_launch("sh_propose", 0, 0)
         third = batch.render(ps, [x + 2 for x in seeds], [x + 1 for x in spps])
         s.synchronize()
+        g_first = [_np(g) for g in g_first]
+        for i, r in enumerate(rs):
+            r.render(ps[i], seeds[i], spps[i])
+            _assert_grads_close(g_first[i], _np(r.backward(dls[i])), f"first backward, instance {i}")
         for i, r in enumerate(rs):
             assert torch.equal(first[i], r.render(ps[i], seeds[i], spps[i])), f"first render, instance {i}"
             assert torch.equal(second[i], r.render(ps[i], seeds[i] + 1, spps[i])), f"second render, instance {i}"
@@ -301,7 +309,7 @@ def test_batch_errors(torch):
     assert e.value.code == -1
     for bad in [(0, 300), (0, 1024), (2, 512), (-1, 256)]:
         with pytest.raises(facert.FrError):
-            batch.set_launch("sh_propose", *bad)
+            batch.set_launch("edge_secondary", *bad)
     batch.render(ps, seeds, spps)
     rs[1].render(ps[1], 9, spps[1])           # instance 1 rendered on its own since
     with pytest.raises(facert.FrError) as e:
