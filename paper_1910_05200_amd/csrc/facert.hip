@@ -693,9 +693,6 @@ __global__ __launch_bounds__(256) void k_cam_resolve(Scene S, long long n, HitRe
 // The shadow-boundary kernel keeps its accepted samples' two side rays in
 // LDS (48 bytes each), so its tile is smaller: 256 samples.
 constexpr int kSecTile = 256;
-// Camera-silhouette sides: most of a tile's sides trace nothing (the side
-// that misses the face), so a smaller tile keeps more blocks in flight.
-constexpr int kPvTile = 256;
 __device__ __forceinline__ int lanes_below(unsigned long long m) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0));
 }
@@ -732,55 +729,49 @@ __device__ __forceinline__ Light light_geom(const Scene &S, int j) {
     L.c = mk(g[0], g[1], g[2]); L.e1 = mk(g[3], g[4], g[5]); L.e2 = mk(g[6], g[7], g[8]);
     return L;
 }
-// For the indices i in [bx TS, (bx + 1) TS) ∩ [0, n) that accept(i, v)
-// takes, appends their values v to queue j (row j of a [nl][qcap] array):
-// the block gathers them in LDS, reserves its slots with one atomic on
-// cnt[j], then writes them out.  Returns how many of this thread's indices
-// were taken.
-template <int TS, class Accept>
-__device__ __forceinline__ uint32_t propose_body(long long n, uint32_t *__restrict__ queue, uint32_t qcap,
-                                                 uint32_t *__restrict__ cnt, int bx, int j, Accept accept) {
-    __shared__ uint32_t q[TS];
-    __shared__ int q_n;
-    __shared__ uint32_t q_base;
-    const int lane = threadIdx.x & 63;
-    if (threadIdx.x == 0) q_n = 0;
-    __syncthreads();
-    const long long base = (long long)bx * TS;
-    uint32_t taken = 0;
-    for (int k = 0; k < TS; k += 256) {
-        const long long i = base + k + (int)threadIdx.x;
-        uint32_t v = 0;
-        const bool need = i < n && accept(i, v);
-        const unsigned long long m = __ballot(need);
-        int wbase = 0;
-        if (lane == 0 && m) wbase = atomicAdd(&q_n, __popcll(m));
-        wbase = __shfl(wbase, 0);
-        if (need) { q[wbase + lanes_below(m)] = v; ++taken; }
-    }
-    __syncthreads();
-    const int nq = q_n;
-    if (threadIdx.x == 0 && nq > 0) q_base = atomicAdd(&cnt[j], (uint32_t)nq);
-    __syncthreads();
-    for (int e = threadIdx.x; e < nq; e += 256) queue[(size_t)j * qcap + q_base + e] = q[e];
-    return taken;
-}
-// k_sh_propose: one block per 256 samples for every light.  Each sample's
-// surface is decided once, then each light's horizon test runs on the same
-// lanes; a light's accepted samples gather in the block's byte list for that
-// light (the lane index), and each list goes to the light's queue with one
-// atomic.  The batched path runs the same body.
-__device__ __forceinline__ void sh_propose_all_body(const Scene &S, uint64_t seed, long long s0, long long n,
-        const HitRec *__restrict__ hits, uint32_t *__restrict__ queue, uint32_t qcap, uint32_t *__restrict__ cnt,
-        unsigned long long *ctr, int bx) {
+// The proposals of one block of 256 items (samples or sides) for every
+// light: accept(j, L) is this lane's horizon test for light j (its surface
+// already decided by the caller).  A light's accepted lanes gather in the
+// block's byte list for that light; each list goes to the light's queue
+// (row j of a [nl][qcap] array) with one atomic on cnt[j], as the values v
+// of its lanes.  Returns how many lights this lane's item was queued for.
+template <class Accept>
+__device__ __forceinline__ uint32_t propose_all_body(const Scene &S, uint32_t v, uint32_t *__restrict__ queue,
+                                                     uint32_t qcap, uint32_t *__restrict__ cnt, Accept accept) {
     __shared__ uint8_t ql[kMaxLights * 256];
+    __shared__ uint32_t val[256];
     __shared__ Light Ls[kMaxLights];
     __shared__ int q_n[kMaxLights];
     __shared__ uint32_t q_base[kMaxLights];
     for (int k = threadIdx.x; k < S.nl; k += 256) { Ls[k] = light_geom(S, k); q_n[k] = 0; }
+    val[threadIdx.x] = v;
     __syncthreads();
     const int lane = threadIdx.x & 63;
-    const long long base = (long long)bx * 256, i = base + threadIdx.x;
+    uint32_t taken = 0;
+    for (int j = 0; j < S.nl; ++j) {
+        const bool need = accept(j, Ls[j]);
+        const unsigned long long m = __ballot(need);
+        if (m) {   // the same for every lane of the wave
+            int wbase = 0;
+            if (lane == 0) wbase = atomicAdd(&q_n[j], __popcll(m));
+            wbase = __shfl(wbase, 0);
+            if (need) { ql[j * 256 + wbase + lanes_below(m)] = (uint8_t)threadIdx.x; ++taken; }
+        }
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < S.nl; j += 256) q_base[j] = q_n[j] > 0 ? atomicAdd(&cnt[j], (uint32_t)q_n[j]) : 0u;
+    __syncthreads();
+    for (int j = 0; j < S.nl; ++j)
+        for (int e = threadIdx.x; e < q_n[j]; e += 256) queue[(size_t)j * qcap + q_base[j] + e] = val[ql[j * 256 + e]];
+    return taken;
+}
+// k_sh_propose: one block per 256 samples for every light.  Each sample's
+// surface is decided once, then each light's horizon test runs on the same
+// lanes (the decisions of sh_ray).  The batched path runs the same body.
+__device__ __forceinline__ void sh_propose_all_body(const Scene &S, uint64_t seed, long long s0, long long n,
+        const HitRec *__restrict__ hits, uint32_t *__restrict__ queue, uint32_t qcap, uint32_t *__restrict__ cnt,
+        unsigned long long *ctr, int bx) {
+    const long long i = (long long)bx * 256 + threadIdx.x;
     bool have = false;
     SurfDec sd;
     if (i < n) {
@@ -791,28 +782,12 @@ __device__ __forceinline__ void sh_propose_all_body(const Scene &S, uint64_t see
         }
     }
     LightRng rng(seed, (uint32_t)(s0 + i), 0, 2);
-    uint32_t n_sh = 0;
-    for (int j = 0; j < S.nl; ++j) {
-        bool need = false;
-        if (have) {
-            float u, v;
-            rng.get(j, u, v);
-            need = above(sd, light_point(Ls[j], u, v));
-        }
-        const unsigned long long m = __ballot(need);
-        if (m) {   // the same for every lane of the wave
-            int wbase = 0;
-            if (lane == 0) wbase = atomicAdd(&q_n[j], __popcll(m));
-            wbase = __shfl(wbase, 0);
-            if (need) { ql[j * 256 + wbase + lanes_below(m)] = (uint8_t)threadIdx.x; ++n_sh; }
-        }
-    }
-    __syncthreads();
-    for (int j = threadIdx.x; j < S.nl; j += 256) q_base[j] = q_n[j] > 0 ? atomicAdd(&cnt[j], (uint32_t)q_n[j]) : 0u;
-    __syncthreads();
-    for (int j = 0; j < S.nl; ++j)
-        for (int e = threadIdx.x; e < q_n[j]; e += 256)
-            queue[(size_t)j * qcap + q_base[j] + e] = (uint32_t)(base + ql[j * 256 + e]);
+    const uint32_t n_sh = propose_all_body(S, (uint32_t)i, queue, qcap, cnt, [&](int j, const Light &L) {
+        if (!have) return false;
+        float u, v;
+        rng.get(j, u, v);
+        return above(sd, light_point(L, u, v));
+    });
     flush_count(ctr, 1, n_sh);
 }
 __global__ __launch_bounds__(256) void k_sh_propose(Scene S, uint64_t seed, long long s0, long long n,
@@ -1624,30 +1599,39 @@ __device__ __forceinline__ bool pe_light(const Scene &S, uint64_t seed, const Pe
 // k_edge_primary_shade: one lane per side, the fp64 radiance of its visible
 // lights summed in light order (no atomics; the fp64 shading registers stay
 // out of the traversal kernel).
-// k_pv_propose walks the sides in screen order: position k is side k & 1 of
-// sample perm[k >> 1]; the queue holds side indices.
-template <int TS>
-__device__ __forceinline__ void pv_propose_body(const Scene &S, uint64_t seed, int M,
-        const PeSample *__restrict__ ps_in, const Hit *__restrict__ hits, const uint32_t *__restrict__ perm,
-        uint32_t *__restrict__ aux, uint32_t *__restrict__ queue, uint32_t qcap, unsigned long long *ctr, int bx,
-        int j) {
-    const Light L = light_geom(S, j);
+// k_pv_propose: one block per 256 sides in screen order (position k is
+// side k & 1 of sample perm[k >> 1]) for every light, each side's surface
+// decided once (the decisions of pe_light); the queues hold side indices.
+__device__ __forceinline__ void pv_propose_body(const Scene &S, uint64_t seed, const PeSample *__restrict__ ps_in,
+        const Hit *__restrict__ hits, const uint32_t *__restrict__ perm, uint32_t *__restrict__ aux,
+        uint32_t *__restrict__ queue, uint32_t qcap, unsigned long long *ctr, int bx) {
     const int nk = pv_keys(S.W, S.H);
     const long long n = 2 * (long long)aux[nk - kPvSortCopies];   // sides of the samples with an edge
-    const uint32_t n_sh = propose_body<TS>(n, queue, qcap, aux + 2 * nk, bx, j, [&](long long k, uint32_t &v) {
-        v3 o, d, y;
-        Hit h;
-        SurfDec sd;
-        const int ms = 2 * (int)perm[k >> 1] + (int)(k & 1);
-        v = (uint32_t)ms;
-        return pe_light(S, seed, ps_in, hits, L, j, ms, o, d, h, sd, y);
+    const long long k = (long long)bx * 256 + threadIdx.x;
+    int ms = 0;
+    bool have = false;
+    SurfDec sd;
+    if (k < n) {
+        ms = 2 * (int)perm[k >> 1] + (int)(k & 1);
+        const Hit h = hits[ms];
+        if (ps_in[ms >> 1].e >= 0 && h.tri >= 0) {
+            surf_decide(S, mk(S.cam_x, S.cam_y, S.cam_z), h, sd);
+            have = true;
+        }
+    }
+    LightRng rng(seed, (uint32_t)(ms >> 1), 2, 4);
+    const uint32_t n_sh = propose_all_body(S, (uint32_t)ms, queue, qcap, aux + 2 * nk, [&](int j, const Light &L) {
+        if (!have) return false;
+        float u, v;
+        rng.get(j, u, v);
+        return above(sd, light_point(L, u, v));
     });
     flush_count(ctr, 2, n_sh);
 }
-__global__ __launch_bounds__(256) void k_pv_propose(Scene S, uint64_t seed, int M,
-        const PeSample *__restrict__ ps_in, const Hit *__restrict__ hits, const uint32_t *__restrict__ perm,
-        uint32_t *__restrict__ aux, uint32_t *__restrict__ queue, uint32_t qcap, unsigned long long *ctr) {
-    pv_propose_body<kPvTile>(S, seed, M, ps_in, hits, perm, aux, queue, qcap, ctr, blockIdx.x, blockIdx.y);
+__global__ __launch_bounds__(256) void k_pv_propose(Scene S, uint64_t seed, const PeSample *__restrict__ ps_in,
+        const Hit *__restrict__ hits, const uint32_t *__restrict__ perm, uint32_t *__restrict__ aux,
+        uint32_t *__restrict__ queue, uint32_t qcap, unsigned long long *ctr) {
+    pv_propose_body(S, seed, ps_in, hits, perm, aux, queue, qcap, ctr, blockIdx.x);
 }
 __device__ __forceinline__ void pv_trace_body(const Scene &S, uint64_t seed, const PeSample *__restrict__ ps_in,
         const Hit *__restrict__ hits, const uint32_t *__restrict__ queue, uint32_t qcap,
@@ -2707,8 +2691,8 @@ static void primary_pass(fr_ctx *c, const Scene &S, const float *dLdI, hipStream
     hipLaunchKernelGGL(k_pe_resolve, dim3(nblk(2 * (size_t)M, 256)), dim3(256), 0, st, S, M, ncx, nc,
                        c->pe_samples, c->pe_q, c->pe_cell_n, c->pe_rec, cap, c->pe_hits, c->pe_vis, pctr);
     const uint32_t pv_cap = 2 * (uint32_t)M;
-    hipLaunchKernelGGL(k_pv_propose, dim3(nblk((size_t)pv_cap, kPvTile), c->nl), dim3(256), 0, st, S,
-                       c->last_seed, M, c->pe_samples, c->pe_hits, c->pv_perm, c->pv_aux, c->pv_queue, pv_cap, pctr);
+    hipLaunchKernelGGL(k_pv_propose, dim3(nblk((size_t)pv_cap, 256)), dim3(256), 0, st, S, c->last_seed, c->pe_samples,
+                       c->pe_hits, c->pv_perm, c->pv_aux, c->pv_queue, pv_cap, pctr);
     hipLaunchKernelGGL(k_pv_trace, dim3(nblk((size_t)pv_cap, 256), c->nl), dim3(256), 0, st, S,
                        c->last_seed, c->pe_samples, c->pe_hits, c->pv_queue, pv_cap, c->pv_aux + 2 * pv_nk,
                        c->pe_vis, pctr);

@@ -17,9 +17,8 @@
 //               contiguous eighths (the dispatcher issues block b to XCD
 //               b mod 8), so that each XCD's L2 serves a few instances at a
 //               time instead of all of them.
-// The per-light proposal kinds (shadow-boundary edges, silhouette
-// visibility) also take their tile size (samples compacted per block: 256
-// or 512).  Every mode computes the same per-sample values:
+// The shadow-boundary kind also takes its tile size (samples compacted per
+// block: 256 or 512).  Every mode computes the same per-sample values:
 // images are bitwise those of single-context renders; gradients differ only
 // by the order of their fp64 atomic sums.
 //
@@ -202,10 +201,10 @@ FR_KIND(KPvOrder, 256) {
     if (!(I.d.terms & FR_TERM_PRIMARY)) return;
     pv_order_body(I.S, I.M, I.pe_samples, I.pv_aux, I.pv_perm, bx);
 }};
-template <int TS> FR_KIND(KPvPropose, 256) {
+FR_KIND(KPvPropose, 256) {
     if (!(I.d.terms & FR_TERM_PRIMARY)) return;
-    pv_propose_body<TS>(I.S, I.d.seed, I.M, I.pe_samples, I.pe_hits, I.pv_perm, I.pv_aux, I.pv_queue,
-                        2 * (uint32_t)I.M, I.ctr + kCtrPerKern * kKernPrimary, bx, by);
+    pv_propose_body(I.S, I.d.seed, I.pe_samples, I.pe_hits, I.pv_perm, I.pv_aux, I.pv_queue, 2 * (uint32_t)I.M,
+                    I.ctr + kCtrPerKern * kKernPrimary, bx);
 }};
 FR_KIND(KPvTrace, 256) {
     if (!(I.d.terms & FR_TERM_PRIMARY)) return;
@@ -280,7 +279,7 @@ __global__ __launch_bounds__(K::kThreads) void k_multi(const Inst *__restrict__ 
 
 static const int kTiles[2] = {256, 512};
 
-static bool kind_tiled(int k) { return k == bkSecondary || k == bkPvPropose; }
+static bool kind_tiled(int k) { return k == bkSecondary; }
 static bool kind_tunable(int k) {
     return k == bkCamera || k == bkShPropose || k == bkShTrace || k == bkShade || k == bkAdj || k == bkSecondary || k == bkSecValue ||
            k == bkPrimarySetup || k == bkPvPropose || k == bkPvTrace || k == bkPrimaryShade;
@@ -371,7 +370,7 @@ static void kind_grid(const fr_batch *b, int k, int i, int &gx, int &gy) {
         gx = (int)nblk(std::max({3 * V, rr, 3 * nl, 8 * kCtrSpread * kNumKern, pv_aux_len(c->W, c->H, nl)}), 256);
         break;
     case bkSecValue: gx = (int)std::min<long long>(1024, std::max<long long>(1, (N + 1023) / 1024)); break;
-    case bkPvPropose: gx = (int)nblk(2 * (size_t)M, ts); gy = nl; break;
+    case bkPvPropose: gx = (int)nblk(2 * (size_t)M, 256); break;
     case bkPvTrace: gx = (int)nblk(2 * (size_t)M, 256); gy = nl; break;
     case bkPrimaryShade: gx = (int)nblk(2 * (size_t)M, 256); break;
     case bkParamPartial: gx = rows; gy = c->nchunks; break;
@@ -469,10 +468,7 @@ static void launch_kind(fr_batch *b, int k, int arg = 0) {
         break;
     case bkSecValue: launch_k<KSecValue>(b, m, arg, grid, b->lds_res2); break;
     case bkPrimarySetup: launch_k<KPrimarySetup>(b, m, arg, grid, 0); break;
-    case bkPvPropose:
-        if (ts == 256) launch_k<KPvPropose<256>>(b, m, arg, grid, 0);
-        else launch_k<KPvPropose<512>>(b, m, arg, grid, 0);
-        break;
+    case bkPvPropose: launch_k<KPvPropose>(b, m, arg, grid, 0); break;
     case bkPvTrace: launch_k<KPvTrace>(b, m, arg, grid, 0); break;
     case bkPvScan: launch_k<KPvScan>(b, m, arg, grid, 0); break;
     case bkPvOrder: launch_k<KPvOrder>(b, m, arg, grid, 0); break;
@@ -636,7 +632,7 @@ int fr_batch_create(int32_t n, fr_ctx *const *ctx, uint32_t flags, fr_batch **ou
     b->dyn.assign(n, InstDyn{});
     b->gen.assign(n, 0);
     for (int k = 0; k < bkNum; ++k)
-        b->launch[k] = fr_launch{FR_LAUNCH_FLAT, k == bkSecondary ? kSecTile : k == bkPvPropose ? kPvTile : 0};
+        b->launch[k] = fr_launch{FR_LAUNCH_FLAT, k == bkSecondary ? kSecTile : 0};
     b->stream = ctx[0]->stream;
     if (hipMalloc((void **)&b->tab, sizeof(Inst) * n) != hipSuccess) {
         fr_batch_destroy(b);

@@ -71,7 +71,7 @@ def _setup(torch, inst, timing=False):
 
 def _set_mode(batch, mode, tile):
     for k in batch.kinds:
-        tiled = k in ("edge_secondary", "pv_propose")
+        tiled = k == "edge_secondary"
         batch.set_launch(k, mode, tile if tiled else 0)
 
 
