@@ -27,8 +27,10 @@
  *     (HIP global memory) read or written on the context's stream, except
  *     where a comment says "host".  fr_create copies its host arrays.
  *   - streams: all work is enqueued on the stream set with fr_set_stream
- *     (default: the null stream) and the calls return without waiting,
- *     except fr_stats and fr_create, which synchronise.  One context must
+ *     (default: the null stream; fr_backward forks part of its work onto
+ *     a second stream of the context's own and joins it back) and the calls
+ *     return without waiting, except fr_stats and fr_create, which
+ *     synchronise.  One context must
  *     not be used from two host threads at once.
  *   - layouts: per-vertex arrays are structure-of-arrays [3][V] (x row, then
  *     y, then z; or r, g, b); bases are [K][3][V]; images are row-major
@@ -181,8 +183,11 @@ int fr_render(fr_ctx *ctx, const fr_params *params, uint64_t seed, int32_t spp,
  * the requested gradients.  Uses the parameters, seed and spp of the last
  * render (the caller must keep its device arrays alive until this call is
  * enqueued).  Gradients are sums over samples with floating-point atomics:
- * reproducible up to summation order.  Errors: FR_ESTATE without a prior
- * render, FR_EINVAL for null dL/dimage. */
+ * reproducible up to summation order.  The camera-silhouette term runs on a
+ * second stream that the context owns: it waits for an event recorded on
+ * the context's stream and the context's stream waits for its end, so the
+ * call is ordered with the caller's stream like any other.  Errors: FR_ESTATE without a prior render, FR_EINVAL
+ * for null dL/dimage. */
 int fr_backward(fr_ctx *ctx, const float *dL_dimage, const fr_grads *grads);
 
 /* Squared-L2 photo-consistency loss E_data (Eq. 1) and its image gradient:
