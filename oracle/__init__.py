@@ -23,8 +23,12 @@ from dataclasses import dataclass
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "liboracle.so")
 SRC = os.path.join(HERE, "oracle.c")
+# FACERT_ORACLE_SANITIZE=1 selects the AddressSanitizer + UBSan build of the
+# same source (oracle/sanitize.py runs the oracle's pins under it)
+SANITIZE = os.environ.get("FACERT_ORACLE_SANITIZE") == "1"
+LIB_PATH = os.path.join(HERE, "liboracle_asan.so" if SANITIZE else "liboracle.so")
+SAN_FLAGS = ["-fsanitize=address,undefined", "-fno-sanitize-recover=undefined", "-fno-omit-frame-pointer", "-g"]
 
 FLAG_INTERIOR, FLAG_PRIMARY, FLAG_SECONDARY = 1, 2, 4
 
@@ -32,7 +36,8 @@ FLAG_INTERIOR, FLAG_PRIMARY, FLAG_SECONDARY = 1, 2, 4
 def build(force: bool = True) -> str:
     """Compile liboracle.so with gcc (no contraction, no fast-math)."""
     if force or not os.path.exists(LIB_PATH):
-        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math",
+        extra = SAN_FLAGS if SANITIZE else []
+        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", *extra,
                                "-fPIC", "-shared", "-pthread", "-o", LIB_PATH, SRC, "-lm"])
     return LIB_PATH
 
@@ -83,6 +88,7 @@ def lib():
         L.orc_any_hit.argtypes = [vp, C.c_int, vp, vp, i32]
         L.orc_render.argtypes = [vp, u64, i32, i32, vp, vp]
         L.orc_render_pixels.argtypes = [vp, u64, i32, i32, vp, i32, vp]
+        L.orc_aov_pixels.argtypes = [vp, u64, i32, i32, vp, i32, vp]
         L.orc_record_decisions.argtypes = [vp, u64, i32, i32, vp]
         L.orc_render_frozen.argtypes = [vp, u64, i32, vp, i32, vp]
         L.orc_backward.argtypes = [vp, u64, i32, vp, i32, i32, vp, vp]
@@ -232,6 +238,18 @@ def render_pixels(osc: OScene, seed: int, spp: int, pixels, threads: int | None 
     return out
 
 
+def aov(osc: OScene, seed: int, spp: int, pixels=None, threads: int | None = None):
+    """Auxiliary buffers [n][7] (albedo RGB, normal xyz, depth) of the given
+    flat pixel indices (all pixels, as [H][W][7], when pixels is None)."""
+    st = osc.struct()
+    full = pixels is None
+    pix = np.arange(osc.height * osc.width, dtype=np.int32) if full else np.ascontiguousarray(pixels, np.int32)
+    out = np.zeros((pix.size, 7))
+    if lib().orc_aov_pixels(C.byref(st), seed, spp, pix.size, _p(pix), threads or default_threads(), _p(out)):
+        raise ValueError("orc_aov_pixels failed")
+    return out.reshape(osc.height, osc.width, 7) if full else out
+
+
 def record(osc: OScene, seed: int, spp: int, threads: int | None = None):
     st = osc.struct()
     rec = np.zeros((osc.height * osc.width * spp, 9), np.int32)
@@ -275,6 +293,15 @@ def backward_frozen(osc: OScene, seed: int, spp: int, rec, dLdI, threads: int | 
     gs = _Grads(*[_p(g[k]) for k, _ in _Grads._fields_])
     lib().orc_backward_frozen(C.byref(st), seed, spp, _p(rec), _p(dL), threads or default_threads(), C.byref(gs))
     return g
+
+
+# ------------------------------------------------------------ loss -------
+
+def loss_l2(image, target):
+    """E_data of Eq. 1 over all pixels and channels, and its image gradient:
+    (sum (I - T)^2, 2 (I - T)), float64."""
+    d = np.asarray(image, np.float64) - np.asarray(target, np.float64)
+    return float(np.sum(d * d)), 2.0 * d
 
 
 # ------------------------------------------------------ parameter chain --

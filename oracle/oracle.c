@@ -865,6 +865,26 @@ static void sample_value(const rctx *C, f3 o, f3 d, const sdec *D, double out[3]
     }
 }
 
+/* Auxiliary buffers of one camera sample, for a denoiser: the first hit's
+ * interpolated albedo, its shading normal turned toward the camera, and its
+ * distance from the camera (all zero on a miss), added to acc[7].  The hit is
+ * the estimator's own closest-hit decision; the values are the value path's
+ * (double, barycentrics re-solved). */
+static void sample_aov(const rctx *C, f3 o, f3 d, double acc[7]) {
+    float t, b1, b2, det;
+    sdec D;
+    D.tri = trace_closest(C->s, C->bvh, o, d, &t, &b1, &b2, &det);
+    if (D.tri < 0) return;
+    D.front = det > 0.0f;
+    D.b1 = b1; D.b2 = b2;
+    D.tex_ix = D.tex_iy = 0;      /* texel cell: not used by the buffers */
+    sgeo G;
+    geo_eval(C, o, d, &D, &G);
+    acc[0] += G.A[0]; acc[1] += G.A[1]; acc[2] += G.A[2];
+    acc[3] += G.ns.x; acc[4] += G.ns.y; acc[5] += G.ns.z;
+    acc[6] += G.olen;
+}
+
 /* ------------------------------------------------ thread-parallel driver -- */
 typedef struct {
     double *d_light, *d_spec, *d_pos, *d_nrm, *d_alb, *d_pos_pe, *d_pos_se;
@@ -1123,6 +1143,23 @@ static void *job_run(void *arg) {
         for (int64_t m = J->s0; m < J->s1; ++m) primary_sample(C, J->seed, m, M, J->dLdI, &J->g, &J->cnt);
         return NULL;
     }
+    if (J->mode == 7) {      /* auxiliary buffers of selected pixels */
+        for (int64_t i = J->s0; i < J->s1; ++i) {
+            int pix = J->pix[i];
+            int px = pix % s->W, py = pix / s->W;
+            double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+            for (int k = 0; k < J->spp; ++k) {
+                int64_t sidx = (int64_t)pix * J->spp + k;
+                uint32_t w[44];
+                camera_words(J->seed, (uint32_t)sidx, w);
+                float qx = (float)px + u01(w[0]), qy = (float)py + u01(w[1]);
+                f3 d = camera_dir(s, qx, qy);
+                sample_aov(C, cam, d, acc);
+            }
+            for (int c = 0; c < 7; ++c) J->pix_out[7 * i + c] = acc[c] / J->spp;
+        }
+        return NULL;
+    }
     if (J->mode == 6) {      /* selected pixels */
         for (int64_t i = J->s0; i < J->s1; ++i) {
             int pix = J->pix[i];
@@ -1251,6 +1288,21 @@ int orc_render_pixels(const orc_scene *s, uint64_t seed, int32_t spp,
     proto.pix = pix; proto.pix_out = out;
     job *jobs;
     run_jobs(&C, 6, seed, spp, n, 1, nthreads, &proto, &jobs);
+    free(jobs);
+    rctx_free(&C);
+    return 0;
+}
+
+int orc_aov_pixels(const orc_scene *s, uint64_t seed, int32_t spp,
+                   int32_t n, const int32_t *pix, int32_t nthreads, double *out) {
+    if (spp <= 0) return -1;
+    rctx C;
+    if (rctx_init(&C, s, 0)) return -1;
+    nthreads = clamp_threads(nthreads);
+    job proto; memset(&proto, 0, sizeof(proto));
+    proto.pix = pix; proto.pix_out = out;
+    job *jobs;
+    run_jobs(&C, 7, seed, spp, n, 1, nthreads, &proto, &jobs);
     free(jobs);
     rctx_free(&C);
     return 0;

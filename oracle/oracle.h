@@ -125,6 +125,15 @@ int orc_render(const orc_scene *s, uint64_t seed, int32_t spp, int32_t nthreads,
 int orc_render_pixels(const orc_scene *s, uint64_t seed, int32_t spp,
                       int32_t n, const int32_t *pix, int32_t nthreads, double *out);
 
+/* Auxiliary buffers of n selected pixels (flat indices pix[i] = y*W + x):
+ * out[i][7] = mean over the pixel's spp camera samples (the estimator's own
+ * jitter and closest hits) of the first hit's albedo (RGB), unit shading
+ * normal turned toward the camera (xyz) and distance from the camera;
+ * misses contribute zeros.  These are the inputs of a denoiser, not part of
+ * the estimator F. */
+int orc_aov_pixels(const orc_scene *s, uint64_t seed, int32_t spp,
+                   int32_t n, const int32_t *pix, int32_t nthreads, double *out);
+
 /* Decision record of every camera sample (for frozen-decision checks), 9
  * int32 words: tri, flags (bit0 front-facing, bit1 specular lobe active,
  * bit2 hit), visibility mask, cos_s-clamp mask, cos_l-clamp mask, V-cavity

@@ -435,35 +435,47 @@ def params_to_device(params, device="cuda"):
     return d
 
 
+def _render_inputs(alpha, beta, delta, pose, lights, spec) -> dict:
+    """Renderer.render's parameter dict from tensors (pose copied to the host)."""
+    return {"alpha": alpha.detach().contiguous(), "beta": beta.detach().contiguous(),
+            "delta": delta.detach().contiguous(), "pose": pose.detach().cpu().numpy(),
+            "lights": lights.detach().contiguous(), "spec": spec.detach().contiguous()}
+
+
 def _make_autograd():
     import torch
 
     class FaceRender(torch.autograd.Function):
         """image = F(alpha, beta, delta, pose, lights, spec; seed, spp).
 
-        The backward recomputes the samples of the forward (same seed and
-        spp) inside fr_backward instead of storing hit records."""
+        The backward is fr_backward, which replays the forward's samples
+        (same seed and spp): it reads the hit records and visibility masks
+        that fr_render kept when the render fitted one chunk of samples, and
+        recomputes them chunk by chunk otherwise.  If another render used the
+        renderer in between, the forward is rendered again from the saved
+        inputs first.  The inputs are saved with save_for_backward, so an
+        in-place change to one of them between forward and backward (say an
+        optimiser step) raises instead of differentiating other values."""
 
         @staticmethod
         def forward(ctx, renderer, seed, spp, alpha, beta, delta, pose, lights, spec):
-            p = {"alpha": alpha.detach().contiguous(), "beta": beta.detach().contiguous(),
-                 "delta": delta.detach().contiguous(), "pose": pose.detach().cpu().numpy(),
-                 "lights": lights.detach().contiguous(), "spec": spec.detach().contiguous()}
+            p = _render_inputs(alpha, beta, delta, pose, lights, spec)
             img = renderer.render(p, seed, spp)
-            ctx.renderer, ctx.seed, ctx.spp, ctx.p = renderer, seed, spp, p
+            ctx.save_for_backward(alpha, beta, delta, pose, lights, spec)
+            ctx.renderer, ctx.seed, ctx.spp = renderer, seed, spp
             ctx.token = renderer.render_token
-            ctx.pose_device = pose.device
             return img
 
         @staticmethod
         def backward(ctx, grad_img):
+            alpha, beta, delta, pose, lights, spec = ctx.saved_tensors   # raises if modified in place
             r = ctx.renderer
-            if r.render_token != ctx.token:       # another render ran since: recompute state
-                r.render(ctx.p, ctx.seed, ctx.spp)
+            if r.render_token != ctx.token:       # another render ran since: replay this one
+                r.render(_render_inputs(alpha, beta, delta, pose, lights, spec), ctx.seed, ctx.spp)
             g = r.backward(grad_img.contiguous(), want=("d_alpha", "d_beta", "d_delta", "d_pose",
                                                         "d_lights", "d_spec"))
             return (None, None, None, g["d_alpha"], g["d_beta"], g["d_delta"],
-                    g["d_pose"].to(ctx.pose_device), g["d_lights"], g["d_spec"])
+                    g["d_pose"].to(pose.device), g["d_lights"], g["d_spec"])
 
     return FaceRender
 

@@ -14,7 +14,10 @@ difference of the exact integral, computed without Monte Carlo:
   is Lambert's formula over the light polygon minus the occluder's central
   projection; derivatives with respect to the occluder's vertices (shadow
   term only) and to a rigid motion of the receiver (interior + shadow term,
-  through the shading point) must match.
+  through the shading point) must match;
+* interior edges: the same two checks with two triangles folded along a
+  shared edge, so that the silhouette (from the camera, or from the shading
+  point toward the light) runs along an edge with a face on either side.
 """
 import math
 
@@ -189,3 +192,194 @@ def test_shadow_boundary_term_matches_fd_of_clipped_lambert(orc):
     e = np.array([0, 0, h])
     fd = 3 * rho / math.pi * (_visible_phi(x0 + e, nz, light, occ64) - _visible_phi(x0 - e, nz, light, occ64)) / (2 * h)
     assert abs(m - fd) < 5 * se + 1e-6 * abs(fd), (m, fd, se)
+
+
+# ---------------------------------------------------------------------------
+# Interior edges.  Every case above uses isolated triangles, whose edges are
+# all boundary edges.  Here two triangles share an edge and are folded along
+# it, so that the shared (interior) edge is a silhouette: seen from the
+# camera for the camera-silhouette term, seen from the shading point for the
+# shadow-boundary term.  The second triangle is folded behind the first, so
+# the visible (or shadowing) region is exactly the first triangle and the
+# closed forms stay a convex clip; an estimator that dropped interior
+# silhouette edges (or misclassified them) loses the boundary term along the
+# shared edge and fails the finite difference.
+
+def _shared_mesh(verts, faces, albedo):
+    pos = np.ascontiguousarray(np.asarray(verts, np.float32).T)
+    fa = np.asarray(faces, np.int32)
+    alb = np.full((3, pos.shape[1]), albedo, np.float32)
+    return synth.Mesh(pos, fa, alb, np.full((2, pos.shape[1]), 0.5, np.float32))
+
+
+def _vertex_normals(verts, faces):
+    """Normalised sums of the face cross products around each vertex."""
+    vs = np.asarray(verts, float)
+    acc = np.zeros_like(vs)
+    for f in faces:
+        n = np.cross(vs[f[1]] - vs[f[0]], vs[f[2]] - vs[f[0]])
+        for k in f:
+            acc[k] += n
+    return acc / np.linalg.norm(acc, axis=1, keepdims=True)
+
+
+FOLD_FACES = [(0, 2, 1), (0, 1, 3)]     # front face (A, C1, B); folded face (A, B, C2)
+
+
+def _fold_image_integral(verts, light, rgb, albedo, W, H, cam, ps):
+    """Exact sum over pixels of the box-filtered radiance of the folded pair
+    when the folded face hides behind the front face: the image of the front
+    face, shaded with its interpolated vertex normals.  Radiance at x is
+    rho/pi * n_s(x) . Gamma(x), Gamma the light's irradiance vector (Lambert's
+    formula is linear in the normal; the light lies above every n_s)."""
+    cam = np.asarray(cam, float)
+    vs = np.asarray(verts, float)
+    nv = _vertex_normals(vs, FOLD_FACES)
+    f = FOLD_FACES[0]
+    P = vs[list(f)]
+    ng = np.cross(P[1] - P[0], P[2] - P[0])
+    scr = []
+    for x in P:
+        r = x - cam
+        scr.append([W / 2 + (r[0] / -r[2]) / ps, H / 2 - (r[1] / -r[2]) / ps])
+    poly = _clip_rect(scr, W, H)
+    corners = cf.quad_corners(light)
+    M = np.stack([P[1] - P[0], P[2] - P[0]], axis=1)
+    total = 0.0
+    for k in range(1, len(poly) - 1):
+        pts, wts = _tri_gauss([poly[0], poly[k], poly[k + 1]])
+        for (qx, qy), w in zip(pts, wts):
+            d = np.array([(qx - W / 2) * ps, (H / 2 - qy) * ps, -1.0])
+            t = ((P[0] - cam) @ ng) / (d @ ng)
+            x = cam + t * d
+            b12 = np.linalg.lstsq(M, x - P[0], rcond=None)[0]
+            b = np.array([1 - b12.sum(), b12[0], b12[1]])
+            ns = b @ nv[list(f)]
+            ns /= np.linalg.norm(ns)
+            total += w * albedo / math.pi * cf.projected_solid_angle(x, ns, corners)
+    return total * np.asarray(rgb, float)
+
+
+def test_camera_silhouette_on_interior_edge_matches_fd(orc):
+    W = H = 16
+    ps = np.float32(0.01)
+    cam = np.array([0.0, 0.0, 0.5])
+    # A, B: the shared edge; C1 completes the front face, C2 the face folded
+    # back under it (its image lies inside the front face's image)
+    verts = np.array([[-0.02, 0.01, 0.0], [0.02, 0.012, 0.002], [0.0, -0.02, 0.0],
+                      [0.0, -0.005, -0.02]], np.float32)
+    v64 = verts.astype(np.float64)
+    n1 = np.cross(v64[2] - v64[0], v64[1] - v64[0])
+    n2 = np.cross(v64[1] - v64[0], v64[3] - v64[0])
+    assert (n1 @ (cam - v64[0]) > 0) and (n2 @ (cam - v64[0]) < 0)     # a silhouette from the camera
+    light = synth.quad_light([0.02, 0.2, 0.35], [0.1, 0, 0], [0, -0.06, 0.08])
+    rgb = np.array([[0.9, 0.6, 0.3]])
+    rho = 0.7
+    # the light lies above every shading normal of the front face and faces it
+    nv = _vertex_normals(v64, FOLD_FACES)
+    for c in cf.quad_corners(light):
+        for k in (0, 1, 2):
+            assert nv[k] @ (c - v64[k]) > 0
+            assert light[9:12].astype(float) @ (v64[k] - c) > 0
+    osc = orc.scene_from_mesh(_shared_mesh(verts, FOLD_FACES, rho), W, H, cam, ps, light, rgb,
+                              np.zeros(1024))
+    edges = orc.build_edges(np.asarray(FOLD_FACES, np.int32), 4)
+    assert (edges[:, 3] >= 0).sum() == 1                                   # one interior edge
+    dL = np.ones((H, W, 3))
+    samples = []
+    for s in range(N_SEEDS):
+        g = orc.backward(osc, 9000 + s, 1, dL, flags=orc.FLAG_INTERIOR | orc.FLAG_PRIMARY, threads=1)
+        samples.append(g["d_pos"].copy())
+    samples = np.array(samples)
+    mean, sem = samples.mean(0), samples.std(0, ddof=1) / math.sqrt(N_SEEDS)
+    h = 1e-6
+    for k in range(4):
+        for c in range(3):
+            vp, vm = v64.copy(), v64.copy()
+            vp[k, c] += h
+            vm[k, c] -= h
+            fd = (_fold_image_integral(vp, light, rgb[0], rho, W, H, cam, float(ps)).sum()
+                  - _fold_image_integral(vm, light, rgb[0], rho, W, H, cam, float(ps)).sum()) / (2 * h)
+            z = abs(mean[c, k] - fd) / max(sem[c, k], 1e-12)
+            assert z < 5.0, (k, c, mean[c, k], fd, sem[c, k])
+    # the shared edge's boundary term matters: the interior term alone misses
+    # the motion of the fold line on the image (vertices A and B)
+    g0 = np.mean([orc.backward(osc, 9000 + s, 1, dL, flags=orc.FLAG_INTERIOR, threads=1)["d_pos"]
+                  for s in range(20)], axis=0)
+    assert np.abs(g0[:, :2] - mean[:, :2]).max() > 20 * sem[:, :2].max()
+
+
+def test_shadow_boundary_on_interior_edge_matches_fd(orc):
+    cam = np.array([0.0, 0.0, 0.5])
+    ps = np.float32(1e-7)
+    light = synth.quad_light([0.35, 0.0, 0.6], [0.15, 0, 0], [0, -0.15, 0])
+    # occluder: front face (A, C1, B) in the plane z = 0.3 seen from the
+    # receiver point, and a face (A, B, C2) folded over it toward the light,
+    # hidden behind it from the receiver point; the fold line A-B crosses
+    # the light's image
+    A, B, C1 = np.array([0.16, -0.02, 0.3]), np.array([0.20, 0.03, 0.3]), np.array([0.12, 0.06, 0.3])
+    C2 = (A + B + C1) / 3 * 1.15
+    occ = np.array([A, B, C1, C2], np.float32)
+    rec = np.array([[-0.01, -0.01, 0.0], [0.01, -0.01, 0.0], [0.01, 0.01, 0.0], [-0.01, 0.01, 0.0]],
+                   np.float32)
+    verts = np.concatenate([rec, occ])
+    faces = [(0, 1, 2), (0, 2, 3), (4, 6, 5), (4, 5, 7)]
+    rho, l = 0.8, np.array([[1.0, 1.0, 1.0]])
+    osc = orc.scene_from_mesh(_shared_mesh(verts, faces, rho), 1, 1, cam, ps, light, l, np.zeros(1024))
+    x0 = np.zeros(3)
+    nz = np.array([0, 0, 1.0])
+    o64 = occ.astype(np.float64)
+    n1 = np.cross(o64[2] - o64[0], o64[1] - o64[0])
+    n2 = np.cross(o64[1] - o64[0], o64[3] - o64[0])
+    assert (n1 @ (x0 - o64[0])) * (n2 @ (x0 - o64[0])) < 0                # a silhouette from the point
+
+    def visible(o):
+        # the folded face hides behind the front face, so the shadow is the
+        # front face's central projection clipped to the light
+        return _visible_phi(x0, nz, light, o[[0, 2, 1]])
+
+    def visible_all(o):
+        corners = cf.quad_corners(light)
+        lp, ln = np.asarray(light[:3], float), np.asarray(light[9:12], float)
+        p1 = cf.clip_convex(cf.project_to_plane(x0, o[[0, 2, 1]], lp, ln), corners)
+        p2 = cf.clip_convex(cf.project_to_plane(x0, o[[0, 1, 3]], lp, ln), corners)
+        p12 = cf.clip_convex(p2, cf.project_to_plane(x0, o[[0, 2, 1]], lp, ln))
+        ar = lambda p: cf.projected_solid_angle(x0, nz, p) if len(p) >= 3 else 0.0
+        return cf.projected_solid_angle(x0, nz, corners) - ar(p1) - ar(p2) + ar(p12)
+    # the hidden face really is hidden, and the fold really half-shadows the point
+    assert abs(visible(o64) - visible_all(o64)) < 1e-12
+    full = cf.projected_solid_angle(x0, nz, cf.quad_corners(light))
+    assert 0.2 * full < visible(o64) < 0.9 * full
+    spp = 4096
+    dL = np.ones((1, 1, 3))
+    gs, gi = [], []
+    for s in range(N_SEEDS // 4):
+        g = orc.backward(osc, 11000 + s, spp, dL, flags=orc.FLAG_INTERIOR | orc.FLAG_SECONDARY, threads=4)
+        gs.append(g["d_pos_secondary"].copy())
+        gi.append(g["d_pos_interior"].copy())
+    gs, gi = np.array(gs), np.array(gi)
+    n = gs.shape[0]
+    mean, sem = gs.mean(0), gs.std(0, ddof=1) / math.sqrt(n)
+    h = 1e-6
+    moved = 0.0
+    for k in range(4):
+        for c in range(3):
+            op, om = o64.copy(), o64.copy()
+            op[k, c] += h
+            om[k, c] -= h
+            fd = 3 * rho / math.pi * (visible(op) - visible(om)) / (2 * h)
+            vi = 4 + k
+            z = abs(mean[c, vi] - fd) / max(sem[c, vi], 1e-12)
+            assert z < 5.0, (k, c, mean[c, vi], fd, sem[c, vi])
+            if k < 2:
+                moved = max(moved, abs(fd) / max(sem[c, vi], 1e-12))
+    # the fold line's vertices carry a derivative far above the noise, so a
+    # term without the shared edge (zero there) would fail the loop above
+    assert moved > 20.0, moved
+    tot = gs + gi
+    lift = tot[:, 2, :4].sum(axis=1)
+    m, se = lift.mean(), lift.std(ddof=1) / math.sqrt(n)
+    e = np.array([0, 0, h])
+    fdl = 3 * rho / math.pi * (_visible_phi(x0 + e, nz, light, o64[[0, 2, 1]])
+                               - _visible_phi(x0 - e, nz, light, o64[[0, 2, 1]])) / (2 * h)
+    assert abs(m - fdl) < 5 * se + 1e-6 * abs(fdl), (m, fdl, se)

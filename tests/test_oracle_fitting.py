@@ -52,3 +52,26 @@ def test_adam_matches_torch_optim():
         opt.step()
         p, m, v = fitting.adam(p, g, m, v, t, 0.03, 0.85, 0.995, 1e-7)
     np.testing.assert_allclose(p, w.detach().numpy(), rtol=1e-12, atol=1e-14)
+
+
+def test_loss_l2_against_its_definition_and_fd():
+    """E_data (Eq. 1): the sum over pixels and channels of squared
+    differences, checked by an explicit loop on a small ragged image, and its
+    gradient by central differences (exact: the loss is quadratic)."""
+    import oracle
+    rng = np.random.default_rng(3)
+    I, T = rng.uniform(0, 0.2, (3, 5, 3)), rng.uniform(0, 0.2, (3, 5, 3))
+    L, g = oracle.loss_l2(I, T)
+    brute = 0.0
+    for y in range(3):
+        for x in range(5):
+            for c in range(3):
+                brute += (I[y, x, c] - T[y, x, c]) ** 2
+    assert abs(L - brute) <= 1e-15 * brute
+    h = 1e-4
+    for idx in [(0, 0, 0), (2, 4, 2), (1, 3, 1)]:
+        Ip, Im = I.copy(), I.copy()
+        Ip[idx] += h
+        Im[idx] -= h
+        fd = (oracle.loss_l2(Ip, T)[0] - oracle.loss_l2(Im, T)[0]) / (2 * h)
+        assert abs(fd - g[idx]) <= 1e-9 * max(1.0, abs(g[idx]))

@@ -112,3 +112,19 @@ def test_edge_counts_match_configs(orc):
         assert faces.shape[0] == F
         ed = orc.build_edges(faces, c["nx"] * c["ny"])
         assert ed.shape[0] == E and (ed[:, 3] < 0).sum() == nb
+
+
+def test_oracle_pins_clean_under_address_and_ub_sanitizers():
+    """The oracle's C code, built with -fsanitize=address,undefined, passes
+    its estimator pins with no sanitizer report (oracle/sanitize.py)."""
+    import os
+    import subprocess
+    import sys
+    if os.environ.get("LD_PRELOAD") or os.environ.get("FACERT_ORACLE_SANITIZE"):
+        import pytest
+        pytest.skip("a preload is already set, or this is the sanitized run itself")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, "-m", "oracle.sanitize", "-x", "-k",
+                        "not unet and not sanitizers"], cwd=root, capture_output=True, text=True, timeout=900)
+    assert r.returncode == 0, r.stdout[-3000:] + r.stderr[-3000:]
+    assert " passed" in r.stdout and "ERROR: AddressSanitizer" not in r.stderr + r.stdout
