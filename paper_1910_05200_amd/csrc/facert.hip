@@ -1942,28 +1942,28 @@ __global__ __launch_bounds__(BS) void k_loss_final(int nb, const double *__restr
 // interpolated vertex albedo), unit shading normal (turned toward the
 // camera) and distance from the camera; a miss contributes zeros.  One lane
 // per pixel, reading the render's hit records (its samples are adjacent).
-__global__ __launch_bounds__(256) void k_aov(Scene S, int spp, const HitRec *__restrict__ hits, float *__restrict__ out) {
+__global__ __launch_bounds__(256) void k_aov(Scene S, uint64_t seed, int spp, const HitRec *__restrict__ hits,
+                                            float *__restrict__ out) {
     int pix = blockIdx.x * blockDim.x + threadIdx.x;
     if (pix >= S.W * S.H) return;
     const v3 cam = mk(S.cam_x, S.cam_y, S.cam_z);
     float acc[7] = {0, 0, 0, 0, 0, 0, 0};
     for (int k = 0; k < spp; ++k) {
-        HitRec rec = hits[(size_t)pix * spp + k];
+        uint32_t s = (uint32_t)((size_t)pix * spp + k);
+        HitRec rec = hits[s];
         if (rec.tri < 0) continue;
         Hit h = hit_of(rec);
+        int px;
+        v3 d = camera_sample(S, seed, s, spp, px);
         SurfDec sd;
         surf_decide(S, cam, h, sd);
-        const int *tr = S.faces + 3 * h.tri;
-        float b1 = h.b1, b2 = h.b2, b0 = (1.0f - b1) - b2;
-        for (int c = 0; c < 3; ++c) {
-            const float *A = S.alb + (size_t)c * S.V;
-            acc[c] += (b0 * A[tr[0]] + b1 * A[tr[1]]) + b2 * A[tr[2]];
-        }
-        float nl = sqrtf(dot(sd.nu, sd.nu));
-        float sg = sd.front ? 1.0f : -1.0f;
-        if (nl > 0.0f) { acc[3] += sg * sd.nu.x / nl; acc[4] += sg * sd.nu.y / nl; acc[5] += sg * sd.nu.z / nl; }
-        v3 r = sd.p - cam;
-        acc[6] += sqrtf(dot(r, r));
+        // the value path's surface: barycentrics re-solved in fp64, as the
+        // shading uses them
+        Surf<float> sv;
+        surf_value<float>(S, S.spec, cam, d, h, sd, sv);
+        for (int c = 0; c < 3; ++c) acc[c] += sv.A[c];
+        acc[3] += sv.ns.x; acc[4] += sv.ns.y; acc[5] += sv.ns.z;
+        acc[6] += sv.olen;
     }
     float inv = 1.0f / (float)spp;
     for (int c = 0; c < 7; ++c) out[(size_t)pix * 7 + c] = acc[c] * inv;
@@ -2787,7 +2787,8 @@ int fr_aov(fr_ctx *c, float *out) {
     if (!c->have_render || !c->records_valid)
         return fail(c, FR_ESTATE, "fr_aov: needs a prior fr_render whose samples fit one chunk");
     Scene S = make_scene(c);
-    hipLaunchKernelGGL(k_aov, dim3(nblk((size_t)c->W * c->H, 256)), dim3(256), 0, c->stream, S, c->last_spp, c->hits, out);
+    hipLaunchKernelGGL(k_aov, dim3(nblk((size_t)c->W * c->H, 256)), dim3(256), 0, c->stream, S, c->last_seed, c->last_spp,
+                       c->hits, out);
     HIPCK(c, hipGetLastError());
     return FR_OK;
 }
