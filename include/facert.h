@@ -196,6 +196,24 @@ int fr_backward(fr_ctx *ctx, const float *dL_dimage, const fr_grads *grads);
 int fr_loss_l2(fr_ctx *ctx, const float *image, const float *target,
                float *dL_dimage, float *loss_dev);
 
+/* fr_loss_l2 for callers that cannot allocate device memory: code being
+ * captured into a HIP graph, tight serving or fitting loops, harnesses that
+ * forbid hipMalloc.  Needs no context: n elements (1 .. FR_LOSS_NOALLOC_MAX)
+ * of image and target (device), dL_dimage = 2 (image - target) and
+ * *loss_dev = sum (image - target)^2 (either output may be NULL), enqueued
+ * on hip_stream (a hipStream_t; NULL: the null stream) of the current
+ * device.  The same kernels as fr_loss_l2, with their fp64 block partial
+ * sums (one per 256 elements) in a fixed array that the library keeps on
+ * each device it runs on (512 KiB, held until the process ends) instead of
+ * a context's buffer: no call allocates.  Calls on one device share that
+ * array, so two calls that overlap on one device (different streams, no
+ * ordering between them) race and may return a wrong loss; order them.
+ * Errors: FR_EINVAL (null image or target, n out of range; nothing is
+ * enqueued), FR_EDEVICE; the message is fr_last_error(NULL). */
+#define FR_LOSS_NOALLOC_MAX (1 << 24)
+int fr_loss_l2_noalloc(void *hip_stream, const float *image, const float *target, int64_t n,
+                       float *dL_dimage, float *loss_dev);
+
 /* Auxiliary buffers of the last render, for the denoiser (fadenoise.h):
  * out [H][W][7] (device) = per pixel, the mean over its samples of the
  * first hit's albedo (RGB), unit shading normal turned toward the camera
@@ -227,7 +245,8 @@ int fr_adam(fr_ctx *ctx, float *param, const float *grad, float *m, float *v, in
 int fr_stats(fr_ctx *ctx, fr_stats_t *out);
 
 /* Message of the last error on this context ("" if none); valid until the
- * next call on the context.  Accepts NULL (returns a static string). */
+ * next call on the context.  With NULL: the message of this thread's last
+ * failed context-free call (fr_loss_l2_noalloc), or a static string. */
 const char *fr_last_error(const fr_ctx *ctx);
 
 /* Release all device memory of the context (synchronises its stream). */

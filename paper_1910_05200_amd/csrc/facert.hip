@@ -33,6 +33,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -2871,7 +2872,63 @@ int fr_stats(fr_ctx *c, fr_stats_t *out) {
     return FR_OK;
 }
 
-const char *fr_last_error(const fr_ctx *c) { return c ? c->err.c_str() : kNoCtx; }
+// ---------------------------------------------- loss without allocation --
+// fr_loss_l2_noalloc: the kernels of fr_loss_l2 with their block partials in
+// a file-scope device array instead of a context's buffer, so the call needs
+// no context and allocates nothing.  Each device the library runs on holds
+// its own copy of the array until the process ends.  Host code never uses
+// the array's name (on the host it is only a stand-in for the symbol): it
+// asks the runtime for the array's address on the current device once, on
+// that device's first call, and keeps it per device.
+static __device__ __align__(256) double scratch[FR_LOSS_NOALLOC_MAX / 256];
+
+static std::mutex g_scratch_mu;
+static double *g_scratch_dev[64];          // per device ordinal
+static thread_local std::string g_noctx_err;
+
+static int noctx_fail(int code, const char *msg) {
+    g_noctx_err = msg;
+    return code;
+}
+
+static int scratch_on_current_device(double **out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return noctx_fail(FR_EDEVICE, hipGetErrorString(e));
+    if (dev < 0 || dev >= 64) return noctx_fail(FR_EDEVICE, "fr_loss_l2_noalloc: device ordinal above 63");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) return noctx_fail(FR_EDEVICE, e != hipSuccess ? hipGetErrorString(e)
+                                                                             : "fr_loss_l2_noalloc: null scratch");
+        g_scratch_dev[dev] = (double *)p;
+    }
+    *out = g_scratch_dev[dev];
+    return FR_OK;
+}
+
+int fr_loss_l2_noalloc(void *hip_stream, const float *img, const float *tgt, int64_t n, float *dL, float *loss) {
+    g_noctx_err.clear();
+    if (!img || !tgt) return noctx_fail(FR_EINVAL, "fr_loss_l2_noalloc: null image or target");
+    if (n < 1 || n > (int64_t)FR_LOSS_NOALLOC_MAX)
+        return noctx_fail(FR_EINVAL, "fr_loss_l2_noalloc: n outside 1 .. FR_LOSS_NOALLOC_MAX (16,777,216)");
+    double *part = nullptr;
+    int rc = scratch_on_current_device(&part);
+    if (rc != FR_OK) return rc;
+    hipStream_t st = (hipStream_t)hip_stream;
+    int nb = (int)nblk((size_t)n, 256);
+    hipLaunchKernelGGL(k_loss_partial<256>, dim3(nb), dim3(256), 0, st, (size_t)n, img, tgt, dL, part);
+    if (loss) hipLaunchKernelGGL(k_loss_final<256>, dim3(1), dim3(256), 0, st, nb, (const double *)part, loss);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return noctx_fail(FR_EDEVICE, hipGetErrorString(e));
+    return FR_OK;
+}
+
+const char *fr_last_error(const fr_ctx *c) {
+    if (c) return c->err.c_str();
+    return g_noctx_err.empty() ? kNoCtx : g_noctx_err.c_str();
+}
 
 void fr_destroy(fr_ctx *c) {
     if (!c) return;

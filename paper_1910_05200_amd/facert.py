@@ -77,7 +77,7 @@ class fr_launch(C.Structure):
 FR_LAUNCH_FLAT, FR_LAUNCH_XCD = 0, 1
 
 EXPORTS = ("fr_create", "fr_set_stream", "fr_set_terms", "fr_set_chunk", "fr_blend", "fr_render", "fr_backward",
-           "fr_loss_l2", "fr_aov", "fr_light_reg", "fr_adam", "fr_stats", "fr_last_error", "fr_destroy",
+           "fr_loss_l2", "fr_loss_l2_noalloc", "fr_aov", "fr_light_reg", "fr_adam", "fr_stats", "fr_last_error", "fr_destroy",
            "fr_batch_create", "fr_batch_set_stream", "fr_batch_render", "fr_batch_backward", "fr_batch_num_kinds",
            "fr_batch_kind_name", "fr_batch_get_launch", "fr_batch_set_launch", "fr_batch_tune", "fr_batch_timing",
            "fr_batch_capture_begin", "fr_batch_capture_end", "fr_batch_graph_launch", "fr_batch_last_error",
@@ -117,6 +117,7 @@ def load():
         L.fr_render.argtypes = [vp, C.POINTER(fr_params), u64, i32, vp]
         L.fr_backward.argtypes = [vp, vp, C.POINTER(fr_grads)]
         L.fr_loss_l2.argtypes = [vp] * 5
+        L.fr_loss_l2_noalloc.argtypes = [vp, vp, vp, C.c_int64, vp, vp]
         L.fr_aov.argtypes = [vp, vp]
         L.fr_light_reg.argtypes = [vp, vp, C.c_float, vp, vp]
         L.fr_adam.argtypes = [vp, vp, vp, vp, vp, i32, i32, C.c_float, C.c_float, C.c_float, C.c_float]
@@ -424,6 +425,24 @@ class Batch:
     def graph_launch(self):
         self._stream()
         _bcheck(self.b, load().fr_batch_graph_launch(self.b))
+
+
+def loss_l2_noalloc(image, target, dL=None, loss=None, want_dL=True):
+    """fr_loss_l2_noalloc on torch's current stream: E_data and 2 (I - T) of
+    n = image.numel() elements with no context and no device allocation by
+    the library (outputs are written into dL / loss when given, else new
+    tensors).  Returns (dL or None, loss)."""
+    import torch
+    assert image.is_contiguous() and target.is_contiguous() and image.numel() == target.numel()
+    if want_dL and dL is None:
+        dL = torch.empty_like(image)
+    if loss is None:
+        loss = torch.empty((), device=image.device, dtype=torch.float32)
+    code = load().fr_loss_l2_noalloc(torch.cuda.current_stream().cuda_stream, _ptr(image), _ptr(target),
+                                     image.numel(), _ptr(dL) if want_dL else None, _ptr(loss))
+    if code != 0:
+        raise FrError(code, load().fr_last_error(None).decode())
+    return dL, loss
 
 
 def params_to_device(params, device="cuda"):

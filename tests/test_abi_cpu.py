@@ -45,6 +45,13 @@ def test_null_context_and_argument_errors_without_gpu():
     assert lib.fr_set_chunk(None, 1024) == -1
     assert lib.fr_last_error(None) == b"no context"
     lib.fr_destroy(None)
+    # the context-free loss rejects its arguments before touching a device
+    assert lib.fr_loss_l2_noalloc(None, None, None, 12, None, None) == -1
+    assert b"null" in lib.fr_last_error(None)
+    buf = (C.c_float * 4)()
+    assert lib.fr_loss_l2_noalloc(None, buf, buf, 0, None, None) == -1
+    assert lib.fr_loss_l2_noalloc(None, buf, buf, (1 << 24) + 1, None, None) == -1
+    assert b"FR_LOSS_NOALLOC_MAX" in lib.fr_last_error(None)
     # invalid model: zero vertices
     md = facert.fr_model_desc()
     sd = facert.fr_scene_desc()
