@@ -148,16 +148,16 @@ __global__ __launch_bounds__(256) void k_normals(int V, const int *__restrict__ 
 constexpr int kRefitLeaves = 512;
 struct SubTree { int node, slot, count, height; };
 
-__device__ __forceinline__ void refit_union(uint4 *nodes, int n, int r, int esc) {
-    QBox L = qbox(nodes[n + 1]), R = qbox(nodes[r]);   // binary16 values: the union re-encodes exactly
-    nodes[n] = qnode(fminf(L.lx, R.lx), fminf(L.ly, R.ly), fminf(L.lz, R.lz),
+__device__ __forceinline__ void refit_union(Node *nodes, int n, int r, int esc) {
+    NBox L = node_box(nodes[n + 1]), R = node_box(nodes[r]);
+    nodes[n] = make_node(fminf(L.lx, R.lx), fminf(L.ly, R.ly), fminf(L.lz, R.lz),
                      fmaxf(L.hx, R.hx), fmaxf(L.hy, R.hy), fmaxf(L.hz, R.hz), esc);
 }
 
 __global__ __launch_bounds__(256) void k_refit_sub(const SubTree *__restrict__ subs, const int *__restrict__ faces,
         const float *__restrict__ pos, int V, const int *__restrict__ sorted_tri, const int *__restrict__ leaf_node,
         const int *__restrict__ height, const int *__restrict__ right, const int *__restrict__ escape,
-        uint4 *nodes, float4 *__restrict__ tris) {
+        Node *nodes, float4 *__restrict__ tris) {
     const SubTree st = subs[blockIdx.x];
     for (int i = st.slot + threadIdx.x; i < st.slot + st.count; i += blockDim.x) {
         int f = sorted_tri[i];
@@ -166,7 +166,7 @@ __global__ __launch_bounds__(256) void k_refit_sub(const SubTree *__restrict__ s
         tris[3 * i] = make_float4(a.x, a.y, a.z, b.x);
         tris[3 * i + 1] = make_float4(b.y, b.z, c.x, c.y);
         tris[3 * i + 2] = make_float4(c.z, __int_as_float(f), 0.0f, 0.0f);
-        nodes[leaf_node[i]] = qnode(fminf(fminf(a.x, b.x), c.x) - kBoxPad, fminf(fminf(a.y, b.y), c.y) - kBoxPad,
+        nodes[leaf_node[i]] = make_node(fminf(fminf(a.x, b.x), c.x) - kBoxPad, fminf(fminf(a.y, b.y), c.y) - kBoxPad,
                                     fminf(fminf(a.z, b.z), c.z) - kBoxPad, fmaxf(fmaxf(a.x, b.x), c.x) + kBoxPad,
                                     fmaxf(fmaxf(a.y, b.y), c.y) + kBoxPad, fmaxf(fmaxf(a.z, b.z), c.z) + kBoxPad, ~i);
     }
@@ -179,7 +179,7 @@ __global__ __launch_bounds__(256) void k_refit_sub(const SubTree *__restrict__ s
 }
 
 __global__ __launch_bounds__(256) void k_refit_top(int n_top, const int *__restrict__ top, const int *__restrict__ top_off,
-        int top_levels, const int *__restrict__ right, const int *__restrict__ escape, uint4 *nodes) {
+        int top_levels, const int *__restrict__ right, const int *__restrict__ escape, Node *nodes) {
     for (int lv = 0; lv < top_levels; ++lv) {
         for (int k = top_off[lv] + threadIdx.x; k < top_off[lv + 1]; k += blockDim.x) {
             int n = top[k];
@@ -2034,7 +2034,7 @@ struct fr_ctx {
     SubTree *subs = nullptr; int n_subs = 0;
     LbvhBufs lb{};                 // per-evaluation build (without FR_REFIT)
     int *height = nullptr, *top = nullptr, *top_off = nullptr; int n_top = 0, top_levels = 0;
-    uint4 *nodes = nullptr;
+    Node *nodes = nullptr;
     float4 *tris = nullptr;
     // per evaluation (device)
     double *vm_d = nullptr;

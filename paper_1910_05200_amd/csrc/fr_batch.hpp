@@ -52,7 +52,7 @@ struct Inst {
     int *tbl_edge, *tbl_n, *tbl_guide;
     float4 *edge_rec;
     uint64_t *tbl_prefix, *tbl_Q;
-    uint4 *nodes;
+    Node *nodes;
     float4 *tris;
     LbvhBufs lb;
     HitRec *hits;

@@ -27,7 +27,7 @@ constexpr float kEdgeOffM = 2e-5f;       // shadow-boundary sides, in metres
 constexpr float kQScale = 1048576.0f;    // 2^20 edge-weight quantisation
 constexpr double kBeckmannM = 0.35;
 constexpr double kPi = 3.14159265358979323846;
-constexpr float kSlabGrow = 1.0000004f;  // 1 + 2 gamma_3 (Ize 2013)
+constexpr float kSlabGrow = 1.0000004f;  // far-time growth of the slab test (see traversal)
 constexpr int kMaxLights = 64;
 
 template <class T> struct vec3 { T x, y, z; };
@@ -69,6 +69,7 @@ __device__ __forceinline__ u4 philox(uint64_t key, uint32_t c0, uint32_t c1, uin
 __device__ __forceinline__ float u01(uint32_t w) { return (float)(w >> 8) * (1.0f / 16777216.0f); }
 
 // ------------------------------------------------------ scene on device --
+using Node = uint4;
 struct Scene {
     int V, F, W, H, nl, res, n_nodes, E;
     float cam_x, cam_y, cam_z, ps;
@@ -77,7 +78,7 @@ struct Scene {
     const float *nrm;          // [3][V]
     const float *alb;          // [3][V]
     const float *uv;           // [2][V]
-    const uint4 *nodes;        // [n_nodes]: fp16 box + link (see QNode below)
+    const Node *nodes;         // [n_nodes]: binary16 box + link (see the traversal)
     const float4 *tris;        // [3 F]: v0 v1 v2, original index
     const float *lgeom;        // [nl][12]
     const float *lrgb;         // [nl][3]
@@ -139,9 +140,25 @@ __device__ __forceinline__ bool ray_tri(v3 o, v3 d, v3 v0, v3 v1, v3 v2, float t
 //
 // A node is 16 bytes, one vector load: its box as six binary16 values,
 // lo rounded toward -inf and hi toward +inf so that the stored box always
-// contains the fp32 one, and a link word: >= 0 the escape index of an
+// contains the fp32 one (the triangle boxes padded by kBoxPad, internal
+// boxes their unions), and a link word: >= 0 the escape index of an
 // internal node, < 0 the complement of a leaf's triangle slot.  Boxes only
-// cull, so a box that is slightly larger changes the work, never a result.
+// cull, so a box test may err toward entering; it must never reject a box
+// that holds an accepted hit.  (32-byte fp32 nodes save the six conversions
+// but were slower: the walk is bound by the bytes each visit moves.)
+//
+// Why the slab test below cannot reject such a box: a ray/triangle test
+// accepts only a hit point within the triangle's box widened by kHitMargin,
+// and every box of the tree holds that triangle's box widened by kBoxPad =
+// 2 kHitMargin, so the exact ray is at least kHitMargin (minus the hit
+// point's own fp32 rounding, ~1e-7 m) inside every slab of every box on the
+// way to an accepted hit.  In parameter units that is a margin of
+// kHitMargin / |d_i| on each axis i.  The slab times are computed as
+// fma(bound, 1/d_i, -o_i/d_i) with o_i/d_i rounded once per ray; their
+// absolute error is below (|bound - o_i| + |o_i|) * 2^-22 / |d_i|, under
+// 1e-6 / |d_i| for scenes within a few metres of the origin, an order of
+// magnitude inside the margin.  The growth factor on the far time keeps the
+// test conservative at the clamps (t = 0, t = thi) as well.
 __device__ __forceinline__ float h2f(uint32_t bits16) {
     return (float)__builtin_bit_cast(_Float16, (uint16_t)bits16);
 }
@@ -155,36 +172,43 @@ __device__ __forceinline__ uint32_t f2h_dir(float x, bool up) {
     else if (!up && b > x) u = neg ? u + 1u : (u == 0u ? 0x8001u : u - 1u);
     return u;
 }
-struct QBox { float lx, ly, lz, hx, hy, hz; };
-__device__ __forceinline__ QBox qbox(uint4 q) {
-    QBox b;
+struct NBox { float lx, ly, lz, hx, hy, hz; };
+__device__ __forceinline__ NBox node_box(const Node &q) {
+    NBox b;
     b.lx = h2f(q.x & 0xffffu); b.ly = h2f(q.x >> 16); b.lz = h2f(q.y & 0xffffu);
     b.hx = h2f(q.y >> 16); b.hy = h2f(q.z & 0xffffu); b.hz = h2f(q.z >> 16);
     return b;
 }
-__device__ __forceinline__ uint4 qnode(float lx, float ly, float lz, float hx, float hy, float hz, int link) {
-    uint4 q;
+__device__ __forceinline__ Node make_node(float lx, float ly, float lz, float hx, float hy, float hz, int link) {
+    Node q;
     q.x = f2h_dir(lx, false) | (f2h_dir(ly, false) << 16);
     q.y = f2h_dir(lz, false) | (f2h_dir(hx, true) << 16);
     q.z = f2h_dir(hy, true) | (f2h_dir(hz, true) << 16);
     q.w = (uint32_t)link;
     return q;
 }
+__device__ __forceinline__ int node_link(const Node &q) { return (int)q.w; }
+// node i of the array, addressed with a 32-bit byte offset from the base
+__device__ __forceinline__ Node load_node(const Node *nodes, int i) {
+    const char *base = reinterpret_cast<const char *>(nodes);
+    return *reinterpret_cast<const Node *>(base + ((uint32_t)i << 4));
+}
 
 struct Ray {
-    v3 o, d, id;   // origin, direction, 1/direction (tiny components clamped)
+    v3 o, d, id, oid;   // origin, direction, 1/direction (tiny components clamped), o/d
 };
 __device__ __forceinline__ float safe_inv(float x) {
     return 1.0f / (fabsf(x) < 1e-20f ? copysignf(1e-20f, x) : x);
 }
 __device__ __forceinline__ Ray make_ray(v3 o, v3 d) {
     Ray r; r.o = o; r.d = d; r.id = mk(safe_inv(d.x), safe_inv(d.y), safe_inv(d.z));
+    r.oid = mk(o.x * r.id.x, o.y * r.id.y, o.z * r.id.z);
     return r;
 }
-__device__ __forceinline__ bool slab(const Ray &r, const QBox &b, float thi) {
-    float tx0 = (b.lx - r.o.x) * r.id.x, tx1 = (b.hx - r.o.x) * r.id.x;
-    float ty0 = (b.ly - r.o.y) * r.id.y, ty1 = (b.hy - r.o.y) * r.id.y;
-    float tz0 = (b.lz - r.o.z) * r.id.z, tz1 = (b.hz - r.o.z) * r.id.z;
+__device__ __forceinline__ bool slab(const Ray &r, const NBox &b, float thi) {
+    float tx0 = fmaf(b.lx, r.id.x, -r.oid.x), tx1 = fmaf(b.hx, r.id.x, -r.oid.x);
+    float ty0 = fmaf(b.ly, r.id.y, -r.oid.y), ty1 = fmaf(b.hy, r.id.y, -r.oid.y);
+    float tz0 = fmaf(b.lz, r.id.z, -r.oid.z), tz1 = fmaf(b.hz, r.id.z, -r.oid.z);
     float tn = fmaxf(fmaxf(fminf(tx0, tx1), fminf(ty0, ty1)), fmaxf(fminf(tz0, tz1), 0.0f));
     float tf = fminf(fminf(fmaxf(tx0, tx1), fmaxf(ty0, ty1)), fminf(fmaxf(tz0, tz1), thi));
     return tn <= tf * kSlabGrow;
@@ -200,10 +224,10 @@ __device__ inline Hit trace_closest(const Scene &S, v3 o, v3 d, Work &wk) {
     Hit h; h.tri = -1; h.t = INFINITY; h.b1 = h.b2 = h.det = 0.0f;
     int node = 0;
     while (node < S.n_nodes) {
-        uint4 q = S.nodes[node];
-        int link = (int)q.w;
+        const Node q = load_node(S.nodes, node);
+        int link = node_link(q);
         ++wk.box;
-        if (slab(r, qbox(q), h.t)) {
+        if (slab(r, node_box(q), h.t)) {
             if (link < 0) {
                 int leaf = ~link;
                 float4 q0 = S.tris[3 * leaf], q1 = S.tris[3 * leaf + 1], q2 = S.tris[3 * leaf + 2];
@@ -228,10 +252,10 @@ __device__ inline bool trace_any(const Scene &S, v3 o, v3 d, int skip, Work &wk)
     Ray r = make_ray(o, d);
     int node = 0;
     while (node < S.n_nodes) {
-        uint4 q = S.nodes[node];
-        int link = (int)q.w;
+        const Node q = load_node(S.nodes, node);
+        int link = node_link(q);
         ++wk.box;
-        if (slab(r, qbox(q), 1.0f)) {
+        if (slab(r, node_box(q), 1.0f)) {
             if (link < 0) {
                 int leaf = ~link;
                 float4 q0 = S.tris[3 * leaf], q1 = S.tris[3 * leaf + 1], q2 = S.tris[3 * leaf + 2];
@@ -260,9 +284,9 @@ __device__ inline void trace_closest2(const Scene &S, v3 o, v3 d1, v3 d2, Hit &h
     h2 = h1;
     int node = 0;
     while (node < S.n_nodes) {
-        const uint4 q = S.nodes[node];
-        const int link = (int)q.w;
-        const QBox b = qbox(q);
+        const Node q = load_node(S.nodes, node);
+        const int link = node_link(q);
+        const NBox b = node_box(q);
         const bool e1 = slab(r1, b, h1.t), e2 = slab(r2, b, h2.t);
         wk.box += 2;
         if (e1 || e2) {
@@ -304,9 +328,9 @@ __device__ inline void trace_any2(const Scene &S, v3 o, v3 d1, v3 d2, int skip, 
     hit1 = hit2 = false;
     int node = 0;
     while (node < S.n_nodes && !(hit1 && hit2)) {
-        const uint4 q = S.nodes[node];
-        const int link = (int)q.w;
-        const QBox b = qbox(q);
+        const Node q = load_node(S.nodes, node);
+        const int link = node_link(q);
+        const NBox b = node_box(q);
         const bool e1 = !hit1 && slab(r1, b, 1.0f), e2 = !hit2 && slab(r2, b, 1.0f);
         wk.box += (hit1 ? 0u : 1u) + (hit2 ? 0u : 1u);
         if (e1 || e2) {

@@ -282,7 +282,7 @@ __global__ __launch_bounds__(256) void k_lbvh_layout(int F, const int *__restric
 // LDS counters at the slots k_lbvh_karras assigned (global ones, whose
 // parity needs no reset, past kTopSlots).
 __device__ __forceinline__ void lbvh_union_write(int F, int p, const int *child, const int *first, const int *last,
-        const int *pre, float *box, uint4 *nodes) {
+        const int *pre, float *box, Node *nodes) {
     const volatile float *vb = box;
     int cl = child[2 * p], cr = child[2 * p + 1];
     float u[6];
@@ -292,13 +292,13 @@ __device__ __forceinline__ void lbvh_union_write(int F, int p, const int *child,
     }
     for (int k = 0; k < 6; ++k) box[6 * p + k] = u[k];
     int pp = pre[p];
-    nodes[pp] = qnode(u[0], u[1], u[2], u[3], u[4], u[5], pp + 2 * (last[p] - first[p] + 1) - 1);
+    nodes[pp] = make_node(u[0], u[1], u[2], u[3], u[4], u[5], pp + 2 * (last[p] - first[p] + 1) - 1);
 }
 
 __device__ __forceinline__ void lbvh_boxes_body(int F, const int *__restrict__ faces, const float *__restrict__ pos,
         int V, const int *__restrict__ sorted, const int *__restrict__ child, const int *__restrict__ parent,
         const int *__restrict__ first, const int *__restrict__ last, const int *__restrict__ pre,
-        float *box, uint4 *__restrict__ nodes, float4 *__restrict__ tris, int *__restrict__ roots,
+        float *box, Node *__restrict__ nodes, float4 *__restrict__ tris, int *__restrict__ roots,
         int *__restrict__ n_roots, int tb) {
     __shared__ unsigned int arr[kBoxTile];
     arr[threadIdx.x] = 0u;
@@ -317,7 +317,7 @@ __device__ __forceinline__ void lbvh_boxes_body(int F, const int *__restrict__ f
                    fmaxf(fmaxf(a.y, b.y), c.y) + kBoxPad, fmaxf(fmaxf(a.z, b.z), c.z) + kBoxPad};
     int x = (F - 1) + l;
     for (int k = 0; k < 6; ++k) box[6 * x + k] = bx[k];
-    nodes[pre[x]] = qnode(bx[0], bx[1], bx[2], bx[3], bx[4], bx[5], ~l);
+    nodes[pre[x]] = make_node(bx[0], bx[1], bx[2], bx[3], bx[4], bx[5], ~l);
     if (F == 1) return;
     __threadfence_block();
     for (;;) {
@@ -338,7 +338,7 @@ __device__ __forceinline__ void lbvh_boxes_body(int F, const int *__restrict__ f
 __global__ __launch_bounds__(kBoxTile) void k_lbvh_boxes(int F, const int *__restrict__ faces, const float *__restrict__ pos,
         int V, const int *__restrict__ sorted, const int *__restrict__ child, const int *__restrict__ parent,
         const int *__restrict__ first, const int *__restrict__ last, const int *__restrict__ pre,
-        float *box, uint4 *__restrict__ nodes, float4 *__restrict__ tris, int *__restrict__ roots,
+        float *box, Node *__restrict__ nodes, float4 *__restrict__ tris, int *__restrict__ roots,
         int *__restrict__ n_roots) {
     lbvh_boxes_body(F, faces, pos, V, sorted, child, parent, first, last, pre, box, nodes, tris, roots, n_roots,
                     blockIdx.x);
@@ -347,7 +347,7 @@ __global__ __launch_bounds__(kBoxTile) void k_lbvh_boxes(int F, const int *__res
 __device__ __forceinline__ void lbvh_boxes_top_body(int F, const int *__restrict__ child,
         const int *__restrict__ parent, const int *__restrict__ first, const int *__restrict__ last,
         const int *__restrict__ pre, const int *__restrict__ top_idx, unsigned int *__restrict__ arrive, float *box,
-        uint4 *__restrict__ nodes, const int *__restrict__ roots, const int *__restrict__ n_roots) {
+        Node *__restrict__ nodes, const int *__restrict__ roots, const int *__restrict__ n_roots) {
     __shared__ unsigned int arr[kTopSlots];
     for (int k = threadIdx.x; k < kTopSlots; k += blockDim.x) arr[k] = 0u;
     __syncthreads();
@@ -370,6 +370,6 @@ __device__ __forceinline__ void lbvh_boxes_top_body(int F, const int *__restrict
 __global__ __launch_bounds__(1024) void k_lbvh_boxes_top(int F, const int *__restrict__ child,
         const int *__restrict__ parent, const int *__restrict__ first, const int *__restrict__ last,
         const int *__restrict__ pre, const int *__restrict__ top_idx, unsigned int *__restrict__ arrive, float *box,
-        uint4 *__restrict__ nodes, const int *__restrict__ roots, const int *__restrict__ n_roots) {
+        Node *__restrict__ nodes, const int *__restrict__ roots, const int *__restrict__ n_roots) {
     lbvh_boxes_top_body(F, child, parent, first, last, pre, top_idx, arrive, box, nodes, roots, n_roots);
 }
