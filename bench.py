@@ -25,28 +25,36 @@ if ROOT not in sys.path:
 
 METRIC = "fwd+bwd ms/iter & Mrays/s at 256x256; denoised-2spp vs plain-256spp at equal PSNR"
 
-# Algorithmic VALU work per unit, counted as gfx950 VALU instructions (one
-# lane operation each) in the compiled code of each piece (address
-# arithmetic excluded): one BVH node test (six binary16 -> fp32 conversions
-# and the slab test), one full ray/triangle test with its hit-box check, one
-# light sample's shading, and one light sample's shading plus reverse-mode
-# adjoint.
-OPS_BOX = 30
-OPS_TRI = 95
+# Algorithmic VALU work per unit, in fp32 lane operations, at fixed costs
+# that do not depend on how this build compiles: a box (slab) test 15 (six
+# fused subtract-multiply slab times, six min/max, the entry/exit compare),
+# a Moller-Trumbore triangle test 50 (two cross products, three dot
+# products, the reciprocal, the bound tests).  These price the roofline.
+OPS_BOX = 15
+OPS_TRI = 50
+# The same units as this build's gfx950 code issues them (VALU instructions
+# per lane in the compiled loop, address arithmetic included): a node visit
+# 21 (binary16 decode folded into v_fma_mix_f32), a full triangle test with
+# its hit-box check 95, one light sample's shading 215, one light sample's
+# shading plus reverse-mode adjoint 590.  Reported beside the fixed-cost
+# fraction, never in its place.
+ISA_BOX = 21
+ISA_TRI = 95
 OPS_SHADE_FWD = 215
 OPS_SHADE_ADJ = 590
 # fp32 VALU issue ceiling: 256 CU x 4 SIMD x 16 lanes x 2.4 GHz, one
 # non-packed, non-fused operation per lane per clock
 PEAK_VALU = 39.3      # T lane-ops/s
+VALU_UNIT = "Tlane-ops/s"
 # the renderer's kernel sources (a traffic figure is valid while they hash as when it was taken)
 KERNEL_SOURCES = ("facert.hip", "fr_device.hpp", "fr_lbvh.hpp", "fr_batch.hpp")
 
 
-def profiled_traffic(kernel: str, workload: str):
-    """HBM bytes per launch from the committed rocprofv3 PMC summary, or None
-    when the kernel sources changed since the counters were taken."""
+def _profile_fields(name: str, workload: str):
+    """key: value lines of a committed rocprofv3 summary, or None when the
+    kernel sources changed since its counters were taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", f"fwd_bwd_{workload}_traffic.md")
+    path = os.path.join(ROOT, "profiles", f"fwd_bwd_{workload}_{name}.md")
     if not os.path.exists(path):
         return None
     src = b"".join(open(os.path.join(ROOT, "paper_1910_05200_amd", "csrc", f), "rb").read()
@@ -54,8 +62,70 @@ def profiled_traffic(kernel: str, workload: str):
     fields = dict(l.split(": ", 1) for l in open(path).read().splitlines() if ": " in l and not l.startswith("|"))
     if fields.get("kernel_source_sha256", "").strip() != hashlib.sha256(src).hexdigest():
         return None
-    v = fields.get(f"{kernel}_traffic_bytes_per_launch")
+    return fields
+
+
+def profiled_traffic(kernel: str, workload: str):
+    """HBM bytes per launch from the committed PMC summary (FETCH_SIZE and
+    WRITE_SIZE, calibrated), or None when it is stale."""
+    f = _profile_fields("traffic", workload)
+    v = f.get(f"{kernel}_traffic_bytes_per_launch") if f else None
     return float(v) if v else None
+
+
+def profiled_valu(kernel: str, workload: str):
+    """VALU counters per launch from the committed PMC summary: wave-level
+    VALU instructions (SQ_INSTS_VALU) and active lanes per VALU instruction
+    (SQ_THREAD_CYCLES_VALU / SQ_ACTIVE_INST_VALU), or None when stale."""
+    f = _profile_fields("valu", workload)
+    if not f or not f.get(f"{kernel}_sq_insts_valu"):
+        return None
+    return {"sq_insts_valu": float(f[f"{kernel}_sq_insts_valu"]),
+            "active_lanes_per_valu_inst": float(f[f"{kernel}_active_lanes_per_valu_inst"])}
+
+
+def host_cpu() -> dict:
+    """The host's logical CPU count, the cores this process may use, and the CPU model."""
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    usable = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    return {"nproc": os.cpu_count(), "usable": usable, "model": model}
+
+
+def oracle_threads(requested: int = 0) -> int:
+    """All the cores this process may use, up to 16 (the CPU share of one GPU
+    on the GPU machines; there nproc and the affinity are both 16)."""
+    return requested or max(1, min(16, host_cpu()["usable"]))
+
+
+def roofline_entry(kernel: str, box: float, tri: float, shade: float, shade_cost: int, sec: float, workload: str):
+    """The roofline object of one kernel's launch: work at the fixed unit
+    costs over its measured time against the VALU ceiling, the same work at
+    this build's instruction costs, and the VALU counters of the committed
+    profile (issue rate of wave-level VALU instructions, as lane slots, and
+    the active lanes per instruction)."""
+    ops = box * OPS_BOX + tri * OPS_TRI + shade * shade_cost
+    ops_isa = box * ISA_BOX + tri * ISA_TRI + shade * shade_cost
+    achieved = ops / sec / 1e12
+    out = {"bound": "alu", "kernel": kernel, "achieved": achieved, "peak": PEAK_VALU, "unit": VALU_UNIT,
+           "frac": achieved / PEAK_VALU, "traffic": profiled_traffic(kernel, workload),
+           "ops_per_launch": ops, "ms_per_launch": sec * 1e3,
+           "unit_costs": {"box": OPS_BOX, "tri": OPS_TRI, "shade": shade_cost},
+           "frac_at_isa_costs": ops_isa / sec / 1e12 / PEAK_VALU,
+           "isa_costs": {"box": ISA_BOX, "tri": ISA_TRI, "shade": shade_cost}}
+    v = profiled_valu(kernel, workload)
+    if v:
+        out["counters"] = {"valu_lane_slots_per_launch": v["sq_insts_valu"] * 64,
+                           "valu_issue_frac": v["sq_insts_valu"] * 64 / sec / 1e12 / PEAK_VALU,
+                           "active_lanes_per_valu_inst": v["active_lanes_per_valu_inst"],
+                           "active_lane_ops_per_launch": v["sq_insts_valu"] * v["active_lanes_per_valu_inst"]}
+    return out
 
 
 def parse():
@@ -90,7 +160,7 @@ def cpu_baseline(model, scene, params, target, seed, spp, threads):
     dt = time.perf_counter() - t0
     rays = c1.total() + c2.total()
     return {"value": rays / dt / 1e6, "unit": "Mrays/s", "cores": threads, "kind": "oracle",
-            "ms_per_iter": dt * 1e3,
+            "ms_per_iter": dt * 1e3, "host": host_cpu(),
             "sample": "one full forward+adjoint iteration (all terms) of the same paper-scale workload, "
                       "same seed and spp"}
 
@@ -176,9 +246,9 @@ def bench_batch(args):
         sequential(0)
         ms_seq = timed(sequential, max(2, args.steps // 4))
     k_sh = facert.KERNELS.index("k_sh_trace")
-    ops_sh = sum(st["kernel_box_tests"][k_sh] * OPS_BOX + st["kernel_tri_tests"][k_sh] * OPS_TRI for st in stats)
+    box_sh = sum(st["kernel_box_tests"][k_sh] for st in stats)
+    tri_sh = sum(st["kernel_tri_tests"][k_sh] for st in stats)
     ms_sh = tm["sh_trace"]
-    achieved = ops_sh / (ms_sh * 1e-3) / 1e12
     V = [m.n_vertices for m, *_ in inst]
     out = {
         "metric": METRIC,
@@ -201,13 +271,11 @@ def bench_batch(args):
                    "ms_kinds": {k: round(v, 3) for k, v in tm.items() if v > 0.05 and k not in ("render", "backward")},
                    "tuned": {k: {"mode": ["flat", "xcd"][v[0][0]], "tile": v[0][1], "ms": round(v[1], 3)}
                              for k, v in tuned.items()}},
-        "roofline": {"bound": "alu", "kernel": "sh_trace (batched)", "achieved": achieved, "peak": PEAK_VALU,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_VALU,
-                     "traffic": profiled_traffic("k_multi_KShTrace", "batch"),
-                     "ops_per_launch": ops_sh, "ms_per_launch": ms_sh},
+        "roofline": roofline_entry("k_multi_KShTrace", box_sh, tri_sh, 0, 0, ms_sh * 1e-3, "batch"),
     }
+    out["roofline"]["kernel"] = "sh_trace (batched, k_multi_KShTrace)"
     if not args.no_cpu_baseline:
-        threads = args.cpu_threads or min(16, os.cpu_count() or 1)
+        threads = oracle_threads(args.cpu_threads)
         i = min(range(n), key=lambda k: inst[k][1].width * inst[k][1].height * inst[k][3])
         m, sc, p, spp = inst[i]
         cb = cpu_baseline(m, sc, p, np.zeros((sc.height, sc.width, 3)), 1000, spp, threads)
@@ -277,12 +345,10 @@ def main():
     rays_per_iter = float(np.mean(rays))
     kern = {}
     for k, name in enumerate(facert.KERNELS):
-        shade_ops = OPS_SHADE_ADJ if name == "k_render_adj" else OPS_SHADE_FWD
-        ops = [st["kernel_box_tests"][k] * OPS_BOX + st["kernel_tri_tests"][k] * OPS_TRI
-               + st["kernel_shades"][k] * shade_ops for st in per_step]
-        kern[name] = (float(np.mean(ops)), float(np.mean([st["ms_kernel"][k] for st in per_step])) * 1e-3)
-    dom = max(kern, key=lambda k: kern[k][1])
-    achieved = kern[dom][0] / kern[dom][1] / 1e12
+        mean = lambda key: float(np.mean([st[key][k] for st in per_step]))
+        kern[name] = (mean("kernel_box_tests"), mean("kernel_tri_tests"), mean("kernel_shades"),
+                      mean("ms_kernel") * 1e-3, OPS_SHADE_ADJ if name == "k_render_adj" else OPS_SHADE_FWD)
+    dom = max(kern, key=lambda k: kern[k][3])
     last = per_step[-1]
     out = {
         "metric": METRIC,
@@ -299,18 +365,16 @@ def main():
                    "ms_bvh": round(float(np.mean([st["ms_bvh"] for st in per_step])), 4),
                    "rays_per_iter": rays_per_iter,
                    "traversal_overflow": int(last["traversal_overflow"]),
-                   "ms_kernels": {n: round(kern[n][1] * 1e3, 3) for n in facert.KERNELS},
+                   "ms_kernels": {n: round(kern[n][3] * 1e3, 3) for n in facert.KERNELS},
                    "box_tests_per_ray": {n: round(last["kernel_box_tests"][k] / max(1, last["kernel_rays"][k]), 2)
                                          for k, n in enumerate(facert.KERNELS)},
                    "tri_tests_per_ray": {n: round(last["kernel_tri_tests"][k] / max(1, last["kernel_rays"][k]), 2)
                                          for k, n in enumerate(facert.KERNELS)}},
-        "roofline": {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": PEAK_VALU,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_VALU,
-                     "traffic": profiled_traffic(dom, args.workload),
-                     "ops_per_launch": kern[dom][0], "ms_per_launch": kern[dom][1] * 1e3},
+        "roofline": roofline_entry(dom, kern[dom][0], kern[dom][1], kern[dom][2], kern[dom][4], kern[dom][3],
+                                   args.workload),
     }
     if not args.no_cpu_baseline:
-        threads = args.cpu_threads or min(16, os.cpu_count() or 1)
+        threads = oracle_threads(args.cpu_threads)
         # the oracle gets its own inputs only: a zero target (dL/dI = 2 I)
         zero = np.zeros((scene.height, scene.width, 3))
         out["cpu_baseline"] = cpu_baseline(model, scene, params, zero, 1000, spp, threads)

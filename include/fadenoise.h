@@ -60,6 +60,14 @@ int fd_layer_shape(const fd_net *net, int32_t i, int32_t *cin, int32_t *cout, in
 int fd_set_params(fd_net *net, const float *params);
 int fd_get_params(const fd_net *net, float *params);
 
+/* Training state, for checkpoints: parameters, Adam moments m and v (each
+ * [fd_num_params], device) and the step count.  fd_get_state copies them
+ * out (any pointer may be NULL); fd_set_state restores them (params, m, v
+ * all given).  Errors: FD_EINVAL (null net or, for fd_set_state, a null
+ * array or step < 0). */
+int fd_get_state(const fd_net *net, float *params, float *m, float *v, int32_t *step);
+int fd_set_state(fd_net *net, const float *params, const float *m, const float *v, int32_t step);
+
 /* Denoise: rgb [H][W][3] (the low-spp render), aux [H][W][7] (albedo,
  * normal, depth of the first hits, averaged over the pixel's samples) ->
  * out [H][W][3] radiance.  out may alias neither input. */
@@ -82,6 +90,31 @@ int fd_train_step(fd_net *net, const float *rgb, const float *aux, const float *
  * the gradient on the low-spp render.  Errors: -1 null argument, -4 no
  * prior fd_forward. */
 int fd_backward_input(fd_net *net, const float *rgb, const float *dL_dout, float *dL_drgb);
+
+/* Single layers: the kernels the network runs, callable on their own (for
+ * element-wise checks of each kernel, or to compose other networks).  No
+ * network is needed; work is enqueued on hip_stream (a hipStream_t, NULL for
+ * the null stream).  Layouts as above: x [H][W][cin], y [H][W][cout],
+ * weights [cout][9][cin] as bfloat16 bit patterns (the 16 high bits of the
+ * fp32 value), tap t = 3 (dy + 1) + (dx + 1) reading pixel (y + dy, x + dx),
+ * zero outside the image.
+ *
+ * fd_conv3x3: y = act(bias + conv(x, w)) in fp32 (before any rounding of
+ * the stored activation), act = leaky ReLU (slope 0.01) when relu, else the
+ * identity; bias may be NULL.  x is bfloat16 bit patterns, or fp32 (rounded
+ * to bfloat16 as it is read) when x_is_f32 - the form the input-gradient
+ * pass takes, with the flipped weights.  cin a multiple of 16.
+ *
+ * fd_conv3x3_wgrad: dw[co][t][ci] = sum_p g[p][co] x[nbr(p, t)][ci] (g fp32,
+ * rounded to bfloat16 as it is read; x bfloat16), db[co] = sum_p g[p][co]
+ * (db may be NULL).  Both are overwritten; sums are fp32 in an order that
+ * varies between runs.  cin and cout multiples of 8.
+ *
+ * Errors: FD_EINVAL (sizes, null arrays), FD_EDEVICE. */
+int fd_conv3x3(void *hip_stream, int32_t H, int32_t W, int32_t cin, int32_t cout, const void *x, int32_t x_is_f32,
+               const uint16_t *w, const float *bias, int32_t relu, float *y);
+int fd_conv3x3_wgrad(void *hip_stream, int32_t H, int32_t W, int32_t cin, int32_t cout, const uint16_t *x,
+                     const float *g, float *dw, float *db);
 
 const char *fd_last_error(const fd_net *net);
 void fd_destroy(fd_net *net);

@@ -161,3 +161,43 @@ def input_grad(params, rgb, aux, dL_dout, bf16=False):
     out = (torch.expm1(pred) / EXPOSURE)[0].permute(1, 2, 0)
     (out * torch.as_tensor(np.asarray(dL_dout, np.float64))).sum().backward()
     return rgb_t.grad.numpy().copy()
+
+
+# ------------------------------------------------------------ single layers
+# One 3x3 convolution and its two gradients in float64, [H][W][C] layouts,
+# weights [Cout][9][Cin] with tap t = 3 (dy + 1) + (dx + 1) (the layout the
+# direct-loop pin checks).  Inputs are taken as given (a caller that models
+# bfloat16 storage rounds them first with bf16_round).
+
+def _w4(w):
+    w = torch.as_tensor(np.asarray(w, np.float64))
+    co, _, ci = w.shape
+    return w.reshape(co, 3, 3, ci).permute(0, 3, 1, 2).contiguous()      # [co][ci][ky][kx]
+
+
+def conv3x3_layer(x, w, bias=None, relu=False):
+    """act(bias + conv(x, w)), [H][W][Cout] float64."""
+    xt = torch.as_tensor(np.asarray(x, np.float64)).permute(2, 0, 1)[None]
+    b = None if bias is None else torch.as_tensor(np.asarray(bias, np.float64))
+    y = F.conv2d(xt, _w4(w), b, padding=1)
+    if relu:
+        y = F.leaky_relu(y, SLOPE)
+    return y[0].permute(1, 2, 0).numpy()
+
+
+def conv3x3_input_grad(g, w):
+    """d/dx of sum(g * conv(x, w)), [H][W][Cin] float64."""
+    gt = torch.as_tensor(np.asarray(g, np.float64)).permute(2, 0, 1)[None]
+    w4 = _w4(w)
+    H, W = gt.shape[2:]
+    dx = torch.nn.grad.conv2d_input((1, w4.shape[1], H, W), w4, gt, padding=1)
+    return dx[0].permute(1, 2, 0).numpy()
+
+
+def conv3x3_weight_grad(x, g):
+    """(d/dw [Cout][9][Cin], d/dbias [Cout]) of sum(g * (bias + conv(x, w))), float64."""
+    xt = torch.as_tensor(np.asarray(x, np.float64)).permute(2, 0, 1)[None]
+    gt = torch.as_tensor(np.asarray(g, np.float64)).permute(2, 0, 1)[None]
+    co, ci = gt.shape[1], xt.shape[1]
+    dw = torch.nn.grad.conv2d_weight(xt, (co, ci, 3, 3), gt, padding=1)       # [co][ci][ky][kx]
+    return dw.permute(0, 2, 3, 1).reshape(co, 9, ci).numpy(), gt.sum(dim=(0, 2, 3)).numpy()

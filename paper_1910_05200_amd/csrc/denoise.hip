@@ -3,13 +3,14 @@
 // Layout: activations NHWC bfloat16 [H*W][C] (bf16 stored as its 16 high
 // bits), weights [Cout][9][Cin].  Every 3x3 convolution is an implicit GEMM
 // (rows = pixels, columns = output channels, reduction = 9 taps x input
-// channels) on v_mfma_f32_32x32x8bf16_1k with fp32 accumulation: a block of
-// four waves owns a 64-pixel x 64-channel tile, each wave a 32 x 32 quarter,
-// and the reduction runs in steps of 16 channels of one tap staged in LDS.
-// The gradient with respect to a convolution's input is the same kernel on
-// the flipped, transposed weights; the weight gradient is a second GEMM
-// (rows = output channels, columns = input channels of one tap, reduction =
-// pixels) split over pixel chunks and summed with fp32 atomics.
+// channels) on gfx950's v_mfma_f32_32x32x16_bf16 with fp32 accumulation; a
+// block owns an 8 x 16-pixel tile and 32 or 64 output channels, and stages
+// the tile's input patch (with its halo) once per group of input channels
+// for all nine taps (k_conv3x3).  The gradient with respect to a
+// convolution's input is the same kernel on the flipped, transposed
+// weights; the weight gradient is a second GEMM (rows = output channels,
+// columns = input channels of one tap, reduction = pixels) split over pixel
+// chunks and summed with fp32 atomics (k_conv3x3_wgrad).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -22,7 +23,6 @@
 #include "../../include/fadenoise.h"
 
 typedef uint16_t bf16;
-typedef short s4v __attribute__((ext_vector_type(4)));
 typedef float f16v __attribute__((ext_vector_type(16)));
 
 __device__ __forceinline__ float bf2f(bf16 h) { return __uint_as_float((uint32_t)h << 16); }
@@ -37,110 +37,194 @@ constexpr float kSlope = 0.01f;    // leaky ReLU
 // Radiance enters as log(1 + kExposure x): the light stage's pixel values
 // are a few hundredths, and this brings them to order one.
 constexpr float kExposure = 16.0f;
-constexpr int kTM = 64, kTN = 64, kKC = 16;   // GEMM tile, reduction step (channels)
 
 // ------------------------------------------------------------ conv 3x3 --
 // Y[p][co] = act(bias[co] + sum_{t, ci} W[co][t][ci] X[nbr(p, t)][ci]), zero
 // outside the image; act = leaky ReLU when relu, else identity (bias may be
-// NULL).  Cin multiple of 16; Y has ldy channels per pixel starting at
-// channel yoff (so a result can land inside a concatenation).
-// four consecutive values as bf16 (8 bytes)
-__device__ __forceinline__ uint2 load4(const bf16 *p) { return *(const uint2 *)p; }
-__device__ __forceinline__ uint2 load4(const float *p) {
-    float4 f = *(const float4 *)p;
-    return make_uint2((uint32_t)f2bf(f.x) | ((uint32_t)f2bf(f.y) << 16), (uint32_t)f2bf(f.z) | ((uint32_t)f2bf(f.w) << 16));
+// NULL).  Y has ldy channels per pixel starting at channel yoff (so a result
+// can land inside a concatenation).
+//
+// Implicit GEMM on v_mfma_f32_32x32x16_bf16 (rows = pixels, columns =
+// output channels, reduction = 9 taps x input channels).  A block of four
+// waves owns a tile of 8 x 16 pixels and NT output channels; each wave owns
+// two of its pixel rows (32 pixels) and all NT channels (NT / 32
+// accumulators).  The reduction runs in stages of KC input channels: the
+// stage's input patch (the tile plus a one-pixel halo, 10 x 18 pixels) and
+// its weights for all nine taps go to LDS once, and every tap reads its
+// shifted window of the same patch, so the input is fetched once per stage
+// instead of once per tap.  The next stage's global loads are issued into
+// registers before the current stage's MFMAs.  LDS rows are padded by 16
+// bytes, which spreads a half-wave's 16-byte reads over all 64 banks.
+typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ uint32_t pack2(float a, float b) { return (uint32_t)f2bf(a) | ((uint32_t)f2bf(b) << 16); }
+// eight consecutive values as bf16 (16 bytes)
+__device__ __forceinline__ uint4 load8(const bf16 *p) { return *(const uint4 *)p; }
+__device__ __forceinline__ uint4 load8(const float *p) {
+    const float4 a = *(const float4 *)p, b = *(const float4 *)(p + 4);
+    return make_uint4(pack2(a.x, a.y), pack2(a.z, a.w), pack2(b.x, b.y), pack2(b.z, b.w));
 }
 __device__ __forceinline__ void store1(bf16 *p, float v) { *p = f2bf(v); }
 __device__ __forceinline__ void store1(float *p, float v) { *p = v; }
 
-template <class TX, class TY>
+constexpr int kPR = 8, kPC = 16;                  // pixel tile: 8 rows x 16 columns
+constexpr int kHR = kPR + 2, kHC = kPC + 2;       // with the one-pixel halo
+constexpr int kLPad = 8;                          // bf16 of padding per LDS row
+
+template <class TX, class TY, int NT, int KC>
 __global__ __launch_bounds__(256) void k_conv3x3(int H, int W, int Cin, int Cout, const TX *__restrict__ X,
         const bf16 *__restrict__ Wt, const float *__restrict__ bias, int relu, TY *__restrict__ Y, int ldy,
         int yoff) {
-    __shared__ bf16 As[kTM][kKC + 4];
-    __shared__ bf16 Bs[kTN][kKC + 4];
-    const int P = H * W;
-    const int p0 = blockIdx.x * kTM, co0 = blockIdx.y * kTN;
+    constexpr int NA = NT / 32;                   // accumulators per wave
+    constexpr int XQ = KC / 8;                    // 16-byte parts per pixel per stage
+    constexpr int XN = kHR * kHC * XQ, WN = 9 * NT * XQ;
+    constexpr int XI = (XN + 255) / 256, WI = (WN + 255) / 256;
+    __shared__ __attribute__((aligned(16))) bf16 Xs[kHR * kHC][KC + kLPad];
+    __shared__ __attribute__((aligned(16))) bf16 Ws[9 * NT][KC + kLPad];
+    const int tiles_x = (W + kPC - 1) / kPC;
+    const int ty0 = (int)(blockIdx.x / tiles_x) * kPR, tx0 = (int)(blockIdx.x % tiles_x) * kPC;
+    const int co0 = blockIdx.y * NT;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm = wave >> 1, wn = wave & 1;
-    const int lr = tid >> 2, lq = (tid & 3) * 4;        // loader: row, 4-channel quad
-    const int lp = p0 + lr, ly = lp / W, lx = lp - ly * W;
-    f16v acc;
-    for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
-    for (int t = 0; t < 9; ++t) {
-        const int dy = t / 3 - 1, dx = t % 3 - 1;
-        const int sy = ly + dy, sx = lx + dx;
-        const bool in = lp < P && sy >= 0 && sy < H && sx >= 0 && sx < W;
-        const TX *xa = X + (in ? (size_t)(sy * W + sx) * Cin : 0);
-        const bool wn_ok = co0 + lr < Cout;
-        const bf16 *wb = Wt + ((size_t)(co0 + lr) * 9 + t) * Cin;
-        for (int c0 = 0; c0 < Cin; c0 += kKC) {
-            uint2 va = make_uint2(0u, 0u), vb = make_uint2(0u, 0u);
-            if (in) va = load4(xa + c0 + lq);
-            if (wn_ok) vb = load4(wb + c0 + lq);
-            __syncthreads();
-            *(uint2 *)&As[lr][lq] = va;
-            *(uint2 *)&Bs[lr][lq] = vb;
-            __syncthreads();
-            for (int kk = 0; kk < kKC; kk += 8) {
-                const int k = kk + (lane >> 5) * 4;
-                s4v a = *(const s4v *)&As[wm * 32 + (lane & 31)][k];
-                s4v b = *(const s4v *)&Bs[wn * 32 + (lane & 31)][k];
-                acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc, 0, 0, 0);
+    const int m = lane & 31, kh = (lane >> 5) * 8;   // the lane's pixel (A) / channel (B) row, k half
+    const int pr = 2 * wave + (m >> 4), pc = m & 15;
+    f16v acc[NA];
+    for (int a = 0; a < NA; ++a)
+        for (int r = 0; r < 16; ++r) acc[a][r] = 0.0f;
+    uint4 xr[XI], wr[WI];
+    auto fetch = [&](int c0) {
+#pragma unroll
+        for (int u = 0; u < XI; ++u) {
+            const int idx = tid + u * 256;
+            uint4 v = make_uint4(0u, 0u, 0u, 0u);
+            if (idx < XN) {
+                const int q = idx / XQ, part = idx % XQ;
+                const int py = ty0 - 1 + q / kHC, px = tx0 - 1 + q % kHC;
+                if (py >= 0 && py < H && px >= 0 && px < W) v = load8(X + (size_t)(py * W + px) * Cin + c0 + part * 8);
+            }
+            xr[u] = v;
+        }
+#pragma unroll
+        for (int u = 0; u < WI; ++u) {
+            const int idx = tid + u * 256;
+            uint4 v = make_uint4(0u, 0u, 0u, 0u);
+            if (idx < WN) {
+                const int part = idx % XQ, row = idx / XQ, co = row % NT, t = row / NT;
+                if (co0 + co < Cout) v = load8(Wt + ((size_t)(co0 + co) * 9 + t) * Cin + c0 + part * 8);
+            }
+            wr[u] = v;
+        }
+    };
+    fetch(0);
+    for (int c0 = 0; c0 < Cin; c0 += KC) {
+        __syncthreads();                           // the previous stage's LDS reads are done
+#pragma unroll
+        for (int u = 0; u < XI; ++u) {
+            const int idx = tid + u * 256;
+            if (idx < XN) *(uint4 *)&Xs[idx / XQ][(idx % XQ) * 8] = xr[u];
+        }
+#pragma unroll
+        for (int u = 0; u < WI; ++u) {
+            const int idx = tid + u * 256;
+            if (idx < WN) *(uint4 *)&Ws[idx / XQ][(idx % XQ) * 8] = wr[u];
+        }
+        __syncthreads();
+        if (c0 + KC < Cin) fetch(c0 + KC);         // in flight during this stage's MFMAs
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+            const int q = (pr + t / 3) * kHC + pc + t % 3;
+#pragma unroll
+            for (int ks = 0; ks < KC; ks += 16) {
+                const bf8v a = *(const bf8v *)&Xs[q][ks + kh];
+#pragma unroll
+                for (int na = 0; na < NA; ++na) {
+                    const bf8v b = *(const bf8v *)&Ws[t * NT + na * 32 + m][ks + kh];
+                    acc[na] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[na], 0, 0, 0);
+                }
             }
         }
     }
-    const int co = co0 + wn * 32 + (lane & 31);
-    if (co >= Cout) return;
-    const float bv = bias ? bias[co] : 0.0f;
-    for (int r = 0; r < 16; ++r) {
-        const int p = p0 + wm * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-        if (p >= P) continue;
-        float v = acc[r] + bv;
-        if (relu) v = v > 0.0f ? v : kSlope * v;
-        store1(&Y[(size_t)p * ldy + yoff + co], v);
+    // acc[na][r] holds pixel 8 (r / 4) + 4 (lane / 32) + r % 4 of the wave's
+    // 32 and channel na * 32 + lane % 32
+#pragma unroll
+    for (int na = 0; na < NA; ++na) {
+        const int co = co0 + na * 32 + m;
+        if (co >= Cout) continue;
+        const float bv = bias ? bias[co] : 0.0f;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int mm = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+            const int py = ty0 + 2 * wave + (mm >> 4), px = tx0 + (mm & 15);
+            if (py >= H || px >= W) continue;
+            float v = acc[na][r] + bv;
+            if (relu) v = v > 0.0f ? v : kSlope * v;
+            store1(&Y[(size_t)(py * W + px) * ldy + yoff + co], v);
+        }
+    }
+}
+
+// Launch k_conv3x3 for one layer: NT = 64 channels per block when Cout >= 64
+// (else 32), stages of 32 input channels when Cin allows (else 16).
+template <class TX, class TY>
+static void conv3x3_launch(hipStream_t s, int H, int W, int Cin, int Cout, const TX *X, const bf16 *Wt,
+                           const float *bias, int relu, TY *Y, int ldy, int yoff) {
+    const unsigned tiles = (unsigned)(((H + kPR - 1) / kPR) * ((W + kPC - 1) / kPC));
+    if (Cout >= 64) {
+        dim3 g(tiles, (unsigned)((Cout + 63) / 64));
+        if (Cin % 32 == 0) hipLaunchKernelGGL((k_conv3x3<TX, TY, 64, 32>), g, dim3(256), 0, s, H, W, Cin, Cout, X, Wt, bias, relu, Y, ldy, yoff);
+        else hipLaunchKernelGGL((k_conv3x3<TX, TY, 64, 16>), g, dim3(256), 0, s, H, W, Cin, Cout, X, Wt, bias, relu, Y, ldy, yoff);
+    } else {
+        dim3 g(tiles, (unsigned)((Cout + 31) / 32));
+        if (Cin % 32 == 0) hipLaunchKernelGGL((k_conv3x3<TX, TY, 32, 32>), g, dim3(256), 0, s, H, W, Cin, Cout, X, Wt, bias, relu, Y, ldy, yoff);
+        else hipLaunchKernelGGL((k_conv3x3<TX, TY, 32, 16>), g, dim3(256), 0, s, H, W, Cin, Cout, X, Wt, bias, relu, Y, ldy, yoff);
     }
 }
 
 // Weight gradient of one tap, one chunk of pixels:
-// dW[co][t][ci] += sum_{p in chunk} G[p][co] X[nbr(p, t)][ci]  (fp32 atomics).
-constexpr int kWChunk = 512;
+// dW[co][t][ci] += sum_{p in chunk} G[p][co] X[nbr(p, t)][ci]  (fp32 atomics
+// per block).  GEMM rows = output channels, columns = input channels,
+// reduction = pixels, 16 per v_mfma_f32_32x32x16_bf16; a block of four waves
+// owns a 64 x 64 tile, each wave a 32 x 32 quarter, and stages 32 pixels of
+// G and of the tap-shifted X in LDS (pixel-contiguous rows, padded to 16-byte
+// multiples) per step.
+constexpr int kWTile = 64, kWStep = 32, kWChunk = 2048;
 __global__ __launch_bounds__(256) void k_conv3x3_wgrad(int H, int W, int Cin, int Cout, const bf16 *__restrict__ X,
         const float *__restrict__ G, float *__restrict__ dW) {
-    __shared__ bf16 As[kTN][kKC + 4];   // [co][px]
-    __shared__ bf16 Bs[kTN][kKC + 4];   // [ci][px]
+    __shared__ __attribute__((aligned(16))) bf16 As[kWTile][kWStep + kLPad];   // [co][px]
+    __shared__ __attribute__((aligned(16))) bf16 Bs[kWTile][kWStep + kLPad];   // [ci][px]
     const int P = H * W;
-    const int co0 = blockIdx.x * kTN, ci0 = blockIdx.y * kTN;
+    const int co0 = blockIdx.x * kWTile, ci0 = blockIdx.y * kWTile;
     const int t = blockIdx.z % 9, chunk = blockIdx.z / 9;
     const int dy = t / 3 - 1, dx = t % 3 - 1;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
-    const int lpx = tid >> 4, lc = (tid & 15) * 4;      // loader: pixel of the step, 4 channels
+    const int m = lane & 31, kh = (lane >> 5) * 8;
+    const int lpx = tid >> 3, lc = (tid & 7) * 8;       // loader: pixel of the step, 8 channels
     f16v acc;
     for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
     const int pbeg = chunk * kWChunk, pend = min(P, pbeg + kWChunk);
-    for (int pb = pbeg; pb < pend; pb += kKC) {
+    for (int pb = pbeg; pb < pend; pb += kWStep) {
         const int p = pb + lpx;
-        const int y = p / W, x = p - (p / W) * W;
-        const int sy = y + dy, sx = x + dx;
-        uint2 vg = make_uint2(0u, 0u), vx = make_uint2(0u, 0u);
+        uint4 vg = make_uint4(0u, 0u, 0u, 0u), vx = make_uint4(0u, 0u, 0u, 0u);
         if (p < pend) {
-            if (co0 + lc < Cout) vg = load4(G + (size_t)p * Cout + co0 + lc);
+            const int y = p / W, x = p - y * W;
+            const int sy = y + dy, sx = x + dx;
+            if (co0 + lc < Cout) vg = load8(G + (size_t)p * Cout + co0 + lc);
             if (ci0 + lc < Cin && sy >= 0 && sy < H && sx >= 0 && sx < W)
-                vx = *(const uint2 *)(X + (size_t)(sy * W + sx) * Cin + ci0 + lc);
+                vx = load8(X + (size_t)(sy * W + sx) * Cin + ci0 + lc);
         }
         __syncthreads();
-        const bf16 *g4 = (const bf16 *)&vg, *x4 = (const bf16 *)&vx;
-        for (int q = 0; q < 4; ++q) { As[lc + q][lpx] = g4[q]; Bs[lc + q][lpx] = x4[q]; }
+        const bf16 *g8 = (const bf16 *)&vg, *x8 = (const bf16 *)&vx;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) { As[lc + q][lpx] = g8[q]; Bs[lc + q][lpx] = x8[q]; }
         __syncthreads();
-        for (int kk = 0; kk < kKC; kk += 8) {
-            const int k = kk + (lane >> 5) * 4;
-            s4v a = *(const s4v *)&As[wm * 32 + (lane & 31)][k];
-            s4v b = *(const s4v *)&Bs[wn * 32 + (lane & 31)][k];
-            acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc, 0, 0, 0);
+#pragma unroll
+        for (int ks = 0; ks < kWStep; ks += 16) {
+            const bf8v a = *(const bf8v *)&As[wm * 32 + m][ks + kh];
+            const bf8v b = *(const bf8v *)&Bs[wn * 32 + m][ks + kh];
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
         }
     }
-    const int ci = ci0 + wn * 32 + (lane & 31);
+    const int ci = ci0 + wn * 32 + m;
     if (ci >= Cin) return;
     for (int r = 0; r < 16; ++r) {
         const int co = co0 + wm * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
@@ -363,10 +447,9 @@ static int pix(const fd_net *n, int level) { return (n->H >> level) * (n->W >> l
 
 static int conv(fd_net *n, int li, const Act &x, bf16 *y, int ldy, int yoff, bool relu) {
     const Layer &l = n->L[li];
-    int H = n->H >> l.level, W = n->W >> l.level, P = H * W;
-    dim3 grid(nblk(P, kTM), nblk(l.cout, kTN));
-    hipLaunchKernelGGL((k_conv3x3<bf16, bf16>), grid, dim3(256), 0, n->stream, H, W, l.cin, l.cout, x.y,
-                       n->wbf + l.woff, n->params + l.boff, relu ? 1 : 0, y, ldy, yoff);
+    int H = n->H >> l.level, W = n->W >> l.level;
+    conv3x3_launch<bf16, bf16>(n->stream, H, W, l.cin, l.cout, x.y, n->wbf + l.woff, n->params + l.boff,
+                               relu ? 1 : 0, y, ldy, yoff);
     return 0;
 }
 
@@ -377,7 +460,7 @@ static void conv_bwd(fd_net *n, int li, const Act &x, const float *gout, float *
     const Layer &l = n->L[li];
     int H = n->H >> l.level, W = n->W >> l.level, P = H * W;
     if (wgrad) {
-        dim3 gw(nblk(l.cout, kTN), nblk(l.cin, kTN), 9 * nblk(P, kWChunk));
+        dim3 gw(nblk(l.cout, kWTile), nblk(l.cin, kWTile), 9 * nblk(P, kWChunk));
         hipLaunchKernelGGL(k_conv3x3_wgrad, gw, dim3(256), 0, n->stream, H, W, l.cin, l.cout, x.y, gout,
                            n->grads + l.woff);
         hipLaunchKernelGGL(k_bias_grad, dim3(nblk(P, 256)), dim3(256), 0, n->stream, P, l.cout, gout, n->grads + l.boff);
@@ -385,9 +468,8 @@ static void conv_bwd(fd_net *n, int li, const Act &x, const float *gout, float *
     if (gx) {
         hipLaunchKernelGGL(k_flip_weights, dim3(nblk((size_t)l.cin * 9 * l.cout, 256)), dim3(256), 0, n->stream,
                            l.cin, l.cout, n->params + l.woff, n->wflip);
-        dim3 grid(nblk(P, kTM), nblk(l.cin, kTN));
-        hipLaunchKernelGGL((k_conv3x3<float, float>), grid, dim3(256), 0, n->stream, H, W, l.cout, l.cin, gout,
-                           n->wflip, (const float *)nullptr, 0, gx, l.cin, 0);
+        conv3x3_launch<float, float>(n->stream, H, W, l.cout, l.cin, gout, n->wflip, (const float *)nullptr, 0, gx,
+                                     l.cin, 0);
     }
 }
 
@@ -563,6 +645,28 @@ int fd_get_params(const fd_net *n, float *p) {
     return 0;
 }
 
+int fd_get_state(const fd_net *n, float *p, float *m, float *v, int32_t *step) {
+    if (!n) return -1;
+    const size_t bytes = n->nparam * sizeof(float);
+    if (p && hipMemcpyAsync(p, n->params, bytes, hipMemcpyDeviceToDevice, n->stream) != hipSuccess) return -3;
+    if (m && hipMemcpyAsync(m, n->m, bytes, hipMemcpyDeviceToDevice, n->stream) != hipSuccess) return -3;
+    if (v && hipMemcpyAsync(v, n->v, bytes, hipMemcpyDeviceToDevice, n->stream) != hipSuccess) return -3;
+    if (step) *step = n->step;
+    return 0;
+}
+
+int fd_set_state(fd_net *n, const float *p, const float *m, const float *v, int32_t step) {
+    if (!n) return -1;
+    n->err.clear();
+    if (!p || !m || !v || step < 0) return fail(n, -1, "fd_set_state: null array or negative step");
+    const size_t bytes = n->nparam * sizeof(float);
+    HIPCK(n, hipMemcpyAsync(n->params, p, bytes, hipMemcpyDeviceToDevice, n->stream));
+    HIPCK(n, hipMemcpyAsync(n->m, m, bytes, hipMemcpyDeviceToDevice, n->stream));
+    HIPCK(n, hipMemcpyAsync(n->v, v, bytes, hipMemcpyDeviceToDevice, n->stream));
+    n->step = step;
+    return 0;
+}
+
 int fd_forward(fd_net *n, const float *rgb, const float *aux, float *out) {
     if (!n) return -1;
     n->err.clear();
@@ -608,6 +712,38 @@ int fd_backward_input(fd_net *n, const float *rgb, const float *dL_dout, float *
     hipLaunchKernelGGL(k_drgb, dim3(nblk(cnt, 256)), dim3(256), 0, n->stream, P, rgb, n->dpred, n->x0.g, dL_drgb);
     HIPCK(n, hipGetLastError());
     return 0;
+}
+
+// ---------------------------------------------------- single layers ----
+int fd_conv3x3(void *stream, int32_t H, int32_t W, int32_t cin, int32_t cout, const void *x, int32_t x_is_f32,
+               const uint16_t *w, const float *bias, int32_t relu, float *y) {
+    if (H < 1 || W < 1 || H > 4096 || W > 4096 || cin < 16 || cin % 16 || cin > 4096 || cout < 1 || cout > 4096 ||
+        !x || !w || !y)
+        return -1;
+    hipStream_t s = (hipStream_t)stream;
+    if (x_is_f32)
+        conv3x3_launch<float, float>(s, H, W, cin, cout, (const float *)x, (const bf16 *)w, bias, relu ? 1 : 0, y, cout, 0);
+    else
+        conv3x3_launch<bf16, float>(s, H, W, cin, cout, (const bf16 *)x, (const bf16 *)w, bias, relu ? 1 : 0, y, cout, 0);
+    return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+int fd_conv3x3_wgrad(void *stream, int32_t H, int32_t W, int32_t cin, int32_t cout, const uint16_t *x, const float *g,
+                     float *dw, float *db) {
+    if (H < 1 || W < 1 || H > 4096 || W > 4096 || cin < 8 || cin % 8 || cin > 4096 || cout < 8 || cout % 8 ||
+        cout > 4096 || !x || !g || !dw)
+        return -1;
+    hipStream_t s = (hipStream_t)stream;
+    const size_t nw = (size_t)cout * 9 * cin;
+    const int P = H * W;
+    hipLaunchKernelGGL(k_zero_f, dim3(nblk(nw, 256)), dim3(256), 0, s, nw, dw);
+    dim3 gw(nblk(cout, kWTile), nblk(cin, kWTile), 9 * nblk(P, kWChunk));
+    hipLaunchKernelGGL(k_conv3x3_wgrad, gw, dim3(256), 0, s, H, W, cin, cout, (const bf16 *)x, g, dw);
+    if (db) {
+        hipLaunchKernelGGL(k_zero_f, dim3(nblk(cout, 256)), dim3(256), 0, s, (size_t)cout, db);
+        hipLaunchKernelGGL(k_bias_grad, dim3(nblk(P, 256)), dim3(256), 0, s, P, cout, g, db);
+    }
+    return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 
 const char *fd_last_error(const fd_net *n) { return n ? n->err.c_str() : "null network"; }

@@ -688,11 +688,11 @@ __global__ __launch_bounds__(256) void k_cam_resolve(Scene S, long long n, HitRe
 // tests and append the rays that need tracing to lists (one LDS atomic per
 // wave and list).  About a third of the (sample, light) pairs need a ray at
 // the paper's framing (camera misses and lights below the horizon need
-// none), so tracing in place would leave two lanes in three idle.  Where a
-// block takes a tile of samples for one light, the tile size is a template
-// parameter of the body (the batched launcher may pick 256 or 512).
-// The shadow-boundary kernel keeps its accepted samples' two side rays in
-// LDS (48 bytes each), so its tile is smaller: 256 samples.
+// none), so tracing in place would leave two lanes in three idle.  The
+// shadow-boundary kernel takes a tile of samples for one light per block;
+// the tile size is a template parameter of its body (the batched launcher
+// may pick 256 or 512).  It keeps its accepted samples' two side rays in
+// LDS (48 bytes each), so its default tile is 256 samples.
 constexpr int kSecTile = 256;
 __device__ __forceinline__ int lanes_below(unsigned long long m) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0));
@@ -701,10 +701,10 @@ __device__ __forceinline__ int lanes_below(unsigned long long m) {
 // Single context: the shadow rays in two kernels.  After a fused block's
 // compaction only about a third of its lanes have a ray (most pairs fail
 // the horizon test), so most of its waves sit idle while the rest trace.
-//   k_sh_propose  one block per (tile of samples, light): each sample's
-//                 horizon test; the accepted samples' indices go to the
-//                 light's queue (one atomic per block on that light's
-//                 counter);
+//   k_sh_propose  one block per 256 samples for all lights: each sample's
+//                 surface decided once, then every light's horizon test;
+//                 the accepted samples' indices go to each light's queue
+//                 (one atomic per block and light on that light's counter);
 //   k_sh_trace    one lane per queued ray, rebuilt from the sample's hit
 //                 record and light sample as k_sh_propose built it, traced.
 // Every resident wave of k_sh_trace traces.  The batched path runs the same
@@ -1592,8 +1592,9 @@ __device__ __forceinline__ bool pe_light(const Scene &S, uint64_t seed, const Pe
 // The sides' shadow rays in two kernels, as the pixel samples' (most sides
 // trace nothing: the side off the face has no hit, and about half of the
 // rest have the light below their horizon):
-//   k_pv_propose  one block per (tile of kPvTile sides, light): the horizon
-//                 test; the accepted sides' indices go to the light's queue;
+//   k_pv_propose  one block per 256 sides (in screen order) for all lights:
+//                 the horizon tests; the accepted sides' indices go to each
+//                 light's queue;
 //   k_pv_trace    one lane per queued side, its ray rebuilt as k_pv_propose
 //                 built it, traced; a clear path sets the light's bit in the
 //                 side's mask.

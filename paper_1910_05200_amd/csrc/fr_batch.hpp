@@ -671,8 +671,8 @@ int fr_batch_set_launch(fr_batch *b, int32_t kind, const fr_launch *l) {
     if (kind_tiled(kind)) {
         if (v.tile != 256 && v.tile != 512)
             return bfail(b, FR_EINVAL, "fr_batch_set_launch: tile %d not in {256, 512}", v.tile);
-    } else {
-        v.tile = 0;
+    } else if (v.tile != 0) {
+        return bfail(b, FR_EINVAL, "fr_batch_set_launch: kind %s takes no tile size (pass 0)", kKindName[kind]);
     }
     if (kind_tiled(kind) && v.tile != b->launch[kind].tile) b->plan_dirty = true;
     b->launch[kind] = v;

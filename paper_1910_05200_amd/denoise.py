@@ -35,7 +35,8 @@ from paper_1910_05200_amd import facert, synth
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libfadenoise.so")
 EXPORTS = ("fd_create", "fd_set_stream", "fd_num_params", "fd_layer_shape", "fd_set_params", "fd_get_params",
-           "fd_forward", "fd_train_step", "fd_backward_input", "fd_last_error", "fd_destroy")
+           "fd_get_state", "fd_set_state", "fd_forward", "fd_train_step", "fd_backward_input", "fd_conv3x3",
+           "fd_conv3x3_wgrad", "fd_last_error", "fd_destroy")
 
 _lib = None
 
@@ -55,15 +56,20 @@ def load():
         L.fd_layer_shape.argtypes = [vp, i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]
         L.fd_set_params.argtypes = [vp, vp]
         L.fd_get_params.argtypes = [vp, vp]
+        L.fd_get_state.argtypes = [vp, vp, vp, vp, C.POINTER(i32)]
+        L.fd_set_state.argtypes = [vp, vp, vp, vp, i32]
         L.fd_forward.argtypes = [vp, vp, vp, vp]
         L.fd_train_step.argtypes = [vp, vp, vp, vp, C.c_float, vp, vp]
         L.fd_backward_input.argtypes = [vp, vp, vp, vp]
+        L.fd_conv3x3.argtypes = [vp, i32, i32, i32, i32, vp, i32, vp, vp, i32, vp]
+        L.fd_conv3x3_wgrad.argtypes = [vp, i32, i32, i32, i32, vp, vp, vp, vp]
         L.fd_last_error.argtypes = [vp]
         L.fd_last_error.restype = C.c_char_p
         L.fd_destroy.argtypes = [vp]
         L.fd_destroy.restype = None
-        for n in ("fd_create", "fd_set_stream", "fd_layer_shape", "fd_set_params", "fd_get_params", "fd_forward",
-                  "fd_train_step", "fd_backward_input"):
+        for n in ("fd_create", "fd_set_stream", "fd_layer_shape", "fd_set_params", "fd_get_params", "fd_get_state",
+                  "fd_set_state", "fd_forward", "fd_train_step", "fd_backward_input", "fd_conv3x3",
+                  "fd_conv3x3_wgrad"):
             getattr(L, n).restype = C.c_int
         _lib = L
     return _lib
@@ -131,6 +137,26 @@ class Denoiser:
         self._check(load().fd_get_params(self.net, _ptr(p)))
         return p
 
+    def get_state(self) -> dict:
+        """Parameters, Adam moments and step count (host arrays), for checkpoints."""
+        self._stream()
+        t = self.torch
+        p, m, v = (t.empty(self.n_params, device="cuda", dtype=t.float32) for _ in range(3))
+        step = C.c_int32()
+        self._check(load().fd_get_state(self.net, _ptr(p), _ptr(m), _ptr(v), C.byref(step)))
+        t.cuda.current_stream().synchronize()
+        return {"params": p.cpu().numpy(), "m": m.cpu().numpy(), "v": v.cpu().numpy(),
+                "step": np.int32(step.value)}
+
+    def set_state(self, st: dict):
+        self._stream()
+        t = self.torch
+        arrs = [t.from_numpy(np.ascontiguousarray(st[k], np.float32)).cuda() for k in ("params", "m", "v")]
+        for a in arrs:
+            assert a.numel() == self.n_params
+        self._check(load().fd_set_state(self.net, *[_ptr(a) for a in arrs], int(st["step"])))
+        t.cuda.current_stream().synchronize()
+
     def forward(self, rgb, aux, out=None):
         self._stream()
         if out is None:
@@ -153,6 +179,35 @@ class Denoiser:
         self._check(load().fd_train_step(self.net, _ptr(rgb.contiguous()), _ptr(aux.contiguous()),
                                          _ptr(target.contiguous()), float(lr), _ptr(loss), _ptr(g)))
         return (loss, g) if want_grads else loss
+
+
+def conv3x3(x, w_bf16, bias=None, relu=False, x_is_f32=False):
+    """fd_conv3x3 on torch's current stream: x [H][W][cin] (int16 bfloat16
+    bit patterns, or float32 when x_is_f32), w_bf16 [cout][9][cin] int16 ->
+    y [H][W][cout] float32."""
+    import torch
+    H, W, cin = x.shape
+    cout = w_bf16.shape[0]
+    y = torch.empty((H, W, cout), device=x.device, dtype=torch.float32)
+    code = load().fd_conv3x3(torch.cuda.current_stream().cuda_stream, H, W, cin, cout, _ptr(x.contiguous()),
+                             1 if x_is_f32 else 0, _ptr(w_bf16.contiguous()), _ptr(bias), 1 if relu else 0, _ptr(y))
+    if code != 0:
+        raise FdError(code, "fd_conv3x3 failed")
+    return y
+
+
+def conv3x3_wgrad(x_bf16, g, want_bias=True):
+    """fd_conv3x3_wgrad: (dw [cout][9][cin], db [cout] or None) float32."""
+    import torch
+    H, W, cin = x_bf16.shape
+    cout = g.shape[-1]
+    dw = torch.empty((cout, 9, cin), device=g.device, dtype=torch.float32)
+    db = torch.empty(cout, device=g.device, dtype=torch.float32) if want_bias else None
+    code = load().fd_conv3x3_wgrad(torch.cuda.current_stream().cuda_stream, H, W, cin, cout,
+                                   _ptr(x_bf16.contiguous()), _ptr(g.contiguous()), _ptr(dw), _ptr(db))
+    if code != 0:
+        raise FdError(code, "fd_conv3x3_wgrad failed")
+    return dw, db
 
 
 def init_params(shapes, seed: int = 0) -> np.ndarray:
@@ -194,30 +249,88 @@ def render_pair(r: facert.Renderer, i: int, spp_in: int, spp_ref: int, seed: int
 
 
 def train(r: facert.Renderer, dn: Denoiser, pairs: int, epochs: int, spp_in: int = 2, spp_target: int = 256,
-          lr: float = 1e-3, seed: int = 0, log=sys.stderr):
-    """Seeded initialisation, renderer-generated pairs, Adam with a cosine
-    decaying step.  Returns (data seconds, training seconds, loss per epoch)."""
+          lr: float = 1e-3, seed: int = 0, log=sys.stderr, first_pair: int = 0, state: dict | None = None,
+          total_steps: int | None = None):
+    """Renderer-generated pairs first_pair .. first_pair + pairs - 1, then
+    epochs passes over them with Adam and a cosine-decaying step over
+    total_steps (default: this call's steps).  Starts from a seeded
+    initialisation, or from state (a checkpoint of get_state; its step count
+    continues the schedule).  Returns (data seconds, training seconds, loss
+    per epoch)."""
     import torch
-    dn.set_params(torch.from_numpy(init_params(dn.layer_shapes(), seed)).cuda())
+    if state is None:
+        dn.set_params(torch.from_numpy(init_params(dn.layer_shapes(), seed)).cuda())
+        step0 = 0
+    else:
+        dn.set_state(state)
+        step0 = int(state["step"])
     t0 = time.perf_counter()
-    data = [render_pair(r, i, spp_in, spp_target, 50_000 + 7 * i) for i in range(pairs)]
+    data = []
+    for i in range(first_pair, first_pair + pairs):
+        data.append(render_pair(r, i, spp_in, spp_target, 50_000 + 7 * i))
+        if log and (i - first_pair + 1) % 500 == 0:
+            torch.cuda.synchronize()
+            print(f"rendered {i - first_pair + 1}/{pairs} pairs ({time.perf_counter() - t0:.0f} s)", file=log,
+                  flush=True)
     torch.cuda.synchronize()
     t_data = time.perf_counter() - t0
-    rng = np.random.default_rng(seed)
+    rng = np.random.default_rng(seed + first_pair)
     losses = []
     steps = epochs * pairs
+    total = total_steps or (step0 + steps)
     t0 = time.perf_counter()
     for ep in range(epochs):
         for k in rng.permutation(pairs):
-            step = len(losses)
+            step = step0 + len(losses)
             rgb, aux, ref = data[k]
-            losses.append(dn.train_step(rgb, aux, ref, lr * 0.5 * (1.0 + math.cos(math.pi * step / steps))))
+            losses.append(dn.train_step(rgb, aux, ref, lr * 0.5 * (1.0 + math.cos(math.pi * min(step, total) / total))))
         if log:
-            print(f"epoch {ep}: loss {float(torch.stack(losses[-pairs:]).mean()):.5f}", file=log, flush=True)
+            print(f"epoch {ep}: loss {float(torch.stack(losses[-pairs:]).mean()):.5f} "
+                  f"({time.perf_counter() - t0:.0f} s)", file=log, flush=True)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     curve = [float(x) for x in torch.stack(losses).reshape(epochs, -1).mean(1)]
     return t_data, t_train, curve
+
+
+def conv_flops(shapes, H: int, W: int) -> float:
+    """Multiply-add FLOPs (2 per MAC) of one forward pass at H x W."""
+    levels = [0, 0, 1, 1, 2, 2, 3, 3, 2, 2, 1, 1, 0, 0, 0]
+    return float(sum(2.0 * (H >> lv) * (W >> lv) * k * k * ci * co for (ci, co, k), lv in zip(shapes, levels)))
+
+
+def bench(H: int = 256, W: int = 256, reps: int = 20) -> dict:
+    """Time fd_forward, fd_backward_input and fd_train_step on one H x W image
+    (seeded weights and inputs) with HIP events on the network's stream."""
+    import torch
+    dn = Denoiser(H, W)
+    shapes = dn.layer_shapes()
+    dn.set_params(torch.from_numpy(init_params(shapes, 0)).cuda())
+    g = torch.Generator(device="cpu").manual_seed(0)
+    rgb = (torch.rand((H, W, 3), generator=g) * 0.05).cuda()
+    aux = torch.rand((H, W, 7), generator=g).cuda()
+    tgt = (torch.rand((H, W, 3), generator=g) * 0.05).cuda()
+    out = torch.empty_like(rgb)
+    flops = conv_flops(shapes, H, W)
+
+    def timed(fn):
+        for _ in range(3):
+            fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    ms_f = timed(lambda: dn.forward(rgb, aux, out))
+    ms_b = timed(lambda: dn.backward_input(rgb, out))
+    ms_t = timed(lambda: dn.train_step(rgb, aux, tgt, 0.0))
+    dn.close()
+    # a training step runs the forward, the input-gradient and the weight-gradient GEMMs: 3x the forward's FLOPs
+    return {"H": H, "W": W, "gflop_forward": flops / 1e9, "ms_forward": ms_f, "ms_backward_input": ms_b,
+            "ms_train_step": ms_t, "tflops_forward": flops / ms_f / 1e9, "tflops_train_step": 3 * flops / ms_t / 1e9}
 
 
 def main():
@@ -230,14 +343,35 @@ def main():
     ap.add_argument("--eval", type=int, default=4, help="held-out scenes")
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--first-pair", type=int, default=0, help="index of the first training scene of this run")
+    ap.add_argument("--resume", default=None, help="checkpoint (.npz) to continue from")
+    ap.add_argument("--save", default=None, help="write the training state (.npz) here")
+    ap.add_argument("--total-steps", type=int, default=None, help="length of the cosine schedule across runs")
+    ap.add_argument("--bench", action="store_true", help="only time the network's calls at 256x256")
     args = ap.parse_args()
     import torch
     assert torch.cuda.is_available(), "the denoiser needs a HIP device"
+    if args.bench:
+        print(json.dumps(bench()))
+        return
     model, scene, _, _ = synth.workload("paper")
     r = facert.Renderer(model, scene)
     dn = Denoiser(scene.height, scene.width)
-    t_data, t_train, curve = train(r, dn, args.pairs, args.epochs, args.spp_in, args.spp_target, args.lr, args.seed)
+    state = None
+    if args.resume:
+        with np.load(args.resume, allow_pickle=False) as z:
+            state = {k: z[k] for k in ("params", "m", "v", "step")}
     steps = args.epochs * args.pairs
+    t_data, t_train, curve = (0.0, 0.0, [])
+    if args.pairs > 0:
+        t_data, t_train, curve = train(r, dn, args.pairs, args.epochs, args.spp_in, args.spp_target, args.lr,
+                                       args.seed, first_pair=args.first_pair, state=state,
+                                       total_steps=args.total_steps)
+    elif state is not None:
+        dn.set_state(state)
+    if args.save:
+        st = dn.get_state()
+        np.savez(args.save, **st)
 
     # held-out evaluation against a 1024-spp reference
     spps = [2, 4, 8, 16, 32, 64, 128, 256]
@@ -283,7 +417,9 @@ def main():
     if equiv is None and den > plain[spps[-1]]:
         equiv = f">{spps[-1]}"
     out = {"pairs": args.pairs, "epochs": args.epochs, "spp_in": args.spp_in, "spp_target": args.spp_target,
-           "data_s": t_data, "train_s": t_train, "ms_per_train_step": t_train / steps * 1e3, "loss_per_epoch": curve,
+           "first_pair": args.first_pair, "resumed": bool(args.resume),
+           "data_s": t_data, "train_s": t_train, "ms_per_train_step": t_train / max(steps, 1) * 1e3,
+           "loss_per_epoch": curve,
            "psnr_db": {"denoised_2spp": den, "plain": plain}, "equal_psnr_plain_spp": equiv, "timing": timing}
     print(json.dumps(out))
 

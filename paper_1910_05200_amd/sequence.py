@@ -98,9 +98,28 @@ def frame_renderers(model, scene, n: int):
     return [facert.Renderer(model, scene) for _ in range(n)]
 
 
+def _state_out(shared, betas, poses, st, stf, it, elapsed, log, nonfinite) -> dict:
+    """Host copy of a run's state, for a checkpoint (see run)."""
+    h = lambda t: t.detach().cpu().numpy()
+    d = {"iter": np.int64(it), "elapsed": np.float64(elapsed),
+         "log": np.frombuffer(json.dumps({"log": log, "nonfinite": nonfinite}).encode(), np.uint8)}
+    for k in SHARED:
+        d[f"p_{k}"], d[f"m_{k}"], d[f"v_{k}"] = h(shared[k]), h(st[k][0]), h(st[k][1])
+    d["betas"] = np.stack([h(b) for b in betas])
+    d["poses"] = np.stack([h(q) for q in poses])
+    d["mb"] = np.stack([h(x[0][0]) for x in stf]); d["vb"] = np.stack([h(x[0][1]) for x in stf])
+    d["mp"] = np.stack([h(x[1][0]) for x in stf]); d["vp"] = np.stack([h(x[1][1]) for x in stf])
+    return d
+
+
 def run(r: facert.Renderer, targets, base, frames, start, start_frames, iters: int, mode: str, spp: int,
         dn: denoise.Denoiser = None, eval_spp: int = synth.TARGET_SPP, log_every: int = 25, decay: float = fit.DECAY,
-        rs=None):
+        rs=None, seed: int = 0, state: dict | None = None, stop_after_s: float | None = None):
+    """Fit for iterations [state's iteration or 0, iters) (the step-size
+    schedule spans all iters).  seed offsets the render seeds.  state
+    resumes a checkpoint written by an earlier call (the "state" entry of the
+    result, present when the run stopped early at stop_after_s seconds of
+    fitting)."""
     import torch
     shared = facert.params_to_device(start)
     shared.pop("beta"), shared.pop("pose")
@@ -113,6 +132,20 @@ def run(r: facert.Renderer, targets, base, frames, start, start_frames, iters: i
     n = len(targets)
     log, elapsed = [], 0.0
     nonfinite = {}                       # parameter group -> skipped updates
+    it0 = 0
+    if state is not None:
+        dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+        for k in SHARED:
+            shared[k].copy_(dev(state[f"p_{k}"]).reshape(shared[k].shape))
+            st[k][0].copy_(dev(state[f"m_{k}"]).reshape(shared[k].shape))
+            st[k][1].copy_(dev(state[f"v_{k}"]).reshape(shared[k].shape))
+        for f in range(n):
+            betas[f].copy_(dev(state["betas"][f])); poses[f].copy_(dev(state["poses"][f]))
+            stf[f][0][0].copy_(dev(state["mb"][f])); stf[f][0][1].copy_(dev(state["vb"][f]))
+            stf[f][1][0].copy_(dev(state["mp"][f])); stf[f][1][1].copy_(dev(state["vp"][f]))
+        it0, elapsed = int(state["iter"]), float(state["elapsed"])
+        meta = json.loads(bytes(state["log"]).decode())
+        log, nonfinite = meta["log"], meta["nonfinite"]
     batch = None
     if rs is not None and len(rs) == n and r.W * r.H * spp <= facert.FR_CHUNK_MAX:
         batch = facert.Batch(rs)
@@ -126,15 +159,20 @@ def run(r: facert.Renderer, targets, base, frames, start, start_frames, iters: i
         log.append({"iter": it, "seconds": elapsed, "psnr_db": float(np.mean(psnrs)), "errors": e})
         print(f"{mode}:{spp} iteration {it}: {elapsed:.2f} s, {log[-1]['psnr_db']:.2f} dB", file=sys.stderr, flush=True)
 
-    evaluate(0)
-    for it in range(iters):
+    if it0 == 0:
+        evaluate(0)
+    stopped = None
+    for it in range(it0, iters):
+        if stop_after_s is not None and elapsed - (float(state["elapsed"]) if state is not None else 0.0) > stop_after_s:
+            stopped = it
+            break
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         acc = {k: torch.zeros_like(shared[k]) for k in SHARED}
         f_lr = decay ** (it / max(1, iters - 1))
         pose_h = torch.stack(poses).cpu().numpy()
         ps = [frame_params(shared, betas[f], pose_h[f]) for f in range(n)]
-        seeds = [1000 + it * n + f for f in range(n)]
+        seeds = [1000 + 10_000_000 * seed + it * n + f for f in range(n)]
 
         def data_grad(rf, img, f):
             if mode in ("denoised", "denoised-st"):
@@ -177,8 +215,13 @@ def run(r: facert.Renderer, targets, base, frames, start, start_frames, iters: i
             evaluate(it + 1)
     if batch is not None:
         batch.close()
-    return {"mode": mode, "spp": spp, "frames": n, "iters": iters, "s_per_iter": elapsed / iters,
-            "batched": batch is not None, "nonfinite_updates_skipped": nonfinite, "log": log}
+    done = stopped if stopped is not None else iters
+    out = {"mode": mode, "spp": spp, "frames": n, "iters": iters, "iters_done": done, "seed": seed,
+           "s_per_iter": elapsed / max(1, done), "batched": batch is not None,
+           "nonfinite_updates_skipped": nonfinite, "log": log}
+    if stopped is not None:
+        out["state"] = _state_out(shared, betas, poses, st, stf, stopped, elapsed, log, nonfinite)
+    return out
 
 
 def main():
@@ -194,6 +237,12 @@ def main():
     ap.add_argument("--dn-epochs", type=int, default=10)
     ap.add_argument("--log-every", type=int, default=25)
     ap.add_argument("--sequential", action="store_true", help="render and differentiate frame by frame")
+    ap.add_argument("--seed", type=int, default=0, help="start perturbation and render seeds of the run")
+    ap.add_argument("--dn-ckpt", default=None, help="denoiser checkpoint (.npz from denoise.py --save) to use "
+                                                    "instead of training one")
+    ap.add_argument("--resume", default=None, help="continue the (single) mode from this checkpoint (.npz)")
+    ap.add_argument("--save-state", default=None, help="where to write the checkpoint if the run stops early")
+    ap.add_argument("--stop-after", type=float, default=None, help="stop after this many seconds of fitting")
     args = ap.parse_args()
     import torch
     assert torch.cuda.is_available(), "sequence fitting needs a HIP device"
@@ -201,12 +250,17 @@ def main():
     r = facert.Renderer(model, scene)
     rs = None if args.sequential else frame_renderers(model, scene, args.frames)
     base, frames = make_truth(args.frames)
-    start, start_frames = make_start(base, frames)
+    start, start_frames = make_start(base, frames, seed=fit.START_SEED + args.seed)
     targets = [r.render(facert.params_to_device(frame_params_np(base, b, p)), synth.TARGET_RENDER_SEED + f,
                         synth.TARGET_SPP).clone() for f, (b, p) in enumerate(frames)]
     dn = None
     modes = [(m.split(":")[0], int(m.split(":")[1])) for m in args.modes.split(",")]
-    if any(m.startswith("denoised") for m, _ in modes):
+    if any(m.startswith("denoised") for m, _ in modes) and args.dn_ckpt:
+        dn = denoise.Denoiser(scene.height, scene.width)
+        with np.load(args.dn_ckpt, allow_pickle=False) as z:
+            dn.set_params(torch.from_numpy(np.ascontiguousarray(z["params"], np.float32)).cuda())
+        print(json.dumps({"denoiser": args.dn_ckpt}), flush=True)
+    elif any(m.startswith("denoised") for m, _ in modes):
         t0 = time.perf_counter()
         dn = denoise.Denoiser(scene.height, scene.width)
         dw = args.dn_workload or args.workload
@@ -223,9 +277,18 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"denoiser_training_s": time.perf_counter() - t0, "pairs": args.dn_pairs,
                           "epochs": args.dn_epochs, "trained_on": dw}), flush=True)
+    state = None
+    if args.resume:
+        assert len(modes) == 1, "--resume continues one mode"
+        with np.load(args.resume, allow_pickle=False) as z:
+            state = {k: z[k] for k in z.files}
     for m, spp in modes:
         out = run(r, targets, base, frames, start, start_frames, args.iters, m, spp, dn, log_every=args.log_every,
-                  rs=rs)
+                  rs=rs, seed=args.seed, state=state, stop_after_s=args.stop_after)
+        st = out.pop("state", None)
+        if st is not None and args.save_state:
+            np.savez(args.save_state, **st)
+            out["saved_state"] = args.save_state
         print(json.dumps(out), flush=True)
 
 

@@ -264,7 +264,7 @@ def test_batch_relaunch_does_not_disturb_enqueued_work(torch):
         g_first = batch.backward(dls)
         batch.set_launch("sh_propose", 1, 0)
         batch.set_launch("edge_secondary", 0, 512)
-        batch.set_launch("pv_propose", 1, 256)
+        batch.set_launch("pv_propose", 1, 0)
         second = batch.render(ps, [x + 1 for x in seeds], spps)
         for _ in range(4):
             a = a @ a * 1e-3
@@ -310,6 +310,8 @@ def test_batch_errors(torch):
     for bad in [(0, 300), (0, 1024), (2, 512), (-1, 256)]:
         with pytest.raises(facert.FrError):
             batch.set_launch("edge_secondary", *bad)
+    with pytest.raises(facert.FrError):             # only edge_secondary takes a tile size
+        batch.set_launch("pv_propose", 1, 256)
     batch.render(ps, seeds, spps)
     rs[1].render(ps[1], 9, spps[1])           # instance 1 rendered on its own since
     with pytest.raises(facert.FrError) as e:

@@ -149,3 +149,85 @@ def test_bad_arguments(torch):
     with pytest.raises(denoise.FdError) as e:            # no fd_forward yet
         dn.backward_input(torch.zeros(16, 16, 3, device="cuda"), torch.zeros(16, 16, 3, device="cuda"))
     assert e.value.code == -4
+
+
+# ---------------------------------------------------------------------------
+# Single layers, element by element.  Each kernel of the network (the 3x3
+# convolution, its input-gradient form on fp32 gradients, the weight and
+# bias gradients) against the float64 oracle on bfloat16-representable
+# inputs: the only differences left are the order and precision of the fp32
+# sums, so the renderer's parity rule applies, |gpu - ref| <= 1e-4 *
+# max(|ref|, 1e-2 * max|ref|).  Sizes cover ragged pixel tiles (8 x 16) and
+# channel counts that are not multiples of the channel tile.
+
+LAYER_CASES = [(8, 16, 16, 32), (24, 40, 32, 64), (17, 23, 96, 32), (13, 31, 64, 128), (32, 32, 384, 128),
+               (16, 16, 256, 256), (9, 33, 32, 16), (64, 64, 32, 32)]
+
+
+def _bf16_bits(t64):
+    """bfloat16 bit patterns (int16 tensor) of the bfloat16-rounded values."""
+    import torch
+    r = unet.bf16_round(torch.as_tensor(t64))
+    u = r.to(torch.float32).contiguous().numpy().view(np.uint32) >> 16
+    return torch.from_numpy(u.astype(np.uint16).view(np.int16)), r.numpy()
+
+
+def _floor_rule(got, ref, name):
+    from parity import assert_group_parity
+    return assert_group_parity(got, ref, name)
+
+
+@pytest.mark.parametrize("H,W,cin,cout", LAYER_CASES)
+def test_conv3x3_layer_elementwise(torch, H, W, cin, cout):
+    from paper_1910_05200_amd import denoise
+    rng = np.random.default_rng(H * 1000 + cin)
+    xb, x = _bf16_bits(rng.normal(size=(H, W, cin)))
+    wb, w = _bf16_bits(rng.normal(0, 1 / np.sqrt(9 * cin), size=(cout, 9, cin)))
+    bias = rng.normal(0, 0.1, size=cout).astype(np.float32)
+    y = denoise.conv3x3(xb.cuda(), wb.cuda(), torch.from_numpy(bias).cuda(), relu=True)
+    torch.cuda.synchronize()
+    ref = unet.conv3x3_layer(x, w, bias.astype(np.float64), relu=True)
+    print(_floor_rule(y.cpu().numpy(), ref, f"conv {H}x{W} {cin}->{cout}"))
+
+
+@pytest.mark.parametrize("H,W,cin,cout", LAYER_CASES[:5])
+def test_conv3x3_input_gradient_elementwise(torch, H, W, cin, cout):
+    """The input-gradient pass: fp32 gradients (rounded to bfloat16 as read)
+    through the flipped, transposed weights equal the oracle's input
+    gradient of the layer."""
+    from paper_1910_05200_amd import denoise
+    rng = np.random.default_rng(W * 100 + cout)
+    g = rng.normal(size=(H, W, cout)).astype(np.float32)
+    _, g_r = _bf16_bits(g.astype(np.float64))
+    wb, w = _bf16_bits(rng.normal(0, 1 / np.sqrt(9 * cin), size=(cout, 9, cin)))
+    # flipped, transposed weights: wf[ci][t][co] = w[co][8 - t][ci]
+    wf = np.ascontiguousarray(w[:, ::-1, :].transpose(2, 1, 0))
+    wfb, _ = _bf16_bits(wf)
+    dx = denoise.conv3x3(torch.from_numpy(g).cuda(), wfb.cuda(), x_is_f32=True)
+    torch.cuda.synchronize()
+    print(_floor_rule(dx.cpu().numpy(), unet.conv3x3_input_grad(g_r, w), f"input grad {H}x{W} {cin}<-{cout}"))
+
+
+@pytest.mark.parametrize("H,W,cin,cout", LAYER_CASES)
+def test_conv3x3_weight_gradient_elementwise(torch, H, W, cin, cout):
+    from paper_1910_05200_amd import denoise
+    rng = np.random.default_rng(H + W + cin + cout)
+    xb, x = _bf16_bits(rng.normal(size=(H, W, cin)))
+    g = rng.normal(size=(H, W, cout)).astype(np.float32)
+    _, g_r = _bf16_bits(g.astype(np.float64))
+    dw, db = denoise.conv3x3_wgrad(xb.cuda(), torch.from_numpy(g).cuda())
+    torch.cuda.synchronize()
+    ref_w, ref_b = unet.conv3x3_weight_grad(x, g_r)
+    print(_floor_rule(dw.cpu().numpy(), ref_w, f"weight grad {H}x{W} {cin}->{cout}"))
+    # the bias gradient sums the unrounded fp32 gradient
+    print(_floor_rule(db.cpu().numpy(), g.astype(np.float64).sum(axis=(0, 1)), "bias grad"))
+
+
+def test_single_layer_argument_errors(torch):
+    from paper_1910_05200_amd import denoise
+    lib = denoise.load()
+    z = torch.zeros(64, device="cuda")
+    assert lib.fd_conv3x3(None, 4, 4, 24, 8, z.data_ptr(), 0, z.data_ptr(), None, 0, z.data_ptr()) == -1  # cin % 16
+    assert lib.fd_conv3x3(None, 0, 4, 16, 8, z.data_ptr(), 0, z.data_ptr(), None, 0, z.data_ptr()) == -1
+    assert lib.fd_conv3x3(None, 4, 4, 16, 8, None, 0, z.data_ptr(), None, 0, z.data_ptr()) == -1
+    assert lib.fd_conv3x3_wgrad(None, 4, 4, 12, 8, z.data_ptr(), z.data_ptr(), z.data_ptr(), None) == -1

@@ -77,3 +77,33 @@ def test_gradient_matches_finite_differences(which):
         pm[j] -= h
         fd = (unet.loss_and_grad(pp, rgb, aux, tgt)[0] - unet.loss_and_grad(pm, rgb, aux, tgt)[0]) / (2 * h)
         assert fd == pytest.approx(g[j], rel=1e-5, abs=1e-10)
+
+
+def test_single_layer_gradients_are_the_adjoints_of_the_layer():
+    """The single-layer references: the input and weight gradients satisfy
+    <conv(x, w), g> = <x, input_grad(g, w)> = <w, weight_grad(x, g)>, and
+    the bias gradient is the sum of g; the layer itself is the direct-loop
+    layout (test_conv_layout_matches_a_direct_loop) through conv3x3_layer."""
+    rng = np.random.default_rng(4)
+    H, W, ci, co = 6, 9, 16, 24
+    x, w, g = rng.normal(size=(H, W, ci)), rng.normal(size=(co, 9, ci)), rng.normal(size=(H, W, co))
+    b = rng.normal(size=co)
+    y = unet.conv3x3_layer(x, w)
+    dx = unet.conv3x3_input_grad(g, w)
+    dw, db = unet.conv3x3_weight_grad(x, g)
+    lhs = float(np.sum(y * g))
+    assert abs(lhs - float(np.sum(x * dx))) <= 1e-10 * abs(lhs)
+    assert abs(lhs - float(np.sum(w * dw))) <= 1e-10 * abs(lhs)
+    np.testing.assert_allclose(db, g.sum(axis=(0, 1)), rtol=1e-12)
+    yb = unet.conv3x3_layer(x, w, b, relu=True)
+    pre = y + b
+    np.testing.assert_allclose(yb, np.where(pre > 0, pre, unet.SLOPE * pre), rtol=1e-12, atol=1e-12)
+    # the direct loop of the layout pin, once more through conv3x3_layer
+    want = np.zeros((H, W, co))
+    for yy in range(H):
+        for xx in range(W):
+            for t in range(9):
+                sy, sx = yy + t // 3 - 1, xx + t % 3 - 1
+                if 0 <= sy < H and 0 <= sx < W:
+                    want[yy, xx] += w[:, t, :] @ x[sy, sx]
+    np.testing.assert_allclose(y, want, rtol=1e-11, atol=1e-11)
