@@ -63,8 +63,10 @@ __device__ __forceinline__ void blend_body(int V, int n_id, int n_exp, int n_alb
         const float *__restrict__ mean, const float *__restrict__ b_id, const float *__restrict__ b_exp,
         const float *__restrict__ alb_mean, const float *__restrict__ b_alb,
         const float *__restrict__ alpha, const float *__restrict__ beta, const float *__restrict__ delta,
-        double *__restrict__ vm_d, float *__restrict__ vmodel, float *__restrict__ alb, int bx, int row) {
+        double *__restrict__ vm_d, float *__restrict__ vmodel, float *__restrict__ alb, int bx, int row,
+        float *geo_R) {
     int i = bx * blockDim.x + threadIdx.x;
+    if (bx == 0 && row == 0 && threadIdx.x == 0) *geo_R = 0.0f;   // pose_body takes the maximum
     if (i >= V) return;
     size_t V3 = (size_t)3 * V;
     if (row < 3) {
@@ -88,24 +90,33 @@ __global__ __launch_bounds__(64) void k_blend(int V, int n_id, int n_exp, int n_
         const float *__restrict__ mean, const float *__restrict__ b_id, const float *__restrict__ b_exp,
         const float *__restrict__ alb_mean, const float *__restrict__ b_alb,
         const float *__restrict__ alpha, const float *__restrict__ beta, const float *__restrict__ delta,
-        double *__restrict__ vm_d, float *__restrict__ vmodel, float *__restrict__ alb) {
+        double *__restrict__ vm_d, float *__restrict__ vmodel, float *__restrict__ alb, float *geo_R) {
     blend_body(V, n_id, n_exp, n_alb, mean, b_id, b_exp, alb_mean, b_alb, alpha, beta, delta, vm_d, vmodel, alb,
-               blockIdx.x, blockIdx.y);
+               blockIdx.x, blockIdx.y, geo_R);
 }
 
+// Also the largest |coordinate| of the posed vertices, into *geo_R (zeroed
+// by blend_body; one atomic maximum per wave on the bit pattern, which
+// orders non-negative floats): the shadow-boundary proposals' plane
+// pre-test scales its rounding bound by it.
 __device__ __forceinline__ void pose_body(int V, const double *__restrict__ vm_d, const PoseArgs &P,
-                                          float *__restrict__ pos, int bx) {
+                                          float *__restrict__ pos, int bx, float *geo_R) {
     int i = bx * blockDim.x + threadIdx.x;
-    if (i >= V) return;
-    double m[3] = {vm_d[i], vm_d[V + i], vm_d[2 * (size_t)V + i]};
-    for (int c = 0; c < 3; ++c) {
-        double v = ((P.R[3 * c] * m[0] + P.R[3 * c + 1] * m[1]) + P.R[3 * c + 2] * m[2]) + P.t[c];
-        pos[(size_t)c * V + i] = (float)v;
+    float r = 0.0f;
+    if (i < V) {
+        double m[3] = {vm_d[i], vm_d[V + i], vm_d[2 * (size_t)V + i]};
+        for (int c = 0; c < 3; ++c) {
+            double v = ((P.R[3 * c] * m[0] + P.R[3 * c + 1] * m[1]) + P.R[3 * c + 2] * m[2]) + P.t[c];
+            pos[(size_t)c * V + i] = (float)v;
+            r = fmaxf(r, fabsf((float)v));
+        }
     }
+    for (int off = 32; off > 0; off >>= 1) r = fmaxf(r, __shfl_xor(r, off));
+    if ((threadIdx.x & 63) == 0 && r > 0.0f) atomicMax((unsigned int *)geo_R, __float_as_uint(r));
 }
 __global__ __launch_bounds__(256) void k_pose(int V, const double *__restrict__ vm_d, PoseArgs P,
-                                              float *__restrict__ pos) {
-    pose_body(V, vm_d, P, pos, blockIdx.x);
+                                              float *__restrict__ pos, float *geo_R) {
+    pose_body(V, vm_d, P, pos, blockIdx.x, geo_R);
 }
 
 // ---------------------------------------------------------- normals -----
@@ -203,8 +214,20 @@ __device__ __forceinline__ bool project(const Scene &S, v3 x, float &sx, float &
 
 // weights: table 0 = camera silhouettes (screen length), table 1+j = shadow
 // candidates of light j (3D length).
+// Besides the 80-byte record, each edge gets a 32-byte plane record for the
+// proposals' pre-test: each face's unit normal u = N / |N| (N its fp32
+// cross product, the one the exact silhouette test uses) and offset
+// d = u . o (o its first vertex), NaN for a boundary edge's first face.
+// For a shading point p, t = u . p - d approximates N . (p - o) / |N| within
+// about 17 eps (|p|_inf + R) + eps |t| (R: largest |coordinate| of the
+// posed mesh, eps = 2^-24), and the exact fp32 value of N . (p - o), as the
+// silhouette test computes it, lies within 7 eps (|p|_inf + R) |N| of the
+// real one.  So |t| > 64 eps (|p|_inf + R) + 4 eps |t| fixes the exact
+// test's sign; when both faces' signs are fixed and equal, the exact test
+// would reject the edge, and the proposal rejects it without the full
+// record (a NaN, from a degenerate face or a boundary edge, fixes nothing).
 __device__ __forceinline__ void edge_weights_body(const Scene &S, const float *__restrict__ lgeom,
-        float *__restrict__ w, float4 *__restrict__ rec, int tb) {
+        float *__restrict__ w, float4 *__restrict__ rec, float4 *__restrict__ pl, int tb) {
     const int e = tb * blockDim.x + threadIdx.x;
     if (e >= S.E) return;
     const int *ed = S.edges + 4 * e;
@@ -221,6 +244,15 @@ __device__ __forceinline__ void edge_weights_body(const Scene &S, const float *_
     rec[5 * e + 2] = make_float4(n1.z, o1.x, o1.y, o1.z);
     rec[5 * e + 3] = make_float4(n2.x, n2.y, n2.z, o2.x);
     rec[5 * e + 4] = make_float4(o2.y, o2.z, __int_as_float(ed[2]), __int_as_float(ed[3]));
+    if (interior) {
+        const float l1 = sqrtf(dot(n1, n1)), l2 = sqrtf(dot(n2, n2));
+        const v3 u1 = mk(n1.x / l1, n1.y / l1, n1.z / l1), u2 = mk(n2.x / l2, n2.y / l2, n2.z / l2);
+        pl[2 * e] = make_float4(u1.x, u1.y, u1.z, dot(u1, o1));
+        pl[2 * e + 1] = make_float4(u2.x, u2.y, u2.z, dot(u2, o2));
+    } else {
+        pl[2 * e] = make_float4(NAN, NAN, NAN, NAN);
+        pl[2 * e + 1] = make_float4(NAN, NAN, NAN, NAN);
+    }
     size_t E = (size_t)S.E;
     v3 cam = mk(S.cam_x, S.cam_y, S.cam_z);
     bool sil = true;
@@ -254,8 +286,8 @@ __device__ __forceinline__ void edge_weights_body(const Scene &S, const float *_
     }
 }
 __global__ __launch_bounds__(256) void k_edge_weights(Scene S, const float *__restrict__ lgeom,
-        float *__restrict__ w, float4 *__restrict__ rec) {
-    edge_weights_body(S, lgeom, w, rec, blockIdx.x);
+        float *__restrict__ w, float4 *__restrict__ rec, float4 *__restrict__ pl) {
+    edge_weights_body(S, lgeom, w, rec, pl, blockIdx.x);
 }
 
 // One block per table: the table's max weight wmax (block reduction), then
@@ -1105,7 +1137,7 @@ template <int kMode>
 __device__ inline bool secondary_edge(const Scene &S, const Light &L, int j, uint64_t seed, uint32_t sidx,
                                       const float *spec_lds, v3 o, v3 dcam, const Hit &h, const SurfDec &sf,
                                       const float *w, double *d_pos, bool &vp, uint32_t &n_rays, Work &steps,
-                                      v3 *d_sides = nullptr) {
+                                      float geoR, v3 *d_sides = nullptr) {
     int n = S.se_n[j];
     uint64_t Q = S.se_Q[j];
     if (n == 0 || Q == 0) return false;
@@ -1114,6 +1146,15 @@ __device__ inline bool secondary_edge(const Scene &S, const Light &L, int j, uin
     uint64_t target = __umul64hi(((uint64_t)wd.y << 32) | wd.x, Q);
     int i = cdf_pick_guided(pre, S.se_guide + (size_t)j * (S.E + 1), n, Q, target);
     int e = S.se_edge[(size_t)j * S.E + i];
+    {   // the plane pre-test (edge_weights_body): most proposals end here
+        const float4 q1 = S.edge_pl[2 * (size_t)e], q2 = S.edge_pl[2 * (size_t)e + 1];
+        const v3 p = sf.p;
+        const float t1 = dot(mk(q1.x, q1.y, q1.z), p) - q1.w, t2 = dot(mk(q2.x, q2.y, q2.z), p) - q2.w;
+        const float eps = 5.9604645e-8f;
+        const float base = 64.0f * eps * (fmaxf(fmaxf(fabsf(p.x), fabsf(p.y)), fabsf(p.z)) + geoR);
+        const float b1 = base + 4.0f * eps * fabsf(t1), b2 = base + 4.0f * eps * fabsf(t2);
+        if ((t1 > b1 && t2 > b2) || (t1 < -b1 && t2 < -b2)) return false;
+    }
     // the edge's endpoints, its faces' normals and first vertices (the
     // values face_normal and vpos give), and the face ids
     const float4 *er = S.edge_rec + 5 * (size_t)e;
@@ -1231,6 +1272,7 @@ __device__ __forceinline__ void edge_secondary_body(const Scene &S, uint64_t see
     }
     if (threadIdx.x == 0) q_n = 0;
     __syncthreads();
+    const float geoR = *S.geo_R;
     const long long base = (long long)bx * TS;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     uint32_t n_sec = 0;
@@ -1247,7 +1289,7 @@ __device__ __forceinline__ void edge_secondary_body(const Scene &S, uint64_t see
             sec_setup(S, seed, spp, s0, i, dLdI, hits, o, d, w, h, sd, s, live);
             if (live) {
                 need = secondary_edge<kSecPropose>(S, Ls[j], j, seed, s, nullptr, o, d, h, sd, w, nullptr, vp, n_sec,
-                                                   wk, sides);
+                                                   wk, geoR, sides);
                 p0 = sd.p;
                 tri = h.tri;
             }
@@ -1303,6 +1345,7 @@ __device__ __forceinline__ void edge_secondary_value_body(const Scene &S, uint64
     stage_tables(S, Ls, spec_lds);
     __syncthreads();
     const uint32_t cnt = *list_n;
+    const float geoR = *S.geo_R;
     uint32_t n_dummy = 0;
     Work wk;
     for (uint32_t k = bx * blockDim.x + threadIdx.x; k < cnt; k += gx * blockDim.x) {
@@ -1312,7 +1355,7 @@ __device__ __forceinline__ void edge_secondary_value_body(const Scene &S, uint64
         bool vp = (q >> 30) & 1u;
         v3 o, d; float w[3]; Hit h; SurfDec sd; uint32_t s; bool live;
         sec_setup(S, seed, spp, s0, i, dLdI, hits, o, d, w, h, sd, s, live);
-        secondary_edge<kSecValue>(S, Ls[j], j, seed, s, spec_lds, o, d, h, sd, w, d_pos, vp, n_dummy, wk);
+        secondary_edge<kSecValue>(S, Ls[j], j, seed, s, spec_lds, o, d, h, sd, w, d_pos, vp, n_dummy, wk, geoR);
     }
 }
 __global__ __launch_bounds__(256) void k_edge_secondary_value(Scene S, uint64_t seed, int spp, long long s0,
@@ -2047,6 +2090,8 @@ struct fr_ctx {
     uint64_t *es_csum = nullptr;     // [1 + nl][chunks] quantised sums per chunk
     uint32_t *es_ccnt = nullptr;     // [1 + nl][chunks] positive counts per chunk
     float4 *edge_rec = nullptr;      // [E][5] edge geometry for the shadow-boundary proposals
+    float4 *edge_pl = nullptr;       // [E][2] face planes for their pre-test
+    float *geo_R = nullptr;          // largest |coordinate| of the posed vertices
     uint32_t *sh_queue = nullptr;    // [nl][sh_cap] queued shadow rays (sample index) per light
     size_t sh_cap = 0;               // its capacity per light (samples of one chunk); fr_render only
     uint32_t *sh_cnt = nullptr;      // [nl] queue lengths
@@ -2347,7 +2392,7 @@ static Scene make_scene(fr_ctx *c) {
     S.pe_edge = c->tbl_edge; S.pe_prefix = c->tbl_prefix; S.pe_n = c->tbl_n; S.pe_Q = c->tbl_Q;
     S.se_edge = c->tbl_edge + E; S.se_prefix = c->tbl_prefix + E; S.se_n = c->tbl_n + 1; S.se_Q = c->tbl_Q + 1;
     S.pe_guide = c->tbl_guide; S.se_guide = c->tbl_guide + (E + 1);
-    S.edge_rec = c->edge_rec;
+    S.edge_rec = c->edge_rec; S.edge_pl = c->edge_pl; S.geo_R = c->geo_R;
     return S;
 }
 
@@ -2436,6 +2481,7 @@ int fr_create(const fr_model_desc *m, const fr_scene_desc *s, uint32_t flags, fr
         R(dalloc(c, &c->es_wmax, (size_t)(1 + c->nl))) || R(dalloc(c, &c->sh_cnt, (size_t)c->nl)) ||
         R(dalloc(c, &c->es_csum, (size_t)(1 + c->nl) * nblk(c->E, kEsChunk))) ||
         R(dalloc(c, &c->es_ccnt, (size_t)(1 + c->nl) * nblk(c->E, kEsChunk))) || R(dalloc(c, &c->edge_rec, (size_t)5 * c->E)) ||
+        R(dalloc(c, &c->edge_pl, (size_t)2 * c->E)) || R(dalloc(c, &c->geo_R, 1)) ||
         R(dalloc(c, &c->ctr, (size_t)kCtrPerKern * kNumKern)) || R(dalloc(c, &c->sec_n, 1)) ||
         R(dalloc(c, &c->pe_samples, (size_t)c->W * c->H)) || R(dalloc(c, &c->pe_hits, 2 * (size_t)c->W * c->H)) ||
         R(dalloc(c, &c->pe_f, 6 * (size_t)c->W * c->H)) || R(dalloc(c, &c->pe_vis, 2 * (size_t)c->W * c->H)) ||
@@ -2543,8 +2589,9 @@ static int blend_impl(fr_ctx *c, const float *alpha, const float *beta, const fl
     drotation(pose, c->drot.dR);
     hipLaunchKernelGGL(k_blend, dim3(nblk(c->V, 64), 6), dim3(64), 0, c->stream, c->V, c->n_id, c->n_exp, c->n_alb,
                        c->mean, c->b_id, c->b_exp, c->alb_mean, c->b_alb, alpha, beta, delta,
-                       c->vm_d, c->vmodel, c->alb);
-    hipLaunchKernelGGL(k_pose, dim3(nblk(c->V, 256)), dim3(256), 0, c->stream, c->V, c->vm_d, c->pose, c->pos);
+                       c->vm_d, c->vmodel, c->alb, c->geo_R);
+    hipLaunchKernelGGL(k_pose, dim3(nblk(c->V, 256)), dim3(256), 0, c->stream, c->V, c->vm_d, c->pose, c->pos,
+                       c->geo_R);
     hipLaunchKernelGGL(k_normals, dim3(nblk(c->V, 256)), dim3(256), 0, c->stream, c->V, c->faces, c->vf_off, c->vf_idx,
                        c->pos, c->nrm, c->nlen);
     HIPCK(c, hipGetLastError());
@@ -2632,7 +2679,8 @@ int fr_render(fr_ctx *c, const fr_params *p, uint64_t seed, int32_t spp, float *
     }
     ev_record(c, 2);
     Scene S = make_scene(c);
-    hipLaunchKernelGGL(k_edge_weights, dim3(nblk(c->E, 256)), dim3(256), 0, c->stream, S, c->lgeom, c->ew, c->edge_rec);
+    hipLaunchKernelGGL(k_edge_weights, dim3(nblk(c->E, 256)), dim3(256), 0, c->stream, S, c->lgeom, c->ew, c->edge_rec,
+                       c->edge_pl);
     {
         const dim3 g(nblk(c->E, kEsChunk), 1 + c->nl);
         hipLaunchKernelGGL(k_zero_u32, dim3(nblk(1 + c->nl, 64)), dim3(64), 0, c->stream, c->es_wmax, 1 + c->nl);
@@ -2937,7 +2985,7 @@ void fr_destroy(fr_ctx *c) {
     void *ptrs[] = {c->faces, c->edges, c->vf_off, c->vf_idx, c->mean, c->b_id, c->b_exp, c->alb_mean, c->b_alb, c->uv,
                     c->lgeom, c->sorted_tri, c->leaf_node, c->right, c->escape, c->subs, c->height, c->top, c->top_off, c->nodes, c->tris,
                     c->vmodel, c->vm_d, c->pos, c->nrm, c->nlen, c->alb, c->ew, c->tbl_edge, c->tbl_prefix, c->tbl_n,
-                    c->tbl_Q, c->tbl_guide, c->es_wmax, c->es_csum, c->es_ccnt, c->edge_rec, c->samples, c->ctr, c->g_light, c->g_spec, c->g_pos, c->g_nrm, c->g_alb, c->g_N,
+                    c->tbl_Q, c->tbl_guide, c->es_wmax, c->es_csum, c->es_ccnt, c->edge_rec, c->edge_pl, c->geo_R, c->samples, c->ctr, c->g_light, c->g_spec, c->g_pos, c->g_nrm, c->g_alb, c->g_N,
                     c->g_vert, c->g_m, c->partial, c->loss_partial, c->hits, c->vis, c->sh_queue, c->sh_cnt, c->pe_q, c->pe_cell_n, c->pe_rec, c->sec_list, c->sec_n, c->pe_samples, c->pe_hits,
                     c->pe_f, c->pe_vis, c->pv_queue, c->pv_aux, c->pv_perm, c->lb.key[0], c->lb.key[1], c->lb.val[0], c->lb.val[1], c->lb.hist,
                     c->lb.bounds, c->lb.child, c->lb.parent, c->lb.first, c->lb.last, c->lb.pre, c->lb.arrive, c->lb.box, c->lb.roots, c->lb.n_roots, c->lb.top_idx, c->lb.n_top};

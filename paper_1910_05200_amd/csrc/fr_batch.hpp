@@ -50,7 +50,7 @@ struct Inst {
     double *vm_d;
     float *vmodel, *pos, *nrm, *nlen, *alb, *ew;
     int *tbl_edge, *tbl_n, *tbl_guide;
-    float4 *edge_rec;
+    float4 *edge_rec, *edge_pl;
     uint64_t *tbl_prefix, *tbl_Q;
     Node *nodes;
     float4 *tris;
@@ -109,9 +109,9 @@ static const char *const kKindName[bkNum] = {
 
 FR_KIND(KBlend, 64) {
     blend_body(I.S.V, I.n_id, I.n_exp, I.n_alb, I.mean, I.b_id, I.b_exp, I.alb_mean, I.b_alb, I.d.alpha, I.d.beta,
-               I.d.delta, I.vm_d, I.vmodel, I.alb, bx, by);
+               I.d.delta, I.vm_d, I.vmodel, I.alb, bx, by, I.S.geo_R);
 }};
-FR_KIND(KPose, 256) { pose_body(I.S.V, I.vm_d, I.d.P, I.pos, bx); }};
+FR_KIND(KPose, 256) { pose_body(I.S.V, I.vm_d, I.d.P, I.pos, bx, I.S.geo_R); }};
 FR_KIND(KNormals, 256) { normals_body(I.S.V, I.S.faces, I.vf_off, I.vf_idx, I.pos, I.nrm, I.nlen, bx); }};
 FR_KIND(KLbvhInit, 64) {
     lbvh_bounds_init_body(I.lb.bounds);
@@ -143,7 +143,7 @@ FR_KIND(KBoxesTop, 1024) {
     lbvh_boxes_top_body(I.S.F, I.lb.child, I.lb.parent, I.lb.first, I.lb.last, I.lb.pre, I.lb.top_idx, I.lb.arrive,
                         I.lb.box, I.nodes, I.lb.roots, I.lb.n_roots);
 }};
-FR_KIND(KEdgeWeights, 256) { edge_weights_body(I.S, I.S.lgeom, I.ew, I.edge_rec, bx); }};
+FR_KIND(KEdgeWeights, 256) { edge_weights_body(I.S, I.S.lgeom, I.ew, I.edge_rec, I.edge_pl, bx); }};
 FR_KIND(KEdgeScan, 1024) {
     edge_scan_body<1024>(I.S.E, I.ew, I.tbl_edge, I.tbl_prefix, I.tbl_n, I.tbl_Q, I.tbl_guide, bx);
 }};
@@ -262,10 +262,15 @@ __device__ __forceinline__ void run_tile(const Inst *__restrict__ tab, const Til
     K::run(tab[m.inst[lo]], arg, tl % gx, tl / gx, gx);
 }
 
-// one block per tile
+// One block per tile.  The grid is two-dimensional, rows of kRowTiles
+// blocks (the tile is the block's linear index; a dispatch's work-item
+// count per dimension must fit in 32 bits, and one row of a batch of many
+// large instances would not), and the last row's extra blocks exit.
+constexpr unsigned kRowTiles = 65536;
 template <class K>
 __global__ __launch_bounds__(K::kThreads) void k_multi(const Inst *__restrict__ tab, TileMap m, int arg) {
-    int t = blockIdx.x;
+    int t = (int)(blockIdx.y * gridDim.x + blockIdx.x);
+    if (t >= m.total) return;
     if (m.xcd) {
         const int x = t & 7, k = t >> 3, q = m.total >> 3, r = m.total & 7;
         t = x * q + min(x, r) + k;
@@ -419,7 +424,8 @@ static int build_plan(fr_batch *b) {
 
 template <class K>
 static void launch_k(fr_batch *b, const TileMap &m, int arg, unsigned grid, size_t lds) {
-    hipLaunchKernelGGL(k_multi<K>, dim3(grid), dim3(K::kThreads), lds, b->stream, b->tab, m, arg);
+    const unsigned gx = std::min(grid, kRowTiles), gy = (grid + kRowTiles - 1) / kRowTiles;
+    hipLaunchKernelGGL(k_multi<K>, dim3(gx, gy), dim3(K::kThreads), lds, b->stream, b->tab, m, arg);
 }
 
 static void launch_kind(fr_batch *b, int k, int arg = 0) {
@@ -585,7 +591,7 @@ static int configure(fr_batch *b, const int32_t *spp) {
         I.vf_off = c->vf_off; I.vf_idx = c->vf_idx;
         I.mean = c->mean; I.b_id = c->b_id; I.b_exp = c->b_exp; I.alb_mean = c->alb_mean; I.b_alb = c->b_alb;
         I.vm_d = c->vm_d; I.vmodel = c->vmodel; I.pos = c->pos; I.nrm = c->nrm; I.nlen = c->nlen; I.alb = c->alb;
-        I.ew = c->ew; I.edge_rec = c->edge_rec;
+        I.ew = c->ew; I.edge_rec = c->edge_rec; I.edge_pl = c->edge_pl;
         I.tbl_edge = c->tbl_edge; I.tbl_n = c->tbl_n; I.tbl_prefix = c->tbl_prefix; I.tbl_Q = c->tbl_Q;
         I.tbl_guide = c->tbl_guide;
         I.nodes = c->nodes; I.tris = c->tris;

@@ -89,6 +89,8 @@ struct Scene {
     const int *se_edge; const uint64_t *se_prefix; const int *se_n; const uint64_t *se_Q;  // [nl][E]
     const int *pe_guide, *se_guide;   // cut-point guides: [E + 1], [nl][E + 1]
     const float4 *edge_rec;           // [E][5]: endpoints, face normals and first vertices, face ids
+    const float4 *edge_pl;            // [E][2]: each face's unit normal and offset (see edge_weights_body)
+    float *geo_R;                     // largest |coordinate| of the posed vertices (a bound for edge_pl)
 };
 
 __device__ __forceinline__ v3 vpos_raw(const float *pos, int V, int i) {

@@ -281,6 +281,43 @@ def test_batch_relaunch_does_not_disturb_enqueued_work(torch):
             assert torch.equal(third[i], r.render(ps[i], seeds[i] + 2, spps[i] + 1)), f"third render, instance {i}"
 
 
+def test_batch_launch_beyond_32bit_work_items(torch):
+    """25 instances of 256 x 256 at 64 spp with 42 lights: the shadow-ray and
+    shadow-boundary kinds have 25 x 16,384 x 42 tiles of 256 lanes, 4.4e9
+    work-items, more than one dispatch dimension holds.  The batched launch
+    splits its grid into rows; sampled instances equal their single-context
+    renders bit for bit and their gradients as the other batch tests
+    require.  (A one-dimensional grid ran only part of the tiles.)"""
+    from paper_1910_05200_amd import facert
+    n, nl, spp = 25, 42, 64
+    model = synth.make_model(6, 6, seed=21)
+    scene = synth.make_scene(256, 256)
+    scene.light_geom = synth.light_stage(nl)
+    params = [synth.make_params(300 + i, n_lights=nl) for i in range(n)]
+    rs = [facert.Renderer(model, scene) for _ in range(n)]
+    ps = [facert.params_to_device(p) for p in params]
+    batch = facert.Batch(rs)
+    assert 256 * 256 * spp == facert.FR_CHUNK_MAX
+    tiles = n * (256 * 256 * spp // 256) * nl
+    assert tiles * 256 > 2 ** 32
+    seeds = [7000 + i for i in range(n)]
+    imgs = batch.render(ps, seeds, [spp] * n)
+    rng = np.random.default_rng(8)
+    dls = [torch.from_numpy(rng.normal(size=(256, 256, 3)).astype(np.float32)).cuda() for _ in range(n)]
+    gb = batch.backward(dls)
+    torch.cuda.synchronize()
+    imgs = [x.cpu().numpy() for x in imgs]
+    gb = [_np(g) for g in gb]
+    batch.close()
+    for i in (0, 12, n - 1):
+        ref = rs[i].render(ps[i], seeds[i], spp).cpu().numpy()
+        assert (ref.sum(-1) > 0).mean() > 0.05
+        assert np.array_equal(imgs[i], ref), f"instance {i}: max diff {np.abs(imgs[i] - ref).max()}"
+        _assert_grads_close(gb[i], _np(rs[i].backward(dls[i])), f"instance {i}")
+    for r in rs:
+        r.close()
+
+
 def test_batch_errors(torch):
     from paper_1910_05200_amd import facert
     inst = _small()

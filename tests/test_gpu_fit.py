@@ -125,3 +125,34 @@ def test_sequence_fit_runs_every_mode(torch):
     b = sequence.run(r, targets, base, frames, start, start_frames, 6, "plain", 4, dn, eval_spp=16, log_every=6)
     assert a["batched"] and not b["batched"]
     assert abs(a["log"][-1]["psnr_db"] - b["log"][-1]["psnr_db"]) < 0.05, (a["log"][-1], b["log"][-1])
+
+
+def test_sequence_fit_resumes_from_a_checkpoint(torch, tmp_path):
+    """A fit stopped after its first iteration, written to a checkpoint file
+    and resumed, ends where the uninterrupted fit ends (up to the atomics
+    order of the adjoint's light and texel sums)."""
+    from paper_1910_05200_amd import facert, sequence
+    model, scene, _, _ = synth.workload("tiny")
+    r = facert.Renderer(model, scene)
+    base, frames = sequence.make_truth(2)
+    start, start_frames = sequence.make_start(base, frames, seed=7)
+    targets = [r.render(facert.params_to_device(sequence.frame_params_np(base, b, p)), 7 + f, 64).clone()
+               for f, (b, p) in enumerate(frames)]
+    rs = sequence.frame_renderers(model, scene, 2)
+    whole = sequence.run(r, targets, base, frames, start, start_frames, 6, "plain", 4, eval_spp=16, log_every=3,
+                         rs=rs, seed=3)
+    part = sequence.run(r, targets, base, frames, start, start_frames, 6, "plain", 4, eval_spp=16, log_every=3,
+                        rs=rs, seed=3, stop_after_s=0.0)
+    assert part["iters_done"] == 1 and "state" in part
+    path = tmp_path / "seq.npz"
+    np.savez(path, **part["state"])
+    with np.load(path, allow_pickle=False) as z:
+        st = {k: z[k] for k in z.files}
+    rest = sequence.run(r, targets, base, frames, start, start_frames, 6, "plain", 4, eval_spp=16, log_every=3,
+                        rs=rs, seed=3, state=st)
+    assert rest["iters_done"] == 6 and "state" not in rest
+    assert [e["iter"] for e in rest["log"]] == [0, 3, 6]
+    assert abs(rest["log"][-1]["psnr_db"] - whole["log"][-1]["psnr_db"]) < 0.05, (rest["log"][-1], whole["log"][-1])
+    for k in ("alpha", "delta", "lights", "spec", "beta", "rot_deg", "trans_mm"):
+        a, b = rest["log"][-1]["errors"][k], whole["log"][-1]["errors"][k]
+        assert abs(a - b) <= 2e-3 * max(abs(b), 1e-3), (k, a, b)
