@@ -23,9 +23,15 @@
  *     On failure the context stays usable and fr_last_error() describes it.
  *   - memory: the context owns its own device buffers (model copies, BVH,
  *     edge tables, scratch).  Every array argument is owned by the caller.
- *     Array arguments of fr_blend/fr_render/fr_backward are DEVICE pointers
- *     (HIP global memory) read or written on the context's stream, except
- *     where a comment says "host".  fr_create copies its host arrays.
+ *     fr_create copies its host arrays.  The array arguments of the compute
+ *     calls (fr_blend, fr_render, fr_backward, fr_loss_l2, fr_aov,
+ *     fr_light_reg, fr_adam) are, except where a comment says "host":
+ *       with FR_DEVICE_PTRS given to fr_create, DEVICE pointers (HIP global
+ *       memory) read or written on the context's stream (the PyTorch path);
+ *       without it, HOST pointers: the call copies its inputs to device
+ *       buffers of the context, runs on the context's stream, copies its
+ *       outputs back and waits for the stream before it returns.
+ *     Comments below say "device" for the first mode.
  *   - streams: all work is enqueued on the stream set with fr_set_stream
  *     (default: the null stream; fr_backward forks part of its work onto
  *     a second stream of the context's own and joins it back) and the calls
@@ -84,7 +90,8 @@ typedef struct {
     int32_t spec_res;                /* specular texture side (32)             */
 } fr_scene_desc;
 
-/* Parameters of one evaluation.  Device pointers except pose. */
+/* Parameters of one evaluation.  Arrays in the context's mode (device with
+ * FR_DEVICE_PTRS, else host), except pose, which is always host. */
 typedef struct {
     const float *alpha;              /* [n_id]                                 */
     const float *beta;               /* [n_exp]                                */
@@ -95,7 +102,7 @@ typedef struct {
     const float *spec;               /* [spec_res^2] gray specular texels      */
 } fr_params;
 
-/* Gradient outputs (device pointers, each nullable; overwritten). */
+/* Gradient outputs (in the context's mode; each nullable; overwritten). */
 typedef struct {
     float *d_lights;                 /* [N][3]                                 */
     float *d_spec;                   /* [spec_res^2]                           */
@@ -124,6 +131,9 @@ typedef struct {
 } fr_stats_t;
 
 #define FR_TIMING 1u                 /* fr_create flag: time phases with events */
+#define FR_DEVICE_PTRS 4u            /* fr_create flag: the compute calls take
+                                        device pointers (see the conventions
+                                        above); without it, host pointers     */
 #define FR_REFIT  2u                 /* fr_create flag: build the BVH's shape
                                         once, over the model's mean shape, and
                                         only refit its boxes per evaluation,
@@ -139,8 +149,8 @@ typedef struct {
 
 /* Create a context: copies the model and scene to the device, builds the
  * topology (edges, vertex-to-face lists, and the BVH shape when FR_REFIT is
- * given).  flags: FR_TIMING, FR_REFIT.
- * Errors: FR_EINVAL (sizes <= 0, null arrays, non-manifold mesh, index out
+ * given).  flags: FR_TIMING, FR_REFIT, FR_DEVICE_PTRS.
+ * Errors: FR_EINVAL (sizes <= 0, null arrays, unknown flags, non-manifold mesh, index out
  * of range, n_lights > 64, more than 2^21 edges), FR_ENOMEM, FR_EDEVICE.
  * *out is NULL on error. */
 int fr_create(const fr_model_desc *model, const fr_scene_desc *scene,
@@ -199,7 +209,8 @@ int fr_loss_l2(fr_ctx *ctx, const float *image, const float *target,
 /* fr_loss_l2 for callers that cannot allocate device memory: code being
  * captured into a HIP graph, tight serving or fitting loops, harnesses that
  * forbid hipMalloc.  Needs no context: n elements (1 .. FR_LOSS_NOALLOC_MAX)
- * of image and target (device), dL_dimage = 2 (image - target) and
+ * of image and target (device pointers always: the call has no context),
+ * dL_dimage = 2 (image - target) and
  * *loss_dev = sum (image - target)^2 (either output may be NULL), enqueued
  * on hip_stream (a hipStream_t; NULL: the null stream) of the current
  * device.  The same kernels as fr_loss_l2, with their fp64 block partial
@@ -242,7 +253,7 @@ int fr_adam(fr_ctx *ctx, float *param, const float *grad, float *m, float *v, in
             float lr, float beta1, float beta2, float eps);
 
 /* Counters and phase times of the last render/backward (synchronises). */
-int fr_stats(fr_ctx *ctx, fr_stats_t *out);
+int fr_stats(const fr_ctx *ctx, fr_stats_t *out);
 
 /* Message of the last error on this context ("" if none); valid until the
  * next call on the context.  With NULL: the message of this thread's last
@@ -286,7 +297,8 @@ typedef struct {
                                         512; 0 for the others                  */
 } fr_launch;
 
-/* n contexts (1..4096, distinct, created without FR_REFIT).  flags:
+/* n contexts (1..4096, distinct, created with FR_DEVICE_PTRS and without
+ * FR_REFIT; batched calls take device pointers only).  flags:
  * FR_TIMING (per-kind times, needed by fr_batch_timing / fr_batch_tune).
  * Errors: FR_EINVAL, FR_ENOMEM.  *out is NULL on error. */
 int fr_batch_create(int32_t n, fr_ctx *const *ctx, uint32_t flags, fr_batch **out);

@@ -2065,6 +2065,9 @@ struct fr_ctx {
     hipEvent_t fork_ev = nullptr, join_ev = nullptr;
     uint32_t flags = 0, terms = FR_TERM_INTERIOR | FR_TERM_PRIMARY | FR_TERM_SECONDARY;
     int device = 0;
+    // host-pointer mode (no FR_DEVICE_PTRS): device copies of a call's arrays,
+    // and of the last render's parameter arrays (fr_backward reads them)
+    std::vector<std::pair<void *, size_t>> io_buf, par_buf;
     // sizes
     int V = 0, F = 0, E = 0, n_id = 0, n_exp = 0, n_alb = 0;
     int W = 0, H = 0, nl = 0, res = 0, n_nodes = 0;
@@ -2423,12 +2426,81 @@ static void camera_pass(fr_ctx *c, const Scene &S, uint64_t seed, int spp, long 
     hipLaunchKernelGGL(k_cam_resolve, dim3(nblk(n, 256)), dim3(256), 0, c->stream, S, n, c->hits, c->vis, ctr);
 }
 
+// ------------------------------------------------ host-pointer mode ----
+// A context created without FR_DEVICE_PTRS takes host arrays.  A call copies
+// its input arrays into device buffers that the context keeps (one per
+// argument position, grown as needed), runs exactly as in device mode on
+// the context's stream, copies its output arrays back and waits for the
+// stream.  fr_render's parameter arrays keep buffers of their own until the
+// next render, since fr_backward reads the lights and texels of the last
+// render.  Every call ends with the stream idle, so a buffer is never in use
+// when a later call grows it.
+struct HostCall {
+    fr_ctx *c;
+    std::vector<std::pair<void *, size_t>> &bufs;
+    size_t slot = 0;
+    int err = FR_OK;
+    struct Back { void *host; const void *dev; size_t bytes; };
+    std::vector<Back> back;
+    HostCall(fr_ctx *c_, std::vector<std::pair<void *, size_t>> &b) : c(c_), bufs(b) {}
+    void *buffer(size_t bytes) {
+        if (err) return nullptr;
+        if (slot == bufs.size()) bufs.push_back({nullptr, 0});
+        auto &b = bufs[slot++];
+        if (b.second < bytes) {
+            if (b.first) (void)hipFree(b.first);
+            b.first = nullptr; b.second = 0;
+            const size_t cap = std::max(bytes, (size_t)256);
+            const hipError_t e = hipMalloc(&b.first, cap);
+            if (e != hipSuccess) {
+                err = fail(c, e == hipErrorOutOfMemory ? FR_ENOMEM : FR_EDEVICE, "staging %zu bytes: %s", cap,
+                           hipGetErrorString(e));
+                return nullptr;
+            }
+            b.second = cap;
+        }
+        return b.first;
+    }
+    template <class T> T *in(const T *h, size_t n) {
+        if (!h) return nullptr;
+        T *d = (T *)buffer(n * sizeof(T));
+        if (d && n) {
+            const hipError_t e = hipMemcpyAsync(d, h, n * sizeof(T), hipMemcpyHostToDevice, c->stream);
+            if (e != hipSuccess) { err = fail(c, FR_EDEVICE, "staging copy: %s", hipGetErrorString(e)); return nullptr; }
+        }
+        return d;
+    }
+    template <class T> T *out(T *h, size_t n) {
+        if (!h) return nullptr;
+        T *d = (T *)buffer(n * sizeof(T));
+        if (d) back.push_back({h, d, n * sizeof(T)});
+        return d;
+    }
+    template <class T> T *inout(T *h, size_t n) {
+        T *d = in(h, n);
+        if (d) back.push_back({h, d, n * sizeof(T)});
+        return d;
+    }
+    // after the call: its outputs back to the host (on success), stream idle
+    int finish(int r) {
+        if (r == FR_OK)
+            for (const Back &b : back) {
+                const hipError_t e = hipMemcpyAsync(b.host, b.dev, b.bytes, hipMemcpyDeviceToHost, c->stream);
+                if (e != hipSuccess) { r = fail(c, FR_EDEVICE, "copy back: %s", hipGetErrorString(e)); break; }
+            }
+        const hipError_t e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess && r == FR_OK) r = fail(c, FR_EDEVICE, "hipStreamSynchronize: %s", hipGetErrorString(e));
+        return r;
+    }
+};
+static inline bool device_ptrs(const fr_ctx *c) { return (c->flags & FR_DEVICE_PTRS) != 0; }
+
 extern "C" {
 
 int fr_create(const fr_model_desc *m, const fr_scene_desc *s, uint32_t flags, fr_ctx **out) {
     if (!out) return FR_EINVAL;
     *out = nullptr;
-    if (!m || !s) return FR_EINVAL;
+    if (!m || !s || (flags & ~(FR_TIMING | FR_REFIT | FR_DEVICE_PTRS))) return FR_EINVAL;
     if (m->n_vertices <= 0 || m->n_faces <= 0 || m->n_id < 0 || m->n_exp < 0 || m->n_alb < 0 ||
         !m->faces || !m->mean || !m->alb_mean || !m->uv || (m->n_id && !m->b_id) || (m->n_exp && !m->b_exp) ||
         (m->n_alb && !m->b_alb) || s->width <= 0 || s->height <= 0 || s->n_lights < 1 ||
@@ -2598,8 +2670,8 @@ static int blend_impl(fr_ctx *c, const float *alpha, const float *beta, const fl
     return FR_OK;
 }
 
-int fr_blend(fr_ctx *c, const float *alpha, const float *beta, const float *delta,
-             const float *pose, float *out_vertices, float *out_albedo) {
+static int blend_call(fr_ctx *c, const float *alpha, const float *beta, const float *delta,
+                      const float *pose, float *out_vertices, float *out_albedo) {
     if (!c) return FR_EINVAL;
     c->err.clear();
     if ((c->n_id && !alpha) || (c->n_exp && !beta) || (c->n_alb && !delta) || !pose)
@@ -2617,7 +2689,7 @@ static void ev_record(fr_ctx *c, int i) {
     if (c->flags & FR_TIMING) (void)hipEventRecord(c->ev[i], c->stream);
 }
 
-int fr_render(fr_ctx *c, const fr_params *p, uint64_t seed, int32_t spp, float *out) {
+static int render_call(fr_ctx *c, const fr_params *p, uint64_t seed, int32_t spp, float *out) {
     if (!c) return FR_EINVAL;
     c->err.clear();
     if (!p || !out || !p->lights || !p->spec || !p->pose || (c->n_id && !p->alpha) || (c->n_exp && !p->beta) ||
@@ -2753,7 +2825,7 @@ static void primary_pass(fr_ctx *c, const Scene &S, const float *dLdI, hipStream
     if (c->flags & FR_TIMING) (void)hipEventRecord(c->ev[9 + 2 * kKernPrimary], st);
 }
 
-int fr_backward(fr_ctx *c, const float *dLdI, const fr_grads *g) {
+static int backward_call(fr_ctx *c, const float *dLdI, const fr_grads *g) {
     if (!c) return FR_EINVAL;
     c->err.clear();
     if (!c->have_render) return fail(c, FR_ESTATE, "fr_backward: no prior fr_render");
@@ -2830,7 +2902,7 @@ int fr_backward(fr_ctx *c, const float *dLdI, const fr_grads *g) {
     return FR_OK;
 }
 
-int fr_aov(fr_ctx *c, float *out) {
+static int aov_call(fr_ctx *c, float *out) {
     if (!c) return FR_EINVAL;
     c->err.clear();
     if (!out) return fail(c, FR_EINVAL, "fr_aov: null output");
@@ -2843,7 +2915,7 @@ int fr_aov(fr_ctx *c, float *out) {
     return FR_OK;
 }
 
-int fr_light_reg(fr_ctx *c, const float *lights, float w2, float *grad_lights, float *loss) {
+static int light_reg_call(fr_ctx *c, const float *lights, float w2, float *grad_lights, float *loss) {
     if (!c) return FR_EINVAL;
     c->err.clear();
     if (!lights) return fail(c, FR_EINVAL, "fr_light_reg: null lights");
@@ -2853,8 +2925,8 @@ int fr_light_reg(fr_ctx *c, const float *lights, float w2, float *grad_lights, f
     return FR_OK;
 }
 
-int fr_adam(fr_ctx *c, float *param, const float *grad, float *m, float *v, int32_t n, int32_t step,
-            float lr, float beta1, float beta2, float eps) {
+static int adam_call(fr_ctx *c, float *param, const float *grad, float *m, float *v, int32_t n, int32_t step,
+                     float lr, float beta1, float beta2, float eps) {
     if (!c) return FR_EINVAL;
     c->err.clear();
     if (n < 0 || (n > 0 && (!param || !grad || !m || !v)))
@@ -2871,7 +2943,7 @@ int fr_adam(fr_ctx *c, float *param, const float *grad, float *m, float *v, int3
     return FR_OK;
 }
 
-int fr_loss_l2(fr_ctx *c, const float *img, const float *tgt, float *dL, float *loss) {
+static int loss_l2_call(fr_ctx *c, const float *img, const float *tgt, float *dL, float *loss) {
     if (!c) return FR_EINVAL;
     c->err.clear();
     if (!img || !tgt) return fail(c, FR_EINVAL, "fr_loss_l2: null argument");
@@ -2883,8 +2955,98 @@ int fr_loss_l2(fr_ctx *c, const float *img, const float *tgt, float *dL, float *
     return FR_OK;
 }
 
-int fr_stats(fr_ctx *c, fr_stats_t *out) {
-    if (!c || !out) return FR_EINVAL;
+
+int fr_blend(fr_ctx *c, const float *alpha, const float *beta, const float *delta, const float *pose,
+             float *out_vertices, float *out_albedo) {
+    if (!c) return FR_EINVAL;
+    if (device_ptrs(c)) return blend_call(c, alpha, beta, delta, pose, out_vertices, out_albedo);
+    c->err.clear();
+    HostCall h(c, c->io_buf);
+    const size_t V3 = 3 * (size_t)c->V;
+    const float *a = h.in(alpha, c->n_id), *b = h.in(beta, c->n_exp), *d = h.in(delta, c->n_alb);
+    float *ov = h.out(out_vertices, V3), *oa = h.out(out_albedo, V3);
+    if (h.err) return h.finish(h.err);
+    return h.finish(blend_call(c, a, b, d, pose, ov, oa));
+}
+
+int fr_render(fr_ctx *c, const fr_params *p, uint64_t seed, int32_t spp, float *out) {
+    if (!c) return FR_EINVAL;
+    if (device_ptrs(c) || !p) return render_call(c, p, seed, spp, out);
+    c->err.clear();
+    HostCall hp(c, c->par_buf), h(c, c->io_buf);
+    fr_params q = *p;
+    q.alpha = hp.in(p->alpha, c->n_id); q.beta = hp.in(p->beta, c->n_exp); q.delta = hp.in(p->delta, c->n_alb);
+    q.lights = hp.in(p->lights, 3 * (size_t)c->nl); q.spec = hp.in(p->spec, (size_t)c->res * c->res);
+    float *o = h.out(out, (size_t)c->W * c->H * 3);
+    if (hp.err || h.err) return h.finish(hp.err ? hp.err : h.err);
+    return h.finish(render_call(c, &q, seed, spp, o));
+}
+
+int fr_backward(fr_ctx *c, const float *dLdI, const fr_grads *g) {
+    if (!c) return FR_EINVAL;
+    if (device_ptrs(c) || !g) return backward_call(c, dLdI, g);
+    c->err.clear();
+    HostCall h(c, c->io_buf);
+    const size_t V3 = 3 * (size_t)c->V;
+    const float *dl = h.in(dLdI, (size_t)c->W * c->H * 3);
+    fr_grads q;
+    q.d_lights = h.out(g->d_lights, 3 * (size_t)c->nl); q.d_spec = h.out(g->d_spec, (size_t)c->res * c->res);
+    q.d_vertices = h.out(g->d_vertices, V3); q.d_albedo = h.out(g->d_albedo, V3);
+    q.d_alpha = h.out(g->d_alpha, c->n_id); q.d_beta = h.out(g->d_beta, c->n_exp);
+    q.d_delta = h.out(g->d_delta, c->n_alb); q.d_pose = h.out(g->d_pose, 6);
+    if (h.err) return h.finish(h.err);
+    return h.finish(backward_call(c, dl, &q));
+}
+
+int fr_aov(fr_ctx *c, float *out) {
+    if (!c) return FR_EINVAL;
+    if (device_ptrs(c)) return aov_call(c, out);
+    c->err.clear();
+    HostCall h(c, c->io_buf);
+    float *o = h.out(out, (size_t)c->W * c->H * 7);
+    if (h.err) return h.finish(h.err);
+    return h.finish(aov_call(c, o));
+}
+
+int fr_light_reg(fr_ctx *c, const float *lights, float w2, float *grad_lights, float *loss) {
+    if (!c) return FR_EINVAL;
+    if (device_ptrs(c)) return light_reg_call(c, lights, w2, grad_lights, loss);
+    c->err.clear();
+    HostCall h(c, c->io_buf);
+    const size_t n3 = 3 * (size_t)c->nl;
+    const float *l = h.in(lights, n3);
+    float *g = h.inout(grad_lights, n3), *ls = h.out(loss, 1);
+    if (h.err) return h.finish(h.err);
+    return h.finish(light_reg_call(c, l, w2, g, ls));
+}
+
+int fr_adam(fr_ctx *c, float *param, const float *grad, float *m, float *v, int32_t n, int32_t step, float lr,
+            float beta1, float beta2, float eps) {
+    if (!c) return FR_EINVAL;
+    if (device_ptrs(c) || n < 0) return adam_call(c, param, grad, m, v, n, step, lr, beta1, beta2, eps);
+    c->err.clear();
+    HostCall h(c, c->io_buf);
+    float *pp = h.inout(param, (size_t)n), *mm = h.inout(m, (size_t)n), *vv = h.inout(v, (size_t)n);
+    const float *gg = h.in(grad, (size_t)n);
+    if (h.err) return h.finish(h.err);
+    return h.finish(adam_call(c, pp, gg, mm, vv, n, step, lr, beta1, beta2, eps));
+}
+
+int fr_loss_l2(fr_ctx *c, const float *img, const float *tgt, float *dL, float *loss) {
+    if (!c) return FR_EINVAL;
+    if (device_ptrs(c)) return loss_l2_call(c, img, tgt, dL, loss);
+    c->err.clear();
+    HostCall h(c, c->io_buf);
+    const size_t n = (size_t)c->W * c->H * 3;
+    const float *a = h.in(img, n), *b = h.in(tgt, n);
+    float *g = h.out(dL, n), *ls = h.out(loss, 1);
+    if (h.err) return h.finish(h.err);
+    return h.finish(loss_l2_call(c, a, b, g, ls));
+}
+
+int fr_stats(const fr_ctx *cc, fr_stats_t *out) {
+    if (!cc || !out) return FR_EINVAL;
+    fr_ctx *c = const_cast<fr_ctx *>(cc);   // only its error message is written
     HIPCK(c, hipStreamSynchronize(c->stream));
     std::vector<unsigned long long> all((size_t)kCtrPerKern * kNumKern);
     HIPCK(c, hipMemcpy(all.data(), c->ctr, all.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost));
@@ -2990,6 +3152,8 @@ void fr_destroy(fr_ctx *c) {
                     c->pe_f, c->pe_vis, c->pv_queue, c->pv_aux, c->pv_perm, c->lb.key[0], c->lb.key[1], c->lb.val[0], c->lb.val[1], c->lb.hist,
                     c->lb.bounds, c->lb.child, c->lb.parent, c->lb.first, c->lb.last, c->lb.pre, c->lb.arrive, c->lb.box, c->lb.roots, c->lb.n_roots, c->lb.top_idx, c->lb.n_top};
     for (void *p : ptrs) if (p) (void)hipFree(p);
+    for (auto &b : c->io_buf) if (b.first) (void)hipFree(b.first);
+    for (auto &b : c->par_buf) if (b.first) (void)hipFree(b.first);
     for (auto &e : c->ev) if (e) (void)hipEventDestroy(e);
     if (c->side) { (void)hipStreamSynchronize(c->side); (void)hipStreamDestroy(c->side); }
     if (c->fork_ev) (void)hipEventDestroy(c->fork_ev);

@@ -627,7 +627,7 @@ int fr_batch_create(int32_t n, fr_ctx *const *ctx, uint32_t flags, fr_batch **ou
     *out = nullptr;
     if (n < 1 || n > 4096 || !ctx || (flags & ~FR_TIMING)) return FR_EINVAL;
     for (int i = 0; i < n; ++i) {
-        if (!ctx[i] || (ctx[i]->flags & FR_REFIT)) return FR_EINVAL;
+        if (!ctx[i] || (ctx[i]->flags & FR_REFIT) || !(ctx[i]->flags & FR_DEVICE_PTRS)) return FR_EINVAL;
         for (int k = 0; k < i; ++k)
             if (ctx[k] == ctx[i]) return FR_EINVAL;
     }

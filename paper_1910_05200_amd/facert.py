@@ -23,6 +23,7 @@ LIB_PATH = os.path.join(HERE, "libfacert.so")
 
 FR_TIMING = 1
 FR_REFIT = 2
+FR_DEVICE_PTRS = 4
 FR_CHUNK_MAX = 1 << 22
 FR_TERM_INTERIOR, FR_TERM_PRIMARY, FR_TERM_SECONDARY = 1, 2, 4
 STATUS = {0: "FR_OK", -1: "FR_EINVAL", -2: "FR_ENOMEM", -3: "FR_EDEVICE", -4: "FR_ESTATE"}
@@ -173,9 +174,10 @@ class Renderer:
     ``pose`` (6 floats, host).
     """
 
-    def __init__(self, model, scene, timing: bool = False, refit: bool = False):
+    def __init__(self, model, scene, timing: bool = False, refit: bool = False, host_ptrs: bool = False):
         import torch
         self.torch = torch
+        self.host = host_ptrs
         L = load()
         self._keep = {k: np.ascontiguousarray(getattr(model, k)) for k in
                       ("faces", "mean", "b_id", "b_exp", "alb_mean", "b_alb", "uv")}
@@ -190,7 +192,7 @@ class Renderer:
         sd = fr_scene_desc(scene.width, scene.height, (C.c_float * 3)(*[float(x) for x in scene.cam]),
                            float(scene.pix_scale), self._lg.shape[0], self._lg.ctypes.data, scene.spec_res)
         ctx = C.c_void_p()
-        flags = (FR_TIMING if timing else 0) | (FR_REFIT if refit else 0)
+        flags = (FR_TIMING if timing else 0) | (FR_REFIT if refit else 0) | (0 if host_ptrs else FR_DEVICE_PTRS)
         code = L.fr_create(C.byref(md), C.byref(sd), flags, C.byref(ctx))
         if code != 0:
             raise FrError(code, "fr_create failed")
@@ -225,22 +227,28 @@ class Renderer:
     def set_chunk(self, samples: int):
         _check(self.ctx, load().fr_set_chunk(self.ctx, samples))
 
-    # -- calls
+    def _empty(self, shape, like=None):
+        """An output array: numpy in host-pointer mode, else a float32 tensor
+        on like's device (the current HIP device without like)."""
+        if self.host:
+            return np.empty(shape, np.float32)
+        dev = like.device if like is not None else "cuda"
+        return self.torch.empty(shape, device=dev, dtype=self.torch.float32)
+
+    # -- calls (host-pointer mode: numpy arrays in and out, each call waits)
     def blend(self, alpha, beta, delta, pose):
-        t = self.torch
         self._stream()
-        v = t.empty((3, self.V), device=alpha.device, dtype=t.float32)
-        a = t.empty((3, self.V), device=alpha.device, dtype=t.float32)
+        v = self._empty((3, self.V), alpha)
+        a = self._empty((3, self.V), alpha)
         pose_h = np.ascontiguousarray(np.asarray(pose, np.float32).reshape(6))
         _check(self.ctx, load().fr_blend(self.ctx, _ptr(alpha), _ptr(beta), _ptr(delta),
                                          pose_h.ctypes.data, _ptr(v), _ptr(a)))
         return v, a
 
     def render(self, p: dict, seed: int, spp: int, out=None):
-        t = self.torch
         self._stream()
         if out is None:
-            out = t.empty((self.H, self.W, 3), device=p["lights"].device, dtype=t.float32)
+            out = self._empty((self.H, self.W, 3), p["lights"])
         pose_h = np.ascontiguousarray(np.asarray(p["pose"], np.float32).reshape(6))
         fp = fr_params(_ptr(p["alpha"]), _ptr(p["beta"]), _ptr(p["delta"]), pose_h.ctypes.data,
                        _ptr(p["lights"]), _ptr(p["spec"]))
@@ -251,49 +259,51 @@ class Renderer:
 
     def backward(self, dL_dimage, want=("d_lights", "d_spec", "d_vertices", "d_albedo",
                                          "d_alpha", "d_beta", "d_delta", "d_pose")):
-        t = self.torch
         self._stream()
-        dev = dL_dimage.device
         shapes = {"d_lights": (self.n_lights, 3), "d_spec": (self.spec_res ** 2,),
                   "d_vertices": (3, self.V), "d_albedo": (3, self.V), "d_alpha": (self.n_id,),
                   "d_beta": (self.n_exp,), "d_delta": (self.n_alb,), "d_pose": (6,)}
-        out = {k: t.empty(shapes[k], device=dev, dtype=t.float32) for k in want}
+        out = {k: self._empty(shapes[k], dL_dimage) for k in want}
         g = fr_grads(*[_ptr(out.get(k)) for k, _ in fr_grads._fields_])
-        _check(self.ctx, load().fr_backward(self.ctx, _ptr(dL_dimage.contiguous()), C.byref(g)))
+        dl = np.ascontiguousarray(dL_dimage, np.float32) if self.host else dL_dimage.contiguous()
+        _check(self.ctx, load().fr_backward(self.ctx, _ptr(dl), C.byref(g)))
         return out
 
     def loss_l2(self, image, target):
-        t = self.torch
         self._stream()
-        dL = t.empty_like(image)
-        loss = t.empty((), device=image.device, dtype=t.float32)
+        dL = self._empty(tuple(image.shape), image)
+        loss = self._empty((), image)
         _check(self.ctx, load().fr_loss_l2(self.ctx, _ptr(image), _ptr(target), _ptr(dL), _ptr(loss)))
         return dL, loss
 
     def aov(self, out=None):
         """Albedo, shading normal and depth of the last render, [H][W][7]."""
-        t = self.torch
         self._stream()
         if out is None:
-            out = t.empty((self.H, self.W, 7), device="cuda", dtype=t.float32)
+            out = self._empty((self.H, self.W, 7))
         _check(self.ctx, load().fr_aov(self.ctx, _ptr(out)))
         return out
 
     def light_reg(self, lights, w2: float, grad=None):
         """w2 E_light (device scalar); adds its gradient to grad when given."""
-        t = self.torch
         self._stream()
-        loss = t.empty((), device=lights.device, dtype=t.float32)
+        loss = self._empty((), lights)
         _check(self.ctx, load().fr_light_reg(self.ctx, _ptr(lights), float(w2), _ptr(grad), _ptr(loss)))
         return loss
 
     def adam(self, param, grad, m, v, step: int, lr: float, beta1=0.9, beta2=0.999, eps=1e-8):
-        """One in-place Adam step on float32 device tensors of equal size."""
+        """One in-place Adam step on contiguous float32 arrays of equal size
+        (device tensors, or numpy arrays in host-pointer mode)."""
         self._stream()
-        n = param.numel()
-        for x in (grad, m, v):
-            assert x.numel() == n and x.is_contiguous() and x.dtype == param.dtype
-        assert param.is_contiguous()
+        if self.host:
+            n = param.size
+            for x in (param, grad, m, v):
+                assert x.size == n and x.flags.c_contiguous and x.dtype == np.float32
+        else:
+            n = param.numel()
+            for x in (grad, m, v):
+                assert x.numel() == n and x.is_contiguous() and x.dtype == param.dtype
+            assert param.is_contiguous()
         _check(self.ctx, load().fr_adam(self.ctx, _ptr(param), _ptr(grad), _ptr(m), _ptr(v), n, step,
                                         float(lr), float(beta1), float(beta2), float(eps)))
 

@@ -3,6 +3,7 @@ import ctypes as C
 import os
 import re
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -56,6 +57,29 @@ def test_null_context_and_argument_errors_without_gpu():
     md = facert.fr_model_desc()
     sd = facert.fr_scene_desc()
     assert lib.fr_create(C.byref(md), C.byref(sd), 0, C.byref(out)) == -1
+
+
+def test_create_rejects_unknown_flags_without_gpu():
+    """A valid model and scene with a flag bit the header does not define:
+    FR_EINVAL before any device call.  The binding's flag values are the
+    header's."""
+    from paper_1910_05200_amd import facert, synth
+    hdr = open(os.path.join(ROOT, "include", "facert.h")).read()
+    for name in ("FR_TIMING", "FR_REFIT", "FR_DEVICE_PTRS"):
+        m = re.search(r"#define %s\s+(\d+)u" % name, hdr)
+        assert m and int(m.group(1)) == getattr(facert, name), name
+    lib = facert.load()
+    model, scene = synth.make_model(4, 4), synth.make_scene(8, 8)
+    k = {n: np.ascontiguousarray(getattr(model, n), np.float32) for n in ("mean", "b_id", "b_exp", "alb_mean", "b_alb", "uv")}
+    faces = np.ascontiguousarray(model.faces, np.int32)
+    lg = np.ascontiguousarray(scene.light_geom, np.float32)
+    md = facert.fr_model_desc(model.n_vertices, model.n_faces, k["b_id"].shape[0], k["b_exp"].shape[0], k["b_alb"].shape[0],
+                              faces.ctypes.data, *(k[n].ctypes.data for n in ("mean", "b_id", "b_exp", "alb_mean", "b_alb", "uv")))
+    sd = facert.fr_scene_desc(scene.width, scene.height, (C.c_float * 3)(*[float(x) for x in scene.cam]),
+                              float(scene.pix_scale), lg.shape[0], lg.ctypes.data, scene.spec_res)
+    out = C.c_void_p()
+    for bad in (8, 1 << 31, facert.FR_DEVICE_PTRS | 16):
+        assert lib.fr_create(C.byref(md), C.byref(sd), bad, C.byref(out)) == -1 and not out.value
 
 
 def test_batch_argument_errors_without_gpu():
