@@ -42,6 +42,16 @@ typedef struct fd_net fd_net;
  * FD_ENOMEM, FD_EDEVICE. */
 int fd_create(int32_t height, int32_t width, fd_net **out);
 
+/* The same for n images per call (n >= 1; for n > 1, H a multiple of 64;
+ * n*H*W at most 22,369,621 pixels).  Every array argument of fd_forward,
+ * fd_train_step and fd_backward_input then holds n images, [n][H][W][c],
+ * and one call runs them all: each kernel launch covers every image, which
+ * fills the chip where a single image's deep layers cannot.  Results per
+ * image equal those of a one-image network; the training loss is the mean
+ * over all n images' pixels.  fd_create(H, W) is fd_create_batch(H, W, 1).
+ * Device memory grows with n (about 0.7 GB per 512 x 512 image). */
+int fd_create_batch(int32_t height, int32_t width, int32_t n, fd_net **out);
+
 /* Enqueue all later work on this HIP stream (hipStream_t). */
 int fd_set_stream(fd_net *net, void *hip_stream);
 

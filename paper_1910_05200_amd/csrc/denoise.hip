@@ -1,7 +1,12 @@
 // fadenoise: U-Net denoiser for low-spp renders on MI355X (gfx950).
 //
 // Layout: activations NHWC bfloat16 [H*W][C] (bf16 stored as its 16 high
-// bits), weights [Cout][9][Cin].  Every 3x3 convolution is an implicit GEMM
+// bits), weights [Cout][9][Cin].  A network made for n images keeps them
+// stacked as one image n*H rows tall: the pooling, upsampling and
+// elementwise kernels run over the stack unchanged (every level's image
+// height is even, so no 2x2 window crosses two images), and the 3x3
+// convolutions take the rows per image and read zeros across an image's
+// top and bottom edges as they do outside the stack.  Every 3x3 convolution is an implicit GEMM
 // (rows = pixels, columns = output channels, reduction = 9 taps x input
 // channels) on gfx950's v_mfma_f32_32x32x16_bf16 with fp32 accumulation; a
 // block owns an 8 x 16-pixel tile and 32 or 64 output channels, and stages
@@ -37,6 +42,9 @@ constexpr float kSlope = 0.01f;    // leaky ReLU
 // Radiance enters as log(1 + kExposure x): the light stage's pixel values
 // are a few hundredths, and this brings them to order one.
 constexpr float kExposure = 16.0f;
+// pixels of all images of one network: every index of its largest tensor
+// (96 channels at full size) stays below 2^31
+constexpr long long kMaxBatchPixels = ((1ll << 31) - 1) / 96;
 
 // ------------------------------------------------------------ conv 3x3 --
 // Y[p][co] = act(bias[co] + sum_{t, ci} W[co][t][ci] X[nbr(p, t)][ci]), zero
@@ -71,8 +79,11 @@ constexpr int kPR = 8, kPC = 16;                  // pixel tile: 8 rows x 16 col
 constexpr int kHR = kPR + 2, kHC = kPC + 2;       // with the one-pixel halo
 constexpr int kLPad = 8;                          // bf16 of padding per LDS row
 
+// H is the stack's height and Himg the rows of one image (H for a single
+// image); when images are stacked, Himg is a multiple of the tile's rows, so
+// a tile never spans two images.
 template <class TX, class TY, int NT, int KC>
-__global__ __launch_bounds__(256) void k_conv3x3(int H, int W, int Cin, int Cout, const TX *__restrict__ X,
+__global__ __launch_bounds__(256) void k_conv3x3(int H, int Himg, int W, int Cin, int Cout, const TX *__restrict__ X,
         const bf16 *__restrict__ Wt, const float *__restrict__ bias, int relu, TY *__restrict__ Y, int ldy,
         int yoff) {
     constexpr int NA = NT / 32;                   // accumulators per wave
@@ -84,6 +95,7 @@ __global__ __launch_bounds__(256) void k_conv3x3(int H, int W, int Cin, int Cout
     const int tiles_x = (W + kPC - 1) / kPC;
     const int ty0 = (int)(blockIdx.x / tiles_x) * kPR, tx0 = (int)(blockIdx.x % tiles_x) * kPC;
     const int co0 = blockIdx.y * NT;
+    const int ylo = ty0 - ty0 % Himg, yhi = min(H, ylo + Himg);   // the tile's image
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int m = lane & 31, kh = (lane >> 5) * 8;   // the lane's pixel (A) / channel (B) row, k half
     const int pr = 2 * wave + (m >> 4), pc = m & 15;
@@ -99,7 +111,7 @@ __global__ __launch_bounds__(256) void k_conv3x3(int H, int W, int Cin, int Cout
             if (idx < XN) {
                 const int q = idx / XQ, part = idx % XQ;
                 const int py = ty0 - 1 + q / kHC, px = tx0 - 1 + q % kHC;
-                if (py >= 0 && py < H && px >= 0 && px < W) v = load8(X + (size_t)(py * W + px) * Cin + c0 + part * 8);
+                if (py >= ylo && py < yhi && px >= 0 && px < W) v = load8(X + ((size_t)py * W + px) * Cin + c0 + part * 8);
             }
             xr[u] = v;
         }
@@ -157,7 +169,7 @@ __global__ __launch_bounds__(256) void k_conv3x3(int H, int W, int Cin, int Cout
             if (py >= H || px >= W) continue;
             float v = acc[na][r] + bv;
             if (relu) v = v > 0.0f ? v : kSlope * v;
-            store1(&Y[(size_t)(py * W + px) * ldy + yoff + co], v);
+            store1(&Y[((size_t)py * W + px) * ldy + yoff + co], v);
         }
     }
 }
@@ -165,17 +177,17 @@ __global__ __launch_bounds__(256) void k_conv3x3(int H, int W, int Cin, int Cout
 // Launch k_conv3x3 for one layer: NT = 64 channels per block when Cout >= 64
 // (else 32), stages of 32 input channels when Cin allows (else 16).
 template <class TX, class TY>
-static void conv3x3_launch(hipStream_t s, int H, int W, int Cin, int Cout, const TX *X, const bf16 *Wt,
+static void conv3x3_launch(hipStream_t s, int H, int Himg, int W, int Cin, int Cout, const TX *X, const bf16 *Wt,
                            const float *bias, int relu, TY *Y, int ldy, int yoff) {
     const unsigned tiles = (unsigned)(((H + kPR - 1) / kPR) * ((W + kPC - 1) / kPC));
     if (Cout >= 64) {
         dim3 g(tiles, (unsigned)((Cout + 63) / 64));
-        if (Cin % 32 == 0) hipLaunchKernelGGL((k_conv3x3<TX, TY, 64, 32>), g, dim3(256), 0, s, H, W, Cin, Cout, X, Wt, bias, relu, Y, ldy, yoff);
-        else hipLaunchKernelGGL((k_conv3x3<TX, TY, 64, 16>), g, dim3(256), 0, s, H, W, Cin, Cout, X, Wt, bias, relu, Y, ldy, yoff);
+        if (Cin % 32 == 0) hipLaunchKernelGGL((k_conv3x3<TX, TY, 64, 32>), g, dim3(256), 0, s, H, Himg, W, Cin, Cout, X, Wt, bias, relu, Y, ldy, yoff);
+        else hipLaunchKernelGGL((k_conv3x3<TX, TY, 64, 16>), g, dim3(256), 0, s, H, Himg, W, Cin, Cout, X, Wt, bias, relu, Y, ldy, yoff);
     } else {
         dim3 g(tiles, (unsigned)((Cout + 31) / 32));
-        if (Cin % 32 == 0) hipLaunchKernelGGL((k_conv3x3<TX, TY, 32, 32>), g, dim3(256), 0, s, H, W, Cin, Cout, X, Wt, bias, relu, Y, ldy, yoff);
-        else hipLaunchKernelGGL((k_conv3x3<TX, TY, 32, 16>), g, dim3(256), 0, s, H, W, Cin, Cout, X, Wt, bias, relu, Y, ldy, yoff);
+        if (Cin % 32 == 0) hipLaunchKernelGGL((k_conv3x3<TX, TY, 32, 32>), g, dim3(256), 0, s, H, Himg, W, Cin, Cout, X, Wt, bias, relu, Y, ldy, yoff);
+        else hipLaunchKernelGGL((k_conv3x3<TX, TY, 32, 16>), g, dim3(256), 0, s, H, Himg, W, Cin, Cout, X, Wt, bias, relu, Y, ldy, yoff);
     }
 }
 
@@ -187,13 +199,14 @@ static void conv3x3_launch(hipStream_t s, int H, int W, int Cin, int Cout, const
 // G and of the tap-shifted X in LDS (pixel-contiguous rows, padded to 16-byte
 // multiples) per step.
 constexpr int kWTile = 64, kWStep = 32, kWChunk = 2048;
-__global__ __launch_bounds__(256) void k_conv3x3_wgrad(int H, int W, int Cin, int Cout, const bf16 *__restrict__ X,
+__global__ __launch_bounds__(256) void k_conv3x3_wgrad(int H, int Himg, int W, int Cin, int Cout, const bf16 *__restrict__ X,
         const float *__restrict__ G, float *__restrict__ dW) {
     __shared__ __attribute__((aligned(16))) bf16 As[kWTile][kWStep + kLPad];   // [co][px]
     __shared__ __attribute__((aligned(16))) bf16 Bs[kWTile][kWStep + kLPad];   // [ci][px]
     const int P = H * W;
-    const int co0 = blockIdx.x * kWTile, ci0 = blockIdx.y * kWTile;
-    const int t = blockIdx.z % 9, chunk = blockIdx.z / 9;
+    const int nco = (Cout + kWTile - 1) / kWTile;      // grid: (channel tiles x pixel chunks, ci tiles, taps)
+    const int co0 = (int)(blockIdx.x % nco) * kWTile, chunk = (int)(blockIdx.x / nco), ci0 = blockIdx.y * kWTile;
+    const int t = blockIdx.z;
     const int dy = t / 3 - 1, dx = t % 3 - 1;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
@@ -207,10 +220,10 @@ __global__ __launch_bounds__(256) void k_conv3x3_wgrad(int H, int W, int Cin, in
         uint4 vg = make_uint4(0u, 0u, 0u, 0u), vx = make_uint4(0u, 0u, 0u, 0u);
         if (p < pend) {
             const int y = p / W, x = p - y * W;
-            const int sy = y + dy, sx = x + dx;
+            const int sy = y + dy, sx = x + dx, ylo = y - y % Himg;   // the pixel's image: rows [ylo, ylo + Himg)
             if (co0 + lc < Cout) vg = load8(G + (size_t)p * Cout + co0 + lc);
-            if (ci0 + lc < Cin && sy >= 0 && sy < H && sx >= 0 && sx < W)
-                vx = load8(X + (size_t)(sy * W + sx) * Cin + ci0 + lc);
+            if (ci0 + lc < Cin && sy >= ylo && sy < ylo + Himg && sy < H && sx >= 0 && sx < W)
+                vx = load8(X + ((size_t)sy * W + sx) * Cin + ci0 + lc);
         }
         __syncthreads();
         const bf16 *g8 = (const bf16 *)&vg, *x8 = (const bf16 *)&vx;
@@ -413,7 +426,7 @@ inline unsigned nblk(size_t n, unsigned b) { return (unsigned)((n + b - 1) / b);
 struct fd_net {
     std::string err;
     hipStream_t stream = nullptr;
-    int H = 0, W = 0;
+    int H = 0, W = 0, N = 1;         // image size, images per call (stacked)
     std::vector<Layer> L;
     size_t nparam = 0;
     float *params = nullptr, *grads = nullptr, *m = nullptr, *v = nullptr;
@@ -443,12 +456,14 @@ template <class T> static int dalloc(fd_net *n, T **p, size_t count) {
     return 0;
 }
 
-static int pix(const fd_net *n, int level) { return (n->H >> level) * (n->W >> level); }
+// pixels of all n images at a level; rows of the stack and of one image
+static int pix(const fd_net *n, int level) { return n->N * (n->H >> level) * (n->W >> level); }
+static int rows(const fd_net *n, int level) { return n->N * (n->H >> level); }
 
 static int conv(fd_net *n, int li, const Act &x, bf16 *y, int ldy, int yoff, bool relu) {
     const Layer &l = n->L[li];
-    int H = n->H >> l.level, W = n->W >> l.level;
-    conv3x3_launch<bf16, bf16>(n->stream, H, W, l.cin, l.cout, x.y, n->wbf + l.woff, n->params + l.boff,
+    int H = rows(n, l.level), Himg = n->H >> l.level, W = n->W >> l.level;
+    conv3x3_launch<bf16, bf16>(n->stream, H, Himg, W, l.cin, l.cout, x.y, n->wbf + l.woff, n->params + l.boff,
                                relu ? 1 : 0, y, ldy, yoff);
     return 0;
 }
@@ -458,18 +473,18 @@ static int conv(fd_net *n, int li, const Act &x, bf16 *y, int ldy, int yoff, boo
 // the input gradient gx [P][cin].
 static void conv_bwd(fd_net *n, int li, const Act &x, const float *gout, float *gx, bool wgrad) {
     const Layer &l = n->L[li];
-    int H = n->H >> l.level, W = n->W >> l.level, P = H * W;
+    int H = rows(n, l.level), Himg = n->H >> l.level, W = n->W >> l.level, P = H * W;
     if (wgrad) {
-        dim3 gw(nblk(l.cout, kWTile), nblk(l.cin, kWTile), 9 * nblk(P, kWChunk));
-        hipLaunchKernelGGL(k_conv3x3_wgrad, gw, dim3(256), 0, n->stream, H, W, l.cin, l.cout, x.y, gout,
+        dim3 gw(nblk(l.cout, kWTile) * nblk(P, kWChunk), nblk(l.cin, kWTile), 9);
+        hipLaunchKernelGGL(k_conv3x3_wgrad, gw, dim3(256), 0, n->stream, H, Himg, W, l.cin, l.cout, x.y, gout,
                            n->grads + l.woff);
         hipLaunchKernelGGL(k_bias_grad, dim3(nblk(P, 256)), dim3(256), 0, n->stream, P, l.cout, gout, n->grads + l.boff);
     }
     if (gx) {
         hipLaunchKernelGGL(k_flip_weights, dim3(nblk((size_t)l.cin * 9 * l.cout, 256)), dim3(256), 0, n->stream,
                            l.cin, l.cout, n->params + l.woff, n->wflip);
-        conv3x3_launch<float, float>(n->stream, H, W, l.cout, l.cin, gout, n->wflip, (const float *)nullptr, 0, gx,
-                                     l.cin, 0);
+        conv3x3_launch<float, float>(n->stream, H, Himg, W, l.cout, l.cin, gout, n->wflip, (const float *)nullptr, 0,
+                                     gx, l.cin, 0);
     }
 }
 
@@ -484,12 +499,12 @@ static void forward(fd_net *n, const float *rgb, const float *aux) {
     hipLaunchKernelGGL(k_to_bf16, dim3(nblk(n->nparam, 256)), dim3(256), 0, s, n->nparam, n->params, n->wbf);
     hipLaunchKernelGGL(k_pack_input, dim3(nblk(P0, 256)), dim3(256), 0, s, P0, rgb, aux, n->x0.y);
     auto pool = [&](const Act &x, const Act &y) {
-        int H = n->H >> x.level, W = n->W >> x.level;
+        int H = rows(n, x.level), W = n->W >> x.level;
         hipLaunchKernelGGL(k_pool2, dim3(nblk((size_t)(H / 2) * (W / 2) * x.c, 256)), dim3(256), 0, s, H, W, x.c, x.y,
                            x.c, y.y);
     };
     auto upcat = [&](const Act &lo, const Act &skip, const Act &cat) {
-        int H = n->H >> cat.level, W = n->W >> cat.level;
+        int H = rows(n, cat.level), W = n->W >> cat.level;
         hipLaunchKernelGGL(k_up2, dim3(nblk((size_t)H * W * lo.c, 256)), dim3(256), 0, s, H, W, lo.c, lo.y, cat.y, cat.c);
         hipLaunchKernelGGL(k_copy_ch<bf16>, dim3(nblk((size_t)H * W * skip.c, 256)), dim3(256), 0, s, H * W, skip.c,
                            skip.y, skip.c, 0, cat.y, cat.c, lo.c);
@@ -529,14 +544,14 @@ static void backward(fd_net *n, bool wgrad, bool input) {
     hipLaunchKernelGGL(k_out_bwd, dim3(nblk(P0, 256)), dim3(256), 0, s, P0, 32, n->d0.y, n->params + lo.woff, n->dpred,
                        n->grads + lo.woff, n->grads + lo.boff, n->d0.g);
     auto split = [&](const Act &cat, const Act &lo_, const Act &skip) {   // cat grad -> lo grad, skip grad (set)
-        int H = n->H >> cat.level, W = n->W >> cat.level;
+        int H = rows(n, cat.level), W = n->W >> cat.level;
         hipLaunchKernelGGL(k_up2_bwd, dim3(nblk((size_t)(H / 2) * (W / 2) * lo_.c, 256)), dim3(256), 0, s, H, W, lo_.c,
                            cat.g, cat.c, lo_.g);
         hipLaunchKernelGGL(k_copy_ch<float>, dim3(nblk((size_t)H * W * skip.c, 256)), dim3(256), 0, s, H * W, skip.c,
                            cat.g, cat.c, lo_.c, skip.g, skip.c, 0);
     };
     auto pool_bwd = [&](const Act &py, const Act &x) {   // x.g += pool gradient
-        int H = n->H >> x.level, W = n->W >> x.level;
+        int H = rows(n, x.level), W = n->W >> x.level;
         hipLaunchKernelGGL(k_pool2_bwd_add, dim3(nblk((size_t)H * W * x.c, 256)), dim3(256), 0, s, H, W, x.c, py.g, x.g);
     };
     act_bwd(n, n->d0);  conv_bwd(n, 13, n->d0a, n->d0.g, n->d0a.g, wgrad);
@@ -563,12 +578,16 @@ static void backward(fd_net *n, bool wgrad, bool input) {
 
 extern "C" {
 
-int fd_create(int32_t H, int32_t W, fd_net **out) {
+int fd_create(int32_t H, int32_t W, fd_net **out) { return fd_create_batch(H, W, 1, out); }
+
+int fd_create_batch(int32_t H, int32_t W, int32_t N, fd_net **out) {
     if (!out) return -1;
     *out = nullptr;
-    if (H <= 0 || W <= 0 || H % 8 || W % 8 || H > 4096 || W > 4096) return -1;
+    if (H <= 0 || W <= 0 || H % 8 || W % 8 || H > 4096 || W > 4096 || N < 1 || (N > 1 && H % 64) ||
+        (long long)N * H * W > kMaxBatchPixels)
+        return -1;
     fd_net *n = new fd_net();
-    n->H = H; n->W = W;
+    n->H = H; n->W = W; n->N = N;
     const int cin[15] = {16, 32, 32, 64, 64, 128, 128, 256, 384, 128, 192, 64, 96, 32, 32};
     const int cout[15] = {32, 32, 64, 64, 128, 128, 256, 256, 128, 128, 64, 64, 32, 32, 3};
     const int lev[15] = {0, 0, 1, 1, 2, 2, 3, 3, 2, 2, 1, 1, 0, 0, 0};
@@ -583,7 +602,7 @@ int fd_create(int32_t H, int32_t W, fd_net **out) {
     int rc = 0;
     auto A = [&](Act &a, int c, int level) {
         a.c = c; a.level = level;
-        size_t cnt = (size_t)((H >> level) * (W >> level)) * c;
+        size_t cnt = (size_t)N * (size_t)((H >> level) * (W >> level)) * c;
         if (!rc) rc = dalloc(n, &a.y, cnt);
         if (!rc) rc = dalloc(n, &a.g, cnt);
     };
@@ -591,7 +610,7 @@ int fd_create(int32_t H, int32_t W, fd_net **out) {
     A(n->p2, 64, 2); A(n->e2a, 128, 2); A(n->e2, 128, 2); A(n->p3, 128, 3); A(n->e3a, 256, 3); A(n->e3, 256, 3);
     A(n->c2, 384, 2); A(n->d2a, 128, 2); A(n->d2, 128, 2); A(n->c1, 192, 1); A(n->d1a, 64, 1); A(n->d1, 64, 1);
     A(n->c0, 96, 0); A(n->d0a, 32, 0); A(n->d0, 32, 0);
-    size_t P0 = (size_t)H * W;
+    size_t P0 = (size_t)N * H * W;
     if (!rc) rc = dalloc(n, &n->params, n->nparam);
     if (!rc) rc = dalloc(n, &n->grads, n->nparam);
     if (!rc) rc = dalloc(n, &n->m, n->nparam);
@@ -722,9 +741,9 @@ int fd_conv3x3(void *stream, int32_t H, int32_t W, int32_t cin, int32_t cout, co
         return -1;
     hipStream_t s = (hipStream_t)stream;
     if (x_is_f32)
-        conv3x3_launch<float, float>(s, H, W, cin, cout, (const float *)x, (const bf16 *)w, bias, relu ? 1 : 0, y, cout, 0);
+        conv3x3_launch<float, float>(s, H, H, W, cin, cout, (const float *)x, (const bf16 *)w, bias, relu ? 1 : 0, y, cout, 0);
     else
-        conv3x3_launch<bf16, float>(s, H, W, cin, cout, (const bf16 *)x, (const bf16 *)w, bias, relu ? 1 : 0, y, cout, 0);
+        conv3x3_launch<bf16, float>(s, H, H, W, cin, cout, (const bf16 *)x, (const bf16 *)w, bias, relu ? 1 : 0, y, cout, 0);
     return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 
@@ -737,8 +756,8 @@ int fd_conv3x3_wgrad(void *stream, int32_t H, int32_t W, int32_t cin, int32_t co
     const size_t nw = (size_t)cout * 9 * cin;
     const int P = H * W;
     hipLaunchKernelGGL(k_zero_f, dim3(nblk(nw, 256)), dim3(256), 0, s, nw, dw);
-    dim3 gw(nblk(cout, kWTile), nblk(cin, kWTile), 9 * nblk(P, kWChunk));
-    hipLaunchKernelGGL(k_conv3x3_wgrad, gw, dim3(256), 0, s, H, W, cin, cout, (const bf16 *)x, g, dw);
+    dim3 gw(nblk(cout, kWTile) * nblk(P, kWChunk), nblk(cin, kWTile), 9);
+    hipLaunchKernelGGL(k_conv3x3_wgrad, gw, dim3(256), 0, s, H, H, W, cin, cout, (const bf16 *)x, g, dw);
     if (db) {
         hipLaunchKernelGGL(k_zero_f, dim3(nblk(cout, 256)), dim3(256), 0, s, (size_t)cout, db);
         hipLaunchKernelGGL(k_bias_grad, dim3(nblk(P, 256)), dim3(256), 0, s, P, cout, g, db);

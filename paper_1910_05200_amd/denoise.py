@@ -34,7 +34,7 @@ from paper_1910_05200_amd import facert, synth
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libfadenoise.so")
-EXPORTS = ("fd_create", "fd_set_stream", "fd_num_params", "fd_layer_shape", "fd_set_params", "fd_get_params",
+EXPORTS = ("fd_create", "fd_create_batch", "fd_set_stream", "fd_num_params", "fd_layer_shape", "fd_set_params", "fd_get_params",
            "fd_get_state", "fd_set_state", "fd_forward", "fd_train_step", "fd_backward_input", "fd_conv3x3",
            "fd_conv3x3_wgrad", "fd_last_error", "fd_destroy")
 
@@ -50,6 +50,7 @@ def load():
         L = C.CDLL(LIB_PATH)
         vp, i32 = C.c_void_p, C.c_int32
         L.fd_create.argtypes = [i32, i32, C.POINTER(vp)]
+        L.fd_create_batch.argtypes = [i32, i32, i32, C.POINTER(vp)]
         L.fd_set_stream.argtypes = [vp, vp]
         L.fd_num_params.argtypes = [vp]
         L.fd_num_params.restype = C.c_int64
@@ -67,7 +68,7 @@ def load():
         L.fd_last_error.restype = C.c_char_p
         L.fd_destroy.argtypes = [vp]
         L.fd_destroy.restype = None
-        for n in ("fd_create", "fd_set_stream", "fd_layer_shape", "fd_set_params", "fd_get_params", "fd_get_state",
+        for n in ("fd_create", "fd_create_batch", "fd_set_stream", "fd_layer_shape", "fd_set_params", "fd_get_params", "fd_get_state",
                   "fd_set_state", "fd_forward", "fd_train_step", "fd_backward_input", "fd_conv3x3",
                   "fd_conv3x3_wgrad"):
             getattr(L, n).restype = C.c_int
@@ -86,16 +87,17 @@ def _ptr(t):
 
 
 class Denoiser:
-    """One network for H x W images; tensors are float32 on the device."""
+    """One network for n images of H x W per call (n = 1: arrays [H][W][c];
+    n > 1: [n][H][W][c]); tensors are float32 on the device."""
 
-    def __init__(self, height: int, width: int):
+    def __init__(self, height: int, width: int, n: int = 1):
         import torch
         self.torch = torch
-        self.H, self.W = height, width
+        self.H, self.W, self.n = height, width, n
         net = C.c_void_p()
-        code = load().fd_create(height, width, C.byref(net))
+        code = load().fd_create_batch(height, width, n, C.byref(net))
         if code != 0:
-            raise FdError(code, "fd_create failed")
+            raise FdError(code, "fd_create_batch failed")
         self.net = net
         self.n_params = int(load().fd_num_params(net))
 
@@ -157,28 +159,42 @@ class Denoiser:
         self._check(load().fd_set_state(self.net, *[_ptr(a) for a in arrs], int(st["step"])))
         t.cuda.current_stream().synchronize()
 
+    def _shape(self, c):
+        return (self.H, self.W, c) if self.n == 1 else (self.n, self.H, self.W, c)
+
     def forward(self, rgb, aux, out=None):
         self._stream()
+        for a, c in ((rgb, 3), (aux, facert_aux_channels())):
+            assert a.numel() == self.n * self.H * self.W * c
         if out is None:
-            out = self.torch.empty((self.H, self.W, 3), device="cuda", dtype=self.torch.float32)
+            out = self.torch.empty(self._shape(3), device="cuda", dtype=self.torch.float32)
         self._check(load().fd_forward(self.net, _ptr(rgb.contiguous()), _ptr(aux.contiguous()), _ptr(out)))
         return out
 
     def backward_input(self, rgb, dL_dout, out=None):
         """Gradient with respect to the rgb input of the last forward."""
         self._stream()
+        for a in (rgb, dL_dout):
+            assert a.numel() == self.n * self.H * self.W * 3
         if out is None:
-            out = self.torch.empty((self.H, self.W, 3), device="cuda", dtype=self.torch.float32)
+            out = self.torch.empty(self._shape(3), device="cuda", dtype=self.torch.float32)
         self._check(load().fd_backward_input(self.net, _ptr(rgb.contiguous()), _ptr(dL_dout.contiguous()), _ptr(out)))
         return out
 
     def train_step(self, rgb, aux, target, lr: float, want_grads: bool = False):
         self._stream()
+        for a, c in ((rgb, 3), (aux, facert_aux_channels()), (target, 3)):
+            assert a.numel() == self.n * self.H * self.W * c
         loss = self.torch.empty((), device="cuda", dtype=self.torch.float32)
         g = self.torch.empty(self.n_params, device="cuda", dtype=self.torch.float32) if want_grads else None
         self._check(load().fd_train_step(self.net, _ptr(rgb.contiguous()), _ptr(aux.contiguous()),
                                          _ptr(target.contiguous()), float(lr), _ptr(loss), _ptr(g)))
         return (loss, g) if want_grads else loss
+
+
+def facert_aux_channels() -> int:
+    """Channels of fr_aov's buffers (FD_IN_AUX): albedo, normal, depth."""
+    return 7
 
 
 def conv3x3(x, w_bf16, bias=None, relu=False, x_is_f32=False):
@@ -299,19 +315,21 @@ def conv_flops(shapes, H: int, W: int) -> float:
     return float(sum(2.0 * (H >> lv) * (W >> lv) * k * k * ci * co for (ci, co, k), lv in zip(shapes, levels)))
 
 
-def bench(H: int = 256, W: int = 256, reps: int = 20) -> dict:
-    """Time fd_forward, fd_backward_input and fd_train_step on one H x W image
-    (seeded weights and inputs) with HIP events on the network's stream."""
+def bench(H: int = 256, W: int = 256, reps: int = 20, n: int = 1) -> dict:
+    """Time fd_forward, fd_backward_input and fd_train_step on n H x W images
+    per call (seeded weights and inputs) with HIP events on the network's
+    stream; times and FLOP rates are per call."""
     import torch
-    dn = Denoiser(H, W)
+    dn = Denoiser(H, W, n=n)
     shapes = dn.layer_shapes()
     dn.set_params(torch.from_numpy(init_params(shapes, 0)).cuda())
     g = torch.Generator(device="cpu").manual_seed(0)
-    rgb = (torch.rand((H, W, 3), generator=g) * 0.05).cuda()
-    aux = torch.rand((H, W, 7), generator=g).cuda()
-    tgt = (torch.rand((H, W, 3), generator=g) * 0.05).cuda()
+    shape = (H, W) if n == 1 else (n, H, W)
+    rgb = (torch.rand(shape + (3,), generator=g) * 0.05).cuda()
+    aux = torch.rand(shape + (7,), generator=g).cuda()
+    tgt = (torch.rand(shape + (3,), generator=g) * 0.05).cuda()
     out = torch.empty_like(rgb)
-    flops = conv_flops(shapes, H, W)
+    flops = n * conv_flops(shapes, H, W)
 
     def timed(fn):
         for _ in range(3):
@@ -329,7 +347,7 @@ def bench(H: int = 256, W: int = 256, reps: int = 20) -> dict:
     ms_t = timed(lambda: dn.train_step(rgb, aux, tgt, 0.0))
     dn.close()
     # a training step runs the forward, the input-gradient and the weight-gradient GEMMs: 3x the forward's FLOPs
-    return {"H": H, "W": W, "gflop_forward": flops / 1e9, "ms_forward": ms_f, "ms_backward_input": ms_b,
+    return {"H": H, "W": W, "n": n, "gflop_forward": flops / 1e9, "ms_forward": ms_f, "ms_backward_input": ms_b,
             "ms_train_step": ms_t, "tflops_forward": flops / ms_f / 1e9, "tflops_train_step": 3 * flops / ms_t / 1e9}
 
 
@@ -347,12 +365,16 @@ def main():
     ap.add_argument("--resume", default=None, help="checkpoint (.npz) to continue from")
     ap.add_argument("--save", default=None, help="write the training state (.npz) here")
     ap.add_argument("--total-steps", type=int, default=None, help="length of the cosine schedule across runs")
-    ap.add_argument("--bench", action="store_true", help="only time the network's calls at 256x256")
+    ap.add_argument("--bench", action="store_true", help="only time the network's calls: one, 8 and 64 "
+                    "images of 256x256 per call, and 64 of 512x512 (the sequence fit's frames)")
     args = ap.parse_args()
     import torch
     assert torch.cuda.is_available(), "the denoiser needs a HIP device"
     if args.bench:
-        print(json.dumps(bench()))
+        print(json.dumps(bench()), flush=True)
+        for n in (8, 64):          # several images per call: the deep layers fill the chip
+            print(json.dumps(bench(n=n, reps=5)), flush=True)
+        print(json.dumps(bench(512, 512, reps=3, n=64)), flush=True)
         return
     model, scene, _, _ = synth.workload("paper")
     r = facert.Renderer(model, scene)

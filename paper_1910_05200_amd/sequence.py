@@ -181,9 +181,26 @@ def run(r: facert.Renderer, targets, base, frames, start, start_frames, iters: i
                 return dn.backward_input(img, dL) if mode == "denoised" else dL
             return rf.loss_l2(img, targets[f])[0]
 
+        def data_grads_stacked(imgs):
+            # a denoiser made for all n frames: one forward and one input
+            # gradient for the stack instead of n of each
+            rgb = torch.stack(imgs)
+            aux = torch.empty((n, r.H, r.W, denoise.facert_aux_channels()), device="cuda", dtype=torch.float32)
+            for f in range(n):
+                rs[f].aov(out=aux[f])
+            den = dn.forward(rgb, aux)
+            dL = torch.stack([rs[f].loss_l2(den[f], targets[f])[0] for f in range(n)])
+            if mode == "denoised":
+                dL = dn.backward_input(rgb, dL)
+            return [dL[f] for f in range(n)]
+
         if batch is not None:
             imgs = batch.render(ps, seeds, [spp] * n)
-            gs = batch.backward([data_grad(rs[f], imgs[f], f) for f in range(n)], want=want)
+            if mode in ("denoised", "denoised-st") and dn.n == n > 1:
+                dls = data_grads_stacked(imgs)
+            else:
+                dls = [data_grad(rs[f], imgs[f], f) for f in range(n)]
+            gs = batch.backward(dls, want=want)
         else:
             gs = []
             for f in range(n):
@@ -255,17 +272,23 @@ def main():
                         synth.TARGET_SPP).clone() for f, (b, p) in enumerate(frames)]
     dn = None
     modes = [(m.split(":")[0], int(m.split(":")[1])) for m in args.modes.split(",")]
+    # with batched frames, one network runs all of them per call
+    dn_n = args.frames if rs is not None and args.frames > 1 and scene.height % 64 == 0 else 1
     if any(m.startswith("denoised") for m, _ in modes) and args.dn_ckpt:
-        dn = denoise.Denoiser(scene.height, scene.width)
+        dn = denoise.Denoiser(scene.height, scene.width, n=dn_n)
         with np.load(args.dn_ckpt, allow_pickle=False) as z:
             dn.set_params(torch.from_numpy(np.ascontiguousarray(z["params"], np.float32)).cuda())
         print(json.dumps({"denoiser": args.dn_ckpt}), flush=True)
     elif any(m.startswith("denoised") for m, _ in modes):
         t0 = time.perf_counter()
-        dn = denoise.Denoiser(scene.height, scene.width)
+        dn = denoise.Denoiser(scene.height, scene.width, n=dn_n)
         dw = args.dn_workload or args.workload
         if dw == args.workload:
-            denoise.train(r, dn, args.dn_pairs, args.dn_epochs, spp_in=2, spp_target=synth.TARGET_SPP)
+            dn1 = denoise.Denoiser(scene.height, scene.width) if dn_n > 1 else dn
+            denoise.train(r, dn1, args.dn_pairs, args.dn_epochs, spp_in=2, spp_target=synth.TARGET_SPP)
+            if dn1 is not dn:
+                dn.set_params(dn1.get_params())
+                dn1.close()
         else:
             m2, s2, _, _ = synth.workload(dw)
             r2 = facert.Renderer(m2, s2)

@@ -100,3 +100,24 @@ def test_batch_argument_errors_without_gpu():
     assert len(set(names)) == n and "sh_trace" in names and "render_adj" in names
     assert lib.fr_batch_kind_name(n) is None and lib.fr_batch_kind_name(-1) is None
     lib.fr_batch_destroy(None)
+
+
+def test_denoiser_batch_arguments_without_gpu():
+    """fd_create_batch refuses its sizes before any device call: n < 1, a
+    height that is not a multiple of 64 with n > 1, more pixels than the
+    network's 32-bit indexing allows."""
+    from paper_1910_05200_amd import denoise
+    lib = denoise.load()
+    out = C.c_void_p()
+    for H, W, n in ((64, 64, 0), (72, 64, 2), (512, 512, 100), (60, 64, 1)):
+        assert lib.fd_create_batch(H, W, n, C.byref(out)) == -1 and not out.value, (H, W, n)
+
+
+def test_denoiser_header_declares_what_the_library_exports():
+    src = open(os.path.join(ROOT, "include", "fadenoise.h")).read()
+    names = set(re.findall(r"^(?:int|int64_t|void|const char \*)\s*\*?\s*(fd_\w+)\s*\(", src, re.M))
+    from paper_1910_05200_amd import denoise
+    assert names == set(denoise.EXPORTS), names ^ set(denoise.EXPORTS)
+    lib = denoise.load()
+    for n in names:
+        assert getattr(lib, n) is not None, n

@@ -231,3 +231,52 @@ def test_single_layer_argument_errors(torch):
     assert lib.fd_conv3x3(None, 0, 4, 16, 8, z.data_ptr(), 0, z.data_ptr(), None, 0, z.data_ptr()) == -1
     assert lib.fd_conv3x3(None, 4, 4, 16, 8, None, 0, z.data_ptr(), None, 0, z.data_ptr()) == -1
     assert lib.fd_conv3x3_wgrad(None, 4, 4, 12, 8, z.data_ptr(), z.data_ptr(), z.data_ptr(), None) == -1
+
+
+def test_batched_network_equals_single_image_networks(torch):
+    """A network made for n images per call (fd_create_batch) against a
+    one-image network with the same weights: the forward and the input
+    gradient of every image bit for bit (the same kernels, per-pixel sums in
+    the same order; no image reads another's pixels across the stack), the
+    training gradient equal to the mean of the single images' gradients up
+    to fp32 summation order (the batched loss is the mean over all images'
+    pixels), at the renderer's per-component bar with each layer's floor.
+    n is a power of two: the batched loss gradient is the single image's
+    divided by n, and only then does that scaling commute with the bfloat16
+    rounding of the gradients where they enter a product (with n = 3 the
+    two roundings differ by up to 2^-8 per element, and the weight
+    gradients by about 1%, as for any two equally valid bf16 evaluations)."""
+    from paper_1910_05200_amd import denoise
+    from parity import assert_group_parity
+    H, W, n = 64, 96, 4
+    one, p = _net(torch, H, W, seed=4)
+    many = denoise.Denoiser(H, W, n=n)
+    many.set_params(torch.from_numpy(p).cuda())
+    ins = [_inputs(H, W, 40 + i) for i in range(n)]
+    rgb = torch.from_numpy(np.stack([a[0] for a in ins])).cuda()
+    aux = torch.from_numpy(np.stack([a[1] for a in ins])).cuda()
+    tgt = torch.from_numpy(np.stack([a[2] for a in ins])).cuda()
+    out = many.forward(rgb, aux).clone()
+    rng = np.random.default_rng(8)
+    gout = torch.from_numpy(rng.normal(size=(n, H, W, 3)).astype(np.float32)).cuda()
+    gin = many.backward_input(rgb, gout).clone()
+    for i in range(n):
+        o1 = one.forward(rgb[i], aux[i])
+        assert torch.equal(o1, out[i]), i
+        assert torch.equal(one.backward_input(rgb[i], gout[i]), gin[i]), i
+    # gradients of a training step (the step's update itself is not compared)
+    many.set_params(torch.from_numpy(p).cuda())
+    _, g_many = many.train_step(rgb, aux, tgt, 0.0, want_grads=True)
+    g_ref = np.zeros(p.shape, np.float64)
+    for i in range(n):
+        one.set_params(torch.from_numpy(p).cuda())
+        _, g1 = one.train_step(rgb[i], aux[i], tgt[i], 0.0, want_grads=True)
+        g_ref += g1.cpu().numpy().astype(np.float64) / n
+    g_many = g_many.cpu().numpy()
+    off = 0
+    for li, (ci, co, k) in enumerate(many.layer_shapes()):
+        nw = co * k * k * ci
+        assert_group_parity(g_many[off:off + nw], g_ref[off:off + nw], f"layer {li} weights")
+        assert_group_parity(g_many[off + nw:off + nw + co], g_ref[off + nw:off + nw + co], f"layer {li} bias")
+        off += nw + co
+    assert off == p.size

@@ -119,6 +119,17 @@ def test_sequence_fit_runs_every_mode(torch):
         first, last = out["log"][0]["psnr_db"], out["log"][-1]["psnr_db"]
         print(mode, spp, first, last)
         assert out["batched"] and last > first + 1.0, (mode, first, last)
+    # a denoiser made for both frames (one call for the stack) gives each
+    # frame's denoised image and input gradient bit for bit: the same fit
+    # up to the renderer's atomics order
+    dn2 = denoise.Denoiser(scene.height, scene.width, n=2)
+    dn2.set_params(dn.get_params())
+    for mode in ("denoised", "denoised-st"):
+        one = sequence.run(r, targets, base, frames, start, start_frames, 6, mode, 2, dn, eval_spp=16,
+                           log_every=6, rs=rs)
+        two = sequence.run(r, targets, base, frames, start, start_frames, 6, mode, 2, dn2, eval_spp=16,
+                           log_every=6, rs=rs)
+        assert abs(one["log"][-1]["psnr_db"] - two["log"][-1]["psnr_db"]) < 0.05, (mode, one["log"][-1], two["log"][-1])
     # frame by frame: the same images and, up to atomics order, the same gradients: the same fit
     a = sequence.run(r, targets, base, frames, start, start_frames, 6, "plain", 4, dn, eval_spp=16, log_every=6,
                      rs=rs)
