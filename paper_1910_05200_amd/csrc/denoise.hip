@@ -245,12 +245,32 @@ __global__ __launch_bounds__(256) void k_conv3x3_wgrad(int H, int Himg, int W, i
     }
 }
 
-// bias gradient: db[c] += sum_p G[p][c] (one block per 256 pixels)
+// bias gradient: db[c] += sum_p G[p][c], one block per 256 pixels.  With
+// C < 256 channels the block's threads form 256 / C rows of C channels
+// (consecutive threads read consecutive channels of one pixel), each row
+// summing every (256 / C)-th pixel; the rows' partial sums meet in LDS and
+// each channel takes one atomic per block.
 __global__ __launch_bounds__(256) void k_bias_grad(int P, int C, const float *__restrict__ G, float *__restrict__ db) {
-    for (int c = threadIdx.x; c < C; c += blockDim.x) {
-        float s = 0.0f;
-        for (int p = blockIdx.x * 256; p < min(P, blockIdx.x * 256 + 256); ++p) s += G[(size_t)p * C + c];
-        if (s != 0.0f) atomicAdd(&db[c], s);
+    __shared__ float part[256];
+    const int p0 = blockIdx.x * 256, p1 = min(P, p0 + 256);
+    if (C >= 256) {
+        for (int c = threadIdx.x; c < C; c += 256) {
+            float s = 0.0f;
+            for (int p = p0; p < p1; ++p) s += G[(size_t)p * C + c];
+            if (s != 0.0f) atomicAdd(&db[c], s);
+        }
+        return;
+    }
+    const int rows = 256 / C, c = threadIdx.x % C, r = threadIdx.x / C;
+    float s = 0.0f;
+    if (r < rows)
+        for (int p = p0 + r; p < p1; p += rows) s += G[(size_t)p * C + c];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    if (threadIdx.x < C) {
+        float t = 0.0f;
+        for (int k = 0; k < rows; ++k) t += part[k * C + threadIdx.x];
+        if (t != 0.0f) atomicAdd(&db[threadIdx.x], t);
     }
 }
 
@@ -349,39 +369,55 @@ __global__ void k_expm1(int n, const float *__restrict__ pred, float *__restrict
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) out[i] = expm1f(pred[i]) / kExposure;
 }
-// loss and its gradient: d = pred - log(1 + kExposure target); loss += d^2 / n; dpred = 2 d / n
+// loss and its gradient: d = pred - log(1 + kExposure target); loss += d^2 / n; dpred = 2 d / n.
+// One block per kLossBlock values; the block's sum takes one atomic (one per
+// wave serialised on the single loss word once many images run per call).
+constexpr int kLossBlock = 4096;
 __global__ __launch_bounds__(256) void k_loss(int n, const float *__restrict__ pred, const float *__restrict__ tgt,
                                              float *__restrict__ dpred, float *__restrict__ loss) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ float part[4];
     float e = 0.0f;
-    if (i < n) {
+    const int i1 = min(n, (int)(blockIdx.x + 1) * kLossBlock);
+    for (int i = (int)blockIdx.x * kLossBlock + (int)threadIdx.x; i < i1; i += 256) {
         float d = pred[i] - log1pf(kExposure * fmaxf(tgt[i], 0.0f));
         dpred[i] = 2.0f * d / (float)n;
-        e = d * d / (float)n;
+        e += d * d / (float)n;
     }
     for (int off = 32; off > 0; off >>= 1) e += __shfl_xor(e, off);
-    if ((threadIdx.x & 63) == 0 && e != 0.0f) atomicAdd(loss, e);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = e;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const float t = (part[0] + part[1]) + (part[2] + part[3]);
+        if (t != 0.0f) atomicAdd(loss, t);
+    }
 }
 // output layer backward: dw[k][c] += sum_p dpred[p][k] x[p][c]; db[k] += sum_p dpred;
-// gx[p][c] = sum_k dpred[p][k] w[k][c]
+// gx[p][c] = sum_k dpred[p][k] w[k][c].  One block per 256 pixels (C <= 64):
+// first one thread per pixel writes gx; then one thread per (k, c) weight
+// and per k bias sums its products over the block's pixels (staged in LDS)
+// and adds them with one atomic.
 __global__ __launch_bounds__(256) void k_out_bwd(int P, int C, const bf16 *__restrict__ x, const float *__restrict__ w,
         const float *__restrict__ dpred, float *__restrict__ dw, float *__restrict__ db, float *__restrict__ gx) {
-    __shared__ float sw[3 * 64 + 3];
-    for (int k = threadIdx.x; k < 3 * C + 3; k += blockDim.x) sw[k] = 0.0f;
-    __syncthreads();
-    int p = blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ float sd[256][3];
+    const int p0 = blockIdx.x * 256, p = p0 + threadIdx.x, np = min(256, P - p0);
     if (p < P) {
-        float d[3] = {dpred[3 * p], dpred[3 * p + 1], dpred[3 * p + 2]};
-        for (int c = 0; c < C; ++c) {
-            float xv = bf2f(x[(size_t)p * C + c]);
-            gx[(size_t)p * C + c] = d[0] * w[c] + d[1] * w[C + c] + d[2] * w[2 * C + c];
-            for (int k = 0; k < 3; ++k) atomicAdd(&sw[k * C + c], d[k] * xv);
-        }
-        for (int k = 0; k < 3; ++k) atomicAdd(&sw[3 * C + k], d[k]);
+        const float d0 = dpred[3 * p], d1 = dpred[3 * p + 1], d2 = dpred[3 * p + 2];
+        sd[threadIdx.x][0] = d0; sd[threadIdx.x][1] = d1; sd[threadIdx.x][2] = d2;
+        for (int c = 0; c < C; ++c) gx[(size_t)p * C + c] = d0 * w[c] + d1 * w[C + c] + d2 * w[2 * C + c];
     }
     __syncthreads();
-    for (int k = threadIdx.x; k < 3 * C; k += blockDim.x) if (sw[k] != 0.0f) atomicAdd(&dw[k], sw[k]);
-    for (int k = threadIdx.x; k < 3; k += blockDim.x) if (sw[3 * C + k] != 0.0f) atomicAdd(&db[k], sw[3 * C + k]);
+    const int t = threadIdx.x;
+    if (t < 3 * C) {
+        const int k = t / C, c = t % C;
+        float s = 0.0f;
+        for (int q = 0; q < np; ++q) s += sd[q][k] * bf2f(x[(size_t)(p0 + q) * C + c]);
+        if (s != 0.0f) atomicAdd(&dw[t], s);
+    } else if (t < 3 * C + 3) {
+        const int k = t - 3 * C;
+        float s = 0.0f;
+        for (int q = 0; q < np; ++q) s += sd[q][k];
+        if (s != 0.0f) atomicAdd(&db[k], s);
+    }
 }
 
 // d loss / d pred from d loss / d out, out = expm1(pred) / kExposure
@@ -709,7 +745,7 @@ int fd_train_step(fd_net *n, const float *rgb, const float *aux, const float *ta
     int cnt = 3 * pix(n, 0);
     float *lp = loss ? loss : n->loss_s;
     hipLaunchKernelGGL(k_zero_f, dim3(1), dim3(64), 0, n->stream, (size_t)1, lp);
-    hipLaunchKernelGGL(k_loss, dim3(nblk(cnt, 256)), dim3(256), 0, n->stream, cnt, n->pred, target, n->dpred, lp);
+    hipLaunchKernelGGL(k_loss, dim3(nblk(cnt, kLossBlock)), dim3(256), 0, n->stream, cnt, n->pred, target, n->dpred, lp);
     backward(n, true, false);
     if (grads) HIPCK(n, hipMemcpyAsync(grads, n->grads, n->nparam * sizeof(float), hipMemcpyDeviceToDevice, n->stream));
     ++n->step;

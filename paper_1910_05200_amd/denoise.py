@@ -367,10 +367,14 @@ def main():
     ap.add_argument("--total-steps", type=int, default=None, help="length of the cosine schedule across runs")
     ap.add_argument("--bench", action="store_true", help="only time the network's calls: one, 8 and 64 "
                     "images of 256x256 per call, and 64 of 512x512 (the sequence fit's frames)")
+    ap.add_argument("--bench-n", type=int, default=0, help="with --bench: only n images of 256x256 per call")
     args = ap.parse_args()
     import torch
     assert torch.cuda.is_available(), "the denoiser needs a HIP device"
     if args.bench:
+        if args.bench_n:
+            print(json.dumps(bench(n=args.bench_n)), flush=True)
+            return
         print(json.dumps(bench()), flush=True)
         for n in (8, 64):          # several images per call: the deep layers fill the chip
             print(json.dumps(bench(n=n, reps=5)), flush=True)
