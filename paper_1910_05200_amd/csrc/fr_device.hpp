@@ -249,32 +249,45 @@ __device__ inline Hit trace_closest(const Scene &S, v3 o, v3 d, Work &wk) {
     return h;
 }
 
-// any hit on o + t d, t in (kShadowTmin, kShadowTmax), ignoring triangle skip
+// any hit on o + t d, t in (kShadowTmin, kShadowTmax), ignoring triangle skip.
+// The loop runs while any lane of the wave still walks (a wave-uniform exit),
+// so the node tests can be counted per wave in a scalar register, from the
+// mask of walking lanes, and added to one lane's counter at the end: a
+// per-lane count costs a vector instruction on every step of a loop whose
+// vector issue is its limit.  The total is the per-lane sum.
 __device__ inline bool trace_any(const Scene &S, v3 o, v3 d, int skip, Work &wk) {
-    Ray r = make_ray(o, d);
+    const Ray r = make_ray(o, d);
     int node = 0;
-    while (node < S.n_nodes) {
-        const Node q = load_node(S.nodes, node);
-        int link = node_link(q);
-        ++wk.box;
-        if (slab(r, node_box(q), 1.0f)) {
-            if (link < 0) {
-                int leaf = ~link;
-                float4 q0 = S.tris[3 * leaf], q1 = S.tris[3 * leaf + 1], q2 = S.tris[3 * leaf + 2];
-                int id = __float_as_int(q2.y);
-                if (id != skip) {
-                    v3 v0 = mk(q0.x, q0.y, q0.z), v1 = mk(q0.w, q1.x, q1.y), v2 = mk(q1.z, q1.w, q2.x);
+    bool hit = false;
+    uint32_t boxes = 0;                            // wave-uniform
+    for (;;) {
+        const bool walk = node < S.n_nodes;
+        const unsigned long long m = __ballot(walk);
+        if (!m) break;
+        boxes += (uint32_t)__popcll(m);
+        if (walk) {
+            const Node q = load_node(S.nodes, node);
+            const int link = node_link(q);
+            const bool in = slab(r, node_box(q), 1.0f), leaf = link < 0;
+            node = (in || leaf) ? node + 1 : link;
+            if (in && leaf) {
+                const int k = ~link;
+                const float4 q0 = S.tris[3 * k], q1 = S.tris[3 * k + 1], q2 = S.tris[3 * k + 2];
+                if (__float_as_int(q2.y) != skip) {
+                    const v3 v0 = mk(q0.x, q0.y, q0.z), v1 = mk(q0.w, q1.x, q1.y), v2 = mk(q1.z, q1.w, q2.x);
                     float t, b1, b2, det;
                     ++wk.tri;
-                    if (ray_tri(o, d, v0, v1, v2, kShadowTmin, kShadowTmax, t, b1, b2, det)) return true;
+                    if (ray_tri(o, d, v0, v1, v2, kShadowTmin, kShadowTmax, t, b1, b2, det)) {
+                        hit = true;
+                        node = S.n_nodes;          // this lane's walk ends
+                    }
                 }
             }
-            node = node + 1;
-        } else {
-            node = link < 0 ? node + 1 : link;
         }
     }
-    return false;
+    // every lane that entered is active again: the first of them takes the wave's count
+    if ((int)__lane_id() == __ffsll((unsigned long long)__builtin_amdgcn_read_exec()) - 1) wk.box += boxes;
+    return hit;
 }
 
 // Closest hits of two rays from one origin in one traversal (the two sides
