@@ -26,13 +26,13 @@ if ROOT not in sys.path:
 METRIC = "fwd+bwd ms/iter & Mrays/s at 256x256; denoised-2spp vs plain-256spp at equal PSNR"
 
 # Algorithmic VALU work per unit, in fp32 lane operations, at fixed costs
-# that do not depend on how this build compiles: a box (slab) test 15 (six
+# that do not depend on how the kernels compile: a box (slab) test 15 (six
 # fused subtract-multiply slab times, six min/max, the entry/exit compare),
 # a Moller-Trumbore triangle test 50 (two cross products, three dot
 # products, the reciprocal, the bound tests).  These price the roofline.
 OPS_BOX = 15
 OPS_TRI = 50
-# The same units as this build's gfx950 code issues them (VALU instructions
+# The same units as the compiled gfx950 code issues them (VALU instructions
 # per lane in the compiled loop, address arithmetic included): a node visit
 # 21 (binary16 decode folded into v_fma_mix_f32), a full triangle test with
 # its hit-box check 95, one light sample's shading 215, one light sample's
@@ -107,7 +107,7 @@ def oracle_threads(requested: int = 0) -> int:
 def roofline_entry(kernel: str, box: float, tri: float, shade: float, shade_cost: int, sec: float, workload: str):
     """The roofline object of one kernel's launch: work at the fixed unit
     costs over its measured time against the VALU ceiling, the same work at
-    this build's instruction costs, and the VALU counters of the committed
+    the compiled code's instruction costs, and the VALU counters of the committed
     profile (issue rate of wave-level VALU instructions, as lane slots, and
     the active lanes per instruction)."""
     ops = box * OPS_BOX + tri * OPS_TRI + shade * shade_cost
@@ -289,8 +289,8 @@ def bench_batch(args):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the path shards by image "
-              "rows with one gradient all-reduce, which this build does not run)", file=sys.stderr)
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the path would shard by image "
+              "rows with one gradient all-reduce; the library implements one GPU's share)", file=sys.stderr)
         sys.exit(2)
     if args.workload == "batch":
         return bench_batch(args)
