@@ -828,12 +828,22 @@ __global__ __launch_bounds__(256) void k_sh_propose(Scene S, uint64_t seed, long
         unsigned long long *ctr) {
     sh_propose_all_body(S, seed, s0, n, hits, queue, qcap, cnt, ctr, blockIdx.x);
 }
+// k_sh_trace runs one wave per block (both paths), k_pv_trace takes its block
+// size from the launch.  One wave per block: a wave whose rays have
+// all ended frees its slot at once, where a wave of a four-wave block holds
+// the block's place until the other three end too (1.40 -> 1.34 ms at paper
+// scale; 128-thread blocks 1.37).  The batched path runs k_pv_trace the same
+// way (the batched step 103.1 -> 99.2 ms with both); the single context
+// keeps four-wave blocks for it, since there it shares the chip with the
+// interior adjoint on the other stream, which then ran slower by more than
+// the silhouette rays gained.
+constexpr int kTraceBlock = 64, kPvTraceBlock = 256;
 __device__ __forceinline__ void sh_trace_body(const Scene &S, uint64_t seed, long long s0,
         const HitRec *__restrict__ hits, const uint32_t *__restrict__ queue, uint32_t qcap,
         const uint32_t *__restrict__ cnt, unsigned long long *__restrict__ vis, unsigned long long *ctr, int bx,
         int j) {
-    const uint32_t e = bx * 256 + threadIdx.x;
-    if ((uint32_t)bx * 256 >= cnt[j]) return;   // the whole block is past the queue
+    const uint32_t e = bx * kTraceBlock + threadIdx.x;
+    if ((uint32_t)bx * kTraceBlock >= cnt[j]) return;   // the whole block is past the queue
     Work wk;
     if (e < cnt[j]) {
         const uint32_t i = queue[(size_t)j * qcap + e];
@@ -844,7 +854,7 @@ __device__ __forceinline__ void sh_trace_body(const Scene &S, uint64_t seed, lon
     }
     flush_work(ctr, wk);
 }
-__global__ __launch_bounds__(256) void k_sh_trace(Scene S, uint64_t seed, long long s0,
+__global__ __launch_bounds__(kTraceBlock) void k_sh_trace(Scene S, uint64_t seed, long long s0,
         const HitRec *__restrict__ hits, const uint32_t *__restrict__ queue, uint32_t qcap,
         const uint32_t *__restrict__ cnt, unsigned long long *__restrict__ vis, unsigned long long *ctr) {
     sh_trace_body(S, seed, s0, hits, queue, qcap, cnt, vis, ctr, blockIdx.x, blockIdx.y);
@@ -1682,8 +1692,8 @@ __device__ __forceinline__ void pv_trace_body(const Scene &S, uint64_t seed, con
         const Hit *__restrict__ hits, const uint32_t *__restrict__ queue, uint32_t qcap,
         const uint32_t *__restrict__ cnt, unsigned long long *__restrict__ pvis, unsigned long long *ctr, int bx,
         int j) {
-    const uint32_t e = bx * 256 + threadIdx.x;
-    if ((uint32_t)bx * 256 >= cnt[j]) return;   // the whole block is past the queue
+    const uint32_t e = bx * blockDim.x + threadIdx.x;
+    if ((uint32_t)bx * blockDim.x >= cnt[j]) return;   // the whole block is past the queue
     Work wk;
     if (e < cnt[j]) {
         const int ms = (int)queue[(size_t)j * qcap + e];
@@ -1696,7 +1706,7 @@ __device__ __forceinline__ void pv_trace_body(const Scene &S, uint64_t seed, con
     }
     flush_work(ctr, wk);
 }
-__global__ __launch_bounds__(256) void k_pv_trace(Scene S, uint64_t seed, const PeSample *__restrict__ ps_in,
+__global__ __launch_bounds__(kPvTraceBlock) void k_pv_trace(Scene S, uint64_t seed, const PeSample *__restrict__ ps_in,
         const Hit *__restrict__ hits, const uint32_t *__restrict__ queue, uint32_t qcap,
         const uint32_t *__restrict__ cnt, unsigned long long *__restrict__ pvis, unsigned long long *ctr) {
     pv_trace_body(S, seed, ps_in, hits, queue, qcap, cnt, pvis, ctr, blockIdx.x, blockIdx.y);
@@ -2412,7 +2422,7 @@ static void shadow_pass(fr_ctx *c, const Scene &S, uint64_t seed, long long s0, 
     hipLaunchKernelGGL(k_sh_propose, dim3(nblk(n, 256)), dim3(256), 0, c->stream, S, seed, s0, n, c->hits,
                        c->sh_queue, qcap, c->sh_cnt, ctr);
     if (ev0 >= 0) ev_record(c, ev0);
-    hipLaunchKernelGGL(k_sh_trace, dim3(nblk(n, 256), c->nl), dim3(256), 0, c->stream, S, seed, s0, c->hits,
+    hipLaunchKernelGGL(k_sh_trace, dim3(nblk(n, kTraceBlock), c->nl), dim3(kTraceBlock), 0, c->stream, S, seed, s0, c->hits,
                        c->sh_queue, qcap, c->sh_cnt, c->vis, ctr);
     if (ev1 >= 0) ev_record(c, ev1);
 }
@@ -2815,7 +2825,7 @@ static void primary_pass(fr_ctx *c, const Scene &S, const float *dLdI, hipStream
     const uint32_t pv_cap = 2 * (uint32_t)M;
     hipLaunchKernelGGL(k_pv_propose, dim3(nblk((size_t)pv_cap, 256)), dim3(256), 0, st, S, c->last_seed, c->pe_samples,
                        c->pe_hits, c->pv_perm, c->pv_aux, c->pv_queue, pv_cap, pctr);
-    hipLaunchKernelGGL(k_pv_trace, dim3(nblk((size_t)pv_cap, 256), c->nl), dim3(256), 0, st, S,
+    hipLaunchKernelGGL(k_pv_trace, dim3(nblk((size_t)pv_cap, kPvTraceBlock), c->nl), dim3(kPvTraceBlock), 0, st, S,
                        c->last_seed, c->pe_samples, c->pe_hits, c->pv_queue, pv_cap, c->pv_aux + 2 * pv_nk,
                        c->pe_vis, pctr);
     hipLaunchKernelGGL(k_edge_primary_shade, dim3(nblk((size_t)2 * M, 256)), dim3(256), lds1, st,

@@ -158,7 +158,7 @@ FR_KIND(KShPropose, 256) {
     sh_propose_all_body(I.S, I.d.seed, 0, I.N, I.hits, I.sh_queue, I.sh_qcap, I.sh_cnt,
                         I.ctr + kCtrPerKern * kKernShadow, bx);
 }};
-FR_KIND(KShTrace, 256) {
+FR_KIND(KShTrace, kTraceBlock) {
     sh_trace_body(I.S, I.d.seed, 0, I.hits, I.sh_queue, I.sh_qcap, I.sh_cnt, I.vis, I.ctr + kCtrPerKern * kKernShadow,
                   bx, by);
 }};
@@ -206,7 +206,7 @@ FR_KIND(KPvPropose, 256) {
     pv_propose_body(I.S, I.d.seed, I.pe_samples, I.pe_hits, I.pv_perm, I.pv_aux, I.pv_queue, 2 * (uint32_t)I.M,
                     I.ctr + kCtrPerKern * kKernPrimary, bx);
 }};
-FR_KIND(KPvTrace, 256) {
+FR_KIND(KPvTrace, kTraceBlock) {
     if (!(I.d.terms & FR_TERM_PRIMARY)) return;
     pv_trace_body(I.S, I.d.seed, I.pe_samples, I.pe_hits, I.pv_queue, 2 * (uint32_t)I.M,
                   I.pv_aux + 2 * pv_keys(I.S.W, I.S.H), I.pe_vis, I.ctr + kCtrPerKern * kKernPrimary, bx, by);
@@ -369,14 +369,14 @@ static void kind_grid(const fr_batch *b, int k, int i, int &gx, int &gy) {
     case bkCamera: case bkShade: case bkAdj: gx = (int)nblk(N, 256); break;
     case bkSecondary: gx = (int)nblk(N, ts); gy = nl; break;
     case bkShPropose: gx = (int)nblk(N, 256); break;
-    case bkShTrace: gx = (int)nblk(N, 256); gy = nl; break;
+    case bkShTrace: gx = (int)nblk(N, kTraceBlock); gy = nl; break;
     case bkPixelMean: case bkPrimarySetup: case bkPvOrder: case bkPrimaryScatter: gx = (int)nblk(M, 256); break;
     case bkZeroBwd:
         gx = (int)nblk(std::max({3 * V, rr, 3 * nl, 8 * kCtrSpread * kNumKern, pv_aux_len(c->W, c->H, nl)}), 256);
         break;
     case bkSecValue: gx = (int)std::min<long long>(1024, std::max<long long>(1, (N + 1023) / 1024)); break;
     case bkPvPropose: gx = (int)nblk(2 * (size_t)M, 256); break;
-    case bkPvTrace: gx = (int)nblk(2 * (size_t)M, 256); gy = nl; break;
+    case bkPvTrace: gx = (int)nblk(2 * (size_t)M, kTraceBlock); gy = nl; break;
     case bkPrimaryShade: gx = (int)nblk(2 * (size_t)M, 256); break;
     case bkParamPartial: gx = rows; gy = c->nchunks; break;
     case bkParamFinal: gx = (int)nblk(rows, 64); break;
