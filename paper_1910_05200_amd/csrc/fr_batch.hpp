@@ -151,7 +151,7 @@ FR_KIND(KZeroFwd, 64) {
     for (int e = (int)threadIdx.x; e < 8 * kCtrSpread * kKernAdj; e += 64) I.ctr[e * kCtrPad] = 0ull;
     for (int e = (int)threadIdx.x; e < I.S.nl; e += 64) I.sh_cnt[e] = 0u;
 }};
-FR_KIND(KCamera, 256) {
+FR_KIND(KCamera, kTraceBlock) {
     fwd_camera_body(I.S, I.d.seed, I.d.spp, 0, I.N, I.hits, I.vis, I.ctr + kCtrPerKern * kKernCamera, bx);
 }};
 FR_KIND(KShPropose, 256) {
@@ -188,7 +188,7 @@ FR_KIND(KSecValue, 256) {
     if (!(I.d.terms & FR_TERM_SECONDARY)) return;
     edge_secondary_value_body(I.S, I.d.seed, I.d.spp, 0, I.d.dLdI, I.hits, I.sec_list, I.sec_n, I.G.d_pos, bx, gx);
 }};
-FR_KIND(KPrimarySetup, 256) {
+FR_KIND(KPrimarySetup, kTraceBlock) {
     if (!(I.d.terms & FR_TERM_PRIMARY)) return;
     edge_primary_setup_body(I.S, I.d.seed, I.M, I.pe_samples, I.pe_hits, I.pe_vis, I.pv_aux,
                             I.ctr + kCtrPerKern * kKernPrimary, bx);
@@ -366,11 +366,13 @@ static void kind_grid(const fr_batch *b, int k, int i, int &gx, int &gy) {
     case bkBoxesTop: gx = F > 1 ? 1 : 0; break;
     case bkEdgeWeights: gx = (int)nblk(c->E, 256); break;
     case bkEdgeScan: gx = 1 + nl; break;
-    case bkCamera: case bkShade: case bkAdj: gx = (int)nblk(N, 256); break;
+    case bkCamera: gx = (int)nblk(N, kTraceBlock); break;
+    case bkShade: case bkAdj: gx = (int)nblk(N, 256); break;
     case bkSecondary: gx = (int)nblk(N, ts); gy = nl; break;
     case bkShPropose: gx = (int)nblk(N, 256); break;
     case bkShTrace: gx = (int)nblk(N, kTraceBlock); gy = nl; break;
-    case bkPixelMean: case bkPrimarySetup: case bkPvOrder: case bkPrimaryScatter: gx = (int)nblk(M, 256); break;
+    case bkPrimarySetup: gx = (int)nblk(M, kTraceBlock); break;
+    case bkPixelMean: case bkPvOrder: case bkPrimaryScatter: gx = (int)nblk(M, 256); break;
     case bkZeroBwd:
         gx = (int)nblk(std::max({3 * V, rr, 3 * nl, 8 * kCtrSpread * kNumKern, pv_aux_len(c->W, c->H, nl)}), 256);
         break;
