@@ -304,14 +304,18 @@ typedef struct {
 int fr_batch_create(int32_t n, fr_ctx *const *ctx, uint32_t flags, fr_batch **out);
 int fr_batch_set_stream(fr_batch *batch, void *hip_stream);
 
-/* Render every instance: params[n], seeds[n] (host), spp[n] (host, each
- * with W*H*spp <= FR_CHUNK_MAX), out[n] image pointers (host array of
- * device pointers, [H][W][3] each).  A new set of spp values reallocates
- * scratch and synchronises; the same set again does not.  Errors: FR_EINVAL
- * (null or out-of-range arguments, a context on another stream), FR_ESTATE
- * (new spp values during graph capture), FR_ENOMEM.  A call after new spp
- * values or a changed launch (fr_batch_set_launch) first waits for the
- * batch's enqueued work, which reads the tables it rewrites. */
+/* Render every instance: params[n], seeds[n] (host), spp[n] (host, 1..4096),
+ * out[n] image pointers (host array of device pointers, [H][W][3] each).
+ * Instances with W*H*spp <= FR_CHUNK_MAX share one launch per kernel kind;
+ * a larger one (high spp) runs its context's own fr_render after them, on
+ * the same stream, and fr_batch_backward its fr_backward (chunked, records
+ * recomputed), with the same results as those calls.  A new set of spp
+ * values reallocates scratch and synchronises; the same set again does
+ * not.  Errors: FR_EINVAL (null or out-of-range arguments, a context on
+ * another stream), FR_ESTATE (new spp values during graph capture),
+ * FR_ENOMEM.  A call after new spp values or a changed launch
+ * (fr_batch_set_launch) first waits for the batch's enqueued work, which
+ * reads the tables it rewrites. */
 int fr_batch_render(fr_batch *batch, const fr_params *params, const uint64_t *seeds, const int32_t *spp,
                     float *const *out);
 
@@ -330,7 +334,8 @@ int fr_batch_set_launch(fr_batch *batch, int32_t kind, const fr_launch *launch);
 
 /* Autotuner: replays the last fr_batch_render + fr_batch_backward (same
  * inputs and outputs, which the caller keeps alive; the outputs are written
- * again with the same values up to atomics order) and picks the launches
+ * again with the same values up to atomics order; instances above one
+ * chunk, which no batched launch holds, are left out) and picks the launches
  * by coordinate descent on the whole replay's time: each tunable kind in
  * turn tries its candidates ('trials' replays each, 1..16, median) with the
  * other kinds at their current choice and keeps the fastest.  ms_best

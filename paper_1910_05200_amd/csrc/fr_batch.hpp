@@ -303,6 +303,7 @@ struct fr_batch {
     std::vector<InstDyn> dyn;             // mirror of the per-call part
     std::vector<int> spp;                 // configured sample counts (empty: none)
     std::vector<long long> N;
+    std::vector<char> solo;               // instances above one chunk: their context's own path
     std::vector<int> order;               // slots: instances by decreasing N
     std::vector<uint64_t> gen;            // contexts' render generations after the last batch render
     fr_launch launch[bkNum];
@@ -354,6 +355,7 @@ static void kind_grid(const fr_batch *b, int k, int i, int &gx, int &gy) {
     const int rows = c->n_id + c->n_exp + c->n_alb + 12;
     const int ts = b->launch[k].tile;
     gy = 1;
+    if (b->solo[i]) { gx = 0; return; }      // no tiles: rendered on its own
     switch (k) {
     case bkBlend: gx = (int)nblk(V, 64); gy = 6; break;
     case bkPose: case bkNormals: case bkNormalAdj: case bkChainGather: gx = (int)nblk(V, 256); break;
@@ -551,10 +553,17 @@ static int configure(fr_batch *b, const int32_t *spp) {
     b->N.resize(b->n);
     b->host.resize(b->n);
     b->lds_res2 = b->lds_adj = 0;
+    b->solo.assign(b->n, 0);
     for (int i = 0; i < b->n; ++i) {
         fr_ctx *c = b->ctx[i];
         const long long N = (long long)c->W * c->H * spp[i];
         b->N[i] = N;
+        Inst &I = b->host[i];
+        memset(&I, 0, sizeof I);
+        if (N > FR_CHUNK_MAX) {      // its own path sizes its scratch on its first render
+            b->solo[i] = 1;
+            continue;
+        }
         if ((size_t)N * 3 > c->samples_cap) {
             if (c->samples) (void)hipFree(c->samples);
             c->samples = nullptr; c->samples_cap = 0;
@@ -584,8 +593,6 @@ static int configure(fr_batch *b, const int32_t *spp) {
         }
         c->records_valid = false;
         c->have_render = false;
-        Inst &I = b->host[i];
-        memset(&I, 0, sizeof I);
         I.S = make_scene(c);
         I.n_id = c->n_id; I.n_exp = c->n_exp; I.n_alb = c->n_alb;
         I.nchunks = c->nchunks; I.chunk = c->chunk; I.M = c->W * c->H;
@@ -617,6 +624,22 @@ static int configure(fr_batch *b, const int32_t *spp) {
     b->plan_dirty = true;
     b->have_render = b->have_backward = false;
     return FR_OK;
+}
+
+// An instance above one chunk (W*H*spp > FR_CHUNK_MAX) goes through its
+// context's own render or adjoint on the batch's stream, after the batched
+// kinds: chunk by chunk, the adjoint recomputing each chunk's records.  Its
+// scratch is sized by its first render, so a capture after that allocates
+// nothing; inside a capture its timing events are left out, since a graph
+// keeps no timing.
+template <class F>
+static int solo_call(fr_batch *b, int i, F f) {
+    fr_ctx *c = b->ctx[i];
+    const uint32_t flags = c->flags;
+    if (b->capturing) c->flags &= ~FR_TIMING;
+    const int r = f(c);
+    c->flags = flags;
+    return r ? bfail(b, r, "instance %d: %s", i, c->err.c_str()) : FR_OK;
 }
 
 extern "C" {
@@ -700,8 +723,8 @@ int fr_batch_render(fr_batch *b, const fr_params *params, const uint64_t *seeds,
             return bfail(b, FR_EINVAL, "fr_batch_render: null argument of instance %d", i);
         if (spp[i] < 1 || spp[i] > 4096)
             return bfail(b, FR_EINVAL, "fr_batch_render: instance %d: spp %d out of [1, 4096]", i, spp[i]);
-        if ((long long)c->W * c->H * spp[i] > FR_CHUNK_MAX)
-            return bfail(b, FR_EINVAL, "fr_batch_render: instance %d: W*H*spp above %d", i, FR_CHUNK_MAX);
+        if ((long long)c->W * c->H * spp[i] > (1ll << 31) - 1)
+            return bfail(b, FR_EINVAL, "fr_batch_render: instance %d: W*H*spp too large", i);
         for (int k = 0; k < 6; ++k)
             if (!std::isfinite(p->pose[k]))
                 return bfail(b, FR_EINVAL, "fr_batch_render: instance %d: non-finite pose[%d]", i, k);
@@ -710,6 +733,7 @@ int fr_batch_render(fr_batch *b, const fr_params *params, const uint64_t *seeds,
     }
     bool stale = b->spp.empty() || !std::equal(b->spp.begin(), b->spp.end(), spp);
     for (int i = 0; i < b->n && !stale; ++i) {   // a context's own render may have moved its scratch
+        if (b->solo[i]) continue;
         const fr_ctx *c = b->ctx[i];
         const Inst &I = b->host[i];
         stale = c->hits != I.hits || c->vis != I.vis || c->samples != I.samples || c->sec_list != I.sec_list ||
@@ -735,6 +759,7 @@ int fr_batch_render(fr_batch *b, const fr_params *params, const uint64_t *seeds,
         drotation(p->pose, d.D.dR);
         d.alpha = p->alpha; d.beta = p->beta; d.delta = p->delta; d.lights = p->lights; d.spec = p->spec;
         d.img = out[i];
+        if (b->solo[i]) continue;     // its own render sets its state
         // the context's own state, so that fr_backward / fr_aov on it follow this render
         c->last = *p;
         c->last_seed = seeds[i];
@@ -747,10 +772,16 @@ int fr_batch_render(fr_batch *b, const fr_params *params, const uint64_t *seeds,
     if (tm) (void)hipEventRecord(b->ev[2 * bkNum], b->stream);
     put_dyn(b);
     seq_forward(b);
+    for (int i = 0; i < b->n; ++i) {
+        if (!b->solo[i]) continue;
+        const int r = solo_call(b, i, [&](fr_ctx *c) { return render_call(c, &params[i], seeds[i], spp[i], out[i]); });
+        if (r) return r;
+    }
     if (tm) (void)hipEventRecord(b->ev[2 * bkNum + 1], b->stream);
     BHIPCK(b, hipGetLastError());
     for (int i = 0; i < b->n; ++i) {
         fr_ctx *c = b->ctx[i];
+        if (b->solo[i]) { b->gen[i] = c->gen; continue; }
         c->records_valid = true;
         c->have_render = true;
         c->have_backward = false;
@@ -784,6 +815,11 @@ int fr_batch_backward(fr_batch *b, const float *const *dLdI, const fr_grads *gra
     if (tm) (void)hipEventRecord(b->ev[2 * bkNum + 2], b->stream);
     put_dyn(b);
     seq_backward(b);
+    for (int i = 0; i < b->n; ++i) {
+        if (!b->solo[i]) continue;
+        const int r = solo_call(b, i, [&](fr_ctx *c) { return backward_call(c, dLdI[i], &grads[i]); });
+        if (r) return r;
+    }
     if (tm) (void)hipEventRecord(b->ev[2 * bkNum + 3], b->stream);
     BHIPCK(b, hipGetLastError());
     for (fr_ctx *c : b->ctx) c->have_backward = true;

@@ -336,14 +336,6 @@ def test_batch_errors(torch):
     with pytest.raises(facert.FrError) as e:
         batch.render(ps, seeds, [1, 1, 1, 1, 1, 4097])
     assert e.value.code == -1
-    m, sc, p, _ = inst[0]
-    big = synth.make_scene(64, 64)
-    big.light_geom = sc.light_geom
-    rb = facert.Renderer(m, big)
-    b2 = facert.Batch([rb])
-    with pytest.raises(facert.FrError) as e:       # 64 x 64 x 1025 samples > FR_CHUNK_MAX
-        b2.render([ps[0]], [1], [1025])
-    assert e.value.code == -1
     for bad in [(0, 300), (0, 1024), (2, 512), (-1, 256)]:
         with pytest.raises(facert.FrError):
             batch.set_launch("edge_secondary", *bad)
@@ -365,6 +357,95 @@ def test_batch_errors(torch):
     assert e.value.code == -4
     lib = facert.load()
     assert lib.fr_batch_render(batch.b, None, None, None, None) == -1
+
+
+def _with_big(torch):
+    """Three small instances and one of 64 x 64 at 1,100 spp (4,505,600
+    camera samples, above one chunk)."""
+    inst = _small()[:3]
+    model = synth.make_model(14, 12, seed=31)
+    scene = synth.make_scene(64, 64)
+    scene.light_geom = synth.light_stage(20)
+    inst.insert(1, (model, scene, synth.make_params(91, n_lights=20), 1100))
+    return inst
+
+
+def test_batch_instance_above_one_chunk(torch):
+    """An instance with more camera samples than one chunk goes through its
+    context's own chunked render and recomputing adjoint inside the batch:
+    its image equals fr_render's bit for bit and its gradients
+    fr_backward's; the batched instances beside it are unaffected, also
+    after autotuning (which leaves it out)."""
+    from paper_1910_05200_amd import facert
+    inst = _with_big(torch)
+    assert 64 * 64 * 1100 > facert.FR_CHUNK_MAX
+    rs, ps, batch = _setup(torch, inst, timing=True)
+    seeds = [8000 + i for i in range(len(inst))]
+    spps = [spp for *_, spp in inst]
+    dls = _dls(torch, inst, seed=5)
+    for tuned in (False, True):
+        imgs = [x.cpu().numpy() for x in batch.render(ps, seeds, spps)]
+        gb = [_np(g) for g in batch.backward(dls)]
+        t = batch.timing()
+        assert t["render"] > 0 and t["backward"] > 0
+        for i, r in enumerate(rs):
+            ref = r.render(ps[i], seeds[i], spps[i]).cpu().numpy()
+            assert (ref.sum(-1) > 0).mean() > 0.1
+            assert np.array_equal(imgs[i], ref), f"tuned={tuned} instance {i}"
+            _assert_grads_close(gb[i], _np(r.backward(dls[i])), f"tuned={tuned} instance {i}")
+        if not tuned:
+            batch.render(ps, seeds, spps)
+            batch.backward(dls)
+            batch.tune(trials=1)
+
+
+def test_batch_graph_with_instance_above_one_chunk(torch):
+    """The same batch captured in a HIP graph (the large instance's chunk
+    loop and its second-stream silhouette work included) and replayed
+    twice with eager work in between: each replay equals the eager run.
+    The large instance's context keeps timing events, which a capture must
+    leave out."""
+    from paper_1910_05200_amd import facert
+    inst = _with_big(torch)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        rs = [facert.Renderer(m, sc, timing=(spp > 64)) for m, sc, _, spp in inst]
+        ps = [facert.params_to_device(p) for _, _, p, _ in inst]
+        batch = facert.Batch(rs, timing=True)
+        seeds = [8100 + i for i in range(len(inst))]
+        spps = [spp for *_, spp in inst]
+        dls = _dls(torch, inst, seed=6)
+        imgs = [torch.empty((sc.height, sc.width, 3), device="cuda") for _, sc, _, _ in inst]
+        shapes = lambda r: {"d_lights": (r.n_lights, 3), "d_spec": (r.spec_res ** 2,), "d_vertices": (3, r.V),
+                            "d_albedo": (3, r.V), "d_alpha": (r.n_id,), "d_beta": (r.n_exp,),
+                            "d_delta": (r.n_alb,), "d_pose": (6,)}
+        grads = [{k: torch.empty(v, device="cuda") for k, v in shapes(r).items()} for r in rs]
+
+        def iteration():
+            batch.render(ps, seeds, spps, outs=imgs)
+            batch.backward(dls, outs=grads)
+
+        iteration()
+        s.synchronize()
+        eager_img = [x.cpu().numpy() for x in imgs]
+        eager_g = [_np(g) for g in grads]
+        batch.capture_begin()
+        iteration()
+        batch.capture_end()
+        for rep in range(2):
+            for x in imgs:
+                x.zero_()
+            for g in grads:
+                for v in g.values():
+                    v.fill_(7.0)
+            junk = torch.randn(1 << 16, device="cuda")
+            junk.mul_(2.0)
+            s.synchronize()
+            batch.graph_launch()
+            s.synchronize()
+            for i in range(len(inst)):
+                assert np.array_equal(imgs[i].cpu().numpy(), eager_img[i]), f"replay {rep} image {i}"
+                _assert_grads_close(_np(grads[i]), eager_g[i], f"replay {rep} instance {i}")
 
 
 def test_batch_full_workload_matches_single(torch):
