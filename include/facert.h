@@ -33,8 +33,9 @@
  *       outputs back and waits for the stream before it returns.
  *     Comments below say "device" for the first mode.
  *   - streams: all work is enqueued on the stream set with fr_set_stream
- *     (default: the null stream; fr_backward forks part of its work onto
- *     a second stream of the context's own and joins it back) and the calls
+ *     (default: the null stream; fr_render and fr_backward fork part of
+ *     their work onto a second stream of the context's own and join it
+ *     back) and the calls
  *     return without waiting, except fr_stats and fr_create, which
  *     synchronise.  One context must
  *     not be used from two host threads at once.
@@ -184,8 +185,10 @@ int fr_blend(fr_ctx *ctx, const float *alpha, const float *beta, const float *de
  * edge tables, then per pixel the mean over spp jittered camera samples of
  * the direct light from every light (one area sample and one shadow ray per
  * light per hit).  out_image [H][W][3] (device).  The realisation is fixed by
- * (params, seed, spp) and bitwise reproducible.  Errors: FR_EINVAL (spp < 1
- * or > 4096, null pointers). */
+ * (params, seed, spp) and bitwise reproducible.  The BVH is built on the
+ * context's second stream, beside the camera step, the shadow-ray
+ * proposals and the edge tables, and joined before the first shadow ray.
+ * Errors: FR_EINVAL (spp < 1 or > 4096, null pointers). */
 int fr_render(fr_ctx *ctx, const fr_params *params, uint64_t seed, int32_t spp,
               float *out_image);
 

@@ -2416,11 +2416,12 @@ static void ev_record(fr_ctx *c, int i);
 // ev0, ev1 (when >= 0) bracket the trace kernel, which holds all the
 // traversal work
 static void shadow_pass(fr_ctx *c, const Scene &S, uint64_t seed, long long s0, long long n, unsigned long long *ctr,
-                        int ev0 = -1, int ev1 = -1) {
+                        int ev0 = -1, int ev1 = -1, hipEvent_t tree = nullptr) {
     const uint32_t qcap = (uint32_t)c->sh_cap;   // >= n: fr_render sized it for this chunk size
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, c->stream, c->sh_cnt, c->nl);
     hipLaunchKernelGGL(k_sh_propose, dim3(nblk(n, 256)), dim3(256), 0, c->stream, S, seed, s0, n, c->hits,
                        c->sh_queue, qcap, c->sh_cnt, ctr);
+    if (tree) (void)hipStreamWaitEvent(c->stream, tree, 0);   // the tree, built on the second stream
     if (ev0 >= 0) ev_record(c, ev0);
     hipLaunchKernelGGL(k_sh_trace, dim3(nblk(n, kTraceBlock), c->nl), dim3(kTraceBlock), 0, c->stream, S, seed, s0, c->hits,
                        c->sh_queue, qcap, c->sh_cnt, c->vis, ctr);
@@ -2634,32 +2635,32 @@ int fr_set_terms(fr_ctx *c, uint32_t terms) {
     return FR_OK;
 }
 
-static void lbvh_build(fr_ctx *c) {
+static void lbvh_build(fr_ctx *c, hipStream_t st) {
     const int F = c->F, nb = c->lb.nb;
     LbvhBufs &L = c->lb;
-    hipLaunchKernelGGL(k_lbvh_bounds_init, dim3(1), dim3(64), 0, c->stream, L.bounds);
-    hipLaunchKernelGGL(k_lbvh_bounds, dim3(nblk(F, 256)), dim3(256), 0, c->stream, F, c->pos, c->V, c->faces, L.bounds);
-    hipLaunchKernelGGL(k_lbvh_morton, dim3(nblk(F, 256)), dim3(256), 0, c->stream, F, c->pos, c->V, c->faces, L.bounds,
+    hipLaunchKernelGGL(k_lbvh_bounds_init, dim3(1), dim3(64), 0, st, L.bounds);
+    hipLaunchKernelGGL(k_lbvh_bounds, dim3(nblk(F, 256)), dim3(256), 0, st, F, c->pos, c->V, c->faces, L.bounds);
+    hipLaunchKernelGGL(k_lbvh_morton, dim3(nblk(F, 256)), dim3(256), 0, st, F, c->pos, c->V, c->faces, L.bounds,
                        L.key[0], L.val[0]);
     for (int pass = 0; pass < 4; ++pass) {
         int in = pass & 1, out = in ^ 1;
-        hipLaunchKernelGGL(k_sort_hist, dim3(nb), dim3(256), 0, c->stream, F, 8 * pass, L.key[in], L.hist, nb);
-        hipLaunchKernelGGL(k_scan_u32, dim3(1), dim3(1024), 0, c->stream, 256 * nb, L.hist);
-        hipLaunchKernelGGL(k_sort_scatter, dim3(nb), dim3(256), 0, c->stream, F, 8 * pass, L.key[in], L.val[in], L.hist,
+        hipLaunchKernelGGL(k_sort_hist, dim3(nb), dim3(256), 0, st, F, 8 * pass, L.key[in], L.hist, nb);
+        hipLaunchKernelGGL(k_scan_u32, dim3(1), dim3(1024), 0, st, 256 * nb, L.hist);
+        hipLaunchKernelGGL(k_sort_scatter, dim3(nb), dim3(256), 0, st, F, 8 * pass, L.key[in], L.val[in], L.hist,
                            nb, L.key[out], L.val[out]);
     }
-    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, c->stream, (unsigned int *)L.n_top, 1);
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, (unsigned int *)L.n_top, 1);
     if (F > 1)
-        hipLaunchKernelGGL(k_lbvh_karras, dim3(nblk(F - 1, 256)), dim3(256), 0, c->stream, F, L.key[0], L.child,
+        hipLaunchKernelGGL(k_lbvh_karras, dim3(nblk(F - 1, 256)), dim3(256), 0, st, F, L.key[0], L.child,
                            L.parent, L.first, L.last, L.top_idx, L.n_top);
-    hipLaunchKernelGGL(k_lbvh_layout, dim3(nblk(2 * (size_t)F - 1, 256)), dim3(256), 0, c->stream, F, L.child, L.parent,
+    hipLaunchKernelGGL(k_lbvh_layout, dim3(nblk(2 * (size_t)F - 1, 256)), dim3(256), 0, st, F, L.child, L.parent,
                        L.first, L.pre);
-    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, c->stream, (unsigned int *)L.n_roots, 1);
-    hipLaunchKernelGGL(k_lbvh_boxes, dim3(nblk(F, kBoxTile)), dim3(kBoxTile), 0, c->stream, F, c->faces, c->pos, c->V,
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, (unsigned int *)L.n_roots, 1);
+    hipLaunchKernelGGL(k_lbvh_boxes, dim3(nblk(F, kBoxTile)), dim3(kBoxTile), 0, st, F, c->faces, c->pos, c->V,
                        L.val[0], L.child, L.parent, L.first, L.last, L.pre, L.box, c->nodes, c->tris,
                        L.roots, L.n_roots);
     if (F > 1)
-        hipLaunchKernelGGL(k_lbvh_boxes_top, dim3(1), dim3(1024), 0, c->stream, F, L.child, L.parent, L.first, L.last,
+        hipLaunchKernelGGL(k_lbvh_boxes_top, dim3(1), dim3(1024), 0, st, F, L.child, L.parent, L.first, L.last,
                            L.pre, L.top_idx, L.arrive, L.box, c->nodes, L.roots, L.n_roots);
 }
 
@@ -2750,16 +2751,24 @@ static int render_call(fr_ctx *c, const fr_params *p, uint64_t seed, int32_t spp
     int r = blend_impl(c, p->alpha, p->beta, p->delta, p->pose);
     if (r) return r;
     ev_record(c, 1);
+    // The tree is built on the context's second stream.  Only the shadow
+    // rays read it: the screen-space camera step, the shadow-ray proposals
+    // and the edge tables run beside the build on the context's stream,
+    // which waits for it before the first shadow-ray trace.
+    (void)hipEventRecord(c->fork_ev, c->stream);
+    (void)hipStreamWaitEvent(c->side, c->fork_ev, 0);
     if (!(c->flags & FR_REFIT)) {
-        lbvh_build(c);
+        lbvh_build(c, c->side);
     } else {
-        hipLaunchKernelGGL(k_refit_sub, dim3(c->n_subs), dim3(256), 0, c->stream, c->subs, c->faces, c->pos, c->V,
+        hipLaunchKernelGGL(k_refit_sub, dim3(c->n_subs), dim3(256), 0, c->side, c->subs, c->faces, c->pos, c->V,
                            c->sorted_tri, c->leaf_node, c->height, c->right, c->escape, c->nodes, c->tris);
         if (c->n_top > 0)
-            hipLaunchKernelGGL(k_refit_top, dim3(1), dim3(256), 0, c->stream, c->n_top, c->top, c->top_off,
+            hipLaunchKernelGGL(k_refit_top, dim3(1), dim3(256), 0, c->side, c->n_top, c->top, c->top_off,
                                c->top_levels, c->right, c->escape, c->nodes);
     }
-    ev_record(c, 2);
+    if (c->flags & FR_TIMING) (void)hipEventRecord(c->ev[2], c->side);
+    (void)hipEventRecord(c->join_ev, c->side);
+    ev_record(c, 7);
     Scene S = make_scene(c);
     hipLaunchKernelGGL(k_edge_weights, dim3(nblk(c->E, 256)), dim3(256), 0, c->stream, S, c->lgeom, c->ew, c->edge_rec,
                        c->edge_pl);
@@ -2781,7 +2790,8 @@ static int render_call(fr_ctx *c, const fr_params *p, uint64_t seed, int32_t spp
         ev_record(c, 8 + 2 * kKernCamera);
         camera_pass(c, S, seed, spp, s0, n, c->ctr + kCtrPerKern * kKernCamera);
         ev_record(c, 9 + 2 * kKernCamera);
-        shadow_pass(c, S, seed, s0, n, c->ctr + kCtrPerKern * kKernShadow, 8 + 2 * kKernShadow, 9 + 2 * kKernShadow);
+        shadow_pass(c, S, seed, s0, n, c->ctr + kCtrPerKern * kKernShadow, 8 + 2 * kKernShadow, 9 + 2 * kKernShadow,
+                    s0 == 0 ? c->join_ev : nullptr);
         ev_record(c, 8 + 2 * kKernShade);
         hipLaunchKernelGGL(k_fwd_shade, dim3(nblk(n, 256)), dim3(256), lds, c->stream, S, seed, spp, s0, n,
                            c->hits, c->vis, c->samples, c->ctr + kCtrPerKern * kKernShade);
@@ -3079,7 +3089,7 @@ int fr_stats(const fr_ctx *cc, fr_stats_t *out) {
         // events of a phase that has not run since the last render are not queried
         if (hipEventElapsedTime(&t, c->ev[0], c->ev[1]) == hipSuccess) out->ms_blend = t;
         if (hipEventElapsedTime(&t, c->ev[1], c->ev[2]) == hipSuccess) out->ms_bvh = t;
-        if (hipEventElapsedTime(&t, c->ev[2], c->ev[3]) == hipSuccess) out->ms_edges = t;
+        if (hipEventElapsedTime(&t, c->ev[7], c->ev[3]) == hipSuccess) out->ms_edges = t;
         if (hipEventElapsedTime(&t, c->ev[3], c->ev[4]) == hipSuccess) out->ms_render = t;
         for (int k = 0; k < kKernAdj; ++k)
             if (hipEventElapsedTime(&t, c->ev[8 + 2 * k], c->ev[9 + 2 * k]) == hipSuccess) out->ms_kernel[k] = t;
