@@ -2072,6 +2072,8 @@ struct fr_ctx {
     std::string err;
     hipStream_t stream = nullptr;
     hipStream_t side = nullptr;           // the camera-silhouette term's stream (fr_backward)
+    hipStream_t side2 = nullptr;          // the shadow-boundary term's stream (fr_backward)
+    hipEvent_t fork2_ev = nullptr, join2_ev = nullptr;
     hipEvent_t fork_ev = nullptr, join_ev = nullptr;
     uint32_t flags = 0, terms = FR_TERM_INTERIOR | FR_TERM_PRIMARY | FR_TERM_SECONDARY;
     int device = 0;
@@ -2607,8 +2609,11 @@ int fr_create(const fr_model_desc *m, const fr_scene_desc *s, uint32_t flags, fr
     if (flags & FR_TIMING)
         for (int i = 0; i < kNumEvents; ++i) (void)hipEventCreate(&c->ev[i]);
     if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
+        hipStreamCreateWithFlags(&c->side2, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&c->join_ev, hipEventDisableTiming) != hipSuccess) {
+        hipEventCreateWithFlags(&c->join_ev, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->fork2_ev, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->join2_ev, hipEventDisableTiming) != hipSuccess) {
         fr_destroy(c);
         return FR_EDEVICE;
     }
@@ -2882,23 +2887,38 @@ static int backward_call(fr_ctx *c, const float *dLdI, const fr_grads *g) {
             camera_pass(c, S, c->last_seed, c->last_spp, s0, n, c->ctr + kCtrPerKern * kKernAdj);
             shadow_pass(c, S, c->last_seed, s0, n, c->ctr + kCtrPerKern * kKernAdj);
         }
+        // The shadow-boundary term, bound by the latency of its dependent
+        // loads, runs on a third stream beside the interior adjoint, which is
+        // bound by its arithmetic; both read this chunk's records and add
+        // into the gradients with atomics.  The context's stream waits for
+        // it before the next chunk's records replace these.
+        const bool sec = (c->terms & FR_TERM_SECONDARY) != 0, third = sec && (c->terms & FR_TERM_INTERIOR);
+        const hipStream_t st2 = third ? c->side2 : c->stream;
+        if (third) {
+            (void)hipEventRecord(c->fork2_ev, c->stream);
+            (void)hipStreamWaitEvent(c->side2, c->fork2_ev, 0);
+        }
+        if (c->flags & FR_TIMING) (void)hipEventRecord(c->ev[8 + 2 * kKernSecondary], st2);
+        if (sec)
+            for (long long o = 0; o < n; o += kSecSub) {
+                long long m = std::min(kSecSub, n - o);
+                hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st2, c->sec_n, 1);
+                hipLaunchKernelGGL(k_edge_secondary, dim3(nblk(m, kSecTile), c->nl), dim3(256), 0, st2, S,
+                                   c->last_seed, c->last_spp, s0 + o, m, dLdI, c->hits + o, c->sec_list, c->sec_n,
+                                   c->ctr + kCtrPerKern * kKernSecondary);
+                hipLaunchKernelGGL(k_edge_secondary_value, dim3(1024), dim3(256), lds1, st2, S, c->last_seed,
+                                   c->last_spp, s0 + o, dLdI, c->hits + o, c->sec_list, c->sec_n, c->g_pos);
+            }
+        if (c->flags & FR_TIMING) (void)hipEventRecord(c->ev[9 + 2 * kKernSecondary], st2);
         ev_record(c, 8 + 2 * kKernAdj);
         if (c->terms & FR_TERM_INTERIOR)
             hipLaunchKernelGGL(k_render_adj, dim3(nblk(n, 256)), dim3(256), lds, c->stream, S, c->last_seed,
                                c->last_spp, s0, n, dLdI, G, c->hits, c->vis, c->ctr + kCtrPerKern * kKernAdj);
         ev_record(c, 9 + 2 * kKernAdj);
-        ev_record(c, 8 + 2 * kKernSecondary);
-        if (c->terms & FR_TERM_SECONDARY)
-            for (long long o = 0; o < n; o += kSecSub) {
-                long long m = std::min(kSecSub, n - o);
-                hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, c->stream, c->sec_n, 1);
-                hipLaunchKernelGGL(k_edge_secondary, dim3(nblk(m, kSecTile), c->nl), dim3(256), 0, c->stream, S,
-                                   c->last_seed, c->last_spp, s0 + o, m, dLdI, c->hits + o, c->sec_list, c->sec_n,
-                                   c->ctr + kCtrPerKern * kKernSecondary);
-                hipLaunchKernelGGL(k_edge_secondary_value, dim3(1024), dim3(256), lds1, c->stream, S, c->last_seed,
-                                   c->last_spp, s0 + o, dLdI, c->hits + o, c->sec_list, c->sec_n, c->g_pos);
-            }
-        ev_record(c, 9 + 2 * kKernSecondary);
+        if (third) {
+            (void)hipEventRecord(c->join2_ev, c->side2);
+            (void)hipStreamWaitEvent(c->stream, c->join2_ev, 0);
+        }
     }
     if (side) (void)hipStreamWaitEvent(c->stream, c->join_ev, 0);
     hipLaunchKernelGGL(k_normal_adj, dim3(nblk(c->V, 256)), dim3(256), 0, c->stream, c->V, c->nrm, c->nlen, c->g_nrm, c->g_N);
@@ -3164,6 +3184,8 @@ const char *fr_last_error(const fr_ctx *c) {
 void fr_destroy(fr_ctx *c) {
     if (!c) return;
     if (c->stream) (void)hipStreamSynchronize(c->stream); else (void)hipDeviceSynchronize();
+    if (c->side) (void)hipStreamSynchronize(c->side);
+    if (c->side2) (void)hipStreamSynchronize(c->side2);
     void *ptrs[] = {c->faces, c->edges, c->vf_off, c->vf_idx, c->mean, c->b_id, c->b_exp, c->alb_mean, c->b_alb, c->uv,
                     c->lgeom, c->sorted_tri, c->leaf_node, c->right, c->escape, c->subs, c->height, c->top, c->top_off, c->nodes, c->tris,
                     c->vmodel, c->vm_d, c->pos, c->nrm, c->nlen, c->alb, c->ew, c->tbl_edge, c->tbl_prefix, c->tbl_n,
@@ -3175,9 +3197,10 @@ void fr_destroy(fr_ctx *c) {
     for (auto &b : c->io_buf) if (b.first) (void)hipFree(b.first);
     for (auto &b : c->par_buf) if (b.first) (void)hipFree(b.first);
     for (auto &e : c->ev) if (e) (void)hipEventDestroy(e);
-    if (c->side) { (void)hipStreamSynchronize(c->side); (void)hipStreamDestroy(c->side); }
-    if (c->fork_ev) (void)hipEventDestroy(c->fork_ev);
-    if (c->join_ev) (void)hipEventDestroy(c->join_ev);
+    if (c->side) (void)hipStreamDestroy(c->side);
+    if (c->side2) (void)hipStreamDestroy(c->side2);
+    for (hipEvent_t e : {c->fork_ev, c->join_ev, c->fork2_ev, c->join2_ev})
+        if (e) (void)hipEventDestroy(e);
     delete c;
 }
 
