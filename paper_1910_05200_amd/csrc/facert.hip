@@ -2591,7 +2591,7 @@ int fr_create(const fr_model_desc *m, const fr_scene_desc *s, uint32_t flags, fr
             dalloc(c, &L.parent, 2 * (size_t)F) || dalloc(c, &L.first, (size_t)F) || dalloc(c, &L.last, (size_t)F) ||
             dalloc(c, &L.pre, 2 * (size_t)F) || dalloc(c, &L.arrive, (size_t)F) || dalloc(c, &L.box, 12 * (size_t)F) ||
             dalloc(c, &L.roots, (size_t)F) || dalloc(c, &L.n_roots, 1) || dalloc(c, &L.top_idx, (size_t)F) ||
-            dalloc(c, &L.n_top, 1)) {
+            dalloc(c, &L.n_top, 1) || dalloc(c, &L.top_node, (size_t)F)) {
             fr_destroy(c);
             return FR_ENOMEM;
         }
@@ -2657,7 +2657,7 @@ static void lbvh_build(fr_ctx *c, hipStream_t st) {
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, (unsigned int *)L.n_top, 1);
     if (F > 1)
         hipLaunchKernelGGL(k_lbvh_karras, dim3(nblk(F - 1, 256)), dim3(256), 0, st, F, L.key[0], L.child,
-                           L.parent, L.first, L.last, L.top_idx, L.n_top);
+                           L.parent, L.first, L.last, L.top_idx, L.n_top, L.top_node);
     hipLaunchKernelGGL(k_lbvh_layout, dim3(nblk(2 * (size_t)F - 1, 256)), dim3(256), 0, st, F, L.child, L.parent,
                        L.first, L.pre);
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, (unsigned int *)L.n_roots, 1);
@@ -2666,7 +2666,7 @@ static void lbvh_build(fr_ctx *c, hipStream_t st) {
                        L.roots, L.n_roots);
     if (F > 1)
         hipLaunchKernelGGL(k_lbvh_boxes_top, dim3(1), dim3(1024), 0, st, F, L.child, L.parent, L.first, L.last,
-                           L.pre, L.top_idx, L.arrive, L.box, c->nodes, L.roots, L.n_roots);
+                           L.pre, L.top_idx, L.top_node, L.n_top, L.arrive, L.box, c->nodes, L.roots, L.n_roots);
 }
 
 static int blend_impl(fr_ctx *c, const float *alpha, const float *beta, const float *delta, const float *pose) {
@@ -3192,7 +3192,7 @@ void fr_destroy(fr_ctx *c) {
                     c->tbl_Q, c->tbl_guide, c->es_wmax, c->es_csum, c->es_ccnt, c->edge_rec, c->edge_pl, c->geo_R, c->samples, c->ctr, c->g_light, c->g_spec, c->g_pos, c->g_nrm, c->g_alb, c->g_N,
                     c->g_vert, c->g_m, c->partial, c->loss_partial, c->hits, c->vis, c->sh_queue, c->sh_cnt, c->pe_q, c->pe_cell_n, c->pe_rec, c->sec_list, c->sec_n, c->pe_samples, c->pe_hits,
                     c->pe_f, c->pe_vis, c->pv_queue, c->pv_aux, c->pv_perm, c->lb.key[0], c->lb.key[1], c->lb.val[0], c->lb.val[1], c->lb.hist,
-                    c->lb.bounds, c->lb.child, c->lb.parent, c->lb.first, c->lb.last, c->lb.pre, c->lb.arrive, c->lb.box, c->lb.roots, c->lb.n_roots, c->lb.top_idx, c->lb.n_top};
+                    c->lb.bounds, c->lb.child, c->lb.parent, c->lb.first, c->lb.last, c->lb.pre, c->lb.arrive, c->lb.box, c->lb.roots, c->lb.n_roots, c->lb.top_idx, c->lb.n_top, c->lb.top_node};
     for (void *p : ptrs) if (p) (void)hipFree(p);
     for (auto &b : c->io_buf) if (b.first) (void)hipFree(b.first);
     for (auto &b : c->par_buf) if (b.first) (void)hipFree(b.first);

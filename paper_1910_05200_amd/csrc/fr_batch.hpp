@@ -132,7 +132,8 @@ FR_KIND(KSortScatter, 256) {
                       I.lb.val[in ^ 1], bx);
 }};
 FR_KIND(KKarras, 256) {
-    lbvh_karras_body(I.S.F, I.lb.key[0], I.lb.child, I.lb.parent, I.lb.first, I.lb.last, I.lb.top_idx, I.lb.n_top, bx);
+    lbvh_karras_body(I.S.F, I.lb.key[0], I.lb.child, I.lb.parent, I.lb.first, I.lb.last, I.lb.top_idx, I.lb.n_top,
+                     I.lb.top_node, bx);
 }};
 FR_KIND(KLayout, 256) { lbvh_layout_body(I.S.F, I.lb.child, I.lb.parent, I.lb.first, I.lb.pre, bx); }};
 FR_KIND(KBoxes, kBoxTile) {
@@ -140,8 +141,8 @@ FR_KIND(KBoxes, kBoxTile) {
                     I.lb.pre, I.lb.box, I.nodes, I.tris, I.lb.roots, I.lb.n_roots, bx);
 }};
 FR_KIND(KBoxesTop, 1024) {
-    lbvh_boxes_top_body(I.S.F, I.lb.child, I.lb.parent, I.lb.first, I.lb.last, I.lb.pre, I.lb.top_idx, I.lb.arrive,
-                        I.lb.box, I.nodes, I.lb.roots, I.lb.n_roots);
+    lbvh_boxes_top_body(I.S.F, I.lb.child, I.lb.parent, I.lb.first, I.lb.last, I.lb.pre, I.lb.top_idx,
+                        I.lb.top_node, I.lb.n_top, I.lb.arrive, I.lb.box, I.nodes, I.lb.roots, I.lb.n_roots);
 }};
 FR_KIND(KEdgeWeights, 256) { edge_weights_body(I.S, I.S.lgeom, I.ew, I.edge_rec, I.edge_pl, bx); }};
 FR_KIND(KEdgeScan, 1024) {

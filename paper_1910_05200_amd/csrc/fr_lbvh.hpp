@@ -29,7 +29,8 @@
 // ray kernel is unchanged.
 
 constexpr int kBoxTile = 1024;      // sorted leaves per block of the box pass
-constexpr int kTopSlots = 8192;     // LDS arrival counters of the top pass
+constexpr int kTopSlots = 8192;     // LDS arrival counters of the top pass (global-memory climb)
+constexpr int kTopFast = 2048;      // spanning nodes climbed in LDS (128 KiB)
 
 struct LbvhBufs {
     uint32_t *key[2]; int *val[2];      // sort ping-pong
@@ -43,6 +44,7 @@ struct LbvhBufs {
     float *box;                         // [2F-1][6]
     int *roots, *n_roots;               // nodes whose parent spans box tiles
     int *top_idx, *n_top;               // [F-1] LDS slot of a node spanning tiles, or -1
+    int *top_node;                      // [F-1] node of each such slot
 };
 
 __device__ __forceinline__ unsigned int f2ord(float f) {
@@ -218,7 +220,7 @@ __device__ __forceinline__ int lbvh_delta(const uint32_t *key, int F, int i, int
 
 __device__ __forceinline__ void lbvh_karras_body(int F, const uint32_t *__restrict__ key, int *__restrict__ child,
         int *__restrict__ parent, int *__restrict__ first, int *__restrict__ last, int *__restrict__ top_idx,
-        int *__restrict__ n_top, int bx) {
+        int *__restrict__ n_top, int *__restrict__ top_node, int bx) {
     int i = bx * blockDim.x + threadIdx.x;
     if (i >= F - 1) return;
     int d = lbvh_delta(key, F, i, i + 1) > lbvh_delta(key, F, i, i - 1) ? 1 : -1;
@@ -246,13 +248,18 @@ __device__ __forceinline__ void lbvh_karras_body(int F, const uint32_t *__restri
     parent[cr] = i;
     first[i] = lo;
     last[i] = hi;
-    top_idx[i] = lo / kBoxTile != hi / kBoxTile ? atomicAdd(n_top, 1) : -1;
+    int slot = -1;
+    if (lo / kBoxTile != hi / kBoxTile) {
+        slot = atomicAdd(n_top, 1);   // at most F - 1 nodes
+        top_node[slot] = i;
+    }
+    top_idx[i] = slot;
     if (i == 0) parent[0] = -1;
 }
 __global__ __launch_bounds__(256) void k_lbvh_karras(int F, const uint32_t *__restrict__ key, int *__restrict__ child,
         int *__restrict__ parent, int *__restrict__ first, int *__restrict__ last, int *__restrict__ top_idx,
-        int *__restrict__ n_top) {
-    lbvh_karras_body(F, key, child, parent, first, last, top_idx, n_top, blockIdx.x);
+        int *__restrict__ n_top, int *__restrict__ top_node) {
+    lbvh_karras_body(F, key, child, parent, first, last, top_idx, n_top, top_node, blockIdx.x);
 }
 
 __device__ __forceinline__ void lbvh_layout_body(int F, const int *__restrict__ child, const int *__restrict__ parent,
@@ -278,8 +285,13 @@ __global__ __launch_bounds__(256) void k_lbvh_layout(int F, const int *__restric
 // range, so its arrival counter is an LDS word at (index - first leaf of
 // the block); workgroup-scope fences order the box writes.  The node where a
 // climb stops at a parent spanning blocks goes to a list.  Pass 2: one block
-// climbs from the listed nodes through the spanning nodes the same way, with
-// LDS counters at the slots k_lbvh_karras assigned (global ones, whose
+// climbs from the listed nodes through the spanning nodes the same way.
+// With at most kTopFast spanning nodes (every face mesh here) the climb runs
+// in LDS: each spanning node's slot (assigned by k_lbvh_karras) holds its two
+// child boxes, its parent's slot and its node's position and link, all
+// loaded at once before the climb, so a climb step costs LDS accesses only
+// instead of a chain of dependent global loads.  Past that, the boxes go
+// through global memory, with LDS counters at the slots (global ones, whose
 // parity needs no reset, past kTopSlots).
 __device__ __forceinline__ void lbvh_union_write(int F, int p, const int *child, const int *first, const int *last,
         const int *pre, float *box, Node *nodes) {
@@ -346,12 +358,54 @@ __global__ __launch_bounds__(kBoxTile) void k_lbvh_boxes(int F, const int *__res
 
 __device__ __forceinline__ void lbvh_boxes_top_body(int F, const int *__restrict__ child,
         const int *__restrict__ parent, const int *__restrict__ first, const int *__restrict__ last,
-        const int *__restrict__ pre, const int *__restrict__ top_idx, unsigned int *__restrict__ arrive, float *box,
-        Node *__restrict__ nodes, const int *__restrict__ roots, const int *__restrict__ n_roots) {
-    __shared__ unsigned int arr[kTopSlots];
+        const int *__restrict__ pre, const int *__restrict__ top_idx, const int *__restrict__ top_node,
+        const int *__restrict__ n_top, unsigned int *__restrict__ arrive, float *box, Node *__restrict__ nodes,
+        const int *__restrict__ roots, const int *__restrict__ n_roots) {
+    __shared__ float4 smem[kTopFast * 4];
+    const int nt = *n_top, nr = *n_roots;
+    if (nt <= kTopFast) {
+        float *cb = (float *)smem;                          // [slot][2 children][6]
+        int *pinfo = (int *)(cb + 12 * kTopFast);           // 2 * parent slot + side, or -1 at the root
+        int *pos = pinfo + kTopFast;                        // the node's depth-first position
+        int *link = pos + kTopFast;                         // its escape link
+        unsigned int *arr = (unsigned int *)(link + kTopFast);
+        for (int s = threadIdx.x; s < nt; s += blockDim.x) {
+            const int p = top_node[s], q = parent[p], a = pre[p];
+            pinfo[s] = q < 0 ? -1 : 2 * top_idx[q] + (child[2 * q] == p ? 0 : 1);
+            pos[s] = a;
+            link[s] = a + 2 * (last[p] - first[p] + 1) - 1;
+            arr[s] = 0u;
+        }
+        for (int r = threadIdx.x; r < nr; r += blockDim.x) {   // the listed nodes' boxes, done by pass 1
+            const int x = roots[r], q = parent[x];
+            float *d = cb + 6 * (2 * top_idx[q] + (child[2 * q] == x ? 0 : 1));
+            for (int k = 0; k < 6; ++k) d[k] = box[6 * x + k];
+        }
+        __syncthreads();
+        for (int r = threadIdx.x; r < nr; r += blockDim.x) {
+            int s = top_idx[parent[roots[r]]];
+            for (;;) {
+                __threadfence_block();
+                if (atomicAdd(&arr[s], 1u) == 0u) break;     // first child: the sibling continues
+                __threadfence_block();
+                const float *c = cb + 12 * s;
+                float u[6];
+                for (int k = 0; k < 3; ++k) {
+                    u[k] = fminf(c[k], c[6 + k]);
+                    u[3 + k] = fmaxf(c[3 + k], c[9 + k]);
+                }
+                nodes[pos[s]] = make_node(u[0], u[1], u[2], u[3], u[4], u[5], link[s]);
+                const int pi = pinfo[s];
+                if (pi < 0) break;                             // the tree's root
+                for (int k = 0; k < 6; ++k) cb[6 * pi + k] = u[k];
+                s = pi >> 1;
+            }
+        }
+        return;
+    }
+    unsigned int *arr = (unsigned int *)smem;               // kTopSlots counters
     for (int k = threadIdx.x; k < kTopSlots; k += blockDim.x) arr[k] = 0u;
     __syncthreads();
-    const int nr = *n_roots;
     for (int r = threadIdx.x; r < nr; r += blockDim.x) {
         int x = roots[r];
         for (;;) {
@@ -369,7 +423,9 @@ __device__ __forceinline__ void lbvh_boxes_top_body(int F, const int *__restrict
 }
 __global__ __launch_bounds__(1024) void k_lbvh_boxes_top(int F, const int *__restrict__ child,
         const int *__restrict__ parent, const int *__restrict__ first, const int *__restrict__ last,
-        const int *__restrict__ pre, const int *__restrict__ top_idx, unsigned int *__restrict__ arrive, float *box,
-        Node *__restrict__ nodes, const int *__restrict__ roots, const int *__restrict__ n_roots) {
-    lbvh_boxes_top_body(F, child, parent, first, last, pre, top_idx, arrive, box, nodes, roots, n_roots);
+        const int *__restrict__ pre, const int *__restrict__ top_idx, const int *__restrict__ top_node,
+        const int *__restrict__ n_top, unsigned int *__restrict__ arrive, float *box, Node *__restrict__ nodes,
+        const int *__restrict__ roots, const int *__restrict__ n_roots) {
+    lbvh_boxes_top_body(F, child, parent, first, last, pre, top_idx, top_node, n_top, arrive, box, nodes, roots,
+                        n_roots);
 }

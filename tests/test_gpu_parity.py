@@ -110,6 +110,24 @@ def test_lbvh_and_refit_trees_render_identically(torch):
     assert np.array_equal(a, b)
 
 
+@pytest.mark.parametrize("nx,ny", [(240, 250), (400, 400)])
+def test_large_mesh_trees_match_oracle(torch, orc, nx, ny):
+    """Meshes whose per-evaluation tree has 1,298 and 3,569 nodes spanning
+    the box pass's 1024-leaf tiles (119k and 318k triangles): the first
+    climbs those nodes in LDS, the second, past 2,048, through global
+    memory.  Both images equal the refitted tree's bit for bit and the
+    oracle's at the pixel bar."""
+    model = synth.make_model(nx, ny, seed=5)
+    scene = synth.make_scene(48, 40)
+    params = synth.make_params(1)
+    a, _ = _gpu_render(torch, _renderer(torch, model, scene, False), params, SEED, 2)
+    b, _ = _gpu_render(torch, _renderer(torch, model, scene, True), params, SEED, 2)
+    assert (a.sum(-1) > 0).mean() > 0.2
+    assert np.array_equal(a, b)
+    osc, _, _ = orc.scene_from_model(model, scene, params)
+    assert_image_parity(a, orc.render(osc, SEED, 2))
+
+
 def _grad_case(torch, orc, name, terms, chunk=None, refit=False, size=None):
     from paper_1910_05200_amd import facert
     model, scene, params, spp = _case(name)
