@@ -348,7 +348,11 @@ def main():
         mean = lambda key: float(np.mean([st[key][k] for st in per_step]))
         kern[name] = (mean("kernel_box_tests"), mean("kernel_tri_tests"), mean("kernel_shades"),
                       mean("ms_kernel") * 1e-3, OPS_SHADE_ADJ if name == "k_render_adj" else OPS_SHADE_FWD)
-    dom = max(kern, key=lambda k: kern[k][3])
+    # The roofline kernel is the shadow-ray trace: the largest single kernel
+    # by GPU time, and one that runs alone on the chip, so that its event
+    # time is its own.  (The adjoint's kernels share the chip across three
+    # streams, and the silhouette entry times a phase of several kernels.)
+    dom = "k_sh_trace"
     last = per_step[-1]
     out = {
         "metric": METRIC,

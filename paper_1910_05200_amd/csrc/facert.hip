@@ -542,14 +542,14 @@ __device__ __forceinline__ v3 camera_sample(const Scene &S, uint64_t seed, uint3
 // to the same few words.  fr_stats sums the copies.
 constexpr int kCtrSpread = 64, kCtrPad = 16;
 constexpr int kCtrPerKern = 8 * kCtrSpread * kCtrPad;   // words per kernel
-__device__ inline void flush_count(unsigned long long *ctr, int slot, uint32_t v) {
+__device__ inline void flush_count(unsigned long long *ctr, int slot, unsigned long long v) {
     unsigned long long s = v;
     for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
     const unsigned r = (blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) & (kCtrSpread - 1);
     if ((threadIdx.x & 63) == 0 && s) atomicAdd(&ctr[(slot * kCtrSpread + r) * kCtrPad], s);
 }
 __device__ inline void flush_work(unsigned long long *ctr, const Work &w) {
-    flush_count(ctr, 4, w.box);
+    flush_count(ctr, 4, (unsigned long long)w.box - w.box_back);   // the wave's sum is >= 0
     flush_count(ctr, 5, w.tri);
     flush_count(ctr, 6, w.shade);
 }
@@ -842,6 +842,7 @@ __device__ __forceinline__ void sh_trace_body(const Scene &S, uint64_t seed, lon
         const HitRec *__restrict__ hits, const uint32_t *__restrict__ queue, uint32_t qcap,
         const uint32_t *__restrict__ cnt, unsigned long long *__restrict__ vis, unsigned long long *ctr, int bx,
         int j) {
+    __shared__ int lq[kTraceBlock * 2 * kLeafQ];         // the waves' triangle queues
     const uint32_t e = bx * kTraceBlock + threadIdx.x;
     if ((uint32_t)bx * kTraceBlock >= cnt[j]) return;   // the whole block is past the queue
     Work wk;
@@ -849,7 +850,8 @@ __device__ __forceinline__ void sh_trace_body(const Scene &S, uint64_t seed, lon
         const uint32_t i = queue[(size_t)j * qcap + e];
         v3 p, dd;
         int tri;
-        if (sh_ray(S, light_geom(S, j), seed, s0, i, hits, j, p, dd, tri) && !trace_any(S, p, dd, tri, wk))
+        if (sh_ray(S, light_geom(S, j), seed, s0, i, hits, j, p, dd, tri) &&
+            !trace_any(S, p, dd, tri, wk, lq + (threadIdx.x >> 6) * 128 * kLeafQ))
             atomicOr(&vis[i], 1ull << j);
     }
     flush_work(ctr, wk);
@@ -1688,10 +1690,12 @@ __global__ __launch_bounds__(256) void k_pv_propose(Scene S, uint64_t seed, cons
         uint32_t *__restrict__ queue, uint32_t qcap, unsigned long long *ctr) {
     pv_propose_body(S, seed, ps_in, hits, perm, aux, queue, qcap, ctr, blockIdx.x);
 }
+template <int BLOCK>
 __device__ __forceinline__ void pv_trace_body(const Scene &S, uint64_t seed, const PeSample *__restrict__ ps_in,
         const Hit *__restrict__ hits, const uint32_t *__restrict__ queue, uint32_t qcap,
         const uint32_t *__restrict__ cnt, unsigned long long *__restrict__ pvis, unsigned long long *ctr, int bx,
         int j) {
+    __shared__ int lq[BLOCK * 2 * kLeafQ];              // the waves' triangle queues
     const uint32_t e = bx * blockDim.x + threadIdx.x;
     if ((uint32_t)bx * blockDim.x >= cnt[j]) return;   // the whole block is past the queue
     Work wk;
@@ -1701,7 +1705,7 @@ __device__ __forceinline__ void pv_trace_body(const Scene &S, uint64_t seed, con
         Hit h;
         SurfDec sd;
         if (pe_light(S, seed, ps_in, hits, light_geom(S, j), j, ms, o, d, h, sd, y) &&
-            !trace_any(S, sd.p, y - sd.p, h.tri, wk))
+            !trace_any(S, sd.p, y - sd.p, h.tri, wk, lq + (threadIdx.x >> 6) * 128 * kLeafQ))
             atomicOr(&pvis[ms], 1ull << j);
     }
     flush_work(ctr, wk);
@@ -1709,7 +1713,7 @@ __device__ __forceinline__ void pv_trace_body(const Scene &S, uint64_t seed, con
 __global__ __launch_bounds__(kPvTraceBlock) void k_pv_trace(Scene S, uint64_t seed, const PeSample *__restrict__ ps_in,
         const Hit *__restrict__ hits, const uint32_t *__restrict__ queue, uint32_t qcap,
         const uint32_t *__restrict__ cnt, unsigned long long *__restrict__ pvis, unsigned long long *ctr) {
-    pv_trace_body(S, seed, ps_in, hits, queue, qcap, cnt, pvis, ctr, blockIdx.x, blockIdx.y);
+    pv_trace_body<kPvTraceBlock>(S, seed, ps_in, hits, queue, qcap, cnt, pvis, ctr, blockIdx.x, blockIdx.y);
 }
 
 __device__ __forceinline__ void edge_primary_shade_body(const Scene &S, uint64_t seed, int M,
