@@ -174,12 +174,12 @@ __global__ __launch_bounds__(256) void k_refit_sub(const SubTree *__restrict__ s
         int f = sorted_tri[i];
         const int *t = faces + 3 * f;
         v3 a = vpos_raw(pos, V, t[0]), b = vpos_raw(pos, V, t[1]), c = vpos_raw(pos, V, t[2]);
-        tris[3 * i] = make_float4(a.x, a.y, a.z, b.x);
-        tris[3 * i + 1] = make_float4(b.y, b.z, c.x, c.y);
-        tris[3 * i + 2] = make_float4(c.z, __int_as_float(f), 0.0f, 0.0f);
+        tris[3 * f] = make_float4(a.x, a.y, a.z, b.x);
+        tris[3 * f + 1] = make_float4(b.y, b.z, c.x, c.y);
+        tris[3 * f + 2] = make_float4(c.z, __int_as_float(f), 0.0f, 0.0f);
         nodes[leaf_node[i]] = make_node(fminf(fminf(a.x, b.x), c.x) - kBoxPad, fminf(fminf(a.y, b.y), c.y) - kBoxPad,
                                     fminf(fminf(a.z, b.z), c.z) - kBoxPad, fmaxf(fmaxf(a.x, b.x), c.x) + kBoxPad,
-                                    fmaxf(fmaxf(a.y, b.y), c.y) + kBoxPad, fmaxf(fmaxf(a.z, b.z), c.z) + kBoxPad, ~i);
+                                    fmaxf(fmaxf(a.y, b.y), c.y) + kBoxPad, fmaxf(fmaxf(a.z, b.z), c.z) + kBoxPad, ~f);
     }
     const int n_end = st.node + 2 * st.count - 1;
     for (int h = 1; h <= st.height; ++h) {

@@ -79,7 +79,7 @@ struct Scene {
     const float *alb;          // [3][V]
     const float *uv;           // [2][V]
     const Node *nodes;         // [n_nodes]: binary16 box + link (see the traversal)
-    const float4 *tris;        // [3 F]: v0 v1 v2, original index
+    const float4 *tris;        // [3 F] by triangle index: v0 v1 v2, the index
     const float *lgeom;        // [nl][12]
     const float *lrgb;         // [nl][3]
     const float *spec;         // [res^2]
@@ -144,7 +144,9 @@ __device__ __forceinline__ bool ray_tri(v3 o, v3 d, v3 v0, v3 v1, v3 v2, float t
 // lo rounded toward -inf and hi toward +inf so that the stored box always
 // contains the fp32 one (the triangle boxes padded by kBoxPad, internal
 // boxes their unions), and a link word: >= 0 the escape index of an
-// internal node, < 0 the complement of a leaf's triangle slot.  Boxes only
+// internal node, < 0 the complement of a leaf's triangle (its index in the
+// mesh, which also indexes its record in tris, so a walk can skip its ray's
+// own triangle before loading anything).  Boxes only
 // cull, so a box test may err toward entering; it must never reject a box
 // that holds an accepted hit.  (32-byte fp32 nodes save the six conversions
 // but were slower: the walk is bound by the bytes each visit moves.)
@@ -259,8 +261,9 @@ __device__ inline Hit trace_closest(const Scene &S, v3 o, v3 d, Work &wk) {
 // per-lane count costs a vector instruction on every step of a loop whose
 // vector issue is its limit.  The total is the per-lane sum.
 //
-// Triangle tests are queued.  A lane whose ray enters a leaf's box appends
-// the leaf (and the step it was reached at) to its own queue of kLeafQ
+// Triangle tests are queued.  A lane whose ray enters a leaf's box (other
+// than its own triangle's) appends the leaf's triangle (and the step it was
+// reached at) to its own queue of kLeafQ
 // entries in LDS and walks on; the wave tests the queued triangles together,
 // one entry per lane per round in queue order, when every lane of the wave
 // holds one, when a lane's queue is full, or when no lane walks any more.
@@ -292,15 +295,13 @@ __device__ inline bool trace_any(const Scene &S, v3 o, v3 d, int skip, Work &wk,
                 if (has) {
                     const int t = lq[k * 64 + lane];
                     const float4 q0 = S.tris[3 * t], q1 = S.tris[3 * t + 1], q2 = S.tris[3 * t + 2];
-                    if (__float_as_int(q2.y) != skip) {
-                        const v3 v0 = mk(q0.x, q0.y, q0.z), v1 = mk(q0.w, q1.x, q1.y), v2 = mk(q1.z, q1.w, q2.x);
-                        float tt, b1, b2, det;
-                        ++wk.tri;
-                        if (ray_tri(o, d, v0, v1, v2, kShadowTmin, kShadowTmax, tt, b1, b2, det)) {
-                            hit = true;
-                            node = S.n_nodes;      // this lane's walk ends
-                            wk.box_back += step - (uint32_t)lq[(kLeafQ + k) * 64 + lane] - 1u;
-                        }
+                    const v3 v0 = mk(q0.x, q0.y, q0.z), v1 = mk(q0.w, q1.x, q1.y), v2 = mk(q1.z, q1.w, q2.x);
+                    float tt, b1, b2, det;
+                    ++wk.tri;
+                    if (ray_tri(o, d, v0, v1, v2, kShadowTmin, kShadowTmax, tt, b1, b2, det)) {
+                        hit = true;
+                        node = S.n_nodes;          // this lane's walk ends
+                        wk.box_back += step - (uint32_t)lq[(kLeafQ + k) * 64 + lane] - 1u;
                     }
                 }
             }
@@ -314,7 +315,7 @@ __device__ inline bool trace_any(const Scene &S, v3 o, v3 d, int skip, Work &wk,
             const int link = node_link(q);
             const bool in = slab(r, node_box(q), 1.0f), leaf = link < 0;
             node = (in || leaf) ? node + 1 : link;
-            if (in && leaf) {
+            if (in && leaf && ~link != skip) {
                 lq[qn * 64 + lane] = ~link;
                 lq[(kLeafQ + qn) * 64 + lane] = (int)step;
                 ++qn;

@@ -321,15 +321,15 @@ __device__ __forceinline__ void lbvh_boxes_body(int F, const int *__restrict__ f
     int f = sorted[l];
     const int *t = faces + 3 * f;
     v3 a = vpos_raw(pos, V, t[0]), b = vpos_raw(pos, V, t[1]), c = vpos_raw(pos, V, t[2]);
-    tris[3 * l] = make_float4(a.x, a.y, a.z, b.x);
-    tris[3 * l + 1] = make_float4(b.y, b.z, c.x, c.y);
-    tris[3 * l + 2] = make_float4(c.z, __int_as_float(f), 0.0f, 0.0f);
+    tris[3 * f] = make_float4(a.x, a.y, a.z, b.x);
+    tris[3 * f + 1] = make_float4(b.y, b.z, c.x, c.y);
+    tris[3 * f + 2] = make_float4(c.z, __int_as_float(f), 0.0f, 0.0f);
     float bx[6] = {fminf(fminf(a.x, b.x), c.x) - kBoxPad, fminf(fminf(a.y, b.y), c.y) - kBoxPad,
                    fminf(fminf(a.z, b.z), c.z) - kBoxPad, fmaxf(fmaxf(a.x, b.x), c.x) + kBoxPad,
                    fmaxf(fmaxf(a.y, b.y), c.y) + kBoxPad, fmaxf(fmaxf(a.z, b.z), c.z) + kBoxPad};
     int x = (F - 1) + l;
     for (int k = 0; k < 6; ++k) box[6 * x + k] = bx[k];
-    nodes[pre[x]] = make_node(bx[0], bx[1], bx[2], bx[3], bx[4], bx[5], ~l);
+    nodes[pre[x]] = make_node(bx[0], bx[1], bx[2], bx[3], bx[4], bx[5], ~f);
     if (F == 1) return;
     __threadfence_block();
     for (;;) {
