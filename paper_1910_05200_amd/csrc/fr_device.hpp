@@ -286,42 +286,45 @@ __device__ inline bool trace_any(const Scene &S, v3 o, v3 d, int skip, Work &wk,
     bool hit = false;
     uint32_t boxes = 0, step = 0;                  // wave-uniform
     for (;;) {
-        const bool walk = node < S.n_nodes;
-        const unsigned long long m = __ballot(walk), pend = __ballot(qn > 0);
-        if (pend && (!m || pend == __builtin_amdgcn_read_exec() || __ballot(qn == kLeafQ))) {
-            for (int k = 0; k < kLeafQ; ++k) {
-                const bool has = k < qn && !hit;
-                if (!__ballot(has)) break;
-                if (has) {
-                    const int t = lq[k * 64 + lane];
-                    const float4 q0 = S.tris[3 * t], q1 = S.tris[3 * t + 1], q2 = S.tris[3 * t + 2];
-                    const v3 v0 = mk(q0.x, q0.y, q0.z), v1 = mk(q0.w, q1.x, q1.y), v2 = mk(q1.z, q1.w, q2.x);
-                    float tt, b1, b2, det;
-                    ++wk.tri;
-                    if (ray_tri(o, d, v0, v1, v2, kShadowTmin, kShadowTmax, tt, b1, b2, det)) {
-                        hit = true;
-                        node = S.n_nodes;          // this lane's walk ends
-                        wk.box_back += step - (uint32_t)lq[(kLeafQ + k) * 64 + lane] - 1u;
-                    }
+        // walk until every lane holds a queued triangle, a queue is full or no lane walks
+        unsigned long long pend;
+        for (;;) {
+            const bool walk = node < S.n_nodes;
+            const unsigned long long m = __ballot(walk);
+            pend = __ballot(qn > 0);
+            if (!m || (pend && (pend == __builtin_amdgcn_read_exec() || __ballot(qn == kLeafQ)))) break;
+            boxes += (uint32_t)__popcll(m);
+            if (walk) {
+                const Node q = load_node(S.nodes, node);
+                const int link = node_link(q);
+                const bool in = slab(r, node_box(q), 1.0f), leaf = link < 0;
+                node = (in || leaf) ? node + 1 : link;
+                if (in && leaf && ~link != skip) {
+                    lq[qn * 64 + lane] = ~link;
+                    lq[(kLeafQ + qn) * 64 + lane] = (int)step;
+                    ++qn;
                 }
             }
-            qn = 0;
-            continue;
+            ++step;
         }
-        if (!m) break;
-        boxes += (uint32_t)__popcll(m);
-        if (walk) {
-            const Node q = load_node(S.nodes, node);
-            const int link = node_link(q);
-            const bool in = slab(r, node_box(q), 1.0f), leaf = link < 0;
-            node = (in || leaf) ? node + 1 : link;
-            if (in && leaf && ~link != skip) {
-                lq[qn * 64 + lane] = ~link;
-                lq[(kLeafQ + qn) * 64 + lane] = (int)step;
-                ++qn;
+        if (!pend) break;
+        for (int k = 0; k < kLeafQ; ++k) {
+            const bool has = k < qn && !hit;
+            if (!__ballot(has)) break;
+            if (has) {
+                const int t = lq[k * 64 + lane];
+                const float4 q0 = S.tris[3 * t], q1 = S.tris[3 * t + 1], q2 = S.tris[3 * t + 2];
+                const v3 v0 = mk(q0.x, q0.y, q0.z), v1 = mk(q0.w, q1.x, q1.y), v2 = mk(q1.z, q1.w, q2.x);
+                float tt, b1, b2, det;
+                ++wk.tri;
+                if (ray_tri(o, d, v0, v1, v2, kShadowTmin, kShadowTmax, tt, b1, b2, det)) {
+                    hit = true;
+                    node = S.n_nodes;              // this lane's walk ends
+                    wk.box_back += step - (uint32_t)lq[(kLeafQ + k) * 64 + lane] - 1u;
+                }
             }
         }
-        ++step;
+        qn = 0;
     }
     // every lane that entered is active again: the first of them takes the wave's count
     if ((int)__lane_id() == __ffsll((unsigned long long)__builtin_amdgcn_read_exec()) - 1) wk.box += boxes;
