@@ -832,12 +832,10 @@ __global__ __launch_bounds__(256) void k_sh_propose(Scene S, uint64_t seed, long
 // size from the launch.  One wave per block: a wave whose rays have
 // all ended frees its slot at once, where a wave of a four-wave block holds
 // the block's place until the other three end too (1.40 -> 1.34 ms at paper
-// scale; 128-thread blocks 1.37).  The batched path runs k_pv_trace the same
-// way (the batched step 103.1 -> 99.2 ms with both); the single context
-// keeps four-wave blocks for it, since there it shares the chip with the
-// interior adjoint on the other stream, which then ran slower by more than
-// the silhouette rays gained.
-constexpr int kTraceBlock = 64, kPvTraceBlock = 256;
+// scale; 128-thread blocks 1.37).  k_pv_trace runs the same way (with the
+// queued triangle tests and the adjoint on three streams, the step went
+// from 3.02 to 2.98 ms; 128-thread blocks 3.00).
+constexpr int kTraceBlock = 64;
 __device__ __forceinline__ void sh_trace_body(const Scene &S, uint64_t seed, long long s0,
         const HitRec *__restrict__ hits, const uint32_t *__restrict__ queue, uint32_t qcap,
         const uint32_t *__restrict__ cnt, unsigned long long *__restrict__ vis, unsigned long long *ctr, int bx,
@@ -1690,14 +1688,13 @@ __global__ __launch_bounds__(256) void k_pv_propose(Scene S, uint64_t seed, cons
         uint32_t *__restrict__ queue, uint32_t qcap, unsigned long long *ctr) {
     pv_propose_body(S, seed, ps_in, hits, perm, aux, queue, qcap, ctr, blockIdx.x);
 }
-template <int BLOCK>
 __device__ __forceinline__ void pv_trace_body(const Scene &S, uint64_t seed, const PeSample *__restrict__ ps_in,
         const Hit *__restrict__ hits, const uint32_t *__restrict__ queue, uint32_t qcap,
         const uint32_t *__restrict__ cnt, unsigned long long *__restrict__ pvis, unsigned long long *ctr, int bx,
         int j) {
-    __shared__ int lq[BLOCK * 2 * kLeafQ];              // the waves' triangle queues
-    const uint32_t e = bx * blockDim.x + threadIdx.x;
-    if ((uint32_t)bx * blockDim.x >= cnt[j]) return;   // the whole block is past the queue
+    __shared__ int lq[kTraceBlock * 2 * kLeafQ];        // the waves' triangle queues
+    const uint32_t e = bx * kTraceBlock + threadIdx.x;
+    if ((uint32_t)bx * kTraceBlock >= cnt[j]) return;   // the whole block is past the queue
     Work wk;
     if (e < cnt[j]) {
         const int ms = (int)queue[(size_t)j * qcap + e];
@@ -1710,10 +1707,10 @@ __device__ __forceinline__ void pv_trace_body(const Scene &S, uint64_t seed, con
     }
     flush_work(ctr, wk);
 }
-__global__ __launch_bounds__(kPvTraceBlock) void k_pv_trace(Scene S, uint64_t seed, const PeSample *__restrict__ ps_in,
+__global__ __launch_bounds__(kTraceBlock) void k_pv_trace(Scene S, uint64_t seed, const PeSample *__restrict__ ps_in,
         const Hit *__restrict__ hits, const uint32_t *__restrict__ queue, uint32_t qcap,
         const uint32_t *__restrict__ cnt, unsigned long long *__restrict__ pvis, unsigned long long *ctr) {
-    pv_trace_body<kPvTraceBlock>(S, seed, ps_in, hits, queue, qcap, cnt, pvis, ctr, blockIdx.x, blockIdx.y);
+    pv_trace_body(S, seed, ps_in, hits, queue, qcap, cnt, pvis, ctr, blockIdx.x, blockIdx.y);
 }
 
 __device__ __forceinline__ void edge_primary_shade_body(const Scene &S, uint64_t seed, int M,
@@ -2844,7 +2841,7 @@ static void primary_pass(fr_ctx *c, const Scene &S, const float *dLdI, hipStream
     const uint32_t pv_cap = 2 * (uint32_t)M;
     hipLaunchKernelGGL(k_pv_propose, dim3(nblk((size_t)pv_cap, 256)), dim3(256), 0, st, S, c->last_seed, c->pe_samples,
                        c->pe_hits, c->pv_perm, c->pv_aux, c->pv_queue, pv_cap, pctr);
-    hipLaunchKernelGGL(k_pv_trace, dim3(nblk((size_t)pv_cap, kPvTraceBlock), c->nl), dim3(kPvTraceBlock), 0, st, S,
+    hipLaunchKernelGGL(k_pv_trace, dim3(nblk((size_t)pv_cap, kTraceBlock), c->nl), dim3(kTraceBlock), 0, st, S,
                        c->last_seed, c->pe_samples, c->pe_hits, c->pv_queue, pv_cap, c->pv_aux + 2 * pv_nk,
                        c->pe_vis, pctr);
     hipLaunchKernelGGL(k_edge_primary_shade, dim3(nblk((size_t)2 * M, 256)), dim3(256), lds1, st,

@@ -209,7 +209,7 @@ FR_KIND(KPvPropose, 256) {
 }};
 FR_KIND(KPvTrace, kTraceBlock) {
     if (!(I.d.terms & FR_TERM_PRIMARY)) return;
-    pv_trace_body<kTraceBlock>(I.S, I.d.seed, I.pe_samples, I.pe_hits, I.pv_queue, 2 * (uint32_t)I.M,
+    pv_trace_body(I.S, I.d.seed, I.pe_samples, I.pe_hits, I.pv_queue, 2 * (uint32_t)I.M,
                   I.pv_aux + 2 * pv_keys(I.S.W, I.S.H), I.pe_vis, I.ctr + kCtrPerKern * kKernPrimary, bx, by);
 }};
 FR_KIND(KPrimaryShade, 256) {
