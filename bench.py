@@ -34,11 +34,11 @@ OPS_BOX = 15
 OPS_TRI = 50
 # The same units as the compiled gfx950 code issues them (VALU instructions
 # per lane in the compiled loop, address arithmetic included): a node visit
-# 21 (binary16 decode folded into v_fma_mix_f32), a full triangle test with
-# its hit-box check 95, one light sample's shading 215, one light sample's
-# shading plus reverse-mode adjoint 590.  Reported beside the fixed-cost
-# fraction, never in its place.
-ISA_BOX = 21
+# 24 (binary16 decode folded into v_fma_mix_f32; the loop's exit and queue
+# tests included), a full triangle test with its hit-box check 95, one light
+# sample's shading 215, one light sample's shading plus reverse-mode
+# adjoint 590.  Reported beside the fixed-cost fraction, never in its place.
+ISA_BOX = 24
 ISA_TRI = 95
 OPS_SHADE_FWD = 215
 OPS_SHADE_ADJ = 590
