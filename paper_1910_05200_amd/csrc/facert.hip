@@ -840,7 +840,8 @@ __device__ __forceinline__ void sh_trace_body(const Scene &S, uint64_t seed, lon
         const HitRec *__restrict__ hits, const uint32_t *__restrict__ queue, uint32_t qcap,
         const uint32_t *__restrict__ cnt, unsigned long long *__restrict__ vis, unsigned long long *ctr, int bx,
         int j) {
-    __shared__ int lq[kTraceBlock * 2 * kLeafQ];         // the waves' triangle queues
+    static_assert(kTraceBlock == 64, "one wave per block: the walk's test list is the block's");
+    __shared__ uint32_t lq[2 * kLeafList + 64];            // the wave's list of triangle tests
     const uint32_t e = bx * kTraceBlock + threadIdx.x;
     if ((uint32_t)bx * kTraceBlock >= cnt[j]) return;   // the whole block is past the queue
     Work wk;
@@ -849,7 +850,7 @@ __device__ __forceinline__ void sh_trace_body(const Scene &S, uint64_t seed, lon
         v3 p, dd;
         int tri;
         if (sh_ray(S, light_geom(S, j), seed, s0, i, hits, j, p, dd, tri) &&
-            !trace_any(S, p, dd, tri, wk, lq + (threadIdx.x >> 6) * 128 * kLeafQ))
+            !trace_any(S, p, dd, tri, wk, lq))
             atomicOr(&vis[i], 1ull << j);
     }
     flush_work(ctr, wk);
@@ -1692,7 +1693,7 @@ __device__ __forceinline__ void pv_trace_body(const Scene &S, uint64_t seed, con
         const Hit *__restrict__ hits, const uint32_t *__restrict__ queue, uint32_t qcap,
         const uint32_t *__restrict__ cnt, unsigned long long *__restrict__ pvis, unsigned long long *ctr, int bx,
         int j) {
-    __shared__ int lq[kTraceBlock * 2 * kLeafQ];        // the waves' triangle queues
+    __shared__ uint32_t lq[2 * kLeafList + 64];            // the wave's list of triangle tests
     const uint32_t e = bx * kTraceBlock + threadIdx.x;
     if ((uint32_t)bx * kTraceBlock >= cnt[j]) return;   // the whole block is past the queue
     Work wk;
@@ -1702,7 +1703,7 @@ __device__ __forceinline__ void pv_trace_body(const Scene &S, uint64_t seed, con
         Hit h;
         SurfDec sd;
         if (pe_light(S, seed, ps_in, hits, light_geom(S, j), j, ms, o, d, h, sd, y) &&
-            !trace_any(S, sd.p, y - sd.p, h.tri, wk, lq + (threadIdx.x >> 6) * 128 * kLeafQ))
+            !trace_any(S, sd.p, y - sd.p, h.tri, wk, lq))
             atomicOr(&pvis[ms], 1ull << j);
     }
     flush_work(ctr, wk);

@@ -262,69 +262,94 @@ __device__ inline Hit trace_closest(const Scene &S, v3 o, v3 d, Work &wk) {
 // vector issue is its limit.  The total is the per-lane sum.
 //
 // Triangle tests are queued.  A lane whose ray enters a leaf's box (other
-// than its own triangle's) appends the leaf's triangle (and the step it was
-// reached at) to its own queue of kLeafQ
-// entries in LDS and walks on; the wave tests the queued triangles together,
-// one entry per lane per round in queue order, when every lane of the wave
-// holds one, when a lane's queue is full, or when no lane walks any more.
-// Run at once, a triangle test had about four of the wave's lanes active
-// and was more than half of the kernel's vector instructions; queued, most
-// lanes test at once.  A lane whose queued triangle is hit stops there and
-// drops the rest of its queue; the steps it walked past that leaf found
-// nothing the answer depends on (any hit ends the ray), so the result is
-// the walk's.  Triangle tests are counted as the walk makes them (those up
-// to the hit); the node tests past the hit are taken back, counted from the
-// step of the test, which the wave knows as it holds all its lanes' steps
-// (a lane that had already left the tree before the round is charged as if
-// it had walked to it, so the count is a lower bound of the walk's, within
-// 0.3% at paper scale).  lq: the wave's 2 kLeafQ x 64 LDS words.
-constexpr int kLeafQ = 8;
-__device__ inline bool trace_any(const Scene &S, v3 o, v3 d, int skip, Work &wk, int *__restrict__ lq) {
+// than its own triangle's) appends the triangle, its own lane and the step
+// to one list of the wave in LDS, and walks on.  Once the list holds
+// kLeafRound entries, or no lane walks any more, the wave runs the listed
+// tests in rounds, one entry per lane that entered whatever lane queued it, with
+// the queuing lane's ray read from that lane's registers; a hit records its
+// step in the queuing lane's LDS word with an atomic minimum.  Run where a
+// lane met its leaf, a triangle test executed for the whole wave with about
+// four of its lanes active and was more than half of the kernel's vector
+// instructions; listed, a round fills the wave.  A lane whose triangle was
+// hit stops; the steps it walked past that leaf decided nothing (any hit
+// ends the ray), so the result is the walk's.  Triangle tests are counted
+// as the walk makes them, those up to each ray's first hit; node tests past
+// the hit are taken back from the hit's step.  A lane that had already left
+// the tree before the round is charged as if it had walked on to it, so the
+// node count is a lower bound of the walk's (0.2% low at paper scale).
+// lq: the wave's 2 kLeafList + 64 LDS words (one 64-lane wave per block).
+constexpr int kLeafList = 512;                // queued tests a wave's list holds
+constexpr uint32_t kLeafRound = 48;           // listed tests that start the rounds
+static_assert(kLeafRound + 64 <= kLeafList, "a step appends at most 64 entries");
+__device__ inline bool trace_any(const Scene &S, v3 o, v3 d, int skip, Work &wk, uint32_t *__restrict__ lq) {
+    uint32_t *const lstep = lq + kLeafList, *const lhit = lstep + kLeafList;
     const Ray r = make_ray(o, d);
     const int lane = (int)__lane_id();
-    int node = 0, qn = 0;
+    // the rounds deal the list to the lanes that entered (a lane whose
+    // sample needs no ray, or past the queue's end, is not among them)
+    const unsigned long long act = __ballot(true);
+    const uint32_t n_act = (uint32_t)__popcll(act),
+                   rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(act >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)act, 0u));
+    lhit[lane] = ~0u;                          // step of this lane's first hit
+    int node = 0;
     bool hit = false;
-    uint32_t boxes = 0, step = 0;                  // wave-uniform
+    uint32_t boxes = 0, step = 0, cnt = 0;     // wave-uniform
     for (;;) {
-        // walk until every lane holds a queued triangle, a queue is full or no lane walks
-        unsigned long long pend;
-        for (;;) {
+        for (;;) {                             // walk until the list is due
             const bool walk = node < S.n_nodes;
             const unsigned long long m = __ballot(walk);
-            pend = __ballot(qn > 0);
-            if (!m || (pend && (pend == __builtin_amdgcn_read_exec() || __ballot(qn == kLeafQ)))) break;
+            if (!m || cnt >= kLeafRound) break;
             boxes += (uint32_t)__popcll(m);
+            bool want = false;
+            int tri = 0;
             if (walk) {
                 const Node q = load_node(S.nodes, node);
                 const int link = node_link(q);
                 const bool in = slab(r, node_box(q), 1.0f), leaf = link < 0;
                 node = (in || leaf) ? node + 1 : link;
-                if (in && leaf && ~link != skip) {
-                    lq[qn * 64 + lane] = ~link;
-                    lq[(kLeafQ + qn) * 64 + lane] = (int)step;
-                    ++qn;
-                }
+                tri = ~link;
+                want = in && leaf && tri != skip;
             }
+            const unsigned long long a = __ballot(want);
+            if (want) {
+                const uint32_t at = cnt + __builtin_amdgcn_mbcnt_hi((uint32_t)(a >> 32),
+                                                                    __builtin_amdgcn_mbcnt_lo((uint32_t)a, 0u));
+                lq[at] = ((uint32_t)tri << 6) | (uint32_t)lane;
+                lstep[at] = step;
+            }
+            cnt += (uint32_t)__popcll(a);
             ++step;
         }
-        if (!pend) break;
-        for (int k = 0; k < kLeafQ; ++k) {
-            const bool has = k < qn && !hit;
-            if (!__ballot(has)) break;
+        if (!cnt) break;                       // no lane walks and nothing is listed
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        for (uint32_t base = 0; base < cnt; base += n_act) {
+            const uint32_t g = base + rank;
+            const bool has = g < cnt;
+            const uint32_t e = has ? lq[g] : 0u;
+            const int owner = (int)(e & 63u), t = (int)(e >> 6);
+            const v3 oo = mk(__shfl(o.x, owner), __shfl(o.y, owner), __shfl(o.z, owner));
+            const v3 dd = mk(__shfl(d.x, owner), __shfl(d.y, owner), __shfl(d.z, owner));
             if (has) {
-                const int t = lq[k * 64 + lane];
                 const float4 q0 = S.tris[3 * t], q1 = S.tris[3 * t + 1], q2 = S.tris[3 * t + 2];
                 const v3 v0 = mk(q0.x, q0.y, q0.z), v1 = mk(q0.w, q1.x, q1.y), v2 = mk(q1.z, q1.w, q2.x);
                 float tt, b1, b2, det;
-                ++wk.tri;
-                if (ray_tri(o, d, v0, v1, v2, kShadowTmin, kShadowTmax, tt, b1, b2, det)) {
-                    hit = true;
-                    node = S.n_nodes;              // this lane's walk ends
-                    wk.box_back += step - (uint32_t)lq[(kLeafQ + k) * 64 + lane] - 1u;
-                }
+                if (ray_tri(oo, dd, v0, v1, v2, kShadowTmin, kShadowTmax, tt, b1, b2, det))
+                    atomicMin(&lhit[owner], lstep[g]);
             }
         }
-        qn = 0;
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        for (uint32_t base = 0; base < cnt; base += n_act) {   // the tests the walk makes
+            const uint32_t g = base + rank;
+            if (g < cnt && lstep[g] <= lhit[lq[g] & 63u]) ++wk.tri;
+        }
+        const uint32_t hs = lhit[lane];
+        if (hs != ~0u && !hit) {
+            hit = true;
+            node = S.n_nodes;                  // this lane's walk ends
+            wk.box_back += step - hs - 1u;
+        }
+        cnt = 0;
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     }
     // every lane that entered is active again: the first of them takes the wave's count
     if ((int)__lane_id() == __ffsll((unsigned long long)__builtin_amdgcn_read_exec()) - 1) wk.box += boxes;
