@@ -2645,7 +2645,7 @@ int fr_set_terms(fr_ctx *c, uint32_t terms) {
 static void lbvh_build(fr_ctx *c, hipStream_t st) {
     const int F = c->F, nb = c->lb.nb;
     LbvhBufs &L = c->lb;
-    hipLaunchKernelGGL(k_lbvh_bounds_init, dim3(1), dim3(64), 0, st, L.bounds);
+    hipLaunchKernelGGL(k_lbvh_bounds_init, dim3(1), dim3(64), 0, st, L.bounds, L.n_top, L.n_roots);
     hipLaunchKernelGGL(k_lbvh_bounds, dim3(nblk(F, 256)), dim3(256), 0, st, F, c->pos, c->V, c->faces, L.bounds);
     hipLaunchKernelGGL(k_lbvh_morton, dim3(nblk(F, 256)), dim3(256), 0, st, F, c->pos, c->V, c->faces, L.bounds,
                        L.key[0], L.val[0]);
@@ -2656,13 +2656,11 @@ static void lbvh_build(fr_ctx *c, hipStream_t st) {
         hipLaunchKernelGGL(k_sort_scatter, dim3(nb), dim3(256), 0, st, F, 8 * pass, L.key[in], L.val[in], L.hist,
                            nb, L.key[out], L.val[out]);
     }
-    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, (unsigned int *)L.n_top, 1);
     if (F > 1)
         hipLaunchKernelGGL(k_lbvh_karras, dim3(nblk(F - 1, 256)), dim3(256), 0, st, F, L.key[0], L.child,
                            L.parent, L.first, L.last, L.top_idx, L.n_top, L.top_node);
     hipLaunchKernelGGL(k_lbvh_layout, dim3(nblk(2 * (size_t)F - 1, 256)), dim3(256), 0, st, F, L.child, L.parent,
                        L.first, L.pre);
-    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, (unsigned int *)L.n_roots, 1);
     hipLaunchKernelGGL(k_lbvh_boxes, dim3(nblk(F, kBoxTile)), dim3(kBoxTile), 0, st, F, c->faces, c->pos, c->V,
                        L.val[0], L.child, L.parent, L.first, L.last, L.pre, L.box, c->nodes, c->tris,
                        L.roots, L.n_roots);

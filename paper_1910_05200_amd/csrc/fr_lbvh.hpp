@@ -64,7 +64,12 @@ __device__ __forceinline__ void lbvh_bounds_init_body(unsigned int *bounds) {
     if (threadIdx.x < 3) bounds[threadIdx.x] = 0xffffffffu;
     else if (threadIdx.x < 6) bounds[threadIdx.x] = 0u;
 }
-__global__ __launch_bounds__(256) void k_lbvh_bounds_init(unsigned int *bounds) { lbvh_bounds_init_body(bounds); }
+// the bounds and the two list counters of the box passes
+__global__ __launch_bounds__(64) void k_lbvh_bounds_init(unsigned int *bounds, int *n_top, int *n_roots) {
+    lbvh_bounds_init_body(bounds);
+    if (threadIdx.x == 8) *n_top = 0;
+    if (threadIdx.x == 9) *n_roots = 0;
+}
 
 __device__ __forceinline__ void lbvh_bounds_body(int F, const float *__restrict__ pos, int V,
         const int *__restrict__ faces, unsigned int *bounds, int bx) {
@@ -148,25 +153,28 @@ __global__ __launch_bounds__(256) void k_sort_hist(int n, int shift, const uint3
     sort_hist_body(n, shift, key, hist, nb, blockIdx.x);
 }
 
-// exclusive scan of n counts in place, one block of 1024 threads
+// exclusive scan of n counts in place, one block of 1024 threads: each
+// thread sums a run of consecutive counts, one block-wide scan of the runs'
+// sums, then each thread writes its run's offsets (one barrier in all)
 __device__ __forceinline__ void scan_u32_body(int n, uint32_t *a) {
     __shared__ uint32_t s_w[16];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    uint32_t base = 0;
-    for (int start = 0; start < n; start += 1024) {
-        int i = start + threadIdx.x;
-        uint32_t x = i < n ? a[i] : 0u, inc = x;
-        for (int off = 1; off < 64; off <<= 1) {
-            uint32_t t = __shfl_up(inc, off);
-            if (lane >= off) inc += t;
-        }
-        if (lane == 63) s_w[w] = inc;
-        __syncthreads();
-        uint32_t before = 0, total = 0;
-        for (int k = 0; k < 16; ++k) { if (k < w) before += s_w[k]; total += s_w[k]; }
-        if (i < n) a[i] = base + before + inc - x;
-        base += total;
-        __syncthreads();
+    const int per = (n + 1023) / 1024, i0 = (int)threadIdx.x * per, i1 = min(n, i0 + per);
+    uint32_t sum = 0;
+    for (int i = i0; i < i1; ++i) sum += a[i];
+    uint32_t inc = sum;
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t t = __shfl_up(inc, off);
+        if (lane >= off) inc += t;
+    }
+    if (lane == 63) s_w[w] = inc;
+    __syncthreads();
+    uint32_t run = inc - sum;
+    for (int k = 0; k < w; ++k) run += s_w[k];
+    for (int i = i0; i < i1; ++i) {
+        const uint32_t x = a[i];
+        a[i] = run;
+        run += x;
     }
 }
 __global__ __launch_bounds__(1024) void k_scan_u32(int n, uint32_t *a) { scan_u32_body(n, a); }
