@@ -1928,14 +1928,6 @@ __global__ __launch_bounds__(256) void k_zero(float *a, size_t n) {
     size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) a[i] = 0.0f;
 }
-__global__ __launch_bounds__(256) void k_zero_d(double *a, size_t n) {
-    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) a[i] = 0.0;
-}
-__global__ __launch_bounds__(256) void k_copy_d2f(const double *__restrict__ a, float *__restrict__ b, size_t n) {
-    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) b[i] = (float)a[i];
-}
 __global__ void k_zero_u32(unsigned int *a, int n) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) a[i] = 0u;
@@ -1952,6 +1944,25 @@ __global__ void k_zero_ctr(unsigned long long *ctr, int k0, int k1) {
 __global__ __launch_bounds__(256) void k_copy(const float *__restrict__ a, float *__restrict__ b, size_t n) {
     size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) b[i] = a[i];
+}
+// the adjoint's accumulators and its kernels' counters cleared in one launch
+// (counter words first .. first + n - 1, kCtrPad apart)
+__global__ __launch_bounds__(256) void k_zero_bwd(GradBufs G, int nl3, int rr, int V3, unsigned long long *ctr,
+                                                  int ctr_first, int ctr_n) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < nl3) G.d_light[i] = 0.0;
+    if (i < rr) G.d_spec[i] = 0.0;
+    if (i < V3) { G.d_pos[i] = 0.0; G.d_nrm[i] = 0.0; G.d_alb[i] = 0.0; }
+    if (i < ctr_n) ctr[(ctr_first + i) * kCtrPad] = 0ull;
+}
+// the requested gradients rounded to the caller's float arrays in one launch
+__global__ __launch_bounds__(256) void k_grads_out(GradBufs G, const float *__restrict__ g_vert, int nl3, int rr, int V3,
+        float *d_lights, float *d_spec, float *d_vertices, float *d_albedo) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (d_lights && i < nl3) d_lights[i] = (float)G.d_light[i];
+    if (d_spec && i < rr) d_spec[i] = (float)G.d_spec[i];
+    if (d_vertices && i < V3) d_vertices[i] = g_vert[i];
+    if (d_albedo && i < V3) d_albedo[i] = (float)G.d_alb[i];
 }
 
 template <int BS>
@@ -2856,19 +2867,17 @@ static int backward_call(fr_ctx *c, const float *dLdI, const fr_grads *g) {
     if (!c->have_render) return fail(c, FR_ESTATE, "fr_backward: no prior fr_render");
     if (!dLdI || !g) return fail(c, FR_EINVAL, "fr_backward: null argument");
     size_t V3 = 3 * (size_t)c->V;
+    const int rr = c->res * c->res, nl3 = 3 * c->nl;
     ev_record(c, 5);
-    hipLaunchKernelGGL(k_zero_d, dim3(nblk(3 * c->nl, 256)), dim3(256), 0, c->stream, c->g_light, (size_t)3 * c->nl);
-    hipLaunchKernelGGL(k_zero_d, dim3(nblk((size_t)c->res * c->res, 256)), dim3(256), 0, c->stream, c->g_spec, (size_t)c->res * c->res);
-    hipLaunchKernelGGL(k_zero_d, dim3(nblk(V3, 256)), dim3(256), 0, c->stream, c->g_pos, V3);
-    hipLaunchKernelGGL(k_zero_d, dim3(nblk(V3, 256)), dim3(256), 0, c->stream, c->g_nrm, V3);
-    hipLaunchKernelGGL(k_zero_d, dim3(nblk(V3, 256)), dim3(256), 0, c->stream, c->g_alb, V3);
+    GradBufs G{c->g_light, c->g_spec, c->g_pos, c->g_nrm, c->g_alb};
+    hipLaunchKernelGGL(k_zero_bwd, dim3(nblk(std::max({V3, (size_t)rr, (size_t)nl3,
+                                                       (size_t)8 * kCtrSpread * (kNumKern - kKernAdj)}), 256)),
+                       dim3(256), 0, c->stream, G, nl3, rr, (int)V3, c->ctr, 8 * kCtrSpread * kKernAdj,
+                       8 * kCtrSpread * (kNumKern - kKernAdj));
     Scene S = make_scene(c);
     long long N = (long long)c->W * c->H * c->last_spp;
-    GradBufs G{c->g_light, c->g_spec, c->g_pos, c->g_nrm, c->g_alb};
     const long long kChunk = c->last_cam_chunk;
     size_t lds = ((size_t)2 * c->res * c->res + (size_t)kLightCopies * light_stride(c->nl)) * sizeof(float);
-    hipLaunchKernelGGL(k_zero_ctr, dim3(nblk(8 * kCtrSpread * (kNumKern - kKernAdj), 256)), dim3(256), 0, c->stream, c->ctr,
-                       kKernAdj, kNumKern);
     size_t lds1 = (size_t)c->res * c->res * sizeof(float);
     // The silhouette term reads none of the other terms' scratch and adds
     // into the vertex gradient with atomics, as they do: it runs on the
@@ -2932,10 +2941,10 @@ static int backward_call(fr_ctx *c, const float *dLdI, const fr_grads *g) {
         hipLaunchKernelGGL(k_param_final, dim3(nblk(rows, 64)), dim3(64), 0, c->stream, c->n_id, c->n_exp, c->n_alb,
                            c->nchunks, c->partial, c->drot, g->d_alpha, g->d_beta, g->d_delta, g->d_pose);
     }
-    if (g->d_lights) hipLaunchKernelGGL(k_copy_d2f, dim3(1), dim3(256), 0, c->stream, c->g_light, g->d_lights, (size_t)3 * c->nl);
-    if (g->d_spec) hipLaunchKernelGGL(k_copy_d2f, dim3(nblk((size_t)c->res * c->res, 256)), dim3(256), 0, c->stream, c->g_spec, g->d_spec, (size_t)c->res * c->res);
-    if (g->d_vertices) hipLaunchKernelGGL(k_copy, dim3(nblk(V3, 256)), dim3(256), 0, c->stream, c->g_vert, g->d_vertices, V3);
-    if (g->d_albedo) hipLaunchKernelGGL(k_copy_d2f, dim3(nblk(V3, 256)), dim3(256), 0, c->stream, c->g_alb, g->d_albedo, V3);
+    if (g->d_lights || g->d_spec || g->d_vertices || g->d_albedo)
+        hipLaunchKernelGGL(k_grads_out, dim3(nblk(std::max({V3, (size_t)rr, (size_t)nl3}), 256)), dim3(256), 0,
+                           c->stream, G, c->g_vert, nl3, rr, (int)V3, g->d_lights, g->d_spec, g->d_vertices,
+                           g->d_albedo);
     ev_record(c, 6);
     HIPCK(c, hipGetLastError());
     c->have_backward = true;
