@@ -75,33 +75,41 @@ __device__ __forceinline__ uint4 load8(const float *p) {
 __device__ __forceinline__ void store1(bf16 *p, float v) { *p = f2bf(v); }
 __device__ __forceinline__ void store1(float *p, float v) { *p = v; }
 
-constexpr int kPR = 8, kPC = 16;                  // pixel tile: 8 rows x 16 columns
-constexpr int kHR = kPR + 2, kHC = kPC + 2;       // with the one-pixel halo
+constexpr int kPR = 8;                            // pixel tile: 8 rows x PC columns (16 or 32)
 constexpr int kLPad = 8;                          // bf16 of padding per LDS row
 
 // H is the stack's height and Himg the rows of one image (H for a single
 // image); when images are stacked, Himg is a multiple of the tile's rows, so
-// a tile never spans two images.
-template <class TX, class TY, int NT, int KC>
+// a tile never spans two images.  Each wave owns two pixel rows of the tile
+// (2 PC pixels, PC / 16 row blocks of 32 pixels for the instruction) and all
+// NT channels: with 32 columns every weight fragment read from LDS serves
+// two instructions instead of one, which halves the LDS reads per
+// instruction of the B operand.
+// act (nullable, [P][Cout] like Y): the leaky ReLU outputs whose derivative
+// multiplies the result (the input gradient of a layer whose input is an
+// activation), so that no separate pass over the gradient is needed.
+template <class TX, class TY, int NT, int KC, int PC>
 __global__ __launch_bounds__(256) void k_conv3x3(int H, int Himg, int W, int Cin, int Cout, const TX *__restrict__ X,
         const bf16 *__restrict__ Wt, const float *__restrict__ bias, int relu, TY *__restrict__ Y, int ldy,
-        int yoff) {
-    constexpr int NA = NT / 32;                   // accumulators per wave
+        int yoff, const bf16 *__restrict__ act) {
+    constexpr int kHR = kPR + 2, kHC = PC + 2;    // the patch: the tile with its one-pixel halo
+    constexpr int NA = NT / 32;                   // accumulators per wave and row block
+    constexpr int MB = PC / 16;                   // row blocks of 32 pixels per wave
     constexpr int XQ = KC / 8;                    // 16-byte parts per pixel per stage
     constexpr int XN = kHR * kHC * XQ, WN = 9 * NT * XQ;
     constexpr int XI = (XN + 255) / 256, WI = (WN + 255) / 256;
     __shared__ __attribute__((aligned(16))) bf16 Xs[kHR * kHC][KC + kLPad];
     __shared__ __attribute__((aligned(16))) bf16 Ws[9 * NT][KC + kLPad];
-    const int tiles_x = (W + kPC - 1) / kPC;
-    const int ty0 = (int)(blockIdx.x / tiles_x) * kPR, tx0 = (int)(blockIdx.x % tiles_x) * kPC;
+    const int tiles_x = (W + PC - 1) / PC;
+    const int ty0 = (int)(blockIdx.x / tiles_x) * kPR, tx0 = (int)(blockIdx.x % tiles_x) * PC;
     const int co0 = blockIdx.y * NT;
     const int ylo = ty0 - ty0 % Himg, yhi = min(H, ylo + Himg);   // the tile's image
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int m = lane & 31, kh = (lane >> 5) * 8;   // the lane's pixel (A) / channel (B) row, k half
-    const int pr = 2 * wave + (m >> 4), pc = m & 15;
-    f16v acc[NA];
-    for (int a = 0; a < NA; ++a)
-        for (int r = 0; r < 16; ++r) acc[a][r] = 0.0f;
+    f16v acc[MB][NA];
+    for (int mb = 0; mb < MB; ++mb)
+        for (int a = 0; a < NA; ++a)
+            for (int r = 0; r < 16; ++r) acc[mb][a][r] = 0.0f;
     uint4 xr[XI], wr[WI];
     auto fetch = [&](int c0) {
 #pragma unroll
@@ -143,52 +151,72 @@ __global__ __launch_bounds__(256) void k_conv3x3(int H, int Himg, int W, int Cin
         if (c0 + KC < Cin) fetch(c0 + KC);         // in flight during this stage's MFMAs
 #pragma unroll
         for (int t = 0; t < 9; ++t) {
-            const int q = (pr + t / 3) * kHC + pc + t % 3;
 #pragma unroll
             for (int ks = 0; ks < KC; ks += 16) {
-                const bf8v a = *(const bf8v *)&Xs[q][ks + kh];
+                bf8v a[MB];
+#pragma unroll
+                for (int mb = 0; mb < MB; ++mb) {
+                    const int pi = mb * 32 + m, pr = 2 * wave + pi / PC, pc = pi % PC;
+                    a[mb] = *(const bf8v *)&Xs[(pr + t / 3) * kHC + pc + t % 3][ks + kh];
+                }
 #pragma unroll
                 for (int na = 0; na < NA; ++na) {
                     const bf8v b = *(const bf8v *)&Ws[t * NT + na * 32 + m][ks + kh];
-                    acc[na] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[na], 0, 0, 0);
+#pragma unroll
+                    for (int mb = 0; mb < MB; ++mb)
+                        acc[mb][na] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[mb], b, acc[mb][na], 0, 0, 0);
                 }
             }
         }
     }
-    // acc[na][r] holds pixel 8 (r / 4) + 4 (lane / 32) + r % 4 of the wave's
-    // 32 and channel na * 32 + lane % 32
+    // acc[mb][na][r] holds pixel 32 mb + 8 (r / 4) + 4 (lane / 32) + r % 4 of
+    // the wave's 2 PC (row-major) and channel na * 32 + lane % 32
 #pragma unroll
     for (int na = 0; na < NA; ++na) {
         const int co = co0 + na * 32 + m;
         if (co >= Cout) continue;
         const float bv = bias ? bias[co] : 0.0f;
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const int mm = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-            const int py = ty0 + 2 * wave + (mm >> 4), px = tx0 + (mm & 15);
-            if (py >= H || px >= W) continue;
-            float v = acc[na][r] + bv;
-            if (relu) v = v > 0.0f ? v : kSlope * v;
-            store1(&Y[((size_t)py * W + px) * ldy + yoff + co], v);
-        }
+        for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int pi = mb * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                const int py = ty0 + 2 * wave + pi / PC, px = tx0 + pi % PC;
+                if (py >= H || px >= W) continue;
+                float v = acc[mb][na][r] + bv;
+                if (relu) v = v > 0.0f ? v : kSlope * v;
+                if (act && !(bf2f(act[((size_t)py * W + px) * Cout + co]) > 0.0f)) v *= kSlope;
+                store1(&Y[((size_t)py * W + px) * ldy + yoff + co], v);
+            }
+    }
+}
+
+template <class TX, class TY, int PC>
+static void conv3x3_launch_pc(hipStream_t s, int H, int Himg, int W, int Cin, int Cout, const TX *X, const bf16 *Wt,
+                              const float *bias, int relu, TY *Y, int ldy, int yoff, const bf16 *act) {
+    const unsigned tiles = (unsigned)(((H + kPR - 1) / kPR) * ((W + PC - 1) / PC));
+    if (Cout >= 64) {
+        dim3 g(tiles, (unsigned)((Cout + 63) / 64));
+        if (Cin % 32 == 0) hipLaunchKernelGGL((k_conv3x3<TX, TY, 64, 32, PC>), g, dim3(256), 0, s, H, Himg, W, Cin, Cout, X, Wt, bias, relu, Y, ldy, yoff, act);
+        else hipLaunchKernelGGL((k_conv3x3<TX, TY, 64, 16, PC>), g, dim3(256), 0, s, H, Himg, W, Cin, Cout, X, Wt, bias, relu, Y, ldy, yoff, act);
+    } else {
+        dim3 g(tiles, (unsigned)((Cout + 31) / 32));
+        if (Cin % 32 == 0) hipLaunchKernelGGL((k_conv3x3<TX, TY, 32, 32, PC>), g, dim3(256), 0, s, H, Himg, W, Cin, Cout, X, Wt, bias, relu, Y, ldy, yoff, act);
+        else hipLaunchKernelGGL((k_conv3x3<TX, TY, 32, 16, PC>), g, dim3(256), 0, s, H, Himg, W, Cin, Cout, X, Wt, bias, relu, Y, ldy, yoff, act);
     }
 }
 
 // Launch k_conv3x3 for one layer: NT = 64 channels per block when Cout >= 64
-// (else 32), stages of 32 input channels when Cin allows (else 16).
+// (else 32), stages of 32 input channels when Cin allows (else 16); tiles of
+// 32 columns when the layer still has kWideBlocks blocks with them (the chip
+// stays full), else 16.
+constexpr long long kWideBlocks = 2048;
 template <class TX, class TY>
 static void conv3x3_launch(hipStream_t s, int H, int Himg, int W, int Cin, int Cout, const TX *X, const bf16 *Wt,
-                           const float *bias, int relu, TY *Y, int ldy, int yoff) {
-    const unsigned tiles = (unsigned)(((H + kPR - 1) / kPR) * ((W + kPC - 1) / kPC));
-    if (Cout >= 64) {
-        dim3 g(tiles, (unsigned)((Cout + 63) / 64));
-        if (Cin % 32 == 0) hipLaunchKernelGGL((k_conv3x3<TX, TY, 64, 32>), g, dim3(256), 0, s, H, Himg, W, Cin, Cout, X, Wt, bias, relu, Y, ldy, yoff);
-        else hipLaunchKernelGGL((k_conv3x3<TX, TY, 64, 16>), g, dim3(256), 0, s, H, Himg, W, Cin, Cout, X, Wt, bias, relu, Y, ldy, yoff);
-    } else {
-        dim3 g(tiles, (unsigned)((Cout + 31) / 32));
-        if (Cin % 32 == 0) hipLaunchKernelGGL((k_conv3x3<TX, TY, 32, 32>), g, dim3(256), 0, s, H, Himg, W, Cin, Cout, X, Wt, bias, relu, Y, ldy, yoff);
-        else hipLaunchKernelGGL((k_conv3x3<TX, TY, 32, 16>), g, dim3(256), 0, s, H, Himg, W, Cin, Cout, X, Wt, bias, relu, Y, ldy, yoff);
-    }
+                           const float *bias, int relu, TY *Y, int ldy, int yoff, const bf16 *act = nullptr) {
+    const long long wide = (long long)((H + kPR - 1) / kPR) * ((W + 31) / 32) * ((Cout + (Cout >= 64 ? 63 : 31)) / (Cout >= 64 ? 64 : 32));
+    if (wide >= kWideBlocks) conv3x3_launch_pc<TX, TY, 32>(s, H, Himg, W, Cin, Cout, X, Wt, bias, relu, Y, ldy, yoff, act);
+    else conv3x3_launch_pc<TX, TY, 16>(s, H, Himg, W, Cin, Cout, X, Wt, bias, relu, Y, ldy, yoff, act);
 }
 
 // Weight gradient of one tap, one chunk of pixels:
@@ -506,8 +534,9 @@ static int conv(fd_net *n, int li, const Act &x, bf16 *y, int ldy, int yoff, boo
 
 // backward of conv layer li: g_out (bf16 [P][cout], already multiplied by
 // the activation's derivative) -> weight and bias gradients, and (when gx)
-// the input gradient gx [P][cin].
-static void conv_bwd(fd_net *n, int li, const Act &x, const float *gout, float *gx, bool wgrad) {
+// the input gradient gx [P][cin], multiplied by the derivative of x's leaky
+// ReLU when x_act (x is an activation output).
+static void conv_bwd(fd_net *n, int li, const Act &x, const float *gout, float *gx, bool wgrad, bool x_act = false) {
     const Layer &l = n->L[li];
     int H = rows(n, l.level), Himg = n->H >> l.level, W = n->W >> l.level, P = H * W;
     if (wgrad) {
@@ -520,7 +549,7 @@ static void conv_bwd(fd_net *n, int li, const Act &x, const float *gout, float *
         hipLaunchKernelGGL(k_flip_weights, dim3(nblk((size_t)l.cin * 9 * l.cout, 256)), dim3(256), 0, n->stream,
                            l.cin, l.cout, n->params + l.woff, n->wflip);
         conv3x3_launch<float, float>(n->stream, H, Himg, W, l.cout, l.cin, gout, n->wflip, (const float *)nullptr, 0,
-                                     gx, l.cin, 0);
+                                     gx, l.cin, 0, x_act ? x.y : nullptr);
     }
 }
 
@@ -590,26 +619,26 @@ static void backward(fd_net *n, bool wgrad, bool input) {
         int H = rows(n, x.level), W = n->W >> x.level;
         hipLaunchKernelGGL(k_pool2_bwd_add, dim3(nblk((size_t)H * W * x.c, 256)), dim3(256), 0, s, H, W, x.c, py.g, x.g);
     };
-    act_bwd(n, n->d0);  conv_bwd(n, 13, n->d0a, n->d0.g, n->d0a.g, wgrad);
-    act_bwd(n, n->d0a); conv_bwd(n, 12, n->c0, n->d0a.g, n->c0.g, wgrad);
+    act_bwd(n, n->d0);  conv_bwd(n, 13, n->d0a, n->d0.g, n->d0a.g, wgrad, true);
+    conv_bwd(n, 12, n->c0, n->d0a.g, n->c0.g, wgrad);
     split(n->c0, n->d1, n->e0);
-    act_bwd(n, n->d1);  conv_bwd(n, 11, n->d1a, n->d1.g, n->d1a.g, wgrad);
-    act_bwd(n, n->d1a); conv_bwd(n, 10, n->c1, n->d1a.g, n->c1.g, wgrad);
+    act_bwd(n, n->d1);  conv_bwd(n, 11, n->d1a, n->d1.g, n->d1a.g, wgrad, true);
+    conv_bwd(n, 10, n->c1, n->d1a.g, n->c1.g, wgrad);
     split(n->c1, n->d2, n->e1);
-    act_bwd(n, n->d2);  conv_bwd(n, 9, n->d2a, n->d2.g, n->d2a.g, wgrad);
-    act_bwd(n, n->d2a); conv_bwd(n, 8, n->c2, n->d2a.g, n->c2.g, wgrad);
+    act_bwd(n, n->d2);  conv_bwd(n, 9, n->d2a, n->d2.g, n->d2a.g, wgrad, true);
+    conv_bwd(n, 8, n->c2, n->d2a.g, n->c2.g, wgrad);
     split(n->c2, n->e3, n->e2);
-    act_bwd(n, n->e3);  conv_bwd(n, 7, n->e3a, n->e3.g, n->e3a.g, wgrad);
-    act_bwd(n, n->e3a); conv_bwd(n, 6, n->p3, n->e3a.g, n->p3.g, wgrad);
+    act_bwd(n, n->e3);  conv_bwd(n, 7, n->e3a, n->e3.g, n->e3a.g, wgrad, true);
+    conv_bwd(n, 6, n->p3, n->e3a.g, n->p3.g, wgrad);
     pool_bwd(n->p3, n->e2);
-    act_bwd(n, n->e2);  conv_bwd(n, 5, n->e2a, n->e2.g, n->e2a.g, wgrad);
-    act_bwd(n, n->e2a); conv_bwd(n, 4, n->p2, n->e2a.g, n->p2.g, wgrad);
+    act_bwd(n, n->e2);  conv_bwd(n, 5, n->e2a, n->e2.g, n->e2a.g, wgrad, true);
+    conv_bwd(n, 4, n->p2, n->e2a.g, n->p2.g, wgrad);
     pool_bwd(n->p2, n->e1);
-    act_bwd(n, n->e1);  conv_bwd(n, 3, n->e1a, n->e1.g, n->e1a.g, wgrad);
-    act_bwd(n, n->e1a); conv_bwd(n, 2, n->p1, n->e1a.g, n->p1.g, wgrad);
+    act_bwd(n, n->e1);  conv_bwd(n, 3, n->e1a, n->e1.g, n->e1a.g, wgrad, true);
+    conv_bwd(n, 2, n->p1, n->e1a.g, n->p1.g, wgrad);
     pool_bwd(n->p1, n->e0);
-    act_bwd(n, n->e0);  conv_bwd(n, 1, n->e0a, n->e0.g, n->e0a.g, wgrad);
-    act_bwd(n, n->e0a); conv_bwd(n, 0, n->x0, n->e0a.g, input ? n->x0.g : nullptr, wgrad);
+    act_bwd(n, n->e0);  conv_bwd(n, 1, n->e0a, n->e0.g, n->e0a.g, wgrad, true);
+    conv_bwd(n, 0, n->x0, n->e0a.g, input ? n->x0.g : nullptr, wgrad);
 }
 
 extern "C" {
