@@ -34,7 +34,7 @@
  *     Comments below say "device" for the first mode.
  *   - streams: all work is enqueued on the stream set with fr_set_stream
  *     (default: the null stream; fr_render and fr_backward fork part of
- *     their work onto a second stream of the context's own and join it
+ *     their work onto two more streams of the context's own and join them
  *     back) and the calls
  *     return without waiting, except fr_stats and fr_create, which
  *     synchronise.  One context must
@@ -197,9 +197,10 @@ int fr_render(fr_ctx *ctx, const fr_params *params, uint64_t seed, int32_t spp,
  * render (the caller must keep its device arrays alive until this call is
  * enqueued).  Gradients are sums over samples with floating-point atomics:
  * reproducible up to summation order.  The camera-silhouette term runs on a
- * second stream that the context owns: it waits for an event recorded on
- * the context's stream and the context's stream waits for its end, so the
- * call is ordered with the caller's stream like any other.  Errors: FR_ESTATE without a prior render, FR_EINVAL
+ * second stream and the shadow-boundary term on a third, both owned by the
+ * context: each waits for an event recorded on the context's stream and the
+ * context's stream waits for their ends, so the call is ordered with the
+ * caller's stream like any other.  Errors: FR_ESTATE without a prior render, FR_EINVAL
  * for null dL/dimage. */
 int fr_backward(fr_ctx *ctx, const float *dL_dimage, const fr_grads *grads);
 
