@@ -1548,8 +1548,11 @@ __global__ __launch_bounds__(256) void k_pe_tri_fill(Scene S, int ncx, const uin
             }
         }
 }
+// (a sample without an edge gets its sides' empty hits and visibility here:
+// k_pe_resolve walks only the samples with one, in screen order)
 __global__ __launch_bounds__(256) void k_pe_pick(Scene S, uint64_t seed, int M, PeSample *__restrict__ ps_out,
-        float2 *__restrict__ q, uint32_t *__restrict__ pv_aux) {
+        float2 *__restrict__ q, uint32_t *__restrict__ pv_aux, Hit *__restrict__ hits,
+        unsigned long long *__restrict__ pvis) {
     const int m = blockIdx.x * blockDim.x + threadIdx.x;
     if (m >= M) return;
     PeSample ps;
@@ -1558,16 +1561,25 @@ __global__ __launch_bounds__(256) void k_pe_pick(Scene S, uint64_t seed, int M, 
         q[2 * m] = make_float2(px[0], py[0]);
         q[2 * m + 1] = make_float2(px[1], py[1]);
         atomicAdd(&pv_aux[pv_key(S, m, ps.pix)], 1u);
+    } else {
+        Hit h; h.tri = -1; h.t = 0.0f; h.b1 = h.b2 = h.det = 0.0f;
+        hits[2 * m] = h; hits[2 * m + 1] = h;
+        pvis[2 * m] = 0ull; pvis[2 * m + 1] = 0ull;
     }
     ps_out[m] = ps;
 }
+// Lane g takes side g % 2 of the (g / 2)-th sample with an edge in screen
+// order (perm, n_edge samples): neighbouring lanes then test the triangles
+// of the same or neighbouring cells, so their loops run about as long.
 __global__ __launch_bounds__(256) void k_pe_resolve(Scene S, int M, int ncx, int nc, const PeSample *__restrict__ ps,
         const float2 *__restrict__ q, const uint32_t *__restrict__ off, const float4 *__restrict__ rec, uint32_t cap,
-        Hit *__restrict__ hits, unsigned long long *__restrict__ pvis, unsigned long long *ctr) {
-    const int side = blockIdx.x * blockDim.x + threadIdx.x;
+        const uint32_t *__restrict__ perm, const uint32_t *__restrict__ n_edge, Hit *__restrict__ hits,
+        unsigned long long *__restrict__ pvis, unsigned long long *ctr) {
+    const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
     uint32_t n_cam = 0;
     Work wk;
-    if (side < 2 * M) {
+    if (g < 2 * *n_edge) {
+        const int side = 2 * (int)perm[g >> 1] + (int)(g & 1);
         Hit h; h.tri = -1; h.t = 0.0f; h.b1 = h.b2 = h.det = 0.0f;
         if (ps[side >> 1].e >= 0) {
             n_cam = 1;
@@ -2842,12 +2854,13 @@ static void primary_pass(fr_ctx *c, const Scene &S, const float *dLdI, hipStream
     const int pv_n = pv_aux_len(c->W, c->H, c->nl), pv_nk = pv_keys(c->W, c->H);
     hipLaunchKernelGGL(k_zero_u32, dim3(nblk(pv_n, 256)), dim3(256), 0, st, c->pv_aux, pv_n);
     hipLaunchKernelGGL(k_pe_pick, dim3(nblk(M, 256)), dim3(256), 0, st, S, c->last_seed, M, c->pe_samples,
-                       c->pe_q, c->pv_aux);
+                       c->pe_q, c->pv_aux, c->pe_hits, c->pe_vis);
     hipLaunchKernelGGL(k_scan_u32, dim3(1), dim3(1024), 0, st, pv_nk, c->pv_aux);
     hipLaunchKernelGGL(k_pv_order, dim3(nblk(M, 256)), dim3(256), 0, st, S, M, c->pe_samples, c->pv_aux,
                        c->pv_perm);
     hipLaunchKernelGGL(k_pe_resolve, dim3(nblk(2 * (size_t)M, 256)), dim3(256), 0, st, S, M, ncx, nc,
-                       c->pe_samples, c->pe_q, c->pe_cell_n, c->pe_rec, cap, c->pe_hits, c->pe_vis, pctr);
+                       c->pe_samples, c->pe_q, c->pe_cell_n, c->pe_rec, cap, c->pv_perm,
+                       c->pv_aux + pv_tiles(c->W, c->H) * kPvSortCopies, c->pe_hits, c->pe_vis, pctr);
     const uint32_t pv_cap = 2 * (uint32_t)M;
     hipLaunchKernelGGL(k_pv_propose, dim3(nblk((size_t)pv_cap, 256)), dim3(256), 0, st, S, c->last_seed, c->pe_samples,
                        c->pe_hits, c->pv_perm, c->pv_aux, c->pv_queue, pv_cap, pctr);
