@@ -218,6 +218,35 @@ __device__ __forceinline__ bool slab(const Ray &r, const NBox &b, float thi) {
     return tn <= tf * kSlabGrow;
 }
 
+// The any-hit walk's slab test, the same decision as slab(r, node_box(q),
+// 1) in fewer instructions.  With 1/d_i of either sign the rounded slab
+// times keep the order of the bounds (fma with a fixed multiplier is
+// monotone in the bound), so the smaller of an axis's two times is that of
+// its near bound.  Each ray picks, per axis, its near and far bounds' 16-bit
+// halves out of the node's words with one byte permutation (selectors set
+// once per ray), which replaces the six minima and maxima.  The ray's own
+// leaf enters as an empty box: its near time is raised to infinity through
+// the clamp at t = 0 that the test makes anyway.
+struct SlabSel { uint32_t x, y, z; };
+__device__ __forceinline__ SlabSel slab_sel(const Ray &r) {
+    // byte selectors of __builtin_amdgcn_perm(a, b, sel): 0-3 pick b's bytes, 4-7 a's
+    SlabSel k;
+    k.x = r.id.x >= 0.0f ? 0x03020504u : 0x05040302u;   // lx: q.x bytes 0-1, hx: q.y bytes 2-3
+    k.y = r.id.y >= 0.0f ? 0x01000706u : 0x07060100u;   // ly: q.x bytes 2-3, hy: q.z bytes 0-1
+    k.z = r.id.z >= 0.0f ? 0x03020504u : 0x05040302u;   // lz: q.y bytes 0-1, hz: q.z bytes 2-3
+    return k;
+}
+__device__ __forceinline__ bool slab_any(const Ray &r, const SlabSel &k, const Node &q, float t0) {
+    const uint32_t wx = __builtin_amdgcn_perm(q.x, q.y, k.x), wy = __builtin_amdgcn_perm(q.x, q.z, k.y),
+                   wz = __builtin_amdgcn_perm(q.y, q.z, k.z);
+    const float nx = fmaf(h2f(wx & 0xffffu), r.id.x, -r.oid.x), fx = fmaf(h2f(wx >> 16), r.id.x, -r.oid.x);
+    const float ny = fmaf(h2f(wy & 0xffffu), r.id.y, -r.oid.y), fy = fmaf(h2f(wy >> 16), r.id.y, -r.oid.y);
+    const float nz = fmaf(h2f(wz & 0xffffu), r.id.z, -r.oid.z), fz = fmaf(h2f(wz >> 16), r.id.z, -r.oid.z);
+    const float tn = fmaxf(fmaxf(nx, ny), fmaxf(nz, t0));
+    const float tf = fminf(fminf(fx, fy), fminf(fz, 1.0f));
+    return tn <= tf * kSlabGrow;
+}
+
 struct Hit { int tri; float t, b1, b2, det; };
 // work counters of one lane: box tests, triangle tests, shaded light samples
 // Work counters of a lane: node tests, triangle tests, shaded samples, and
@@ -294,27 +323,34 @@ __device__ inline bool trace_any(const Scene &S, v3 o, v3 d, int skip, Work &wk,
     int node = 0;
     bool hit = false;
     uint32_t boxes = 0, step = 0, cnt = 0;     // wave-uniform
+    const int last = S.n_nodes - 1;
+    int own = ~skip;                           // the ray's own leaf link
+    asm volatile("" : "+v"(own));              // kept as is: one compare per step
+    const SlabSel sel = slab_sel(r);
     for (;;) {
         for (;;) {                             // walk until the list is due
             const bool walk = node < S.n_nodes;
             const unsigned long long m = __ballot(walk);
             if (!m || cnt >= kLeafRound) break;
             boxes += (uint32_t)__popcll(m);
-            bool want = false;
-            int tri = 0;
-            if (walk) {
-                const Node q = load_node(S.nodes, node);
-                const int link = node_link(q);
-                const bool in = slab(r, node_box(q), 1.0f), leaf = link < 0;
-                node = (in || leaf) ? node + 1 : link;
-                tri = ~link;
-                want = in && leaf && tri != skip;
-            }
-            const unsigned long long a = __ballot(want);
+            // Every lane takes the step, with no branch around it: a lane
+            // that has left the tree visits the last node, a leaf of the
+            // depth-first layout, so its index only grows, and its test is
+            // dropped.  (The branch cost a vector select and a mask copy
+            // per step.)
+            const Node q = load_node(S.nodes, min(node, last));
+            const int link = node_link(q);
+            const bool in = slab_any(r, sel, q, link == own ? INFINITY : 0.0f), leaf = link < 0;
+            node = (in || leaf) ? node + 1 : link;
+            const bool want = walk && in && leaf;
+            // the mask of wanting lanes from one ballot per compare (leaf:
+            // link < 0, predicate 40), ANDed in scalar registers; a ballot
+            // of the combined flag is copied through a vector register
+            const unsigned long long a = m & __builtin_amdgcn_ballot_w64(in) & __builtin_amdgcn_sicmp(link, 0, 40);
             if (want) {
                 const uint32_t at = cnt + __builtin_amdgcn_mbcnt_hi((uint32_t)(a >> 32),
                                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)a, 0u));
-                lq[at] = ((uint32_t)tri << 6) | (uint32_t)lane;
+                lq[at] = ((uint32_t)~link << 6) | (uint32_t)lane;
                 lstep[at] = step;
             }
             cnt += (uint32_t)__popcll(a);
