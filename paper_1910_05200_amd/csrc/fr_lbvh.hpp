@@ -320,39 +320,71 @@ __device__ __forceinline__ void lbvh_boxes_body(int F, const int *__restrict__ f
         const int *__restrict__ first, const int *__restrict__ last, const int *__restrict__ pre,
         float *box, Node *__restrict__ nodes, float4 *__restrict__ tris, int *__restrict__ roots,
         int *__restrict__ n_roots, int tb) {
+    // The climb runs in LDS.  Every internal node inside the block's range
+    // has its index in [lo, hi] (an internal node's index lies in its own
+    // leaf range), so slot (index - lo) holds its parent, range, children,
+    // position and box, loaded at once before the climb, and leaf l's box
+    // sits at slot (l - lo).  A climb step then costs LDS accesses only
+    // instead of a chain of dependent global loads; only the boxes of the
+    // nodes handed to the second pass go to global memory.
+    __shared__ int s_par[kBoxTile], s_first[kBoxTile], s_last[kBoxTile], s_cl[kBoxTile], s_cr[kBoxTile],
+        s_pre[kBoxTile];
+    __shared__ float s_ibox[6 * kBoxTile], s_lbox[6 * kBoxTile];
     __shared__ unsigned int arr[kBoxTile];
-    arr[threadIdx.x] = 0u;
-    __syncthreads();
     const int lo = tb * kBoxTile, hi = min(F, lo + kBoxTile) - 1;
-    int l = lo + (int)threadIdx.x;
-    if (l >= F) return;
-    int f = sorted[l];
-    const int *t = faces + 3 * f;
-    v3 a = vpos_raw(pos, V, t[0]), b = vpos_raw(pos, V, t[1]), c = vpos_raw(pos, V, t[2]);
-    tris[3 * f] = make_float4(a.x, a.y, a.z, b.x);
-    tris[3 * f + 1] = make_float4(b.y, b.z, c.x, c.y);
-    tris[3 * f + 2] = make_float4(c.z, __int_as_float(f), 0.0f, 0.0f);
-    float bx[6] = {fminf(fminf(a.x, b.x), c.x) - kBoxPad, fminf(fminf(a.y, b.y), c.y) - kBoxPad,
-                   fminf(fminf(a.z, b.z), c.z) - kBoxPad, fmaxf(fmaxf(a.x, b.x), c.x) + kBoxPad,
-                   fmaxf(fmaxf(a.y, b.y), c.y) + kBoxPad, fmaxf(fmaxf(a.z, b.z), c.z) + kBoxPad};
+    const int t = (int)threadIdx.x;
+    arr[t] = 0u;
+    if (lo + t <= min(hi, F - 2)) {              // internal node lo + t
+        const int p = lo + t;
+        s_par[t] = parent[p]; s_first[t] = first[p]; s_last[t] = last[p];
+        s_cl[t] = child[2 * p]; s_cr[t] = child[2 * p + 1]; s_pre[t] = pre[p];
+    }
+    const int l = lo + t;
     int x = (F - 1) + l;
-    for (int k = 0; k < 6; ++k) box[6 * x + k] = bx[k];
-    nodes[pre[x]] = make_node(bx[0], bx[1], bx[2], bx[3], bx[4], bx[5], ~f);
-    if (F == 1) return;
-    __threadfence_block();
+    int p = -1;
+    if (l < F) {
+        const int f = sorted[l];
+        const int *tv = faces + 3 * f;
+        v3 a = vpos_raw(pos, V, tv[0]), b = vpos_raw(pos, V, tv[1]), c = vpos_raw(pos, V, tv[2]);
+        tris[3 * f] = make_float4(a.x, a.y, a.z, b.x);
+        tris[3 * f + 1] = make_float4(b.y, b.z, c.x, c.y);
+        tris[3 * f + 2] = make_float4(c.z, __int_as_float(f), 0.0f, 0.0f);
+        float bx[6] = {fminf(fminf(a.x, b.x), c.x) - kBoxPad, fminf(fminf(a.y, b.y), c.y) - kBoxPad,
+                       fminf(fminf(a.z, b.z), c.z) - kBoxPad, fmaxf(fmaxf(a.x, b.x), c.x) + kBoxPad,
+                       fmaxf(fmaxf(a.y, b.y), c.y) + kBoxPad, fmaxf(fmaxf(a.z, b.z), c.z) + kBoxPad};
+        for (int k = 0; k < 6; ++k) s_lbox[6 * t + k] = bx[k];
+        nodes[pre[x]] = make_node(bx[0], bx[1], bx[2], bx[3], bx[4], bx[5], ~f);
+        p = F > 1 ? parent[x] : -1;
+    }
+    __syncthreads();
+    if (l >= F) return;
+    const float *xb = s_lbox + 6 * t;           // box of x
     for (;;) {
-        int p = parent[x];
         if (p < 0) return;                                    // x is the root
-        if (first[p] < lo || last[p] > hi) {                  // parent spans blocks
+        if (p < lo || p > hi || s_first[p - lo] < lo || s_last[p - lo] > hi) {   // parent spans blocks
+            for (int k = 0; k < 6; ++k) box[6 * x + k] = xb[k];
             roots[atomicAdd(n_roots, 1)] = x;
             return;
         }
-        unsigned int old = atomicAdd(&arr[p - lo], 1u);
-        if (old == 0u) return;                                // first child: the sibling continues
+        const int sp = p - lo;
+        if (atomicAdd(&arr[sp], 1u) == 0u) return;           // first child: the sibling continues
         __threadfence_block();
-        lbvh_union_write(F, p, child, first, last, pre, box, nodes);
+        const int cl = s_cl[sp], cr = s_cr[sp];
+        const float *bl = cl >= F - 1 ? s_lbox + 6 * (cl - (F - 1) - lo) : s_ibox + 6 * (cl - lo);
+        const float *br = cr >= F - 1 ? s_lbox + 6 * (cr - (F - 1) - lo) : s_ibox + 6 * (cr - lo);
+        float u[6];
+        for (int k = 0; k < 3; ++k) {
+            u[k] = fminf(bl[k], br[k]);
+            u[3 + k] = fmaxf(bl[3 + k], br[3 + k]);
+        }
+        float *pb = s_ibox + 6 * sp;
+        for (int k = 0; k < 6; ++k) pb[k] = u[k];
+        const int pp = s_pre[sp];
+        nodes[pp] = make_node(u[0], u[1], u[2], u[3], u[4], u[5], pp + 2 * (s_last[sp] - s_first[sp] + 1) - 1);
         __threadfence_block();
         x = p;
+        xb = pb;
+        p = s_par[sp];
     }
 }
 __global__ __launch_bounds__(kBoxTile) void k_lbvh_boxes(int F, const int *__restrict__ faces, const float *__restrict__ pos,
