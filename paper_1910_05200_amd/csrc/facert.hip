@@ -723,8 +723,7 @@ __global__ __launch_bounds__(256) void k_cam_resolve(Scene S, long long n, HitRe
 // none), so tracing in place would leave two lanes in three idle.  The
 // shadow-boundary kernel takes a tile of samples for one light per block;
 // the tile size is a template parameter of its body (the batched launcher
-// may pick 256 or 512).  It keeps its accepted samples' two side rays in
-// LDS (48 bytes each), so its default tile is 256 samples.
+// may pick 256 or 512); its default tile is 256 samples.
 constexpr int kSecTile = 256;
 __device__ __forceinline__ int lanes_below(unsigned long long m) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0));
@@ -1236,13 +1235,19 @@ __device__ inline bool secondary_edge(const Scene &S, const Light &L, int j, uin
     return true;
 }
 
-// One block per (tile of kSecTile camera samples, light).  The lanes first
-// run each sample's edge pick and acceptance tests (no rays) and compact the
-// accepted samples' shading point and two side rays into an LDS list; the
-// block's waves then trace each entry's two rays in one walk.  Most samples
-// are rejected before any ray, so tracing in place would leave most lanes
-// idle, and keeping the rays spares the trace phase a second run of the
-// edge pick (a binary search over the CDF) and the acceptance tests.
+// One block per tile of kSecTile camera samples and group of kSecLights
+// lights.  Each
+// lane decides its sample's surface once (sec_setup), then runs the edge
+// pick and acceptance tests (no rays) for one light after another; the
+// first kept the block per (tile, light) and repeated the sample's camera
+// ray, hit record and surface for each light, a chain of dependent loads
+// ahead of each pick.  A proposal that needs its two side rays goes to the
+// block's list in LDS (4 bytes: the list holds every (sample, light) pair of
+// the block at worst), and after the proposals the block's waves trace the
+// listed pairs' rays.  Proposals are accepted rarely (about 1 in 10^4 at the
+// paper's framing), so a listed pair's lane sets up its sample and pick
+// again rather than keep the rays: the proposal loop then needs 45 vector
+// registers, and the trace phase's registers are not held beside them.
 __device__ __forceinline__ void sec_setup(const Scene &S, uint64_t seed, int spp, long long s0, long long i,
         const float *dLdI, const HitRec *hits, v3 &o, v3 &d, float w[3], Hit &h, SurfDec &sd, uint32_t &s,
         bool &live) {
@@ -1265,14 +1270,20 @@ __device__ __forceinline__ void sec_setup(const Scene &S, uint64_t seed, int spp
 // go to a global list as (chunk index | light << 24 | vp << 30).
 // k_edge_secondary_value: the value path of each listed sample.  Splitting
 // them keeps the fp64 value code's registers out of the traversal kernel.
+// Lights per block, measured at the paper's framing (20 lights; ms per
+// step): 1 2.65, 2 2.56, 4 2.44, 5 2.43, 7 2.45, 10 2.48, all 20 2.63 (long
+// blocks hold their registers and LDS beside the other two terms for the
+// whole adjoint).  The per-(tile, light) form that kept each listed
+// proposal's rays took 2.49.
+constexpr int kSecLights = 5;
+__host__ __device__ inline int sec_light_groups(int nl) { return (nl + kSecLights - 1) / kSecLights; }
 template <int TS>
 __device__ __forceinline__ void edge_secondary_body(const Scene &S, uint64_t seed, int spp, long long s0, long long n,
         const float *__restrict__ dLdI, const HitRec *__restrict__ hits, uint32_t *__restrict__ out,
-        uint32_t *__restrict__ out_n, unsigned long long *ctr, int bx, int j) {
+        uint32_t *__restrict__ out_n, unsigned long long *ctr, int bx, int by) {
+    static_assert(TS % 256 == 0 && TS <= 65536, "a tile is whole blocks of 256 samples");
     __shared__ Light Ls[kMaxLights];
-    __shared__ float4 q_a[TS];   // shading point, its triangle
-    __shared__ float4 q_b[TS];   // toward the + side point, tile-local sample index
-    __shared__ float4 q_c[TS];   // toward the - side point
+    __shared__ uint32_t ql[TS * kSecLights];   // proposals that need rays: tile index | light << 16
     __shared__ int q_n;
     for (int k = threadIdx.x; k < S.nl; k += blockDim.x) {
         const float *g = S.lgeom + 12 * k;
@@ -1285,57 +1296,57 @@ __device__ __forceinline__ void edge_secondary_body(const Scene &S, uint64_t see
     __syncthreads();
     const float geoR = *S.geo_R;
     const long long base = (long long)bx * TS;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int jbeg = by * kSecLights, jend = min(S.nl, jbeg + kSecLights);
     uint32_t n_sec = 0;
     Work wk;
-    bool vp = false;
     for (int k = 0; k < TS; k += 256) {
         const int li = k + (int)threadIdx.x;
         const long long i = base + li;
-        bool need = false;
-        v3 sides[2], p0;
-        int tri = -1;
-        if (i < n) {
-            v3 o, d; float w[3]; Hit h; SurfDec sd; uint32_t s; bool live;
-            sec_setup(S, seed, spp, s0, i, dLdI, hits, o, d, w, h, sd, s, live);
-            if (live) {
+        v3 o, d; float w[3]; Hit h; SurfDec sd; uint32_t s; bool live = false;
+        if (i < n) sec_setup(S, seed, spp, s0, i, dLdI, hits, o, d, w, h, sd, s, live);
+        for (int j = jbeg; j < jend; ++j) {
+            bool need = false, vp = false;
+            if (live)
                 need = secondary_edge<kSecPropose>(S, Ls[j], j, seed, s, nullptr, o, d, h, sd, w, nullptr, vp, n_sec,
-                                                   wk, geoR, sides);
-                p0 = sd.p;
-                tri = h.tri;
-            }
-        }
-        unsigned long long m = __ballot(need);
-        int wbase = 0;
-        if (lane == 0 && m) wbase = atomicAdd(&q_n, __popcll(m));
-        wbase = __shfl(wbase, 0);
-        if (need) {
-            const int slot = wbase + lanes_below(m);
-            q_a[slot] = make_float4(p0.x, p0.y, p0.z, __int_as_float(tri));
-            q_b[slot] = make_float4(sides[0].x, sides[0].y, sides[0].z, __int_as_float(li));
-            q_c[slot] = make_float4(sides[1].x, sides[1].y, sides[1].z, 0.0f);
+                                                   wk, geoR);
+            const unsigned long long m = __ballot(need);
+            int wbase = 0;
+            if (lane == 0 && m) wbase = atomicAdd(&q_n, __popcll(m));
+            wbase = __shfl(wbase, 0);
+            if (need) ql[wbase + lanes_below(m)] = (uint32_t)li | ((uint32_t)j << 16);
         }
     }
     __syncthreads();
+    // each listed proposal's two side rays, rebuilt from its sample and
+    // light exactly as the proposal built them, traced in one walk
     const int nq = q_n;
-    for (int e = wave * 64 + lane; e - lane < nq; e += 256) {
-        bool val = false;
-        long long i = 0;
+    for (int e = threadIdx.x; e - lane < nq; e += 256) {
+        bool val = false, vq = false;
+        long long i2 = 0;
+        uint32_t j2 = 0;
         if (e < nq) {
-            // the two side rays as the proposal computed them
-            const float4 a = q_a[e], b = q_b[e], c = q_c[e];
-            i = base + __float_as_int(b.w);
-            bool bp, bm;
-            n_sec += 2;
-            trace_any2(S, mk(a.x, a.y, a.z), mk(b.x, b.y, b.z), mk(c.x, c.y, c.z), __float_as_int(a.w), bp, bm, wk);
-            vp = !bp;
-            val = bp != bm;
+            const uint32_t q = ql[e];
+            i2 = base + (long long)(q & 0xffffu);
+            j2 = q >> 16;
+            v3 o, d; float w[3]; Hit h; SurfDec sd; uint32_t s; bool live;
+            sec_setup(S, seed, spp, s0, i2, dLdI, hits, o, d, w, h, sd, s, live);
+            v3 sides[2];
+            bool vdummy = false;
+            if (live && secondary_edge<kSecPropose>(S, Ls[j2], (int)j2, seed, s, nullptr, o, d, h, sd, w, nullptr,
+                                                    vdummy, n_sec, wk, geoR, sides)) {
+                bool bp, bm;
+                n_sec += 2;
+                trace_any2(S, sd.p, sides[0], sides[1], h.tri, bp, bm, wk);
+                vq = !bp;
+                val = bp != bm;
+            }
         }
-        unsigned long long m = __ballot(val);
+        const unsigned long long mv = __ballot(val);
         uint32_t obase = 0;
-        if (lane == 0 && m) obase = atomicAdd(out_n, (uint32_t)__popcll(m));
+        if (lane == 0 && mv) obase = atomicAdd(out_n, (uint32_t)__popcll(mv));
         obase = (uint32_t)__shfl((int)obase, 0);
-        if (val) out[obase + lanes_below(m)] = (uint32_t)i | ((uint32_t)j << 24) | (vp ? 1u << 30 : 0u);
+        if (val) out[obase + lanes_below(mv)] = (uint32_t)i2 | (j2 << 24) | (vq ? 1u << 30 : 0u);
     }
     flush_count(ctr, 3, n_sec);
     flush_work(ctr, wk);
@@ -2925,7 +2936,7 @@ static int backward_call(fr_ctx *c, const float *dLdI, const fr_grads *g) {
             for (long long o = 0; o < n; o += kSecSub) {
                 long long m = std::min(kSecSub, n - o);
                 hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st2, c->sec_n, 1);
-                hipLaunchKernelGGL(k_edge_secondary, dim3(nblk(m, kSecTile), c->nl), dim3(256), 0, st2, S,
+                hipLaunchKernelGGL(k_edge_secondary, dim3(nblk(m, kSecTile), sec_light_groups(c->nl)), dim3(256), 0, st2, S,
                                    c->last_seed, c->last_spp, s0 + o, m, dLdI, c->hits + o, c->sec_list, c->sec_n,
                                    c->ctr + kCtrPerKern * kKernSecondary);
                 hipLaunchKernelGGL(k_edge_secondary_value, dim3(1024), dim3(256), lds1, st2, S, c->last_seed,

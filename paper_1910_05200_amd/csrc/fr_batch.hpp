@@ -371,7 +371,7 @@ static void kind_grid(const fr_batch *b, int k, int i, int &gx, int &gy) {
     case bkEdgeScan: gx = 1 + nl; break;
     case bkCamera: gx = (int)nblk(N, kTraceBlock); break;
     case bkShade: case bkAdj: gx = (int)nblk(N, 256); break;
-    case bkSecondary: gx = (int)nblk(N, ts); gy = nl; break;
+    case bkSecondary: gx = (int)nblk(N, ts); gy = sec_light_groups(nl); break;
     case bkShPropose: gx = (int)nblk(N, 256); break;
     case bkShTrace: gx = (int)nblk(N, kTraceBlock); gy = nl; break;
     case bkPrimarySetup: gx = (int)nblk(M, kTraceBlock); break;
