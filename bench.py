@@ -34,11 +34,12 @@ OPS_BOX = 15
 OPS_TRI = 50
 # The same units as the compiled gfx950 code issues them (VALU instructions
 # per lane in the compiled loop, address arithmetic included): a node visit
-# 24 (binary16 decode folded into v_fma_mix_f32; the loop's exit and queue
-# tests included), a full triangle test with its hit-box check 95, one light
+# of the any-hit walk 23 (three byte permutations pick the near and far
+# bounds, the binary16 decode is folded into v_fma_mix_f32; the loop's exit
+# and queue tests included), a full triangle test with its hit-box check 95, one light
 # sample's shading 215, one light sample's shading plus reverse-mode
 # adjoint 590.  Reported beside the fixed-cost fraction, never in its place.
-ISA_BOX = 24
+ISA_BOX = 23
 ISA_TRI = 95
 OPS_SHADE_FWD = 215
 OPS_SHADE_ADJ = 590
