@@ -128,12 +128,18 @@ def test_large_mesh_trees_match_oracle(torch, orc, nx, ny):
     assert_image_parity(a, orc.render(osc, SEED, 2))
 
 
-def _grad_case(torch, orc, name, terms, chunk=None, refit=False, size=None):
+def _grad_case(torch, orc, name, terms, chunk=None, refit=False, size=None, n_lights=None):
     from paper_1910_05200_amd import facert
     model, scene, params, spp = _case(name)
     if size:
         scene = synth.make_scene(*size)
-    tosc, _, _ = orc.scene_from_model(model, scene, synth.make_params(synth.TARGET_SCENE_SEED))
+    nl = synth.N_LIGHTS
+    if n_lights:
+        nl = n_lights
+        scene.light_geom = synth.light_stage(nl)
+        params = synth.make_params(synth.EVAL_SCENE_SEED, n_lights=nl, n_off=min(5, nl // 3))
+    tosc, _, _ = orc.scene_from_model(model, scene, synth.make_params(synth.TARGET_SCENE_SEED, n_lights=nl,
+                                                                      n_off=min(5, nl // 3)))
     target = orc.render(tosc, synth.TARGET_RENDER_SEED, 16)
     osc, vm, R = orc.scene_from_model(model, scene, params)
     ref_img = orc.render(osc, SEED, spp)
@@ -176,6 +182,17 @@ def test_backward_all_terms_tiny(torch, orc):
     g, ref, pg, r = _grad_case(torch, orc, "tiny", 7)
     st = r.stats()
     assert st["rays_edge_secondary"] > 0 and st["rays_edge_primary"] > 0
+    _compare(g, ref, pg)
+
+
+@pytest.mark.parametrize("n_lights", [12, 3])
+def test_backward_all_terms_light_groups(torch, orc, n_lights):
+    """Light counts that are not a multiple of the shadow-boundary kernel's
+    lights per block (a short last group, and a single short group)."""
+    g, ref, pg, r = _grad_case(torch, orc, "tiny", 7, n_lights=n_lights)
+    assert g["d_lights"].shape[0] == n_lights
+    if n_lights >= 12:
+        assert r.stats()["rays_edge_secondary"] > 0
     _compare(g, ref, pg)
 
 
