@@ -286,9 +286,9 @@ void fr_destroy(fr_ctx *ctx);
  * Launch modes per kernel kind (kinds 0 .. fr_batch_num_kinds() - 1, named
  * by fr_batch_kind_name): FR_LAUNCH_FLAT, one block per tile, the tiles in
  * order; FR_LAUNCH_XCD, one block per tile, the tiles dealt to the eight
- * XCDs in contiguous eighths.  The shadow-boundary kind, which compacts
- * rays per (tile, light), also takes a tile size (samples per block: 256 or
- * 512).
+ * XCDs in contiguous eighths.  The shadow-boundary kind, whose blocks
+ * each take a tile of samples and a group of five lights, also takes a tile
+ * size (samples per block: 256 or 512).
  * fr_batch_tune picks them by measurement. */
 typedef struct fr_batch fr_batch;
 
@@ -296,9 +296,10 @@ typedef struct fr_batch fr_batch;
 #define FR_LAUNCH_XCD 1
 typedef struct {
     int32_t mode;                    /* FR_LAUNCH_*                            */
-    int32_t tile;                    /* edge_secondary, which compacts its
-                                        samples per (tile, light): 256 or
-                                        512; 0 for the others                  */
+    int32_t tile;                    /* edge_secondary, whose blocks each
+                                        take a tile of samples (and five
+                                        lights): 256 or 512; 0 for the
+                                        others                                 */
 } fr_launch;
 
 /* n contexts (1..4096, distinct, created with FR_DEVICE_PTRS and without
